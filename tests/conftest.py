@@ -1,0 +1,22 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    config.addinivalue_line("markers", "slow: large CPU-side case")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _cpu_libs():
+    """The seeded generators and the oracle are plain C; build them if absent."""
+    import oracle
+    import synth
+    synth._load()
+    oracle._load()
