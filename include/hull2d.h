@@ -1,0 +1,164 @@
+/*
+ * hull2d.h - exact 2D convex hulls on AMD Instinct MI355X (gfx950).
+ *
+ * The data-parallel first stage of gScan (G. Mei, "gScan: Accelerating
+ * Graham Scan on the GPU", Sections 2 and 3) as hand-written HIP kernels,
+ * followed by the paper's final stack scan on the host (Step 8):
+ *
+ *   Step 1  four extreme points by parallel reduction           (Section 3.1)
+ *   Step 2  discard points strictly inside their quadrilateral  (Section 3.1)
+ *   Step 3  exact angle keys about the pivot and farthest point (Section 3.2)
+ *   Step 4  sort of the survivors by exact angle                 (Section 3.3)
+ *   Step 5-6 farthest point P_l splits the sorted list          (Section 2.1)
+ *   Step 7  second-round filter per region (Figure 2)           (Section 3.4)
+ *   Step 8  Graham stack scan of the kept points (host)         (Section 3)
+ *
+ * Input: n points as float64 [n][2] (x, y interleaved) in device memory.
+ * Output: the canonical hull as int32 input indices in host memory:
+ * counter-clockwise, starting at the lexicographically smallest vertex
+ * (smallest x, then smallest y), collinear points and duplicates dropped,
+ * each vertex reported by the smallest index holding its coordinates.
+ * All geometric decisions are exact (float64 error-free products with an
+ * adaptive expansion fallback), so the output is a deterministic function of
+ * the input bytes.
+ *
+ * Input domain: every coordinate finite, and either 0 or of magnitude in
+ * [2^-300, 2^300] (then the exact arithmetic never leaves the normal range);
+ * -0.0 equals +0.0.  At most 2^31 - 1 points per set.
+ *
+ * Ownership and threading: the caller owns every input and output buffer;
+ * inputs are never written.  A context owns a device workspace that grows on
+ * demand and is freed by hull2d_destroy.  A context is bound to one device
+ * and one HIP stream and is not thread-safe: use one context per stream.
+ * Calls return after the host output is written (they synchronise the
+ * context's stream).  Nothing throws across this interface.
+ */
+#ifndef HULL2D_H
+#define HULL2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hull2d_ctx hull2d_ctx;
+
+typedef enum {
+    HULL2D_OK = 0,
+    HULL2D_ERR_INVALID_ARG = 1,  /* null pointer, negative size, bad option       */
+    HULL2D_ERR_NONFINITE = 2,    /* a coordinate is NaN or infinite                */
+    HULL2D_ERR_RANGE = 3,        /* a non-zero coordinate outside [2^-300, 2^300]  */
+    HULL2D_ERR_CAPACITY = 4,     /* output too small; required size written back  */
+    HULL2D_ERR_OUT_OF_MEMORY = 5,/* device or pinned host allocation failed        */
+    HULL2D_ERR_DEVICE = 6,       /* a HIP call failed; the context is unusable     */
+    HULL2D_ERR_WEIGHTS = 7,      /* learned-filter weights missing or corrupt      */
+    HULL2D_ERR_UNIMPLEMENTED = 8
+} hull2d_status;
+
+/* Options.  Zero-initialise, then set struct_size = sizeof(hull2d_options). */
+typedef struct {
+    uint32_t struct_size;
+    /* Round-2 subsets (Section 3.4).  0: each region is filtered as one
+     * sequence, exactly as Figure 2 prints it (computed in parallel as a
+     * prefix scan; the default).  -1: the paper's division of each region into
+     * 1024 subsets of ceil(m/1024) points, each subset walked by one thread.
+     * c > 0: subsets of c points.  The hull is identical in every mode; only
+     * the number of round-2 survivors and the time change. */
+    int32_t round2_chunk;
+    /* 1: record per-kernel device times (HIP events) into hull2d_stats. */
+    int32_t profile;
+    int32_t reserved[5];
+} hull2d_options;
+
+/* Per-kernel stage indices of hull2d_stats.ms_stage. */
+enum {
+    HULL2D_STAGE_EXTREMES = 0,   /* Step 1 partial reduction                       */
+    HULL2D_STAGE_EXTREMES_FINAL, /* Step 1 final reduction and quadrilateral        */
+    HULL2D_STAGE_FILTER1,        /* Step 2 discard + Step 3 keys + compaction       */
+    HULL2D_STAGE_LONGEST,        /* Step 5 farthest point                           */
+    HULL2D_STAGE_HISTOGRAM,      /* Step 4 digit histograms                         */
+    HULL2D_STAGE_SORT0,          /* Step 4 radix passes (bits 0-7 ... 24-31)        */
+    HULL2D_STAGE_SORT1,
+    HULL2D_STAGE_SORT2,
+    HULL2D_STAGE_SORT3,
+    HULL2D_STAGE_TIES,           /* Step 4 exact order inside equal-key runs        */
+    HULL2D_STAGE_TIES_LONG,
+    HULL2D_STAGE_ROUND2,         /* Steps 6-7 second-round filter                   */
+    HULL2D_STAGE_COMPACT,        /* Step 7 stable removal of interior points        */
+    HULL2D_STAGE_D2H,            /* copy of the kept points to the host             */
+    HULL2D_STAGE_HOST_SCAN,      /* Step 8 on the host (wall clock)                 */
+    HULL2D_NUM_STAGES
+};
+
+typedef struct {
+    int64_t n;            /* points in                                             */
+    int64_t n_round1;     /* points that survived round 1 (Step 2)                 */
+    int64_t n_sorted;     /* round-1 survivors other than copies of the pivot      */
+    int64_t n_round2;     /* points kept by round 2, the pivot included            */
+    int64_t n_hull;       /* hull vertices                                          */
+    double ms_total;      /* host wall clock of the whole call                     */
+    double ms_device;     /* first kernel start to end of the host copy (events)   */
+    double ms_stage[HULL2D_NUM_STAGES]; /* filled when options.profile = 1        */
+} hull2d_stats;
+
+/* Create a context on HIP device `device` using stream `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  opt may be NULL (defaults).
+ * Errors: INVALID_ARG, DEVICE. */
+hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
+                            const hull2d_options* opt);
+
+/* Hull of n points at d_xy (device, float64 [n][2], 8-byte aligned).
+ * Writes at most `cap` indices to h_out (host) and the hull size to *n_out.
+ * CAPACITY: *n_out holds the required size and h_out is untouched.
+ * NONFINITE / RANGE: input outside the domain; *n_out = 0.
+ * stats may be NULL. */
+hull2d_status hull2d_compute(hull2d_ctx* ctx, const double* d_xy, int64_t n,
+                             int32_t* h_out, int64_t cap, int64_t* n_out,
+                             hull2d_stats* stats);
+
+/* Hulls of S independent sets stored back to back at d_xy: set s is points
+ * [h_offsets[s], h_offsets[s+1]) (host array of S+1 non-decreasing int64,
+ * h_offsets[0] = 0).  Each set's hull (indices local to the set) is written
+ * to h_out at [h_out_offsets[s], h_out_offsets[s+1]).  CAPACITY: the
+ * offsets are still written, with h_out_offsets[S] the required size. */
+hull2d_status hull2d_batch(hull2d_ctx* ctx, const double* d_xy,
+                           const int64_t* h_offsets, int32_t S,
+                           int32_t* h_out, int64_t cap, int64_t* h_out_offsets,
+                           hull2d_stats* stats);
+
+void hull2d_destroy(hull2d_ctx* ctx);
+
+const char* hull2d_status_string(hull2d_status s);
+
+/* ---- Checking entry points (exact predicates on the device) ------------ */
+
+/* out[i] = sign of (b - a) x (c - a) for triple i, computed by the device
+ * predicate; abc is device float64 [count][6] = (ax, ay, bx, by, cx, cy),
+ * out is device int32 [count].  Synchronous. */
+hull2d_status hull2d_debug_orient(hull2d_ctx* ctx, const double* d_abc, int64_t count,
+                                  int32_t* d_out);
+
+/* out[i] = the exact 32-bit angle key of point i about the pivot (x0, y0):
+ * floor(2^31 * phi) with phi = dy/(|dx|+dy) for dx >= 0 and
+ * 2 - dy/(|dx|+dy) for dx < 0 (dx = x - x0, dy = y - y0 >= 0).  Points must
+ * satisfy y > y0, or y == y0 and x > x0.  d_xy device float64 [count][2],
+ * d_out device uint32 [count].  Synchronous. */
+hull2d_status hull2d_debug_angle_key(hull2d_ctx* ctx, const double* d_xy, int64_t count,
+                                     double x0, double y0, uint32_t* d_out);
+
+/* Stage results of the last hull2d_compute on this context, for checking
+ * against a step-by-step model.  Any pointer may be NULL.  Host buffers:
+ * extremes[4] (input indices of P_minx, P_miny, P_maxx, P_maxy);
+ * sorted[cap] (input indices of the sorted round-1 survivors, Step 4);
+ * round2[cap] (input indices kept by round 2 in angular order, pivot first);
+ * counts[4] = {n_sorted, l (position of P_l in [pivot, sorted...]),
+ * n_round2, longest (input index of P_l)}.
+ * CAPACITY if cap is smaller than n_sorted or n_round2. */
+hull2d_status hull2d_debug_stages(hull2d_ctx* ctx, int32_t* extremes, int32_t* sorted,
+                                  int32_t* round2, int64_t cap, int64_t* counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,219 @@
+"""Exact 2D convex hulls on AMD Instinct MI355X (gfx950).
+
+Python binding of ``libhull2d.so`` (C ABI in ``include/hull2d.h``).  This
+module only marshals arguments: every step of the hull path runs in the
+library's HIP kernels and its host stack scan.  PyTorch provides device
+memory and the stream.  There is no fallback: if the library is missing the
+functions raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhull2d.so")
+
+STATUS = {
+    0: "ok", 1: "invalid argument", 2: "non-finite coordinate",
+    3: "coordinate magnitude outside [2^-300, 2^300]", 4: "output capacity too small",
+    5: "out of memory", 6: "device error", 7: "weights missing or corrupt",
+    8: "not implemented",
+}
+OK, INVALID_ARG, NONFINITE, RANGE, CAPACITY, OUT_OF_MEMORY, DEVICE, WEIGHTS, UNIMPLEMENTED = range(9)
+
+STAGES = ["extremes", "extremes_final", "filter1", "longest", "histogram", "sort0", "sort1",
+          "sort2", "sort3", "ties", "ties_long", "round2", "compact", "d2h", "host_scan"]
+
+EXPORTED = ["hull2d_create", "hull2d_compute", "hull2d_batch", "hull2d_destroy",
+            "hull2d_status_string", "hull2d_debug_orient", "hull2d_debug_angle_key",
+            "hull2d_debug_stages"]
+
+
+class HullError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        super().__init__(f"{where}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("round2_chunk", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_round1", ctypes.c_int64),
+                ("n_sorted", ctypes.c_int64), ("n_round2", ctypes.c_int64),
+                ("n_hull", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("ms_device", ctypes.c_double),
+                ("ms_stage", ctypes.c_double * len(STAGES))]
+
+
+_lib = None
+
+
+def load_library():
+    """Load ``libhull2d.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1508_05931_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.hull2d_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(_Options)]
+    lib.hull2d_create.restype = ctypes.c_int
+    lib.hull2d_compute.argtypes = [vp, vp, i64, ctypes.POINTER(i32), i64, ctypes.POINTER(i64),
+                                   ctypes.POINTER(_Stats)]
+    lib.hull2d_compute.restype = ctypes.c_int
+    lib.hull2d_batch.argtypes = [vp, vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32), i64,
+                                 ctypes.POINTER(i64), ctypes.POINTER(_Stats)]
+    lib.hull2d_batch.restype = ctypes.c_int
+    lib.hull2d_destroy.argtypes = [vp]
+    lib.hull2d_destroy.restype = None
+    lib.hull2d_status_string.argtypes = [ctypes.c_int]
+    lib.hull2d_status_string.restype = ctypes.c_char_p
+    lib.hull2d_debug_orient.argtypes = [vp, vp, i64, vp]
+    lib.hull2d_debug_orient.restype = ctypes.c_int
+    lib.hull2d_debug_angle_key.argtypes = [vp, vp, i64, ctypes.c_double, ctypes.c_double, vp]
+    lib.hull2d_debug_angle_key.restype = ctypes.c_int
+    lib.hull2d_debug_stages.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
+    lib.hull2d_debug_stages.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Stats:
+    n: int = 0
+    n_round1: int = 0
+    n_sorted: int = 0
+    n_round2: int = 0
+    n_hull: int = 0
+    ms_total: float = 0.0
+    ms_device: float = 0.0
+    ms_stage: dict = field(default_factory=dict)
+
+    @staticmethod
+    def _from(s: _Stats) -> "Stats":
+        return Stats(s.n, s.n_round1, s.n_sorted, s.n_round2, s.n_hull, s.ms_total,
+                     s.ms_device, {k: float(s.ms_stage[i]) for i, k in enumerate(STAGES)})
+
+
+def _i32p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Hull2D:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
+                 profile: bool = False):
+        import torch
+        lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = int(device)
+        self.stream = stream
+        opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(bool(profile)))
+        h = ctypes.c_void_p()
+        st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
+                               ctypes.byref(opt))
+        if st != OK:
+            raise HullError(st, "hull2d_create")
+        self._h = h
+        self._lib = lib
+        self.last_stats: Stats | None = None
+        self._out = np.empty(1024, dtype=np.int32)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.hull2d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compute(self, xy) -> np.ndarray:
+        """Canonical hull (int32 input indices) of a float64 [n, 2] device tensor."""
+        import torch
+        if not (isinstance(xy, torch.Tensor) and xy.is_cuda and xy.dtype == torch.float64):
+            raise TypeError("xy must be a float64 CUDA tensor of shape [n, 2]")
+        if xy.dim() != 2 or xy.shape[1] != 2 or not xy.is_contiguous():
+            raise ValueError("xy must be a contiguous [n, 2] tensor")
+        n = xy.shape[0]
+        stats = _Stats()
+        hn = ctypes.c_int64(0)
+        for _ in range(2):
+            st = self._lib.hull2d_compute(self._h, ctypes.c_void_p(xy.data_ptr() if n else 0), n,
+                                          _i32p(self._out), self._out.shape[0], ctypes.byref(hn),
+                                          ctypes.byref(stats))
+            if st == CAPACITY:
+                self._out = np.empty(max(int(hn.value), 2 * self._out.shape[0]), dtype=np.int32)
+                continue
+            break
+        if st != OK:
+            raise HullError(st, "hull2d_compute")
+        self.last_stats = Stats._from(stats)
+        return self._out[:hn.value].copy()
+
+    def stages(self, cap: int) -> dict:
+        """Stage results of the last compute (for checking against the model)."""
+        ext = np.zeros(4, dtype=np.int32)
+        srt = np.zeros(max(cap, 1), dtype=np.int32)
+        r2 = np.zeros(max(cap, 1), dtype=np.int32)
+        counts = np.zeros(4, dtype=np.int64)
+        st = self._lib.hull2d_debug_stages(self._h, _i32p(ext), _i32p(srt), _i32p(r2), cap,
+                                           counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        if st != OK:
+            raise HullError(st, "hull2d_debug_stages")
+        ns, l, m2, longest = (int(v) for v in counts)
+        return {"extremes": ext.tolist(), "sorted": srt[:ns].copy(), "l": l,
+                "round2": r2[:m2].copy(), "longest": longest, "m2": m2}
+
+    def debug_orient(self, abc) -> "np.ndarray":
+        import torch
+        abc = abc.contiguous()
+        out = torch.empty(abc.shape[0], dtype=torch.int32, device=abc.device)
+        st = self._lib.hull2d_debug_orient(self._h, ctypes.c_void_p(abc.data_ptr()),
+                                           abc.shape[0], ctypes.c_void_p(out.data_ptr()))
+        if st != OK:
+            raise HullError(st, "hull2d_debug_orient")
+        return out.cpu().numpy()
+
+    def debug_angle_key(self, xy, x0: float, y0: float) -> "np.ndarray":
+        import torch
+        xy = xy.contiguous()
+        out = torch.empty(xy.shape[0], dtype=torch.int32, device=xy.device)
+        st = self._lib.hull2d_debug_angle_key(self._h, ctypes.c_void_p(xy.data_ptr()),
+                                              xy.shape[0], float(x0), float(y0),
+                                              ctypes.c_void_p(out.data_ptr()))
+        if st != OK:
+            raise HullError(st, "hull2d_debug_angle_key")
+        return out.cpu().numpy().view(np.uint32)
+
+
+_default: dict = {}
+
+
+def compute(xy) -> np.ndarray:
+    """Hull of a float64 [n, 2] CUDA tensor on the current device and stream."""
+    import torch
+    dev = xy.device.index if xy.device.index is not None else torch.cuda.current_device()
+    stream = torch.cuda.current_stream(dev)
+    key = (dev, stream.cuda_stream)
+    ctx = _default.get(key)
+    if ctx is None:
+        ctx = Hull2D(dev, stream)
+        _default[key] = ctx
+    return ctx.compute(xy)

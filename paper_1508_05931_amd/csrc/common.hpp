@@ -1,0 +1,99 @@
+// common.hpp - shared device data structures of the hull path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hx {
+
+// One extreme-point candidate of Step 1.
+struct Cand {
+    double x, y;
+    int32_t i;
+    int32_t pad;
+};
+
+// Per-call results that later kernels read (device memory, written once).
+struct Params {
+    Cand ext[4];        // P_minx, P_miny, P_maxx, P_maxy
+    double qx[4], qy[4];  // distinct corners of the quadrilateral, counter-clockwise
+    double ex[4], ey[4];  // edge vectors qx[j+1]-qx[j] (rounded)
+    double qbound;      // float64 error bound valid for every edge test of Step 2
+    double x0, y0;      // pivot P_0 = P_miny
+    int32_t ncorner;    // distinct corners (discard nothing below 3)
+    int32_t p0_idx;
+    uint32_t flags;     // kFlagNonfinite | kFlagRange
+    int32_t pad;
+    // Step 5
+    double lx, ly;      // P_l
+    int32_t l_idx;      // input index of P_l (-1: no sorted points)
+    uint32_t l_slot;    // slot of P_l in the compacted round-1 arrays
+};
+
+constexpr uint32_t kFlagNonfinite = 1u;
+constexpr uint32_t kFlagRange = 2u;
+
+// Results the host reads back at the end of a call.
+struct DevStatus {
+    uint32_t flags;       // domain flags
+    uint32_t huge_runs;   // equal-key runs too long for one workgroup
+    uint32_t n_sorted;    // round-1 survivors other than copies of P_0
+    uint32_t n_p0;        // points equal to P_0 (P_0 included)
+    uint32_t l_pos;       // position of P_l among the sorted survivors
+    uint32_t n_kept;      // round-2 survivors other than P_0
+    uint32_t long_runs;   // equal-key runs handed to the workgroup sorter
+    uint32_t pad;
+    int32_t ext[4];
+    int32_t p0_idx, l_idx;
+    double x0, y0;
+};
+
+// Counters that persist across calls; each kernel that takes tickets resets its
+// own counter when the last ticket has been taken.
+struct Counters {
+    uint32_t ticket[16];
+};
+
+enum TicketId {
+    kTicketFilter1 = 0,
+    kTicketSort0 = 1,  // ..4
+    kTicketRound2 = 5,
+    kTicketCompact = 6,
+    kTicketHist = 7,
+};
+
+// Look-back status word: [epoch:30 | flag:2 | value:32].  The epoch changes
+// on every call, so stale words from an earlier call never look ready and the
+// status arrays need no clearing.
+constexpr uint32_t kStatAggregate = 1u;
+constexpr uint32_t kStatInclusive = 2u;
+
+__device__ inline uint64_t stat_pack(uint32_t epoch, uint32_t flag, uint32_t value) {
+    return ((uint64_t)((epoch << 2) | flag) << 32) | value;
+}
+__device__ inline uint32_t stat_flag(uint64_t w, uint32_t epoch) {
+    uint32_t hi = (uint32_t)(w >> 32);
+    return (hi >> 2) == (epoch & 0x3FFFFFFFu) ? (hi & 3u) : 0u;
+}
+__device__ inline uint32_t stat_value(uint64_t w) { return (uint32_t)w; }
+
+__device__ inline void stat_store(uint64_t* p, uint64_t w) {
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t stat_load(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t take_ticket(uint32_t* c) {
+    return __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void reset_ticket(uint32_t* c) {
+    __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave64 helpers.
+__device__ inline uint64_t lanemask_lt() {
+    uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+}  // namespace hx

@@ -1,0 +1,514 @@
+// hull2d_api.cpp - C ABI of the exact 2D hull library (include/hull2d.h):
+// context and workspace management, the per-call pipeline of gfx950 kernels,
+// and the final Graham stack scan on the host (Step 8 of gScan, Section 3).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "exact.hpp"
+#include "hull2d.h"
+#include "kernels.hpp"
+
+using namespace hx;
+
+struct hull2d_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hull2d_options opt{};
+    int cu_count = 256;
+    bool broken = false;
+
+    // device workspace (grows on demand)
+    int64_t cap_n = -1;
+    char* dmem = nullptr;
+    Cand* partial = nullptr;
+    Params* prm = nullptr;
+    DevStatus* ds = nullptr;
+    uint32_t* hist = nullptr;
+    double2* comp_xy = nullptr;
+    uint32_t* comp_idx = nullptr;
+    uint32_t *keys_a = nullptr, *keys_b = nullptr, *vals_a = nullptr, *vals_b = nullptr;
+    uint64_t* stat = nullptr;
+    double* tile_d2 = nullptr;
+    uint32_t* tile_best = nullptr;
+    uint32_t* long_list = nullptr;
+    uint32_t* huge_list = nullptr;
+    uint8_t* keep = nullptr;
+    double2* out_xy = nullptr;
+    int32_t* out_idx = nullptr;
+    Counters* ctr = nullptr;  // separate allocation, zeroed once, persists
+
+    // pinned host buffers
+    DevStatus* h_ds = nullptr;
+    double2* h_xy = nullptr;
+    int32_t* h_idx = nullptr;
+    int64_t h_cap = 0;
+
+    uint32_t epoch = 0;
+    hipEvent_t ev[HULL2D_NUM_STAGES + 2] = {};  // per stage, then begin and end
+    bool have_events = false;
+
+    // the last compute call, for hull2d_debug_stages
+    bool have_last = false;
+    int64_t last_n = 0;
+    DevStatus last_ds{};
+};
+
+namespace {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t off[20];
+    size_t total;
+};
+
+Layout plan(int64_t n) {
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    const size_t sort_tiles = (size_t)ceil_div((int64_t)N, kSortTile);
+    const size_t f1_tiles = (size_t)ceil_div((int64_t)N, kF1Tile);
+    size_t stat_words = sort_tiles * 256;
+    stat_words = std::max(stat_words, f1_tiles + 2);
+    stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kR2Tile) + 4);
+    stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kCpTile) + 2);
+    const size_t sizes[20] = {
+        (size_t)kExtGridMax * 4 * sizeof(Cand),      // 0 partial
+        sizeof(Params),                              // 1
+        sizeof(DevStatus),                           // 2
+        4 * 256 * sizeof(uint32_t),                  // 3 hist
+        N * sizeof(double2),                         // 4 comp_xy
+        N * sizeof(uint32_t),                        // 5 comp_idx
+        N * sizeof(uint32_t),                        // 6 keys_a
+        N * sizeof(uint32_t),                        // 7 keys_b
+        N * sizeof(uint32_t),                        // 8 vals_a
+        N * sizeof(uint32_t),                        // 9 vals_b
+        stat_words * sizeof(uint64_t),               // 10 stat
+        f1_tiles * sizeof(double),                   // 11 tile_d2
+        f1_tiles * 2 * sizeof(uint32_t),             // 12 tile_best
+        (N / (kRunSmall + 1) + 2) * sizeof(uint32_t),  // 13 long_list
+        (N / kRunCap + 2) * 2 * sizeof(uint32_t),    // 14 huge_list
+        align_up(N, kCpTile) + kCpTile,              // 15 keep (padded for 16-byte loads)
+        N * sizeof(double2),                         // 16 out_xy
+        N * sizeof(int32_t),                         // 17 out_idx
+        0, 0};
+    Layout L{};
+    size_t o = 0;
+    for (int i = 0; i < 20; ++i) {
+        L.off[i] = o;
+        o = align_up(o + sizes[i], 256);
+    }
+    L.total = o;
+    return L;
+}
+
+hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
+    if (n <= c->cap_n) return HULL2D_OK;
+    int64_t want = n;
+    if (c->cap_n > 0 && want < c->cap_n + c->cap_n / 4) want = c->cap_n + c->cap_n / 4;
+    if (c->dmem) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->dmem);
+        c->dmem = nullptr;
+        c->cap_n = -1;
+    }
+    Layout L = plan(want);
+    if (hipMalloc((void**)&c->dmem, L.total) != hipSuccess) {
+        (void)hipGetLastError();
+        c->dmem = nullptr;
+        return HULL2D_ERR_OUT_OF_MEMORY;
+    }
+    char* b = c->dmem;
+    c->partial = (Cand*)(b + L.off[0]);
+    c->prm = (Params*)(b + L.off[1]);
+    c->ds = (DevStatus*)(b + L.off[2]);
+    c->hist = (uint32_t*)(b + L.off[3]);
+    c->comp_xy = (double2*)(b + L.off[4]);
+    c->comp_idx = (uint32_t*)(b + L.off[5]);
+    c->keys_a = (uint32_t*)(b + L.off[6]);
+    c->keys_b = (uint32_t*)(b + L.off[7]);
+    c->vals_a = (uint32_t*)(b + L.off[8]);
+    c->vals_b = (uint32_t*)(b + L.off[9]);
+    c->stat = (uint64_t*)(b + L.off[10]);
+    c->tile_d2 = (double*)(b + L.off[11]);
+    c->tile_best = (uint32_t*)(b + L.off[12]);
+    c->long_list = (uint32_t*)(b + L.off[13]);
+    c->huge_list = (uint32_t*)(b + L.off[14]);
+    c->keep = (uint8_t*)(b + L.off[15]);
+    c->out_xy = (double2*)(b + L.off[16]);
+    c->out_idx = (int32_t*)(b + L.off[17]);
+    // Look-back words carry the call's epoch; zero means "not ready" for any epoch.
+    if (hipMemsetAsync(c->stat, 0, L.off[11] - L.off[10], c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->broken = true;
+        return HULL2D_ERR_DEVICE;
+    }
+    c->cap_n = want;
+    return HULL2D_OK;
+}
+
+hull2d_status ensure_host(hull2d_ctx* c, int64_t m) {
+    if (m <= c->h_cap) return HULL2D_OK;
+    int64_t want = std::max<int64_t>(m, 4096);
+    if (c->h_xy) (void)hipHostFree(c->h_xy);
+    if (c->h_idx) (void)hipHostFree(c->h_idx);
+    c->h_xy = nullptr;
+    c->h_idx = nullptr;
+    c->h_cap = 0;
+    if (hipHostMalloc((void**)&c->h_xy, (size_t)want * sizeof(double2), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_idx, (size_t)want * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return HULL2D_ERR_OUT_OF_MEMORY;
+    }
+    c->h_cap = want;
+    return HULL2D_OK;
+}
+
+int grid_for(const hull2d_ctx* c, int64_t tiles, int per_cu) {
+    int64_t g = std::min<int64_t>(tiles, (int64_t)c->cu_count * per_cu);
+    return (int)std::max<int64_t>(g, 1);
+}
+
+#define HX_TRY(call)                      \
+    do {                                  \
+        if ((call) != hipSuccess) {       \
+            (void)hipGetLastError();      \
+            c->broken = true;             \
+            return HULL2D_ERR_DEVICE;     \
+        }                                 \
+    } while (0)
+
+// Step 8 (Section 3): Graham stack scan of the kept points, already in
+// angular order with the pivot first.  A non-left turn pops (collinear points
+// are dropped), a repeat of the top point is skipped (the first copy has the
+// smallest index).  The result is rotated to start at the lexicographically
+// smallest vertex.
+int64_t graham_scan(double x0, double y0, int32_t i0, const double2* pts, const int32_t* idx,
+                    int64_t m, std::vector<int64_t>& st, std::vector<int32_t>& out) {
+    st.clear();
+    auto X = [&](int64_t k) { return k < 0 ? x0 : pts[k].x; };
+    auto Y = [&](int64_t k) { return k < 0 ? y0 : pts[k].y; };
+    st.push_back(-1);  // the pivot
+    for (int64_t k = 0; k < m; ++k) {
+        const double px = pts[k].x, py = pts[k].y;
+        int64_t t = st.back();
+        if (X(t) == px && Y(t) == py) continue;
+        while (st.size() >= 2) {
+            int64_t a = st[st.size() - 2], b = st.back();
+            if (orient(X(a), Y(a), X(b), Y(b), px, py) > 0) break;
+            st.pop_back();
+        }
+        st.push_back(k);
+    }
+    const size_t h = st.size();
+    size_t start = 0;
+    for (size_t k = 1; k < h; ++k) {
+        double x = X(st[k]), y = Y(st[k]);
+        double bx = X(st[start]), by = Y(st[start]);
+        if (x < bx || (x == bx && y < by)) start = k;
+    }
+    out.resize(h);
+    for (size_t k = 0; k < h; ++k) {
+        int64_t s = st[(start + k) % h];
+        out[k] = s < 0 ? i0 : idx[s];
+    }
+    return (int64_t)h;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hull2d_status_string(hull2d_status s) {
+    switch (s) {
+        case HULL2D_OK: return "ok";
+        case HULL2D_ERR_INVALID_ARG: return "invalid argument";
+        case HULL2D_ERR_NONFINITE: return "non-finite coordinate";
+        case HULL2D_ERR_RANGE: return "coordinate magnitude outside [2^-300, 2^300]";
+        case HULL2D_ERR_CAPACITY: return "output capacity too small";
+        case HULL2D_ERR_OUT_OF_MEMORY: return "out of memory";
+        case HULL2D_ERR_DEVICE: return "device error";
+        case HULL2D_ERR_WEIGHTS: return "learned-filter weights missing or corrupt";
+        case HULL2D_ERR_UNIMPLEMENTED: return "not implemented";
+    }
+    return "unknown status";
+}
+
+hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
+                            const hull2d_options* opt) {
+    if (!out) return HULL2D_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (opt && opt->struct_size < sizeof(uint32_t) + sizeof(int32_t)) return HULL2D_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return ndev > 0 ? HULL2D_ERR_INVALID_ARG : HULL2D_ERR_DEVICE;
+    }
+    hull2d_ctx* c = new (std::nothrow) hull2d_ctx();
+    if (!c) return HULL2D_ERR_OUT_OF_MEMORY;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->opt.struct_size = sizeof(hull2d_options);
+    c->opt.round2_chunk = 0;
+    if (opt) {
+        size_t n = std::min<size_t>(opt->struct_size, sizeof(hull2d_options));
+        std::memcpy(&c->opt, opt, n);
+        c->opt.struct_size = sizeof(hull2d_options);
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return HULL2D_ERR_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->cu_count = prop.multiProcessorCount;
+    if (hipMalloc((void**)&c->ctr, sizeof(Counters)) != hipSuccess ||
+        hipMemset(c->ctr, 0, sizeof(Counters)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_ds, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        hull2d_destroy(c);
+        return HULL2D_ERR_OUT_OF_MEMORY;
+    }
+    bool ev_ok = true;
+    for (int i = 0; i < HULL2D_NUM_STAGES + 2; ++i)
+        ev_ok = ev_ok && hipEventCreate(&c->ev[i]) == hipSuccess;
+    c->have_events = ev_ok;
+    *out = c;
+    return HULL2D_OK;
+}
+
+void hull2d_destroy(hull2d_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream || c->dmem) (void)hipStreamSynchronize(c->stream);
+    if (c->dmem) (void)hipFree(c->dmem);
+    if (c->ctr) (void)hipFree(c->ctr);
+    if (c->h_ds) (void)hipHostFree(c->h_ds);
+    if (c->h_xy) (void)hipHostFree(c->h_xy);
+    if (c->h_idx) (void)hipHostFree(c->h_idx);
+    for (int i = 0; i < HULL2D_NUM_STAGES + 2; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    delete c;
+}
+
+hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32_t* h_out,
+                             int64_t cap, int64_t* n_out, hull2d_stats* stats) {
+    auto t_start = std::chrono::steady_clock::now();
+    if (!c || !n_out || n < 0 || cap < 0 || (n > 0 && !d_xy) || (cap > 0 && !h_out))
+        return HULL2D_ERR_INVALID_ARG;
+    if (n > (int64_t)INT32_MAX) return HULL2D_ERR_INVALID_ARG;
+    if (c->broken) return HULL2D_ERR_DEVICE;
+    *n_out = 0;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->n = n;
+    }
+    c->have_last = false;
+    if (n == 0) return HULL2D_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    hull2d_status st = ensure_workspace(c, n);
+    if (st != HULL2D_OK) return st;
+
+    const bool prof = c->opt.profile && c->have_events;
+    hipStream_t s = c->stream;
+    auto mark = [&](int i) {
+        if (prof) (void)hipEventRecord(c->ev[i], s);
+    };
+    hipEvent_t ev_begin = c->ev[HULL2D_NUM_STAGES];
+    hipEvent_t ev_end = c->ev[HULL2D_NUM_STAGES + 1];
+    if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
+
+    // Step 1
+    const int grid_ext = (int)std::max<int64_t>(1, std::min<int64_t>(kExtGridMax, ceil_div(n, kExtBlock * 4)));
+    HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, s));
+    mark(HULL2D_STAGE_EXTREMES);
+    // Steps 2-3
+    const uint32_t e_f1 = ++c->epoch;
+    HX_TRY(launch_filter1(d_xy, n, c->prm, c->comp_xy, c->comp_idx, c->keys_a, c->stat, c->tile_d2,
+                          c->tile_best, c->ds, c->ctr, e_f1, grid_for(c, ceil_div(n, kF1Tile), 8), s));
+    mark(HULL2D_STAGE_FILTER1);
+    // Step 5 (needs every survivor's distance; the sort does not)
+    HX_TRY(launch_longest(n, c->tile_d2, c->tile_best, c->comp_xy, c->prm, c->ds, s));
+    mark(HULL2D_STAGE_LONGEST);
+    // Step 4
+    HX_TRY(launch_histogram(c->keys_a, c->ds, c->hist,
+                            (int)std::min<int64_t>(kHistGridMax, std::max<int64_t>(1, ceil_div(n, 4096))), s));
+    mark(HULL2D_STAGE_HISTOGRAM);
+    const int grid_sort = grid_for(c, ceil_div(n, kSortTile), 4);
+    uint32_t* kin = c->keys_a;
+    uint32_t* vin = nullptr;
+    uint32_t* kout = c->keys_b;
+    uint32_t* vout = c->vals_b;
+    for (int pass = 0; pass < 4; ++pass) {
+        const uint32_t e = ++c->epoch;
+        HX_TRY(launch_sort_pass(pass, kin, vin, kout, vout, c->hist, c->ds, c->stat, c->ctr, e,
+                                grid_sort, s));
+        mark(HULL2D_STAGE_SORT0 + pass);
+        kin = kout;
+        vin = vout;
+        kout = (kout == c->keys_b) ? c->keys_a : c->keys_b;
+        vout = (vout == c->vals_b) ? c->vals_a : c->vals_b;
+    }
+    uint32_t* keys = kin;   // after four passes: keys_a / vals_a
+    uint32_t* slots = vin;
+    HX_TRY(launch_ties(n, keys, slots, c->comp_xy, c->comp_idx, c->prm, c->ds, c->long_list, s));
+    mark(HULL2D_STAGE_TIES);
+    HX_TRY(launch_ties_long(keys, slots, c->comp_xy, c->comp_idx, c->prm, c->ds, c->long_list,
+                            c->huge_list, c->cu_count, s));
+    mark(HULL2D_STAGE_TIES_LONG);
+    // Steps 6-7
+    if (c->opt.round2_chunk == 0) {
+        const uint32_t e = ++c->epoch;
+        HX_TRY(launch_round2_scan(slots, c->comp_xy, c->prm, c->ds, c->keep, c->stat, c->ctr, e,
+                                  grid_for(c, ceil_div(n, kR2Tile) + 2, 8), s));
+    } else {
+        HX_TRY(launch_round2_chunks(n, c->opt.round2_chunk, slots, c->comp_xy, c->prm, c->ds,
+                                    c->keep, s));
+    }
+    mark(HULL2D_STAGE_ROUND2);
+    {
+        const uint32_t e = ++c->epoch;
+        HX_TRY(launch_compact(c->keep, slots, c->comp_xy, c->comp_idx, c->out_xy, c->out_idx, c->ds,
+                              c->stat, c->ctr, e, grid_for(c, ceil_div(n, kCpTile), 8), s));
+    }
+    mark(HULL2D_STAGE_COMPACT);
+    HX_TRY(hipMemcpyAsync(c->h_ds, c->ds, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HX_TRY(hipStreamSynchronize(s));
+    const DevStatus D = *c->h_ds;
+    if (D.flags & kFlagNonfinite) return HULL2D_ERR_NONFINITE;
+    if (D.flags & kFlagRange) return HULL2D_ERR_RANGE;
+    if (D.huge_runs > 0) return HULL2D_ERR_UNIMPLEMENTED;
+    const int64_t m = (int64_t)D.n_kept;
+    st = ensure_host(c, m);
+    if (st != HULL2D_OK) return st;
+    auto t_d2h = std::chrono::steady_clock::now();
+    if (m > 0) {
+        HX_TRY(hipMemcpyAsync(c->h_xy, c->out_xy, (size_t)m * sizeof(double2), hipMemcpyDeviceToHost, s));
+        HX_TRY(hipMemcpyAsync(c->h_idx, c->out_idx, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    mark(HULL2D_STAGE_D2H);
+    if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
+    HX_TRY(hipStreamSynchronize(s));
+    const double ms_d2h_wall = ms_since(t_d2h);
+
+    auto t_scan = std::chrono::steady_clock::now();
+    std::vector<int64_t> stk;
+    std::vector<int32_t> hull;
+    stk.reserve((size_t)m + 1);
+    const int64_t h = graham_scan(D.x0, D.y0, D.p0_idx, c->h_xy, c->h_idx, m, stk, hull);
+    const double ms_scan = ms_since(t_scan);
+
+    c->have_last = true;
+    c->last_n = n;
+    c->last_ds = D;
+
+    *n_out = h;
+    if (stats) {
+        stats->n_round1 = (int64_t)D.n_sorted + (int64_t)D.n_p0;
+        stats->n_sorted = D.n_sorted;
+        stats->n_round2 = m + 1;
+        stats->n_hull = h;
+        if (c->have_events) {
+            float f = 0.f;
+            if (hipEventElapsedTime(&f, ev_begin, ev_end) == hipSuccess)
+                stats->ms_device = f;
+        }
+        if (prof) {
+            // stage i ends at event i; Step 1's two kernels are reported
+            // together under EXTREMES.
+            const int order[] = {HULL2D_STAGE_EXTREMES, HULL2D_STAGE_FILTER1, HULL2D_STAGE_LONGEST,
+                                 HULL2D_STAGE_HISTOGRAM, HULL2D_STAGE_SORT0, HULL2D_STAGE_SORT1,
+                                 HULL2D_STAGE_SORT2, HULL2D_STAGE_SORT3, HULL2D_STAGE_TIES,
+                                 HULL2D_STAGE_TIES_LONG, HULL2D_STAGE_ROUND2, HULL2D_STAGE_COMPACT,
+                                 HULL2D_STAGE_D2H};
+            hipEvent_t prev = ev_begin;
+            for (int k = 0; k < (int)(sizeof(order) / sizeof(order[0])); ++k) {
+                float f = 0.f;
+                if (hipEventElapsedTime(&f, prev, c->ev[order[k]]) == hipSuccess)
+                    stats->ms_stage[order[k]] = f;
+                prev = c->ev[order[k]];
+            }
+        }
+        stats->ms_stage[HULL2D_STAGE_HOST_SCAN] = ms_scan;
+        if (!prof) stats->ms_stage[HULL2D_STAGE_D2H] = ms_d2h_wall;
+    }
+    if (h > cap) {
+        if (stats) stats->ms_total = ms_since(t_start);
+        return HULL2D_ERR_CAPACITY;
+    }
+    std::memcpy(h_out, hull.data(), (size_t)h * sizeof(int32_t));
+    if (stats) stats->ms_total = ms_since(t_start);
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_offsets, int32_t S,
+                           int32_t* h_out, int64_t cap, int64_t* h_out_offsets,
+                           hull2d_stats* stats) {
+    if (!c || S < 0 || !h_offsets || !h_out_offsets || cap < 0 || (cap > 0 && !h_out))
+        return HULL2D_ERR_INVALID_ARG;
+    if (h_offsets[0] != 0) return HULL2D_ERR_INVALID_ARG;
+    for (int32_t s = 0; s < S; ++s)
+        if (h_offsets[s + 1] < h_offsets[s] || h_offsets[s + 1] - h_offsets[s] > (int64_t)INT32_MAX)
+            return HULL2D_ERR_INVALID_ARG;
+    if (h_offsets[S] > 0 && !d_xy) return HULL2D_ERR_INVALID_ARG;
+    (void)stats;
+    return HULL2D_ERR_UNIMPLEMENTED;
+}
+
+hull2d_status hull2d_debug_orient(hull2d_ctx* c, const double* d_abc, int64_t count, int32_t* d_out) {
+    if (!c || count < 0 || (count > 0 && (!d_abc || !d_out))) return HULL2D_ERR_INVALID_ARG;
+    if (c->broken) return HULL2D_ERR_DEVICE;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    HX_TRY(launch_debug_orient(d_abc, count, d_out, c->stream));
+    HX_TRY(hipStreamSynchronize(c->stream));
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_debug_angle_key(hull2d_ctx* c, const double* d_xy, int64_t count, double x0,
+                                     double y0, uint32_t* d_out) {
+    if (!c || count < 0 || (count > 0 && (!d_xy || !d_out))) return HULL2D_ERR_INVALID_ARG;
+    if (c->broken) return HULL2D_ERR_DEVICE;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    HX_TRY(launch_debug_key(d_xy, count, x0, y0, d_out, c->stream));
+    HX_TRY(hipStreamSynchronize(c->stream));
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_debug_stages(hull2d_ctx* c, int32_t* extremes, int32_t* sorted, int32_t* round2,
+                                  int64_t cap, int64_t* counts) {
+    if (!c || cap < 0) return HULL2D_ERR_INVALID_ARG;
+    if (!c->have_last) return HULL2D_ERR_INVALID_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    const DevStatus& D = c->last_ds;
+    const int64_t ms = D.n_sorted, m2 = (int64_t)D.n_kept + 1;
+    if (counts) {
+        counts[0] = ms;
+        counts[1] = ms > 0 ? (int64_t)D.l_pos + 1 : 0;
+        counts[2] = m2;
+        counts[3] = D.l_idx;
+    }
+    if (extremes)
+        for (int k = 0; k < 4; ++k) extremes[k] = D.ext[k];
+    if ((sorted && cap < ms) || (round2 && cap < m2)) return HULL2D_ERR_CAPACITY;
+    if (sorted && ms > 0) {
+        // the sorted slots sit in vals_a after four passes
+        std::vector<uint32_t> sl((size_t)ms), ix((size_t)c->last_n);
+        HX_TRY(hipMemcpy(sl.data(), c->vals_a, (size_t)ms * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HX_TRY(hipMemcpy(ix.data(), c->comp_idx, (size_t)ms * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < ms; ++i) sorted[i] = (int32_t)ix[sl[i]];
+    }
+    if (round2) {
+        round2[0] = D.p0_idx;
+        for (int64_t i = 0; i + 1 < m2; ++i) round2[i + 1] = c->h_idx[i];
+    }
+    return HULL2D_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,949 @@
+// kernels_filter.hip - Steps 1-3 and 5-7 of gScan on gfx950.
+//
+//   k_extremes / k_extremes_final  Step 1: four extreme points (Section 3.1)
+//   k_filter1                      Step 2: discard points strictly inside the
+//                                  quadrilateral (Section 3.1), fused with
+//                                  Step 3 (exact angle key and squared
+//                                  distance, Section 3.2) and an
+//                                  order-preserving compaction
+//   k_longest                      Step 5: farthest point from the pivot
+//   k_round2_scan                  Steps 6-7: the Figure 2 filter, each region
+//                                  as one walk, evaluated as a prefix scan
+//   k_round2_chunks                Steps 6-7 with the paper's subsets, one
+//                                  thread per subset (Section 3.4)
+//   k_compact                      Step 7: stable removal of interior points
+//
+// Streaming kernels take tiles from a ticket counter (tiles are started in
+// order) and chain tile prefixes by decoupled look-back (Merrill & Garland,
+// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016).
+#include <float.h>
+
+#include "exact.hpp"
+#include "kernels.hpp"
+
+namespace hx {
+namespace {
+
+constexpr uint32_t kSlotP0 = 0xFFFFFFFFu;    // stands for the pivot P_0
+constexpr uint32_t kSlotNone = 0xFFFFFFFEu;  // identity of the running maximum
+
+// ---------------------------------------------------------------------------
+// wave64 primitives
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Decoupled look-back for a sum, run by one whole wave.  Publishes the tile's
+// aggregate, walks back over predecessors 64 at a time until an inclusive
+// prefix is found, publishes its own inclusive prefix and returns the
+// exclusive prefix (same value in every lane).
+__device__ uint32_t lookback_sum(uint64_t* stat, uint32_t t, uint32_t agg, uint32_t epoch) {
+    const uint32_t lane = __lane_id();
+    if (t == 0) {
+        if (lane == 0) stat_store(&stat[0], stat_pack(epoch, kStatInclusive, agg));
+        return 0;
+    }
+    if (lane == 0) stat_store(&stat[t], stat_pack(epoch, kStatAggregate, agg));
+    uint32_t excl = 0;
+    int64_t top = (int64_t)t - 1;
+    for (;;) {
+        int64_t me = top - (int64_t)lane;
+        uint32_t f = kStatInclusive, v = 0;
+        if (me >= 0) {
+            uint64_t w = stat_load(&stat[me]);
+            f = stat_flag(w, epoch);
+            v = stat_value(w);
+        }
+        uint64_t incl = __ballot(f == kStatInclusive);
+        uint64_t notready = __ballot(f == 0u);
+        uint32_t first = incl ? (uint32_t)(__ffsll((unsigned long long)incl) - 1) : 64u;
+        uint64_t upto = first >= 63u ? ~0ull : ((2ull << first) - 1ull);
+        if (notready & upto) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_sum(lane <= first ? v : 0u);
+        if (first < 64u) break;
+        top -= 64;
+    }
+    if (lane == 0) stat_store(&stat[t], stat_pack(epoch, kStatInclusive, excl + agg));
+    return excl;
+}
+
+// ---------------------------------------------------------------------------
+// Step 1
+// ---------------------------------------------------------------------------
+// Strict total orders of the four extreme criteria (ties: P_minx -> larger y,
+// P_miny -> smaller x, P_maxx -> smaller y, P_maxy -> larger x, then smaller
+// index), so every reduction order returns the same candidates.
+template <int C>
+__device__ inline bool better(const Cand& a, const Cand& b) {
+    if (C == 0) return a.x < b.x || (a.x == b.x && (a.y > b.y || (a.y == b.y && a.i < b.i)));
+    if (C == 1) return a.y < b.y || (a.y == b.y && (a.x < b.x || (a.x == b.x && a.i < b.i)));
+    if (C == 2) return a.x > b.x || (a.x == b.x && (a.y < b.y || (a.y == b.y && a.i < b.i)));
+    return a.y > b.y || (a.y == b.y && (a.x > b.x || (a.x == b.x && a.i < b.i)));
+}
+
+__device__ inline Cand sentinel(int c) {
+    Cand s;
+    s.i = INT32_MAX;
+    s.pad = 0;
+    s.x = (c == 0 || c == 1) ? INFINITY : -INFINITY;
+    s.y = (c == 1 || c == 2) ? INFINITY : -INFINITY;
+    return s;
+}
+
+__device__ inline Cand shfl_xor_cand(const Cand& c, int m) {
+    Cand r;
+    r.x = __shfl_xor(c.x, m);
+    r.y = __shfl_xor(c.y, m);
+    r.i = __shfl_xor(c.i, m);
+    r.pad = 0;
+    return r;
+}
+
+template <int C>
+__device__ inline void take_better(Cand& c, const Cand& o) {
+    if (better<C>(o, c)) c = o;
+}
+
+__device__ inline void reduce4_wave(Cand (&c)[4]) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        take_better<0>(c[0], shfl_xor_cand(c[0], m));
+        take_better<1>(c[1], shfl_xor_cand(c[1], m));
+        take_better<2>(c[2], shfl_xor_cand(c[2], m));
+        take_better<3>(c[3], shfl_xor_cand(c[3], m));
+    }
+}
+
+__device__ inline uint32_t domain_flags(double v) {
+    double a = fabs(v);
+    if (!(a <= DBL_MAX)) return kFlagNonfinite;
+    if (a != 0.0 && (a < 0x1p-300 || a > 0x1p300)) return kFlagRange;
+    return 0u;
+}
+
+__device__ inline void offer(Cand (&c)[4], double x, double y, int32_t i) {
+    Cand p;
+    p.x = x;
+    p.y = y;
+    p.i = i;
+    p.pad = 0;
+    take_better<0>(c[0], p);
+    take_better<1>(c[1], p);
+    take_better<2>(c[2], p);
+    take_better<3>(c[3], p);
+}
+
+__global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restrict__ xy, int64_t n,
+                                                        Cand* __restrict__ partial) {
+    constexpr int NW = kExtBlock / 64;
+    constexpr int U = 4;
+    __shared__ Cand s_c[NW][4];
+    __shared__ uint32_t s_flags;
+    Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
+    uint32_t bad = 0;
+    if (threadIdx.x == 0) s_flags = 0;
+    const int64_t stride = (int64_t)gridDim.x * kExtBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kExtBlock + threadIdx.x; i < n; i += stride * U) {
+        double2 p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t j = i + u * stride;
+            if (j < n) p[u] = xy[j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t j = i + u * stride;
+            if (j < n) {
+                offer(c, p[u].x, p[u].y, (int32_t)j);
+                bad |= domain_flags(p[u].x) | domain_flags(p[u].y);
+            }
+        }
+    }
+    reduce4_wave(c);
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    __syncthreads();
+    if (bad) atomicOr(&s_flags, bad);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_c[wave][k] = c[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        int k = (int)threadIdx.x;
+        Cand b = s_c[0][k];
+        for (int w = 1; w < NW; ++w) {
+            Cand o = s_c[w][k];
+            bool take = k == 0 ? better<0>(o, b) : k == 1 ? better<1>(o, b)
+                      : k == 2 ? better<2>(o, b) : better<3>(o, b);
+            if (take) b = o;
+        }
+        b.pad = (int32_t)s_flags;
+        partial[(int64_t)blockIdx.x * 4 + k] = b;
+    }
+}
+
+// One block: final reduction of the partial candidates, the distinct
+// counter-clockwise corners P_minx -> P_miny -> P_maxx -> P_maxy, the pivot,
+// and the per-call reset of the status fields later kernels accumulate into.
+__global__ __launch_bounds__(256) void k_extremes_final(const Cand* __restrict__ partial, int nblocks,
+                                                        Params* __restrict__ prm,
+                                                        DevStatus* __restrict__ ds) {
+    constexpr int NW = 256 / 64;
+    __shared__ Cand s_c[NW][4];
+    __shared__ uint32_t s_flags;
+    if (threadIdx.x == 0) s_flags = 0;
+    __syncthreads();
+    Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
+    uint32_t bad = 0;
+    for (int b = (int)threadIdx.x; b < nblocks; b += 256) {
+        take_better<0>(c[0], partial[b * 4 + 0]);
+        take_better<1>(c[1], partial[b * 4 + 1]);
+        take_better<2>(c[2], partial[b * 4 + 2]);
+        take_better<3>(c[3], partial[b * 4 + 3]);
+        bad |= (uint32_t)partial[b * 4 + 0].pad;
+    }
+    reduce4_wave(c);
+    if (bad) atomicOr(&s_flags, bad);
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_c[wave][k] = c[k];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    Cand e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = s_c[0][k];
+    for (int w = 1; w < NW; ++w) {
+        take_better<0>(e[0], s_c[w][0]);
+        take_better<1>(e[1], s_c[w][1]);
+        take_better<2>(e[2], s_c[w][2]);
+        take_better<3>(e[3], s_c[w][3]);
+    }
+    Params P;
+    for (int k = 0; k < 4; ++k) {
+        e[k].pad = 0;
+        P.ext[k] = e[k];
+    }
+    int nc = 0;
+    for (int k = 0; k < 4; ++k) {
+        bool dup = false;
+        for (int j = 0; j < nc; ++j) dup |= (P.qx[j] == e[k].x && P.qy[j] == e[k].y);
+        if (!dup) {
+            P.qx[nc] = e[k].x;
+            P.qy[nc] = e[k].y;
+            ++nc;
+        }
+    }
+    for (int j = nc; j < 4; ++j) {
+        P.qx[j] = P.qx[0];
+        P.qy[j] = P.qy[0];
+    }
+    for (int j = 0; j < 4; ++j) {
+        int j1 = (j + 1) % (nc > 0 ? nc : 1);
+        P.ex[j] = P.qx[j1] - P.qx[j];
+        P.ey[j] = P.qy[j1] - P.qy[j];
+    }
+    // Every point and corner lies in the bounding box W x H, so for an edge
+    // test ex*dy - ey*dx (four rounded differences, two rounded products, one
+    // rounded difference) |ex dy| + |ey dx| <= 2WH and the rounding error is
+    // below 4.01 eps * 2WH; 9 eps W H also covers the rounding of W and H.
+    double W = e[2].x - e[0].x, H = e[3].y - e[1].y;
+    P.qbound = 9.0 * kEps * W * H;
+    P.ncorner = nc;
+    P.x0 = e[1].x;
+    P.y0 = e[1].y;
+    P.p0_idx = e[1].i;
+    P.flags = s_flags;
+    P.pad = 0;
+    P.lx = P.x0;
+    P.ly = P.y0;
+    P.l_idx = -1;
+    P.l_slot = kSlotNone;
+    *prm = P;
+    DevStatus S;
+    S.flags = s_flags;
+    S.huge_runs = 0;
+    S.n_sorted = 0;
+    S.n_p0 = 0;
+    S.l_pos = 0;
+    S.n_kept = 0;
+    S.long_runs = 0;
+    S.pad = 0;
+    for (int k = 0; k < 4; ++k) S.ext[k] = e[k].i;
+    S.p0_idx = e[1].i;
+    S.l_idx = -1;
+    S.x0 = P.x0;
+    S.y0 = P.y0;
+    *ds = S;
+}
+
+// ---------------------------------------------------------------------------
+// Steps 2-3
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kF1Block) void k_filter1(
+    const double2* __restrict__ xy, int64_t n, const Params* __restrict__ prm,
+    double2* __restrict__ comp_xy, uint32_t* __restrict__ comp_idx, uint32_t* __restrict__ keys,
+    uint64_t* __restrict__ stat, double* __restrict__ tile_d2, uint32_t* __restrict__ tile_best,
+    DevStatus* __restrict__ ds, Counters* __restrict__ ctr, uint32_t epoch) {
+    constexpr int NW = kF1Block / 64;
+    constexpr int G = kF1Ipt * NW;  // (item, wave) groups in position order
+    __shared__ uint32_t s_ticket;
+    __shared__ uint32_t s_off[G];
+    __shared__ uint32_t s_excl;
+    __shared__ double s_bd2[NW];
+    __shared__ uint32_t s_bidx[NW], s_bslot[NW], s_p0[NW];
+
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int nc = prm->ncorner;
+    const bool discard_all = prm->flags != 0u;
+    const double x0 = prm->x0, y0 = prm->y0, qb = prm->qbound;
+    double qx[4], qy[4], ex[4], ey[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        qx[j] = prm->qx[j];
+        qy[j] = prm->qy[j];
+        ex[j] = prm->ex[j];
+        ey[j] = prm->ey[j];
+    }
+    const uint32_t ntiles = (uint32_t)ceil_div(n, kF1Tile);
+    uint32_t* ticket = &ctr->ticket[kTicketFilter1];
+
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = take_ticket(ticket);
+        __syncthreads();
+        const uint32_t t = s_ticket;
+        __syncthreads();
+        if (t >= ntiles) {
+            if (threadIdx.x == 0 && t == ntiles + gridDim.x - 1) reset_ticket(ticket);
+            break;
+        }
+        const int64_t base = (int64_t)t * kF1Tile;
+        double2 p[kF1Ipt];
+#pragma unroll
+        for (int k = 0; k < kF1Ipt; ++k) {
+            int64_t pos = base + k * kF1Block + threadIdx.x;
+            if (pos < n) p[k] = xy[pos];
+        }
+        uint64_t mask[kF1Ipt];
+        uint32_t key[kF1Ipt];
+        double bd2 = -1.0;
+        uint32_t bidx = 0xFFFFFFFFu, bgrp = 0, brank = 0;
+        uint32_t p0c = 0;
+#pragma unroll
+        for (int k = 0; k < kF1Ipt; ++k) {
+            int64_t pos = base + k * kF1Block + threadIdx.x;
+            bool surv = false;
+            key[k] = 0;
+            if (pos < n && !discard_all) {
+                const double px = p[k].x, py = p[k].y;
+                bool inside = nc >= 3;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (inside && j < nc) {
+                        double dx = px - qx[j], dy = py - qy[j];
+                        double l = ex[j] * dy;
+                        double r = ey[j] * dx;
+                        double det = l - r;
+                        int o = det > qb ? 1 : (-det > qb ? -1 : 0);
+                        if (o == 0) {
+                            int j1 = (j + 1) % nc;
+                            o = orient(qx[j], qy[j], qx[j1], qy[j1], px, py);
+                        }
+                        inside = o > 0;
+                    }
+                }
+                surv = !inside;
+                if (surv && px == x0 && py == y0) {
+                    surv = false;
+                    ++p0c;
+                }
+                if (surv) {
+                    key[k] = angle_key(px, py, x0, y0);
+                    double dx = px - x0, dy = py - y0;
+                    double dxx = dx * dx;
+                    double dyy = dy * dy;
+                    double d2 = dxx + dyy;
+                    if (d2 > bd2 || (d2 == bd2 && (uint32_t)pos < bidx)) {
+                        bd2 = d2;
+                        bidx = (uint32_t)pos;
+                        bgrp = (uint32_t)(k * NW + wave);
+                    }
+                }
+            }
+            mask[k] = __ballot(surv);
+            if (surv && bidx == (uint32_t)pos) brank = __popcll(mask[k] & lanemask_lt());
+            if (lane == 0) s_off[k * NW + wave] = (uint32_t)__popcll(mask[k]);
+        }
+        // pivot copies
+        uint32_t p0w = wave_sum(p0c);
+        if (lane == 0) s_p0[wave] = p0w;
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t v = lane < G ? s_off[lane] : 0u;
+            uint32_t inc = wave_incl_scan(v);
+            if (lane < G) s_off[lane] = inc - v;
+            uint32_t total = __shfl(inc, 63);
+            uint32_t excl = lookback_sum(stat, t, total, epoch);
+            if (lane == 0) {
+                s_excl = excl;
+                uint32_t pc = 0;
+                for (int w = 0; w < NW; ++w) pc += s_p0[w];
+                if (pc) atomicAdd(&ds->n_p0, pc);
+                if (t == ntiles - 1) ds->n_sorted = excl + total;
+            }
+        }
+        __syncthreads();
+        const uint32_t excl = s_excl;
+#pragma unroll
+        for (int k = 0; k < kF1Ipt; ++k) {
+            if ((mask[k] >> lane) & 1ull) {
+                int64_t pos = base + k * kF1Block + threadIdx.x;
+                uint32_t o = excl + s_off[k * NW + wave] + (uint32_t)__popcll(mask[k] & lanemask_lt());
+                comp_xy[o] = p[k];
+                comp_idx[o] = (uint32_t)pos;
+                keys[o] = key[k];
+            }
+        }
+        // farthest point of the tile: largest d2, then smallest index
+        uint32_t bslot = bidx == 0xFFFFFFFFu ? 0xFFFFFFFFu : excl + s_off[bgrp] + brank;
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) {
+            double od = __shfl_xor(bd2, m);
+            uint32_t oi = __shfl_xor(bidx, m);
+            uint32_t os = __shfl_xor(bslot, m);
+            if (od > bd2 || (od == bd2 && oi < bidx)) {
+                bd2 = od;
+                bidx = oi;
+                bslot = os;
+            }
+        }
+        if (lane == 0) {
+            s_bd2[wave] = bd2;
+            s_bidx[wave] = bidx;
+            s_bslot[wave] = bslot;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double d = s_bd2[0];
+            uint32_t bi = s_bidx[0], bs = s_bslot[0];
+            for (int w = 1; w < NW; ++w) {
+                if (s_bd2[w] > d || (s_bd2[w] == d && s_bidx[w] < bi)) {
+                    d = s_bd2[w];
+                    bi = s_bidx[w];
+                    bs = s_bslot[w];
+                }
+            }
+            tile_d2[t] = d;
+            tile_best[2 * t] = bi;
+            tile_best[2 * t + 1] = bs;
+        }
+        __syncthreads();
+    }
+}
+
+// Step 5: the farthest survivor (largest d2, then smallest index) over the
+// per-tile partials.  One block.
+__global__ __launch_bounds__(1024) void k_longest(int ntiles, const double* __restrict__ tile_d2,
+                                                  const uint32_t* __restrict__ tile_best,
+                                                  const double2* __restrict__ comp_xy,
+                                                  Params* __restrict__ prm,
+                                                  DevStatus* __restrict__ ds) {
+    __shared__ double s_d[16];
+    __shared__ uint32_t s_i[16], s_s[16];
+    double d = -1.0;
+    uint32_t bi = 0xFFFFFFFFu, bs = 0xFFFFFFFFu;
+    if (ds->n_sorted > 0u) {
+        for (int t = (int)threadIdx.x; t < ntiles; t += 1024) {
+            double od = tile_d2[t];
+            uint32_t oi = tile_best[2 * t];
+            if (od > d || (od == d && oi < bi)) {
+                d = od;
+                bi = oi;
+                bs = tile_best[2 * t + 1];
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        double od = __shfl_xor(d, m);
+        uint32_t oi = __shfl_xor(bi, m);
+        uint32_t os = __shfl_xor(bs, m);
+        if (od > d || (od == d && oi < bi)) {
+            d = od;
+            bi = oi;
+            bs = os;
+        }
+    }
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    if (lane == 0) {
+        s_d[wave] = d;
+        s_i[wave] = bi;
+        s_s[wave] = bs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) {
+            if (s_d[w] > d || (s_d[w] == d && s_i[w] < bi)) {
+                d = s_d[w];
+                bi = s_i[w];
+                bs = s_s[w];
+            }
+        }
+        if (bs != 0xFFFFFFFFu && ds->n_sorted > 0u) {
+            double2 q = comp_xy[bs];
+            prm->lx = q.x;
+            prm->ly = q.y;
+            prm->l_idx = (int32_t)bi;
+            prm->l_slot = bs;
+            ds->l_idx = (int32_t)bi;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Steps 6-7, one walk per region as a prefix scan.
+//
+// Right region (sorted before P_l, walked forward from P_temp = P_0): P_i is
+// interior when it is strictly left of P_temp -> P_l, i.e. when
+// orient(P_l, P_temp, P_i) < 0; otherwise P_temp <- P_i.  Seen from P_l, the
+// directions to P_0 and to the right-region points lie in a half-open
+// half-plane, so "B follows A" := orient(P_l, A, B) >= 0 is a total preorder
+// there, and the walk's P_temp is always a maximum of everything walked so
+// far.  Hence P_i is kept exactly when P_i follows the maximum of
+// {P_0, P_1, ..., P_{i-1}}: a max-scan, associative, computed by tiles with
+// a decoupled look-back of the running maximum.  The left region (walked
+// backward from its last point, discarding points strictly right of
+// P_temp -> P_l) is the mirror image with the sign flipped.  Copies of P_l
+// (zero direction) only occur at the very end of the left walk and are
+// always kept, which the formula reproduces.
+// ---------------------------------------------------------------------------
+struct Pt {
+    double x, y;
+    uint32_t s;
+};
+
+__device__ inline Pt pt_load(uint32_t slot, const double2* __restrict__ comp, double x0, double y0) {
+    Pt p;
+    p.s = slot;
+    if (slot == kSlotP0) {
+        p.x = x0;
+        p.y = y0;
+    } else if (slot == kSlotNone) {
+        p.x = 0.0;
+        p.y = 0.0;
+    } else {
+        double2 v = comp[slot];
+        p.x = v.x;
+        p.y = v.y;
+    }
+    return p;
+}
+
+// Later of a and b in the region's order (kSlotNone is the identity).
+__device__ inline Pt pmax(const Pt& a, const Pt& b, double lx, double ly, int sgn) {
+    if (a.s == kSlotNone) return b;
+    if (b.s == kSlotNone) return a;
+    int o = orient(lx, ly, a.x, a.y, b.x, b.y);
+    return sgn * o >= 0 ? b : a;
+}
+
+__device__ inline Pt shfl_pt(const Pt& p, int src) {
+    Pt r;
+    r.x = __shfl(p.x, src);
+    r.y = __shfl(p.y, src);
+    r.s = __shfl(p.s, src);
+    return r;
+}
+
+__device__ inline Pt shfl_up_pt(const Pt& p, int d) {
+    Pt r;
+    r.x = __shfl_up(p.x, d);
+    r.y = __shfl_up(p.y, d);
+    r.s = __shfl_up(p.s, d);
+    return r;
+}
+
+__device__ inline Pt shfl_xor_pt(const Pt& p, int m) {
+    Pt r;
+    r.x = __shfl_xor(p.x, m);
+    r.y = __shfl_xor(p.y, m);
+    r.s = __shfl_xor(p.s, m);
+    return r;
+}
+
+// Look-back of the running maximum; one wave.  `initial` is the value before
+// tile 0 (P_0 for the right region, none for the left region).
+__device__ Pt lookback_max(uint64_t* stat, uint32_t t, const Pt& agg, uint32_t initial,
+                           const double2* __restrict__ comp, double x0, double y0, double lx,
+                           double ly, int sgn, uint32_t epoch) {
+    const uint32_t lane = __lane_id();
+    Pt pre = pt_load(initial, comp, x0, y0);
+    if (t == 0) {
+        Pt inc = pmax(pre, agg, lx, ly, sgn);
+        if (lane == 0) stat_store(&stat[0], stat_pack(epoch, kStatInclusive, inc.s));
+        return pre;
+    }
+    if (lane == 0) stat_store(&stat[t], stat_pack(epoch, kStatAggregate, agg.s));
+    Pt acc;
+    acc.s = kSlotNone;
+    acc.x = acc.y = 0.0;
+    int64_t top = (int64_t)t - 1;
+    for (;;) {
+        int64_t me = top - (int64_t)lane;
+        uint32_t f = kStatInclusive, v = initial;
+        if (me >= 0) {
+            uint64_t w = stat_load(&stat[me]);
+            f = stat_flag(w, epoch);
+            v = stat_value(w);
+        }
+        uint64_t incl = __ballot(f == kStatInclusive);
+        uint64_t notready = __ballot(f == 0u);
+        uint32_t first = incl ? (uint32_t)(__ffsll((unsigned long long)incl) - 1) : 64u;
+        uint64_t upto = first >= 63u ? ~0ull : ((2ull << first) - 1ull);
+        if (notready & upto) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        Pt mine = pt_load(lane <= first ? v : kSlotNone, comp, x0, y0);
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) mine = pmax(mine, shfl_xor_pt(mine, m), lx, ly, sgn);
+        acc = pmax(mine, acc, lx, ly, sgn);
+        if (first < 64u) break;
+        top -= 64;
+    }
+    Pt inc = pmax(acc, agg, lx, ly, sgn);
+    if (lane == 0) stat_store(&stat[t], stat_pack(epoch, kStatInclusive, inc.s));
+    return acc;
+}
+
+__global__ __launch_bounds__(kR2Block) void k_round2_scan(
+    const uint32_t* __restrict__ slots, const double2* __restrict__ comp,
+    const Params* __restrict__ prm, const DevStatus* __restrict__ ds, uint8_t* __restrict__ keep,
+    uint64_t* __restrict__ stat, Counters* __restrict__ ctr, uint32_t epoch) {
+    constexpr int NW = kR2Block / 64;
+    __shared__ uint32_t s_ticket;
+    __shared__ Pt s_wave[NW];
+    __shared__ Pt s_pre;
+
+    const uint32_t ms = ds->n_sorted;
+    const uint32_t lp = ds->l_pos;
+    const uint32_t nR = ms > 0 ? lp : 0u;
+    const uint32_t nL = ms > 0 ? ms - 1u - lp : 0u;
+    const uint32_t ntR = (nR + kR2Tile - 1) / kR2Tile;
+    const uint32_t ntL = (nL + kR2Tile - 1) / kR2Tile;
+    const uint32_t ntiles = ntR + ntL;
+    const double x0 = prm->x0, y0 = prm->y0, lx = prm->lx, ly = prm->ly;
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    uint32_t* ticket = &ctr->ticket[kTicketRound2];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ms > 0) keep[lp] = 1;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = take_ticket(ticket);
+        __syncthreads();
+        const uint32_t t = s_ticket;
+        __syncthreads();
+        if (t >= ntiles) {
+            if (threadIdx.x == 0 && t == ntiles + gridDim.x - 1) reset_ticket(ticket);
+            break;
+        }
+        const bool right = t < ntR;
+        const uint32_t rt = right ? t : t - ntR;
+        const int sgn = right ? 1 : -1;
+        const uint32_t cnt = min((uint32_t)kR2Tile, (right ? nR : nL) - rt * kR2Tile);
+        uint64_t* st = right ? stat : stat + ntR;
+        // this thread's items, consecutive in walk order
+        Pt it[kR2Ipt];
+        uint32_t pos[kR2Ipt];
+        Pt m;
+        m.s = kSlotNone;
+        m.x = m.y = 0.0;
+#pragma unroll
+        for (int k = 0; k < kR2Ipt; ++k) {
+            uint32_t w = threadIdx.x * kR2Ipt + k;
+            uint32_t g = rt * kR2Tile + w;
+            pos[k] = right ? g : ms - 1u - g;
+            it[k].s = kSlotNone;
+            it[k].x = it[k].y = 0.0;
+            if (w < cnt) it[k] = pt_load(slots[pos[k]], comp, x0, y0);
+        }
+#pragma unroll
+        for (int k = 0; k < kR2Ipt; ++k) m = pmax(m, it[k], lx, ly, sgn);
+        // block exclusive scan of the thread maxima
+        Pt inc = m;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            Pt o = shfl_up_pt(inc, d);
+            if (lane >= d) inc = pmax(o, inc, lx, ly, sgn);
+        }
+        Pt ex = shfl_up_pt(inc, 1);
+        if (lane == 0) {
+            ex.s = kSlotNone;
+            ex.x = ex.y = 0.0;
+        }
+        if (lane == 63) s_wave[wave] = inc;
+        __syncthreads();
+        Pt wpre;
+        wpre.s = kSlotNone;
+        wpre.x = wpre.y = 0.0;
+        for (int w = 0; w < wave; ++w) wpre = pmax(wpre, s_wave[w], lx, ly, sgn);
+        ex = pmax(wpre, ex, lx, ly, sgn);
+        if (wave == 0) {
+            Pt agg = s_wave[0];
+            for (int w = 1; w < NW; ++w) agg = pmax(agg, s_wave[w], lx, ly, sgn);
+            Pt pre = lookback_max(st, rt, agg, right ? kSlotP0 : kSlotNone, comp, x0, y0, lx,
+                                  ly, sgn, epoch);
+            if (lane == 0) s_pre = pre;
+        }
+        __syncthreads();
+        Pt run = pmax(s_pre, ex, lx, ly, sgn);
+#pragma unroll
+        for (int k = 0; k < kR2Ipt; ++k) {
+            uint32_t w = threadIdx.x * kR2Ipt + k;
+            if (w < cnt) {
+                bool kp = run.s == kSlotNone ||
+                          sgn * orient(lx, ly, run.x, run.y, it[k].x, it[k].y) >= 0;
+                keep[pos[k]] = kp ? 1 : 0;
+                run = pmax(run, it[k], lx, ly, sgn);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Steps 6-7 with the paper's subsets (Section 3.4): one thread walks one
+// subset sequentially.  Every subset restarts P_temp at its first point in
+// walking order (kept untested), except the right region's first subset,
+// which starts from P_0 as Figure 2 does.
+__global__ __launch_bounds__(256) void k_round2_chunks(int64_t chunk, const uint32_t* __restrict__ slots,
+                                                       const double2* __restrict__ comp,
+                                                       const Params* __restrict__ prm,
+                                                       const DevStatus* __restrict__ ds,
+                                                       uint8_t* __restrict__ keep) {
+    const int64_t ms = ds->n_sorted;
+    if (ms == 0) return;
+    const int64_t lp = ds->l_pos;
+    const int64_t mR = lp, mL = ms - 1 - lp;
+    auto clen = [&](int64_t m) -> int64_t {
+        if (m < 1) return 1;
+        if (chunk == 0) return m;
+        if (chunk < 0) return (m + 1023) / 1024;
+        return chunk;
+    };
+    const int64_t cR = clen(mR), cL = clen(mL);
+    const int64_t nchR = mR > 0 ? (mR + cR - 1) / cR : 0;
+    const int64_t nchL = mL > 0 ? (mL + cL - 1) / cL : 0;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double x0 = prm->x0, y0 = prm->y0, lx = prm->lx, ly = prm->ly;
+    if (c == 0) keep[lp] = 1;
+    if (c < nchR) {
+        int64_t s = c * cR, e = min(s + cR, mR);
+        double tx = x0, ty = y0;
+        int64_t i = s;
+        if (c != 0) {
+            double2 v = comp[slots[s]];
+            tx = v.x;
+            ty = v.y;
+            keep[s] = 1;
+            i = s + 1;
+        }
+        for (; i < e; ++i) {
+            double2 v = comp[slots[i]];
+            if (orient(tx, ty, lx, ly, v.x, v.y) > 0) {
+                keep[i] = 0;
+            } else {
+                keep[i] = 1;
+                tx = v.x;
+                ty = v.y;
+            }
+        }
+    } else if (c < nchR + nchL) {
+        int64_t u = c - nchR;
+        int64_t top = ms - 1 - u * cL;
+        int64_t bot = max(lp + 1, top - cL + 1);
+        double2 v = comp[slots[top]];
+        double tx = v.x, ty = v.y;
+        keep[top] = 1;
+        for (int64_t i = top - 1; i >= bot; --i) {
+            v = comp[slots[i]];
+            if (orient(tx, ty, lx, ly, v.x, v.y) < 0) {
+                keep[i] = 0;
+            } else {
+                keep[i] = 1;
+                tx = v.x;
+                ty = v.y;
+            }
+        }
+    }
+}
+
+// Stable removal of the interior points (the kept ones stay in angular order).
+__global__ __launch_bounds__(kCpBlock) void k_compact(
+    const uint8_t* __restrict__ keep, const uint32_t* __restrict__ slots,
+    const double2* __restrict__ comp, const uint32_t* __restrict__ comp_idx,
+    double2* __restrict__ out_xy, int32_t* __restrict__ out_idx, DevStatus* __restrict__ ds,
+    uint64_t* __restrict__ stat, Counters* __restrict__ ctr, uint32_t epoch) {
+    constexpr int NW = kCpBlock / 64;
+    static_assert(kCpIpt == 16, "one 16-byte vector of flags per thread");
+    __shared__ uint32_t s_ticket;
+    __shared__ uint32_t s_wave[NW];
+    __shared__ uint32_t s_excl;
+    const uint32_t ms = ds->n_sorted;
+    const uint32_t ntiles = (ms + kCpTile - 1) / kCpTile;
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    uint32_t* ticket = &ctr->ticket[kTicketCompact];
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = take_ticket(ticket);
+        __syncthreads();
+        const uint32_t t = s_ticket;
+        __syncthreads();
+        if (t >= ntiles) {
+            if (threadIdx.x == 0 && t == ntiles + gridDim.x - 1) reset_ticket(ticket);
+            break;
+        }
+        const uint32_t p0 = t * kCpTile + threadIdx.x * kCpIpt;
+        uint4 v = *reinterpret_cast<const uint4*>(keep + p0);
+        uint32_t wds[4] = {v.x, v.y, v.z, v.w};
+        uint32_t bits = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            uint32_t b = (wds[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+            if (b && p0 + k < ms) bits |= 1u << k;
+        }
+        uint32_t c = __popc(bits);
+        uint32_t inc = wave_incl_scan(c);
+        if (lane == 63) s_wave[wave] = inc;
+        __syncthreads();
+        uint32_t wpre = 0, tot = 0;
+        for (int w = 0; w < NW; ++w) {
+            uint32_t x = s_wave[w];
+            if (w < wave) wpre += x;
+            tot += x;
+        }
+        if (wave == 0) {
+            uint32_t excl = lookback_sum(stat, t, tot, epoch);
+            if (lane == 0) {
+                s_excl = excl;
+                if (t == ntiles - 1) ds->n_kept = excl + tot;
+            }
+        }
+        __syncthreads();
+        uint32_t o = s_excl + wpre + inc - c;
+        while (bits) {
+            int k = __ffs(bits) - 1;
+            bits &= bits - 1;
+            uint32_t s = slots[p0 + k];
+            out_xy[o] = comp[s];
+            out_idx[o] = (int32_t)comp_idx[s];
+            ++o;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_debug_orient(const double* __restrict__ abc, int64_t count, int32_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const double* q = abc + 6 * i;
+    out[i] = orient(q[0], q[1], q[2], q[3], q[4], q[5]);
+}
+
+__global__ void k_debug_key(const double* __restrict__ xy, int64_t count, double x0, double y0,
+                            uint32_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    out[i] = angle_key(xy[2 * i], xy[2 * i + 1], x0, y0);
+}
+
+}  // namespace
+
+hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
+                           DevStatus* ds, hipStream_t s) {
+    hipLaunchKernelGGL(k_extremes, dim3(grid), dim3(kExtBlock), 0, s,
+                       reinterpret_cast<const double2*>(xy), n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_extremes_final, dim3(1), dim3(256), 0, s, partial, grid, prm, ds);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter1(const double* xy, int64_t n, const Params* prm, double2* comp_xy,
+                          uint32_t* comp_idx, uint32_t* keys, uint64_t* stat, double* tile_d2,
+                          uint32_t* tile_best, DevStatus* ds, Counters* ctr, uint32_t epoch,
+                          int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_filter1, dim3(grid), dim3(kF1Block), 0, s,
+                       reinterpret_cast<const double2*>(xy), n, prm, comp_xy, comp_idx, keys, stat,
+                       tile_d2, tile_best, ds, ctr, epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_longest(int64_t n, const double* tile_d2, const uint32_t* tile_best,
+                          const double2* comp_xy, Params* prm, DevStatus* ds, hipStream_t s) {
+    int ntiles = (int)ceil_div(n, kF1Tile);
+    hipLaunchKernelGGL(k_longest, dim3(1), dim3(1024), 0, s, ntiles, tile_d2, tile_best, comp_xy,
+                       prm, ds);
+    return hipGetLastError();
+}
+
+hipError_t launch_round2_scan(const uint32_t* slots, const double2* comp_xy, const Params* prm,
+                              const DevStatus* ds, uint8_t* keep, uint64_t* stat,
+                              Counters* ctr, uint32_t epoch, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_round2_scan, dim3(grid), dim3(kR2Block), 0, s, slots, comp_xy, prm, ds,
+                       keep, stat, ctr, epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_round2_chunks(int64_t n, int64_t chunk, const uint32_t* slots,
+                                const double2* comp_xy, const Params* prm, const DevStatus* ds,
+                                uint8_t* keep, hipStream_t s) {
+    int64_t nch;
+    if (chunk < 0) nch = 2 * 1024 + 2;
+    else if (chunk == 0) nch = 2;
+    else nch = ceil_div(n, chunk) + 2;
+    int64_t grid = ceil_div(nch, 256);
+    hipLaunchKernelGGL(k_round2_chunks, dim3((unsigned)grid), dim3(256), 0, s, chunk, slots,
+                       comp_xy, prm, ds, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const uint8_t* keep, const uint32_t* slots, const double2* comp_xy,
+                          const uint32_t* comp_idx, double2* out_xy, int32_t* out_idx,
+                          DevStatus* ds, uint64_t* stat, Counters* ctr, uint32_t epoch, int grid,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_compact, dim3(grid), dim3(kCpBlock), 0, s, keep, slots, comp_xy,
+                       comp_idx, out_xy, out_idx, ds, stat, ctr, epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_orient(const double* abc, int64_t count, int32_t* out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_debug_orient, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s, abc,
+                       count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_key(const double* xy, int64_t count, double x0, double y0, uint32_t* out,
+                            hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_debug_key, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s, xy,
+                       count, x0, y0, out);
+    return hipGetLastError();
+}
+
+}  // namespace hx

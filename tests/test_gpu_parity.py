@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+* device predicates (orientation, angle key) against exact rationals;
+* every stage (extremes, sorted order, split, round-2 survivors) against the
+  oracle's step-by-step model, for the single-walk and subset modes;
+* the canonical hull against the monotone-chain oracle, bit for bit, on the
+  small configuration, ragged sizes, degenerate and duplicate-heavy inputs;
+* the full-size workloads against oracle-written golden hashes.
+"""
+import hashlib
+import json
+import math
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.exact_ref import orient_q
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden", "hulls.json")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hx(torch_dev):
+    import paper_1508_05931_amd as hx
+    return hx
+
+
+@pytest.fixture(scope="module")
+def ctx(hx):
+    return hx.Hull2D()
+
+
+def to_dev(torch, pts):
+    return torch.from_numpy(np.ascontiguousarray(pts, dtype=np.float64)).cuda()
+
+
+def _walk(v, k):
+    for _ in range(abs(k)):
+        v = math.nextafter(v, math.inf if k > 0 else -math.inf)
+    return v
+
+
+# ---------------------------------------------------------------- predicates
+def test_device_orient_vs_exact(torch_dev, ctx):
+    rng = random.Random(41)
+    rows = []
+    for _ in range(20000):
+        ax, ay, bx, by = (rng.uniform(-1, 1) for _ in range(4))
+        t = rng.uniform(-2, 3)
+        rows.append((ax, ay, bx, by, _walk(ax + t * (bx - ax), rng.randint(-3, 3)),
+                     _walk(ay + t * (by - ay), rng.randint(-3, 3))))
+    for _ in range(3000):
+        s = math.ldexp(1.0, rng.choice([-300, -100, 100, 299]))
+        a = (rng.uniform(1, 2) * s, rng.uniform(1, 2) * s)
+        rows.append((*a, _walk(a[0], rng.randint(1, 4)), _walk(a[1], rng.randint(-4, 4)),
+                     _walk(a[0], rng.randint(-4, 8)), _walk(a[1], rng.randint(-4, 8))))
+    abc = np.array(rows, dtype=np.float64)
+    say(f"device orient on {len(rows)} triples")
+    got = ctx.debug_orient(to_dev(torch_dev, abc))
+    want = np.array([oracle.orient(r[0:2], r[2:4], r[4:6]) for r in rows])
+    assert (got == want).all()
+    for r, g in list(zip(rows, got))[:: 97]:
+        assert g == orient_q(r[0:2], r[2:4], r[4:6])
+
+
+def _key_q(x, y, x0, y0):
+    from fractions import Fraction
+    dx = Fraction(x) - Fraction(x0)
+    dy = Fraction(y) - Fraction(y0)
+    s = dy / (abs(dx) + dy)
+    return math.floor((s if dx >= 0 else 2 - s) * 2 ** 31)
+
+
+def test_device_angle_key_vs_exact(torch_dev, ctx):
+    rng = random.Random(42)
+    x0, y0 = 0.5, 0.25
+    pts = []
+    for _ in range(3000):
+        k = rng.randrange(1, 2 ** 32 - 1)
+        if k < 2 ** 31:
+            dx, dy = float(2 ** 31 - k), float(k)
+        else:
+            dx, dy = -float(k - 2 ** 31), float(2 ** 32 - k)
+        sc = math.ldexp(1.0, rng.randint(-30, 30))
+        x, y = x0 + dx * sc, y0 + dy * sc
+        for px, py in [(x, y), (_walk(x, 1), y), (_walk(x, -1), y), (x, _walk(y, -1))]:
+            if py > y0 or (py == y0 and px > x0):
+                pts.append((px, py))
+    for _ in range(3000):
+        pts.append((rng.uniform(-1, 2), y0 + rng.random()))
+    arr = np.array(pts, dtype=np.float64)
+    say(f"device angle key on {len(pts)} points")
+    got = ctx.debug_angle_key(to_dev(torch_dev, arr), x0, y0)
+    want = np.array([_key_q(p[0], p[1], x0, y0) for p in pts], dtype=np.uint64)
+    assert (got.astype(np.uint64) == want).all()
+
+
+# ------------------------------------------------------------- small inputs
+def _cases():
+    t = np.arange(-700, 800, dtype=np.float64)
+    c = {
+        "square_100k": synth.square(100_000, (1, 1)),
+        "square_100003": synth.square(100_003, (51, 1)),
+        "disk_100k": synth.disk(100_000, (52, 1)),
+        "gauss_50k": synth.gaussian(50_000, 1.0, (53, 1)),
+        "mixture_100k": synth.mixture(100_000, (54, 1)),
+        "annulus_ngon_100k": synth.annulus_ngon(50_000, 50_000, 14, ((55, 1), (56, 1), (57, 1))),
+        "grid_draws_100k": synth.grid_draws(100_000, 64, (58, 1)),
+        "grid_200x3": synth.grid(200, 3, (59, 1)),
+        "ngon_4096": synth.ngon(4096, 12, (60, 1)),
+        "collinear_1500": np.stack([t, 2 * t - 5], axis=1)[np.random.default_rng(1).permutation(1500)],
+        "collinear_dups": np.repeat(np.stack([t[:40], -t[:40]], axis=1), 3, axis=0),
+        "all_equal_1000": np.full((1000, 2), 0.375),
+        "one": np.array([[0.25, -0.5]]),
+        "two_same": np.array([[1.0, 1.0], [1.0, 1.0]]),
+        "two": np.array([[1.0, 3.0], [-1.0, 2.0]]),
+        "three_collinear": np.array([[0.0, 0.0], [2.0, 2.0], [1.0, 1.0]]),
+        "triangle_interior": np.array([[0.0, 0.0], [4.0, 0.0], [0.0, 4.0], [1.0, 1.0], [-0.0, 0.0]]),
+        "tiny_magnitudes": synth.square(5000, (61, 1)) * math.ldexp(1.0, -290),
+        "huge_magnitudes": (synth.disk(5000, (62, 1)) - 0.5) * math.ldexp(1.0, 290),
+    }
+    return c
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_hull_equals_oracle(torch_dev, ctx, name):
+    pts = CASES[name]
+    say(f"hull {name} n={len(pts)}")
+    got = ctx.compute(to_dev(torch_dev, pts))
+    want = oracle.hull(pts)
+    assert got.tolist() == want.tolist()
+    st = ctx.last_stats
+    assert st.n_hull == len(want)
+
+
+@pytest.mark.parametrize("chunk", [0, -1, 5])
+@pytest.mark.parametrize("name", ["square_100k", "disk_100k", "grid_draws_100k", "annulus_ngon_100k",
+                                  "collinear_1500", "grid_200x3", "mixture_100k"])
+def test_stages_equal_model(torch_dev, hx, name, chunk):
+    pts = CASES[name]
+    say(f"stages {name} chunk={chunk}")
+    c = hx.Hull2D(round2_chunk=chunk)
+    got = c.compute(to_dev(torch_dev, pts))
+    m = oracle.model(pts, chunk)
+    s = c.stages(len(pts) + 1)
+    assert s["extremes"] == m["extremes"]
+    assert s["sorted"].tolist() == m["sorted"].tolist()
+    if len(m["sorted"]):
+        assert s["l"] == m["l"]
+        assert s["longest"] == m["longest"]
+    assert s["round2"].tolist() == m["round2"].tolist()
+    assert got.tolist() == m["hull"].tolist()
+    st = c.last_stats
+    assert st.n_round1 == m["m1"]
+    assert st.n_round2 == m["m2"]
+    c.close()
+
+
+def test_repeatable(torch_dev, ctx):
+    pts = CASES["disk_100k"]
+    d = to_dev(torch_dev, pts)
+    a = ctx.compute(d)
+    for _ in range(5):
+        assert ctx.compute(d).tolist() == a.tolist()
+
+
+def test_workspace_shrink_and_grow(torch_dev, ctx):
+    for name in ["square_100k", "one", "annulus_ngon_100k", "two", "square_100003"]:
+        pts = CASES[name]
+        assert ctx.compute(to_dev(torch_dev, pts)).tolist() == oracle.hull(pts).tolist()
+
+
+@pytest.mark.parametrize("bad,status", [(float("nan"), 2), (float("inf"), 2), (1e-310, 3),
+                                        (math.ldexp(1.0, 301), 3)])
+def test_domain_errors(torch_dev, hx, ctx, bad, status):
+    pts = synth.square(10_000, (63, 1))
+    pts[4321, 1] = bad
+    with pytest.raises(hx.HullError) as e:
+        ctx.compute(to_dev(torch_dev, pts))
+    assert e.value.status == status
+    # the context stays usable
+    ok = synth.square(1000, (64, 1))
+    assert ctx.compute(to_dev(torch_dev, ok)).tolist() == oracle.hull(ok).tolist()
+
+
+def test_empty_and_capacity(torch_dev, hx, ctx):
+    import ctypes
+    import torch
+    empty = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    assert ctx.compute(empty).tolist() == []
+    pts = CASES["disk_100k"]
+    want = oracle.hull(pts)
+    d = to_dev(torch_dev, pts)
+    lib = hx.load_library()
+    out = np.zeros(4, dtype=np.int32)
+    n_out = ctypes.c_int64(0)
+    st = lib.hull2d_compute(ctx._h, ctypes.c_void_p(d.data_ptr()), len(pts),
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 4,
+                            ctypes.byref(n_out), None)
+    assert st == hx.CAPACITY
+    assert n_out.value == len(want)
+    assert (out == 0).all()
+
+
+# ---------------------------------------------------------------- full size
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["square_20M", "disk_20M", "annulus_ngon_20M", "grid_500x4",
+                                  "mixture_20M"])
+def test_full_size_matches_golden(torch_dev, ctx, name):
+    g = _golden()[name]
+    say(f"full size {name}: generating")
+    pts = synth.workload(name)
+    assert pts.shape[0] == g["n"]
+    assert synth.content_hash(pts) == g["input_hash"]
+    say(f"full size {name}: hull on GPU")
+    got = ctx.compute(to_dev(torch_dev, pts))
+    assert len(got) == g["h"]
+    assert got[:16].tolist() == g["head"]
+    assert hashlib.sha256(np.ascontiguousarray(got, dtype="<i4").tobytes()).hexdigest() == g["sha256"]
+    st = ctx.last_stats
+    say(f"  n={st.n} round1={st.n_round1} round2={st.n_round2} h={st.n_hull} "
+        f"ms={st.ms_total:.3f}")
