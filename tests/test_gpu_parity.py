@@ -136,7 +136,7 @@ def _cases():
         "two": np.array([[1.0, 3.0], [-1.0, 2.0]]),
         "three_collinear": np.array([[0.0, 0.0], [2.0, 2.0], [1.0, 1.0]]),
         "triangle_interior": np.array([[0.0, 0.0], [4.0, 0.0], [0.0, 4.0], [1.0, 1.0], [-0.0, 0.0]]),
-        "tiny_magnitudes": synth.square(5000, (61, 1)) * math.ldexp(1.0, -290),
+        "tiny_magnitudes": (1.0 + synth.square(5000, (61, 1))) * math.ldexp(1.0, -290),
         "huge_magnitudes": (synth.disk(5000, (62, 1)) - 0.5) * math.ldexp(1.0, 290),
     }
     return c
