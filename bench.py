@@ -1,0 +1,184 @@
+"""Benchmark: exact 2D hulls of the paper's 20M-point workloads on one MI355X.
+
+One step = one hull2d_compute of each set of the workload (20,000,000 points
+uniform in [0,1)^2 and 20,000,000 points uniform in the unit disk, the shapes
+and sizes of the paper's Section 4 groups 1 and 2), inputs resident in HBM.
+The step covers every stage: extremes, round-1 discard with exact keys, the
+angular radix sort with exact tie order, the round-2 filter, compaction, the
+copy of the kept points to the host and the host stack scan.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpoints/s exact 2D hull at 20M pts (plain vs learned-filter/batched); HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+# The paper's gScan total (GPU + CPU) at 20M points on its faster platform
+# (GeForce GT 640, Tables 3 and 5): 446.4 ms (square) + 418.1 ms (disk).
+PAPER_MS_SQUARE_DISK_20M = 446.4 + 418.1
+
+KERNEL_STAGES = ["extremes", "filter1", "longest", "histogram", "sort0", "sort1", "sort2",
+                 "sort3", "ties", "ties_long", "round2", "compact"]
+
+
+def kernel_bytes(stage: str, n: int, ms: int, m2: int) -> float:
+    """Algorithmic HBM bytes of one launch: what the kernel must read and
+    write at least once (float64 x,y = 16 B, index/key/slot = 4 B, flag = 1 B)."""
+    return {
+        "extremes": 16.0 * n,
+        "filter1": 16.0 * n + 24.0 * ms,
+        "longest": 0.0,
+        "histogram": 4.0 * ms,
+        "sort0": 12.0 * ms,
+        "sort1": 16.0 * ms,
+        "sort2": 16.0 * ms,
+        "sort3": 16.0 * ms,
+        "ties": 8.0 * ms,
+        "ties_long": 0.0,
+        "round2": 21.0 * ms,
+        "compact": 1.0 * ms + 44.0 * m2,
+    }[stage]
+
+
+def cpu_baseline(sets, sample_n: int):
+    """The oracle (single-threaded C monotone chain) on the first sample_n
+    points of each set, timed on this host."""
+    import oracle
+    total_pts, total_s = 0, 0.0
+    for pts in sets:
+        s = pts[:sample_n].copy()
+        t0 = time.perf_counter()
+        oracle.hull(s)
+        total_s += time.perf_counter() - t0
+        total_pts += s.shape[0]
+    return {"value": round(total_pts / total_s / 1e6, 3), "unit": "Mpoints/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {sample_n} points of each 20M set ({total_pts} points), "
+                      f"{total_s:.1f} s on {platform.processor() or platform.machine()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--round2-chunk", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=5_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the hull path has no multi-GPU form "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1508_05931_amd as hx
+    import synth
+
+    names = ["square_20M", "disk_20M"]
+    host = [synth.workload(nm) for nm in names]
+    dev = [torch.from_numpy(a).cuda() for a in host]
+    torch.cuda.synchronize()
+    ctx = hx.Hull2D(round2_chunk=args.round2_chunk, profile=True)
+
+    for _ in range(args.warmup):
+        for d in dev:
+            ctx.compute(d)
+    per_set = {nm: {"ms": [], "stats": None} for nm in names}
+    stage_ms = {nm: {k: [] for k in KERNEL_STAGES + ["d2h", "host_scan"]} for nm in names}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for nm, d in zip(names, dev):
+            ctx.compute(d)
+            st = ctx.last_stats
+            per_set[nm]["ms"].append(st.ms_total)
+            per_set[nm]["stats"] = st
+            for k in stage_ms[nm]:
+                stage_ms[nm][k].append(st.ms_stage[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    n_total = sum(a.shape[0] for a in host)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = n_total / (ms_per_step * 1e-3) / 1e6
+
+    # per-kernel averages over the timed region (HIP events on the context's stream)
+    kern = {}
+    for k in KERNEL_STAGES:
+        ms_sum, bytes_sum = 0.0, 0.0
+        for nm, a in zip(names, host):
+            st = per_set[nm]["stats"]
+            avg = float(np.mean(stage_ms[nm][k]))
+            ms_sum += avg
+            bytes_sum += kernel_bytes(k, a.shape[0], st.n_sorted, st.n_round2 - 1)
+        kern[k] = {"ms": ms_sum / len(names), "bytes": bytes_sum / len(names)}
+    dom = max(KERNEL_STAGES, key=lambda k: kern[k]["ms"])
+    achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
+
+    sets_out = {}
+    fs_bytes, fs_ms = 0.0, 0.0
+    for nm, a in zip(names, host):
+        st = per_set[nm]["stats"]
+        n = a.shape[0]
+        t_fs = sum(float(np.mean(stage_ms[nm][k])) for k in KERNEL_STAGES)
+        b_alg = 32.0 * n + 80.0 * st.n_round1 + 20.0 * st.n_round2
+        fs_bytes += b_alg
+        fs_ms += t_fs
+        sets_out[nm] = {
+            "n": n, "h": st.n_hull,
+            "ms_median": round(float(np.median(per_set[nm]["ms"])), 4),
+            "Mpoints_per_s": round(n / (float(np.median(per_set[nm]["ms"])) * 1e-3) / 1e6, 1),
+            "survivors_round1": round(st.n_round1 / n, 5),
+            "survivors_round2": round(st.n_round2 / n, 7),
+            "ms_filter_sort": round(t_fs, 4),
+            "ms_d2h": round(float(np.mean(stage_ms[nm]["d2h"])), 4),
+            "ms_host_scan": round(float(np.mean(stage_ms[nm]["host_scan"])), 4),
+        }
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(value / (n_total / (PAPER_MS_SQUARE_DISK_20M * 1e-3) / 1e6), 1),
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "square_20M + disk_20M (one hull each per step)",
+                   "n_per_set": int(host[0].shape[0]),
+                   "round2": "single walk per region" if args.round2_chunk == 0
+                   else f"subsets ({args.round2_chunk})"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None},
+        "filter_sort": {"GBps_alg": round(fs_bytes / (fs_ms * 1e-3) / 1e9, 1),
+                        "frac_of_peak": round(fs_bytes / (fs_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "bytes_alg_formula": "32n + 80*round1 + 20*round2"},
+        "kernels_ms": {k: round(v["ms"], 4) for k, v in kern.items()},
+        "sets": sets_out,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(host, args.cpu_sample)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
