@@ -27,26 +27,29 @@ HBM_PEAK_GBPS = 8000.0
 # (GeForce GT 640, Tables 3 and 5): 446.4 ms (square) + 418.1 ms (disk).
 PAPER_MS_SQUARE_DISK_20M = 446.4 + 418.1
 
-KERNEL_STAGES = ["extremes", "filter1", "longest", "histogram", "sort0", "sort1", "sort2",
-                 "sort3", "ties", "ties_long", "round2", "compact"]
+KERNEL_STAGES = ["extremes", "filter1", "longest", "buckets", "histogram", "sort0", "sort1",
+                 "sort2", "sort3", "ties", "ties_long", "round2", "compact"]
 
 
-def kernel_bytes(stage: str, n: int, ms: int, m2: int) -> float:
+def kernel_bytes(stage: str, n: int, ms: int, nc: int, m2: int, full: bool) -> float:
     """Algorithmic HBM bytes of one launch: what the kernel must read and
-    write at least once (float64 x,y = 16 B, index/key/slot = 4 B, flag = 1 B)."""
+    write at least once (float64 x,y = 16 B, index/key/slot = 4 B, flag = 1 B).
+    n points, ms sorted round-1 survivors, nc points sorted for round 2
+    (= ms when every survivor is sorted), m2 kept points."""
     return {
         "extremes": 16.0 * n,
         "filter1": 16.0 * n + 24.0 * ms,
         "longest": 0.0,
-        "histogram": 4.0 * ms,
-        "sort0": 12.0 * ms,
-        "sort1": 16.0 * ms,
-        "sort2": 16.0 * ms,
-        "sort3": 16.0 * ms,
-        "ties": 8.0 * ms,
+        "buckets": 12.0 * ms if full else 40.0 * ms + 24.0 * nc,
+        "histogram": 4.0 * nc,
+        "sort0": 12.0 * nc,
+        "sort1": 16.0 * nc,
+        "sort2": 16.0 * nc,
+        "sort3": 16.0 * nc,
+        "ties": 8.0 * nc,
         "ties_long": 0.0,
-        "round2": 21.0 * ms,
-        "compact": 1.0 * ms + 44.0 * m2,
+        "round2": 21.0 * nc,
+        "compact": 1.0 * nc + 44.0 * m2,
     }[stage]
 
 
@@ -73,6 +76,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--round2-chunk", type=int, default=0)
+    ap.add_argument("--full-sort", action="store_true",
+                    help="sort every round-1 survivor (Step 4 as printed)")
+    ap.add_argument("--no-full-sort-line", action="store_true",
+                    help="skip the extra timing of the full-sort mode")
     ap.add_argument("--cpu-sample", type=int, default=5_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -91,7 +98,8 @@ def main():
     host = [synth.workload(nm) for nm in names]
     dev = [torch.from_numpy(a).cuda() for a in host]
     torch.cuda.synchronize()
-    ctx = hx.Hull2D(round2_chunk=args.round2_chunk, profile=True)
+    full = bool(args.full_sort or args.round2_chunk != 0)
+    ctx = hx.Hull2D(round2_chunk=args.round2_chunk, profile=True, full_sort=args.full_sort)
 
     for _ in range(args.warmup):
         for d in dev:
@@ -123,7 +131,8 @@ def main():
             st = per_set[nm]["stats"]
             avg = float(np.mean(stage_ms[nm][k]))
             ms_sum += avg
-            bytes_sum += kernel_bytes(k, a.shape[0], st.n_sorted, st.n_round2 - 1)
+            bytes_sum += kernel_bytes(k, a.shape[0], st.n_sorted, st.n_candidates,
+                                      st.n_round2 - 1, full)
         kern[k] = {"ms": ms_sum / len(names), "bytes": bytes_sum / len(names)}
     dom = max(KERNEL_STAGES, key=lambda k: kern[k]["ms"])
     achieved = kern[dom]["bytes"] / (kern[dom]["ms"] * 1e-3) / 1e9
@@ -143,6 +152,7 @@ def main():
             "Mpoints_per_s": round(n / (float(np.median(per_set[nm]["ms"])) * 1e-3) / 1e6, 1),
             "survivors_round1": round(st.n_round1 / n, 5),
             "survivors_round2": round(st.n_round2 / n, 7),
+            "sorted_for_round2": st.n_candidates,
             "ms_filter_sort": round(t_fs, 4),
             "ms_d2h": round(float(np.mean(stage_ms[nm]["d2h"])), 4),
             "ms_host_scan": round(float(np.mean(stage_ms[nm]["host_scan"])), 4),
@@ -164,7 +174,9 @@ def main():
         "config": {"workload": "square_20M + disk_20M (one hull each per step)",
                    "n_per_set": int(host[0].shape[0]),
                    "round2": "single walk per region" if args.round2_chunk == 0
-                   else f"subsets ({args.round2_chunk})"},
+                   else f"subsets ({args.round2_chunk})",
+                   "sort": "every round-1 survivor" if full else
+                   "candidates of the bucketed filter"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None},
@@ -174,9 +186,25 @@ def main():
         "kernels_ms": {k: round(v["ms"], 4) for k, v in kern.items()},
         "sets": sets_out,
     }
+    ctx.close()
+    if not full and not args.no_full_sort_line:
+        # the paper's Step 4 as printed: every round-1 survivor sorted
+        fctx = hx.Hull2D(full_sort=True)
+        for d in dev:
+            fctx.compute(d)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = max(1, args.steps // 4)
+        for _ in range(reps):
+            for d in dev:
+                fctx.compute(d)
+        torch.cuda.synchronize()
+        fms = (time.perf_counter() - t1) * 1e3 / reps
+        out["full_sort"] = {"ms_per_step": round(fms, 4),
+                            "Mpoints_per_s": round(n_total / (fms * 1e-3) / 1e6, 1)}
+        fctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host, args.cpu_sample)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -68,7 +68,12 @@ typedef struct {
     int32_t round2_chunk;
     /* 1: record per-kernel device times (HIP events) into hull2d_stats. */
     int32_t profile;
-    int32_t reserved[5];
+    /* Only for round2_chunk = 0.  0 (default): sort only the round-1 survivors
+     * that can still be running maxima of the walk (coarse angle buckets and
+     * an exclusive prefix of exact direction keys decide which; the kept set
+     * is identical).  1: sort every round-1 survivor, as Step 4 prints it. */
+    int32_t full_sort;
+    int32_t reserved[4];
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */
@@ -84,6 +89,7 @@ enum {
     HULL2D_STAGE_SORT3,
     HULL2D_STAGE_TIES,           /* Step 4 exact order inside equal-key runs        */
     HULL2D_STAGE_TIES_LONG,
+    HULL2D_STAGE_BUCKETS,        /* Steps 6-7 bucket maxima, prefix, candidates     */
     HULL2D_STAGE_ROUND2,         /* Steps 6-7 second-round filter                   */
     HULL2D_STAGE_COMPACT,        /* Step 7 stable removal of interior points        */
     HULL2D_STAGE_D2H,            /* copy of the kept points to the host             */
@@ -97,6 +103,7 @@ typedef struct {
     int64_t n_sorted;     /* round-1 survivors other than copies of the pivot      */
     int64_t n_round2;     /* points kept by round 2, the pivot included            */
     int64_t n_hull;       /* hull vertices                                          */
+    int64_t n_candidates; /* points sorted for round 2 (= n_sorted with full_sort)  */
     double ms_total;      /* host wall clock of the whole call                     */
     double ms_device;     /* first kernel start to end of the host copy (events)   */
     double ms_stage[HULL2D_NUM_STAGES]; /* filled when options.profile = 1        */
@@ -150,10 +157,12 @@ hull2d_status hull2d_debug_angle_key(hull2d_ctx* ctx, const double* d_xy, int64_
 /* Stage results of the last hull2d_compute on this context, for checking
  * against a step-by-step model.  Any pointer may be NULL.  Host buffers:
  * extremes[4] (input indices of P_minx, P_miny, P_maxx, P_maxy);
- * sorted[cap] (input indices of the sorted round-1 survivors, Step 4);
+ * sorted[cap] (input indices of the sorted round-1 survivors, Step 4; only
+ * filled when every survivor was sorted, see counts[4]);
  * round2[cap] (input indices kept by round 2 in angular order, pivot first);
- * counts[4] = {n_sorted, l (position of P_l in [pivot, sorted...]),
- * n_round2, longest (input index of P_l)}.
+ * counts[6] = {n_sorted, l (position of P_l in [pivot, sorted...]),
+ * n_round2, longest (input index of P_l), 1 if sorted was filled,
+ * n_candidates}.
  * CAPACITY if cap is smaller than n_sorted or n_round2. */
 hull2d_status hull2d_debug_stages(hull2d_ctx* ctx, int32_t* extremes, int32_t* sorted,
                                   int32_t* round2, int64_t cap, int64_t* counts);

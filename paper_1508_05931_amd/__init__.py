@@ -26,7 +26,8 @@ STATUS = {
 OK, INVALID_ARG, NONFINITE, RANGE, CAPACITY, OUT_OF_MEMORY, DEVICE, WEIGHTS, UNIMPLEMENTED = range(9)
 
 STAGES = ["extremes", "extremes_final", "filter1", "longest", "histogram", "sort0", "sort1",
-          "sort2", "sort3", "ties", "ties_long", "round2", "compact", "d2h", "host_scan"]
+          "sort2", "sort3", "ties", "ties_long", "buckets", "round2", "compact", "d2h",
+          "host_scan"]
 
 EXPORTED = ["hull2d_create", "hull2d_compute", "hull2d_batch", "hull2d_destroy",
             "hull2d_status_string", "hull2d_debug_orient", "hull2d_debug_angle_key",
@@ -41,13 +42,15 @@ class HullError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("round2_chunk", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("profile", ctypes.c_int32), ("full_sort", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_round1", ctypes.c_int64),
                 ("n_sorted", ctypes.c_int64), ("n_round2", ctypes.c_int64),
-                ("n_hull", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("n_hull", ctypes.c_int64), ("n_candidates", ctypes.c_int64),
+                ("ms_total", ctypes.c_double),
                 ("ms_device", ctypes.c_double),
                 ("ms_stage", ctypes.c_double * len(STAGES))]
 
@@ -95,14 +98,16 @@ class Stats:
     n_sorted: int = 0
     n_round2: int = 0
     n_hull: int = 0
+    n_candidates: int = 0
     ms_total: float = 0.0
     ms_device: float = 0.0
     ms_stage: dict = field(default_factory=dict)
 
     @staticmethod
     def _from(s: _Stats) -> "Stats":
-        return Stats(s.n, s.n_round1, s.n_sorted, s.n_round2, s.n_hull, s.ms_total,
-                     s.ms_device, {k: float(s.ms_stage[i]) for i, k in enumerate(STAGES)})
+        return Stats(s.n, s.n_round1, s.n_sorted, s.n_round2, s.n_hull, s.n_candidates,
+                     s.ms_total, s.ms_device,
+                     {k: float(s.ms_stage[i]) for i, k in enumerate(STAGES)})
 
 
 def _i32p(a: np.ndarray):
@@ -113,7 +118,7 @@ class Hull2D:
     """A library context bound to one device and one HIP stream."""
 
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
-                 profile: bool = False):
+                 profile: bool = False, full_sort: bool = False):
         import torch
         lib = load_library()
         if device is None:
@@ -122,7 +127,8 @@ class Hull2D:
             stream = torch.cuda.current_stream(device)
         self.device = int(device)
         self.stream = stream
-        opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(bool(profile)))
+        opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(bool(profile)),
+                       int(bool(full_sort)))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))
@@ -172,14 +178,15 @@ class Hull2D:
         ext = np.zeros(4, dtype=np.int32)
         srt = np.zeros(max(cap, 1), dtype=np.int32)
         r2 = np.zeros(max(cap, 1), dtype=np.int32)
-        counts = np.zeros(4, dtype=np.int64)
+        counts = np.zeros(6, dtype=np.int64)
         st = self._lib.hull2d_debug_stages(self._h, _i32p(ext), _i32p(srt), _i32p(r2), cap,
                                            counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
         if st != OK:
             raise HullError(st, "hull2d_debug_stages")
-        ns, l, m2, longest = (int(v) for v in counts)
-        return {"extremes": ext.tolist(), "sorted": srt[:ns].copy(), "l": l,
-                "round2": r2[:m2].copy(), "longest": longest, "m2": m2}
+        ns, l, m2, longest, have_sorted, ncand = (int(v) for v in counts)
+        return {"extremes": ext.tolist(), "sorted": srt[:ns].copy() if have_sorted else None,
+                "l": l, "round2": r2[:m2].copy(), "longest": longest, "m2": m2,
+                "n_sorted": ns, "n_candidates": ncand}
 
     def debug_orient(self, abc) -> "np.ndarray":
         import torch

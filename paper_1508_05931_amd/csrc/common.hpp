@@ -27,44 +27,40 @@ struct Params {
     // Step 5
     double lx, ly;      // P_l
     int32_t l_idx;      // input index of P_l (-1: no sorted points)
-    uint32_t l_slot;    // slot of P_l in the compacted round-1 arrays
+    uint32_t kl;        // angle key of P_l
+    // direction keys (turn_key about P_l) of P_0 - P_l and P_l - P_0
+    uint32_t turn_u, turn_v;
+    int32_t pad2[2];
 };
 
 constexpr uint32_t kFlagNonfinite = 1u;
 constexpr uint32_t kFlagRange = 2u;
 
-// Results the host reads back at the end of a call.
+// Status of one sorting problem (the round-1 survivors, or the round-2
+// candidates of the bucketed filter); the host reads both back at the end of
+// a call.
 struct DevStatus {
     uint32_t flags;       // domain flags
     uint32_t huge_runs;   // equal-key runs too long for one workgroup
-    uint32_t n_sorted;    // round-1 survivors other than copies of P_0
+    uint32_t n_sorted;    // points of this problem (round 1: survivors other than copies of P_0)
     uint32_t n_p0;        // points equal to P_0 (P_0 included)
-    uint32_t l_pos;       // position of P_l among the sorted survivors
+    uint32_t l_pos;       // position of P_l in this problem's sorted order
     uint32_t n_kept;      // round-2 survivors other than P_0
     uint32_t long_runs;   // equal-key runs handed to the workgroup sorter
+    uint32_t l_slot;      // slot of P_l in this problem's arrays
+    uint32_t n_right;     // points before P_l in angular order (bucketed filter)
     uint32_t pad;
     int32_t ext[4];
     int32_t p0_idx, l_idx;
     double x0, y0;
 };
 
-// Counters that persist across calls; each kernel that takes tickets resets its
-// own counter when the last ticket has been taken.
-struct Counters {
-    uint32_t ticket[16];
-};
-
-enum TicketId {
-    kTicketFilter1 = 0,
-    kTicketSort0 = 1,  // ..4
-    kTicketRound2 = 5,
-    kTicketCompact = 6,
-    kTicketHist = 7,
-};
+constexpr int kBucketBits = 12;                 // coarse angle buckets of the bucketed round 2
+constexpr int kBuckets = 1 << kBucketBits;
 
 // Look-back status word: [epoch:30 | flag:2 | value:32].  The epoch changes
-// on every call, so stale words from an earlier call never look ready and the
-// status arrays need no clearing.
+// on every launch, so stale words from an earlier launch never look ready and
+// the status arrays need no clearing.
 constexpr uint32_t kStatAggregate = 1u;
 constexpr uint32_t kStatInclusive = 2u;
 
@@ -82,12 +78,6 @@ __device__ inline void stat_store(uint64_t* p, uint64_t w) {
 }
 __device__ inline uint64_t stat_load(uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline uint32_t take_ticket(uint32_t* c) {
-    return __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void reset_ticket(uint32_t* c) {
-    __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wave64 helpers.

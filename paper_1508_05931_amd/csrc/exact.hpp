@@ -167,6 +167,53 @@ __host__ __device__ inline uint32_t angle_key(double x, double y, double x0, dou
     return key_at_least(x, y, x0, y0, right, ks) ? (uint32_t)ks : (uint32_t)ks - 1u;
 }
 
+// Exact key of the full-turn pseudo-angle of the direction d = p - c (d != 0):
+// the quadrant q (exact signs of the rounded differences) and, after rotating d
+// by -q quarter turns to (a, b) with a > 0, b >= 0, the fraction t = b/(a+b)
+// in [0, 1); key = q*2^30 + floor(2^30 t).  Strictly increasing directions
+// (counter-clockwise from the +x axis) give non-decreasing keys, a half turn
+// adds exactly 2^31, and the floor is exact: near an integer the test
+// (2^30 - k) b - k a >= 0 (a, b exact differences) decides.
+__host__ __device__ __noinline__ inline bool turn_at_least(double a1, double a2, double b1, double b2,
+                                                           double k) {
+    // a = a1 - a2, b = b1 - b2
+    double A = 1073741824.0 - k;
+    double t[8];
+    two_prod(A, b1, t[0], t[1]);
+    two_prod(-A, b2, t[2], t[3]);
+    two_prod(-k, a1, t[4], t[5]);
+    two_prod(k, a2, t[6], t[7]);
+    return exact_sign<8>(t) >= 0;
+}
+
+__host__ __device__ inline uint32_t turn_key(double px, double py, double cx, double cy) {
+    double dx = px - cx, dy = py - cy;
+    uint32_t q;
+    double a, b, a1, a2, b1, b2;
+    if (dx > 0.0 && dy >= 0.0) {
+        q = 0; a = dx; b = dy; a1 = px; a2 = cx; b1 = py; b2 = cy;
+    } else if (dx <= 0.0 && dy > 0.0) {
+        q = 1; a = dy; b = -dx; a1 = py; a2 = cy; b1 = cx; b2 = px;
+    } else if (dx < 0.0 && dy <= 0.0) {
+        q = 2; a = -dx; b = -dy; a1 = cx; a2 = px; b1 = cy; b2 = py;
+    } else {
+        q = 3; a = -dy; b = dx; a1 = cy; a2 = py; b1 = px; b2 = cx;
+    }
+    double t = b / (a + b) * 1073741824.0;
+    double f = floor(t);
+    double fr = t - f;
+    uint32_t k;
+    if (fr > 0.0009765625 && fr < 0.9990234375 && f < 1073741824.0) {
+        k = (uint32_t)f;
+    } else {
+        double ks = rint(t);
+        if (!(ks > 0.0)) k = 0u;
+        else if (ks >= 1073741824.0) k = 1073741823u;
+        else k = turn_at_least(a1, a2, b1, b2, ks) ? (uint32_t)ks : (uint32_t)ks - 1u;
+    }
+    return (q << 30) | k;
+}
+
 // Step 4's total order on round-1 survivors (the pivot's copies excluded):
 // ascending angle about the pivot, then ascending distance along a common
 // ray (larger y is farther; on the horizontal ray larger x), then ascending

@@ -33,16 +33,24 @@ struct hull2d_ctx {
     uint32_t* comp_idx = nullptr;
     uint32_t *keys_a = nullptr, *keys_b = nullptr, *vals_a = nullptr, *vals_b = nullptr;
     uint64_t* stat = nullptr;
-    double* tile_d2 = nullptr;
-    uint32_t* tile_best = nullptr;
     uint32_t* long_list = nullptr;
     uint32_t* huge_list = nullptr;
     uint8_t* keep = nullptr;
     double2* out_xy = nullptr;
     int32_t* out_idx = nullptr;
-    Counters* ctr = nullptr;  // separate allocation, zeroed once, persists
+    double2* cand_xy = nullptr;   // round-2 candidates of the bucketed filter
+    uint32_t* cand_idx = nullptr;
+    uint32_t* cand_key = nullptr;
+    uint32_t* part = nullptr;     // per-block bucket maxima
+    uint32_t* bmax = nullptr;
+    uint32_t* prefix = nullptr;
+    uint32_t* seg_count = nullptr;  // round-1 segments (one per filter block)
+    uint32_t* seg_off = nullptr;
+    double* blk_d2 = nullptr;
+    uint32_t* blk_best = nullptr;
+    int parts = 0;
 
-    // pinned host buffers
+    // pinned host buffers (h_ds holds the two problem statuses)
     DevStatus* h_ds = nullptr;
     double2* h_xy = nullptr;
     int32_t* h_idx = nullptr;
@@ -54,20 +62,23 @@ struct hull2d_ctx {
 
     // the last compute call, for hull2d_debug_stages
     bool have_last = false;
+    bool last_full = false;
     int64_t last_n = 0;
-    DevStatus last_ds{};
+    DevStatus last_ds{}, last_ds2{};
 };
 
 namespace {
 
+constexpr int kMaxSegs = 8192;  // round-1 blocks (cu_count * kF1BlocksPerCu) at most
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t off[20];
+    size_t off[26];
     size_t total;
 };
 
-Layout plan(int64_t n) {
+Layout plan(int64_t n, int parts) {
     const size_t N = (size_t)(n > 0 ? n : 1);
     const size_t sort_tiles = (size_t)ceil_div((int64_t)N, kSortTile);
     const size_t f1_tiles = (size_t)ceil_div((int64_t)N, kF1Tile);
@@ -75,10 +86,10 @@ Layout plan(int64_t n) {
     stat_words = std::max(stat_words, f1_tiles + 2);
     stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kR2Tile) + 4);
     stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kCpTile) + 2);
-    const size_t sizes[20] = {
+    const size_t sizes[26] = {
         (size_t)kExtGridMax * 4 * sizeof(Cand),      // 0 partial
         sizeof(Params),                              // 1
-        sizeof(DevStatus),                           // 2
+        2 * sizeof(DevStatus),                       // 2 round-1 problem, candidate problem
         4 * 256 * sizeof(uint32_t),                  // 3 hist
         N * sizeof(double2),                         // 4 comp_xy
         N * sizeof(uint32_t),                        // 5 comp_idx
@@ -87,17 +98,24 @@ Layout plan(int64_t n) {
         N * sizeof(uint32_t),                        // 8 vals_a
         N * sizeof(uint32_t),                        // 9 vals_b
         stat_words * sizeof(uint64_t),               // 10 stat
-        f1_tiles * sizeof(double),                   // 11 tile_d2
-        f1_tiles * 2 * sizeof(uint32_t),             // 12 tile_best
+        (size_t)kMaxSegs * sizeof(double),           // 11 blk_d2
+        (size_t)kMaxSegs * 2 * sizeof(uint32_t),     // 12 blk_best
         (N / (kRunSmall + 1) + 2) * sizeof(uint32_t),  // 13 long_list
         (N / kRunCap + 2) * 2 * sizeof(uint32_t),    // 14 huge_list
         align_up(N, kCpTile) + kCpTile,              // 15 keep (padded for 16-byte loads)
         N * sizeof(double2),                         // 16 out_xy
         N * sizeof(int32_t),                         // 17 out_idx
-        0, 0};
+        N * sizeof(double2),                         // 18 cand_xy
+        N * sizeof(uint32_t),                        // 19 cand_idx
+        N * sizeof(uint32_t),                        // 20 cand_key
+        (size_t)parts * 2 * kBuckets * sizeof(uint32_t),  // 21 part
+        2 * kBuckets * sizeof(uint32_t),             // 22 bmax
+        2 * kBuckets * sizeof(uint32_t),             // 23 prefix
+        (size_t)kMaxSegs * sizeof(uint32_t),         // 24 seg_count
+        (size_t)kMaxSegs * sizeof(uint32_t)};        // 25 seg_off
     Layout L{};
     size_t o = 0;
-    for (int i = 0; i < 20; ++i) {
+    for (int i = 0; i < 26; ++i) {
         L.off[i] = o;
         o = align_up(o + sizes[i], 256);
     }
@@ -115,7 +133,8 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
         c->dmem = nullptr;
         c->cap_n = -1;
     }
-    Layout L = plan(want);
+    c->parts = 2 * c->cu_count;
+    Layout L = plan(want, c->parts);
     if (hipMalloc((void**)&c->dmem, L.total) != hipSuccess) {
         (void)hipGetLastError();
         c->dmem = nullptr;
@@ -133,13 +152,21 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
     c->vals_a = (uint32_t*)(b + L.off[8]);
     c->vals_b = (uint32_t*)(b + L.off[9]);
     c->stat = (uint64_t*)(b + L.off[10]);
-    c->tile_d2 = (double*)(b + L.off[11]);
-    c->tile_best = (uint32_t*)(b + L.off[12]);
+    c->blk_d2 = (double*)(b + L.off[11]);
+    c->blk_best = (uint32_t*)(b + L.off[12]);
     c->long_list = (uint32_t*)(b + L.off[13]);
     c->huge_list = (uint32_t*)(b + L.off[14]);
     c->keep = (uint8_t*)(b + L.off[15]);
     c->out_xy = (double2*)(b + L.off[16]);
     c->out_idx = (int32_t*)(b + L.off[17]);
+    c->cand_xy = (double2*)(b + L.off[18]);
+    c->cand_idx = (uint32_t*)(b + L.off[19]);
+    c->cand_key = (uint32_t*)(b + L.off[20]);
+    c->part = (uint32_t*)(b + L.off[21]);
+    c->bmax = (uint32_t*)(b + L.off[22]);
+    c->prefix = (uint32_t*)(b + L.off[23]);
+    c->seg_count = (uint32_t*)(b + L.off[24]);
+    c->seg_off = (uint32_t*)(b + L.off[25]);
     // Look-back words carry the call's epoch; zero means "not ready" for any epoch.
     if (hipMemsetAsync(c->stat, 0, L.off[11] - L.off[10], c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -165,11 +192,6 @@ hull2d_status ensure_host(hull2d_ctx* c, int64_t m) {
     }
     c->h_cap = want;
     return HULL2D_OK;
-}
-
-int grid_for(const hull2d_ctx* c, int64_t tiles, int per_cu) {
-    int64_t g = std::min<int64_t>(tiles, (int64_t)c->cu_count * per_cu);
-    return (int)std::max<int64_t>(g, 1);
 }
 
 #define HX_TRY(call)                      \
@@ -269,9 +291,7 @@ hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->cu_count = prop.multiProcessorCount;
-    if (hipMalloc((void**)&c->ctr, sizeof(Counters)) != hipSuccess ||
-        hipMemset(c->ctr, 0, sizeof(Counters)) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_ds, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->h_ds, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         hull2d_destroy(c);
         return HULL2D_ERR_OUT_OF_MEMORY;
@@ -289,7 +309,6 @@ void hull2d_destroy(hull2d_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream || c->dmem) (void)hipStreamSynchronize(c->stream);
     if (c->dmem) (void)hipFree(c->dmem);
-    if (c->ctr) (void)hipFree(c->ctr);
     if (c->h_ds) (void)hipHostFree(c->h_ds);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
@@ -326,66 +345,106 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
 
     // Step 1
-    const int grid_ext = (int)std::max<int64_t>(1, std::min<int64_t>(kExtGridMax, ceil_div(n, kExtBlock * 4)));
+    const int grid_ext = (int)std::max<int64_t>(1, std::min<int64_t>(kExtGridMax, ceil_div(n, kExtBlock * 8)));
     HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, s));
     mark(HULL2D_STAGE_EXTREMES);
     // Steps 2-3
-    const uint32_t e_f1 = ++c->epoch;
-    HX_TRY(launch_filter1(d_xy, n, c->prm, c->comp_xy, c->comp_idx, c->keys_a, c->stat, c->tile_d2,
-                          c->tile_best, c->ds, c->ctr, e_f1, grid_for(c, ceil_div(n, kF1Tile), 8), s));
+    const int segs = std::min(filter1_blocks(n, c->cu_count), kMaxSegs);
+    HX_TRY(launch_filter1(d_xy, n, segs, c->prm, c->comp_xy, c->comp_idx, c->keys_a, c->seg_count,
+                          c->blk_d2, c->blk_best, c->ds, s));
     mark(HULL2D_STAGE_FILTER1);
     // Step 5 (needs every survivor's distance; the sort does not)
-    HX_TRY(launch_longest(n, c->tile_d2, c->tile_best, c->comp_xy, c->prm, c->ds, s));
+    HX_TRY(launch_longest(segs, c->blk_d2, c->blk_best, c->seg_count, c->seg_off, c->comp_xy, c->keys_a,
+                          c->prm, c->ds, s));
     mark(HULL2D_STAGE_LONGEST);
+    // The sorting problem: every round-1 survivor (Step 4 as printed, and the
+    // paper's subsets), or only the candidates of the bucketed filter.
+    const bool full = c->opt.round2_chunk != 0 || c->opt.full_sort != 0;
+    DevStatus* pds = c->ds;
+    const double2* pxy = c->comp_xy;
+    const uint32_t* pidx = c->comp_idx;
+    const uint32_t* pkeys = c->cand_key;   // dense keys of the full problem
+    const uint32_t* pvals = c->cand_idx;   // and their slots in the segments
+    if (!full) {
+        DevStatus* ds2 = c->ds + 1;
+        HX_TRY(launch_bucket_max(n, segs, c->seg_count, c->comp_xy, c->keys_a, c->prm, c->ds, c->part,
+                                 c->parts, s));
+        HX_TRY(launch_bucket_scan(c->part, c->parts, c->bmax, c->prefix, ds2, s));
+        HX_TRY(launch_prefilter(n, segs, c->seg_count, c->comp_xy, c->comp_idx, c->keys_a, c->prm,
+                                c->ds, c->prefix, c->cand_xy, c->cand_idx, c->cand_key, ds2, s));
+        pds = ds2;
+        pxy = c->cand_xy;
+        pidx = c->cand_idx;
+        pkeys = c->cand_key;
+        pvals = nullptr;
+    } else {
+        HX_TRY(launch_densify(n, segs, c->seg_count, c->seg_off, c->keys_a, c->cand_key, c->cand_idx, s));
+    }
+    mark(HULL2D_STAGE_BUCKETS);
     // Step 4
-    HX_TRY(launch_histogram(c->keys_a, c->ds, c->hist,
+    HX_TRY(launch_histogram(pkeys, pds, c->hist,
                             (int)std::min<int64_t>(kHistGridMax, std::max<int64_t>(1, ceil_div(n, 4096))), s));
     mark(HULL2D_STAGE_HISTOGRAM);
-    const int grid_sort = grid_for(c, ceil_div(n, kSortTile), 4);
-    uint32_t* kin = c->keys_a;
-    uint32_t* vin = nullptr;
+    const uint32_t* kin = pkeys;
+    const uint32_t* vin = pvals;
     uint32_t* kout = c->keys_b;
     uint32_t* vout = c->vals_b;
     for (int pass = 0; pass < 4; ++pass) {
         const uint32_t e = ++c->epoch;
-        HX_TRY(launch_sort_pass(pass, kin, vin, kout, vout, c->hist, c->ds, c->stat, c->ctr, e,
-                                grid_sort, s));
+        HX_TRY(launch_sort_pass(n, pass, kin, vin, kout, vout, c->hist, pds, c->stat, e,
+                                c->cu_count, s));
         mark(HULL2D_STAGE_SORT0 + pass);
         kin = kout;
         vin = vout;
         kout = (kout == c->keys_b) ? c->keys_a : c->keys_b;
         vout = (vout == c->vals_b) ? c->vals_a : c->vals_b;
     }
-    uint32_t* keys = kin;   // after four passes: keys_a / vals_a
-    uint32_t* slots = vin;
-    HX_TRY(launch_ties(n, keys, slots, c->comp_xy, c->comp_idx, c->prm, c->ds, c->long_list, s));
+    uint32_t* keys = c->keys_a;   // after four passes the result is in keys_a / vals_a
+    uint32_t* slots = c->vals_a;
+    HX_TRY(launch_ties(n, keys, slots, pxy, pidx, c->prm, pds, c->long_list, s));
     mark(HULL2D_STAGE_TIES);
-    HX_TRY(launch_ties_long(keys, slots, c->comp_xy, c->comp_idx, c->prm, c->ds, c->long_list,
-                            c->huge_list, c->cu_count, s));
+    HX_TRY(launch_ties_long(keys, slots, pxy, pidx, c->prm, pds, c->long_list, c->huge_list,
+                            c->cu_count, s));
     mark(HULL2D_STAGE_TIES_LONG);
-    // Steps 6-7
-    if (c->opt.round2_chunk == 0) {
+    // Steps 6-7 on the sorted problem, then the stable removal
+    auto round2 = [&]() -> hull2d_status {
+        if (c->opt.round2_chunk == 0) {
+            const uint32_t e = ++c->epoch;
+            HX_TRY(launch_round2_scan(n, slots, pxy, c->prm, pds, c->keep, c->stat, e, c->cu_count, s));
+        } else {
+            HX_TRY(launch_round2_chunks(n, c->opt.round2_chunk, slots, pxy, c->prm, pds, c->keep, s));
+        }
+        mark(HULL2D_STAGE_ROUND2);
         const uint32_t e = ++c->epoch;
-        HX_TRY(launch_round2_scan(slots, c->comp_xy, c->prm, c->ds, c->keep, c->stat, c->ctr, e,
-                                  grid_for(c, ceil_div(n, kR2Tile) + 2, 8), s));
-    } else {
-        HX_TRY(launch_round2_chunks(n, c->opt.round2_chunk, slots, c->comp_xy, c->prm, c->ds,
-                                    c->keep, s));
-    }
-    mark(HULL2D_STAGE_ROUND2);
-    {
-        const uint32_t e = ++c->epoch;
-        HX_TRY(launch_compact(c->keep, slots, c->comp_xy, c->comp_idx, c->out_xy, c->out_idx, c->ds,
-                              c->stat, c->ctr, e, grid_for(c, ceil_div(n, kCpTile), 8), s));
-    }
-    mark(HULL2D_STAGE_COMPACT);
-    HX_TRY(hipMemcpyAsync(c->h_ds, c->ds, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    HX_TRY(hipStreamSynchronize(s));
-    const DevStatus D = *c->h_ds;
+        HX_TRY(launch_compact(n, c->keep, slots, pxy, pidx, c->out_xy, c->out_idx, pds, c->stat, e,
+                              c->cu_count, s));
+        mark(HULL2D_STAGE_COMPACT);
+        HX_TRY(hipMemcpyAsync(c->h_ds, c->ds, 2 * sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        HX_TRY(hipStreamSynchronize(s));
+        return HULL2D_OK;
+    };
+    st = round2();
+    if (st != HULL2D_OK) return st;
+    DevStatus D = c->h_ds[0];
+    DevStatus DP = full ? c->h_ds[0] : c->h_ds[1];
     if (D.flags & kFlagNonfinite) return HULL2D_ERR_NONFINITE;
     if (D.flags & kFlagRange) return HULL2D_ERR_RANGE;
-    if (D.huge_runs > 0) return HULL2D_ERR_UNIMPLEMENTED;
-    const int64_t m = (int64_t)D.n_kept;
+    if (DP.huge_runs > 0) {
+        // Runs of equal keys longer than one workgroup sorts: merge them, then
+        // run the second round again on the corrected order.
+        std::vector<uint32_t> hl(2 * (size_t)DP.huge_runs);
+        HX_TRY(hipMemcpyAsync(hl.data(), c->huge_list, hl.size() * sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, s));
+        HX_TRY(hipStreamSynchronize(s));
+        for (uint32_t r = 0; r < DP.huge_runs; ++r)
+            HX_TRY(launch_huge_run(slots, c->vals_b, hl[2 * r], hl[2 * r + 1], pxy, pidx, c->prm, pds, s));
+        st = round2();
+        if (st != HULL2D_OK) return st;
+        D = c->h_ds[0];
+        DP = full ? c->h_ds[0] : c->h_ds[1];
+    }
+    const DevStatus DS = DP;
+    const int64_t m = (int64_t)DS.n_kept;
     st = ensure_host(c, m);
     if (st != HULL2D_OK) return st;
     auto t_d2h = std::chrono::steady_clock::now();
@@ -406,8 +465,10 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     const double ms_scan = ms_since(t_scan);
 
     c->have_last = true;
+    c->last_full = full;
     c->last_n = n;
     c->last_ds = D;
+    c->last_ds2 = DS;
 
     *n_out = h;
     if (stats) {
@@ -415,6 +476,7 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
         stats->n_sorted = D.n_sorted;
         stats->n_round2 = m + 1;
         stats->n_hull = h;
+        stats->n_candidates = DS.n_sorted;
         if (c->have_events) {
             float f = 0.f;
             if (hipEventElapsedTime(&f, ev_begin, ev_end) == hipSuccess)
@@ -424,6 +486,7 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
             // stage i ends at event i; Step 1's two kernels are reported
             // together under EXTREMES.
             const int order[] = {HULL2D_STAGE_EXTREMES, HULL2D_STAGE_FILTER1, HULL2D_STAGE_LONGEST,
+                                 HULL2D_STAGE_BUCKETS,
                                  HULL2D_STAGE_HISTOGRAM, HULL2D_STAGE_SORT0, HULL2D_STAGE_SORT1,
                                  HULL2D_STAGE_SORT2, HULL2D_STAGE_SORT3, HULL2D_STAGE_TIES,
                                  HULL2D_STAGE_TIES_LONG, HULL2D_STAGE_ROUND2, HULL2D_STAGE_COMPACT,
@@ -487,21 +550,27 @@ hull2d_status hull2d_debug_stages(hull2d_ctx* c, int32_t* extremes, int32_t* sor
     if (!c->have_last) return HULL2D_ERR_INVALID_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
     const DevStatus& D = c->last_ds;
-    const int64_t ms = D.n_sorted, m2 = (int64_t)D.n_kept + 1;
+    const DevStatus& DS = c->last_ds2;
+    const int64_t ms = D.n_sorted, m2 = (int64_t)DS.n_kept + 1;
+    int64_t l = 0;
+    if (ms > 0) l = c->last_full ? (int64_t)D.l_pos + 1 : (int64_t)D.n_right + 1;
     if (counts) {
         counts[0] = ms;
-        counts[1] = ms > 0 ? (int64_t)D.l_pos + 1 : 0;
+        counts[1] = l;
         counts[2] = m2;
         counts[3] = D.l_idx;
+        counts[4] = c->last_full ? 1 : 0;
+        counts[5] = DS.n_sorted;
     }
     if (extremes)
         for (int k = 0; k < 4; ++k) extremes[k] = D.ext[k];
-    if ((sorted && cap < ms) || (round2 && cap < m2)) return HULL2D_ERR_CAPACITY;
-    if (sorted && ms > 0) {
+    if ((sorted && c->last_full && cap < ms) || (round2 && cap < m2)) return HULL2D_ERR_CAPACITY;
+    if (sorted && c->last_full && ms > 0) {
         // the sorted slots sit in vals_a after four passes
         std::vector<uint32_t> sl((size_t)ms), ix((size_t)c->last_n);
         HX_TRY(hipMemcpy(sl.data(), c->vals_a, (size_t)ms * sizeof(uint32_t), hipMemcpyDeviceToHost));
-        HX_TRY(hipMemcpy(ix.data(), c->comp_idx, (size_t)ms * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HX_TRY(hipMemcpy(ix.data(), c->comp_idx, (size_t)c->last_n * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < ms; ++i) sorted[i] = (int32_t)ix[sl[i]];
     }
     if (round2) {

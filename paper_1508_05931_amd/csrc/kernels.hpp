@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <tuple>
+
 #include "common.hpp"
 
 namespace hx {
@@ -29,30 +32,83 @@ constexpr int kHistGridMax = 512;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Kernels that chain tile prefixes by look-back take tiles in a fixed order
+// (tile t is processed by block t mod grid, blocks walk their tiles upwards).
+// They are launched cooperatively with at most as many blocks as fit on the
+// device at once, so every tile a block waits for belongs to a running block.
+template <typename K>
+inline int coop_grid(K kernel, int block, int cu_count, int64_t tiles) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel),
+                                                     block, 0) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    int64_t g = std::min<int64_t>(tiles, (int64_t)per_cu * cu_count);
+    return (int)std::max<int64_t>(g, 1);
+}
+
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_coop(void (*kernel)(KArgs...), int grid, int block, hipStream_t s,
+                              Args... args) {
+    std::tuple<KArgs...> t(args...);
+    void* ptrs[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+    std::apply([&](auto&... xs) {
+        int i = 0;
+        ((ptrs[i++] = (void*)&xs), ...);
+    }, t);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block),
+                                      ptrs, 0, s);
+}
+
 // Step 1: partial extreme candidates per block, then the final reduction,
 // the quadrilateral and the pivot.
 hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
                            DevStatus* ds, hipStream_t s);
 
 // Steps 2-3: strict-interior test against the quadrilateral, exact angle key,
-// squared distance, order-preserving compaction of the survivors.
-hipError_t launch_filter1(const double* xy, int64_t n, const Params* prm, double2* comp_xy,
-                          uint32_t* comp_idx, uint32_t* keys, uint64_t* stat, double* tile_d2,
-                          uint32_t* tile_best, DevStatus* ds, Counters* ctr, uint32_t epoch,
-                          int grid, hipStream_t s);
+// squared distance.  Block b compacts the survivors of its input range into
+// the same range of comp_xy / comp_idx / keys (a segment of seg_count[b]
+// points starting at b*filter1_chunk).
+constexpr int kF1BlocksPerCu = 4;
+int filter1_blocks(int64_t n, int cu_count);
+int64_t filter1_chunk(int64_t n, int blocks);
+hipError_t launch_filter1(const double* xy, int64_t n, int blocks, const Params* prm,
+                          double2* comp_xy, uint32_t* comp_idx, uint32_t* keys, uint32_t* seg_count,
+                          double* blk_d2, uint32_t* blk_best, DevStatus* ds, hipStream_t s);
 
-// Step 5: farthest point from the tile partials.
-hipError_t launch_longest(int64_t n, const double* tile_d2, const uint32_t* tile_best,
-                          const double2* comp_xy, Params* prm, DevStatus* ds, hipStream_t s);
+// Step 5 and the segment offsets (one block).
+hipError_t launch_longest(int blocks, const double* blk_d2, const uint32_t* blk_best,
+                          const uint32_t* seg_count, uint32_t* seg_off, const double2* comp_xy,
+                          const uint32_t* keys, Params* prm, DevStatus* ds, hipStream_t s);
+
+// Dense (key, slot) pairs of all survivors (for the full sort).
+hipError_t launch_densify(int64_t n, int blocks, const uint32_t* seg_count, const uint32_t* seg_off,
+                          const uint32_t* keys, uint32_t* dkeys, uint32_t* dslots, hipStream_t s);
+
+// Steps 6-7, bucketed: coarse angle buckets (top bits of the angle key), the
+// maximum direction key seen from P_l per bucket and region, an exclusive
+// prefix over buckets, and the candidates that can still be running maxima.
+// The candidates form a new (small) sorting problem with status ds2.
+constexpr int kBmBlock = 512;
+hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
+                             const uint32_t* keys, const Params* prm, DevStatus* ds, uint32_t* part,
+                             int parts, hipStream_t s);
+hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, uint32_t* prefix,
+                              DevStatus* ds2, hipStream_t s);
+hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
+                            const uint32_t* comp_idx, const uint32_t* keys, const Params* prm,
+                            const DevStatus* ds, const uint32_t* prefix, double2* cand_xy,
+                            uint32_t* cand_idx, uint32_t* cand_key, DevStatus* ds2, hipStream_t s);
 
 // Step 4: digit histograms, four stable radix passes, exact order inside
 // equal-key runs.
 hipError_t launch_histogram(const uint32_t* keys, const DevStatus* ds, uint32_t* hist, int grid,
                             hipStream_t s);
-hipError_t launch_sort_pass(int pass, const uint32_t* keys_in, const uint32_t* vals_in,
+hipError_t launch_sort_pass(int64_t n, int pass, const uint32_t* keys_in, const uint32_t* vals_in,
                             uint32_t* keys_out, uint32_t* vals_out, const uint32_t* hist,
-                            const DevStatus* ds, uint64_t* stat, Counters* ctr, uint32_t epoch,
-                            int grid, hipStream_t s);
+                            const DevStatus* ds, uint64_t* stat, uint32_t epoch, int cu_count,
+                            hipStream_t s);
 hipError_t launch_ties(int64_t n, const uint32_t* keys, uint32_t* slots, const double2* comp_xy,
                        const uint32_t* comp_idx, const Params* prm, DevStatus* ds,
                        uint32_t* long_list, hipStream_t s);
@@ -61,18 +117,24 @@ hipError_t launch_ties_long(const uint32_t* keys, uint32_t* slots, const double2
                             const uint32_t* long_list, uint32_t* huge_list, int grid,
                             hipStream_t s);
 
+// Exact order of one equal-key run longer than kRunCap at [start, start+L)
+// of slots (tmp: scratch of the same size as slots); also finds P_l in it.
+hipError_t launch_huge_run(uint32_t* slots, uint32_t* tmp, uint32_t start, uint32_t L,
+                           const double2* comp_xy, const uint32_t* comp_idx, const Params* prm,
+                           DevStatus* ds, hipStream_t s);
+
 // Steps 6-7: second-round filter (one walk per region as a prefix scan, or
 // the paper's per-thread subsets), then stable compaction of the kept points.
-hipError_t launch_round2_scan(const uint32_t* slots, const double2* comp_xy, const Params* prm,
-                              const DevStatus* ds, uint8_t* keep, uint64_t* stat,
-                              Counters* ctr, uint32_t epoch, int grid, hipStream_t s);
+hipError_t launch_round2_scan(int64_t n, const uint32_t* slots, const double2* comp_xy,
+                              const Params* prm, const DevStatus* ds, uint8_t* keep, uint64_t* stat,
+                              uint32_t epoch, int cu_count, hipStream_t s);
 hipError_t launch_round2_chunks(int64_t n, int64_t chunk, const uint32_t* slots,
                                 const double2* comp_xy, const Params* prm, const DevStatus* ds,
                                 uint8_t* keep, hipStream_t s);
-hipError_t launch_compact(const uint8_t* keep, const uint32_t* slots, const double2* comp_xy,
-                          const uint32_t* comp_idx, double2* out_xy, int32_t* out_idx,
-                          DevStatus* ds, uint64_t* stat, Counters* ctr, uint32_t epoch, int grid,
-                          hipStream_t s);
+hipError_t launch_compact(int64_t n, const uint8_t* keep, const uint32_t* slots,
+                          const double2* comp_xy, const uint32_t* comp_idx, double2* out_xy,
+                          int32_t* out_idx, DevStatus* ds, uint64_t* stat, uint32_t epoch,
+                          int cu_count, hipStream_t s);
 
 // Checking kernels.
 hipError_t launch_debug_orient(const double* abc, int64_t count, int32_t* out, hipStream_t s);

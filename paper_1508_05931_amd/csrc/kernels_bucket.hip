@@ -1,0 +1,287 @@
+// kernels_bucket.hip - Steps 6-7 of gScan without sorting every survivor.
+//
+// Figure 2's walk keeps a point exactly when it follows the running maximum
+// of everything walked before it in the region's order, "B follows A" being
+// orient(P_l, A, B) >= 0 in the right region and <= 0 in the left one (see
+// kernels_filter.hip).  Seen from P_l that order is the order of directions
+// over a half-open half-plane, so an exact 32-bit direction key kappa (the
+// full-turn key of p - P_l, measured from the region's reference direction)
+// satisfies: kappa(A) < kappa(B) implies that B strictly follows A.
+//
+// Split the survivors into coarse angle buckets (top bits of the angle key
+// about P_0; the walk visits buckets in key order in the right region and in
+// reverse order in the left one).  A point whose kappa is below the largest
+// kappa of an earlier bucket is strictly dominated by an earlier point, so the
+// walk discards it.  Every point the walk keeps passes this test, and the
+// walk's running maximum is always a kept point, so running Figure 2 over the
+// passing points alone (the candidates, in exact angular order) keeps exactly
+// the same points as running it over all of them.  The candidates are usually
+// a few tenths of a percent of the survivors; they are then sorted and
+// scanned by the same kernels as the full problem.
+#include "exact.hpp"
+#include "kernels.hpp"
+
+namespace hx {
+namespace {
+
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr int kPfBlock = 256;
+constexpr int kPfItems = 4;    // points loaded per thread before any is used
+constexpr int kPfCap = 4096;   // LDS slots buffered per block before a flush
+constexpr int kBmItems = 4;
+
+struct Cls {
+    int region;      // 0 right of P_l, 1 left of P_l, 2 P_l or a copy of it
+    uint32_t kappa;  // direction key in the region's order (larger follows)
+    uint32_t bucket;
+};
+
+// Region by the exact angular order (angle key first, orientation on equal
+// keys, distance along the ray on the same ray), then the direction key.
+__device__ inline Cls classify(double x, double y, uint32_t key, const Params& P) {
+    Cls c;
+    c.bucket = key >> (32 - kBucketBits);
+    c.kappa = 0;
+    if (x == P.lx && y == P.ly) {
+        c.region = 2;
+        return c;
+    }
+    int region;
+    if (key < P.kl) {
+        region = 0;
+    } else if (key > P.kl) {
+        region = 1;
+    } else {
+        int o = orient(P.x0, P.y0, P.lx, P.ly, x, y);
+        if (o != 0) region = o < 0 ? 0 : 1;
+        else region = (y < P.ly || (y == P.ly && x < P.lx)) ? 0 : 1;
+    }
+    uint32_t F = turn_key(x, y, P.lx, P.ly);
+    // right region: counter-clockwise from P_0 - P_l; left region: clockwise
+    // from P_l - P_0 (the key is reversed so that larger always follows)
+    c.kappa = region == 0 ? F - P.turn_u : 0xFFFFFFFFu - (F - P.turn_v);
+    c.region = region;
+    return c;
+}
+
+__device__ inline Params load_params(const Params* __restrict__ prm) { return *prm; }
+
+// Per-block maxima of kappa per (region, bucket) into LDS, written out as one
+// table per block; also counts the right region.  Each block takes a
+// contiguous range; every thread loads kBmItems points before it uses any of
+// them, so enough loads are in flight to cover the memory latency.
+__global__ __launch_bounds__(kBmBlock) void k_bucket_max(int64_t chunk, int segs,
+                                                        const uint32_t* __restrict__ seg_count,
+                                                        const double2* __restrict__ comp_xy,
+                                                        const uint32_t* __restrict__ keys,
+                                                        const Params* __restrict__ prm,
+                                                        DevStatus* __restrict__ ds,
+                                                        uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_tab[2 * kBuckets];
+    __shared__ uint32_t s_right;
+    for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += kBmBlock) s_tab[i] = 0;
+    if (threadIdx.x == 0) s_right = 0;
+    __syncthreads();
+    const Params P = load_params(prm);
+    const int spb = (segs + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int sg_end = min(segs, ((int)blockIdx.x + 1) * spb);
+    uint32_t nr = 0;
+    for (int sg = (int)blockIdx.x * spb; sg < sg_end; ++sg) {
+    const uint32_t beg = (uint32_t)(sg * chunk);
+    const uint32_t end = beg + seg_count[sg];
+    for (uint32_t base = beg; base < end; base += kBmBlock * kBmItems) {
+        double2 p[kBmItems];
+        uint32_t k[kBmItems];
+#pragma unroll
+        for (int u = 0; u < kBmItems; ++u) {
+            uint32_t s = base + u * kBmBlock + threadIdx.x;
+            if (s < end) {
+                p[u] = comp_xy[s];
+                k[u] = keys[s];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBmItems; ++u) {
+            uint32_t s = base + u * kBmBlock + threadIdx.x;
+            if (s < end) {
+                Cls c = classify(p[u].x, p[u].y, k[u], P);
+                if (c.region != 2) {
+                    nr += c.region == 0;
+                    atomicMax(&s_tab[c.region * kBuckets + c.bucket], c.kappa);
+                }
+            }
+        }
+    }
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) nr += __shfl_xor(nr, m);
+    if (__lane_id() == 0 && nr) atomicAdd(&s_right, nr);
+    __syncthreads();
+    uint32_t* out = part + (size_t)blockIdx.x * 2 * kBuckets;
+    for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += kBmBlock) out[i] = s_tab[i];
+    if (threadIdx.x == 0 && s_right) atomicAdd(&ds->n_right, s_right);
+}
+
+// Column maxima of the per-block tables: a block takes 64 columns, its four
+// waves split the rows, several loads in flight per thread.
+__global__ __launch_bounds__(256) void k_bucket_reduce(const uint32_t* __restrict__ part, int parts,
+                                                       uint32_t* __restrict__ bmax) {
+    __shared__ uint32_t s_m[4][64];
+    const int c = (int)(threadIdx.x & 63), g = (int)(threadIdx.x >> 6);
+    const int col = (int)blockIdx.x * 64 + c;
+    uint32_t m = 0;
+#pragma unroll 8
+    for (int p = g; p < parts; p += 4) m = max(m, part[(size_t)p * 2 * kBuckets + col]);
+    s_m[g][c] = m;
+    __syncthreads();
+    if (g == 0) bmax[col] = max(max(s_m[0][c], s_m[1][c]), max(s_m[2][c], s_m[3][c]));
+}
+
+// Exclusive prefix maxima in walking order: ascending buckets for the right
+// region (starting from kappa(P_0) = 0), descending for the left region
+// (identity 0).  One block of 1024 threads, four buckets per thread.  Also
+// resets the status of the candidate problem.
+__global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict__ bmax,
+                                                      uint32_t* __restrict__ prefix,
+                                                      DevStatus* __restrict__ ds2) {
+    constexpr int PER = kBuckets / 1024;
+    __shared__ uint32_t s_w[16];
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    for (int region = 0; region < 2; ++region) {
+        // walking position w = threadIdx.x*PER + k maps to bucket b(w)
+        uint32_t v[PER];
+        uint32_t tmax = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            int w = (int)threadIdx.x * PER + k;
+            int b = region == 0 ? w : kBuckets - 1 - w;
+            v[k] = bmax[region * kBuckets + b];
+            tmax = max(tmax, v[k]);
+        }
+        // exclusive scan of the thread maxima
+        uint32_t inc = tmax;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            uint32_t o = __shfl_up(inc, d);
+            if (lane >= d) inc = max(inc, o);
+        }
+        uint32_t ex = __shfl_up(inc, 1);
+        if (lane == 0) ex = 0;
+        if (lane == 63) s_w[wave] = inc;
+        __syncthreads();
+        for (int w = 0; w < wave; ++w) ex = max(ex, s_w[w]);
+        __syncthreads();
+        uint32_t run = ex;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            int w = (int)threadIdx.x * PER + k;
+            int b = region == 0 ? w : kBuckets - 1 - w;
+            prefix[region * kBuckets + b] = run;
+            run = max(run, v[k]);
+        }
+    }
+    if (threadIdx.x == 0) {
+        ds2->flags = 0;
+        ds2->huge_runs = 0;
+        ds2->n_sorted = 0;
+        ds2->n_p0 = 0;
+        ds2->l_pos = 0;
+        ds2->n_kept = 0;
+        ds2->long_runs = 0;
+        ds2->l_slot = kNoSlot;
+        ds2->n_right = 0;
+    }
+}
+
+// Candidates: P_l and its copies, and every point whose kappa reaches the
+// prefix maximum of its bucket.  Buffered per block in LDS, then appended
+// with one atomic per flush (their order does not matter: they are sorted
+// next).
+__global__ __launch_bounds__(kPfBlock) void k_prefilter(
+    int64_t chunk, const uint32_t* __restrict__ seg_count,
+    const double2* __restrict__ comp_xy, const uint32_t* __restrict__ comp_idx,
+    const uint32_t* __restrict__ keys, const Params* __restrict__ prm,
+    const DevStatus* __restrict__ ds, const uint32_t* __restrict__ prefix,
+    double2* __restrict__ cand_xy, uint32_t* __restrict__ cand_idx, uint32_t* __restrict__ cand_key,
+    DevStatus* __restrict__ ds2) {
+    __shared__ uint32_t s_buf[kPfCap];
+    __shared__ uint32_t s_n, s_base;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const Params P = load_params(prm);
+    const uint32_t lslot = ds->l_slot;
+    const uint32_t beg = (uint32_t)(blockIdx.x * chunk);   // one segment per block
+    const uint32_t end = beg + seg_count[blockIdx.x];
+    auto flush = [&]() {
+        __syncthreads();
+        const uint32_t cnt = s_n;
+        if (threadIdx.x == 0 && cnt) s_base = atomicAdd(&ds2->n_sorted, cnt);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += kPfBlock) {
+            uint32_t s = s_buf[i];
+            uint32_t o = s_base + i;
+            cand_xy[o] = comp_xy[s];
+            cand_idx[o] = comp_idx[s];
+            cand_key[o] = keys[s];
+            if (s == lslot) ds2->l_slot = o;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+    };
+    for (uint32_t base = beg; base < end; base += kPfBlock * kPfItems) {
+        double2 p[kPfItems];
+        uint32_t k[kPfItems];
+#pragma unroll
+        for (int u = 0; u < kPfItems; ++u) {
+            uint32_t s = base + u * kPfBlock + threadIdx.x;
+            if (s < end) {
+                p[u] = comp_xy[s];
+                k[u] = keys[s];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPfItems; ++u) {
+            uint32_t s = base + u * kPfBlock + threadIdx.x;
+            if (s < end) {
+                Cls c = classify(p[u].x, p[u].y, k[u], P);
+                const bool keep = (c.region == 2) ||
+                                  (c.kappa >= prefix[(c.region & 1) * kBuckets + c.bucket]);
+                if (keep) s_buf[atomicAdd(&s_n, 1u)] = s;
+            }
+        }
+        __syncthreads();
+        if (s_n > (uint32_t)(kPfCap - kPfBlock * kPfItems)) flush();
+    }
+    flush();
+}
+
+}  // namespace
+
+hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
+                             const uint32_t* keys, const Params* prm, DevStatus* ds, uint32_t* part,
+                             int parts, hipStream_t s) {
+    hipLaunchKernelGGL(k_bucket_max, dim3(parts), dim3(kBmBlock), 0, s, filter1_chunk(n, segs), segs,
+                       seg_count, comp_xy, keys, prm, ds, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, uint32_t* prefix,
+                              DevStatus* ds2, hipStream_t s) {
+    hipLaunchKernelGGL(k_bucket_reduce, dim3(2 * kBuckets / 64), dim3(256), 0, s, part, parts, bmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, bmax, prefix, ds2);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
+                            const uint32_t* comp_idx, const uint32_t* keys, const Params* prm,
+                            const DevStatus* ds, const uint32_t* prefix, double2* cand_xy,
+                            uint32_t* cand_idx, uint32_t* cand_key, DevStatus* ds2, hipStream_t s) {
+    hipLaunchKernelGGL(k_prefilter, dim3(segs), dim3(kPfBlock), 0, s, filter1_chunk(n, segs), seg_count,
+                       comp_xy, comp_idx, keys, prm, ds, prefix, cand_xy, cand_idx, cand_key, ds2);
+    return hipGetLastError();
+}
+
+}  // namespace hx

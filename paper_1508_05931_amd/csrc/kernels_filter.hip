@@ -13,9 +13,10 @@
 //                                  thread per subset (Section 3.4)
 //   k_compact                      Step 7: stable removal of interior points
 //
-// Streaming kernels take tiles from a ticket counter (tiles are started in
-// order) and chain tile prefixes by decoupled look-back (Merrill & Garland,
-// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016).
+// Streaming kernels chain tile prefixes by decoupled look-back (Merrill &
+// Garland, "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016);
+// tile t belongs to block t mod grid and the grid is launched cooperatively
+// (every block resident), so a predecessor tile is always being processed.
 #include <float.h>
 
 #include "exact.hpp"
@@ -89,12 +90,22 @@ __device__ uint32_t lookback_sum(uint64_t* stat, uint32_t t, uint32_t agg, uint3
 // Strict total orders of the four extreme criteria (ties: P_minx -> larger y,
 // P_miny -> smaller x, P_maxx -> smaller y, P_maxy -> larger x, then smaller
 // index), so every reduction order returns the same candidates.
+//
+// These comparisons and the selections that use them are written with
+// bitwise operators and explicit per-field selects: with short-circuit
+// conditions guarding a whole-struct copy, the gfx950 code generator of this
+// toolchain kept the old index on the tie path (wrong Step-1 corners on
+// grid inputs).  Straight-line code avoids that shape.
 template <int C>
 __device__ inline bool better(const Cand& a, const Cand& b) {
-    if (C == 0) return a.x < b.x || (a.x == b.x && (a.y > b.y || (a.y == b.y && a.i < b.i)));
-    if (C == 1) return a.y < b.y || (a.y == b.y && (a.x < b.x || (a.x == b.x && a.i < b.i)));
-    if (C == 2) return a.x > b.x || (a.x == b.x && (a.y < b.y || (a.y == b.y && a.i < b.i)));
-    return a.y > b.y || (a.y == b.y && (a.x > b.x || (a.x == b.x && a.i < b.i)));
+    const double a1 = (C == 0 || C == 2) ? a.x : a.y, b1 = (C == 0 || C == 2) ? b.x : b.y;
+    const double a2 = (C == 0 || C == 2) ? a.y : a.x, b2 = (C == 0 || C == 2) ? b.y : b.x;
+    // primary: smaller for P_minx / P_miny, larger for P_maxx / P_maxy;
+    // secondary: larger for P_minx / P_maxy, smaller for P_miny / P_maxx
+    const bool p_win = (C <= 1) ? (a1 < b1) : (a1 > b1);
+    const bool s_win = (C == 0 || C == 3) ? (a2 > b2) : (a2 < b2);
+    const bool p_eq = a1 == b1, s_eq = a2 == b2, i_win = a.i < b.i;
+    return p_win | (p_eq & (s_win | (s_eq & i_win)));
 }
 
 __device__ inline Cand sentinel(int c) {
@@ -117,7 +128,10 @@ __device__ inline Cand shfl_xor_cand(const Cand& c, int m) {
 
 template <int C>
 __device__ inline void take_better(Cand& c, const Cand& o) {
-    if (better<C>(o, c)) c = o;
+    const bool t = better<C>(o, c);
+    c.x = t ? o.x : c.x;
+    c.y = t ? o.y : c.y;
+    c.i = t ? o.i : c.i;
 }
 
 __device__ inline void reduce4_wave(Cand (&c)[4]) {
@@ -152,7 +166,7 @@ __device__ inline void offer(Cand (&c)[4], double x, double y, int32_t i) {
 __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restrict__ xy, int64_t n,
                                                         Cand* __restrict__ partial) {
     constexpr int NW = kExtBlock / 64;
-    constexpr int U = 4;
+    constexpr int U = 8;
     __shared__ Cand s_c[NW][4];
     __shared__ uint32_t s_flags;
     Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
@@ -189,9 +203,10 @@ __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restric
         Cand b = s_c[0][k];
         for (int w = 1; w < NW; ++w) {
             Cand o = s_c[w][k];
-            bool take = k == 0 ? better<0>(o, b) : k == 1 ? better<1>(o, b)
-                      : k == 2 ? better<2>(o, b) : better<3>(o, b);
-            if (take) b = o;
+            if (k == 0) take_better<0>(b, o);
+            else if (k == 1) take_better<1>(b, o);
+            else if (k == 2) take_better<2>(b, o);
+            else take_better<3>(b, o);
         }
         b.pad = (int32_t)s_flags;
         partial[(int64_t)blockIdx.x * 4 + k] = b;
@@ -275,7 +290,9 @@ __global__ __launch_bounds__(256) void k_extremes_final(const Cand* __restrict__
     P.lx = P.x0;
     P.ly = P.y0;
     P.l_idx = -1;
-    P.l_slot = kSlotNone;
+    P.kl = 0;
+    P.turn_u = P.turn_v = 0;
+    P.pad2[0] = P.pad2[1] = 0;
     *prm = P;
     DevStatus S;
     S.flags = s_flags;
@@ -285,6 +302,8 @@ __global__ __launch_bounds__(256) void k_extremes_final(const Cand* __restrict__
     S.l_pos = 0;
     S.n_kept = 0;
     S.long_runs = 0;
+    S.l_slot = kSlotNone;
+    S.n_right = 0;
     S.pad = 0;
     for (int k = 0; k < 4; ++k) S.ext[k] = e[k].i;
     S.p0_idx = e[1].i;
@@ -296,17 +315,22 @@ __global__ __launch_bounds__(256) void k_extremes_final(const Cand* __restrict__
 
 // ---------------------------------------------------------------------------
 // Steps 2-3
+//
+// Block b owns the input range [b*chunk, (b+1)*chunk) and compacts its
+// survivors, in input order, into the same range of the output arrays (a
+// segment: survivors never outnumber inputs).  No block waits for another;
+// the segment lengths are added up afterwards (k_longest), and later kernels
+// read the survivors segment by segment.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kF1Block) void k_filter1(
-    const double2* __restrict__ xy, int64_t n, const Params* __restrict__ prm,
+    const double2* __restrict__ xy, int64_t n, int64_t chunk, const Params* __restrict__ prm,
     double2* __restrict__ comp_xy, uint32_t* __restrict__ comp_idx, uint32_t* __restrict__ keys,
-    uint64_t* __restrict__ stat, double* __restrict__ tile_d2, uint32_t* __restrict__ tile_best,
-    DevStatus* __restrict__ ds, Counters* __restrict__ ctr, uint32_t epoch) {
+    uint32_t* __restrict__ seg_count, double* __restrict__ blk_d2, uint32_t* __restrict__ blk_best,
+    DevStatus* __restrict__ ds) {
     constexpr int NW = kF1Block / 64;
     constexpr int G = kF1Ipt * NW;  // (item, wave) groups in position order
-    __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_off[G];
-    __shared__ uint32_t s_excl;
+    __shared__ uint32_t s_total;
     __shared__ double s_bd2[NW];
     __shared__ uint32_t s_bidx[NW], s_bslot[NW], s_p0[NW];
 
@@ -322,36 +346,30 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
         ex[j] = prm->ex[j];
         ey[j] = prm->ey[j];
     }
-    const uint32_t ntiles = (uint32_t)ceil_div(n, kF1Tile);
-    uint32_t* ticket = &ctr->ticket[kTicketFilter1];
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = min(n, beg + chunk);
+    int64_t cursor = beg;  // next output position of this segment
+    double bd2 = -1.0;     // this thread's farthest survivor so far
+    uint32_t bidx = 0xFFFFFFFFu, bslot = 0xFFFFFFFFu;
+    uint32_t p0c = 0;
 
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = take_ticket(ticket);
-        __syncthreads();
-        const uint32_t t = s_ticket;
-        __syncthreads();
-        if (t >= ntiles) {
-            if (threadIdx.x == 0 && t == ntiles + gridDim.x - 1) reset_ticket(ticket);
-            break;
-        }
-        const int64_t base = (int64_t)t * kF1Tile;
+    for (int64_t base = beg; base < end; base += kF1Tile) {
         double2 p[kF1Ipt];
 #pragma unroll
         for (int k = 0; k < kF1Ipt; ++k) {
             int64_t pos = base + k * kF1Block + threadIdx.x;
-            if (pos < n) p[k] = xy[pos];
+            if (pos < end) p[k] = xy[pos];
         }
         uint64_t mask[kF1Ipt];
         uint32_t key[kF1Ipt];
-        double bd2 = -1.0;
-        uint32_t bidx = 0xFFFFFFFFu, bgrp = 0, brank = 0;
-        uint32_t p0c = 0;
+        double td2 = -1.0;
+        uint32_t tidx = 0xFFFFFFFFu, tgrp = 0, trank = 0;
 #pragma unroll
         for (int k = 0; k < kF1Ipt; ++k) {
             int64_t pos = base + k * kF1Block + threadIdx.x;
             bool surv = false;
             key[k] = 0;
-            if (pos < n && !discard_all) {
+            if (pos < end && !discard_all) {
                 const double px = p[k].x, py = p[k].y;
                 bool inside = nc >= 3;
 #pragma unroll
@@ -380,140 +398,179 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
                     double dxx = dx * dx;
                     double dyy = dy * dy;
                     double d2 = dxx + dyy;
-                    if (d2 > bd2 || (d2 == bd2 && (uint32_t)pos < bidx)) {
-                        bd2 = d2;
-                        bidx = (uint32_t)pos;
-                        bgrp = (uint32_t)(k * NW + wave);
-                    }
+                    const bool take = (d2 > td2) | ((d2 == td2) & ((uint32_t)pos < tidx));
+                    td2 = take ? d2 : td2;
+                    tidx = take ? (uint32_t)pos : tidx;
+                    tgrp = take ? (uint32_t)(k * NW + wave) : tgrp;
                 }
             }
             mask[k] = __ballot(surv);
-            if (surv && bidx == (uint32_t)pos) brank = __popcll(mask[k] & lanemask_lt());
+            if (surv && tidx == (uint32_t)pos) trank = __popcll(mask[k] & lanemask_lt());
             if (lane == 0) s_off[k * NW + wave] = (uint32_t)__popcll(mask[k]);
         }
-        // pivot copies
-        uint32_t p0w = wave_sum(p0c);
-        if (lane == 0) s_p0[wave] = p0w;
         __syncthreads();
         if (wave == 0) {
             uint32_t v = lane < G ? s_off[lane] : 0u;
             uint32_t inc = wave_incl_scan(v);
             if (lane < G) s_off[lane] = inc - v;
-            uint32_t total = __shfl(inc, 63);
-            uint32_t excl = lookback_sum(stat, t, total, epoch);
-            if (lane == 0) {
-                s_excl = excl;
-                uint32_t pc = 0;
-                for (int w = 0; w < NW; ++w) pc += s_p0[w];
-                if (pc) atomicAdd(&ds->n_p0, pc);
-                if (t == ntiles - 1) ds->n_sorted = excl + total;
-            }
+            if (lane == 63) s_total = inc;
         }
         __syncthreads();
-        const uint32_t excl = s_excl;
 #pragma unroll
         for (int k = 0; k < kF1Ipt; ++k) {
             if ((mask[k] >> lane) & 1ull) {
                 int64_t pos = base + k * kF1Block + threadIdx.x;
-                uint32_t o = excl + s_off[k * NW + wave] + (uint32_t)__popcll(mask[k] & lanemask_lt());
+                int64_t o = cursor + s_off[k * NW + wave] + (uint32_t)__popcll(mask[k] & lanemask_lt());
                 comp_xy[o] = p[k];
                 comp_idx[o] = (uint32_t)pos;
                 keys[o] = key[k];
             }
         }
-        // farthest point of the tile: largest d2, then smallest index
-        uint32_t bslot = bidx == 0xFFFFFFFFu ? 0xFFFFFFFFu : excl + s_off[bgrp] + brank;
+        // this tile's farthest survivor of this thread, with its output slot
+        if (tidx != 0xFFFFFFFFu) {
+            const uint32_t tslot = (uint32_t)(cursor + s_off[tgrp] + trank);
+            const bool take = (td2 > bd2) | ((td2 == bd2) & (tidx < bidx));
+            bd2 = take ? td2 : bd2;
+            bidx = take ? tidx : bidx;
+            bslot = take ? tslot : bslot;
+        }
+        cursor += s_total;
+        __syncthreads();
+    }
+    // block results: segment length, farthest survivor, copies of the pivot
 #pragma unroll
-        for (int m = 32; m > 0; m >>= 1) {
-            double od = __shfl_xor(bd2, m);
-            uint32_t oi = __shfl_xor(bidx, m);
-            uint32_t os = __shfl_xor(bslot, m);
-            if (od > bd2 || (od == bd2 && oi < bidx)) {
-                bd2 = od;
-                bidx = oi;
-                bslot = os;
-            }
+    for (int m = 32; m > 0; m >>= 1) {
+        double od = __shfl_xor(bd2, m);
+        uint32_t oi = __shfl_xor(bidx, m);
+        uint32_t os = __shfl_xor(bslot, m);
+        const bool take = (od > bd2) | ((od == bd2) & (oi < bidx));
+        bd2 = take ? od : bd2;
+        bidx = take ? oi : bidx;
+        bslot = take ? os : bslot;
+    }
+    uint32_t p0w = wave_sum(p0c);
+    if (lane == 0) {
+        s_bd2[wave] = bd2;
+        s_bidx[wave] = bidx;
+        s_bslot[wave] = bslot;
+        s_p0[wave] = p0w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double d = s_bd2[0];
+        uint32_t bi = s_bidx[0], bs = s_bslot[0], pc = s_p0[0];
+        for (int w = 1; w < NW; ++w) {
+            const bool take = (s_bd2[w] > d) | ((s_bd2[w] == d) & (s_bidx[w] < bi));
+            d = take ? s_bd2[w] : d;
+            bi = take ? s_bidx[w] : bi;
+            bs = take ? s_bslot[w] : bs;
+            pc += s_p0[w];
         }
-        if (lane == 0) {
-            s_bd2[wave] = bd2;
-            s_bidx[wave] = bidx;
-            s_bslot[wave] = bslot;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double d = s_bd2[0];
-            uint32_t bi = s_bidx[0], bs = s_bslot[0];
-            for (int w = 1; w < NW; ++w) {
-                if (s_bd2[w] > d || (s_bd2[w] == d && s_bidx[w] < bi)) {
-                    d = s_bd2[w];
-                    bi = s_bidx[w];
-                    bs = s_bslot[w];
-                }
-            }
-            tile_d2[t] = d;
-            tile_best[2 * t] = bi;
-            tile_best[2 * t + 1] = bs;
-        }
-        __syncthreads();
+        blk_d2[blockIdx.x] = d;
+        blk_best[2 * blockIdx.x] = bi;
+        blk_best[2 * blockIdx.x + 1] = bs;
+        seg_count[blockIdx.x] = (uint32_t)(cursor - beg);
+        if (pc) atomicAdd(&ds->n_p0, pc);
     }
 }
 
-// Step 5: the farthest survivor (largest d2, then smallest index) over the
-// per-tile partials.  One block.
-__global__ __launch_bounds__(1024) void k_longest(int ntiles, const double* __restrict__ tile_d2,
-                                                  const uint32_t* __restrict__ tile_best,
+// Step 5 and the segment totals: one block.  The farthest survivor (largest
+// d2, then smallest index) over the block partials; the exclusive prefix of
+// the segment lengths (seg_off) and their total n_sorted.
+__global__ __launch_bounds__(1024) void k_longest(int nblk, const double* __restrict__ blk_d2,
+                                                  const uint32_t* __restrict__ blk_best,
+                                                  const uint32_t* __restrict__ seg_count,
+                                                  uint32_t* __restrict__ seg_off,
                                                   const double2* __restrict__ comp_xy,
+                                                  const uint32_t* __restrict__ keys,
                                                   Params* __restrict__ prm,
                                                   DevStatus* __restrict__ ds) {
     __shared__ double s_d[16];
-    __shared__ uint32_t s_i[16], s_s[16];
+    __shared__ uint32_t s_i[16], s_s[16], s_c[16];
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
     double d = -1.0;
     uint32_t bi = 0xFFFFFFFFu, bs = 0xFFFFFFFFu;
-    if (ds->n_sorted > 0u) {
-        for (int t = (int)threadIdx.x; t < ntiles; t += 1024) {
-            double od = tile_d2[t];
-            uint32_t oi = tile_best[2 * t];
-            if (od > d || (od == d && oi < bi)) {
-                d = od;
-                bi = oi;
-                bs = tile_best[2 * t + 1];
-            }
-        }
+    for (int t = (int)threadIdx.x; t < nblk; t += 1024) {
+        const double od = blk_d2[t];
+        const uint32_t oi = blk_best[2 * t];
+        const uint32_t os = blk_best[2 * t + 1];
+        const bool tk = (od > d) | ((od == d) & (oi < bi));
+        d = tk ? od : d;
+        bi = tk ? oi : bi;
+        bs = tk ? os : bs;
     }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) {
         double od = __shfl_xor(d, m);
         uint32_t oi = __shfl_xor(bi, m);
         uint32_t os = __shfl_xor(bs, m);
-        if (od > d || (od == d && oi < bi)) {
-            d = od;
-            bi = oi;
-            bs = os;
-        }
+        const bool tk = (od > d) | ((od == d) & (oi < bi));
+        d = tk ? od : d;
+        bi = tk ? oi : bi;
+        bs = tk ? os : bs;
     }
-    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
     if (lane == 0) {
         s_d[wave] = d;
         s_i[wave] = bi;
         s_s[wave] = bs;
     }
+    // exclusive scan of the segment lengths, 1024 at a time
+    uint32_t carry = 0;
+    for (int base = 0; base < nblk; base += 1024) {
+        const int t = base + (int)threadIdx.x;
+        const uint32_t v = t < nblk ? seg_count[t] : 0u;
+        uint32_t inc = wave_incl_scan(v);
+        __syncthreads();
+        if (lane == 63) s_c[wave] = inc;
+        __syncthreads();
+        uint32_t pre = carry;
+        uint32_t tot = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wave) pre += s_c[w];
+            tot += s_c[w];
+        }
+        if (t < nblk) seg_off[t] = pre + inc - v;
+        carry += tot;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < 16; ++w) {
-            if (s_d[w] > d || (s_d[w] == d && s_i[w] < bi)) {
-                d = s_d[w];
-                bi = s_i[w];
-                bs = s_s[w];
-            }
+            const bool tk = (s_d[w] > d) | ((s_d[w] == d) & (s_i[w] < bi));
+            d = tk ? s_d[w] : d;
+            bi = tk ? s_i[w] : bi;
+            bs = tk ? s_s[w] : bs;
         }
-        if (bs != 0xFFFFFFFFu && ds->n_sorted > 0u) {
+        ds->n_sorted = carry;
+        if (bs != 0xFFFFFFFFu && carry > 0u) {
             double2 q = comp_xy[bs];
             prm->lx = q.x;
             prm->ly = q.y;
             prm->l_idx = (int32_t)bi;
-            prm->l_slot = bs;
+            prm->kl = keys[bs];
+            // reference directions of the second round, seen from P_l: toward
+            // P_0 (right region) and away from it (left region, a half turn)
+            uint32_t tu = turn_key(prm->x0, prm->y0, q.x, q.y);
+            prm->turn_u = tu;
+            prm->turn_v = tu + 0x80000000u;
+            ds->l_slot = bs;
             ds->l_idx = (int32_t)bi;
         }
+    }
+}
+
+// Dense (key, slot) pairs of the survivors, for the sort of every survivor:
+// block b copies segment b to [seg_off[b], seg_off[b] + seg_count[b]).
+__global__ __launch_bounds__(256) void k_densify(int64_t chunk, const uint32_t* __restrict__ seg_count,
+                                                 const uint32_t* __restrict__ seg_off,
+                                                 const uint32_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ dkeys,
+                                                 uint32_t* __restrict__ dslots) {
+    const uint32_t cnt = seg_count[blockIdx.x];
+    const uint32_t o = seg_off[blockIdx.x];
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+        dkeys[o + i] = keys[beg + i];
+        dslots[o + i] = (uint32_t)(beg + i);
     }
 }
 
@@ -558,10 +615,14 @@ __device__ inline Pt pt_load(uint32_t slot, const double2* __restrict__ comp, do
 
 // Later of a and b in the region's order (kSlotNone is the identity).
 __device__ inline Pt pmax(const Pt& a, const Pt& b, double lx, double ly, int sgn) {
-    if (a.s == kSlotNone) return b;
-    if (b.s == kSlotNone) return a;
-    int o = orient(lx, ly, a.x, a.y, b.x, b.y);
-    return sgn * o >= 0 ? b : a;
+    const bool an = a.s == kSlotNone, bn = b.s == kSlotNone;
+    const int o = orient(lx, ly, a.x, a.y, b.x, b.y);
+    const bool take_b = an | ((!bn) & (sgn * o >= 0));
+    Pt r;
+    r.x = take_b ? b.x : a.x;
+    r.y = take_b ? b.y : a.y;
+    r.s = take_b ? b.s : a.s;
+    return r;
 }
 
 __device__ inline Pt shfl_pt(const Pt& p, int src) {
@@ -636,9 +697,8 @@ __device__ Pt lookback_max(uint64_t* stat, uint32_t t, const Pt& agg, uint32_t i
 __global__ __launch_bounds__(kR2Block) void k_round2_scan(
     const uint32_t* __restrict__ slots, const double2* __restrict__ comp,
     const Params* __restrict__ prm, const DevStatus* __restrict__ ds, uint8_t* __restrict__ keep,
-    uint64_t* __restrict__ stat, Counters* __restrict__ ctr, uint32_t epoch) {
+    uint64_t* __restrict__ stat, uint32_t epoch) {
     constexpr int NW = kR2Block / 64;
-    __shared__ uint32_t s_ticket;
     __shared__ Pt s_wave[NW];
     __shared__ Pt s_pre;
 
@@ -651,18 +711,9 @@ __global__ __launch_bounds__(kR2Block) void k_round2_scan(
     const uint32_t ntiles = ntR + ntL;
     const double x0 = prm->x0, y0 = prm->y0, lx = prm->lx, ly = prm->ly;
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
-    uint32_t* ticket = &ctr->ticket[kTicketRound2];
     if (blockIdx.x == 0 && threadIdx.x == 0 && ms > 0) keep[lp] = 1;
 
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = take_ticket(ticket);
-        __syncthreads();
-        const uint32_t t = s_ticket;
-        __syncthreads();
-        if (t >= ntiles) {
-            if (threadIdx.x == 0 && t == ntiles + gridDim.x - 1) reset_ticket(ticket);
-            break;
-        }
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const bool right = t < ntR;
         const uint32_t rt = right ? t : t - ntR;
         const int sgn = right ? 1 : -1;
@@ -798,25 +849,15 @@ __global__ __launch_bounds__(kCpBlock) void k_compact(
     const uint8_t* __restrict__ keep, const uint32_t* __restrict__ slots,
     const double2* __restrict__ comp, const uint32_t* __restrict__ comp_idx,
     double2* __restrict__ out_xy, int32_t* __restrict__ out_idx, DevStatus* __restrict__ ds,
-    uint64_t* __restrict__ stat, Counters* __restrict__ ctr, uint32_t epoch) {
+    uint64_t* __restrict__ stat, uint32_t epoch) {
     constexpr int NW = kCpBlock / 64;
     static_assert(kCpIpt == 16, "one 16-byte vector of flags per thread");
-    __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_wave[NW];
     __shared__ uint32_t s_excl;
     const uint32_t ms = ds->n_sorted;
     const uint32_t ntiles = (ms + kCpTile - 1) / kCpTile;
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
-    uint32_t* ticket = &ctr->ticket[kTicketCompact];
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = take_ticket(ticket);
-        __syncthreads();
-        const uint32_t t = s_ticket;
-        __syncthreads();
-        if (t >= ntiles) {
-            if (threadIdx.x == 0 && t == ntiles + gridDim.x - 1) reset_ticket(ticket);
-            break;
-        }
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t p0 = t * kCpTile + threadIdx.x * kCpIpt;
         uint4 v = *reinterpret_cast<const uint4*>(keep + p0);
         uint32_t wds[4] = {v.x, v.y, v.z, v.w};
@@ -883,30 +924,45 @@ hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid,
     return hipGetLastError();
 }
 
-hipError_t launch_filter1(const double* xy, int64_t n, const Params* prm, double2* comp_xy,
-                          uint32_t* comp_idx, uint32_t* keys, uint64_t* stat, double* tile_d2,
-                          uint32_t* tile_best, DevStatus* ds, Counters* ctr, uint32_t epoch,
-                          int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_filter1, dim3(grid), dim3(kF1Block), 0, s,
-                       reinterpret_cast<const double2*>(xy), n, prm, comp_xy, comp_idx, keys, stat,
-                       tile_d2, tile_best, ds, ctr, epoch);
+int filter1_blocks(int64_t n, int cu_count) {
+    int64_t g = std::min<int64_t>((int64_t)cu_count * kF1BlocksPerCu, ceil_div(n, kF1Tile));
+    return (int)std::max<int64_t>(g, 1);
+}
+
+int64_t filter1_chunk(int64_t n, int blocks) {
+    // whole tiles per block keep the loads aligned
+    return ceil_div(ceil_div(n, blocks), kF1Tile) * kF1Tile;
+}
+
+hipError_t launch_filter1(const double* xy, int64_t n, int blocks, const Params* prm,
+                          double2* comp_xy, uint32_t* comp_idx, uint32_t* keys, uint32_t* seg_count,
+                          double* blk_d2, uint32_t* blk_best, DevStatus* ds, hipStream_t s) {
+    hipLaunchKernelGGL(k_filter1, dim3(blocks), dim3(kF1Block), 0, s,
+                       reinterpret_cast<const double2*>(xy), n, filter1_chunk(n, blocks), prm,
+                       comp_xy, comp_idx, keys, seg_count, blk_d2, blk_best, ds);
     return hipGetLastError();
 }
 
-hipError_t launch_longest(int64_t n, const double* tile_d2, const uint32_t* tile_best,
-                          const double2* comp_xy, Params* prm, DevStatus* ds, hipStream_t s) {
-    int ntiles = (int)ceil_div(n, kF1Tile);
-    hipLaunchKernelGGL(k_longest, dim3(1), dim3(1024), 0, s, ntiles, tile_d2, tile_best, comp_xy,
-                       prm, ds);
+hipError_t launch_longest(int blocks, const double* blk_d2, const uint32_t* blk_best,
+                          const uint32_t* seg_count, uint32_t* seg_off, const double2* comp_xy,
+                          const uint32_t* keys, Params* prm, DevStatus* ds, hipStream_t s) {
+    hipLaunchKernelGGL(k_longest, dim3(1), dim3(1024), 0, s, blocks, blk_d2, blk_best, seg_count,
+                       seg_off, comp_xy, keys, prm, ds);
     return hipGetLastError();
 }
 
-hipError_t launch_round2_scan(const uint32_t* slots, const double2* comp_xy, const Params* prm,
-                              const DevStatus* ds, uint8_t* keep, uint64_t* stat,
-                              Counters* ctr, uint32_t epoch, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_round2_scan, dim3(grid), dim3(kR2Block), 0, s, slots, comp_xy, prm, ds,
-                       keep, stat, ctr, epoch);
+hipError_t launch_densify(int64_t n, int blocks, const uint32_t* seg_count, const uint32_t* seg_off,
+                          const uint32_t* keys, uint32_t* dkeys, uint32_t* dslots, hipStream_t s) {
+    hipLaunchKernelGGL(k_densify, dim3(blocks), dim3(256), 0, s, filter1_chunk(n, blocks), seg_count,
+                       seg_off, keys, dkeys, dslots);
     return hipGetLastError();
+}
+
+hipError_t launch_round2_scan(int64_t n, const uint32_t* slots, const double2* comp_xy,
+                              const Params* prm, const DevStatus* ds, uint8_t* keep, uint64_t* stat,
+                              uint32_t epoch, int cu_count, hipStream_t s) {
+    const int grid = coop_grid(k_round2_scan, kR2Block, cu_count, ceil_div(n, kR2Tile) + 2);
+    return launch_coop(k_round2_scan, grid, kR2Block, s, slots, comp_xy, prm, ds, keep, stat, epoch);
 }
 
 hipError_t launch_round2_chunks(int64_t n, int64_t chunk, const uint32_t* slots,
@@ -922,13 +978,13 @@ hipError_t launch_round2_chunks(int64_t n, int64_t chunk, const uint32_t* slots,
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const uint8_t* keep, const uint32_t* slots, const double2* comp_xy,
-                          const uint32_t* comp_idx, double2* out_xy, int32_t* out_idx,
-                          DevStatus* ds, uint64_t* stat, Counters* ctr, uint32_t epoch, int grid,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_compact, dim3(grid), dim3(kCpBlock), 0, s, keep, slots, comp_xy,
-                       comp_idx, out_xy, out_idx, ds, stat, ctr, epoch);
-    return hipGetLastError();
+hipError_t launch_compact(int64_t n, const uint8_t* keep, const uint32_t* slots,
+                          const double2* comp_xy, const uint32_t* comp_idx, double2* out_xy,
+                          int32_t* out_idx, DevStatus* ds, uint64_t* stat, uint32_t epoch,
+                          int cu_count, hipStream_t s) {
+    const int grid = coop_grid(k_compact, kCpBlock, cu_count, ceil_div(n, kCpTile));
+    return launch_coop(k_compact, grid, kCpBlock, s, keep, slots, comp_xy, comp_idx, out_xy,
+                       out_idx, ds, stat, epoch);
 }
 
 hipError_t launch_debug_orient(const double* abc, int64_t count, int32_t* out, hipStream_t s) {

@@ -66,11 +66,10 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
     int pass, const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ hist, const DevStatus* __restrict__ ds,
-    uint64_t* __restrict__ stat, Counters* __restrict__ ctr, uint32_t epoch) {
+    uint64_t* __restrict__ stat, uint32_t epoch) {
     constexpr int NW = kSortBlock / 64;
     constexpr int IPT = kSortIpt;
     static_assert(kSortBlock == kRadix, "one thread per digit");
-    __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_wc[NW][kRadix];     // per-wave digit counters, then wave prefixes
     __shared__ uint32_t s_tl[kRadix];         // tile-local digit offsets
     __shared__ int64_t s_adj[kRadix];         // global destination minus tile-local position
@@ -84,7 +83,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
     const uint32_t ms = ds->n_sorted;
     const uint32_t ntiles = (ms + kSortTile - 1) / kSortTile;
     const int shift = 8 * pass;
-    uint32_t* ticket = &ctr->ticket[kTicketSort0 + pass];
+    if (blockIdx.x >= ntiles) return;
 
     // exclusive scan of this pass's global histogram: digit bases
     {
@@ -98,16 +97,9 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
         __syncthreads();
     }
 
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = take_ticket(ticket);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         for (int w = 0; w < NW; ++w) s_wc[w][d] = 0;
         __syncthreads();
-        const uint32_t t = s_ticket;
-        __syncthreads();
-        if (t >= ntiles) {
-            if (threadIdx.x == 0 && t == ntiles + gridDim.x - 1) reset_ticket(ticket);
-            break;
-        }
         const uint32_t base = t * kSortTile;
         uint32_t key[IPT], val[IPT], rank[IPT];
 #pragma unroll
@@ -237,7 +229,7 @@ __global__ __launch_bounds__(256) void k_ties(const uint32_t* __restrict__ keys,
                                               DevStatus* __restrict__ ds,
                                               uint32_t* __restrict__ long_list) {
     const uint32_t ms = ds->n_sorted;
-    const uint32_t lslot = prm->l_slot;
+    const uint32_t lslot = ds->l_slot;
     const double x0 = prm->x0, y0 = prm->y0;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ms; i += stride) {
@@ -274,9 +266,48 @@ __global__ __launch_bounds__(256) void k_ties(const uint32_t* __restrict__ keys,
     }
 }
 
-// Longer equal-key runs: one workgroup per run, bitonic sort of an index
-// permutation in LDS with the exact comparator.  Runs beyond kRunCap are
-// counted and listed for the host's merge fallback.
+// Bitonic sort of one run of at most kRunCap slots in LDS by the exact
+// comparator (an index permutation is sorted; padding sorts last).  All
+// threads of the block take part.
+__device__ void sort_run_lds(uint32_t* __restrict__ run, uint32_t L, const double2* __restrict__ comp,
+                             const uint32_t* __restrict__ comp_idx, double x0, double y0,
+                             uint32_t lslot, uint32_t pos0, DevStatus* __restrict__ ds,
+                             Rec* s_r, uint16_t* s_p) {
+    uint32_t P = 1;
+    while (P < L) P <<= 1;
+    for (uint32_t a = threadIdx.x; a < L; a += blockDim.x) s_r[a] = rec_load(run[a], comp, comp_idx);
+    for (uint32_t a = threadIdx.x; a < P; a += blockDim.x) s_p[a] = (uint16_t)a;
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t a = threadIdx.x; a < P; a += blockDim.x) {
+                uint32_t b = a ^ j;
+                if (b > a) {
+                    uint32_t ia = s_p[a], ib = s_p[b];
+                    bool b_first;
+                    if (ia >= L) b_first = ib < L;
+                    else if (ib >= L) b_first = false;
+                    else b_first = rec_less(s_r[ib], s_r[ia], x0, y0);
+                    bool asc = (a & kk) == 0;
+                    if (asc ? b_first : !b_first && ia != ib) {
+                        s_p[a] = (uint16_t)ib;
+                        s_p[b] = (uint16_t)ia;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t a = threadIdx.x; a < L; a += blockDim.x) {
+        uint32_t sl = s_r[s_p[a]].slot;
+        run[a] = sl;
+        if (sl == lslot) ds->l_pos = pos0 + a;
+    }
+    __syncthreads();
+}
+
+// Longer equal-key runs: one workgroup per run.  Runs beyond kRunCap are
+// listed for the merge fallback.
 __global__ __launch_bounds__(256) void k_ties_long(const uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ slots,
                                                    const double2* __restrict__ comp,
@@ -290,7 +321,7 @@ __global__ __launch_bounds__(256) void k_ties_long(const uint32_t* __restrict__ 
     __shared__ uint32_t s_len;
     const uint32_t nl = ds->long_runs;
     const uint32_t ms = ds->n_sorted;
-    const uint32_t lslot = prm->l_slot;
+    const uint32_t lslot = ds->l_slot;
     const double x0 = prm->x0, y0 = prm->y0;
     for (uint32_t r = blockIdx.x; r < nl; r += gridDim.x) {
         const uint32_t s = long_list[r];
@@ -316,39 +347,61 @@ __global__ __launch_bounds__(256) void k_ties_long(const uint32_t* __restrict__ 
             __syncthreads();
             continue;
         }
-        uint32_t P = 1;
-        while (P < L) P <<= 1;
-        for (uint32_t a = threadIdx.x; a < L; a += blockDim.x) s_r[a] = rec_load(slots[s + a], comp, comp_idx);
-        for (uint32_t a = threadIdx.x; a < P; a += blockDim.x) s_p[a] = (uint16_t)a;
-        __syncthreads();
-        for (uint32_t kk = 2; kk <= P; kk <<= 1) {
-            for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-                for (uint32_t a = threadIdx.x; a < P; a += blockDim.x) {
-                    uint32_t b = a ^ j;
-                    if (b > a) {
-                        uint32_t ia = s_p[a], ib = s_p[b];
-                        // padding (index >= L) sorts last
-                        bool b_first;
-                        if (ia >= L) b_first = ib < L;
-                        else if (ib >= L) b_first = false;
-                        else b_first = rec_less(s_r[ib], s_r[ia], x0, y0);
-                        bool asc = (a & kk) == 0;
-                        if (asc ? b_first : !b_first && ia != ib) {
-                            s_p[a] = (uint16_t)ib;
-                            s_p[b] = (uint16_t)ia;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (uint32_t a = threadIdx.x; a < L; a += blockDim.x) {
-            uint32_t sl = s_r[s_p[a]].slot;
-            slots[s + a] = sl;
-            if (sl == lslot) ds->l_pos = s + a;
-        }
-        __syncthreads();
+        sort_run_lds(slots + s, L, comp, comp_idx, x0, y0, lslot, s, ds, s_r, s_p);
     }
+}
+
+// Merge fallback for a run longer than kRunCap (many points on one ray from
+// the pivot, or many copies of one point): every kRunCap-chunk is sorted in
+// LDS, then sorted blocks of width w are merged pairwise, one output element
+// per thread, by a binary search of its merge-path diagonal.
+__global__ __launch_bounds__(256) void k_chunk_sort(uint32_t* __restrict__ run, uint32_t L,
+                                                    const double2* __restrict__ comp,
+                                                    const uint32_t* __restrict__ comp_idx,
+                                                    const Params* __restrict__ prm,
+                                                    DevStatus* __restrict__ ds) {
+    __shared__ Rec s_r[kRunCap];
+    __shared__ uint16_t s_p[kRunCap];
+    const uint32_t c0 = blockIdx.x * (uint32_t)kRunCap;
+    const uint32_t len = min((uint32_t)kRunCap, L - c0);
+    sort_run_lds(run + c0, len, comp, comp_idx, prm->x0, prm->y0, 0xFFFFFFFFu, 0u, ds, s_r, s_p);
+}
+
+__global__ __launch_bounds__(256) void k_merge_pass(const uint32_t* __restrict__ in,
+                                                    uint32_t* __restrict__ out, uint32_t L,
+                                                    uint32_t w, const double2* __restrict__ comp,
+                                                    const uint32_t* __restrict__ comp_idx,
+                                                    const Params* __restrict__ prm,
+                                                    DevStatus* __restrict__ ds, uint32_t pos0) {
+    const uint32_t p = blockIdx.x * 256u + threadIdx.x;
+    if (p >= L) return;
+    const double x0 = prm->x0, y0 = prm->y0;
+    const uint32_t pair = p / (2 * w);
+    const uint32_t a0 = pair * 2 * w;
+    const uint32_t na = min(w, L - a0);
+    const uint32_t b0 = a0 + na;
+    const uint32_t nb = min(w, L - b0 < L ? L - b0 : 0u);
+    const uint32_t d = p - a0;
+    // smallest i in [max(0, d-nb), min(d, na)] with A[i] after B[d-i-1]
+    uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
+    while (lo < hi) {
+        uint32_t i = lo + (hi - lo) / 2;
+        Rec ra = rec_load(in[a0 + i], comp, comp_idx);
+        Rec rb = rec_load(in[b0 + d - i - 1], comp, comp_idx);
+        if (rec_less(rb, ra, x0, y0)) hi = i;
+        else lo = i + 1;
+    }
+    const uint32_t i = lo, j = d - lo;
+    uint32_t v;
+    if (i >= na) v = in[b0 + j];
+    else if (j >= nb) v = in[a0 + i];
+    else {
+        Rec ra = rec_load(in[a0 + i], comp, comp_idx);
+        Rec rb = rec_load(in[b0 + j], comp, comp_idx);
+        v = rec_less(rb, ra, x0, y0) ? rb.slot : ra.slot;
+    }
+    out[p] = v;
+    if (v == ds->l_slot) ds->l_pos = pos0 + p;
 }
 
 }  // namespace
@@ -361,13 +414,13 @@ hipError_t launch_histogram(const uint32_t* keys, const DevStatus* ds, uint32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_sort_pass(int pass, const uint32_t* keys_in, const uint32_t* vals_in,
+hipError_t launch_sort_pass(int64_t n, int pass, const uint32_t* keys_in, const uint32_t* vals_in,
                             uint32_t* keys_out, uint32_t* vals_out, const uint32_t* hist,
-                            const DevStatus* ds, uint64_t* stat, Counters* ctr, uint32_t epoch,
-                            int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_sort_pass, dim3(grid), dim3(kSortBlock), 0, s, pass, keys_in, vals_in,
-                       keys_out, vals_out, hist, ds, stat, ctr, epoch);
-    return hipGetLastError();
+                            const DevStatus* ds, uint64_t* stat, uint32_t epoch, int cu_count,
+                            hipStream_t s) {
+    const int grid = coop_grid(k_sort_pass, kSortBlock, cu_count, ceil_div(n, kSortTile));
+    return launch_coop(k_sort_pass, grid, kSortBlock, s, pass, keys_in, vals_in, keys_out, vals_out,
+                       hist, ds, stat, epoch);
 }
 
 hipError_t launch_ties(int64_t n, const uint32_t* keys, uint32_t* slots, const double2* comp_xy,
@@ -379,6 +432,30 @@ hipError_t launch_ties(int64_t n, const uint32_t* keys, uint32_t* slots, const d
     hipLaunchKernelGGL(k_ties, dim3((unsigned)grid), dim3(256), 0, s, keys, slots, comp_xy,
                        comp_idx, prm, ds, long_list);
     return hipGetLastError();
+}
+
+hipError_t launch_huge_run(uint32_t* slots, uint32_t* tmp, uint32_t start, uint32_t L,
+                           const double2* comp_xy, const uint32_t* comp_idx, const Params* prm,
+                           DevStatus* ds, hipStream_t s) {
+    uint32_t* run = slots + start;
+    uint32_t* other = tmp + start;
+    const uint32_t chunks = (L + kRunCap - 1) / kRunCap;
+    hipLaunchKernelGGL(k_chunk_sort, dim3(chunks), dim3(256), 0, s, run, L, comp_xy, comp_idx, prm, ds);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint32_t* a = run;
+    uint32_t* b = other;
+    for (uint32_t w = kRunCap; w < L; w *= 2) {
+        hipLaunchKernelGGL(k_merge_pass, dim3((L + 255) / 256), dim3(256), 0, s, a, b, L, w, comp_xy,
+                           comp_idx, prm, ds, start);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint32_t* t = a;
+        a = b;
+        b = t;
+    }
+    if (a != run) return hipMemcpyAsync(run, a, (size_t)L * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    return hipSuccess;
 }
 
 hipError_t launch_ties_long(const uint32_t* keys, uint32_t* slots, const double2* comp_xy,

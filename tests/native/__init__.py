@@ -31,6 +31,8 @@ def host_exact():
             getattr(lib, name).restype = ctypes.c_int
         lib.hx_angle_key.argtypes = [d] * 4
         lib.hx_angle_key.restype = ctypes.c_uint
+        lib.hx_turn_key.argtypes = [d] * 4
+        lib.hx_turn_key.restype = ctypes.c_uint
         lib.hx_key_at_least.argtypes = [d] * 5
         lib.hx_key_at_least.restype = ctypes.c_int
         _lib = lib

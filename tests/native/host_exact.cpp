@@ -16,3 +16,7 @@ int hx_key_at_least(double x, double y, double x0, double y0, double k) {
     return hx::key_at_least(x, y, x0, y0, x - x0 >= 0.0, k) ? 1 : 0;
 }
 }
+
+extern "C" unsigned hx_turn_key(double px, double py, double cx, double cy) {
+    return hx::turn_key(px, py, cx, cy);
+}

@@ -115,3 +115,52 @@ def test_key_monotone_vs_orientation(L):
             assert o > 0
         elif ka > kb:
             assert o < 0
+
+
+def turn_q(px, py, cx, cy) -> int:
+    """Full-turn pseudo-angle key of p - c in exact rational arithmetic."""
+    dx = Fraction(px) - Fraction(cx)
+    dy = Fraction(py) - Fraction(cy)
+    assert dx != 0 or dy != 0
+    if dx > 0 and dy >= 0:
+        q, a, b = 0, dx, dy
+    elif dx <= 0 and dy > 0:
+        q, a, b = 1, dy, -dx
+    elif dx < 0 and dy <= 0:
+        q, a, b = 2, -dx, -dy
+    else:
+        q, a, b = 3, -dy, dx
+    return q * 2 ** 30 + math.floor(b / (a + b) * 2 ** 30)
+
+
+def test_turn_key_random_and_axes(L):
+    rng = random.Random(22)
+    for _ in range(4000):
+        cx, cy = rng.uniform(-1, 1), rng.uniform(-1, 1)
+        px, py = rng.uniform(-2, 2), rng.uniform(-2, 2)
+        assert L.hx_turn_key(px, py, cx, cy) == turn_q(px, py, cx, cy)
+    for px, py in [(1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]:
+        assert L.hx_turn_key(float(px), float(py), 0.0, 0.0) == turn_q(px, py, 0, 0)
+
+
+def test_turn_key_exact_boundaries_and_half_turn(L):
+    rng = random.Random(23)
+    checked = 0
+    for _ in range(1500):
+        k = rng.randrange(1, 2 ** 30)
+        a, b = float(2 ** 30 - k), float(k)     # b/(a+b) = k/2^30 exactly
+        q = rng.randrange(4)
+        dx, dy = [(a, b), (-b, a), (-a, -b), (b, -a)][q]
+        sc = math.ldexp(1.0, rng.randint(-30, 30))
+        cx, cy = rng.choice([(0.0, 0.0), (0.5, -0.25), (3.0, 7.0)])
+        px, py = cx + dx * sc, cy + dy * sc
+        for qx, qy in [(px, py), (_walk(px, 1), py), (px, _walk(py, -1)), (_walk(px, -2), _walk(py, 1))]:
+            if qx == cx and qy == cy:
+                continue
+            assert L.hx_turn_key(qx, qy, cx, cy) == turn_q(qx, qy, cx, cy)
+            checked += 1
+        # a half turn adds exactly 2^31 (mod 2^32)
+        k1 = L.hx_turn_key(cx + dx, cy + dy, cx, cy)
+        k2 = L.hx_turn_key(cx - dx, cy - dy, cx, cy)
+        assert (k2 - k1) % 2 ** 32 == 2 ** 31
+    assert checked > 5000

@@ -130,6 +130,10 @@ def _cases():
         "ngon_4096": synth.ngon(4096, 12, (60, 1)),
         "collinear_1500": np.stack([t, 2 * t - 5], axis=1)[np.random.default_rng(1).permutation(1500)],
         "collinear_dups": np.repeat(np.stack([t[:40], -t[:40]], axis=1), 3, axis=0),
+        "collinear_10k": np.stack([np.arange(10_000.0), 0.5 * np.arange(10_000.0) + 3.0],
+                                  axis=1)[np.random.default_rng(2).permutation(10_000)],
+        "dup_heavy": np.concatenate([np.full((5000, 2), 0.25), synth.square(3000, (65, 1)),
+                                     np.full((3000, 2), 1.0)])[np.random.default_rng(3).permutation(11_000)],
         "all_equal_1000": np.full((1000, 2), 0.375),
         "one": np.array([[0.25, -0.5]]),
         "two_same": np.array([[1.0, 1.0], [1.0, 1.0]]),
@@ -156,18 +160,26 @@ def test_hull_equals_oracle(torch_dev, ctx, name):
     assert st.n_hull == len(want)
 
 
-@pytest.mark.parametrize("chunk", [0, -1, 5])
+@pytest.mark.parametrize("mode", ["bucketed", "full", "paper", "chunk5"])
 @pytest.mark.parametrize("name", ["square_100k", "disk_100k", "grid_draws_100k", "annulus_ngon_100k",
-                                  "collinear_1500", "grid_200x3", "mixture_100k"])
-def test_stages_equal_model(torch_dev, hx, name, chunk):
+                                  "collinear_1500", "grid_200x3", "mixture_100k", "collinear_10k",
+                                  "dup_heavy"])
+def test_stages_equal_model(torch_dev, hx, name, mode):
+    chunk, full = {"bucketed": (0, False), "full": (0, True), "paper": (-1, True),
+                   "chunk5": (5, True)}[mode]
     pts = CASES[name]
-    say(f"stages {name} chunk={chunk}")
-    c = hx.Hull2D(round2_chunk=chunk)
+    say(f"stages {name} mode={mode}")
+    c = hx.Hull2D(round2_chunk=chunk, full_sort=full)
     got = c.compute(to_dev(torch_dev, pts))
     m = oracle.model(pts, chunk)
     s = c.stages(len(pts) + 1)
     assert s["extremes"] == m["extremes"]
-    assert s["sorted"].tolist() == m["sorted"].tolist()
+    assert s["n_sorted"] == len(m["sorted"])
+    if mode != "bucketed":
+        assert s["sorted"].tolist() == m["sorted"].tolist()
+    else:
+        assert s["sorted"] is None
+        assert s["n_candidates"] <= max(len(m["sorted"]), 1)
     if len(m["sorted"]):
         assert s["l"] == m["l"]
         assert s["longest"] == m["longest"]
@@ -177,6 +189,20 @@ def test_stages_equal_model(torch_dev, hx, name, chunk):
     assert st.n_round1 == m["m1"]
     assert st.n_round2 == m["m2"]
     c.close()
+
+
+@pytest.mark.parametrize("side,n", [(2, 1000), (3, 100_000), (8, 100_003), (64, 100_000),
+                                    (64, 1_000_003), (1000, 2_000_000)])
+def test_extremes_tie_heavy(torch_dev, ctx, side, n):
+    """Step 1 tie rules on inputs where every criterion has many ties."""
+    pts = synth.grid_draws(n, side, (70 + side, n % 97))
+    say(f"extremes grid draws side={side} n={n}")
+    ctx.compute(to_dev(torch_dev, pts))
+    x, y = pts[:, 0], pts[:, 1]
+    idx = np.arange(n)
+    want = [int(np.lexsort((idx, -y, x))[0]), int(np.lexsort((idx, x, y))[0]),
+            int(np.lexsort((idx, y, -x))[0]), int(np.lexsort((idx, -x, -y))[0])]
+    assert ctx.stages(n + 1)["extremes"] == want
 
 
 def test_repeatable(torch_dev, ctx):
