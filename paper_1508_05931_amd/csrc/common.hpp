@@ -55,6 +55,18 @@ struct DevStatus {
     double x0, y0;
 };
 
+// Ticket counters of the look-back kernels; they persist across calls, and
+// each kernel resets its own counter when its last ticket has been taken.
+struct Counters {
+    uint32_t ticket[16 * 16];  // one 64-byte line per counter
+};
+
+enum TicketId {
+    kTicketSort0 = 0,  // ..3
+    kTicketRound2 = 4,
+    kTicketCompact = 5,
+};
+
 constexpr int kBucketBits = 12;                 // coarse angle buckets of the bucketed round 2
 constexpr int kBuckets = 1 << kBucketBits;
 
@@ -72,6 +84,32 @@ __device__ inline uint32_t stat_flag(uint64_t w, uint32_t epoch) {
     return (hi >> 2) == (epoch & 0x3FFFFFFFu) ? (hi & 3u) : 0u;
 }
 __device__ inline uint32_t stat_value(uint64_t w) { return (uint32_t)w; }
+
+__device__ inline uint32_t take_ticket(uint32_t* c) {
+    return __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void reset_ticket(uint32_t* c) {
+    __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile order for the look-back kernels.  Blocks at or beyond the tile count
+// leave at once without touching the counter; the others take tiles in
+// ticket order (a tile's predecessors are then held by running blocks), and
+// each takes one ticket past the end before it leaves; the block that draws
+// the last of those resets the counter for the next launch.  Returns the
+// next tile, or `tiles` when the block is done.  All threads call it.
+__device__ inline uint32_t next_tile(uint32_t* counter, uint32_t tiles, uint32_t* s_ticket) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = take_ticket(counter);
+        const uint32_t players = min(gridDim.x, tiles);
+        if (t == tiles + players - 1) reset_ticket(counter);
+        *s_ticket = t;
+    }
+    __syncthreads();
+    const uint32_t t = *s_ticket;
+    return t < tiles ? t : tiles;
+}
 
 __device__ inline void stat_store(uint64_t* p, uint64_t w) {
     __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -49,6 +49,7 @@ struct hull2d_ctx {
     double* blk_d2 = nullptr;
     uint32_t* blk_best = nullptr;
     int parts = 0;
+    Counters* ctr = nullptr;  // separate allocation, zeroed once, persists
 
     // pinned host buffers (h_ds holds the two problem statuses)
     DevStatus* h_ds = nullptr;
@@ -59,6 +60,10 @@ struct hull2d_ctx {
     uint32_t epoch = 0;
     hipEvent_t ev[HULL2D_NUM_STAGES + 2] = {};  // per stage, then begin and end
     bool have_events = false;
+
+    hipEvent_t ev_sync = nullptr;  // spin-waited: a sleeping wait can add milliseconds
+    std::vector<int64_t> stk;      // host scan buffers, reused across calls
+    std::vector<int32_t> hull;
 
     // the last compute call, for hull2d_debug_stages
     bool have_last = false;
@@ -240,6 +245,18 @@ int64_t graham_scan(double x0, double y0, int32_t i0, const double2* pts, const 
     return (int64_t)h;
 }
 
+// Waits for the stream by polling an event: a blocking wait may put the
+// thread to sleep and wake it up long after the work has finished.
+hipError_t spin_sync(hull2d_ctx* c) {
+    if (!c->ev_sync) return hipStreamSynchronize(c->stream);
+    hipError_t e = hipEventRecord(c->ev_sync, c->stream);
+    if (e != hipSuccess) return e;
+    for (;;) {
+        e = hipEventQuery(c->ev_sync);
+        if (e != hipErrorNotReady) return e;
+    }
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -291,7 +308,9 @@ hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->cu_count = prop.multiProcessorCount;
-    if (hipHostMalloc((void**)&c->h_ds, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+    if (hipMalloc((void**)&c->ctr, sizeof(Counters)) != hipSuccess ||
+        hipMemset(c->ctr, 0, sizeof(Counters)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_ds, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         hull2d_destroy(c);
         return HULL2D_ERR_OUT_OF_MEMORY;
@@ -300,6 +319,10 @@ hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
     for (int i = 0; i < HULL2D_NUM_STAGES + 2; ++i)
         ev_ok = ev_ok && hipEventCreate(&c->ev[i]) == hipSuccess;
     c->have_events = ev_ok;
+    if (hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        c->ev_sync = nullptr;
+    }
     *out = c;
     return HULL2D_OK;
 }
@@ -309,11 +332,13 @@ void hull2d_destroy(hull2d_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream || c->dmem) (void)hipStreamSynchronize(c->stream);
     if (c->dmem) (void)hipFree(c->dmem);
+    if (c->ctr) (void)hipFree(c->ctr);
     if (c->h_ds) (void)hipHostFree(c->h_ds);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
     for (int i = 0; i < HULL2D_NUM_STAGES + 2; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->ev_sync) (void)hipEventDestroy(c->ev_sync);
     delete c;
 }
 
@@ -391,7 +416,7 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     uint32_t* vout = c->vals_b;
     for (int pass = 0; pass < 4; ++pass) {
         const uint32_t e = ++c->epoch;
-        HX_TRY(launch_sort_pass(n, pass, kin, vin, kout, vout, c->hist, pds, c->stat, e,
+        HX_TRY(launch_sort_pass(n, pass, kin, vin, kout, vout, c->hist, pds, c->stat, c->ctr, e,
                                 c->cu_count, s));
         mark(HULL2D_STAGE_SORT0 + pass);
         kin = kout;
@@ -410,17 +435,18 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     auto round2 = [&]() -> hull2d_status {
         if (c->opt.round2_chunk == 0) {
             const uint32_t e = ++c->epoch;
-            HX_TRY(launch_round2_scan(n, slots, pxy, c->prm, pds, c->keep, c->stat, e, c->cu_count, s));
+            HX_TRY(launch_round2_scan(n, slots, pxy, c->prm, pds, c->keep, c->stat, c->ctr, e,
+                                      c->cu_count, s));
         } else {
             HX_TRY(launch_round2_chunks(n, c->opt.round2_chunk, slots, pxy, c->prm, pds, c->keep, s));
         }
         mark(HULL2D_STAGE_ROUND2);
         const uint32_t e = ++c->epoch;
-        HX_TRY(launch_compact(n, c->keep, slots, pxy, pidx, c->out_xy, c->out_idx, pds, c->stat, e,
-                              c->cu_count, s));
+        HX_TRY(launch_compact(n, c->keep, slots, pxy, pidx, c->out_xy, c->out_idx, pds, c->stat,
+                              c->ctr, e, c->cu_count, s));
         mark(HULL2D_STAGE_COMPACT);
         HX_TRY(hipMemcpyAsync(c->h_ds, c->ds, 2 * sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-        HX_TRY(hipStreamSynchronize(s));
+        HX_TRY(spin_sync(c));
         return HULL2D_OK;
     };
     st = round2();
@@ -435,7 +461,7 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
         std::vector<uint32_t> hl(2 * (size_t)DP.huge_runs);
         HX_TRY(hipMemcpyAsync(hl.data(), c->huge_list, hl.size() * sizeof(uint32_t),
                               hipMemcpyDeviceToHost, s));
-        HX_TRY(hipStreamSynchronize(s));
+        HX_TRY(spin_sync(c));
         for (uint32_t r = 0; r < DP.huge_runs; ++r)
             HX_TRY(launch_huge_run(slots, c->vals_b, hl[2 * r], hl[2 * r + 1], pxy, pidx, c->prm, pds, s));
         st = round2();
@@ -454,12 +480,12 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     }
     mark(HULL2D_STAGE_D2H);
     if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
-    HX_TRY(hipStreamSynchronize(s));
+    HX_TRY(spin_sync(c));
     const double ms_d2h_wall = ms_since(t_d2h);
 
     auto t_scan = std::chrono::steady_clock::now();
-    std::vector<int64_t> stk;
-    std::vector<int32_t> hull;
+    std::vector<int64_t>& stk = c->stk;
+    std::vector<int32_t>& hull = c->hull;
     stk.reserve((size_t)m + 1);
     const int64_t h = graham_scan(D.x0, D.y0, D.p0_idx, c->h_xy, c->h_idx, m, stk, hull);
     const double ms_scan = ms_since(t_scan);

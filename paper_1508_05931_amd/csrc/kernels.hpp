@@ -5,7 +5,6 @@
 #include <stdint.h>
 
 #include <algorithm>
-#include <tuple>
 
 #include "common.hpp"
 
@@ -31,35 +30,6 @@ constexpr int kRunCap = 2048;                    // longest run one workgroup so
 constexpr int kHistGridMax = 512;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-// Kernels that chain tile prefixes by look-back take tiles in a fixed order
-// (tile t is processed by block t mod grid, blocks walk their tiles upwards).
-// They are launched cooperatively with at most as many blocks as fit on the
-// device at once, so every tile a block waits for belongs to a running block.
-template <typename K>
-inline int coop_grid(K kernel, int block, int cu_count, int64_t tiles) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel),
-                                                     block, 0) != hipSuccess || per_cu < 1) {
-        (void)hipGetLastError();
-        per_cu = 1;
-    }
-    int64_t g = std::min<int64_t>(tiles, (int64_t)per_cu * cu_count);
-    return (int)std::max<int64_t>(g, 1);
-}
-
-template <typename... KArgs, typename... Args>
-inline hipError_t launch_coop(void (*kernel)(KArgs...), int grid, int block, hipStream_t s,
-                              Args... args) {
-    std::tuple<KArgs...> t(args...);
-    void* ptrs[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
-    std::apply([&](auto&... xs) {
-        int i = 0;
-        ((ptrs[i++] = (void*)&xs), ...);
-    }, t);
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(grid), dim3(block),
-                                      ptrs, 0, s);
-}
 
 // Step 1: partial extreme candidates per block, then the final reduction,
 // the quadrilateral and the pivot.
@@ -107,8 +77,8 @@ hipError_t launch_histogram(const uint32_t* keys, const DevStatus* ds, uint32_t*
                             hipStream_t s);
 hipError_t launch_sort_pass(int64_t n, int pass, const uint32_t* keys_in, const uint32_t* vals_in,
                             uint32_t* keys_out, uint32_t* vals_out, const uint32_t* hist,
-                            const DevStatus* ds, uint64_t* stat, uint32_t epoch, int cu_count,
-                            hipStream_t s);
+                            const DevStatus* ds, uint64_t* stat, Counters* ctr, uint32_t epoch,
+                            int cu_count, hipStream_t s);
 hipError_t launch_ties(int64_t n, const uint32_t* keys, uint32_t* slots, const double2* comp_xy,
                        const uint32_t* comp_idx, const Params* prm, DevStatus* ds,
                        uint32_t* long_list, hipStream_t s);
@@ -127,14 +97,14 @@ hipError_t launch_huge_run(uint32_t* slots, uint32_t* tmp, uint32_t start, uint3
 // the paper's per-thread subsets), then stable compaction of the kept points.
 hipError_t launch_round2_scan(int64_t n, const uint32_t* slots, const double2* comp_xy,
                               const Params* prm, const DevStatus* ds, uint8_t* keep, uint64_t* stat,
-                              uint32_t epoch, int cu_count, hipStream_t s);
+                              Counters* ctr, uint32_t epoch, int cu_count, hipStream_t s);
 hipError_t launch_round2_chunks(int64_t n, int64_t chunk, const uint32_t* slots,
                                 const double2* comp_xy, const Params* prm, const DevStatus* ds,
                                 uint8_t* keep, hipStream_t s);
 hipError_t launch_compact(int64_t n, const uint8_t* keep, const uint32_t* slots,
                           const double2* comp_xy, const uint32_t* comp_idx, double2* out_xy,
-                          int32_t* out_idx, DevStatus* ds, uint64_t* stat, uint32_t epoch,
-                          int cu_count, hipStream_t s);
+                          int32_t* out_idx, DevStatus* ds, uint64_t* stat, Counters* ctr,
+                          uint32_t epoch, int cu_count, hipStream_t s);
 
 // Checking kernels.
 hipError_t launch_debug_orient(const double* abc, int64_t count, int32_t* out, hipStream_t s);

@@ -13,10 +13,9 @@
 //                                  thread per subset (Section 3.4)
 //   k_compact                      Step 7: stable removal of interior points
 //
-// Streaming kernels chain tile prefixes by decoupled look-back (Merrill &
-// Garland, "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016);
-// tile t belongs to block t mod grid and the grid is launched cooperatively
-// (every block resident), so a predecessor tile is always being processed.
+// Scan kernels chain tile prefixes by decoupled look-back (Merrill & Garland,
+// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016), with
+// tiles taken in ticket order (see next_tile).
 #include <float.h>
 
 #include "exact.hpp"
@@ -697,8 +696,9 @@ __device__ Pt lookback_max(uint64_t* stat, uint32_t t, const Pt& agg, uint32_t i
 __global__ __launch_bounds__(kR2Block) void k_round2_scan(
     const uint32_t* __restrict__ slots, const double2* __restrict__ comp,
     const Params* __restrict__ prm, const DevStatus* __restrict__ ds, uint8_t* __restrict__ keep,
-    uint64_t* __restrict__ stat, uint32_t epoch) {
+    uint64_t* __restrict__ stat, Counters* __restrict__ ctr, uint32_t epoch) {
     constexpr int NW = kR2Block / 64;
+    __shared__ uint32_t s_ticket;
     __shared__ Pt s_wave[NW];
     __shared__ Pt s_pre;
 
@@ -712,8 +712,11 @@ __global__ __launch_bounds__(kR2Block) void k_round2_scan(
     const double x0 = prm->x0, y0 = prm->y0, lx = prm->lx, ly = prm->ly;
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
     if (blockIdx.x == 0 && threadIdx.x == 0 && ms > 0) keep[lp] = 1;
+    if (blockIdx.x >= ntiles) return;
 
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint32_t* counter = &ctr->ticket[16 * kTicketRound2];
+    for (uint32_t t = next_tile(counter, ntiles, &s_ticket); t < ntiles;
+         t = next_tile(counter, ntiles, &s_ticket)) {
         const bool right = t < ntR;
         const uint32_t rt = right ? t : t - ntR;
         const int sgn = right ? 1 : -1;
@@ -849,15 +852,19 @@ __global__ __launch_bounds__(kCpBlock) void k_compact(
     const uint8_t* __restrict__ keep, const uint32_t* __restrict__ slots,
     const double2* __restrict__ comp, const uint32_t* __restrict__ comp_idx,
     double2* __restrict__ out_xy, int32_t* __restrict__ out_idx, DevStatus* __restrict__ ds,
-    uint64_t* __restrict__ stat, uint32_t epoch) {
+    uint64_t* __restrict__ stat, Counters* __restrict__ ctr, uint32_t epoch) {
     constexpr int NW = kCpBlock / 64;
     static_assert(kCpIpt == 16, "one 16-byte vector of flags per thread");
+    __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_wave[NW];
     __shared__ uint32_t s_excl;
     const uint32_t ms = ds->n_sorted;
     const uint32_t ntiles = (ms + kCpTile - 1) / kCpTile;
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    if (blockIdx.x >= ntiles) return;
+    uint32_t* counter = &ctr->ticket[16 * kTicketCompact];
+    for (uint32_t t = next_tile(counter, ntiles, &s_ticket); t < ntiles;
+         t = next_tile(counter, ntiles, &s_ticket)) {
         const uint32_t p0 = t * kCpTile + threadIdx.x * kCpIpt;
         uint4 v = *reinterpret_cast<const uint4*>(keep + p0);
         uint32_t wds[4] = {v.x, v.y, v.z, v.w};
@@ -960,9 +967,11 @@ hipError_t launch_densify(int64_t n, int blocks, const uint32_t* seg_count, cons
 
 hipError_t launch_round2_scan(int64_t n, const uint32_t* slots, const double2* comp_xy,
                               const Params* prm, const DevStatus* ds, uint8_t* keep, uint64_t* stat,
-                              uint32_t epoch, int cu_count, hipStream_t s) {
-    const int grid = coop_grid(k_round2_scan, kR2Block, cu_count, ceil_div(n, kR2Tile) + 2);
-    return launch_coop(k_round2_scan, grid, kR2Block, s, slots, comp_xy, prm, ds, keep, stat, epoch);
+                              Counters* ctr, uint32_t epoch, int cu_count, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>(ceil_div(n, kR2Tile) + 2, 4 * cu_count);
+    hipLaunchKernelGGL(k_round2_scan, dim3(grid), dim3(kR2Block), 0, s, slots, comp_xy, prm, ds, keep,
+                       stat, ctr, epoch);
+    return hipGetLastError();
 }
 
 hipError_t launch_round2_chunks(int64_t n, int64_t chunk, const uint32_t* slots,
@@ -980,11 +989,12 @@ hipError_t launch_round2_chunks(int64_t n, int64_t chunk, const uint32_t* slots,
 
 hipError_t launch_compact(int64_t n, const uint8_t* keep, const uint32_t* slots,
                           const double2* comp_xy, const uint32_t* comp_idx, double2* out_xy,
-                          int32_t* out_idx, DevStatus* ds, uint64_t* stat, uint32_t epoch,
-                          int cu_count, hipStream_t s) {
-    const int grid = coop_grid(k_compact, kCpBlock, cu_count, ceil_div(n, kCpTile));
-    return launch_coop(k_compact, grid, kCpBlock, s, keep, slots, comp_xy, comp_idx, out_xy,
-                       out_idx, ds, stat, epoch);
+                          int32_t* out_idx, DevStatus* ds, uint64_t* stat, Counters* ctr,
+                          uint32_t epoch, int cu_count, hipStream_t s) {
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kCpTile), 4 * cu_count));
+    hipLaunchKernelGGL(k_compact, dim3(grid), dim3(kCpBlock), 0, s, keep, slots, comp_xy, comp_idx,
+                       out_xy, out_idx, ds, stat, ctr, epoch);
+    return hipGetLastError();
 }
 
 hipError_t launch_debug_orient(const double* abc, int64_t count, int32_t* out, hipStream_t s) {

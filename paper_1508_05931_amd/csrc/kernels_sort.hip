@@ -66,10 +66,11 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
     int pass, const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ hist, const DevStatus* __restrict__ ds,
-    uint64_t* __restrict__ stat, uint32_t epoch) {
+    uint64_t* __restrict__ stat, Counters* __restrict__ ctr, uint32_t epoch) {
     constexpr int NW = kSortBlock / 64;
     constexpr int IPT = kSortIpt;
     static_assert(kSortBlock == kRadix, "one thread per digit");
+    __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_wc[NW][kRadix];     // per-wave digit counters, then wave prefixes
     __shared__ uint32_t s_tl[kRadix];         // tile-local digit offsets
     __shared__ int64_t s_adj[kRadix];         // global destination minus tile-local position
@@ -97,7 +98,9 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
         __syncthreads();
     }
 
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint32_t* counter = &ctr->ticket[16 * (kTicketSort0 + pass)];
+    for (uint32_t t = next_tile(counter, ntiles, &s_ticket); t < ntiles;
+         t = next_tile(counter, ntiles, &s_ticket)) {
         for (int w = 0; w < NW; ++w) s_wc[w][d] = 0;
         __syncthreads();
         const uint32_t base = t * kSortTile;
@@ -416,11 +419,12 @@ hipError_t launch_histogram(const uint32_t* keys, const DevStatus* ds, uint32_t*
 
 hipError_t launch_sort_pass(int64_t n, int pass, const uint32_t* keys_in, const uint32_t* vals_in,
                             uint32_t* keys_out, uint32_t* vals_out, const uint32_t* hist,
-                            const DevStatus* ds, uint64_t* stat, uint32_t epoch, int cu_count,
-                            hipStream_t s) {
-    const int grid = coop_grid(k_sort_pass, kSortBlock, cu_count, ceil_div(n, kSortTile));
-    return launch_coop(k_sort_pass, grid, kSortBlock, s, pass, keys_in, vals_in, keys_out, vals_out,
-                       hist, ds, stat, epoch);
+                            const DevStatus* ds, uint64_t* stat, Counters* ctr, uint32_t epoch,
+                            int cu_count, hipStream_t s) {
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, kSortTile), 4 * cu_count));
+    hipLaunchKernelGGL(k_sort_pass, dim3(grid), dim3(kSortBlock), 0, s, pass, keys_in, vals_in, keys_out,
+                       vals_out, hist, ds, stat, ctr, epoch);
+    return hipGetLastError();
 }
 
 hipError_t launch_ties(int64_t n, const uint32_t* keys, uint32_t* slots, const double2* comp_xy,
