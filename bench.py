@@ -28,7 +28,7 @@ HBM_PEAK_GBPS = 8000.0
 PAPER_MS_SQUARE_DISK_20M = 446.4 + 418.1
 
 KERNEL_STAGES = ["extremes", "filter1", "longest", "buckets", "histogram", "sort0", "sort1",
-                 "sort2", "sort3", "ties", "ties_long", "round2", "compact"]
+                 "sort2", "sort3", "ties", "ties_long", "round2", "compact", "tail"]
 
 
 def kernel_bytes(stage: str, n: int, ms: int, nc: int, m2: int, full: bool) -> float:
@@ -50,6 +50,7 @@ def kernel_bytes(stage: str, n: int, ms: int, nc: int, m2: int, full: bool) -> f
         "ties_long": 0.0,
         "round2": 21.0 * nc,
         "compact": 1.0 * nc + 44.0 * m2,
+        "tail": 24.0 * nc + 20.0 * m2,
     }[stage]
 
 

@@ -92,6 +92,7 @@ enum {
     HULL2D_STAGE_BUCKETS,        /* Steps 6-7 bucket maxima, prefix, candidates     */
     HULL2D_STAGE_ROUND2,         /* Steps 6-7 second-round filter                   */
     HULL2D_STAGE_COMPACT,        /* Step 7 stable removal of interior points        */
+    HULL2D_STAGE_TAIL,           /* Steps 4, 6-7 on a small candidate set, one workgroup */
     HULL2D_STAGE_D2H,            /* copy of the kept points to the host             */
     HULL2D_STAGE_HOST_SCAN,      /* Step 8 on the host (wall clock)                 */
     HULL2D_NUM_STAGES

@@ -26,7 +26,7 @@ STATUS = {
 OK, INVALID_ARG, NONFINITE, RANGE, CAPACITY, OUT_OF_MEMORY, DEVICE, WEIGHTS, UNIMPLEMENTED = range(9)
 
 STAGES = ["extremes", "extremes_final", "filter1", "longest", "histogram", "sort0", "sort1",
-          "sort2", "sort3", "ties", "ties_long", "buckets", "round2", "compact", "d2h",
+          "sort2", "sort3", "ties", "ties_long", "buckets", "round2", "compact", "tail", "d2h",
           "host_scan"]
 
 EXPORTED = ["hull2d_create", "hull2d_compute", "hull2d_batch", "hull2d_destroy",

@@ -33,6 +33,9 @@ struct Params {
     int32_t pad2[2];
 };
 
+constexpr uint32_t kTailDone = 0u;
+constexpr uint32_t kTailOverflow = 1u;
+
 constexpr uint32_t kFlagNonfinite = 1u;
 constexpr uint32_t kFlagRange = 2u;
 
@@ -49,7 +52,8 @@ struct DevStatus {
     uint32_t long_runs;   // equal-key runs handed to the workgroup sorter
     uint32_t l_slot;      // slot of P_l in this problem's arrays
     uint32_t n_right;     // points before P_l in angular order (bucketed filter)
-    uint32_t pad;
+    uint32_t tail_state;  // candidate problem: kTailDone, or kTailOverflow (too large for
+                          // the one-workgroup tail; the multi-kernel path runs instead)
     int32_t ext[4];
     int32_t p0_idx, l_idx;
     double x0, y0;
@@ -65,6 +69,7 @@ enum TicketId {
     kTicketSort0 = 0,  // ..3
     kTicketRound2 = 4,
     kTicketCompact = 5,
+    kTicketTail = 6,
 };
 
 constexpr int kBucketBits = 12;                 // coarse angle buckets of the bucketed round 2

@@ -20,6 +20,7 @@ struct hull2d_ctx {
     hipStream_t stream = nullptr;
     hull2d_options opt{};
     int cu_count = 256;
+    Occupancy occ;
     bool broken = false;
 
     // device workspace (grows on demand)
@@ -74,7 +75,7 @@ struct hull2d_ctx {
 
 namespace {
 
-constexpr int kMaxSegs = 8192;  // round-1 blocks (cu_count * kF1BlocksPerCu) at most
+constexpr int kMaxSegs = 8192;  // round-1 blocks (resident blocks of the whole chip) at most
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -138,7 +139,7 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
         c->dmem = nullptr;
         c->cap_n = -1;
     }
-    c->parts = 2 * c->cu_count;
+    c->parts = std::min(c->occ.bucket_max, 2) * c->cu_count;
     Layout L = plan(want, c->parts);
     if (hipMalloc((void**)&c->dmem, L.total) != hipSuccess) {
         (void)hipGetLastError();
@@ -308,6 +309,7 @@ hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->cu_count = prop.multiProcessorCount;
+    c->occ = query_occupancy();
     if (hipMalloc((void**)&c->ctr, sizeof(Counters)) != hipSuccess ||
         hipMemset(c->ctr, 0, sizeof(Counters)) != hipSuccess ||
         hipHostMalloc((void**)&c->h_ds, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
@@ -362,19 +364,24 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
 
     const bool prof = c->opt.profile && c->have_events;
     hipStream_t s = c->stream;
+    int marks[2 * HULL2D_NUM_STAGES];
+    int n_marks = 0;
     auto mark = [&](int i) {
-        if (prof) (void)hipEventRecord(c->ev[i], s);
+        if (prof && n_marks < 2 * HULL2D_NUM_STAGES) {
+            (void)hipEventRecord(c->ev[i], s);
+            marks[n_marks++] = i;
+        }
     };
     hipEvent_t ev_begin = c->ev[HULL2D_NUM_STAGES];
     hipEvent_t ev_end = c->ev[HULL2D_NUM_STAGES + 1];
     if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
 
     // Step 1
-    const int grid_ext = (int)std::max<int64_t>(1, std::min<int64_t>(kExtGridMax, ceil_div(n, kExtBlock * 8)));
+    const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
     HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, s));
     mark(HULL2D_STAGE_EXTREMES);
     // Steps 2-3
-    const int segs = std::min(filter1_blocks(n, c->cu_count), kMaxSegs);
+    const int segs = std::min(filter1_blocks(n, c->cu_count, c->occ.filter1), kMaxSegs);
     HX_TRY(launch_filter1(d_xy, n, segs, c->prm, c->comp_xy, c->comp_idx, c->keys_a, c->seg_count,
                           c->blk_d2, c->blk_best, c->ds, s));
     mark(HULL2D_STAGE_FILTER1);
@@ -406,32 +413,36 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
         HX_TRY(launch_densify(n, segs, c->seg_count, c->seg_off, c->keys_a, c->cand_key, c->cand_idx, s));
     }
     mark(HULL2D_STAGE_BUCKETS);
-    // Step 4
-    HX_TRY(launch_histogram(pkeys, pds, c->hist,
-                            (int)std::min<int64_t>(kHistGridMax, std::max<int64_t>(1, ceil_div(n, 4096))), s));
-    mark(HULL2D_STAGE_HISTOGRAM);
-    const uint32_t* kin = pkeys;
-    const uint32_t* vin = pvals;
-    uint32_t* kout = c->keys_b;
-    uint32_t* vout = c->vals_b;
-    for (int pass = 0; pass < 4; ++pass) {
-        const uint32_t e = ++c->epoch;
-        HX_TRY(launch_sort_pass(n, pass, kin, vin, kout, vout, c->hist, pds, c->stat, c->ctr, e,
-                                c->cu_count, s));
-        mark(HULL2D_STAGE_SORT0 + pass);
-        kin = kout;
-        vin = vout;
-        kout = (kout == c->keys_b) ? c->keys_a : c->keys_b;
-        vout = (vout == c->vals_b) ? c->vals_a : c->vals_b;
-    }
-    uint32_t* keys = c->keys_a;   // after four passes the result is in keys_a / vals_a
+
+    // Step 4 and Steps 6-7 with the stable removal, by the multi-kernel path
+    // (any size), followed by the status read-back.
+    auto sort_path = [&]() -> hull2d_status {
+        HX_TRY(launch_histogram(pkeys, pds, c->hist,
+                                (int)std::min<int64_t>(kHistGridMax, std::max<int64_t>(1, ceil_div(n, 4096))), s));
+        mark(HULL2D_STAGE_HISTOGRAM);
+        const uint32_t* kin = pkeys;
+        const uint32_t* vin = pvals;
+        uint32_t* kout = c->keys_b;
+        uint32_t* vout = c->vals_b;
+        for (int pass = 0; pass < 4; ++pass) {
+            const uint32_t e = ++c->epoch;
+            HX_TRY(launch_sort_pass(n, pass, kin, vin, kout, vout, c->hist, pds, c->stat, c->ctr, e,
+                                    c->cu_count, s));
+            mark(HULL2D_STAGE_SORT0 + pass);
+            kin = kout;
+            vin = vout;
+            kout = (kout == c->keys_b) ? c->keys_a : c->keys_b;
+            vout = (vout == c->vals_b) ? c->vals_a : c->vals_b;
+        }
+        // after four passes the result is in keys_a / vals_a
+        HX_TRY(launch_ties(n, c->keys_a, c->vals_a, pxy, pidx, c->prm, pds, c->long_list, s));
+        mark(HULL2D_STAGE_TIES);
+        HX_TRY(launch_ties_long(c->keys_a, c->vals_a, pxy, pidx, c->prm, pds, c->long_list,
+                                c->huge_list, c->cu_count, s));
+        mark(HULL2D_STAGE_TIES_LONG);
+        return HULL2D_OK;
+    };
     uint32_t* slots = c->vals_a;
-    HX_TRY(launch_ties(n, keys, slots, pxy, pidx, c->prm, pds, c->long_list, s));
-    mark(HULL2D_STAGE_TIES);
-    HX_TRY(launch_ties_long(keys, slots, pxy, pidx, c->prm, pds, c->long_list, c->huge_list,
-                            c->cu_count, s));
-    mark(HULL2D_STAGE_TIES_LONG);
-    // Steps 6-7 on the sorted problem, then the stable removal
     auto round2 = [&]() -> hull2d_status {
         if (c->opt.round2_chunk == 0) {
             const uint32_t e = ++c->epoch;
@@ -445,17 +456,37 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
         HX_TRY(launch_compact(n, c->keep, slots, pxy, pidx, c->out_xy, c->out_idx, pds, c->stat,
                               c->ctr, e, c->cu_count, s));
         mark(HULL2D_STAGE_COMPACT);
+        return HULL2D_OK;
+    };
+    auto read_status = [&]() -> hull2d_status {
         HX_TRY(hipMemcpyAsync(c->h_ds, c->ds, 2 * sizeof(DevStatus), hipMemcpyDeviceToHost, s));
         HX_TRY(spin_sync(c));
         return HULL2D_OK;
     };
-    st = round2();
-    if (st != HULL2D_OK) return st;
+    bool tail_done = false;
+    if (!full) {
+        // small candidate sets: one workgroup does the rest
+        const uint32_t e = ++c->epoch;
+        HX_TRY(launch_tail(c->cand_xy, c->cand_idx, c->cand_key, c->prm, c->ds + 1, c->out_xy,
+                           c->out_idx, c->stat, c->ctr, e, s));
+        mark(HULL2D_STAGE_TAIL);
+        st = read_status();
+        if (st != HULL2D_OK) return st;
+        tail_done = c->h_ds[1].tail_state == kTailDone;
+    }
+    if (!tail_done) {
+        st = sort_path();
+        if (st != HULL2D_OK) return st;
+        st = round2();
+        if (st != HULL2D_OK) return st;
+        st = read_status();
+        if (st != HULL2D_OK) return st;
+    }
     DevStatus D = c->h_ds[0];
     DevStatus DP = full ? c->h_ds[0] : c->h_ds[1];
     if (D.flags & kFlagNonfinite) return HULL2D_ERR_NONFINITE;
     if (D.flags & kFlagRange) return HULL2D_ERR_RANGE;
-    if (DP.huge_runs > 0) {
+    if (!tail_done && DP.huge_runs > 0) {
         // Runs of equal keys longer than one workgroup sorts: merge them, then
         // run the second round again on the corrected order.
         std::vector<uint32_t> hl(2 * (size_t)DP.huge_runs);
@@ -465,6 +496,8 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
         for (uint32_t r = 0; r < DP.huge_runs; ++r)
             HX_TRY(launch_huge_run(slots, c->vals_b, hl[2 * r], hl[2 * r + 1], pxy, pidx, c->prm, pds, s));
         st = round2();
+        if (st != HULL2D_OK) return st;
+        st = read_status();
         if (st != HULL2D_OK) return st;
         D = c->h_ds[0];
         DP = full ? c->h_ds[0] : c->h_ds[1];
@@ -509,20 +542,14 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
                 stats->ms_device = f;
         }
         if (prof) {
-            // stage i ends at event i; Step 1's two kernels are reported
-            // together under EXTREMES.
-            const int order[] = {HULL2D_STAGE_EXTREMES, HULL2D_STAGE_FILTER1, HULL2D_STAGE_LONGEST,
-                                 HULL2D_STAGE_BUCKETS,
-                                 HULL2D_STAGE_HISTOGRAM, HULL2D_STAGE_SORT0, HULL2D_STAGE_SORT1,
-                                 HULL2D_STAGE_SORT2, HULL2D_STAGE_SORT3, HULL2D_STAGE_TIES,
-                                 HULL2D_STAGE_TIES_LONG, HULL2D_STAGE_ROUND2, HULL2D_STAGE_COMPACT,
-                                 HULL2D_STAGE_D2H};
+            // each recorded stage ends at its event and starts at the previous
+            // recorded one; Step 1's two kernels are reported under EXTREMES
             hipEvent_t prev = ev_begin;
-            for (int k = 0; k < (int)(sizeof(order) / sizeof(order[0])); ++k) {
+            for (int k = 0; k < n_marks; ++k) {
                 float f = 0.f;
-                if (hipEventElapsedTime(&f, prev, c->ev[order[k]]) == hipSuccess)
-                    stats->ms_stage[order[k]] = f;
-                prev = c->ev[order[k]];
+                if (hipEventElapsedTime(&f, prev, c->ev[marks[k]]) == hipSuccess && f > 0.f)
+                    stats->ms_stage[marks[k]] += f;
+                prev = c->ev[marks[k]];
             }
         }
         stats->ms_stage[HULL2D_STAGE_HOST_SCAN] = ms_scan;

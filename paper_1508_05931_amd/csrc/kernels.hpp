@@ -12,9 +12,9 @@ namespace hx {
 
 // Launch geometry shared by the launchers and the workspace sizing.
 constexpr int kExtBlock = 256;
-constexpr int kExtGridMax = 1024;
+constexpr int kExtGridMax = 4096;   // partial-result slots of Step 1
 constexpr int kF1Block = 256;
-constexpr int kF1Ipt = 8;
+constexpr int kF1Ipt = 4;
 constexpr int kF1Tile = kF1Block * kF1Ipt;       // points per round-1 tile
 constexpr int kSortBlock = 256;
 constexpr int kSortIpt = 16;
@@ -28,6 +28,8 @@ constexpr int kCpTile = kCpBlock * kCpIpt;       // flags per compaction tile
 constexpr int kRunSmall = 16;                    // equal-key runs sorted by one thread
 constexpr int kRunCap = 2048;                    // longest run one workgroup sorts in LDS
 constexpr int kHistGridMax = 512;
+constexpr int kTailBlock = 1024;                 // the one-workgroup tail
+constexpr int kTailCap = 12288;                  // candidates per region it sorts in LDS
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -35,13 +37,38 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 // the quadrilateral and the pivot.
 hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
                            DevStatus* ds, hipStream_t s);
+int extremes_grid(int64_t n, int cu_count, int per_cu);
+
+// Resident blocks per compute unit of the fixed-grid streaming kernels (from
+// the runtime's occupancy calculator), so that one launch fills the chip
+// exactly once: a block that cannot be resident would run in a second,
+// mostly empty wave of blocks.
+struct Occupancy {
+    int extremes = 1, filter1 = 1, bucket_max = 1;
+};
+// At least 1 when the query fails.
+inline int resident_blocks(const void* kernel, int block) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, block, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        b = 0;
+    }
+    return b > 0 ? b : 1;
+}
+void occupancy_filter(Occupancy& o);  // extremes, filter1
+void occupancy_bucket(Occupancy& o);  // bucket_max
+inline Occupancy query_occupancy() {
+    Occupancy o;
+    occupancy_filter(o);
+    occupancy_bucket(o);
+    return o;
+}
 
 // Steps 2-3: strict-interior test against the quadrilateral, exact angle key,
 // squared distance.  Block b compacts the survivors of its input range into
 // the same range of comp_xy / comp_idx / keys (a segment of seg_count[b]
 // points starting at b*filter1_chunk).
-constexpr int kF1BlocksPerCu = 4;
-int filter1_blocks(int64_t n, int cu_count);
+int filter1_blocks(int64_t n, int cu_count, int per_cu);
 int64_t filter1_chunk(int64_t n, int blocks);
 hipError_t launch_filter1(const double* xy, int64_t n, int blocks, const Params* prm,
                           double2* comp_xy, uint32_t* comp_idx, uint32_t* keys, uint32_t* seg_count,
@@ -64,6 +91,13 @@ constexpr int kBmBlock = 512;
 hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
                              const uint32_t* keys, const Params* prm, DevStatus* ds, uint32_t* part,
                              int parts, hipStream_t s);
+// Steps 4 and 6-7 plus the stable removal for a candidate set small enough
+// for one workgroup per region (kTailCap each); otherwise sets tail_state to
+// kTailOverflow in ds2 and writes nothing else that the other path needs.
+// pub: one look-back status word (the right region's kept count).
+hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
+                       const Params* prm, DevStatus* ds2, double2* out_xy, int32_t* out_idx,
+                       uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s);
 hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, uint32_t* prefix,
                               DevStatus* ds2, hipStream_t s);
 hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,

@@ -190,6 +190,7 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
         ds2->long_runs = 0;
         ds2->l_slot = kNoSlot;
         ds2->n_right = 0;
+        ds2->tail_state = kTailDone;
     }
 }
 
@@ -282,6 +283,10 @@ hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, cons
     hipLaunchKernelGGL(k_prefilter, dim3(segs), dim3(kPfBlock), 0, s, filter1_chunk(n, segs), seg_count,
                        comp_xy, comp_idx, keys, prm, ds, prefix, cand_xy, cand_idx, cand_key, ds2);
     return hipGetLastError();
+}
+
+void occupancy_bucket(Occupancy& o) {
+    o.bucket_max = resident_blocks(reinterpret_cast<const void*>(k_bucket_max), kBmBlock);
 }
 
 }  // namespace hx

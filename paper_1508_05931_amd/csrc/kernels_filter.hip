@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void k_extremes_final(const Cand* __restrict__
     S.long_runs = 0;
     S.l_slot = kSlotNone;
     S.n_right = 0;
-    S.pad = 0;
+    S.tail_state = kTailDone;
     for (int k = 0; k < 4; ++k) S.ext[k] = e[k].i;
     S.p0_idx = e[1].i;
     S.l_idx = -1;
@@ -931,9 +931,19 @@ hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid,
     return hipGetLastError();
 }
 
-int filter1_blocks(int64_t n, int cu_count) {
-    int64_t g = std::min<int64_t>((int64_t)cu_count * kF1BlocksPerCu, ceil_div(n, kF1Tile));
+int extremes_grid(int64_t n, int cu_count, int per_cu) {
+    int64_t g = std::min<int64_t>((int64_t)cu_count * per_cu, ceil_div(n, kExtBlock * 8));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, kExtGridMax));
+}
+
+int filter1_blocks(int64_t n, int cu_count, int per_cu) {
+    int64_t g = std::min<int64_t>((int64_t)cu_count * per_cu, ceil_div(n, kF1Tile));
     return (int)std::max<int64_t>(g, 1);
+}
+
+void occupancy_filter(Occupancy& o) {
+    o.extremes = resident_blocks(reinterpret_cast<const void*>(k_extremes), kExtBlock);
+    o.filter1 = resident_blocks(reinterpret_cast<const void*>(k_filter1), kF1Block);
 }
 
 int64_t filter1_chunk(int64_t n, int blocks) {

@@ -15,6 +15,7 @@
 //      for short runs and by one workgroup in LDS for longer ones.
 #include "exact.hpp"
 #include "kernels.hpp"
+#include "records.hpp"
 
 namespace hx {
 namespace {
@@ -199,26 +200,6 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
         }
         __syncthreads();
     }
-}
-
-struct Rec {
-    double x, y;
-    uint32_t idx, slot;
-};
-
-__device__ inline Rec rec_load(uint32_t slot, const double2* __restrict__ comp,
-                               const uint32_t* __restrict__ comp_idx) {
-    double2 v = comp[slot];
-    Rec r;
-    r.x = v.x;
-    r.y = v.y;
-    r.idx = comp_idx[slot];
-    r.slot = slot;
-    return r;
-}
-
-__device__ inline bool rec_less(const Rec& a, const Rec& b, double x0, double y0) {
-    return angle_less(a.x, a.y, a.idx, b.x, b.y, b.idx, x0, y0);
 }
 
 // Equal-key runs: a run of at most kRunSmall keys is put in exact order by

@@ -1,0 +1,530 @@
+// kernels_tail.hip - the end of the bucketed path in one workgroup.
+//
+// After the bucketed filter the second round only has a small candidate set
+// left (typically a few thousand points per region).  For such a set the
+// multi-kernel sort, the look-back scan of Steps 6-7 and the compaction are
+// dominated by launch gaps and look-back latency, so two workgroups of 1024
+// threads do all of it, one region each, with the region's keys and slots in
+// LDS and every global access issued in batches (the run time is a handful of
+// memory latencies):
+//
+//   1. collect the region's candidates: the right region is every candidate
+//      before P_l in the exact angular order of Step 4, the left region is
+//      P_l and every candidate after it;
+//   2. Step 4 on them: a stable LSD radix sort of (angle key, slot), four
+//      passes of 8 bits with wave-level match masks, then the exact order
+//      inside runs of equal keys (one thread per short run, the whole
+//      workgroup per long run);
+//   3. Steps 6-7 as a max-scan (the same formulation as k_round2_scan: a
+//      point is kept when it follows, seen from P_l, the maximum of all points
+//      walked before it; the right region is walked forward from P_0, the left
+//      one backward from its last point, P_l itself is always kept);
+//   4. the stable removal: the kept points in angular order, right region,
+//      then P_l and the left region (the left workgroup waits for the right
+//      one's count; the workgroups take the regions in ticket order, so the
+//      one waited for is always running).
+//
+// A region with more than kTailCap candidates, more than kTailLongMax long
+// runs or a run longer than kRunCap sets tail_state = kTailOverflow and the
+// host runs the multi-kernel path instead; the result is the same.
+#include "exact.hpp"
+#include "kernels.hpp"
+#include "records.hpp"
+
+namespace hx {
+namespace {
+
+constexpr int kTB = kTailBlock;
+constexpr int kTW = kTB / 64;
+constexpr int kTI = kTailCap / kTB;     // items per thread
+constexpr int kTailLongMax = 64;        // equal-key runs longer than kRunSmall per region
+constexpr int kRadixT = 256;
+static_assert(kTailCap % kTB == 0, "whole items per thread");
+static_assert(kTailCap <= 65536, "slots and counters are 16-bit");
+static_assert((size_t)kRunCap * sizeof(Rec) <= (size_t)kTailCap * sizeof(uint32_t),
+              "a long run's records fit in the spare key buffer");
+
+struct alignas(16) TailLds {
+    uint32_t key[2][kTailCap];     // angle keys, ping-pong
+    uint16_t ix[2][kTailCap];      // candidate slots, ping-pong
+    uint16_t wc[kTW][kRadixT];     // per-wave digit counters, then wave prefixes
+    uint32_t dbase[kRadixT];       // digit totals, then digit bases
+    uint32_t wsum[kTW];
+    uint32_t longs[kTailLongMax];
+    double wx[kTW], wy[kTW];       // wave aggregates of the round-2 scan
+    uint32_t wv[kTW];
+    uint32_t count, nlong, total, runlen;
+};
+
+struct TPt {
+    double x, y;
+    bool v;  // false: the identity (nothing walked yet)
+};
+
+__device__ inline TPt tpt_none() {
+    TPt p;
+    p.x = 0.0;
+    p.y = 0.0;
+    p.v = false;
+    return p;
+}
+
+// Later of a and b in the walk's order seen from P_l (sgn +1: right region,
+// -1: left region); straight-line selects.
+__device__ inline TPt tmax(const TPt& a, const TPt& b, double lx, double ly, int sgn) {
+    const int o = orient(lx, ly, a.x, a.y, b.x, b.y);
+    const bool take_b = (!a.v) | (b.v & (sgn * o >= 0));
+    TPt r;
+    r.x = take_b ? b.x : a.x;
+    r.y = take_b ? b.y : a.y;
+    r.v = take_b ? b.v : a.v;
+    return r;
+}
+
+__device__ inline TPt shfl_up_tpt(const TPt& p, int d) {
+    TPt r;
+    r.x = __shfl_up(p.x, d);
+    r.y = __shfl_up(p.y, d);
+    r.v = __shfl_up((int)p.v, d) != 0;
+    return r;
+}
+
+__device__ inline uint32_t wsum_incl(uint32_t v) {
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Lanes of the wave whose `valid` digit equals this lane's (8 ballots).
+__device__ inline uint64_t match_digit(uint32_t dig, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot((dig >> b) & 1u);
+        m &= ((dig >> b) & 1u) ? bb : ~bb;
+    }
+    return m;
+}
+
+// Exclusive block sum (all threads call it; `total` gets the block total).
+__device__ inline uint32_t block_excl_sum(uint32_t v, TailLds& S, uint32_t& total) {
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    const uint32_t inc = wsum_incl(v);
+    if (lane == 63) S.wsum[wave] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kTW; ++w) {
+        const uint32_t x = S.wsum[w];
+        pre += w < wave ? x : 0u;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + inc - v;
+}
+
+constexpr uint32_t kTailPubOverflow = 0xFFFFFFFFu;  // the right region did not fit
+
+__global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_xy,
+                                              const uint32_t* __restrict__ cand_idx,
+                                              const uint32_t* __restrict__ cand_key,
+                                              const Params* __restrict__ prm,
+                                              DevStatus* __restrict__ ds2,
+                                              double2* __restrict__ out_xy,
+                                              int32_t* __restrict__ out_idx,
+                                              uint64_t* __restrict__ pub, Counters* __restrict__ ctr,
+                                              uint32_t epoch) {
+    __shared__ TailLds S;
+    const int tid = (int)threadIdx.x;
+    const int lane = (int)__lane_id(), wave = tid >> 6;
+    if (tid == 0) {
+        uint32_t* counter = &ctr->ticket[16 * kTicketTail];
+        const uint32_t t = take_ticket(counter);
+        if (t == 1u) reset_ticket(counter);  // both workgroups have taken theirs
+        S.count = t;
+    }
+    __syncthreads();
+    const int region = (int)S.count;  // 0: right region, 1: left region
+    const int sgn = region == 0 ? 1 : -1;
+    __syncthreads();
+    const uint32_t nc = ds2->n_sorted;
+    const double x0 = prm->x0, y0 = prm->y0, lx = prm->lx, ly = prm->ly;
+    const uint32_t kl = prm->kl;
+    const uint32_t lslot = ds2->l_slot;
+    // Every exit of the right workgroup publishes its count (or the overflow
+    // mark) so that the left one never waits for nothing.
+    auto give_up = [&]() {
+        if (tid == 0) {
+            ds2->tail_state = kTailOverflow;
+            if (region == 0) stat_store(pub, stat_pack(epoch, kStatInclusive, kTailPubOverflow));
+        }
+    };
+    if (nc == 0) {
+        if (tid == 0 && region == 1) ds2->n_kept = 0;
+        return;  // nobody waits: the left workgroup needs no count
+    }
+    if (nc > 2u * (uint32_t)kTailCap || lslot >= nc) {
+        give_up();
+        return;
+    }
+    const Rec rl = rec_load(lslot, cand_xy, cand_idx);
+
+    // ---- 1. collect this region's candidates (keys loaded kTI at a time)
+    if (tid == 0) {
+        S.count = 0;
+        S.nlong = 0;
+    }
+    __syncthreads();
+    for (uint32_t base = 0; base < nc; base += (uint32_t)(kTB * kTI)) {
+        uint32_t kv[kTI];
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint32_t i = base + (uint32_t)(k * kTB + tid);
+            kv[k] = i < nc ? cand_key[i] : 0u;
+        }
+        bool mine[kTI];
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint32_t i = base + (uint32_t)(k * kTB + tid);
+            mine[k] = false;
+            if (i < nc) {
+                bool before;
+                if (kv[k] != kl) {
+                    before = kv[k] < kl;
+                } else if (i == lslot) {
+                    before = false;
+                } else {
+                    const Rec r = rec_load(i, cand_xy, cand_idx);
+                    before = rec_less(r, rl, x0, y0);
+                }
+                mine[k] = before == (region == 0);
+            }
+        }
+        // one LDS atomic per wave and item slot (a single counter shared by
+        // every thread would serialise)
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint64_t m = __ballot(mine[k]);
+            if (m == 0) continue;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t at = 0;
+            if (lane == leader) at = atomicAdd(&S.count, (uint32_t)__popcll(m));
+            at = __shfl(at, leader) + (uint32_t)__popcll(m & lanemask_lt());
+            const uint32_t i = base + (uint32_t)(k * kTB + tid);
+            if (mine[k] && at < (uint32_t)kTailCap) {
+                S.key[0][at] = kv[k];
+                S.ix[0][at] = (uint16_t)i;
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = S.count;
+    if (cnt > (uint32_t)kTailCap) {
+        give_up();
+        return;
+    }
+    // items per thread for this region (the unrolled loops below stop at ipt)
+    const int ipt = (int)max(1u, (cnt + kTB - 1) / kTB);
+
+    // ---- 2a. stable LSD radix sort in LDS.  Wave w owns positions
+    //          [w*64*ipt, (w+1)*64*ipt), item k of lane l at
+    //          w*64*ipt + k*64 + l, ranked item-major (stable).
+    int cur = 0;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        for (int j = tid; j < kTW * kRadixT; j += kTB) (&S.wc[0][0])[j] = 0;
+        __syncthreads();
+        uint32_t key[kTI], rank[kTI];
+        uint16_t slot[kTI];
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint32_t p = (uint32_t)(wave * 64 * ipt + k * 64 + lane);
+            const bool valid = k < ipt && p < cnt;
+            key[k] = valid ? S.key[cur][p] : 0u;
+            slot[k] = valid ? S.ix[cur][p] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint32_t p = (uint32_t)(wave * 64 * ipt + k * 64 + lane);
+            const bool valid = k < ipt && p < cnt;
+            const uint32_t dig = (key[k] >> shift) & 0xFFu;
+            const uint64_t m = match_digit(dig, valid);
+            uint32_t prior = 0;
+            if (valid) prior = S.wc[wave][dig];
+            const uint32_t below = (uint32_t)__popcll(m & lanemask_lt());
+            // every lane has read its counter before the leaders move it
+            __builtin_amdgcn_wave_barrier();
+            if (valid && below == 0u) S.wc[wave][dig] = (uint16_t)(prior + (uint32_t)__popcll(m));
+            __builtin_amdgcn_wave_barrier();
+            rank[k] = prior + below;
+        }
+        __syncthreads();
+        // digit d: wave prefixes and total
+        if (tid < kRadixT) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int w = 0; w < kTW; ++w) {
+                const uint32_t c = S.wc[w][tid];
+                S.wc[w][tid] = (uint16_t)tot;
+                tot += c;
+            }
+            S.dbase[tid] = tot;
+        }
+        __syncthreads();
+        // a pass where every key has the digit of position 0 keeps the order
+        // (every thread reads the same values; cnt == 0 skips every pass)
+        const bool same = S.dbase[(S.key[cur][0] >> shift) & 0xFFu] == cnt;
+        __syncthreads();
+        if (same) continue;
+        if (tid < kRadixT) {
+            const uint32_t v = S.dbase[tid];
+            const uint32_t inc = wsum_incl(v);
+            if (lane == 63) S.wsum[wave] = inc;
+            S.dbase[tid] = inc - v;  // wave-local exclusive prefix for now
+        }
+        __syncthreads();
+        if (tid < kRadixT) {
+            uint32_t pre = 0;
+            for (int w = 0; w < wave; ++w) pre += S.wsum[w];
+            S.dbase[tid] += pre;
+        }
+        __syncthreads();
+        const int nxt = cur ^ 1;
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint32_t p = (uint32_t)(wave * 64 * ipt + k * 64 + lane);
+            if (k < ipt && p < cnt) {
+                const uint32_t dig = (key[k] >> shift) & 0xFFu;
+                const uint32_t q = S.dbase[dig] + S.wc[wave][dig] + rank[k];
+                S.key[nxt][q] = key[k];
+                S.ix[nxt][q] = slot[k];
+            }
+        }
+        cur = nxt;
+        __syncthreads();
+    }
+
+    // ---- 2b. exact order inside runs of equal keys
+    uint32_t* kk = S.key[cur];
+    uint16_t* xx = S.ix[cur];
+    for (uint32_t p = (uint32_t)tid; p < cnt; p += kTB) {
+        const uint32_t k = kk[p];
+        if (p > 0 && kk[p - 1] == k) continue;
+        if (!(p + 1 < cnt && kk[p + 1] == k)) continue;
+        uint32_t L = 2;
+        while (p + L < cnt && L <= (uint32_t)kRunSmall && kk[p + L] == k) ++L;
+        if (L > (uint32_t)kRunSmall) {
+            const uint32_t at = atomicAdd(&S.nlong, 1u);
+            if (at < (uint32_t)kTailLongMax) S.longs[at] = p;
+            continue;
+        }
+        Rec r[kRunSmall];
+        for (uint32_t a = 0; a < L; ++a) r[a] = rec_load(xx[p + a], cand_xy, cand_idx);
+        for (uint32_t a = 1; a < L; ++a) {
+            const Rec v = r[a];
+            uint32_t b = a;
+            while (b > 0 && rec_less(v, r[b - 1], x0, y0)) {
+                r[b] = r[b - 1];
+                --b;
+            }
+            r[b] = v;
+        }
+        for (uint32_t a = 0; a < L; ++a) xx[p + a] = (uint16_t)r[a].slot;
+    }
+    __syncthreads();
+    const uint32_t nl = S.nlong;
+    if (nl > (uint32_t)kTailLongMax) {
+        give_up();
+        return;
+    }
+    Rec* s_r = reinterpret_cast<Rec*>(S.key[cur ^ 1]);
+    uint16_t* s_p = S.ix[cur ^ 1];
+    for (uint32_t j = 0; j < nl; ++j) {
+        const uint32_t s = S.longs[j];
+        if (tid == 0) {
+            uint32_t e = s + 1;
+            while (e < cnt && kk[e] == kk[s]) ++e;
+            S.runlen = e - s;
+        }
+        __syncthreads();
+        const uint32_t L = S.runlen;
+        if (L > (uint32_t)kRunCap) {
+            give_up();
+            return;
+        }
+        uint32_t P = 1;
+        while (P < L) P <<= 1;
+        for (uint32_t a = (uint32_t)tid; a < L; a += kTB) s_r[a] = rec_load(xx[s + a], cand_xy, cand_idx);
+        for (uint32_t a = (uint32_t)tid; a < P; a += kTB) s_p[a] = (uint16_t)a;
+        __syncthreads();
+        for (uint32_t kb = 2; kb <= P; kb <<= 1) {
+            for (uint32_t jj = kb >> 1; jj > 0; jj >>= 1) {
+                for (uint32_t a = (uint32_t)tid; a < P; a += kTB) {
+                    const uint32_t b = a ^ jj;
+                    if (b > a) {
+                        const uint32_t ia = s_p[a], ib = s_p[b];
+                        bool b_first;
+                        if (ia >= L) b_first = ib < L;
+                        else if (ib >= L) b_first = false;
+                        else b_first = rec_less(s_r[ib], s_r[ia], x0, y0);
+                        const bool asc = (a & kb) == 0;
+                        if (asc ? b_first : (!b_first && ia != ib)) {
+                            s_p[a] = (uint16_t)ib;
+                            s_p[b] = (uint16_t)ia;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t a = (uint32_t)tid; a < L; a += kTB) xx[s + a] = (uint16_t)s_r[s_p[a]].slot;
+        __syncthreads();
+    }
+
+    // ---- 3. Steps 6-7.  Walk index w = tid*ipt + k.  Right region: position
+    //         w, after P_0.  Left region: position cnt-1-w; P_l (position 0)
+    //         is not walked and always kept.  The items stay in registers
+    //         through step 4.
+    const uint32_t nwalk = region == 0 ? cnt : cnt - 1;
+    auto walk_pos = [&](uint32_t w) -> uint32_t { return region == 0 ? w : cnt - 1 - w; };
+    TPt agg = tpt_none();
+    {
+        double2 v[kTI];
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint32_t w = (uint32_t)(tid * ipt + k);
+            if (k < ipt && w < nwalk) v[k] = cand_xy[xx[walk_pos(w)]];
+        }
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint32_t w = (uint32_t)(tid * ipt + k);
+            if (k < ipt && w < nwalk) {
+                TPt q;
+                q.x = v[k].x;
+                q.y = v[k].y;
+                q.v = true;
+                agg = tmax(agg, q, lx, ly, sgn);
+            }
+        }
+    }
+    TPt inc = agg;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const TPt o = shfl_up_tpt(inc, d);
+        if (lane >= d) inc = tmax(o, inc, lx, ly, sgn);
+    }
+    TPt ex = shfl_up_tpt(inc, 1);
+    if (lane == 0) ex = tpt_none();
+    if (lane == 63) {
+        S.wx[wave] = inc.x;
+        S.wy[wave] = inc.y;
+        S.wv[wave] = inc.v ? 1u : 0u;
+    }
+    __syncthreads();
+    TPt run = tpt_none();
+    if (region == 0) {
+        run.x = x0;
+        run.y = y0;
+        run.v = true;
+    }
+    for (int w = 0; w < wave; ++w) {
+        TPt o;
+        o.x = S.wx[w];
+        o.y = S.wy[w];
+        o.v = S.wv[w] != 0u;
+        run = tmax(run, o, lx, ly, sgn);
+    }
+    run = tmax(run, ex, lx, ly, sgn);
+    uint32_t kmask = 0;
+    double2 v[kTI];  // loaded again (cache hits) rather than held across the scan
+    uint32_t id[kTI];
+#pragma unroll
+    for (int k = 0; k < kTI; ++k) {
+        const uint32_t w = (uint32_t)(tid * ipt + k);
+        if (k < ipt && w < nwalk) {
+            const uint32_t sl = xx[walk_pos(w)];
+            v[k] = cand_xy[sl];
+            id[k] = cand_idx[sl];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kTI; ++k) {
+        const uint32_t w = (uint32_t)(tid * ipt + k);
+        if (k < ipt && w < nwalk) {
+            TPt q;
+            q.x = v[k].x;
+            q.y = v[k].y;
+            q.v = true;
+            const bool kp = (!run.v) || sgn * orient(lx, ly, run.x, run.y, q.x, q.y) >= 0;
+            kmask |= kp ? (1u << k) : 0u;
+            run = tmax(run, q, lx, ly, sgn);
+        }
+    }
+
+    // ---- 4. stable removal in angular order.  Right region: thread order is
+    //         position order.  Left region: P_l first, then the walked items,
+    //         whose positions fall as the walk index rises.
+    uint32_t tot;
+    const uint32_t c = (uint32_t)__popc(kmask);
+    const uint32_t excl = block_excl_sum(c, S, tot);
+    uint32_t base = 0;
+    if (region == 1) {
+        if (tid == 0) {
+            uint64_t w;
+            for (;;) {
+                w = stat_load(pub);
+                if (stat_flag(w, epoch) == kStatInclusive) break;
+                __builtin_amdgcn_s_sleep(2);
+            }
+            S.total = stat_value(w);
+        }
+        __syncthreads();
+        base = S.total;
+        if (base == kTailPubOverflow) return;  // the host takes the other path
+    }
+    if (region == 0) {
+        uint32_t o = excl;
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            if ((kmask >> k) & 1u) {
+                out_xy[o] = v[k];
+                out_idx[o] = (int32_t)id[k];
+                ++o;
+            }
+        }
+        if (tid == 0) stat_store(pub, stat_pack(epoch, kStatInclusive, tot));
+    } else {
+        if (tid == 0) {
+            out_xy[base] = make_double2(rl.x, rl.y);
+            out_idx[base] = (int32_t)rl.idx;
+        }
+        // kept items of later threads come first
+        uint32_t o = base + 1u + (tot - excl - c);
+#pragma unroll
+        for (int k = kTI - 1; k >= 0; --k) {
+            if ((kmask >> k) & 1u) {
+                out_xy[o] = v[k];
+                out_idx[o] = (int32_t)id[k];
+                ++o;
+            }
+        }
+        if (tid == 0) ds2->n_kept = base + 1u + tot;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
+                       const Params* prm, DevStatus* ds2, double2* out_xy, int32_t* out_idx,
+                       uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s) {
+    hipLaunchKernelGGL(k_tail, dim3(2), dim3(kTB), 0, s, cand_xy, cand_idx, cand_key, prm, ds2,
+                       out_xy, out_idx, pub, ctr, epoch);
+    return hipGetLastError();
+}
+
+}  // namespace hx

@@ -191,6 +191,30 @@ def test_stages_equal_model(torch_dev, hx, name, mode):
     c.close()
 
 
+TAIL_CAP = 12288  # candidates per region that the one-workgroup tail sorts
+
+
+@pytest.mark.parametrize("name", ["square_100k", "disk_100k", "dup_heavy", "collinear_10k",
+                                  "annulus_ngon_100k", "grid_draws_100k"])
+def test_tail_and_fallback_paths(torch_dev, hx, name):
+    """The bucketed mode finishes small candidate sets in one workgroup and
+    larger ones with the multi-kernel path; both match the oracle."""
+    pts = CASES[name]
+    say(f"tail/fallback {name}")
+    c = hx.Hull2D(profile=True)
+    got = c.compute(to_dev(torch_dev, pts))
+    assert got.tolist() == oracle.hull(pts).tolist()
+    st = c.last_stats
+    tail_ran = st.ms_stage["tail"] > 0.0
+    sort_ran = st.ms_stage["histogram"] > 0.0
+    assert tail_ran or sort_ran
+    if st.n_candidates > 2 * TAIL_CAP:
+        assert sort_ran
+    if name in ("square_100k", "disk_100k"):
+        assert tail_ran and not sort_ran
+    c.close()
+
+
 @pytest.mark.parametrize("side,n", [(2, 1000), (3, 100_000), (8, 100_003), (64, 100_000),
                                     (64, 1_000_003), (1000, 2_000_000)])
 def test_extremes_tie_heavy(torch_dev, ctx, side, n):
