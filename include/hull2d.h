@@ -3,7 +3,8 @@
  *
  * The data-parallel first stage of gScan (G. Mei, "gScan: Accelerating
  * Graham Scan on the GPU", Sections 2 and 3) as hand-written HIP kernels,
- * followed by the paper's final stack scan on the host (Step 8):
+ * followed by the paper's final stack scan (Step 8; on the host for one hull,
+ * on the device in the batched form):
  *
  *   Step 1  four extreme points by parallel reduction           (Section 3.1)
  *   Step 2  discard points strictly inside their quadrilateral  (Section 3.1)
@@ -127,9 +128,16 @@ hull2d_status hull2d_compute(hull2d_ctx* ctx, const double* d_xy, int64_t n,
 
 /* Hulls of S independent sets stored back to back at d_xy: set s is points
  * [h_offsets[s], h_offsets[s+1]) (host array of S+1 non-decreasing int64,
- * h_offsets[0] = 0).  Each set's hull (indices local to the set) is written
- * to h_out at [h_out_offsets[s], h_out_offsets[s+1]).  CAPACITY: the
- * offsets are still written, with h_out_offsets[S] the required size. */
+ * h_offsets[0] = 0).  Each set's hull (indices local to the set, canonical as
+ * above) is written to h_out at [h_out_offsets[s], h_out_offsets[s+1]).
+ * One persistent launch computes every set (Steps 1-8 on the device, one
+ * workgroup per set at a time, largest sets first); a set whose equal-key
+ * runs exceed the workgroup sorter is finished with hull2d_compute.
+ * CAPACITY: the offsets are still written, with h_out_offsets[S] the
+ * required size, and h_out is untouched.  NONFINITE / RANGE: some set is
+ * outside the domain.  stats (may be NULL): n = total points, n_hull = total
+ * hull vertices, n_candidates = sets finished by hull2d_compute, ms_device,
+ * ms_total; the other fields are 0. */
 hull2d_status hull2d_batch(hull2d_ctx* ctx, const double* d_xy,
                            const int64_t* h_offsets, int32_t S,
                            int32_t* h_out, int64_t cap, int64_t* h_out_offsets,

@@ -173,6 +173,37 @@ class Hull2D:
         self.last_stats = Stats._from(stats)
         return self._out[:hn.value].copy()
 
+    def batch(self, xy, offsets) -> "tuple[np.ndarray, np.ndarray]":
+        """Hulls of the sets xy[offsets[s]:offsets[s+1]] of a float64 [N, 2]
+        device tensor: (int32 set-local indices, int64 offsets [S+1])."""
+        import torch
+        if not (isinstance(xy, torch.Tensor) and xy.is_cuda and xy.dtype == torch.float64):
+            raise TypeError("xy must be a float64 CUDA tensor of shape [N, 2]")
+        if xy.dim() != 2 or xy.shape[1] != 2 or not xy.is_contiguous():
+            raise ValueError("xy must be a contiguous [N, 2] tensor")
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        S = offs.shape[0] - 1
+        if S < 0 or offs[-1] != xy.shape[0]:
+            raise ValueError("offsets must have S+1 entries ending at N")
+        out_offs = np.zeros(S + 1, dtype=np.int64)
+        stats = _Stats()
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        cap = max(getattr(self, "_bcap", 0), 1024)
+        for _ in range(2):
+            out = np.empty(cap, dtype=np.int32)
+            st = self._lib.hull2d_batch(self._h, ctypes.c_void_p(xy.data_ptr() if xy.shape[0] else 0),
+                                        offs.ctypes.data_as(i64p), S, _i32p(out), cap,
+                                        out_offs.ctypes.data_as(i64p), ctypes.byref(stats))
+            if st == CAPACITY:
+                cap = int(out_offs[-1])
+                self._bcap = cap
+                continue
+            break
+        if st != OK:
+            raise HullError(st, "hull2d_batch")
+        self.last_stats = Stats._from(stats)
+        return out[:out_offs[-1]].copy(), out_offs
+
     def stages(self, cap: int) -> dict:
         """Stage results of the last compute (for checking against the model)."""
         ext = np.zeros(4, dtype=np.int32)

@@ -70,6 +70,7 @@ enum TicketId {
     kTicketRound2 = 4,
     kTicketCompact = 5,
     kTicketTail = 6,
+    kTicketBatch = 7,
 };
 
 constexpr int kBucketBits = 12;                 // coarse angle buckets of the bucketed round 2

@@ -66,6 +66,26 @@ struct hull2d_ctx {
     std::vector<int64_t> stk;      // host scan buffers, reused across calls
     std::vector<int32_t> hull;
 
+    // batched form: workspace over all points of a batch, per-set results
+    int64_t bcap_n = -1;
+    int32_t bcap_s = -1;
+    char* bmem = nullptr;
+    double2 *b_sv_xy = nullptr, *b_cd_xy = nullptr;
+    uint32_t *b_sv_idx = nullptr, *b_sv_key = nullptr, *b_cd_idx = nullptr, *b_cd_key = nullptr;
+    uint32_t *b_ka = nullptr, *b_kb = nullptr, *b_va = nullptr, *b_vb = nullptr;
+    uint8_t* b_flag = nullptr;
+    int32_t* b_hull = nullptr;
+    int64_t* b_offs = nullptr;
+    int32_t* b_order = nullptr;
+    int32_t* b_meta = nullptr;     // [cursor, count[S], start[S], flags[S]]
+    int64_t hb_cap_s = -1;         // pinned host staging
+    int64_t* hb_offs = nullptr;
+    int32_t* hb_order = nullptr;
+    int32_t* hb_meta = nullptr;
+    int64_t hb_cap_h = -1;
+    int32_t* hb_hull = nullptr;
+    int batch_grid = 0;
+
     // the last compute call, for hull2d_debug_stages
     bool have_last = false;
     bool last_full = false;
@@ -197,6 +217,91 @@ hull2d_status ensure_host(hull2d_ctx* c, int64_t m) {
         return HULL2D_ERR_OUT_OF_MEMORY;
     }
     c->h_cap = want;
+    return HULL2D_OK;
+}
+
+// Batched form: device arrays over all N points of a batch (survivors,
+// candidates, radix ping-pong, keep flags, hull indices) and S-sized per-set
+// arrays, plus pinned staging for the offsets, the order and the results.
+hull2d_status ensure_batch(hull2d_ctx* c, int64_t N, int32_t S) {
+    if (N > c->bcap_n || S > c->bcap_s) {
+        const int64_t wn = std::max<int64_t>(std::max<int64_t>(N, c->bcap_n), 1);
+        const int64_t ws = std::max<int64_t>(std::max<int64_t>(S, c->bcap_s), 1);
+        if (c->bmem) {
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipFree(c->bmem);
+            c->bmem = nullptr;
+            c->bcap_n = -1;
+            c->bcap_s = -1;
+        }
+        const size_t sizes[15] = {
+            (size_t)wn * sizeof(double2), (size_t)wn * 4, (size_t)wn * 4,   // survivors
+            (size_t)wn * sizeof(double2), (size_t)wn * 4, (size_t)wn * 4,   // candidates
+            (size_t)wn * 4, (size_t)wn * 4, (size_t)wn * 4, (size_t)wn * 4,  // ka kb va vb
+            (size_t)wn,                                                      // flags
+            (size_t)wn * 4,                                                  // hull
+            (size_t)(ws + 1) * 8, (size_t)ws * 4,                            // offsets, order
+            (size_t)(3 * ws + 1) * 4};                                       // meta
+        size_t off[15], o = 0;
+        for (int i = 0; i < 15; ++i) {
+            off[i] = o;
+            o = align_up(o + sizes[i], 256);
+        }
+        if (hipMalloc((void**)&c->bmem, o) != hipSuccess) {
+            (void)hipGetLastError();
+            c->bmem = nullptr;
+            return HULL2D_ERR_OUT_OF_MEMORY;
+        }
+        char* b = c->bmem;
+        c->b_sv_xy = (double2*)(b + off[0]);
+        c->b_sv_idx = (uint32_t*)(b + off[1]);
+        c->b_sv_key = (uint32_t*)(b + off[2]);
+        c->b_cd_xy = (double2*)(b + off[3]);
+        c->b_cd_idx = (uint32_t*)(b + off[4]);
+        c->b_cd_key = (uint32_t*)(b + off[5]);
+        c->b_ka = (uint32_t*)(b + off[6]);
+        c->b_kb = (uint32_t*)(b + off[7]);
+        c->b_va = (uint32_t*)(b + off[8]);
+        c->b_vb = (uint32_t*)(b + off[9]);
+        c->b_flag = (uint8_t*)(b + off[10]);
+        c->b_hull = (int32_t*)(b + off[11]);
+        c->b_offs = (int64_t*)(b + off[12]);
+        c->b_order = (int32_t*)(b + off[13]);
+        c->b_meta = (int32_t*)(b + off[14]);
+        c->bcap_n = wn;
+        c->bcap_s = (int32_t)ws;
+    }
+    if (S > c->hb_cap_s) {
+        if (c->hb_offs) (void)hipHostFree(c->hb_offs);
+        if (c->hb_order) (void)hipHostFree(c->hb_order);
+        if (c->hb_meta) (void)hipHostFree(c->hb_meta);
+        c->hb_offs = nullptr;
+        c->hb_order = nullptr;
+        c->hb_meta = nullptr;
+        c->hb_cap_s = -1;
+        const int64_t ws = std::max<int64_t>(S, 1);
+        if (hipHostMalloc((void**)&c->hb_offs, (size_t)(ws + 1) * 8, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&c->hb_order, (size_t)ws * 4, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&c->hb_meta, (size_t)(3 * ws + 1) * 4, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return HULL2D_ERR_OUT_OF_MEMORY;
+        }
+        c->hb_cap_s = ws;
+    }
+    return HULL2D_OK;
+}
+
+hull2d_status ensure_batch_hull(hull2d_ctx* c, int64_t h) {
+    if (h <= c->hb_cap_h) return HULL2D_OK;
+    const int64_t want = std::max<int64_t>(h, 1 << 16);
+    if (c->hb_hull) (void)hipHostFree(c->hb_hull);
+    c->hb_hull = nullptr;
+    c->hb_cap_h = -1;
+    if (hipHostMalloc((void**)&c->hb_hull, (size_t)want * 4, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return HULL2D_ERR_OUT_OF_MEMORY;
+    }
+    c->hb_cap_h = want;
     return HULL2D_OK;
 }
 
@@ -338,6 +443,11 @@ void hull2d_destroy(hull2d_ctx* c) {
     if (c->h_ds) (void)hipHostFree(c->h_ds);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
+    if (c->bmem) (void)hipFree(c->bmem);
+    if (c->hb_offs) (void)hipHostFree(c->hb_offs);
+    if (c->hb_order) (void)hipHostFree(c->hb_order);
+    if (c->hb_meta) (void)hipHostFree(c->hb_meta);
+    if (c->hb_hull) (void)hipHostFree(c->hb_hull);
     for (int i = 0; i < HULL2D_NUM_STAGES + 2; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->ev_sync) (void)hipEventDestroy(c->ev_sync);
@@ -567,6 +677,7 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
 hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_offsets, int32_t S,
                            int32_t* h_out, int64_t cap, int64_t* h_out_offsets,
                            hull2d_stats* stats) {
+    auto t_start = std::chrono::steady_clock::now();
     if (!c || S < 0 || !h_offsets || !h_out_offsets || cap < 0 || (cap > 0 && !h_out))
         return HULL2D_ERR_INVALID_ARG;
     if (h_offsets[0] != 0) return HULL2D_ERR_INVALID_ARG;
@@ -574,8 +685,112 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         if (h_offsets[s + 1] < h_offsets[s] || h_offsets[s + 1] - h_offsets[s] > (int64_t)INT32_MAX)
             return HULL2D_ERR_INVALID_ARG;
     if (h_offsets[S] > 0 && !d_xy) return HULL2D_ERR_INVALID_ARG;
-    (void)stats;
-    return HULL2D_ERR_UNIMPLEMENTED;
+    if (c->broken) return HULL2D_ERR_DEVICE;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->n = h_offsets[S];
+    }
+    h_out_offsets[0] = 0;
+    if (S == 0) return HULL2D_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    const int64_t N = h_offsets[S];
+    hull2d_status st = ensure_batch(c, N, S);
+    if (st != HULL2D_OK) return st;
+    if (c->batch_grid == 0) c->batch_grid = c->cu_count * std::max(1, batch_blocks_per_cu());
+    hipStream_t s = c->stream;
+
+    // largest sets first (by size class: the schedule only needs it roughly)
+    std::memcpy(c->hb_offs, h_offsets, (size_t)(S + 1) * sizeof(int64_t));
+    {
+        int32_t cnt[64] = {0};
+        auto cls = [&](int32_t i) {
+            const int64_t n = h_offsets[i + 1] - h_offsets[i];
+            return 63 - (n > 0 ? __builtin_clzll((unsigned long long)n) : 63);
+        };
+        for (int32_t i = 0; i < S; ++i) ++cnt[cls(i)];
+        int32_t pos[64];
+        int32_t acc = 0;
+        for (int k = 63; k >= 0; --k) {
+            pos[k] = acc;
+            acc += cnt[k];
+        }
+        for (int32_t i = 0; i < S; ++i) c->hb_order[pos[cls(i)]++] = i;
+    }
+    if (c->have_events) HX_TRY(hipEventRecord(c->ev[HULL2D_NUM_STAGES], s));
+    HX_TRY(hipMemcpyAsync(c->b_offs, c->hb_offs, (size_t)(S + 1) * 8, hipMemcpyHostToDevice, s));
+    HX_TRY(hipMemcpyAsync(c->b_order, c->hb_order, (size_t)S * 4, hipMemcpyHostToDevice, s));
+    HX_TRY(hipMemsetAsync(c->b_meta, 0, 4, s));
+    int32_t* d_count = c->b_meta + 1;
+    int32_t* d_start = d_count + S;
+    uint32_t* d_flags = (uint32_t*)(d_start + S);
+    HX_TRY(launch_batch(reinterpret_cast<const double2*>(d_xy), c->b_offs, c->b_order, S, c->b_sv_xy,
+                        c->b_sv_idx, c->b_sv_key, c->b_cd_xy, c->b_cd_idx, c->b_cd_key, c->b_ka,
+                        c->b_kb, c->b_va, c->b_vb, c->b_flag, c->b_hull, (uint32_t*)c->b_meta,
+                        d_count, d_start, d_flags, c->ctr, c->batch_grid, s));
+    HX_TRY(hipMemcpyAsync(c->hb_meta, c->b_meta, (size_t)(3 * S + 1) * 4, hipMemcpyDeviceToHost, s));
+    HX_TRY(spin_sync(c));
+    const int32_t* cnt = c->hb_meta + 1;
+    const int32_t* start = cnt + S;
+    const uint32_t* flags = (const uint32_t*)(start + S);
+    uint32_t any = 0;
+    for (int32_t i = 0; i < S; ++i) any |= flags[i];
+    if (any & kFlagNonfinite) return HULL2D_ERR_NONFINITE;
+    if (any & kFlagRange) return HULL2D_ERR_RANGE;
+    const int64_t total = (int64_t)(uint32_t)c->hb_meta[0];
+    st = ensure_batch_hull(c, total);
+    if (st != HULL2D_OK) return st;
+    if (total > 0) {
+        HX_TRY(hipMemcpyAsync(c->hb_hull, c->b_hull, (size_t)total * 4, hipMemcpyDeviceToHost, s));
+    }
+    if (c->have_events) HX_TRY(hipEventRecord(c->ev[HULL2D_NUM_STAGES + 1], s));
+    HX_TRY(spin_sync(c));
+    float ms_dev = 0.f;
+    if (c->have_events) (void)hipEventElapsedTime(&ms_dev, c->ev[HULL2D_NUM_STAGES], c->ev[HULL2D_NUM_STAGES + 1]);
+
+    // sets the workgroups left to the single-hull path
+    std::vector<std::pair<int32_t, std::vector<int32_t>>> side;
+    if (any & kBatchFallback) {
+        for (int32_t i = 0; i < S; ++i) {
+            if (!(flags[i] & kBatchFallback)) continue;
+            const int64_t n = h_offsets[i + 1] - h_offsets[i];
+            std::vector<int32_t> hv((size_t)std::max<int64_t>(n, 1));
+            int64_t h = 0;
+            st = hull2d_compute(c, d_xy + 2 * h_offsets[i], n, hv.data(), (int64_t)hv.size(), &h,
+                                nullptr);
+            if (st != HULL2D_OK) return st;
+            hv.resize((size_t)h);
+            side.emplace_back(i, std::move(hv));
+        }
+    }
+    size_t si = 0;
+    int64_t need = 0;
+    for (int32_t i = 0; i < S; ++i) {
+        int64_t h = cnt[i];
+        if (si < side.size() && side[si].first == i) h = (int64_t)side[si++].second.size();
+        need += h;
+        h_out_offsets[i + 1] = need;
+    }
+    if (need > cap) {
+        if (stats) stats->ms_total = ms_since(t_start);
+        return HULL2D_ERR_CAPACITY;
+    }
+    si = 0;
+    for (int32_t i = 0; i < S; ++i) {
+        int32_t* dst = h_out + h_out_offsets[i];
+        if (si < side.size() && side[si].first == i) {
+            const std::vector<int32_t>& hv = side[si++].second;
+            if (!hv.empty()) std::memcpy(dst, hv.data(), hv.size() * 4);
+        } else if (cnt[i] > 0) {
+            std::memcpy(dst, c->hb_hull + start[i], (size_t)cnt[i] * 4);
+        }
+    }
+    if (stats) {
+        stats->n_hull = need;
+        stats->n_candidates = (int64_t)side.size();  // sets finished on the host
+        stats->ms_device = ms_dev;
+        stats->ms_total = ms_since(t_start);
+    }
+    return HULL2D_OK;
 }
 
 hull2d_status hull2d_debug_orient(hull2d_ctx* c, const double* d_abc, int64_t count, int32_t* d_out) {

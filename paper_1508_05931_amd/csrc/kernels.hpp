@@ -30,6 +30,7 @@ constexpr int kRunCap = 2048;                    // longest run one workgroup so
 constexpr int kHistGridMax = 512;
 constexpr int kTailBlock = 1024;                 // the one-workgroup tail
 constexpr int kTailCap = 12288;                  // candidates per region it sorts in LDS
+constexpr int kBatchBlock = 512;                 // threads per set in the batched kernel
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -98,6 +99,21 @@ hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, con
 hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
                        const Params* prm, DevStatus* ds2, double2* out_xy, int32_t* out_idx,
                        uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s);
+// The batched form: one persistent launch, each workgroup computing whole
+// hulls of the sets in `order` (device, S entries); per set s, its points are
+// xy[offs[s], offs[s+1]) and its workspace the same range of every array.
+// Output: hull[h_start[s] ..+ h_count[s]] (set-local indices, canonical),
+// h_flags[s] (kFlagNonfinite / kFlagRange, or 4 = finish on the host);
+// hull_cursor must be 0 at launch.
+hipError_t launch_batch(const double2* xy, const int64_t* offs, const int32_t* order, int32_t S,
+                        double2* sv_xy, uint32_t* sv_idx, uint32_t* sv_key, double2* cd_xy,
+                        uint32_t* cd_idx, uint32_t* cd_key, uint32_t* ka, uint32_t* kb,
+                        uint32_t* va, uint32_t* vb, uint8_t* flag, int32_t* hull,
+                        uint32_t* hull_cursor, int32_t* h_count, int32_t* h_start,
+                        uint32_t* h_flags, Counters* ctr, int grid, hipStream_t s);
+int batch_blocks_per_cu();
+constexpr uint32_t kBatchFallback = 4u;
+
 hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, uint32_t* prefix,
                               DevStatus* ds2, hipStream_t s);
 hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,

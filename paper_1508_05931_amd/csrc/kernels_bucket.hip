@@ -20,6 +20,7 @@
 // scanned by the same kernels as the full problem.
 #include "exact.hpp"
 #include "kernels.hpp"
+#include "steps.hpp"
 
 namespace hx {
 namespace {
@@ -29,40 +30,6 @@ constexpr int kPfBlock = 256;
 constexpr int kPfItems = 4;    // points loaded per thread before any is used
 constexpr int kPfCap = 4096;   // LDS slots buffered per block before a flush
 constexpr int kBmItems = 4;
-
-struct Cls {
-    int region;      // 0 right of P_l, 1 left of P_l, 2 P_l or a copy of it
-    uint32_t kappa;  // direction key in the region's order (larger follows)
-    uint32_t bucket;
-};
-
-// Region by the exact angular order (angle key first, orientation on equal
-// keys, distance along the ray on the same ray), then the direction key.
-__device__ inline Cls classify(double x, double y, uint32_t key, const Params& P) {
-    Cls c;
-    c.bucket = key >> (32 - kBucketBits);
-    c.kappa = 0;
-    if (x == P.lx && y == P.ly) {
-        c.region = 2;
-        return c;
-    }
-    int region;
-    if (key < P.kl) {
-        region = 0;
-    } else if (key > P.kl) {
-        region = 1;
-    } else {
-        int o = orient(P.x0, P.y0, P.lx, P.ly, x, y);
-        if (o != 0) region = o < 0 ? 0 : 1;
-        else region = (y < P.ly || (y == P.ly && x < P.lx)) ? 0 : 1;
-    }
-    uint32_t F = turn_key(x, y, P.lx, P.ly);
-    // right region: counter-clockwise from P_0 - P_l; left region: clockwise
-    // from P_l - P_0 (the key is reversed so that larger always follows)
-    c.kappa = region == 0 ? F - P.turn_u : 0xFFFFFFFFu - (F - P.turn_v);
-    c.region = region;
-    return c;
-}
 
 __device__ inline Params load_params(const Params* __restrict__ prm) { return *prm; }
 

@@ -20,6 +20,7 @@
 
 #include "exact.hpp"
 #include "kernels.hpp"
+#include "steps.hpp"
 
 namespace hx {
 namespace {
@@ -86,82 +87,6 @@ __device__ uint32_t lookback_sum(uint64_t* stat, uint32_t t, uint32_t agg, uint3
 // ---------------------------------------------------------------------------
 // Step 1
 // ---------------------------------------------------------------------------
-// Strict total orders of the four extreme criteria (ties: P_minx -> larger y,
-// P_miny -> smaller x, P_maxx -> smaller y, P_maxy -> larger x, then smaller
-// index), so every reduction order returns the same candidates.
-//
-// These comparisons and the selections that use them are written with
-// bitwise operators and explicit per-field selects: with short-circuit
-// conditions guarding a whole-struct copy, the gfx950 code generator of this
-// toolchain kept the old index on the tie path (wrong Step-1 corners on
-// grid inputs).  Straight-line code avoids that shape.
-template <int C>
-__device__ inline bool better(const Cand& a, const Cand& b) {
-    const double a1 = (C == 0 || C == 2) ? a.x : a.y, b1 = (C == 0 || C == 2) ? b.x : b.y;
-    const double a2 = (C == 0 || C == 2) ? a.y : a.x, b2 = (C == 0 || C == 2) ? b.y : b.x;
-    // primary: smaller for P_minx / P_miny, larger for P_maxx / P_maxy;
-    // secondary: larger for P_minx / P_maxy, smaller for P_miny / P_maxx
-    const bool p_win = (C <= 1) ? (a1 < b1) : (a1 > b1);
-    const bool s_win = (C == 0 || C == 3) ? (a2 > b2) : (a2 < b2);
-    const bool p_eq = a1 == b1, s_eq = a2 == b2, i_win = a.i < b.i;
-    return p_win | (p_eq & (s_win | (s_eq & i_win)));
-}
-
-__device__ inline Cand sentinel(int c) {
-    Cand s;
-    s.i = INT32_MAX;
-    s.pad = 0;
-    s.x = (c == 0 || c == 1) ? INFINITY : -INFINITY;
-    s.y = (c == 1 || c == 2) ? INFINITY : -INFINITY;
-    return s;
-}
-
-__device__ inline Cand shfl_xor_cand(const Cand& c, int m) {
-    Cand r;
-    r.x = __shfl_xor(c.x, m);
-    r.y = __shfl_xor(c.y, m);
-    r.i = __shfl_xor(c.i, m);
-    r.pad = 0;
-    return r;
-}
-
-template <int C>
-__device__ inline void take_better(Cand& c, const Cand& o) {
-    const bool t = better<C>(o, c);
-    c.x = t ? o.x : c.x;
-    c.y = t ? o.y : c.y;
-    c.i = t ? o.i : c.i;
-}
-
-__device__ inline void reduce4_wave(Cand (&c)[4]) {
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) {
-        take_better<0>(c[0], shfl_xor_cand(c[0], m));
-        take_better<1>(c[1], shfl_xor_cand(c[1], m));
-        take_better<2>(c[2], shfl_xor_cand(c[2], m));
-        take_better<3>(c[3], shfl_xor_cand(c[3], m));
-    }
-}
-
-__device__ inline uint32_t domain_flags(double v) {
-    double a = fabs(v);
-    if (!(a <= DBL_MAX)) return kFlagNonfinite;
-    if (a != 0.0 && (a < 0x1p-300 || a > 0x1p300)) return kFlagRange;
-    return 0u;
-}
-
-__device__ inline void offer(Cand (&c)[4], double x, double y, int32_t i) {
-    Cand p;
-    p.x = x;
-    p.y = y;
-    p.i = i;
-    p.pad = 0;
-    take_better<0>(c[0], p);
-    take_better<1>(c[1], p);
-    take_better<2>(c[2], p);
-    take_better<3>(c[3], p);
-}
-
 __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restrict__ xy, int64_t n,
                                                         Cand* __restrict__ partial) {
     constexpr int NW = kExtBlock / 64;
@@ -250,48 +175,7 @@ __global__ __launch_bounds__(256) void k_extremes_final(const Cand* __restrict__
         take_better<2>(e[2], s_c[w][2]);
         take_better<3>(e[3], s_c[w][3]);
     }
-    Params P;
-    for (int k = 0; k < 4; ++k) {
-        e[k].pad = 0;
-        P.ext[k] = e[k];
-    }
-    int nc = 0;
-    for (int k = 0; k < 4; ++k) {
-        bool dup = false;
-        for (int j = 0; j < nc; ++j) dup |= (P.qx[j] == e[k].x && P.qy[j] == e[k].y);
-        if (!dup) {
-            P.qx[nc] = e[k].x;
-            P.qy[nc] = e[k].y;
-            ++nc;
-        }
-    }
-    for (int j = nc; j < 4; ++j) {
-        P.qx[j] = P.qx[0];
-        P.qy[j] = P.qy[0];
-    }
-    for (int j = 0; j < 4; ++j) {
-        int j1 = (j + 1) % (nc > 0 ? nc : 1);
-        P.ex[j] = P.qx[j1] - P.qx[j];
-        P.ey[j] = P.qy[j1] - P.qy[j];
-    }
-    // Every point and corner lies in the bounding box W x H, so for an edge
-    // test ex*dy - ey*dx (four rounded differences, two rounded products, one
-    // rounded difference) |ex dy| + |ey dx| <= 2WH and the rounding error is
-    // below 4.01 eps * 2WH; 9 eps W H also covers the rounding of W and H.
-    double W = e[2].x - e[0].x, H = e[3].y - e[1].y;
-    P.qbound = 9.0 * kEps * W * H;
-    P.ncorner = nc;
-    P.x0 = e[1].x;
-    P.y0 = e[1].y;
-    P.p0_idx = e[1].i;
-    P.flags = s_flags;
-    P.pad = 0;
-    P.lx = P.x0;
-    P.ly = P.y0;
-    P.l_idx = -1;
-    P.kl = 0;
-    P.turn_u = P.turn_v = 0;
-    P.pad2[0] = P.pad2[1] = 0;
+    const Params P = make_params(e, s_flags);
     *prm = P;
     DevStatus S;
     S.flags = s_flags;
@@ -370,33 +254,14 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
             key[k] = 0;
             if (pos < end && !discard_all) {
                 const double px = p[k].x, py = p[k].y;
-                bool inside = nc >= 3;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (inside && j < nc) {
-                        double dx = px - qx[j], dy = py - qy[j];
-                        double l = ex[j] * dy;
-                        double r = ey[j] * dx;
-                        double det = l - r;
-                        int o = det > qb ? 1 : (-det > qb ? -1 : 0);
-                        if (o == 0) {
-                            int j1 = (j + 1) % nc;
-                            o = orient(qx[j], qy[j], qx[j1], qy[j1], px, py);
-                        }
-                        inside = o > 0;
-                    }
-                }
-                surv = !inside;
+                surv = !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
                 if (surv && px == x0 && py == y0) {
                     surv = false;
                     ++p0c;
                 }
                 if (surv) {
                     key[k] = angle_key(px, py, x0, y0);
-                    double dx = px - x0, dy = py - y0;
-                    double dxx = dx * dx;
-                    double dyy = dy * dy;
-                    double d2 = dxx + dyy;
+                    const double d2 = dist2(px, py, x0, y0);
                     const bool take = (d2 > td2) | ((d2 == td2) & ((uint32_t)pos < tidx));
                     td2 = take ? d2 : td2;
                     tidx = take ? (uint32_t)pos : tidx;

@@ -1,0 +1,214 @@
+// steps.hpp - per-point pieces of Steps 1-3 and 5-7 shared by the
+// single-hull kernels and the batched kernel.
+#pragma once
+
+#include <float.h>
+
+#include "common.hpp"
+#include "exact.hpp"
+
+namespace hx {
+
+// ---------------------------------------------------------------------------
+// Step 1
+// ---------------------------------------------------------------------------
+// Strict total orders of the four extreme criteria (ties: P_minx -> larger y,
+// P_miny -> smaller x, P_maxx -> smaller y, P_maxy -> larger x, then smaller
+// index), so every reduction order returns the same candidates.
+//
+// These comparisons and the selections that use them are written with
+// bitwise operators and explicit per-field selects: with short-circuit
+// conditions guarding a whole-struct copy, the gfx950 code generator of this
+// toolchain kept the old index on the tie path (wrong Step-1 corners on
+// grid inputs).  Straight-line code avoids that shape.
+template <int C>
+__device__ inline bool better(const Cand& a, const Cand& b) {
+    const double a1 = (C == 0 || C == 2) ? a.x : a.y, b1 = (C == 0 || C == 2) ? b.x : b.y;
+    const double a2 = (C == 0 || C == 2) ? a.y : a.x, b2 = (C == 0 || C == 2) ? b.y : b.x;
+    // primary: smaller for P_minx / P_miny, larger for P_maxx / P_maxy;
+    // secondary: larger for P_minx / P_maxy, smaller for P_miny / P_maxx
+    const bool p_win = (C <= 1) ? (a1 < b1) : (a1 > b1);
+    const bool s_win = (C == 0 || C == 3) ? (a2 > b2) : (a2 < b2);
+    const bool p_eq = a1 == b1, s_eq = a2 == b2, i_win = a.i < b.i;
+    return p_win | (p_eq & (s_win | (s_eq & i_win)));
+}
+
+__device__ inline Cand sentinel(int c) {
+    Cand s;
+    s.i = INT32_MAX;
+    s.pad = 0;
+    s.x = (c == 0 || c == 1) ? INFINITY : -INFINITY;
+    s.y = (c == 1 || c == 2) ? INFINITY : -INFINITY;
+    return s;
+}
+
+__device__ inline Cand shfl_xor_cand(const Cand& c, int m) {
+    Cand r;
+    r.x = __shfl_xor(c.x, m);
+    r.y = __shfl_xor(c.y, m);
+    r.i = __shfl_xor(c.i, m);
+    r.pad = 0;
+    return r;
+}
+
+template <int C>
+__device__ inline void take_better(Cand& c, const Cand& o) {
+    const bool t = better<C>(o, c);
+    c.x = t ? o.x : c.x;
+    c.y = t ? o.y : c.y;
+    c.i = t ? o.i : c.i;
+}
+
+__device__ inline void reduce4_wave(Cand (&c)[4]) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        take_better<0>(c[0], shfl_xor_cand(c[0], m));
+        take_better<1>(c[1], shfl_xor_cand(c[1], m));
+        take_better<2>(c[2], shfl_xor_cand(c[2], m));
+        take_better<3>(c[3], shfl_xor_cand(c[3], m));
+    }
+}
+
+__device__ inline uint32_t domain_flags(double v) {
+    double a = fabs(v);
+    if (!(a <= DBL_MAX)) return kFlagNonfinite;
+    if (a != 0.0 && (a < 0x1p-300 || a > 0x1p300)) return kFlagRange;
+    return 0u;
+}
+
+__device__ inline void offer(Cand (&c)[4], double x, double y, int32_t i) {
+    Cand p;
+    p.x = x;
+    p.y = y;
+    p.i = i;
+    p.pad = 0;
+    take_better<0>(c[0], p);
+    take_better<1>(c[1], p);
+    take_better<2>(c[2], p);
+    take_better<3>(c[3], p);
+}
+
+// The quadrilateral of Step 2 and the pivot from the four extreme points:
+// distinct corners in the order P_minx -> P_miny -> P_maxx -> P_maxy
+// (counter-clockwise), their edge vectors and one error bound for every edge
+// test.  Step-5 fields start empty.
+__device__ inline Params make_params(const Cand (&e)[4], uint32_t flags) {
+    Params P;
+    for (int k = 0; k < 4; ++k) {
+        P.ext[k] = e[k];
+        P.ext[k].pad = 0;
+    }
+    int nc = 0;
+    for (int k = 0; k < 4; ++k) {
+        bool dup = false;
+        for (int j = 0; j < nc; ++j) dup |= (P.qx[j] == e[k].x && P.qy[j] == e[k].y);
+        if (!dup) {
+            P.qx[nc] = e[k].x;
+            P.qy[nc] = e[k].y;
+            ++nc;
+        }
+    }
+    for (int j = nc; j < 4; ++j) {
+        P.qx[j] = P.qx[0];
+        P.qy[j] = P.qy[0];
+    }
+    for (int j = 0; j < 4; ++j) {
+        int j1 = (j + 1) % (nc > 0 ? nc : 1);
+        P.ex[j] = P.qx[j1] - P.qx[j];
+        P.ey[j] = P.qy[j1] - P.qy[j];
+    }
+    // Every point and corner lies in the bounding box W x H, so for an edge
+    // test ex*dy - ey*dx (four rounded differences, two rounded products, one
+    // rounded difference) |ex dy| + |ey dx| <= 2WH and the rounding error is
+    // below 4.01 eps * 2WH; 9 eps W H also covers the rounding of W and H.
+    double W = e[2].x - e[0].x, H = e[3].y - e[1].y;
+    P.qbound = 9.0 * kEps * W * H;
+    P.ncorner = nc;
+    P.x0 = e[1].x;
+    P.y0 = e[1].y;
+    P.p0_idx = e[1].i;
+    P.flags = flags;
+    P.pad = 0;
+    P.lx = P.x0;
+    P.ly = P.y0;
+    P.l_idx = -1;
+    P.kl = 0;
+    P.turn_u = P.turn_v = 0;
+    P.pad2[0] = P.pad2[1] = 0;
+    return P;
+}
+
+// ---------------------------------------------------------------------------
+// Step 2: strictly inside the quadrilateral (strictly left of every edge of
+// the distinct corners; fewer than 3 distinct corners: never).  The float64
+// edge test is decided by the common bound qbound, else exactly.
+// ---------------------------------------------------------------------------
+__device__ inline bool quad_inside(const double (&qx)[4], const double (&qy)[4],
+                                   const double (&ex)[4], const double (&ey)[4], double qb,
+                                   int nc, double px, double py) {
+    bool inside = nc >= 3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (inside && j < nc) {
+            double dx = px - qx[j], dy = py - qy[j];
+            double l = ex[j] * dy;
+            double r = ey[j] * dx;
+            double det = l - r;
+            int o = det > qb ? 1 : (-det > qb ? -1 : 0);
+            if (o == 0) {
+                int j1 = (j + 1) % nc;
+                o = orient(qx[j], qy[j], qx[j1], qy[j1], px, py);
+            }
+            inside = o > 0;
+        }
+    }
+    return inside;
+}
+
+// Step 5's distance (a heuristic choice; only needs to be reproducible):
+// fl(fl(dx*dx) + fl(dy*dy)) with dx = fl(x - x0), dy = fl(y - y0).
+__device__ inline double dist2(double px, double py, double x0, double y0) {
+    double dx = px - x0, dy = py - y0;
+    double dxx = dx * dx;
+    double dyy = dy * dy;
+    return dxx + dyy;
+}
+
+// ---------------------------------------------------------------------------
+// Steps 6-7, bucketed: region and direction key of a round-1 survivor
+// ---------------------------------------------------------------------------
+struct Cls {
+    int region;      // 0 right of P_l, 1 left of P_l, 2 P_l or a copy of it
+    uint32_t kappa;  // direction key in the region's order (larger follows)
+    uint32_t bucket;
+};
+
+// Region by the exact angular order (angle key first, orientation on equal
+// keys, distance along the ray on the same ray), then the direction key.
+__device__ inline Cls classify(double x, double y, uint32_t key, const Params& P) {
+    Cls c;
+    c.bucket = key >> (32 - kBucketBits);
+    c.kappa = 0;
+    if (x == P.lx && y == P.ly) {
+        c.region = 2;
+        return c;
+    }
+    int region;
+    if (key < P.kl) {
+        region = 0;
+    } else if (key > P.kl) {
+        region = 1;
+    } else {
+        int o = orient(P.x0, P.y0, P.lx, P.ly, x, y);
+        if (o != 0) region = o < 0 ? 0 : 1;
+        else region = (y < P.ly || (y == P.ly && x < P.lx)) ? 0 : 1;
+    }
+    uint32_t F = turn_key(x, y, P.lx, P.ly);
+    // right region: counter-clockwise from P_0 - P_l; left region: clockwise
+    // from P_l - P_0 (the key is reversed so that larger always follows)
+    c.kappa = region == 0 ? F - P.turn_u : 0xFFFFFFFFu - (F - P.turn_v);
+    c.region = region;
+    return c;
+}
+
+}  // namespace hx

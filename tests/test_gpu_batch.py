@@ -1,0 +1,188 @@
+"""GPU parity of the batched form (hull2d_batch) against the CPU oracle.
+
+Every set's hull must equal the monotone-chain oracle's hull of that set, bit
+for bit (set-local indices, canonical order).  Covers empty and one-point
+sets, duplicates, collinear sets (including one whose equal-key run is too
+long for the workgroup sorter, finished by the single-hull path), grids,
+thin annuli whose second round keeps most points (the device Graham scan's
+chunk reduction), and the 4096-set workload against an oracle-written hash.
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden", "batch.json")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hx(torch_dev):
+    import paper_1508_05931_amd as hx
+    return hx
+
+
+@pytest.fixture(scope="module")
+def ctx(hx):
+    return hx.Hull2D()
+
+
+def _mixed_sets():
+    t = np.arange(-700, 800, dtype=np.float64)
+    rng = np.random.default_rng(11)
+    sets = [
+        np.zeros((0, 2)),
+        np.array([[0.25, -0.5]]),
+        np.array([[1.0, 1.0], [1.0, 1.0]]),
+        np.array([[1.0, 3.0], [-1.0, 2.0]]),
+        np.array([[0.0, 0.0], [2.0, 2.0], [1.0, 1.0]]),
+        np.full((300, 2), 0.375),
+        np.stack([t, 2 * t - 5], axis=1)[rng.permutation(1500)],
+        np.repeat(np.stack([t[:40], -t[:40]], axis=1), 3, axis=0),
+        # one ray from the pivot holds 10,000 points: a run of equal keys
+        # longer than the workgroup sorter takes
+        np.stack([np.arange(10_000.0), 0.5 * np.arange(10_000.0) + 3.0], axis=1)[rng.permutation(10_000)],
+        synth.grid(40, 3, (81, 1)),
+        synth.grid_draws(20_000, 16, (82, 1)),
+        np.concatenate([np.full((500, 2), 0.25), synth.square(300, (83, 1)),
+                        np.full((300, 2), 1.0)])[rng.permutation(1100)],
+        synth.ngon(2048, 9, (84, 1)),
+    ]
+    for i, n in enumerate([64, 100, 1000, 4097, 20_000, 70_000]):
+        sets.append(synth.square(n, (90 + i, 1)))
+        sets.append(synth.disk(n, (100 + i, 1)))
+        sets.append(synth.gaussian(n, 1.0, (110 + i, 1)))
+        sets.append(synth.annulus(n, 0.999, (120 + i, 1)))
+    sets.append(synth.annulus(150_000, 0.999, (130, 1)))
+    sets.append(synth.mixture(50_000, (131, 1)))
+    return sets
+
+
+def _concat(sets):
+    offs = np.zeros(len(sets) + 1, dtype=np.int64)
+    np.cumsum([len(s) for s in sets], out=offs[1:])
+    pts = np.concatenate([np.asarray(s, dtype=np.float64).reshape(-1, 2) for s in sets])
+    return np.ascontiguousarray(pts), offs
+
+
+def _check_all(hulls, out_offs, sets):
+    for i, s in enumerate(sets):
+        got = hulls[out_offs[i]:out_offs[i + 1]]
+        want = oracle.hull(np.ascontiguousarray(s, dtype=np.float64).reshape(-1, 2))
+        assert got.tolist() == want.tolist(), f"set {i} (n={len(s)})"
+
+
+def test_batch_mixed_sets(torch_dev, ctx):
+    sets = _mixed_sets()
+    pts, offs = _concat(sets)
+    say(f"batch mixed S={len(sets)} N={len(pts)}")
+    d = torch_dev.from_numpy(pts).cuda()
+    hulls, out_offs = ctx.batch(d, offs)
+    _check_all(hulls, out_offs, sets)
+    assert ctx.last_stats.n_candidates >= 1  # the long collinear run went to the host
+
+
+def test_batch_equals_compute(torch_dev, ctx):
+    """The batched result equals hull2d_compute set by set."""
+    sets = [synth.batch_set(int(n), 500 + i)[0] for i, n in enumerate([77, 3000, 12_345, 40_000])]
+    pts, offs = _concat(sets)
+    say("batch vs compute")
+    d = torch_dev.from_numpy(pts).cuda()
+    hulls, out_offs = ctx.batch(d, offs)
+    for i, s in enumerate(sets):
+        one = ctx.compute(torch_dev.from_numpy(np.ascontiguousarray(s)).cuda())
+        assert hulls[out_offs[i]:out_offs[i + 1]].tolist() == one.tolist()
+
+
+def test_batch_repeat_and_shrink(torch_dev, ctx):
+    """Two calls in a row, the second smaller, give the oracle's hulls."""
+    for S, seed in [(300, 1), (40, 2)]:
+        sizes = synth.batch_sizes(S, 64.0, 20_000.0, 900 + seed)
+        sets = [synth.batch_set(int(n), k, 900 + seed)[0] for k, n in enumerate(sizes)]
+        pts, offs = _concat(sets)
+        say(f"batch S={S}")
+        hulls, out_offs = ctx.batch(torch_dev.from_numpy(pts).cuda(), offs)
+        _check_all(hulls, out_offs, sets)
+
+
+def test_batch_errors(torch_dev, ctx):
+    import paper_1508_05931_amd as hx
+    sets = [synth.square(100, (140, 1)), synth.square(100, (141, 1))]
+    sets[1][7, 0] = np.nan
+    pts, offs = _concat(sets)
+    say("batch nonfinite")
+    with pytest.raises(hx.HullError) as e:
+        ctx.batch(torch_dev.from_numpy(pts).cuda(), offs)
+    assert e.value.status == hx.NONFINITE
+    sets[1][7, 0] = 2.0 ** 400
+    pts, offs = _concat(sets)
+    with pytest.raises(hx.HullError) as e:
+        ctx.batch(torch_dev.from_numpy(pts).cuda(), offs)
+    assert e.value.status == hx.RANGE
+    # no sets at all
+    h, o = ctx.batch(torch_dev.zeros((0, 2), dtype=torch_dev.float64, device="cuda"),
+                     np.zeros(1, dtype=np.int64))
+    assert len(h) == 0 and o.tolist() == [0]
+
+
+def test_batch_capacity(torch_dev, hx):
+    """A too-small output buffer: CAPACITY, offsets written, then a retry."""
+    import ctypes
+    c = hx.Hull2D()
+    sets = [synth.disk(5000, (150, 1)), synth.square(3000, (151, 1))]
+    pts, offs = _concat(sets)
+    d = torch_dev.from_numpy(pts).cuda()
+    out = np.empty(4, dtype=np.int32)
+    oo = np.zeros(3, dtype=np.int64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    st = c._lib.hull2d_batch(c._h, ctypes.c_void_p(d.data_ptr()), offs.ctypes.data_as(i64p), 2,
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 4,
+                             oo.ctypes.data_as(i64p), None)
+    assert st == hx.CAPACITY
+    want = [oracle.hull(s) for s in sets]
+    assert oo.tolist() == [0, len(want[0]), len(want[0]) + len(want[1])]
+    hulls, out_offs = c.batch(d, offs)
+    _check_all(hulls, out_offs, sets)
+    c.close()
+
+
+def test_batch_4096_sets_golden(torch_dev, ctx):
+    """The 4096-set workload (sizes log-uniform in [64, 200000], four
+    distributions): hash of all hulls against the oracle's, and a sample of
+    sets compared one by one."""
+    with open(GOLDEN) as f:
+        g = json.load(f)["batch_4096"]
+    pts, offs, kinds = synth.batch(4096)
+    assert synth.content_hash(pts) == g["input_hash"]
+    say(f"batch 4096 sets N={len(pts)}")
+    d = torch_dev.from_numpy(pts).cuda()
+    hulls, out_offs = ctx.batch(d, offs)
+    assert out_offs.tolist()[-1] == g["total"]
+    assert hashlib.sha256(np.ascontiguousarray(out_offs, dtype="<i8").tobytes()).hexdigest() == g["offsets_sha256"]
+    assert hashlib.sha256(np.ascontiguousarray(hulls, dtype="<i4").tobytes()).hexdigest() == g["sha256"]
+    rng = np.random.default_rng(5)
+    sizes = np.diff(offs)
+    pick = list(rng.choice(4096, 24, replace=False)) + list(np.argsort(sizes)[-4:])
+    for i in pick:
+        s = pts[offs[i]:offs[i + 1]]
+        assert hulls[out_offs[i]:out_offs[i + 1]].tolist() == oracle.hull(s).tolist()
