@@ -27,6 +27,48 @@ HBM_PEAK_GBPS = 8000.0
 # (GeForce GT 640, Tables 3 and 5): 446.4 ms (square) + 418.1 ms (disk).
 PAPER_MS_SQUARE_DISK_20M = 446.4 + 418.1
 
+# HBM traffic of one launch from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0, the factors a plain 320 MB copy gives), averaged over the
+# square and disk launches, with the SHA-256 of every source the kernel is
+# built from: once a source differs, the figure no longer describes the
+# kernel and `traffic` is null.
+TRAFFIC = {
+    "filter1": {
+        "bytes": 536_100_000,  # 320.4 MB fetched + 215.7 MB written
+        "profile": "profiles/hull_square_disk_20M_hbm_counters.md",
+        "sources": {
+            "paper_1508_05931_amd/csrc/kernels_filter.hip":
+                "6d2bed648f1220833fa5592e48d70ea88506fe658c821c2d513b85088399c42c",
+            "paper_1508_05931_amd/csrc/steps.hpp":
+                "061f425d5156acfaf0ca11853ad0fb47c35a5629c30b912c2a3fd083b79f16af",
+            "paper_1508_05931_amd/csrc/exact.hpp":
+                "7f48b015bed6a41be070153b2472d7c7a215c3cd311bae3684ba9262af659081",
+            "paper_1508_05931_amd/csrc/common.hpp":
+                "4b00ea1c65565b2f7b09d40210d031a8dab3a8f1a246b9c63af7da04fd0e8bba",
+            "paper_1508_05931_amd/csrc/kernels.hpp":
+                "dd99bf4958ae94e05d64516fa831d1576e1fa45e5c583bc1d0ad7f0f9df2c21a",
+        },
+    },
+}
+
+
+def measured_traffic(kernel: str):
+    """Profiled HBM bytes per launch of `kernel`, or None when there is no
+    profile or the kernel's sources changed since it was taken."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    for rel, digest in t["sources"].items():
+        path = os.path.join(ROOT, rel)
+        if not os.path.exists(path):
+            return None
+        with open(path, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return t["bytes"]
+
+
 KERNEL_STAGES = ["extremes", "filter1", "longest", "buckets", "histogram", "sort0", "sort1",
                  "sort2", "sort3", "ties", "ties_long", "round2", "compact", "tail"]
 
@@ -71,6 +113,35 @@ def cpu_baseline(sets, sample_n: int):
                       f"{total_s:.1f} s on {platform.processor() or platform.machine()}"}
 
 
+def batched(steps: int):
+    """The batched form on 4096 independent sets (sizes log-uniform in
+    [64, 200000], squares, disks, Gaussians and thin annuli; 99.9M points),
+    inputs resident in HBM: one hull2d_batch call per step."""
+    import numpy as np
+    import torch
+    import paper_1508_05931_amd as hx
+    import synth
+    pts, offs, _ = synth.batch(4096)
+    d = torch.from_numpy(pts).cuda()
+    ctx = hx.Hull2D()
+    ctx.batch(d, offs)
+    torch.cuda.synchronize()
+    reps = max(3, steps // 4)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ctx.batch(d, offs)
+        ts.append(time.perf_counter() - t0)
+    st = ctx.last_stats
+    ms = float(np.median(ts)) * 1e3
+    ctx.close()
+    return {"workload": "4096 sets, sizes log-uniform 64..200000, 4 distributions",
+            "n_points": int(offs[-1]), "n_hull": int(st.n_hull), "reps": reps,
+            "ms_median": round(ms, 3), "ms_device": round(float(st.ms_device), 3),
+            "Mpoints_per_s": round(offs[-1] / (ms * 1e-3) / 1e6, 1),
+            "sets_on_host_path": int(st.n_candidates)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +154,8 @@ def main():
                     help="skip the extra timing of the full-sort mode")
     ap.add_argument("--cpu-sample", type=int, default=5_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the timing of the batched form (4096 sets)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 320 MB device buffer three times (reference for HBM "
                          "byte counters) and exit")
@@ -193,7 +266,10 @@ def main():
                    "candidates of the bucketed filter"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": measured_traffic(dom),
+                     "algorithmic_bytes": round(kern[dom]["bytes"]),
+                     "ms_per_launch": round(kern[dom]["ms"], 4)},
         "filter_sort": {"GBps_alg": round(fs_bytes / (fs_ms * 1e-3) / 1e9, 1),
                         "frac_of_peak": round(fs_bytes / (fs_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                         "bytes_alg_formula": "32n + 80*round1 + 20*round2"},
@@ -217,6 +293,8 @@ def main():
         out["full_sort"] = {"ms_per_step": round(fms, 4),
                             "Mpoints_per_s": round(n_total / (fms * 1e-3) / 1e6, 1)}
         fctx.close()
+    if not args.no_batch:
+        out["batched"] = batched(args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host, args.cpu_sample)
     print(json.dumps(out), flush=True)
