@@ -73,6 +73,11 @@ def _load():
         lib.oracle_model.argtypes = [dp, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.POINTER(_ModelResult)]
         lib.oracle_model.restype = ctypes.c_int
+        lib.oracle_learned_round1.argtypes = [dp, ctypes.c_int64, dp, ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_uint8),
+                                              ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_learned_round1.restype = ctypes.c_int
         lib.oracle_round2.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_round2.restype = ctypes.c_int
@@ -157,3 +162,23 @@ def model(xy, chunk: int = 0) -> dict:
         "round2": r2[:r.m2].copy(),
         "hull": hl[:r.h].copy(),
     }
+
+
+def learned_round1(xy, dirs) -> dict:
+    """First round with the learned discard polygon (see oracle.h): the
+    survivors (bool [n]), the candidate indices (the four Step-1 extremes, then
+    one per direction) and the survivor count."""
+    a = _points(xy)
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 2)
+    n, k = a.shape[0], d.shape[0]
+    keep = np.zeros(max(n, 1), dtype=np.uint8)
+    cand = np.zeros(k + 4, dtype=np.int32)
+    m1 = ctypes.c_int64(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = _load().oracle_learned_round1(a.ctypes.data_as(dp), n, d.ctypes.data_as(dp), k,
+                                       keep.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                       cand.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       ctypes.byref(m1))
+    if st != OK:
+        raise OracleError(st)
+    return {"keep": keep[:n].astype(bool), "cand": cand, "m1": int(m1.value)}

@@ -7,6 +7,7 @@
  */
 #include "oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -360,5 +361,62 @@ int oracle_model(const double* xy, int64_t n, int64_t chunk, oracle_model_result
     free(keep);
     free(stack);
     free(sxy);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned-filter variant of the first round (plain definition).            */
+/* ------------------------------------------------------------------------ */
+
+int oracle_learned_round1(const double* xy, int64_t n, const double* dirs, int32_t k,
+                          uint8_t* keep, int32_t* cand, int64_t* m1) {
+    int st = oracle_validate(xy, n);
+    if (st != ORACLE_OK) return st;
+    if (!keep || !m1 || k < 0 || k > 64 || (k > 0 && !dirs)) return ORACLE_BADARG;
+    for (int32_t j = 0; j < 2 * k; ++j)
+        if (!(fabs(dirs[j]) <= DBL_MAX)) return ORACLE_BADARG;
+    *m1 = 0;
+    if (n == 0) return ORACLE_OK;
+
+    /* candidates: the four extremes of Step 1, then one per direction */
+    int32_t c[68];
+    extremes(xy, n, c);
+    for (int32_t j = 0; j < k; ++j) {
+        const double ux = dirs[2 * j], uy = dirs[2 * j + 1];
+        int32_t best = 0;
+        double bv = fma(xy[0], ux, xy[1] * uy);
+        for (int64_t i = 1; i < n; ++i) {
+            double v = fma(xy[2 * i], ux, xy[2 * i + 1] * uy);
+            if (v > bv) { bv = v; best = (int32_t)i; }
+        }
+        c[4 + j] = best;
+    }
+    if (cand) memcpy(cand, c, (size_t)(4 + k) * sizeof(int32_t));
+
+    /* their exact convex hull, as coordinates */
+    int32_t nc = 4 + k;
+    double cxy[2 * 68];
+    for (int32_t j = 0; j < nc; ++j) {
+        cxy[2 * j] = xy[2 * (int64_t)c[j]];
+        cxy[2 * j + 1] = xy[2 * (int64_t)c[j] + 1];
+    }
+    int32_t hv[68];
+    int64_t h = 0;
+    st = oracle_hull(cxy, nc, hv, 68, &h);
+    if (st != ORACLE_OK) return st;
+
+    /* strictly left of every edge: discarded */
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int inside = h >= 3;
+        for (int64_t e = 0; e < h && inside; ++e) {
+            const int32_t a = hv[e], b = hv[(e + 1) % h];
+            inside = oracle_orient(cxy[2 * a], cxy[2 * a + 1], cxy[2 * b], cxy[2 * b + 1],
+                                   xy[2 * i], xy[2 * i + 1]) > 0;
+        }
+        keep[i] = inside ? 0 : 1;
+        cnt += keep[i];
+    }
+    *m1 = cnt;
     return ORACLE_OK;
 }

@@ -1,0 +1,130 @@
+"""Pins of the learned-filter oracle and of the network reference.
+
+The learned first round must keep every hull vertex, keep at least what the
+quadrilateral keeps, match a brute-force exact evaluation of its definition
+on small integer inputs, and give the closed-form survivor count on a
+regular polygon.  The network reference's gradient must match central
+finite differences, and its layers must reduce to the bias on zero weights.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp
+from tests.exact_ref import brute_hull, orient_q
+
+
+def _uniform_dirs(k=16, phase=0.0):
+    return [(math.cos(phase + 2 * math.pi * j / k), math.sin(phase + 2 * math.pi * j / k))
+            for j in range(k)]
+
+
+@pytest.mark.parametrize("name,seed", [("mixture", 1), ("disk", 2), ("square", 3), ("gauss", 4)])
+def test_learned_keeps_hull_and_is_inside_quad(name, seed):
+    gen = {"mixture": lambda: synth.mixture(30_000, (300 + seed, 1)),
+           "disk": lambda: synth.disk(30_000, (300 + seed, 1)),
+           "square": lambda: synth.square(30_000, (300 + seed, 1)),
+           "gauss": lambda: synth.gaussian(30_000, 1.0, (300 + seed, 1))}[name]
+    pts = gen()
+    rng = np.random.default_rng(seed)
+    q = oracle.model(pts)
+    h = oracle.hull(pts)
+    for dirs in (_uniform_dirs(), rng.normal(size=(16, 2)), np.ones((16, 2))):
+        r = oracle.learned_round1(pts, dirs)
+        assert r["keep"][h].all()                         # hull vertices always survive
+        assert np.all(~r["keep"] | q["round1_keep"])      # never more than the quadrilateral
+        assert r["m1"] == int(r["keep"].sum())
+        assert r["m1"] <= q["m1"]
+
+
+def test_learned_matches_brute_force_on_integer_points():
+    """Integer points and directions: every product is exact, so the argmax,
+    the hull of the candidates and the strict-inside test can be evaluated in
+    rational arithmetic independently."""
+    rng = np.random.default_rng(7)
+    for trial in range(40):
+        n = int(rng.integers(1, 60))
+        pts = rng.integers(-20, 21, size=(n, 2)).astype(np.float64)
+        k = int(rng.integers(0, 9))
+        dirs = rng.integers(-5, 6, size=(k, 2)).astype(np.float64)
+        r = oracle.learned_round1(pts, dirs)
+        # candidates: Step-1 extremes with their tie rules, then exact argmax
+        P = [(int(x), int(y)) for x, y in pts]
+        idx = range(n)
+        ext = [min(idx, key=lambda i: (P[i][0], -P[i][1], i)),
+               min(idx, key=lambda i: (P[i][1], P[i][0], i)),
+               min(idx, key=lambda i: (-P[i][0], P[i][1], i)),
+               min(idx, key=lambda i: (-P[i][1], -P[i][0], i))]
+        cand = ext + [min(idx, key=lambda i: (-(P[i][0] * int(ux) + P[i][1] * int(uy)), i))
+                      for ux, uy in dirs]
+        assert r["cand"].tolist() == cand
+        cpts = np.array([P[i] for i in cand], dtype=np.float64)
+        hv = brute_hull(cpts)                          # exact strict corners, CCW
+        for i in range(n):
+            inside = len(hv) >= 3 and all(
+                orient_q(cpts[hv[e]], cpts[hv[(e + 1) % len(hv)]], pts[i]) > 0
+                for e in range(len(hv)))
+            assert r["keep"][i] == (not inside), (trial, i)
+
+
+def test_learned_regular_polygon_closed_form():
+    """64 vertices of a regular polygon plus interior points; the 16
+    directions at multiples of 2 pi / 16 select every 4th vertex, the
+    polygon is the inscribed 16-gon, which holds every interior point of
+    radius below cos(pi/16): exactly the 64 vertices survive."""
+    th = 2 * np.pi * np.arange(64) / 64
+    ring = np.stack([np.cos(th), np.sin(th)], axis=1)
+    inner = synth.disk(5000, (310, 1)) * 0.9
+    pts = np.concatenate([ring, inner])
+    r = oracle.learned_round1(pts, _uniform_dirs())
+    assert sorted(r["cand"][4:].tolist()) == list(range(0, 64, 4))
+    assert r["m1"] == 64 and r["keep"][:64].all()
+
+
+def test_learned_degenerate_inputs():
+    one = np.array([[0.5, 0.5]])
+    assert oracle.learned_round1(one, _uniform_dirs())["m1"] == 1
+    line = np.stack([np.arange(50.0), 2 * np.arange(50.0)], axis=1)
+    assert oracle.learned_round1(line, _uniform_dirs())["m1"] == 50   # no polygon: keep all
+    with pytest.raises(oracle.OracleError):
+        oracle.learned_round1(one, [(float("nan"), 1.0)])
+
+
+def test_mlp_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    flat = rng.normal(scale=0.05, size=mlp.N_PARAMS)
+    x = rng.random(size=(3, mlp.N_IN)) * 2
+    t = rng.normal(size=(3, mlp.N_OUT))
+    g = mlp.grad(flat, x, t)
+    for j in rng.choice(mlp.N_PARAMS, 60, replace=False):
+        e = np.zeros_like(flat)
+        e[j] = 1e-6
+        fd = (mlp.loss(flat + e, x, t) - mlp.loss(flat - e, x, t)) / 2e-6
+        assert abs(fd - g[j]) <= 1e-6 + 1e-4 * abs(fd), (j, fd, g[j])
+
+
+def test_mlp_zero_weights_give_bias_and_bf16_rounding():
+    p = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
+    p["b3"] = np.arange(mlp.N_OUT, dtype=np.float64) - 7.5
+    y, _ = mlp.forward(mlp.pack(p), np.ones((2, mlp.N_IN)))
+    assert np.array_equal(y, np.tile(p["b3"], (2, 1)))
+    # bfloat16: 8 significant bits, ties to even
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, -3.140625], dtype=np.float32)
+    assert mlp.bf16(v).tolist() == [1.0, 1.0, 1.0 + 2 ** -6, 1.0, -3.140625]
+
+
+def test_histogram_definition():
+    pts = synth.square(65_536, (320, 1))
+    h = mlp.histogram(pts)
+    assert h.shape == (1024,) and abs(float(h.sum()) - 1024.0) < 1e-2
+    s = mlp.sample_index(65_536)
+    assert s.size == 4096 and s[0] == 0 and s[255] == 255 and s[256] == 4096
+    # the sample's four extreme coordinates land in the corner cells' rows / columns
+    q = pts[s]
+    assert h.reshape(32, 32)[:, 0].sum() > 0 and h.reshape(32, 32)[:, 31].sum() > 0
+    assert np.allclose(h.reshape(32, 32).sum(), 1024.0)
+    assert mlp.histogram(np.zeros((0, 2))).sum() == 0
