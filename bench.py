@@ -113,6 +113,38 @@ def cpu_baseline(sets, sample_n: int):
                       f"{total_s:.1f} s on {platform.processor() or platform.machine()}"}
 
 
+def learned(steps: int):
+    """The learned first-round filter against the quadrilateral on the 20M
+    anisotropic Gaussian mixture (the shape the paper's third group stands in
+    for), with the weights shipped in the package."""
+    import numpy as np
+    import torch
+    import paper_1508_05931_amd as hx
+    import synth
+    w = os.path.join(ROOT, "paper_1508_05931_amd", "weights", "filter16.f32")
+    if not os.path.exists(w):
+        return None
+    d = torch.from_numpy(synth.workload("mixture_20M")).cuda()
+    out = {"workload": "mixture_20M", "weights": "paper_1508_05931_amd/weights/filter16.f32"}
+    for key, ctx in (("quad", hx.Hull2D(profile=True)),
+                     ("learned", hx.Hull2D(profile=True, learned=True, weights=w))):
+        ctx.compute(d)
+        torch.cuda.synchronize()
+        reps = max(3, steps // 2)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ctx.compute(d)
+            ts.append(time.perf_counter() - t0)
+        st = ctx.last_stats
+        ms = float(np.median(ts)) * 1e3
+        out[key] = {"ms_median": round(ms, 4), "Mpoints_per_s": round(d.shape[0] / (ms * 1e-3) / 1e6, 1),
+                    "survivors_round1": int(st.n_round1), "n_hull": int(st.n_hull),
+                    "ms_learned_stage": round(float(st.ms_stage["learned"]), 4)}
+        ctx.close()
+    return out
+
+
 def batched(steps: int):
     """The batched form on 4096 independent sets (sizes log-uniform in
     [64, 200000], squares, disks, Gaussians and thin annuli; 99.9M points),
@@ -154,6 +186,8 @@ def main():
                     help="skip the extra timing of the full-sort mode")
     ap.add_argument("--cpu-sample", type=int, default=5_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-filter comparison on the 20M mixture")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the timing of the batched form (4096 sets)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -295,6 +329,8 @@ def main():
         fctx.close()
     if not args.no_batch:
         out["batched"] = batched(args.steps)
+    if not args.no_learned:
+        out["learned_filter"] = learned(args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host, args.cpu_sample)
     print(json.dumps(out), flush=True)

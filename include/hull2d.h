@@ -74,7 +74,16 @@ typedef struct {
      * an exclusive prefix of exact direction keys decide which; the kept set
      * is identical).  1: sort every round-1 survivor, as Step 4 prints it. */
     int32_t full_sort;
-    int32_t reserved[4];
+    /* First-round filter.  0 (default): the quadrilateral of Steps 1-2.
+     * 1: the learned discard polygon (not in the paper): a network proposes 16
+     * directions from a 32 x 32 occupancy histogram of a sample; the exact
+     * hull of the points extreme in those directions and of the four Step-1
+     * extremes is the discard polygon.  It contains the quadrilateral, so it
+     * discards at least as much, and never a hull vertex.  Needs weights
+     * (hull2d_set_weights / hull2d_load_weights), else hull2d_compute
+     * returns HULL2D_ERR_WEIGHTS. */
+    int32_t filter;
+    int32_t reserved[3];
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */
@@ -94,6 +103,7 @@ enum {
     HULL2D_STAGE_ROUND2,         /* Steps 6-7 second-round filter                   */
     HULL2D_STAGE_COMPACT,        /* Step 7 stable removal of interior points        */
     HULL2D_STAGE_TAIL,           /* Steps 4, 6-7 on a small candidate set, one workgroup */
+    HULL2D_STAGE_LEARNED,        /* learned filter: histogram, network, polygon     */
     HULL2D_STAGE_D2H,            /* copy of the kept points to the host             */
     HULL2D_STAGE_HOST_SCAN,      /* Step 8 on the host (wall clock)                 */
     HULL2D_NUM_STAGES
@@ -146,6 +156,55 @@ hull2d_status hull2d_batch(hull2d_ctx* ctx, const double* d_xy,
 void hull2d_destroy(hull2d_ctx* ctx);
 
 const char* hull2d_status_string(hull2d_status s);
+
+/* ---- Learned filter: network weights and training ---------------------- */
+
+/* The network: 1024 inputs (the occupancy histogram), two hidden layers of
+ * 256 ReLU units, 32 outputs read as 16 directions (y[2j], y[2j+1]).
+ * Parameters are one float32 vector, W1 [256][1024], b1 [256], W2 [256][256],
+ * b2 [256], W3 [32][256], b3 [32] (row = output unit), HULL2D_MLP_PARAMS
+ * values.  Inference uses bfloat16 weights and layer inputs with float32
+ * sums; training keeps float32 weights. */
+#define HULL2D_MLP_PARAMS 336416
+
+/* Copy parameters from host memory (count = HULL2D_MLP_PARAMS) to the
+ * context: they become the inference weights and the training start point
+ * (the optimiser state is reset).  Errors: INVALID_ARG, WEIGHTS (a
+ * non-finite value), OUT_OF_MEMORY, DEVICE. */
+hull2d_status hull2d_set_weights(hull2d_ctx* ctx, const float* h_params, int64_t count);
+
+/* The same from a file of HULL2D_MLP_PARAMS little-endian float32 values
+ * (no header; the shapes are fixed).  WEIGHTS: missing, short or non-finite. */
+hull2d_status hull2d_load_weights(hull2d_ctx* ctx, const char* path);
+
+/* The current float32 parameters to host memory (count = HULL2D_MLP_PARAMS). */
+hull2d_status hull2d_get_weights(hull2d_ctx* ctx, float* h_params, int64_t count);
+
+/* The network input of a point set: 32 x 32 occupancy histogram of the
+ * sample (points i with ((i >> 8) & 15) == 0) over the sample's bounding box,
+ * cell (cy * 32 + cx), each count times 1024 / (sample size).  d_xy device
+ * float64 [n][2]; d_x device float32 [1024].  Synchronous. */
+hull2d_status hull2d_histogram(hull2d_ctx* ctx, const double* d_xy, int64_t n, float* d_x);
+
+/* Inference (the filter's precision) on `rows` inputs: d_x device float32
+ * [rows][1024], d_y device float32 [rows][32].  WEIGHTS if none are set. */
+hull2d_status hull2d_mlp_infer(hull2d_ctx* ctx, const float* d_x, int32_t rows, float* d_y);
+
+/* One training step on a batch (1 <= B <= 4096): float32 forward pass, mean
+ * squared error against d_t [B][32] (device), gradient by backpropagation;
+ * apply = 1 then takes an Adam step (beta 0.9 / 0.999, eps 1e-8, rate lr).
+ * h_loss (may be NULL) receives the loss before the step, h_grad (may be
+ * NULL, HULL2D_MLP_PARAMS floats) the gradient in the parameter layout. */
+hull2d_status hull2d_train_step(hull2d_ctx* ctx, const float* d_x, const float* d_t, int32_t B,
+                                float lr, int32_t apply, float* h_loss, float* h_grad);
+
+/* What the learned filter used in the last hull2d_compute with filter = 1:
+ * dirs[32] (the 16 directions), cand[20] (input indices: the four Step-1
+ * extremes, then the point extreme along each direction), y[32] (the raw
+ * network outputs), *nv (corners of the discard polygon).  Any pointer may
+ * be NULL.  INVALID_ARG if the last call did not use the learned filter. */
+hull2d_status hull2d_debug_learned(hull2d_ctx* ctx, double* dirs, int32_t* cand, float* y,
+                                   int32_t* nv);
 
 /* ---- Checking entry points (exact predicates on the device) ------------ */
 

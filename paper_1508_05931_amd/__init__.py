@@ -26,12 +26,16 @@ STATUS = {
 OK, INVALID_ARG, NONFINITE, RANGE, CAPACITY, OUT_OF_MEMORY, DEVICE, WEIGHTS, UNIMPLEMENTED = range(9)
 
 STAGES = ["extremes", "extremes_final", "filter1", "longest", "histogram", "sort0", "sort1",
-          "sort2", "sort3", "ties", "ties_long", "buckets", "round2", "compact", "tail", "d2h",
-          "host_scan"]
+          "sort2", "sort3", "ties", "ties_long", "buckets", "round2", "compact", "tail",
+          "learned", "d2h", "host_scan"]
 
 EXPORTED = ["hull2d_create", "hull2d_compute", "hull2d_batch", "hull2d_destroy",
-            "hull2d_status_string", "hull2d_debug_orient", "hull2d_debug_angle_key",
+            "hull2d_status_string", "hull2d_set_weights", "hull2d_load_weights",
+            "hull2d_get_weights", "hull2d_histogram", "hull2d_mlp_infer", "hull2d_train_step",
+            "hull2d_debug_learned", "hull2d_debug_orient", "hull2d_debug_angle_key",
             "hull2d_debug_stages"]
+
+MLP_PARAMS = 336416  # HULL2D_MLP_PARAMS
 
 
 class HullError(RuntimeError):
@@ -43,7 +47,7 @@ class HullError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("round2_chunk", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("full_sort", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("filter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class _Stats(ctypes.Structure):
@@ -87,6 +91,23 @@ def load_library():
     lib.hull2d_debug_stages.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                         ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
     lib.hull2d_debug_stages.restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.hull2d_set_weights.argtypes = [vp, fp, i64]
+    lib.hull2d_set_weights.restype = ctypes.c_int
+    lib.hull2d_load_weights.argtypes = [vp, ctypes.c_char_p]
+    lib.hull2d_load_weights.restype = ctypes.c_int
+    lib.hull2d_get_weights.argtypes = [vp, fp, i64]
+    lib.hull2d_get_weights.restype = ctypes.c_int
+    lib.hull2d_histogram.argtypes = [vp, vp, i64, vp]
+    lib.hull2d_histogram.restype = ctypes.c_int
+    lib.hull2d_mlp_infer.argtypes = [vp, vp, i32, vp]
+    lib.hull2d_mlp_infer.restype = ctypes.c_int
+    lib.hull2d_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, i32, fp, fp]
+    lib.hull2d_train_step.restype = ctypes.c_int
+    lib.hull2d_debug_learned.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int32), fp,
+                                         ctypes.POINTER(ctypes.c_int32)]
+    lib.hull2d_debug_learned.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -118,7 +139,8 @@ class Hull2D:
     """A library context bound to one device and one HIP stream."""
 
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
-                 profile: bool = False, full_sort: bool = False):
+                 profile: bool = False, full_sort: bool = False, learned: bool = False,
+                 weights=None):
         import torch
         lib = load_library()
         if device is None:
@@ -128,7 +150,7 @@ class Hull2D:
         self.device = int(device)
         self.stream = stream
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(bool(profile)),
-                       int(bool(full_sort)))
+                       int(bool(full_sort)), int(bool(learned)))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))
@@ -138,6 +160,11 @@ class Hull2D:
         self._lib = lib
         self.last_stats: Stats | None = None
         self._out = np.empty(1024, dtype=np.int32)
+        if weights is not None:
+            if isinstance(weights, (str, os.PathLike)):
+                self.load_weights(weights)
+            else:
+                self.set_weights(weights)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -203,6 +230,77 @@ class Hull2D:
             raise HullError(st, "hull2d_batch")
         self.last_stats = Stats._from(stats)
         return out[:out_offs[-1]].copy(), out_offs
+
+    # ---- learned filter ------------------------------------------------
+    def set_weights(self, params) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        st = self._lib.hull2d_set_weights(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          p.size)
+        if st != OK:
+            raise HullError(st, "hull2d_set_weights")
+
+    def load_weights(self, path) -> None:
+        st = self._lib.hull2d_load_weights(self._h, os.fsencode(os.fspath(path)))
+        if st != OK:
+            raise HullError(st, "hull2d_load_weights")
+
+    def get_weights(self) -> np.ndarray:
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        st = self._lib.hull2d_get_weights(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          p.size)
+        if st != OK:
+            raise HullError(st, "hull2d_get_weights")
+        return p
+
+    def histogram(self, xy):
+        """The network input of a float64 [n, 2] CUDA tensor (float32 [1024] tensor)."""
+        import torch
+        out = torch.empty(1024, dtype=torch.float32, device=xy.device)
+        st = self._lib.hull2d_histogram(self._h, ctypes.c_void_p(xy.data_ptr() if xy.shape[0] else 0),
+                                        xy.shape[0], ctypes.c_void_p(out.data_ptr()))
+        if st != OK:
+            raise HullError(st, "hull2d_histogram")
+        return out
+
+    def mlp_infer(self, x):
+        """Network outputs [rows, 32] of a float32 [rows, 1024] CUDA tensor."""
+        import torch
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], 32), dtype=torch.float32, device=x.device)
+        st = self._lib.hull2d_mlp_infer(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                        ctypes.c_void_p(y.data_ptr()))
+        if st != OK:
+            raise HullError(st, "hull2d_mlp_infer")
+        return y
+
+    def train_step(self, x, t, lr: float = 1e-3, apply: bool = True, want_grad: bool = False):
+        """One step on float32 CUDA tensors x [B, 1024], t [B, 32]: (loss, grad or None)."""
+        x = x.contiguous()
+        t = t.contiguous()
+        loss = ctypes.c_float(0.0)
+        g = np.empty(MLP_PARAMS, dtype=np.float32) if want_grad else None
+        st = self._lib.hull2d_train_step(
+            self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()), x.shape[0],
+            float(lr), int(bool(apply)), ctypes.byref(loss),
+            g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if g is not None else None)
+        if st != OK:
+            raise HullError(st, "hull2d_train_step")
+        return float(loss.value), g
+
+    def learned_info(self) -> dict:
+        """Directions, candidates, raw outputs and polygon size of the last
+        learned-filter call."""
+        d = np.empty(32, dtype=np.float64)
+        c = np.empty(20, dtype=np.int32)
+        y = np.empty(32, dtype=np.float32)
+        nv = ctypes.c_int32(0)
+        st = self._lib.hull2d_debug_learned(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            y.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            ctypes.byref(nv))
+        if st != OK:
+            raise HullError(st, "hull2d_debug_learned")
+        return {"dirs": d.reshape(16, 2), "cand": c, "y": y, "nv": int(nv.value)}
 
     def stages(self, cap: int) -> dict:
         """Stage results of the last compute (for checking against the model)."""

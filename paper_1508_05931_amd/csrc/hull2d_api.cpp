@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -85,6 +87,24 @@ struct hull2d_ctx {
     int64_t hb_cap_h = -1;
     int32_t* hb_hull = nullptr;
     int batch_grid = 0;
+
+    // learned filter: weights (float32 master + bfloat16 inference copies),
+    // optimiser state, the per-call proposal, training activations
+    bool have_weights = false;
+    char* lmem = nullptr;
+    float *m_params = nullptr, *m_grad = nullptr, *m_am = nullptr, *m_av = nullptr;
+    uint16_t *m_w1t = nullptr, *m_w2t = nullptr, *m_w3t = nullptr;
+    LearnOut* learn = nullptr;
+    uint32_t* l_hist = nullptr;
+    float *l_x = nullptr, *l_y = nullptr, *l_loss = nullptr;
+    double* l_part = nullptr;
+    void* l_dpart = nullptr;
+    int64_t adam_t = 0;
+    int32_t tcap_b = 0;
+    char* tmem = nullptr;
+    float *t_h1 = nullptr, *t_h2 = nullptr, *t_y = nullptr, *t_d3 = nullptr, *t_d2 = nullptr,
+          *t_d1 = nullptr;
+    bool last_learned = false;
 
     // the last compute call, for hull2d_debug_stages
     bool have_last = false;
@@ -305,6 +325,102 @@ hull2d_status ensure_batch_hull(hull2d_ctx* c, int64_t h) {
     return HULL2D_OK;
 }
 
+// Parameter layout (one float32 vector): W1 [256][1024], b1, W2 [256][256],
+// b2, W3 [32][256], b3.
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kMlpHidden * kMlpIn;
+constexpr int64_t kOffW2 = kOffB1 + kMlpHidden;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kMlpHidden * kMlpHidden;
+constexpr int64_t kOffW3 = kOffB2 + kMlpHidden;
+constexpr int64_t kOffB3 = kOffW3 + (int64_t)kMlpOut * kMlpHidden;
+static_assert(kOffB3 + kMlpOut == kMlpParams, "parameter layout");
+static_assert(kMlpParams == HULL2D_MLP_PARAMS, "header constant");
+
+hull2d_status ensure_learned(hull2d_ctx* c) {
+    if (c->lmem) return HULL2D_OK;
+    const size_t P = (size_t)kMlpParams;
+    const size_t sizes[13] = {P * 4, P * 4, P * 4, P * 4,
+                              (size_t)kMlpIn * kMlpHidden * 2, (size_t)kMlpHidden * kMlpHidden * 2,
+                              (size_t)kMlpHidden * kMlpOut * 2, sizeof(LearnOut), (size_t)kMlpIn * 4,
+                              (size_t)kMlpIn * 4, (size_t)kMlpOut * 4 + 16,
+                              (size_t)4 * 8 * c->cu_count, dir_part_bytes(c->cu_count * 4)};
+    size_t off[13], o = 0;
+    for (int i = 0; i < 13; ++i) {
+        off[i] = o;
+        o = align_up(o + sizes[i], 256);
+    }
+    if (hipMalloc((void**)&c->lmem, o) != hipSuccess) {
+        (void)hipGetLastError();
+        c->lmem = nullptr;
+        return HULL2D_ERR_OUT_OF_MEMORY;
+    }
+    char* b = c->lmem;
+    c->m_params = (float*)(b + off[0]);
+    c->m_grad = (float*)(b + off[1]);
+    c->m_am = (float*)(b + off[2]);
+    c->m_av = (float*)(b + off[3]);
+    c->m_w1t = (uint16_t*)(b + off[4]);
+    c->m_w2t = (uint16_t*)(b + off[5]);
+    c->m_w3t = (uint16_t*)(b + off[6]);
+    c->learn = (LearnOut*)(b + off[7]);
+    c->l_hist = (uint32_t*)(b + off[8]);
+    c->l_x = (float*)(b + off[9]);
+    c->l_y = (float*)(b + off[10]);
+    c->l_loss = c->l_y + kMlpOut;
+    c->l_part = (double*)(b + off[11]);
+    c->l_dpart = (void*)(b + off[12]);
+    return HULL2D_OK;
+}
+
+MlpDev mlp_dev(const hull2d_ctx* c) {
+    MlpDev W;
+    W.w1t = c->m_w1t;
+    W.w2t = c->m_w2t;
+    W.w3t = c->m_w3t;
+    W.b1 = c->m_params + kOffB1;
+    W.b2 = c->m_params + kOffB2;
+    W.b3 = c->m_params + kOffB3;
+    return W;
+}
+
+hipError_t refresh_inference(hull2d_ctx* c) {
+    hipError_t e = launch_to_bf16t(c->m_params + kOffW1, kMlpHidden, kMlpIn, c->m_w1t, c->stream);
+    if (e == hipSuccess) e = launch_to_bf16t(c->m_params + kOffW2, kMlpHidden, kMlpHidden, c->m_w2t, c->stream);
+    if (e == hipSuccess) e = launch_to_bf16t(c->m_params + kOffW3, kMlpOut, kMlpHidden, c->m_w3t, c->stream);
+    return e;
+}
+
+hull2d_status ensure_train(hull2d_ctx* c, int32_t B) {
+    if (B <= c->tcap_b) return HULL2D_OK;
+    if (c->tmem) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->tmem);
+        c->tmem = nullptr;
+        c->tcap_b = 0;
+    }
+    const size_t b = (size_t)B;
+    const size_t sizes[6] = {b * kMlpHidden * 4, b * kMlpHidden * 4, b * kMlpOut * 4,
+                             b * kMlpOut * 4, b * kMlpHidden * 4, b * kMlpHidden * 4};
+    size_t off[6], o = 0;
+    for (int i = 0; i < 6; ++i) {
+        off[i] = o;
+        o = align_up(o + sizes[i], 256);
+    }
+    if (hipMalloc((void**)&c->tmem, o) != hipSuccess) {
+        (void)hipGetLastError();
+        c->tmem = nullptr;
+        return HULL2D_ERR_OUT_OF_MEMORY;
+    }
+    c->t_h1 = (float*)(c->tmem + off[0]);
+    c->t_h2 = (float*)(c->tmem + off[1]);
+    c->t_y = (float*)(c->tmem + off[2]);
+    c->t_d3 = (float*)(c->tmem + off[3]);
+    c->t_d2 = (float*)(c->tmem + off[4]);
+    c->t_d1 = (float*)(c->tmem + off[5]);
+    c->tcap_b = B;
+    return HULL2D_OK;
+}
+
 #define HX_TRY(call)                      \
     do {                                  \
         if ((call) != hipSuccess) {       \
@@ -444,6 +560,8 @@ void hull2d_destroy(hull2d_ctx* c) {
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
     if (c->bmem) (void)hipFree(c->bmem);
+    if (c->lmem) (void)hipFree(c->lmem);
+    if (c->tmem) (void)hipFree(c->tmem);
     if (c->hb_offs) (void)hipHostFree(c->hb_offs);
     if (c->hb_order) (void)hipHostFree(c->hb_order);
     if (c->hb_meta) (void)hipHostFree(c->hb_meta);
@@ -467,6 +585,9 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
         stats->n = n;
     }
     c->have_last = false;
+    c->last_learned = false;
+    const bool learned = c->opt.filter == 1;
+    if (learned && !c->have_weights) return HULL2D_ERR_WEIGHTS;
     if (n == 0) return HULL2D_OK;
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
     hull2d_status st = ensure_workspace(c, n);
@@ -490,10 +611,18 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
     HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, s));
     mark(HULL2D_STAGE_EXTREMES);
+    // learned filter: sample histogram, network, directions, polygon
+    if (learned) {
+        HX_TRY(launch_histogram_sample(d_xy, n, c->l_part, learned_grid(n, c->cu_count), c->l_hist, s));
+        HX_TRY(launch_hist_to_x(c->l_hist, n, c->l_x, s));
+        HX_TRY(launch_mlp_infer(c->l_x, 1, mlp_dev(c), c->l_y, c->learn, s));
+        HX_TRY(launch_poly(d_xy, n, c->prm, c->learn, c->l_dpart, dir_grid(n, c->cu_count), s));
+        mark(HULL2D_STAGE_LEARNED);
+    }
     // Steps 2-3
     const int segs = std::min(filter1_blocks(n, c->cu_count, c->occ.filter1), kMaxSegs);
-    HX_TRY(launch_filter1(d_xy, n, segs, c->prm, c->comp_xy, c->comp_idx, c->keys_a, c->seg_count,
-                          c->blk_d2, c->blk_best, c->ds, s));
+    HX_TRY(launch_filter1(d_xy, n, segs, c->prm, learned ? &c->learn->poly : nullptr, c->comp_xy,
+                          c->comp_idx, c->keys_a, c->seg_count, c->blk_d2, c->blk_best, c->ds, s));
     mark(HULL2D_STAGE_FILTER1);
     // Step 5 (needs every survivor's distance; the sort does not)
     HX_TRY(launch_longest(segs, c->blk_d2, c->blk_best, c->seg_count, c->seg_off, c->comp_xy, c->keys_a,
@@ -634,6 +763,7 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     const double ms_scan = ms_since(t_scan);
 
     c->have_last = true;
+    c->last_learned = learned;
     c->last_full = full;
     c->last_n = n;
     c->last_ds = D;
@@ -790,6 +920,123 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         stats->ms_device = ms_dev;
         stats->ms_total = ms_since(t_start);
     }
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_set_weights(hull2d_ctx* c, const float* h_params, int64_t count) {
+    if (!c || !h_params || count != kMlpParams) return HULL2D_ERR_INVALID_ARG;
+    if (c->broken) return HULL2D_ERR_DEVICE;
+    for (int64_t i = 0; i < count; ++i)
+        if (!(std::fabs(h_params[i]) <= 3.4e38f)) return HULL2D_ERR_WEIGHTS;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    hull2d_status st = ensure_learned(c);
+    if (st != HULL2D_OK) return st;
+    HX_TRY(hipMemcpyAsync(c->m_params, h_params, (size_t)count * 4, hipMemcpyHostToDevice, c->stream));
+    HX_TRY(hipMemsetAsync(c->m_am, 0, (size_t)count * 4, c->stream));
+    HX_TRY(hipMemsetAsync(c->m_av, 0, (size_t)count * 4, c->stream));
+    HX_TRY(refresh_inference(c));
+    HX_TRY(hipStreamSynchronize(c->stream));
+    c->adam_t = 0;
+    c->have_weights = true;
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_load_weights(hull2d_ctx* c, const char* path) {
+    if (!c || !path) return HULL2D_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return HULL2D_ERR_WEIGHTS;
+    std::vector<float> w((size_t)kMlpParams);
+    const size_t got = std::fread(w.data(), 4, w.size(), f);
+    const bool extra = std::fgetc(f) != EOF;
+    std::fclose(f);
+    if (got != w.size() || extra) return HULL2D_ERR_WEIGHTS;
+    return hull2d_set_weights(c, w.data(), kMlpParams);
+}
+
+hull2d_status hull2d_get_weights(hull2d_ctx* c, float* h_params, int64_t count) {
+    if (!c || !h_params || count != kMlpParams) return HULL2D_ERR_INVALID_ARG;
+    if (!c->have_weights) return HULL2D_ERR_WEIGHTS;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    HX_TRY(hipMemcpyAsync(h_params, c->m_params, (size_t)count * 4, hipMemcpyDeviceToHost, c->stream));
+    HX_TRY(hipStreamSynchronize(c->stream));
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_histogram(hull2d_ctx* c, const double* d_xy, int64_t n, float* d_x) {
+    if (!c || n < 0 || !d_x || (n > 0 && !d_xy)) return HULL2D_ERR_INVALID_ARG;
+    if (c->broken) return HULL2D_ERR_DEVICE;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    hull2d_status st = ensure_learned(c);
+    if (st != HULL2D_OK) return st;
+    HX_TRY(launch_histogram_sample(d_xy, n, c->l_part, learned_grid(n, c->cu_count), c->l_hist, c->stream));
+    HX_TRY(launch_hist_to_x(c->l_hist, n, d_x, c->stream));
+    HX_TRY(hipStreamSynchronize(c->stream));
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_mlp_infer(hull2d_ctx* c, const float* d_x, int32_t rows, float* d_y) {
+    if (!c || rows < 0 || (rows > 0 && (!d_x || !d_y))) return HULL2D_ERR_INVALID_ARG;
+    if (!c->have_weights) return HULL2D_ERR_WEIGHTS;
+    if (rows == 0) return HULL2D_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    HX_TRY(launch_mlp_infer(d_x, rows, mlp_dev(c), d_y, nullptr, c->stream));
+    HX_TRY(hipStreamSynchronize(c->stream));
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_train_step(hull2d_ctx* c, const float* d_x, const float* d_t, int32_t B,
+                                float lr, int32_t apply, float* h_loss, float* h_grad) {
+    if (!c || !d_x || !d_t || B < 1 || B > 4096) return HULL2D_ERR_INVALID_ARG;
+    if (!c->have_weights) return HULL2D_ERR_WEIGHTS;
+    if (c->broken) return HULL2D_ERR_DEVICE;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    hull2d_status st = ensure_train(c, B);
+    if (st != HULL2D_OK) return st;
+    hipStream_t s = c->stream;
+    const float* p = c->m_params;
+    float* g = c->m_grad;
+    const int H = kMlpHidden, I = kMlpIn, O = kMlpOut;
+    // forward
+    HX_TRY(launch_gemm(B, H, I, d_x, I, 0, p + kOffW1, I, 1, p + kOffB1, 1, nullptr, c->t_h1, H, s));
+    HX_TRY(launch_gemm(B, H, H, c->t_h1, H, 0, p + kOffW2, H, 1, p + kOffB2, 1, nullptr, c->t_h2, H, s));
+    HX_TRY(launch_gemm(B, O, H, c->t_h2, H, 0, p + kOffW3, H, 1, p + kOffB3, 0, nullptr, c->t_y, O, s));
+    HX_TRY(launch_mse(c->t_y, d_t, B * O, c->t_d3, c->l_loss, s));
+    // backward
+    HX_TRY(launch_gemm(O, H, B, c->t_d3, O, 1, c->t_h2, H, 0, nullptr, 0, nullptr, g + kOffW3, H, s));
+    HX_TRY(launch_colsum(c->t_d3, B, O, g + kOffB3, s));
+    HX_TRY(launch_gemm(B, H, O, c->t_d3, O, 0, p + kOffW3, H, 0, nullptr, 0, c->t_h2, c->t_d2, H, s));
+    HX_TRY(launch_gemm(H, H, B, c->t_d2, H, 1, c->t_h1, H, 0, nullptr, 0, nullptr, g + kOffW2, H, s));
+    HX_TRY(launch_colsum(c->t_d2, B, H, g + kOffB2, s));
+    HX_TRY(launch_gemm(B, H, H, c->t_d2, H, 0, p + kOffW2, H, 0, nullptr, 0, c->t_h1, c->t_d1, H, s));
+    HX_TRY(launch_gemm(H, I, B, c->t_d1, H, 1, d_x, I, 0, nullptr, 0, nullptr, g + kOffW1, I, s));
+    HX_TRY(launch_colsum(c->t_d1, B, H, g + kOffB1, s));
+    float loss = 0.f;
+    HX_TRY(hipMemcpyAsync(&loss, c->l_loss, 4, hipMemcpyDeviceToHost, s));
+    if (h_grad) HX_TRY(hipMemcpyAsync(h_grad, g, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost, s));
+    if (apply) {
+        const float b1 = 0.9f, b2 = 0.999f;
+        c->adam_t += 1;
+        const float c1 = 1.f - std::pow(b1, (float)c->adam_t);
+        const float c2 = 1.f - std::pow(b2, (float)c->adam_t);
+        HX_TRY(launch_adam(c->m_params, g, c->m_am, c->m_av, kMlpParams, lr, b1, b2, 1e-8f, c1, c2, s));
+        HX_TRY(refresh_inference(c));
+    }
+    HX_TRY(hipStreamSynchronize(s));
+    if (h_loss) *h_loss = loss;
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_debug_learned(hull2d_ctx* c, double* dirs, int32_t* cand, float* y, int32_t* nv) {
+    if (!c) return HULL2D_ERR_INVALID_ARG;
+    if (!c->have_last || !c->last_learned) return HULL2D_ERR_INVALID_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    LearnOut L;
+    HX_TRY(hipMemcpyAsync(&L, c->learn, sizeof(LearnOut), hipMemcpyDeviceToHost, c->stream));
+    HX_TRY(hipStreamSynchronize(c->stream));
+    if (dirs) std::memcpy(dirs, L.dirs, sizeof(L.dirs));
+    if (cand) std::memcpy(cand, L.cand, sizeof(L.cand));
+    if (y) std::memcpy(y, L.y, sizeof(L.y));
+    if (nv) *nv = L.poly.nv;
     return HULL2D_OK;
 }
 

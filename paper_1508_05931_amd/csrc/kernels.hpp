@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "steps.hpp"
 
 namespace hx {
 
@@ -71,9 +72,11 @@ inline Occupancy query_occupancy() {
 // points starting at b*filter1_chunk).
 int filter1_blocks(int64_t n, int cu_count, int per_cu);
 int64_t filter1_chunk(int64_t n, int blocks);
+// poly: NULL for the quadrilateral, else the learned discard polygon.
 hipError_t launch_filter1(const double* xy, int64_t n, int blocks, const Params* prm,
-                          double2* comp_xy, uint32_t* comp_idx, uint32_t* keys, uint32_t* seg_count,
-                          double* blk_d2, uint32_t* blk_best, DevStatus* ds, hipStream_t s);
+                          const Poly* poly, double2* comp_xy, uint32_t* comp_idx, uint32_t* keys,
+                          uint32_t* seg_count, double* blk_d2, uint32_t* blk_best, DevStatus* ds,
+                          hipStream_t s);
 
 // Step 5 and the segment offsets (one block).
 hipError_t launch_longest(int blocks, const double* blk_d2, const uint32_t* blk_best,
@@ -113,6 +116,51 @@ hipError_t launch_batch(const double2* xy, const int64_t* offs, const int32_t* o
                         uint32_t* h_flags, Counters* ctr, int grid, hipStream_t s);
 int batch_blocks_per_cu();
 constexpr uint32_t kBatchFallback = 4u;
+
+// ---- learned-filter variant of Steps 1-2 and its network ----------------
+constexpr int kMlpIn = 1024, kMlpHidden = 256, kMlpOut = 32, kMlpDirs = 16;
+constexpr int64_t kMlpParams = (int64_t)kMlpIn * kMlpHidden + kMlpHidden +
+                               (int64_t)kMlpHidden * kMlpHidden + kMlpHidden +
+                               (int64_t)kMlpHidden * kMlpOut + kMlpOut;
+
+// Inference weights: bfloat16 bits, transposed to [in][out]; float32 biases.
+struct MlpDev {
+    const uint16_t* w1t;
+    const uint16_t* w2t;
+    const uint16_t* w3t;
+    const float* b1;
+    const float* b2;
+    const float* b3;
+};
+
+// What the proposal produced for one hull.
+struct LearnOut {
+    Poly poly;                  // the discard polygon
+    double dirs[2 * kMlpDirs];  // directions used (network output, or the fallback)
+    float y[kMlpOut];           // raw network outputs
+    int32_t cand[kPolyMax];     // candidates: the four Step-1 extremes, then one per direction
+};
+
+int learned_grid(int64_t n, int cu_count);
+// sample histogram: part holds 4 doubles per block of `grid`; hist 1024 counts
+hipError_t launch_histogram_sample(const double* xy, int64_t n, double* part, int grid, uint32_t* hist,
+                                   hipStream_t s);
+hipError_t launch_hist_to_x(const uint32_t* hist, int64_t n, float* x, hipStream_t s);
+hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* y, LearnOut* lo,
+                            hipStream_t s);
+int dir_grid(int64_t n, int cu_count);
+size_t dir_part_bytes(int grid);
+hipError_t launch_poly(const double* xy, int64_t n, const Params* prm, LearnOut* lo, void* part,
+                       int grid, hipStream_t s);
+// training
+hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int tA, const float* B, int ldb,
+                       int tB, const float* bias, int relu, const float* mask, float* C, int ldc,
+                       hipStream_t s);
+hipError_t launch_mse(const float* y, const float* t, int count, float* d, float* loss, hipStream_t s);
+hipError_t launch_colsum(const float* d, int M, int N, float* out, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_to_bf16t(const float* w, int O, int I, uint16_t* wt, hipStream_t s);
 
 hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, uint32_t* prefix,
                               DevStatus* ds2, hipStream_t s);

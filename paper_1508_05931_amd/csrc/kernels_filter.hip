@@ -205,8 +205,11 @@ __global__ __launch_bounds__(256) void k_extremes_final(const Cand* __restrict__
 // the segment lengths are added up afterwards (k_longest), and later kernels
 // read the survivors segment by segment.
 // ---------------------------------------------------------------------------
+// kPoly: the learned discard polygon replaces the quadrilateral.
+template <bool kPoly>
 __global__ __launch_bounds__(kF1Block) void k_filter1(
     const double2* __restrict__ xy, int64_t n, int64_t chunk, const Params* __restrict__ prm,
+    const Poly* __restrict__ poly,
     double2* __restrict__ comp_xy, uint32_t* __restrict__ comp_idx, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ seg_count, double* __restrict__ blk_d2, uint32_t* __restrict__ blk_best,
     DevStatus* __restrict__ ds) {
@@ -217,7 +220,16 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
     __shared__ double s_bd2[NW];
     __shared__ uint32_t s_bidx[NW], s_bslot[NW], s_p0[NW];
 
+    __shared__ Poly s_poly;
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    if (kPoly) {
+        // one field per thread (the struct is a few hundred bytes)
+        const double* src = reinterpret_cast<const double*>(poly);
+        double* dst = reinterpret_cast<double*>(&s_poly);
+        for (int i = (int)threadIdx.x; i < (int)(sizeof(Poly) / sizeof(double)); i += kF1Block)
+            dst[i] = src[i];
+        __syncthreads();
+    }
     const int nc = prm->ncorner;
     const bool discard_all = prm->flags != 0u;
     const double x0 = prm->x0, y0 = prm->y0, qb = prm->qbound;
@@ -254,7 +266,8 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
             key[k] = 0;
             if (pos < end && !discard_all) {
                 const double px = p[k].x, py = p[k].y;
-                surv = !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
+                surv = kPoly ? !poly_inside(s_poly, px, py)
+                             : !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
                 if (surv && px == x0 && py == y0) {
                     surv = false;
                     ++p0c;
@@ -808,7 +821,7 @@ int filter1_blocks(int64_t n, int cu_count, int per_cu) {
 
 void occupancy_filter(Occupancy& o) {
     o.extremes = resident_blocks(reinterpret_cast<const void*>(k_extremes), kExtBlock);
-    o.filter1 = resident_blocks(reinterpret_cast<const void*>(k_filter1), kF1Block);
+    o.filter1 = resident_blocks(reinterpret_cast<const void*>(k_filter1<false>), kF1Block);
 }
 
 int64_t filter1_chunk(int64_t n, int blocks) {
@@ -817,11 +830,17 @@ int64_t filter1_chunk(int64_t n, int blocks) {
 }
 
 hipError_t launch_filter1(const double* xy, int64_t n, int blocks, const Params* prm,
-                          double2* comp_xy, uint32_t* comp_idx, uint32_t* keys, uint32_t* seg_count,
-                          double* blk_d2, uint32_t* blk_best, DevStatus* ds, hipStream_t s) {
-    hipLaunchKernelGGL(k_filter1, dim3(blocks), dim3(kF1Block), 0, s,
-                       reinterpret_cast<const double2*>(xy), n, filter1_chunk(n, blocks), prm,
-                       comp_xy, comp_idx, keys, seg_count, blk_d2, blk_best, ds);
+                          const Poly* poly, double2* comp_xy, uint32_t* comp_idx, uint32_t* keys,
+                          uint32_t* seg_count, double* blk_d2, uint32_t* blk_best, DevStatus* ds,
+                          hipStream_t s) {
+    if (poly)
+        hipLaunchKernelGGL(k_filter1<true>, dim3(blocks), dim3(kF1Block), 0, s,
+                           reinterpret_cast<const double2*>(xy), n, filter1_chunk(n, blocks), prm,
+                           poly, comp_xy, comp_idx, keys, seg_count, blk_d2, blk_best, ds);
+    else
+        hipLaunchKernelGGL(k_filter1<false>, dim3(blocks), dim3(kF1Block), 0, s,
+                           reinterpret_cast<const double2*>(xy), n, filter1_chunk(n, blocks), prm,
+                           poly, comp_xy, comp_idx, keys, seg_count, blk_d2, blk_best, ds);
     return hipGetLastError();
 }
 

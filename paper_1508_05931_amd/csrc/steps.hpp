@@ -165,6 +165,34 @@ __device__ inline bool quad_inside(const double (&qx)[4], const double (&qy)[4],
     return inside;
 }
 
+// The learned discard polygon (learned-filter variant of Step 2): the exact
+// convex hull of the candidate points, strict corners counter-clockwise.
+constexpr int kPolyMax = 20;  // four Step-1 extremes + 16 directions
+struct Poly {
+    int32_t nv;  // corners (fewer than 3: discard nothing)
+    int32_t pad;
+    double qb;   // error bound of the float64 edge test (as for the quadrilateral)
+    double px[kPolyMax], py[kPolyMax], ex[kPolyMax], ey[kPolyMax];
+};
+
+// Strictly inside the polygon: strictly left of every edge.
+__device__ inline bool poly_inside(const Poly& Q, double x, double y) {
+    if (Q.nv < 3) return false;
+    for (int j = 0; j < Q.nv; ++j) {
+        const double dx = x - Q.px[j], dy = y - Q.py[j];
+        const double l = Q.ex[j] * dy;
+        const double r = Q.ey[j] * dx;
+        const double det = l - r;
+        int o = det > Q.qb ? 1 : (-det > Q.qb ? -1 : 0);
+        if (o == 0) {
+            const int j1 = j + 1 == Q.nv ? 0 : j + 1;
+            o = orient(Q.px[j], Q.py[j], Q.px[j1], Q.py[j1], x, y);
+        }
+        if (o <= 0) return false;
+    }
+    return true;
+}
+
 // Step 5's distance (a heuristic choice; only needs to be reproducible):
 // fl(fl(dx*dx) + fl(dy*dy)) with dx = fl(x - x0), dy = fl(y - y0).
 __device__ inline double dist2(double px, double py, double x0, double y0) {

@@ -1,0 +1,186 @@
+"""GPU parity of the learned-filter variant and of its network kernels.
+
+* the sample histogram equals the reference definition exactly;
+* bfloat16 inference matches the reference within the rounding budget;
+* the float32 training gradient matches the float64 reference, and Adam
+  steps lower the loss;
+* the first round with the learned polygon keeps exactly the points the
+  oracle keeps for the directions the device used, never more than the
+  quadrilateral keeps, and the hull equals the oracle's on every input;
+* with the shipped weights, the learned polygon keeps far fewer points than
+  the quadrilateral on held-out mixture sets.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_1508_05931_amd", "weights", "filter16.f32")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hx(torch_dev):
+    import paper_1508_05931_amd as hx
+    return hx
+
+
+def _random_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shp in mlp.SHAPES:
+        fan_in = shp[1] if len(shp) == 2 else 1
+        s = scale * math.sqrt(2.0 / fan_in) if len(shp) == 2 else 0.1 * scale
+        parts.append(rng.normal(scale=s, size=shp).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("name", ["square", "mixture", "tiny", "line", "equal"])
+def test_histogram_matches_reference(torch_dev, hx, name):
+    pts = {"square": lambda: synth.square(100_003, (400, 1)),
+           "mixture": lambda: synth.mixture(65_536, (401, 1)),
+           "tiny": lambda: synth.disk(37, (402, 1)),
+           "line": lambda: np.stack([np.arange(5000.0), np.zeros(5000)], 1),
+           "equal": lambda: np.full((9000, 2), 0.5)}[name]()
+    say(f"histogram {name}")
+    c = hx.Hull2D()
+    got = c.histogram(_dev(torch_dev, pts)).cpu().numpy()
+    want = mlp.histogram(pts)
+    assert np.array_equal(got, want)
+    c.close()
+
+
+def test_mlp_inference_matches_bf16_reference(torch_dev, hx):
+    c = hx.Hull2D()
+    p = _random_params(5)
+    c.set_weights(p)
+    rng = np.random.default_rng(6)
+    x = (rng.random((9, 1024)) * 3).astype(np.float32)
+    say("mlp inference")
+    y = c.mlp_infer(_dev(torch_dev, x)).cpu().numpy().astype(np.float64)
+    ref = mlp.forward_bf16(p, x)
+    # float32 sums in another order than the reference's float64 sums can move
+    # a hidden activation across a bfloat16 rounding boundary (2^-8 relative);
+    # the budget below covers a few such flips per unit on these scales
+    scale = 1.0 + np.abs(ref)
+    assert np.all(np.abs(y - ref) <= 3e-2 * scale), np.max(np.abs(y - ref) / scale)
+    # and the precision really is bfloat16: the float64 network differs more
+    exact, _ = mlp.forward(p, x)
+    assert np.max(np.abs(y - exact)) > 0
+    c.close()
+
+
+def test_training_gradient_and_descent(torch_dev, hx):
+    c = hx.Hull2D()
+    p = _random_params(7, scale=0.5)
+    c.set_weights(p)
+    rng = np.random.default_rng(8)
+    x = (rng.random((6, 1024)) * 2).astype(np.float32)
+    t = rng.normal(size=(6, 32)).astype(np.float32)
+    say("training gradient")
+    loss, g = c.train_step(_dev(torch_dev, x), _dev(torch_dev, t), apply=False, want_grad=True)
+    ref_g = mlp.grad(p, x, t)
+    ref_l = mlp.loss(p, x, t)
+    assert abs(loss - ref_l) <= 1e-4 * (1 + ref_l)
+    err = np.abs(g.astype(np.float64) - ref_g)
+    assert np.max(err) <= 1e-4 * (np.max(np.abs(ref_g)) + 1e-6), np.max(err)
+    # weights unchanged without apply
+    assert np.array_equal(c.get_weights(), p)
+    first = loss
+    for _ in range(30):
+        loss, _ = c.train_step(_dev(torch_dev, x), _dev(torch_dev, t), lr=1e-3)
+    assert loss < 0.5 * first
+    assert not np.array_equal(c.get_weights(), p)
+    c.close()
+
+
+def _cases():
+    t = np.arange(-700, 800, dtype=np.float64)
+    return {
+        "mixture_100k": synth.mixture(100_000, (410, 1)),
+        "square_100k": synth.square(100_000, (411, 1)),
+        "disk_50k": synth.disk(50_000, (412, 1)),
+        "gauss_30k": synth.gaussian(30_000, 1.0, (413, 1)),
+        "annulus_20k": synth.annulus(20_000, 0.999, (414, 1)),
+        "grid_60x3": synth.grid(60, 3, (415, 1)),
+        "collinear": np.stack([t, 2 * t - 5], axis=1)[np.random.default_rng(1).permutation(1500)],
+        "equal": np.full((500, 2), 0.375),
+        "three": np.array([[0.0, 0.0], [2.0, 2.0], [1.0, 1.0]]),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("wseed", [21, 22])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_learned_first_round_equals_oracle(torch_dev, hx, name, wseed):
+    pts = CASES[name]
+    say(f"learned {name} weights {wseed}")
+    c = hx.Hull2D(learned=True, weights=_random_params(wseed))
+    got = c.compute(_dev(torch_dev, pts))
+    st = c.last_stats
+    assert got.tolist() == oracle.hull(pts).tolist()
+    info = c.learned_info()
+    ref = oracle.learned_round1(pts, info["dirs"])
+    assert info["cand"].tolist() == ref["cand"].tolist()
+    assert st.n_round1 == ref["m1"]
+    assert st.n_round1 <= oracle.model(pts)["m1"]
+    c.close()
+
+
+def test_learned_needs_weights(torch_dev, hx):
+    c = hx.Hull2D(learned=True)
+    with pytest.raises(hx.HullError) as e:
+        c.compute(_dev(torch_dev, synth.square(100, (420, 1))))
+    assert e.value.status == hx.WEIGHTS
+    with pytest.raises(hx.HullError) as e:
+        c.load_weights(os.path.join(ROOT, "no_such_weights.f32"))
+    assert e.value.status == hx.WEIGHTS
+    c.close()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights in the tree")
+def test_shipped_weights_gain_over_quadrilateral(torch_dev, hx):
+    """Held-out mixture sets (streams (3000 + i, 2), not used in training):
+    the trained polygon keeps a small fraction of what the quadrilateral
+    keeps, and every hull still equals the oracle's."""
+    cl = hx.Hull2D(learned=True, weights=WEIGHTS)
+    cq = hx.Hull2D()
+    mq, ml = [], []
+    for i in range(40):
+        pts = synth.mixture(65_536, (3000 + i, 2))
+        d = _dev(torch_dev, pts)
+        h = cl.compute(d)
+        ml.append(cl.last_stats.n_round1)
+        cq.compute(d)
+        mq.append(cq.last_stats.n_round1)
+        if i < 8:
+            assert h.tolist() == oracle.hull(pts).tolist()
+    say(f"mean first-round survivors: quad {np.mean(mq):.0f}, learned {np.mean(ml):.0f}")
+    assert all(a <= b for a, b in zip(ml, mq))
+    assert np.mean(ml) < 0.2 * np.mean(mq)
