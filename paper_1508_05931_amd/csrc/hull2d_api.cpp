@@ -93,12 +93,12 @@ struct hull2d_ctx {
     bool have_weights = false;
     char* lmem = nullptr;
     float *m_params = nullptr, *m_grad = nullptr, *m_am = nullptr, *m_av = nullptr;
-    uint16_t *m_w1t = nullptr, *m_w2t = nullptr, *m_w3t = nullptr;
+    uint16_t *m_w1 = nullptr, *m_w2 = nullptr, *m_w3 = nullptr;
     LearnOut* learn = nullptr;
     uint32_t* l_hist = nullptr;
-    float *l_x = nullptr, *l_y = nullptr, *l_loss = nullptr;
+    float *l_x = nullptr, *l_y = nullptr, *l_loss = nullptr, *l_h1 = nullptr, *l_h2 = nullptr;
     double* l_part = nullptr;
-    void* l_dpart = nullptr;
+    DirBest* l_dpart = nullptr;
     int64_t adam_t = 0;
     int32_t tcap_b = 0;
     char* tmem = nullptr;
@@ -342,8 +342,8 @@ hull2d_status ensure_learned(hull2d_ctx* c) {
     const size_t sizes[13] = {P * 4, P * 4, P * 4, P * 4,
                               (size_t)kMlpIn * kMlpHidden * 2, (size_t)kMlpHidden * kMlpHidden * 2,
                               (size_t)kMlpHidden * kMlpOut * 2, sizeof(LearnOut), (size_t)kMlpIn * 4,
-                              (size_t)kMlpIn * 4, (size_t)kMlpOut * 4 + 16,
-                              (size_t)4 * 8 * c->cu_count, dir_part_bytes(c->cu_count * 4)};
+                              (size_t)kMlpIn * 4 + 2 * (size_t)kMlpHidden * 4, (size_t)kMlpOut * 4 + 16,
+                              (size_t)4 * 8 * c->cu_count, dir_part_bytes(kExtGridMax)};
     size_t off[13], o = 0;
     for (int i = 0; i < 13; ++i) {
         off[i] = o;
@@ -359,24 +359,26 @@ hull2d_status ensure_learned(hull2d_ctx* c) {
     c->m_grad = (float*)(b + off[1]);
     c->m_am = (float*)(b + off[2]);
     c->m_av = (float*)(b + off[3]);
-    c->m_w1t = (uint16_t*)(b + off[4]);
-    c->m_w2t = (uint16_t*)(b + off[5]);
-    c->m_w3t = (uint16_t*)(b + off[6]);
+    c->m_w1 = (uint16_t*)(b + off[4]);
+    c->m_w2 = (uint16_t*)(b + off[5]);
+    c->m_w3 = (uint16_t*)(b + off[6]);
     c->learn = (LearnOut*)(b + off[7]);
     c->l_hist = (uint32_t*)(b + off[8]);
     c->l_x = (float*)(b + off[9]);
+    c->l_h1 = c->l_x + kMlpIn;
+    c->l_h2 = c->l_h1 + kMlpHidden;
     c->l_y = (float*)(b + off[10]);
     c->l_loss = c->l_y + kMlpOut;
     c->l_part = (double*)(b + off[11]);
-    c->l_dpart = (void*)(b + off[12]);
+    c->l_dpart = (DirBest*)(b + off[12]);
     return HULL2D_OK;
 }
 
 MlpDev mlp_dev(const hull2d_ctx* c) {
     MlpDev W;
-    W.w1t = c->m_w1t;
-    W.w2t = c->m_w2t;
-    W.w3t = c->m_w3t;
+    W.w1 = c->m_w1;
+    W.w2 = c->m_w2;
+    W.w3 = c->m_w3;
     W.b1 = c->m_params + kOffB1;
     W.b2 = c->m_params + kOffB2;
     W.b3 = c->m_params + kOffB3;
@@ -384,9 +386,11 @@ MlpDev mlp_dev(const hull2d_ctx* c) {
 }
 
 hipError_t refresh_inference(hull2d_ctx* c) {
-    hipError_t e = launch_to_bf16t(c->m_params + kOffW1, kMlpHidden, kMlpIn, c->m_w1t, c->stream);
-    if (e == hipSuccess) e = launch_to_bf16t(c->m_params + kOffW2, kMlpHidden, kMlpHidden, c->m_w2t, c->stream);
-    if (e == hipSuccess) e = launch_to_bf16t(c->m_params + kOffW3, kMlpOut, kMlpHidden, c->m_w3t, c->stream);
+    hipError_t e = launch_to_bf16(c->m_params + kOffW1, (int64_t)kMlpHidden * kMlpIn, c->m_w1, c->stream);
+    if (e == hipSuccess)
+        e = launch_to_bf16(c->m_params + kOffW2, (int64_t)kMlpHidden * kMlpHidden, c->m_w2, c->stream);
+    if (e == hipSuccess)
+        e = launch_to_bf16(c->m_params + kOffW3, (int64_t)kMlpOut * kMlpHidden, c->m_w3, c->stream);
     return e;
 }
 
@@ -608,19 +612,23 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
 
     // Step 1
-    const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
-    HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, s));
-    mark(HULL2D_STAGE_EXTREMES);
-    // learned filter: sample histogram, network, directions, polygon
+    // learned filter: sample histogram and network first; its directions
+    // ride along in the Step-1 pass, then the discard polygon
     if (learned) {
         HX_TRY(launch_histogram_sample(d_xy, n, c->l_part, learned_grid(n, c->cu_count), c->l_hist, s));
         HX_TRY(launch_hist_to_x(c->l_hist, n, c->l_x, s));
-        HX_TRY(launch_mlp_infer(c->l_x, 1, mlp_dev(c), c->l_y, c->learn, s));
-        HX_TRY(launch_poly(d_xy, n, c->prm, c->learn, c->l_dpart, dir_grid(n, c->cu_count), s));
+        HX_TRY(launch_mlp_infer(c->l_x, 1, mlp_dev(c), c->l_h1, c->l_h2, c->l_y, c->learn, s));
         mark(HULL2D_STAGE_LEARNED);
     }
+    const int grid_ext =
+        extremes_grid(n, c->cu_count, learned ? c->occ.extremes_dirs : c->occ.extremes);
+    HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds,
+                           learned ? c->learn->dirs : nullptr, learned ? c->l_dpart : nullptr, s));
+    if (learned) HX_TRY(launch_poly(d_xy, c->prm, c->learn, c->l_dpart, grid_ext, s));
+    mark(HULL2D_STAGE_EXTREMES);
     // Steps 2-3
-    const int segs = std::min(filter1_blocks(n, c->cu_count, c->occ.filter1), kMaxSegs);
+    const int segs = std::min(
+        filter1_blocks(n, c->cu_count, learned ? c->occ.filter1_poly : c->occ.filter1), kMaxSegs);
     HX_TRY(launch_filter1(d_xy, n, segs, c->prm, learned ? &c->learn->poly : nullptr, c->comp_xy,
                           c->comp_idx, c->keys_a, c->seg_count, c->blk_d2, c->blk_best, c->ds, s));
     mark(HULL2D_STAGE_FILTER1);
@@ -978,8 +986,11 @@ hull2d_status hull2d_mlp_infer(hull2d_ctx* c, const float* d_x, int32_t rows, fl
     if (!c || rows < 0 || (rows > 0 && (!d_x || !d_y))) return HULL2D_ERR_INVALID_ARG;
     if (!c->have_weights) return HULL2D_ERR_WEIGHTS;
     if (rows == 0) return HULL2D_OK;
+    if (rows > 65535) return HULL2D_ERR_INVALID_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
-    HX_TRY(launch_mlp_infer(d_x, rows, mlp_dev(c), d_y, nullptr, c->stream));
+    hull2d_status st = ensure_train(c, rows);
+    if (st != HULL2D_OK) return st;
+    HX_TRY(launch_mlp_infer(d_x, rows, mlp_dev(c), c->t_h1, c->t_h2, d_y, nullptr, c->stream));
     HX_TRY(hipStreamSynchronize(c->stream));
     return HULL2D_OK;
 }

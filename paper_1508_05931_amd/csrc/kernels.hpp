@@ -29,6 +29,7 @@ constexpr int kCpTile = kCpBlock * kCpIpt;       // flags per compaction tile
 constexpr int kRunSmall = 16;                    // equal-key runs sorted by one thread
 constexpr int kRunCap = 2048;                    // longest run one workgroup sorts in LDS
 constexpr int kHistGridMax = 512;
+constexpr int kMlpIn = 1024, kMlpHidden = 256, kMlpOut = 32, kMlpDirs = 16;  // learned filter
 constexpr int kTailBlock = 1024;                 // the one-workgroup tail
 constexpr int kTailCap = 12288;                  // candidates per region it sorts in LDS
 constexpr int kBatchBlock = 512;                 // threads per set in the batched kernel
@@ -37,8 +38,17 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 
 // Step 1: partial extreme candidates per block, then the final reduction,
 // the quadrilateral and the pivot.
+// Per-block best of one direction (learned filter).
+struct DirBest {
+    double v;
+    int32_t i;
+    int32_t pad;
+};
+
+// dirs: NULL, or the learned filter's kMlpDirs directions ([2 * kMlpDirs]
+// doubles, device); then the same pass writes dpart[grid][kMlpDirs].
 hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
-                           DevStatus* ds, hipStream_t s);
+                           DevStatus* ds, const double* dirs, DirBest* dpart, hipStream_t s);
 int extremes_grid(int64_t n, int cu_count, int per_cu);
 
 // Resident blocks per compute unit of the fixed-grid streaming kernels (from
@@ -46,7 +56,7 @@ int extremes_grid(int64_t n, int cu_count, int per_cu);
 // exactly once: a block that cannot be resident would run in a second,
 // mostly empty wave of blocks.
 struct Occupancy {
-    int extremes = 1, filter1 = 1, bucket_max = 1;
+    int extremes = 1, extremes_dirs = 1, filter1 = 1, filter1_poly = 1, bucket_max = 1;
 };
 // At least 1 when the query fails.
 inline int resident_blocks(const void* kernel, int block) {
@@ -118,16 +128,15 @@ int batch_blocks_per_cu();
 constexpr uint32_t kBatchFallback = 4u;
 
 // ---- learned-filter variant of Steps 1-2 and its network ----------------
-constexpr int kMlpIn = 1024, kMlpHidden = 256, kMlpOut = 32, kMlpDirs = 16;
 constexpr int64_t kMlpParams = (int64_t)kMlpIn * kMlpHidden + kMlpHidden +
                                (int64_t)kMlpHidden * kMlpHidden + kMlpHidden +
                                (int64_t)kMlpHidden * kMlpOut + kMlpOut;
 
-// Inference weights: bfloat16 bits, transposed to [in][out]; float32 biases.
+// Inference weights: bfloat16 bits, [out][in]; float32 biases.
 struct MlpDev {
-    const uint16_t* w1t;
-    const uint16_t* w2t;
-    const uint16_t* w3t;
+    const uint16_t* w1;
+    const uint16_t* w2;
+    const uint16_t* w3;
     const float* b1;
     const float* b2;
     const float* b3;
@@ -146,11 +155,14 @@ int learned_grid(int64_t n, int cu_count);
 hipError_t launch_histogram_sample(const double* xy, int64_t n, double* part, int grid, uint32_t* hist,
                                    hipStream_t s);
 hipError_t launch_hist_to_x(const uint32_t* hist, int64_t n, float* x, hipStream_t s);
-hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* y, LearnOut* lo,
-                            hipStream_t s);
-int dir_grid(int64_t n, int cu_count);
+// rows inputs x [rows][1024] -> y [rows][32]; h1, h2 [rows][256] scratch;
+// lo (rows = 1 only, may be NULL) receives the directions.
+hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* h1, float* h2, float* y,
+                            LearnOut* lo, hipStream_t s);
 size_t dir_part_bytes(int grid);
-hipError_t launch_poly(const double* xy, int64_t n, const Params* prm, LearnOut* lo, void* part,
+// the discard polygon from the Step-1 extremes and the per-block direction
+// partials of launch_extremes (grid blocks)
+hipError_t launch_poly(const double* xy, const Params* prm, LearnOut* lo, const DirBest* dpart,
                        int grid, hipStream_t s);
 // training
 hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int tA, const float* B, int ldb,
@@ -160,7 +172,7 @@ hipError_t launch_mse(const float* y, const float* t, int count, float* d, float
 hipError_t launch_colsum(const float* d, int M, int N, float* out, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1,
                        float b2, float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_to_bf16t(const float* w, int O, int I, uint16_t* wt, hipStream_t s);
+hipError_t launch_to_bf16(const float* w, int64_t count, uint16_t* wb, hipStream_t s);
 
 hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, uint32_t* prefix,
                               DevStatus* ds2, hipStream_t s);

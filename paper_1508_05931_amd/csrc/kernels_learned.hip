@@ -5,12 +5,13 @@
 //   k_sample_bbox, k_sample_hist  32 x 32 occupancy histogram of a sample
 //                                 (every 16th block of 256 points) over the
 //                                 sample's bounding box
-//   k_mlp_infer                   1024 -> 256 -> 256 -> 32 network, bfloat16
-//                                 weights and layer inputs, float32 sums:
-//                                 16 directions
-//   k_dir_extremes, k_poly        the point farthest along each direction
-//                                 (fma(x, ux, y * uy), ties: smallest index),
-//                                 and the exact convex hull of those 16
+//   k_mlp_layer ×3, k_mlp_dirs    1024 -> 256 -> 256 -> 32 network, bfloat16
+//                                 weights and layer inputs, float32 sums, one
+//                                 wave per output unit: 16 directions
+//   k_extremes<16>, k_poly        the point farthest along each direction
+//                                 (fma(x, ux, y * uy), ties: smallest index;
+//                                 in the same pass as Step 1), and the exact
+//                                 convex hull of those 16
 //                                 points and the four Step-1 extremes: the
 //                                 discard polygon, which contains the
 //                                 quadrilateral, so the first round stays
@@ -25,7 +26,6 @@ namespace hx {
 namespace {
 
 constexpr int kHB = 256;        // threads of the histogram and network kernels
-constexpr int kDirB = 256;      // threads of the direction extremes
 constexpr int kDirs = kMlpDirs;
 
 __device__ inline bool finite_d(double v) { return fabs(v) <= DBL_MAX; }
@@ -107,14 +107,37 @@ __global__ __launch_bounds__(kHB) void k_sample_hist(const double2* __restrict__
                                                      uint32_t* __restrict__ hist) {
     __shared__ uint32_t s_h[kMlpIn];
     __shared__ double s_box[4];
+    __shared__ double s_v[4][kHB / 64];
     for (int i = (int)threadIdx.x; i < kMlpIn; i += kHB) s_h[i] = 0;
-    if (threadIdx.x == 0) {
+    {
         double lo_x = INFINITY, lo_y = INFINITY, hi_x = -INFINITY, hi_y = -INFINITY;
-        for (int b = 0; b < nparts; ++b) {
+        for (int b = (int)threadIdx.x; b < nparts; b += kHB) {
             lo_x = fmin(lo_x, part[4 * b + 0]);
             lo_y = fmin(lo_y, part[4 * b + 1]);
             hi_x = fmax(hi_x, part[4 * b + 2]);
             hi_y = fmax(hi_y, part[4 * b + 3]);
+        }
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) {
+            lo_x = fmin(lo_x, __shfl_xor(lo_x, m));
+            lo_y = fmin(lo_y, __shfl_xor(lo_y, m));
+            hi_x = fmax(hi_x, __shfl_xor(hi_x, m));
+            hi_y = fmax(hi_y, __shfl_xor(hi_y, m));
+        }
+        const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+        if (lane == 0) {
+            s_v[0][wave] = lo_x;
+            s_v[1][wave] = lo_y;
+            s_v[2][wave] = hi_x;
+            s_v[3][wave] = hi_y;
+        }
+        __syncthreads();
+        if (threadIdx.x != 0) goto binned;
+        for (int w = 1; w < kHB / 64; ++w) {
+            lo_x = fmin(lo_x, s_v[0][w]);
+            lo_y = fmin(lo_y, s_v[1][w]);
+            hi_x = fmax(hi_x, s_v[2][w]);
+            hi_y = fmax(hi_y, s_v[3][w]);
         }
         s_box[0] = lo_x;
         s_box[1] = lo_y;
@@ -122,6 +145,7 @@ __global__ __launch_bounds__(kHB) void k_sample_hist(const double2* __restrict__
         s_box[2] = wx > 0.0 ? 32.0 / wx : 0.0;
         s_box[3] = wy > 0.0 ? 32.0 / wy : 0.0;
     }
+binned:
     __syncthreads();
     const double lo_x = s_box[0], lo_y = s_box[1], sx = s_box[2], sy = s_box[3];
     const int64_t slots = sample_slots(n);
@@ -145,141 +169,80 @@ __global__ void k_hist_to_x(const uint32_t* __restrict__ hist, int64_t n, float*
     x[i] = ns > 0 ? (float)((double)hist[i] * (1024.0 / (double)ns)) : 0.0f;
 }
 
-// One network evaluation per workgroup (row b of x).  Weights are bfloat16,
-// transposed to [in][out] so that a wave reads consecutive outputs.  With
-// `lo` set (one row), also writes the 16 directions used by the filter.
-__global__ __launch_bounds__(kHB) void k_mlp_infer(const float* __restrict__ x, MlpDev W,
-                                                   float* __restrict__ y,
-                                                   LearnOut* __restrict__ lo) {
-    __shared__ float s_a[kMlpIn];
-    __shared__ float s_h[kMlpHidden];
-    __shared__ float s_y[kMlpOut];
-    const int t = (int)threadIdx.x;
-    const float* xr = x + (size_t)blockIdx.x * kMlpIn;
-    for (int i = t; i < kMlpIn; i += kHB) s_a[i] = from_bf16(to_bf16(xr[i]));
-    __syncthreads();
-    // layer 1: thread t owns hidden unit t
-    float acc = 0.f;
-    for (int i = 0; i < kMlpIn; ++i) acc = fmaf(s_a[i], from_bf16(W.w1t[(size_t)i * kMlpHidden + t]), acc);
-    acc += W.b1[t];
-    const float h1 = from_bf16(to_bf16(fmaxf(acc, 0.f)));
-    __syncthreads();
-    s_a[t] = h1;
-    __syncthreads();
-    acc = 0.f;
-    for (int i = 0; i < kMlpHidden; ++i) acc = fmaf(s_a[i], from_bf16(W.w2t[(size_t)i * kMlpHidden + t]), acc);
-    acc += W.b2[t];
-    s_h[t] = from_bf16(to_bf16(fmaxf(acc, 0.f)));
-    __syncthreads();
-    if (t < kMlpOut) {
-        acc = 0.f;
-        for (int i = 0; i < kMlpHidden; ++i) acc = fmaf(s_h[i], from_bf16(W.w3t[(size_t)i * kMlpOut + t]), acc);
-        acc += W.b3[t];
-        s_y[t] = acc;
-        y[(size_t)blockIdx.x * kMlpOut + t] = acc;
-    }
-    __syncthreads();
-    if (lo && t < kDirs) {
-        double ux = (double)s_y[2 * t], uy = (double)s_y[2 * t + 1];
-        if (!finite_d(ux) || !finite_d(uy) || (ux == 0.0 && uy == 0.0)) {
-            // fall back to the evenly spaced direction of this slot
-            const double a = 6.283185307179586 * (double)t / (double)kDirs;
-            ux = cos(a);
-            uy = sin(a);
-        }
-        lo->y[2 * t] = s_y[2 * t];
-        lo->y[2 * t + 1] = s_y[2 * t + 1];
-        lo->dirs[2 * t] = ux;
-        lo->dirs[2 * t + 1] = uy;
-    }
-}
+// One layer for rows of inputs (blockIdx.y = row): out = act(W in + b), one
+// wave per output unit, each lane summing every 64th input (bfloat16 weights
+// [out][in], layer input rounded to bfloat16, float32 sums).  act: ReLU then
+// bfloat16 rounding (hidden layers), or none (the output layer).
+constexpr int kMlpWaves = 4;  // output units per workgroup
 
-struct DirBest {
-    double v;
-    int32_t i;
-    int32_t pad;
-};
-
-__device__ inline void dir_take(double& bv, int32_t& bi, double v, int32_t i) {
-    const bool tk = (v > bv) | ((v == bv) & (i < bi));
-    bv = tk ? v : bv;
-    bi = tk ? i : bi;
-}
-
-__global__ __launch_bounds__(kDirB) void k_dir_extremes(const double2* __restrict__ xy, int64_t n,
-                                                        const LearnOut* __restrict__ lo,
-                                                        DirBest* __restrict__ part) {
-    __shared__ double s_u[2 * kDirs];
-    __shared__ DirBest s_b[kDirB / 64][kDirs];
-    if (threadIdx.x < 2 * kDirs) s_u[threadIdx.x] = lo->dirs[threadIdx.x];
-    __syncthreads();
-    double bv[kDirs];
-    int32_t bi[kDirs];
-#pragma unroll
-    for (int j = 0; j < kDirs; ++j) {
-        bv[j] = -INFINITY;
-        bi[j] = INT32_MAX;
-    }
-    constexpr int U = 4;
-    const int64_t stride = (int64_t)gridDim.x * kDirB;
-    for (int64_t i0 = (int64_t)blockIdx.x * kDirB + threadIdx.x; i0 < n; i0 += stride * U) {
-        double2 p[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * stride;
-            if (i < n) p[u] = xy[i];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * stride;
-            if (i < n) {
-#pragma unroll
-                for (int j = 0; j < kDirs; ++j)
-                    dir_take(bv[j], bi[j], fma(p[u].x, s_u[2 * j], p[u].y * s_u[2 * j + 1]), (int32_t)i);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kDirs; ++j) {
-#pragma unroll
-        for (int m = 32; m > 0; m >>= 1) {
-            const double ov = __shfl_xor(bv[j], m);
-            const int32_t oi = __shfl_xor(bi[j], m);
-            dir_take(bv[j], bi[j], ov, oi);
-        }
-    }
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_layer(const float* __restrict__ in, int n_in,
+                                                             const uint16_t* __restrict__ W,
+                                                             const float* __restrict__ bias, int n_out,
+                                                             int hidden, float* __restrict__ out) {
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
-    if (lane == 0) {
+    const int o = (int)blockIdx.x * kMlpWaves + wave;
+    if (o >= n_out) return;
+    const float* x = in + (size_t)blockIdx.y * n_in;
+    const uint16_t* w = W + (size_t)o * n_in;
+    float acc = 0.f;
+    for (int i = lane; i < n_in; i += 64) acc = fmaf(from_bf16(to_bf16(x[i])), from_bf16(w[i]), acc);
 #pragma unroll
-        for (int j = 0; j < kDirs; ++j) {
-            s_b[wave][j].v = bv[j];
-            s_b[wave][j].i = bi[j];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < kDirs) {
-        const int j = (int)threadIdx.x;
-        double v = s_b[0][j].v;
-        int32_t i = s_b[0][j].i;
-        for (int w = 1; w < kDirB / 64; ++w) dir_take(v, i, s_b[w][j].v, s_b[w][j].i);
-        part[(size_t)blockIdx.x * kDirs + j].v = v;
-        part[(size_t)blockIdx.x * kDirs + j].i = i;
+    for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+    if (lane == 0) {
+        acc += bias[o];
+        out[(size_t)blockIdx.y * n_out + o] = hidden ? from_bf16(to_bf16(fmaxf(acc, 0.f))) : acc;
     }
 }
+
+// The 16 directions of one row of outputs (non-finite or zero: the evenly
+// spaced direction of that slot).
+__global__ void k_mlp_dirs(const float* __restrict__ y, LearnOut* __restrict__ lo) {
+    const int t = (int)threadIdx.x;
+    if (t >= kDirs) return;
+    double ux = (double)y[2 * t], uy = (double)y[2 * t + 1];
+    if (!finite_d(ux) || !finite_d(uy) || (ux == 0.0 && uy == 0.0)) {
+        const double a = 6.283185307179586 * (double)t / (double)kDirs;
+        ux = cos(a);
+        uy = sin(a);
+    }
+    lo->y[2 * t] = y[2 * t];
+    lo->y[2 * t + 1] = y[2 * t + 1];
+    lo->dirs[2 * t] = ux;
+    lo->dirs[2 * t + 1] = uy;
+}
+
 
 // The candidates and their exact convex hull (Andrew's monotone chain on at
 // most 20 points, one thread): the discard polygon.
-__global__ void k_poly(const DirBest* __restrict__ part, int nparts, const double2* __restrict__ xy,
-                       const Params* __restrict__ prm, LearnOut* __restrict__ lo) {
+__global__ __launch_bounds__(64 * kDirs) void k_poly(const DirBest* __restrict__ part, int nparts,
+                                                    const double2* __restrict__ xy,
+                                                    const Params* __restrict__ prm,
+                                                    LearnOut* __restrict__ lo) {
     __shared__ int32_t s_c[kPolyMax];
     const int t = (int)threadIdx.x;
-    if (t < kDirs) {
+    {
+        // wave j reduces direction j over the block partials
+        const int lane = (int)__lane_id(), j = t >> 6;
         double v = -INFINITY;
         int32_t i = INT32_MAX;
-        for (int b = 0; b < nparts; ++b) dir_take(v, i, part[(size_t)b * kDirs + t].v, part[(size_t)b * kDirs + t].i);
-        s_c[4 + t] = i;
+        for (int b = lane; b < nparts; b += 64) dir_take(v, i, part[(size_t)b * kDirs + j].v, part[(size_t)b * kDirs + j].i);
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) {
+            const double ov = __shfl_xor(v, m);
+            const int32_t oi = __shfl_xor(i, m);
+            dir_take(v, i, ov, oi);
+        }
+        if (lane == 0) s_c[4 + j] = i;
     }
     if (t < 4) s_c[t] = prm->ext[t].i;
+    __syncthreads();
+    // the candidates' coordinates, loaded in parallel
+    __shared__ double s_x[kPolyMax], s_y[kPolyMax];
+    if (t < kPolyMax && s_c[t] != INT32_MAX) {
+        const double2 p = xy[s_c[t]];
+        s_x[t] = p.x;
+        s_y[t] = p.y;
+    }
     __syncthreads();
     if (t != 0) return;
     Poly Q;
@@ -291,7 +254,9 @@ __global__ void k_poly(const DirBest* __restrict__ part, int nparts, const doubl
     for (int j = 0; j < kPolyMax; ++j) {
         lo->cand[j] = s_c[j];
         if (!ok || s_c[j] == INT32_MAX) continue;
-        const double2 p = xy[s_c[j]];
+        double2 p;
+        p.x = s_x[j];
+        p.y = s_y[j];
         // insertion by (x, y), dropping repeats
         int k = nc;
         bool dup = false;
@@ -444,12 +409,10 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// master float32 [out][in] -> bfloat16 [in][out]
-__global__ void k_to_bf16t(const float* __restrict__ w, int O, int I, uint16_t* __restrict__ wt) {
+// master float32 -> bfloat16 (same [out][in] layout)
+__global__ void k_to_bf16(const float* __restrict__ w, int64_t count, uint16_t* __restrict__ wb) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)O * I) return;
-    const int o = (int)(e / I), i = (int)(e % I);
-    wt[(size_t)i * O + o] = to_bf16(w[e]);
+    if (e < count) wb[e] = to_bf16(w[e]);
 }
 
 }  // namespace
@@ -478,25 +441,28 @@ hipError_t launch_hist_to_x(const uint32_t* hist, int64_t n, float* x, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* y, LearnOut* lo,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_infer, dim3(rows), dim3(kHB), 0, s, x, W, y, lo);
+hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* h1, float* h2, float* y,
+                            LearnOut* lo, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_layer, dim3(kMlpHidden / kMlpWaves, rows), dim3(64 * kMlpWaves), 0, s, x,
+                       kMlpIn, W.w1, W.b1, kMlpHidden, 1, h1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_layer, dim3(kMlpHidden / kMlpWaves, rows), dim3(64 * kMlpWaves), 0, s, h1,
+                       kMlpHidden, W.w2, W.b2, kMlpHidden, 1, h2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_layer, dim3(kMlpOut / kMlpWaves, rows), dim3(64 * kMlpWaves), 0, s, h2,
+                       kMlpHidden, W.w3, W.b3, kMlpOut, 0, y);
+    e = hipGetLastError();
+    if (e != hipSuccess || !lo) return e;
+    hipLaunchKernelGGL(k_mlp_dirs, dim3(1), dim3(64), 0, s, y, lo);
     return hipGetLastError();
 }
 
-int dir_grid(int64_t n, int cu_count) {
-    const int64_t g = (n + (int64_t)kDirB * 4 - 1) / ((int64_t)kDirB * 4);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, (int64_t)cu_count * 4));
-}
-
-hipError_t launch_poly(const double* xy, int64_t n, const Params* prm, LearnOut* lo, void* part,
+hipError_t launch_poly(const double* xy, const Params* prm, LearnOut* lo, const DirBest* dpart,
                        int grid, hipStream_t s) {
-    DirBest* p = reinterpret_cast<DirBest*>(part);
-    hipLaunchKernelGGL(k_dir_extremes, dim3(grid), dim3(kDirB), 0, s, reinterpret_cast<const double2*>(xy),
-                       n, lo, p);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_poly, dim3(1), dim3(64), 0, s, p, grid, reinterpret_cast<const double2*>(xy), prm, lo);
+    hipLaunchKernelGGL(k_poly, dim3(1), dim3(64 * kDirs), 0, s, dpart, grid,
+                       reinterpret_cast<const double2*>(xy), prm, lo);
     return hipGetLastError();
 }
 
@@ -527,9 +493,8 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t cou
     return hipGetLastError();
 }
 
-hipError_t launch_to_bf16t(const float* w, int O, int I, uint16_t* wt, hipStream_t s) {
-    const int64_t e = (int64_t)O * I;
-    hipLaunchKernelGGL(k_to_bf16t, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, w, O, I, wt);
+hipError_t launch_to_bf16(const float* w, int64_t count, uint16_t* wb, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, w, count, wb);
     return hipGetLastError();
 }
 

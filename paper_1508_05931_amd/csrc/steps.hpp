@@ -175,22 +175,45 @@ struct Poly {
     double px[kPolyMax], py[kPolyMax], ex[kPolyMax], ey[kPolyMax];
 };
 
-// Strictly inside the polygon: strictly left of every edge.
+// Orientation of (a, b, p) with the float64 fast test against the common
+// bound (every segment and point lies in the Step-1 bounding box), else exact.
+__device__ inline int poly_orient(double ax, double ay, double bx, double by, double qb, double x,
+                                  double y) {
+    const double l = (bx - ax) * (y - ay);
+    const double r = (by - ay) * (x - ax);
+    const double det = l - r;
+    if (det > qb) return 1;
+    if (-det > qb) return -1;
+    return orient(ax, ay, bx, by, x, y);
+}
+
+// Strictly inside the polygon (strictly left of every edge), by a binary
+// search over the fan of diagonals from corner 0: p must lie strictly inside
+// the angle at corner 0, then in the wedge between the diagonals to corners
+// j and j+1, and strictly left of the edge j -> j+1.  A point on a diagonal
+// strictly before its far end is inside (the diagonal's interior lies in the
+// polygon's), which the last test decides as well.
 __device__ inline bool poly_inside(const Poly& Q, double x, double y) {
-    if (Q.nv < 3) return false;
-    for (int j = 0; j < Q.nv; ++j) {
-        const double dx = x - Q.px[j], dy = y - Q.py[j];
-        const double l = Q.ex[j] * dy;
-        const double r = Q.ey[j] * dx;
-        const double det = l - r;
-        int o = det > Q.qb ? 1 : (-det > Q.qb ? -1 : 0);
-        if (o == 0) {
-            const int j1 = j + 1 == Q.nv ? 0 : j + 1;
-            o = orient(Q.px[j], Q.py[j], Q.px[j1], Q.py[j1], x, y);
-        }
-        if (o <= 0) return false;
+    const int m = Q.nv;
+    if (m < 3) return false;
+    const double x0 = Q.px[0], y0 = Q.py[0], qb = Q.qb;
+    if (poly_orient(x0, y0, Q.px[1], Q.py[1], qb, x, y) <= 0) return false;
+    if (poly_orient(x0, y0, Q.px[m - 1], Q.py[m - 1], qb, x, y) >= 0) return false;
+    // invariant: p is left of (or on) diagonal lo, strictly right of diagonal hi
+    int lo = 1, hi = m - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (poly_orient(x0, y0, Q.px[mid], Q.py[mid], qb, x, y) >= 0) lo = mid;
+        else hi = mid;
     }
-    return true;
+    return poly_orient(Q.px[lo], Q.py[lo], Q.px[hi], Q.py[hi], qb, x, y) > 0;
+}
+
+// Larger value wins, then the smaller index (extreme point along a direction).
+__device__ inline void dir_take(double& bv, int32_t& bi, double v, int32_t i) {
+    const bool tk = (v > bv) | ((v == bv) & (i < bi));
+    bv = tk ? v : bv;
+    bi = tk ? i : bi;
 }
 
 // Step 5's distance (a heuristic choice; only needs to be reproducible):
