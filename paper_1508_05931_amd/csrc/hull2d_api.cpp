@@ -58,6 +58,8 @@ struct hull2d_ctx {
     DevStatus* h_ds = nullptr;
     double2* h_xy = nullptr;
     int32_t* h_idx = nullptr;
+    double2* h_xy_dev = nullptr;   // the same buffers as the device addresses them
+    int32_t* h_idx_dev = nullptr;
     int64_t h_cap = 0;
 
     uint32_t epoch = 0;
@@ -231,8 +233,13 @@ hull2d_status ensure_host(hull2d_ctx* c, int64_t m) {
     c->h_xy = nullptr;
     c->h_idx = nullptr;
     c->h_cap = 0;
-    if (hipHostMalloc((void**)&c->h_xy, (size_t)want * sizeof(double2), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_idx, (size_t)want * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    // mapped and coherent: the one-workgroup tail writes the kept points
+    // here directly, saving a copy and a wait
+    const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc((void**)&c->h_xy, (size_t)want * sizeof(double2), fl) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_idx, (size_t)want * sizeof(int32_t), fl) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->h_xy_dev, c->h_xy, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->h_idx_dev, c->h_idx, 0) != hipSuccess) {
         (void)hipGetLastError();
         return HULL2D_ERR_OUT_OF_MEMORY;
     }
@@ -712,10 +719,13 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     };
     bool tail_done = false;
     if (!full) {
-        // small candidate sets: one workgroup does the rest
+        // small candidate sets: one workgroup does the rest, writing the kept
+        // points straight to the host buffers (at most 2 * kTailCap of them)
+        st = ensure_host(c, 2 * (int64_t)kTailCap);
+        if (st != HULL2D_OK) return st;
         const uint32_t e = ++c->epoch;
-        HX_TRY(launch_tail(c->cand_xy, c->cand_idx, c->cand_key, c->prm, c->ds + 1, c->out_xy,
-                           c->out_idx, c->stat, c->ctr, e, s));
+        HX_TRY(launch_tail(c->cand_xy, c->cand_idx, c->cand_key, c->prm, c->ds + 1, c->h_xy_dev,
+                           c->h_idx_dev, c->stat, c->ctr, e, s));
         mark(HULL2D_STAGE_TAIL);
         st = read_status();
         if (st != HULL2D_OK) return st;
@@ -754,7 +764,7 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     st = ensure_host(c, m);
     if (st != HULL2D_OK) return st;
     auto t_d2h = std::chrono::steady_clock::now();
-    if (m > 0) {
+    if (m > 0 && !tail_done) {
         HX_TRY(hipMemcpyAsync(c->h_xy, c->out_xy, (size_t)m * sizeof(double2), hipMemcpyDeviceToHost, s));
         HX_TRY(hipMemcpyAsync(c->h_idx, c->out_idx, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }

@@ -17,6 +17,7 @@ constexpr int kExtGridMax = 4096;   // partial-result slots of Step 1
 constexpr int kF1Block = 256;
 constexpr int kF1Ipt = 4;
 constexpr int kF1Tile = kF1Block * kF1Ipt;       // points per round-1 tile
+constexpr bool kF1Prefetch = true;               // round 1 loads tile t+1 during tile t
 constexpr int kSortBlock = 256;
 constexpr int kSortIpt = 16;
 constexpr int kSortTile = kSortBlock * kSortIpt; // keys per radix tile

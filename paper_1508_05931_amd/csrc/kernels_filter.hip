@@ -194,17 +194,17 @@ __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restric
 // One block: final reduction of the partial candidates, the distinct
 // counter-clockwise corners P_minx -> P_miny -> P_maxx -> P_maxy, the pivot,
 // and the per-call reset of the status fields later kernels accumulate into.
-__global__ __launch_bounds__(256) void k_extremes_final(const Cand* __restrict__ partial, int nblocks,
+__global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict__ partial, int nblocks,
                                                         Params* __restrict__ prm,
                                                         DevStatus* __restrict__ ds) {
-    constexpr int NW = 256 / 64;
+    constexpr int NW = 1024 / 64;
     __shared__ Cand s_c[NW][4];
     __shared__ uint32_t s_flags;
     if (threadIdx.x == 0) s_flags = 0;
     __syncthreads();
     Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
     uint32_t bad = 0;
-    for (int b = (int)threadIdx.x; b < nblocks; b += 256) {
+    for (int b = (int)threadIdx.x; b < nblocks; b += 1024) {
         take_better<0>(c[0], partial[b * 4 + 0]);
         take_better<1>(c[1], partial[b * 4 + 1]);
         take_better<2>(c[2], partial[b * 4 + 2]);
@@ -302,12 +302,32 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
     uint32_t bidx = 0xFFFFFFFFu, bslot = 0xFFFFFFFFu;
     uint32_t p0c = 0;
 
-    for (int64_t base = beg; base < end; base += kF1Tile) {
-        double2 p[kF1Ipt];
+    // the next tile's points are loaded while this tile is processed
+    double2 nx[kF1Ipt];
+    if (kF1Prefetch) {
 #pragma unroll
         for (int k = 0; k < kF1Ipt; ++k) {
-            int64_t pos = base + k * kF1Block + threadIdx.x;
-            if (pos < end) p[k] = xy[pos];
+            const int64_t pos = beg + k * kF1Block + threadIdx.x;
+            if (pos < end) nx[k] = xy[pos];
+        }
+    }
+    for (int64_t base = beg; base < end; base += kF1Tile) {
+        double2 p[kF1Ipt];
+        if (kF1Prefetch) {
+#pragma unroll
+            for (int k = 0; k < kF1Ipt; ++k) p[k] = nx[k];
+            const int64_t nb = base + kF1Tile;
+#pragma unroll
+            for (int k = 0; k < kF1Ipt; ++k) {
+                const int64_t pos = nb + k * kF1Block + threadIdx.x;
+                if (pos < end) nx[k] = xy[pos];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kF1Ipt; ++k) {
+                const int64_t pos = base + k * kF1Block + threadIdx.x;
+                if (pos < end) p[k] = xy[pos];
+            }
         }
         uint64_t mask[kF1Ipt];
         uint32_t key[kF1Ipt];
@@ -863,7 +883,7 @@ hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid,
                            reinterpret_cast<const double2*>(xy), n, partial, dirs, dpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_extremes_final, dim3(1), dim3(256), 0, s, partial, grid, prm, ds);
+    hipLaunchKernelGGL(k_extremes_final, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds);
     return hipGetLastError();
 }
 

@@ -69,11 +69,18 @@ __device__ inline void reduce4_wave(Cand (&c)[4]) {
     }
 }
 
+// Input domain from the exponent bits alone (integer operations): NaN and
+// infinity have the all-ones exponent; 0 < |v| < 2^-300 has a biased
+// exponent below 723 (subnormals included); |v| > 2^300 has exponent 1324 or
+// more, or exponent 1323 with a non-zero mantissa.
 __device__ inline uint32_t domain_flags(double v) {
-    double a = fabs(v);
-    if (!(a <= DBL_MAX)) return kFlagNonfinite;
-    if (a != 0.0 && (a < 0x1p-300 || a > 0x1p300)) return kFlagRange;
-    return 0u;
+    const uint64_t b = (uint64_t)__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFull;
+    const uint32_t hi = (uint32_t)(b >> 32);
+    const uint32_t e = hi >> 20;
+    const bool nonfinite = e == 0x7FFu;
+    const bool tiny = (b != 0) & (e < 723u);
+    const bool huge = (b > 0x52B0000000000000ull) & !nonfinite;  // 2^300 = 0x52B0000000000000
+    return (nonfinite ? kFlagNonfinite : 0u) | ((tiny | huge) ? kFlagRange : 0u);
 }
 
 __device__ inline void offer(Cand (&c)[4], double x, double y, int32_t i) {
