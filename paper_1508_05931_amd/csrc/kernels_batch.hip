@@ -15,9 +15,10 @@
 //               as a max-scan, and the stable removal
 //   Step 8      the Graham scan of the kept points (pivot first): chunks are
 //               reduced in parallel to the hull of P_0 and the chunk, which
-//               keeps every vertex of the whole hull, until one thread
-//               finishes the rest; the hull is rotated to its lexicographic
-//               minimum and written as set-local indices
+//               keeps every vertex of the whole hull (in HBM while more than
+//               2048 points are left, then in LDS), until one thread
+//               finishes the last few; the hull is rotated to its
+//               lexicographic minimum and written as set-local indices
 //
 // Everything a set needs lives in its own slice [offset, offset + n) of the
 // workspace arrays, so sets never interfere.  A set whose equal-key runs are
@@ -36,7 +37,8 @@ constexpr int kBW = kBB / 64;           // waves
 constexpr int kBI = 4;                  // items per thread per tile
 constexpr int kBT = kBB * kBI;          // items per tile
 constexpr int kBLongMax = 64;           // equal-key runs longer than kRunSmall per region
-constexpr uint32_t kGFinal = 2048;      // Step 8: one thread finishes below this size
+constexpr uint32_t kGLds = 2048;        // Step 8: below this size the points move to LDS
+constexpr uint32_t kGOne = 64;          // Step 8: one thread finishes below this size
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 struct alignas(16) BatchLds {
@@ -52,6 +54,11 @@ struct alignas(16) BatchLds {
             Rec r[kRunCap];
             uint16_t p[kRunCap];
         } run;
+        struct {
+            double x[kGLds], y[kGLds];  // kept points still in play
+            uint32_t pos[kGLds];        // their kept-list positions
+            uint16_t a[kGLds], b[kGLds], c[kGLds];
+        } gs;
     } u;
     Cand ext[kBW][4];
     double wx[kBW], wy[kBW];
@@ -490,6 +497,38 @@ __device__ uint32_t graham_run(const double2* K, const uint32_t* A, uint32_t beg
     return top;
 }
 
+// graham_run on points staged in LDS (positions are u16 indices into x, y).
+__device__ uint32_t graham_lds(const double* __restrict__ gx, const double* __restrict__ gy,
+                               const uint16_t* A, uint32_t beg, uint32_t end, uint16_t* st, double x0,
+                               double y0) {
+    uint32_t top = 0;
+    double tx = x0, ty = y0, sx = x0, sy = y0;
+    for (uint32_t i = beg; i < end; ++i) {
+        const uint32_t pos = A ? A[i] : i;
+        const double px = gx[pos], py = gy[pos];
+        if (px == tx && py == ty) continue;
+        while (top >= 1) {
+            if (orient(sx, sy, tx, ty, px, py) > 0) break;
+            --top;
+            tx = sx;
+            ty = sy;
+            if (top >= 2) {
+                sx = gx[st[top - 2]];
+                sy = gy[st[top - 2]];
+            } else {
+                sx = x0;
+                sy = y0;
+            }
+        }
+        st[top++] = (uint16_t)pos;
+        sx = tx;
+        sy = ty;
+        tx = px;
+        ty = py;
+    }
+    return top;
+}
+
 // ---------------------------------------------------------------------------
 // One set, start to end.
 // ---------------------------------------------------------------------------
@@ -522,12 +561,19 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
     if (tid == 0) S.flags = 0;
     Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
     uint32_t bad = 0;
+    double2 nx[kBI];  // the next tile, loaded while this one is processed
+#pragma unroll
+    for (int k = 0; k < kBI; ++k) {
+        const uint32_t i = (uint32_t)(k * kBB + tid);
+        if (i < n) nx[k] = xy[i];
+    }
     for (uint32_t b0 = 0; b0 < n; b0 += kBT) {
         double2 p[kBI];
 #pragma unroll
         for (int k = 0; k < kBI; ++k) {
-            const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
-            if (i < n) p[k] = xy[i];
+            p[k] = nx[k];
+            const uint32_t i = b0 + kBT + (uint32_t)(k * kBB + tid);
+            if (i < n) nx[k] = xy[i];
         }
 #pragma unroll
         for (int k = 0; k < kBI; ++k) {
@@ -783,12 +829,14 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
         }
     }
 
-    // ---- Step 8: reduce chunks in parallel, then one thread
+    // ---- Step 8: reduce chunks in parallel (in HBM while many points are
+    //      left, then in LDS), then one thread
     uint32_t* cur_a = nullptr;  // positions into the kept list (null: all of them)
     uint32_t len = m;
     uint32_t* bufs[3] = {ka, kb, va};
     int nb = 0;
-    while (len > kGFinal) {
+    bool stuck = false;
+    while (len > kGLds && !stuck) {
         const uint32_t ch = max(16u, (len + kBB - 1) / kBB);
         uint32_t* st = bufs[nb % 3] == cur_a ? bufs[(nb + 1) % 3] : bufs[nb % 3];
         uint32_t* dst = nullptr;
@@ -800,18 +848,57 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
         const uint32_t at = bexcl(h, S, tot);
         for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
         __syncthreads();
-        const bool stuck = (uint64_t)tot * 10u > (uint64_t)len * 9u;
+        stuck = (uint64_t)tot * 10u > (uint64_t)len * 9u;
         cur_a = dst;
         len = tot;
         ++nb;
-        if (stuck) break;
     }
-    uint32_t* fin = ka;
-    for (int q = 0; q < 3; ++q)
-        if (bufs[q] != cur_a) fin = bufs[q];
-    if (tid == 0) S.h = graham_run(sv_xy, cur_a, 0, len, fin, x0, y0) + 1u;
+    const bool in_lds = len <= kGLds;
+    uint32_t* fin = ka;       // final stack (HBM path)
+    uint16_t* fin16 = nullptr;  // final stack (LDS path)
+    if (in_lds) {
+        for (uint32_t i = (uint32_t)tid; i < len; i += kBB) {
+            const uint32_t pos = cur_a ? cur_a[i] : i;
+            const double2 q = sv_xy[pos];
+            S.u.gs.x[i] = q.x;
+            S.u.gs.y[i] = q.y;
+            S.u.gs.pos[i] = pos;
+        }
+        __syncthreads();
+        uint16_t* cur = nullptr;
+        uint16_t* b16[3] = {S.u.gs.a, S.u.gs.b, S.u.gs.c};
+        int k = 0;
+        bool stk = false;
+        while (len > kGOne && !stk) {
+            const uint32_t ch = max(8u, (len + kBB - 1) / kBB);
+            uint16_t* st = b16[k % 3] == cur ? b16[(k + 1) % 3] : b16[k % 3];
+            uint16_t* dst = nullptr;
+            for (int q = 0; q < 3; ++q)
+                if (b16[q] != cur && b16[q] != st) dst = b16[q];
+            const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
+            const uint32_t h = graham_lds(S.u.gs.x, S.u.gs.y, cur, beg, end, st + beg, x0, y0);
+            uint32_t tot;
+            const uint32_t at = bexcl(h, S, tot);
+            for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
+            __syncthreads();
+            stk = (uint64_t)tot * 10u > (uint64_t)len * 9u;
+            cur = dst;
+            len = tot;
+            ++k;
+        }
+        fin16 = S.u.gs.a;
+        for (int q = 0; q < 3; ++q)
+            if (b16[q] != cur) fin16 = b16[q];
+        if (tid == 0) S.h = graham_lds(S.u.gs.x, S.u.gs.y, cur, 0, len, fin16, x0, y0) + 1u;
+    } else {
+        for (int q = 0; q < 3; ++q)
+            if (bufs[q] != cur_a) fin = bufs[q];
+        if (tid == 0) S.h = graham_run(sv_xy, cur_a, 0, len, fin, x0, y0) + 1u;
+    }
     __syncthreads();
     const uint32_t h = S.h;
+    // stack entry k >= 1: its point and its kept-list position
+    auto vpos = [&](uint32_t k) -> uint32_t { return in_lds ? S.u.gs.pos[fin16[k - 1]] : fin[k - 1]; };
     // canonical start: the lexicographically smallest vertex (P_0 is entry 0)
     {
         double bx = INFINITY, by = INFINITY;
@@ -821,6 +908,9 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
             if (k == 0) {
                 x = x0;
                 y = y0;
+            } else if (in_lds) {
+                x = S.u.gs.x[fin16[k - 1]];
+                y = S.u.gs.y[fin16[k - 1]];
             } else {
                 const double2 q = sv_xy[fin[k - 1]];
                 x = q.x;
@@ -861,7 +951,7 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
     const uint32_t start = S.start, at = S.hpos;
     for (uint32_t k = (uint32_t)tid; k < h; k += kBB) {
         const uint32_t e = (start + k) % h;
-        A.hull[at + k] = e == 0 ? p0_idx : (int32_t)sv_idx[fin[e - 1]];
+        A.hull[at + k] = e == 0 ? p0_idx : (int32_t)sv_idx[vpos(e)];
     }
     if (tid == 0) {
         A.h_count[s] = (int32_t)h;
@@ -871,7 +961,7 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBB) void k_batch(BatchArgs A) {
+__global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchArgs A) {
     __shared__ BatchLds S;
     uint32_t* counter = &A.ctr->ticket[16 * kTicketBatch];
     const uint32_t players = gridDim.x;
