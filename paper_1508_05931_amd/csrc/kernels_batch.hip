@@ -579,7 +579,9 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
         for (int k = 0; k < kBI; ++k) {
             const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
             if (i < n) {
-                offer(c, p[k].x, p[k].y, (int32_t)i);
+                const bool need = (p[k].x <= c[0].x) | (p[k].y <= c[1].y) | (p[k].x >= c[2].x) |
+                                  (p[k].y >= c[3].y);
+                if (need) offer(c, p[k].x, p[k].y, (int32_t)i);
                 bad |= domain_flags(p[k].x) | domain_flags(p[k].y);
             }
         }

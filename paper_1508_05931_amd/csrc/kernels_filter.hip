@@ -128,7 +128,11 @@ __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restric
         for (int u = 0; u < U; ++u) {
             int64_t j = i + u * stride;
             if (j < n) {
-                offer(c, p[u].x, p[u].y, (int32_t)j);
+                // only a point at or beyond one of the four current bests can
+                // change one (exact: ties go through the full comparison)
+                const bool need = (p[u].x <= c[0].x) | (p[u].y <= c[1].y) | (p[u].x >= c[2].x) |
+                                  (p[u].y >= c[3].y);
+                if (need) offer(c, p[u].x, p[u].y, (int32_t)j);
                 bad |= domain_flags(p[u].x) | domain_flags(p[u].y);
                 // this thread's indices only grow: a tie keeps the earlier point
 #pragma unroll
