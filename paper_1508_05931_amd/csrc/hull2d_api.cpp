@@ -44,8 +44,9 @@ struct hull2d_ctx {
     double2* cand_xy = nullptr;   // round-2 candidates of the bucketed filter
     uint32_t* cand_idx = nullptr;
     uint32_t* cand_key = nullptr;
+    uint32_t* cand_kap = nullptr;
     uint32_t* part = nullptr;     // per-block bucket maxima
-    uint32_t* bmax = nullptr;
+    uint32_t* bmax = nullptr;     // sampled bucket maxima, then those over the candidates
     uint32_t* prefix = nullptr;
     uint32_t* seg_count = nullptr;  // round-1 segments (one per filter block)
     uint32_t* seg_off = nullptr;
@@ -122,7 +123,7 @@ constexpr int kMaxSegs = 8192;  // round-1 blocks (resident blocks of the whole 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t off[26];
+    size_t off[27];
     size_t total;
 };
 
@@ -134,7 +135,7 @@ Layout plan(int64_t n, int parts) {
     stat_words = std::max(stat_words, f1_tiles + 2);
     stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kR2Tile) + 4);
     stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kCpTile) + 2);
-    const size_t sizes[26] = {
+    const size_t sizes[27] = {
         (size_t)kExtGridMax * 4 * sizeof(Cand),      // 0 partial
         sizeof(Params),                              // 1
         2 * sizeof(DevStatus),                       // 2 round-1 problem, candidate problem
@@ -160,10 +161,11 @@ Layout plan(int64_t n, int parts) {
         2 * kBuckets * sizeof(uint32_t),             // 22 bmax
         2 * kBuckets * sizeof(uint32_t),             // 23 prefix
         (size_t)kMaxSegs * sizeof(uint32_t),         // 24 seg_count
-        (size_t)kMaxSegs * sizeof(uint32_t)};        // 25 seg_off
+        (size_t)kMaxSegs * sizeof(uint32_t),         // 25 seg_off
+        N * sizeof(uint32_t)};                       // 26 cand_kap
     Layout L{};
     size_t o = 0;
-    for (int i = 0; i < 26; ++i) {
+    for (int i = 0; i < 27; ++i) {
         L.off[i] = o;
         o = align_up(o + sizes[i], 256);
     }
@@ -215,6 +217,7 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
     c->prefix = (uint32_t*)(b + L.off[23]);
     c->seg_count = (uint32_t*)(b + L.off[24]);
     c->seg_off = (uint32_t*)(b + L.off[25]);
+    c->cand_kap = (uint32_t*)(b + L.off[26]);
     // Look-back words carry the call's epoch; zero means "not ready" for any epoch.
     if (hipMemsetAsync(c->stat, 0, L.off[11] - L.off[10], c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -657,7 +660,8 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
                                  c->parts, s));
         HX_TRY(launch_bucket_scan(c->part, c->parts, c->bmax, c->prefix, ds2, s));
         HX_TRY(launch_prefilter(n, segs, c->seg_count, c->comp_xy, c->comp_idx, c->keys_a, c->prm,
-                                c->ds, c->prefix, c->cand_xy, c->cand_idx, c->cand_key, ds2, s));
+                                c->ds, c->prefix, c->cand_xy, c->cand_idx, c->cand_key, c->cand_kap,
+                                c->bmax, ds2, s));
         pds = ds2;
         pxy = c->cand_xy;
         pidx = c->cand_idx;
@@ -719,13 +723,14 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     };
     bool tail_done = false;
     if (!full) {
-        // small candidate sets: one workgroup does the rest, writing the kept
-        // points straight to the host buffers (at most 2 * kTailCap of them)
+        // small candidate sets: one workgroup per region does the rest,
+        // writing the kept points straight to the host buffers (at most
+        // kTailCap per region)
         st = ensure_host(c, 2 * (int64_t)kTailCap);
         if (st != HULL2D_OK) return st;
         const uint32_t e = ++c->epoch;
-        HX_TRY(launch_tail(c->cand_xy, c->cand_idx, c->cand_key, c->prm, c->ds + 1, c->h_xy_dev,
-                           c->h_idx_dev, c->stat, c->ctr, e, s));
+        HX_TRY(launch_tail(c->cand_xy, c->cand_idx, c->cand_key, c->cand_kap, c->bmax, c->prm,
+                           c->ds + 1, c->h_xy_dev, c->h_idx_dev, c->stat, c->ctr, e, s));
         mark(HULL2D_STAGE_TAIL);
         st = read_status();
         if (st != HULL2D_OK) return st;

@@ -33,6 +33,7 @@ constexpr int kHistGridMax = 512;
 constexpr int kMlpIn = 1024, kMlpHidden = 256, kMlpOut = 32, kMlpDirs = 16;  // learned filter
 constexpr int kTailBlock = 1024;                 // the one-workgroup tail
 constexpr int kTailCap = 12288;                  // candidates per region it sorts in LDS
+constexpr uint32_t kTailSlots = 65536;           // candidates it reads (16-bit slots)
 constexpr int kBatchBlock = 512;                 // threads per set in the batched kernel
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -106,13 +107,18 @@ constexpr int kBmBlock = 512;
 hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
                              const uint32_t* keys, const Params* prm, DevStatus* ds, uint32_t* part,
                              int parts, hipStream_t s);
-// Steps 4 and 6-7 plus the stable removal for a candidate set small enough
-// for one workgroup per region (kTailCap each); otherwise sets tail_state to
-// kTailOverflow in ds2 and writes nothing else that the other path needs.
-// pub: one look-back status word (the right region's kept count).
+// The exact prefix maxima from `exact` (the bucket maxima over the
+// candidates, 2 x kBuckets), the candidates they select (cand_kap: their
+// kappa), then Steps 4 and 6-7 plus the stable removal, for a
+// candidate set small enough for one workgroup per region (at most
+// kTailSlots candidates, at most kTailCap selected per region); otherwise
+// sets tail_state to kTailOverflow in ds2 and writes nothing else that the
+// other path needs.  pub: one look-back status word (the right region's
+// kept count).
 hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
-                       const Params* prm, DevStatus* ds2, double2* out_xy, int32_t* out_idx,
-                       uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s);
+                       const uint32_t* cand_kap, const uint32_t* exact, const Params* prm,
+                       DevStatus* ds2, double2* out_xy, int32_t* out_idx, uint64_t* pub, Counters* ctr,
+                       uint32_t epoch, hipStream_t s);
 // The batched form: one persistent launch, each workgroup computing whole
 // hulls of the sets in `order` (device, S entries); per set s, its points are
 // xy[offs[s], offs[s+1]) and its workspace the same range of every array.
@@ -179,8 +185,9 @@ hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, u
                               DevStatus* ds2, hipStream_t s);
 hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
                             const uint32_t* comp_idx, const uint32_t* keys, const Params* prm,
-                            const DevStatus* ds, const uint32_t* prefix, double2* cand_xy,
-                            uint32_t* cand_idx, uint32_t* cand_key, DevStatus* ds2, hipStream_t s);
+                            DevStatus* ds, const uint32_t* prefix, double2* cand_xy,
+                            uint32_t* cand_idx, uint32_t* cand_key, uint32_t* cand_kap, uint32_t* exact,
+                            DevStatus* ds2, hipStream_t s);
 
 // Step 4: digit histograms, four stable radix passes, exact order inside
 // equal-key runs.

@@ -30,13 +30,18 @@ constexpr int kPfBlock = 256;
 constexpr int kPfItems = 4;    // points loaded per thread before any is used
 constexpr int kPfCap = 4096;   // LDS slots buffered per block before a flush
 constexpr int kBmItems = 4;
+constexpr uint32_t kBmSample = 8;  // bucket maxima from 1/8 of each segment
 
 __device__ inline Params load_params(const Params* __restrict__ prm) { return *prm; }
 
 // Per-block maxima of kappa per (region, bucket) into LDS, written out as one
-// table per block; also counts the right region.  Each block takes a
-// contiguous range; every thread loads kBmItems points before it uses any of
-// them, so enough loads are in flight to cover the memory latency.
+// table per block, over a sample: the first 1/kBmSample of each segment's
+// survivors.  Prefix maxima of a table built from any subset of the points
+// are lower bounds of the exact ones, so the candidates they select include
+// every point the exact table selects (the one-workgroup tail narrows them
+// to exactly those).  Each block takes a contiguous range of segments; every
+// thread loads kBmItems points before it uses any of them, so enough loads
+// are in flight to cover the memory latency.
 __global__ __launch_bounds__(kBmBlock) void k_bucket_max(int64_t chunk, int segs,
                                                         const uint32_t* __restrict__ seg_count,
                                                         const double2* __restrict__ comp_xy,
@@ -45,17 +50,15 @@ __global__ __launch_bounds__(kBmBlock) void k_bucket_max(int64_t chunk, int segs
                                                         DevStatus* __restrict__ ds,
                                                         uint32_t* __restrict__ part) {
     __shared__ uint32_t s_tab[2 * kBuckets];
-    __shared__ uint32_t s_right;
     for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += kBmBlock) s_tab[i] = 0;
-    if (threadIdx.x == 0) s_right = 0;
     __syncthreads();
     const Params P = load_params(prm);
     const int spb = (segs + (int)gridDim.x - 1) / (int)gridDim.x;
     const int sg_end = min(segs, ((int)blockIdx.x + 1) * spb);
-    uint32_t nr = 0;
     for (int sg = (int)blockIdx.x * spb; sg < sg_end; ++sg) {
+    // a sample: the first 1/kBmSample of the segment
     const uint32_t beg = (uint32_t)(sg * chunk);
-    const uint32_t end = beg + seg_count[sg];
+    const uint32_t end = beg + (seg_count[sg] + kBmSample - 1) / kBmSample;
     for (uint32_t base = beg; base < end; base += kBmBlock * kBmItems) {
         double2 p[kBmItems];
         uint32_t k[kBmItems];
@@ -72,21 +75,14 @@ __global__ __launch_bounds__(kBmBlock) void k_bucket_max(int64_t chunk, int segs
             uint32_t s = base + u * kBmBlock + threadIdx.x;
             if (s < end) {
                 Cls c = classify(p[u].x, p[u].y, k[u], P);
-                if (c.region != 2) {
-                    nr += c.region == 0;
-                    atomicMax(&s_tab[c.region * kBuckets + c.bucket], c.kappa);
-                }
+                if (c.region != 2) atomicMax(&s_tab[c.region * kBuckets + c.bucket], c.kappa);
             }
         }
     }
     }
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) nr += __shfl_xor(nr, m);
-    if (__lane_id() == 0 && nr) atomicAdd(&s_right, nr);
     __syncthreads();
     uint32_t* out = part + (size_t)blockIdx.x * 2 * kBuckets;
     for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += kBmBlock) out[i] = s_tab[i];
-    if (threadIdx.x == 0 && s_right) atomicAdd(&ds->n_right, s_right);
 }
 
 // Column maxima of the per-block tables: a block takes 64 columns, its four
@@ -106,47 +102,17 @@ __global__ __launch_bounds__(256) void k_bucket_reduce(const uint32_t* __restric
 
 // Exclusive prefix maxima in walking order: ascending buckets for the right
 // region (starting from kappa(P_0) = 0), descending for the left region
-// (identity 0).  One block of 1024 threads, four buckets per thread.  Also
-// resets the status of the candidate problem.
-__global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict__ bmax,
+// (identity 0).  One block of 1024 threads, four buckets per thread.  Then
+// clears the table for the bucket maxima over the candidates, and resets the
+// status of the candidate problem.
+__global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ bmax,
                                                       uint32_t* __restrict__ prefix,
                                                       DevStatus* __restrict__ ds2) {
-    constexpr int PER = kBuckets / 1024;
     __shared__ uint32_t s_w[16];
-    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
-    for (int region = 0; region < 2; ++region) {
-        // walking position w = threadIdx.x*PER + k maps to bucket b(w)
-        uint32_t v[PER];
-        uint32_t tmax = 0;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            int w = (int)threadIdx.x * PER + k;
-            int b = region == 0 ? w : kBuckets - 1 - w;
-            v[k] = bmax[region * kBuckets + b];
-            tmax = max(tmax, v[k]);
-        }
-        // exclusive scan of the thread maxima
-        uint32_t inc = tmax;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            uint32_t o = __shfl_up(inc, d);
-            if (lane >= d) inc = max(inc, o);
-        }
-        uint32_t ex = __shfl_up(inc, 1);
-        if (lane == 0) ex = 0;
-        if (lane == 63) s_w[wave] = inc;
-        __syncthreads();
-        for (int w = 0; w < wave; ++w) ex = max(ex, s_w[w]);
-        __syncthreads();
-        uint32_t run = ex;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            int w = (int)threadIdx.x * PER + k;
-            int b = region == 0 ? w : kBuckets - 1 - w;
-            prefix[region * kBuckets + b] = run;
-            run = max(run, v[k]);
-        }
-    }
+    for (int region = 0; region < 2; ++region)
+        bucket_prefix<1024>(bmax + region * kBuckets, prefix + region * kBuckets, region, s_w);
+    // every read of bmax precedes the barriers inside bucket_prefix
+    for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += 1024) bmax[i] = 0;
     if (threadIdx.x == 0) {
         ds2->flags = 0;
         ds2->huge_runs = 0;
@@ -162,19 +128,24 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* __restrict
 }
 
 // Candidates: P_l and its copies, and every point whose kappa reaches the
-// prefix maximum of its bucket.  Buffered per block in LDS, then appended
-// with one atomic per flush (their order does not matter: they are sorted
-// next).
+// prefix maximum of its bucket, each with its kappa (0 for P_l and its
+// copies).  Buffered per block in LDS, then appended with one atomic per
+// flush (their order does not matter: they are sorted next).  Also the
+// bucket maxima over the candidates (`exact`, cleared beforehand) and the
+// size of the right region (the points before P_l in angular order).
 __global__ __launch_bounds__(kPfBlock) void k_prefilter(
     int64_t chunk, const uint32_t* __restrict__ seg_count,
     const double2* __restrict__ comp_xy, const uint32_t* __restrict__ comp_idx,
     const uint32_t* __restrict__ keys, const Params* __restrict__ prm,
-    const DevStatus* __restrict__ ds, const uint32_t* __restrict__ prefix,
+    DevStatus* __restrict__ ds, const uint32_t* __restrict__ prefix,
     double2* __restrict__ cand_xy, uint32_t* __restrict__ cand_idx, uint32_t* __restrict__ cand_key,
-    DevStatus* __restrict__ ds2) {
-    __shared__ uint32_t s_buf[kPfCap];
-    __shared__ uint32_t s_n, s_base;
-    if (threadIdx.x == 0) s_n = 0;
+    uint32_t* __restrict__ cand_kap, uint32_t* __restrict__ exact, DevStatus* __restrict__ ds2) {
+    __shared__ uint32_t s_buf[kPfCap], s_kap[kPfCap];
+    __shared__ uint32_t s_n, s_base, s_right;
+    if (threadIdx.x == 0) {
+        s_n = 0;
+        s_right = 0;
+    }
     __syncthreads();
     const Params P = load_params(prm);
     const uint32_t lslot = ds->l_slot;
@@ -191,12 +162,14 @@ __global__ __launch_bounds__(kPfBlock) void k_prefilter(
             cand_xy[o] = comp_xy[s];
             cand_idx[o] = comp_idx[s];
             cand_key[o] = keys[s];
+            cand_kap[o] = s_kap[i];
             if (s == lslot) ds2->l_slot = o;
         }
         __syncthreads();
         if (threadIdx.x == 0) s_n = 0;
         __syncthreads();
     };
+    uint32_t nr = 0;
     for (uint32_t base = beg; base < end; base += kPfBlock * kPfItems) {
         double2 p[kPfItems];
         uint32_t k[kPfItems];
@@ -215,13 +188,25 @@ __global__ __launch_bounds__(kPfBlock) void k_prefilter(
                 Cls c = classify(p[u].x, p[u].y, k[u], P);
                 const bool keep = (c.region == 2) ||
                                   (c.kappa >= prefix[(c.region & 1) * kBuckets + c.bucket]);
-                if (keep) s_buf[atomicAdd(&s_n, 1u)] = s;
+                nr += c.region == 0;
+                if (keep) {
+                    const uint32_t at = atomicAdd(&s_n, 1u);
+                    s_buf[at] = s;
+                    s_kap[at] = c.kappa;
+                    if (c.region < 2 && c.kappa != 0u)
+                        atomicMax(&exact[c.region * kBuckets + c.bucket], c.kappa);
+                }
             }
         }
         __syncthreads();
         if (s_n > (uint32_t)(kPfCap - kPfBlock * kPfItems)) flush();
     }
     flush();
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) nr += __shfl_xor(nr, m);
+    if (__lane_id() == 0 && nr) atomicAdd(&s_right, nr);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_right) atomicAdd(&ds->n_right, s_right);
 }
 
 }  // namespace
@@ -245,10 +230,12 @@ hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, u
 
 hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
                             const uint32_t* comp_idx, const uint32_t* keys, const Params* prm,
-                            const DevStatus* ds, const uint32_t* prefix, double2* cand_xy,
-                            uint32_t* cand_idx, uint32_t* cand_key, DevStatus* ds2, hipStream_t s) {
+                            DevStatus* ds, const uint32_t* prefix, double2* cand_xy,
+                            uint32_t* cand_idx, uint32_t* cand_key, uint32_t* cand_kap, uint32_t* exact,
+                            DevStatus* ds2, hipStream_t s) {
     hipLaunchKernelGGL(k_prefilter, dim3(segs), dim3(kPfBlock), 0, s, filter1_chunk(n, segs), seg_count,
-                       comp_xy, comp_idx, keys, prm, ds, prefix, cand_xy, cand_idx, cand_key, ds2);
+                       comp_xy, comp_idx, keys, prm, ds, prefix, cand_xy, cand_idx, cand_key, cand_kap,
+                       exact, ds2);
     return hipGetLastError();
 }
 

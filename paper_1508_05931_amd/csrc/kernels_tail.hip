@@ -1,16 +1,21 @@
 // kernels_tail.hip - the end of the bucketed path in one workgroup.
 //
 // After the bucketed filter the second round only has a small candidate set
-// left (typically a few thousand points per region).  For such a set the
-// multi-kernel sort, the look-back scan of Steps 6-7 and the compaction are
-// dominated by launch gaps and look-back latency, so two workgroups of 1024
-// threads do all of it, one region each, with the region's keys and slots in
-// LDS and every global access issued in batches (the run time is a handful of
-// memory latencies):
+// left (a few ten thousand points at most on uniform inputs of 20M points).
+// For such a set the multi-kernel sort, the look-back scan of Steps 6-7 and
+// the compaction are dominated by launch gaps and look-back latency, so two
+// workgroups of 1024 threads do all of it, one region each, with the
+// region's keys and slots in LDS and every global access issued in batches
+// (the run time is a handful of memory latencies):
 //
-//   1. collect the region's candidates: the right region is every candidate
-//      before P_l in the exact angular order of Step 4, the left region is
-//      P_l and every candidate after it;
+//   0. the exact prefix maxima of the region's buckets in walking order,
+//      from the bucket maxima over the candidates (the candidates were
+//      selected with bucket maxima over a sample of the survivors, so they
+//      are a superset of those the exact table selects);
+//   1. collect the region's candidates that reach the prefix maximum of
+//      their bucket: the right region is every candidate before P_l in the
+//      exact angular order of Step 4, the left region is P_l and every
+//      candidate after it;
 //   2. Step 4 on them: a stable LSD radix sort of (angle key, slot), four
 //      passes of 8 bits with wave-level match masks, then the exact order
 //      inside runs of equal keys (one thread per short run, the whole
@@ -24,12 +29,15 @@
 //      one's count; the workgroups take the regions in ticket order, so the
 //      one waited for is always running).
 //
-// A region with more than kTailCap candidates, more than kTailLongMax long
-// runs or a run longer than kRunCap sets tail_state = kTailOverflow and the
-// host runs the multi-kernel path instead; the result is the same.
+// More than kTailSlots candidates, a region with more than kTailCap selected
+// points, more than kTailLongMax long runs or a run longer than kRunCap sets
+// tail_state = kTailOverflow and the host runs the multi-kernel path on all
+// candidates instead; the result is the same (points that are not running
+// maxima never change the walk).
 #include "exact.hpp"
 #include "kernels.hpp"
 #include "records.hpp"
+#include "steps.hpp"
 
 namespace hx {
 namespace {
@@ -133,6 +141,8 @@ constexpr uint32_t kTailPubOverflow = 0xFFFFFFFFu;  // the right region did not 
 __global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_xy,
                                               const uint32_t* __restrict__ cand_idx,
                                               const uint32_t* __restrict__ cand_key,
+                                              const uint32_t* __restrict__ cand_kap,
+                                              const uint32_t* __restrict__ exact,
                                               const Params* __restrict__ prm,
                                               DevStatus* __restrict__ ds2,
                                               double2* __restrict__ out_xy,
@@ -168,58 +178,97 @@ __global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_x
         if (tid == 0 && region == 1) ds2->n_kept = 0;
         return;  // nobody waits: the left workgroup needs no count
     }
-    if (nc > 2u * (uint32_t)kTailCap || lslot >= nc) {
+    if (nc > kTailSlots || lslot >= nc) {
         give_up();
         return;
     }
     const Rec rl = rec_load(lslot, cand_xy, cand_idx);
 
-    // ---- 1. collect this region's candidates (keys loaded kTI at a time)
+    // Whether candidate i (angle key `key`) lies in this workgroup's region
+    // (right: before P_l in the exact angular order; left: P_l and after),
+    // and whether it is a copy of P_l (always kept).
+    auto in_region = [&](uint32_t i, uint32_t key, bool& copy) -> bool {
+        bool before;
+        copy = false;
+        if (key != kl) {
+            before = key < kl;
+        } else if (i == lslot) {
+            before = false;
+            copy = true;
+        } else {
+            const Rec r = rec_load(i, cand_xy, cand_idx);
+            before = rec_less(r, rl, x0, y0);
+            copy = (r.x == rl.x) & (r.y == rl.y);
+        }
+        return before == (region == 0);
+    };
+
+    // ---- 0. the exact prefix maxima of this region: the candidates hold
+    //         every running maximum of the walk (they were selected with
+    //         lower bounds of the prefix maxima), and every prefix maximum is
+    //         attained at a running maximum, so the bucket maxima over the
+    //         candidates (`exact`, built while they were selected) give the
+    //         exact prefix maxima.  The table lives in the second key buffer
+    //         until the sort needs it.
+    uint32_t* tab = S.key[1];
+    bucket_prefix<kTB>(exact + region * kBuckets, tab, region, S.wsum);
     if (tid == 0) {
         S.count = 0;
         S.nlong = 0;
     }
     __syncthreads();
-    for (uint32_t base = 0; base < nc; base += (uint32_t)(kTB * kTI)) {
-        uint32_t kv[kTI];
+
+    // ---- 1. collect this region's candidates that reach the prefix maximum
+    //         of their bucket (keys loaded kTI at a time, the next batch
+    //         while the current one is placed; one LDS atomic per wave and
+    //         batch)
+    constexpr uint32_t kStep = (uint32_t)(kTB * kTI);
+    uint32_t kv[kTI], kp[kTI];
+#pragma unroll
+    for (int k = 0; k < kTI; ++k) {
+        const uint32_t i = (uint32_t)(k * kTB + tid);
+        kv[k] = i < nc ? cand_key[i] : 0u;
+        kp[k] = i < nc ? cand_kap[i] : 0u;
+    }
+    for (uint32_t base = 0; base < nc; base += kStep) {
+        uint32_t nkv[kTI], nkp[kTI];
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            const uint32_t i = base + kStep + (uint32_t)(k * kTB + tid);
+            nkv[k] = i < nc ? cand_key[i] : 0u;
+            nkp[k] = i < nc ? cand_kap[i] : 0u;
+        }
+        uint64_t mk[kTI];
+        uint32_t tot = 0;
 #pragma unroll
         for (int k = 0; k < kTI; ++k) {
             const uint32_t i = base + (uint32_t)(k * kTB + tid);
-            kv[k] = i < nc ? cand_key[i] : 0u;
+            bool copy = false;
+            const bool mine = i < nc && in_region(i, kv[k], copy) &&
+                              (copy || kp[k] >= tab[kv[k] >> (32 - kBucketBits)]);
+            mk[k] = __ballot(mine);
+            tot += (uint32_t)__popcll(mk[k]);
         }
-        bool mine[kTI];
-#pragma unroll
-        for (int k = 0; k < kTI; ++k) {
-            const uint32_t i = base + (uint32_t)(k * kTB + tid);
-            mine[k] = false;
-            if (i < nc) {
-                bool before;
-                if (kv[k] != kl) {
-                    before = kv[k] < kl;
-                } else if (i == lslot) {
-                    before = false;
-                } else {
-                    const Rec r = rec_load(i, cand_xy, cand_idx);
-                    before = rec_less(r, rl, x0, y0);
-                }
-                mine[k] = before == (region == 0);
-            }
-        }
-        // one LDS atomic per wave and item slot (a single counter shared by
-        // every thread would serialise)
-#pragma unroll
-        for (int k = 0; k < kTI; ++k) {
-            const uint64_t m = __ballot(mine[k]);
-            if (m == 0) continue;
-            const int leader = __ffsll((unsigned long long)m) - 1;
+        if (tot) {
             uint32_t at = 0;
-            if (lane == leader) at = atomicAdd(&S.count, (uint32_t)__popcll(m));
-            at = __shfl(at, leader) + (uint32_t)__popcll(m & lanemask_lt());
-            const uint32_t i = base + (uint32_t)(k * kTB + tid);
-            if (mine[k] && at < (uint32_t)kTailCap) {
-                S.key[0][at] = kv[k];
-                S.ix[0][at] = (uint16_t)i;
+            if (lane == 0) at = atomicAdd(&S.count, tot);
+            at = __shfl(at, 0);
+            const uint64_t lt = lanemask_lt();
+#pragma unroll
+            for (int k = 0; k < kTI; ++k) {
+                const uint32_t i = base + (uint32_t)(k * kTB + tid);
+                const uint32_t q = at + (uint32_t)__popcll(mk[k] & lt);
+                if (((mk[k] >> lane) & 1ull) && q < (uint32_t)kTailCap) {
+                    S.key[0][q] = kv[k];
+                    S.ix[0][q] = (uint16_t)i;
+                }
+                at += (uint32_t)__popcll(mk[k]);
             }
+        }
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            kv[k] = nkv[k];
+            kp[k] = nkp[k];
         }
     }
     __syncthreads();
@@ -520,10 +569,11 @@ __global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_x
 }  // namespace
 
 hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
-                       const Params* prm, DevStatus* ds2, double2* out_xy, int32_t* out_idx,
-                       uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s) {
-    hipLaunchKernelGGL(k_tail, dim3(2), dim3(kTB), 0, s, cand_xy, cand_idx, cand_key, prm, ds2,
-                       out_xy, out_idx, pub, ctr, epoch);
+                       const uint32_t* cand_kap, const uint32_t* exact, const Params* prm,
+                       DevStatus* ds2, double2* out_xy, int32_t* out_idx, uint64_t* pub, Counters* ctr,
+                       uint32_t epoch, hipStream_t s) {
+    hipLaunchKernelGGL(k_tail, dim3(2), dim3(kTB), 0, s, cand_xy, cand_idx, cand_key, cand_kap, exact,
+                       prm, ds2, out_xy, out_idx, pub, ctr, epoch);
     return hipGetLastError();
 }
 

@@ -269,4 +269,44 @@ __device__ inline Cls classify(double x, double y, uint32_t key, const Params& P
     return c;
 }
 
+// Exclusive prefix maxima of one region's bucket maxima in walking order:
+// ascending buckets for the right region (starting from kappa(P_0) = 0),
+// descending for the left region (identity 0).  Called by all kT threads of
+// a workgroup; `in` and `out` may be the same array (every read precedes
+// the first barrier, every write follows the last); `s_w` holds kT / 64
+// words of LDS.
+template <int kT>
+__device__ inline void bucket_prefix(const uint32_t* in, uint32_t* out, int region, uint32_t* s_w) {
+    constexpr int PER = kBuckets / kT;
+    static_assert(kBuckets % kT == 0, "whole buckets per thread");
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    uint32_t v[PER];
+    uint32_t tmax = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int w = (int)threadIdx.x * PER + k;  // walking position
+        v[k] = in[region == 0 ? w : kBuckets - 1 - w];
+        tmax = max(tmax, v[k]);
+    }
+    uint32_t inc = tmax;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d);
+        if (lane >= d) inc = max(inc, o);
+    }
+    uint32_t ex = __shfl_up(inc, 1);
+    if (lane == 0) ex = 0;
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) ex = max(ex, s_w[w]);
+    __syncthreads();
+    uint32_t run = ex;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int w = (int)threadIdx.x * PER + k;
+        out[region == 0 ? w : kBuckets - 1 - w] = run;
+        run = max(run, v[k]);
+    }
+}
+
 }  // namespace hx
