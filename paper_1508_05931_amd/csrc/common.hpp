@@ -130,4 +130,20 @@ __device__ inline uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Lanes of the wave whose `valid` 8-bit digit equals this lane's: one ballot
+// per bit, each folded in as "the lanes whose bit equals mine" with the
+// lane's sign-extended bit (two 32-bit halves, no per-lane select).
+__device__ inline uint64_t match_digit8(uint32_t dig, bool valid) {
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int32_t f = (int32_t)(dig << (31 - b)) >> 31;  // all ones when bit b is set
+        const uint64_t bb = __ballot(f < 0);
+        lo &= ~((uint32_t)bb ^ (uint32_t)f);
+        hi &= ~((uint32_t)(bb >> 32) ^ (uint32_t)f);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
 }  // namespace hx

@@ -114,6 +114,10 @@ __host__ __device__ inline int orient(double ax, double ay, double bx, double by
     double bound = kOrientBound * (fabs(l) + fabs(r));
     if (det > bound) return 1;
     if (-det > bound) return -1;
+    // A difference of two doubles rounds to zero only when they are equal,
+    // so when each product has a zero factor the determinant is exactly
+    // zero (repeated points, and the walk's own maximum compared with itself).
+    if (((acx == 0.0) | (bcy == 0.0)) & ((acy == 0.0) | (bcx == 0.0))) return 0;
     return orient_exact(ax, ay, bx, by, cx, cy);
 }
 

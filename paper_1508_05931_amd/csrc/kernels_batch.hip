@@ -140,16 +140,6 @@ __device__ inline uint32_t wave_append(bool mine, uint32_t* counter) {
     return __shfl(at, leader) + (uint32_t)__popcll(m & lanemask_lt());
 }
 
-__device__ inline uint64_t bmatch(uint32_t dig, bool valid) {
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const uint64_t bb = __ballot((dig >> b) & 1u);
-        m &= ((dig >> b) & 1u) ? bb : ~bb;
-    }
-    return m;
-}
-
 struct BPt {
     double x, y;
     bool v;
@@ -241,7 +231,7 @@ __device__ int wg_radix(BatchLds& S, uint32_t* k0, uint32_t* v0, uint32_t* k1, u
                 const uint32_t p = t0 + (uint32_t)(wave * 64 * kBI + k * 64 + lane);
                 const bool valid = p < cnt;
                 const uint32_t dig = (key[k] >> shift) & 0xFFu;
-                const uint64_t m = bmatch(dig, valid);
+                const uint64_t m = match_digit8(dig, valid);
                 uint32_t prior = 0;
                 if (valid) prior = S.u.rs.wc[wave][dig];
                 const uint32_t below = (uint32_t)__popcll(m & lanemask_lt());

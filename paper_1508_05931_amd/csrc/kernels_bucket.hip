@@ -128,8 +128,10 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ bma
 }
 
 // Candidates: P_l and its copies, and every point whose kappa reaches the
-// prefix maximum of its bucket, each with its kappa (0 for P_l and its
-// copies).  Buffered per block in LDS, then appended with one atomic per
+// prefix maximum of its bucket, each with its kappa (all ones for P_l and
+// its copies: seen from P_l they have no direction, so the exact test keeps
+// each of them; they come last in the left region's walk, where a maximal
+// key keeps them too).  Buffered per block in LDS, then appended with one atomic per
 // flush (their order does not matter: they are sorted next).  Also the
 // bucket maxima over the candidates (`exact`, cleared beforehand) and the
 // size of the right region (the points before P_l in angular order).
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(kPfBlock) void k_prefilter(
                 if (keep) {
                     const uint32_t at = atomicAdd(&s_n, 1u);
                     s_buf[at] = s;
-                    s_kap[at] = c.kappa;
+                    s_kap[at] = c.region == 2 ? 0xFFFFFFFFu : c.kappa;
                     if (c.region < 2 && c.kappa != 0u)
                         atomicMax(&exact[c.region * kBuckets + c.bucket], c.kappa);
                 }

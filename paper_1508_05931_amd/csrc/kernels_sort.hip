@@ -122,12 +122,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(
             uint32_t p = base + wave * 64 * IPT + k * 64 + lane;
             const bool valid = p < ms;
             uint32_t dig = (key[k] >> shift) & 0xFFu;
-            uint64_t m = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                uint64_t bb = __ballot((dig >> b) & 1u);
-                m &= ((dig >> b) & 1u) ? bb : ~bb;
-            }
+            const uint64_t m = match_digit8(dig, valid);
             uint32_t prior = 0;
             if (valid) prior = s_wc[wave][dig];
             uint32_t below = (uint32_t)__popcll(m & lanemask_lt());

@@ -59,41 +59,46 @@ struct alignas(16) TailLds {
     uint32_t dbase[kRadixT];       // digit totals, then digit bases
     uint32_t wsum[kTW];
     uint32_t longs[kTailLongMax];
-    double wx[kTW], wy[kTW];       // wave aggregates of the round-2 scan
-    uint32_t wv[kTW];
+    uint32_t wk[kTW], ws[kTW];     // wave aggregates of the round-2 scan
     uint32_t count, nlong, total, runlen;
 };
 
-struct TPt {
-    double x, y;
-    bool v;  // false: the identity (nothing walked yet)
+// A walked item: its direction key seen from P_l in the region's walking
+// order (larger follows) and its candidate slot (kSlotP0: P_0, whose key is
+// 0; kSlotNone: the identity, nothing walked yet).
+struct KPt {
+    uint32_t k, s;
 };
+constexpr uint32_t kSlotNone = 0xFFFFFFFFu;
+constexpr uint32_t kSlotP0 = 0xFFFFFFFEu;
 
-__device__ inline TPt tpt_none() {
-    TPt p;
-    p.x = 0.0;
-    p.y = 0.0;
-    p.v = false;
+__device__ inline KPt kpt_none() {
+    KPt p;
+    p.k = 0;
+    p.s = kSlotNone;
     return p;
 }
 
-// Later of a and b in the walk's order seen from P_l (sgn +1: right region,
-// -1: left region); straight-line selects.
-__device__ inline TPt tmax(const TPt& a, const TPt& b, double lx, double ly, int sgn) {
-    const int o = orient(lx, ly, a.x, a.y, b.x, b.y);
-    const bool take_b = (!a.v) | (b.v & (sgn * o >= 0));
-    TPt r;
-    r.x = take_b ? b.x : a.x;
-    r.y = take_b ? b.y : a.y;
-    r.v = take_b ? b.v : a.v;
-    return r;
+// Whether b follows a in the walk (sgn +1: right region, -1: left region),
+// i.e. b becomes the running maximum.  A larger key follows strictly (the
+// key is a monotone quantisation of the exact direction); equal keys fall
+// back to the exact orientation seen from P_l, collinear counting as
+// following.
+__device__ inline bool kpt_follows(const KPt& a, const KPt& b, const double2* __restrict__ cand_xy,
+                                   double x0, double y0, double lx, double ly, int sgn) {
+    if (b.s == kSlotNone) return false;
+    if (a.s == kSlotNone) return true;
+    if (a.k != b.k) return b.k > a.k;
+    if (a.s == b.s) return true;
+    const double2 pa = a.s == kSlotP0 ? make_double2(x0, y0) : cand_xy[a.s];
+    const double2 pb = b.s == kSlotP0 ? make_double2(x0, y0) : cand_xy[b.s];
+    return sgn * orient(lx, ly, pa.x, pa.y, pb.x, pb.y) >= 0;
 }
 
-__device__ inline TPt shfl_up_tpt(const TPt& p, int d) {
-    TPt r;
-    r.x = __shfl_up(p.x, d);
-    r.y = __shfl_up(p.y, d);
-    r.v = __shfl_up((int)p.v, d) != 0;
+__device__ inline KPt shfl_up_kpt(const KPt& p, int d) {
+    KPt r;
+    r.k = __shfl_up(p.k, d);
+    r.s = __shfl_up(p.s, d);
     return r;
 }
 
@@ -105,17 +110,6 @@ __device__ inline uint32_t wsum_incl(uint32_t v) {
         if (lane >= off) v += o;
     }
     return v;
-}
-
-// Lanes of the wave whose `valid` digit equals this lane's (8 ballots).
-__device__ inline uint64_t match_digit(uint32_t dig, bool valid) {
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const uint64_t bb = __ballot((dig >> b) & 1u);
-        m &= ((dig >> b) & 1u) ? bb : ~bb;
-    }
-    return m;
 }
 
 // Exclusive block sum (all threads call it; `total` gets the block total).
@@ -299,18 +293,20 @@ __global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_x
         }
 #pragma unroll
         for (int k = 0; k < kTI; ++k) {
-            const uint32_t p = (uint32_t)(wave * 64 * ipt + k * 64 + lane);
-            const bool valid = k < ipt && p < cnt;
-            const uint32_t dig = (key[k] >> shift) & 0xFFu;
-            const uint64_t m = match_digit(dig, valid);
-            uint32_t prior = 0;
-            if (valid) prior = S.wc[wave][dig];
-            const uint32_t below = (uint32_t)__popcll(m & lanemask_lt());
-            // every lane has read its counter before the leaders move it
-            __builtin_amdgcn_wave_barrier();
-            if (valid && below == 0u) S.wc[wave][dig] = (uint16_t)(prior + (uint32_t)__popcll(m));
-            __builtin_amdgcn_wave_barrier();
-            rank[k] = prior + below;
+            if (k < ipt) {  // uniform: the ballots below need every lane
+                const uint32_t p = (uint32_t)(wave * 64 * ipt + k * 64 + lane);
+                const bool valid = p < cnt;
+                const uint32_t dig = (key[k] >> shift) & 0xFFu;
+                const uint64_t m = match_digit8(dig, valid);
+                uint32_t prior = 0;
+                if (valid) prior = S.wc[wave][dig];
+                const uint32_t below = (uint32_t)__popcll(m & lanemask_lt());
+                // every lane has read its counter before the leaders move it
+                __builtin_amdgcn_wave_barrier();
+                if (valid && below == 0u) S.wc[wave][dig] = (uint16_t)(prior + (uint32_t)__popcll(m));
+                __builtin_amdgcn_wave_barrier();
+                rank[k] = prior + below;
+            }
         }
         __syncthreads();
         // digit d: wave prefixes and total
@@ -437,81 +433,64 @@ __global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_x
 
     // ---- 3. Steps 6-7.  Walk index w = tid*ipt + k.  Right region: position
     //         w, after P_0.  Left region: position cnt-1-w; P_l (position 0)
-    //         is not walked and always kept.  The items stay in registers
-    //         through step 4.
+    //         is not walked and always kept.  Each item is its (kappa, slot):
+    //         larger kappa follows, so the scan is integer work except on
+    //         equal keys.
     const uint32_t nwalk = region == 0 ? cnt : cnt - 1;
     auto walk_pos = [&](uint32_t w) -> uint32_t { return region == 0 ? w : cnt - 1 - w; };
-    TPt agg = tpt_none();
-    {
-        double2 v[kTI];
+    auto follows = [&](const KPt& a, const KPt& b) -> bool {
+        return kpt_follows(a, b, cand_xy, x0, y0, lx, ly, sgn);
+    };
+    KPt it[kTI];
 #pragma unroll
-        for (int k = 0; k < kTI; ++k) {
-            const uint32_t w = (uint32_t)(tid * ipt + k);
-            if (k < ipt && w < nwalk) v[k] = cand_xy[xx[walk_pos(w)]];
-        }
-#pragma unroll
-        for (int k = 0; k < kTI; ++k) {
-            const uint32_t w = (uint32_t)(tid * ipt + k);
-            if (k < ipt && w < nwalk) {
-                TPt q;
-                q.x = v[k].x;
-                q.y = v[k].y;
-                q.v = true;
-                agg = tmax(agg, q, lx, ly, sgn);
-            }
-        }
+    for (int k = 0; k < kTI; ++k) {
+        const uint32_t w = (uint32_t)(tid * ipt + k);
+        it[k].s = (k < ipt && w < nwalk) ? (uint32_t)xx[walk_pos(w)] : kSlotNone;
     }
-    TPt inc = agg;
+#pragma unroll
+    for (int k = 0; k < kTI; ++k) it[k].k = it[k].s != kSlotNone ? cand_kap[it[k].s] : 0u;
+    KPt agg = kpt_none();
+#pragma unroll
+    for (int k = 0; k < kTI; ++k)
+        if (follows(agg, it[k])) agg = it[k];
+    KPt inc = agg;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        const TPt o = shfl_up_tpt(inc, d);
-        if (lane >= d) inc = tmax(o, inc, lx, ly, sgn);
+        const KPt o = shfl_up_kpt(inc, d);
+        if (lane >= d && !follows(o, inc)) inc = o;
     }
-    TPt ex = shfl_up_tpt(inc, 1);
-    if (lane == 0) ex = tpt_none();
+    KPt ex = shfl_up_kpt(inc, 1);
+    if (lane == 0) ex = kpt_none();
     if (lane == 63) {
-        S.wx[wave] = inc.x;
-        S.wy[wave] = inc.y;
-        S.wv[wave] = inc.v ? 1u : 0u;
+        S.wk[wave] = inc.k;
+        S.ws[wave] = inc.s;
     }
     __syncthreads();
-    TPt run = tpt_none();
-    if (region == 0) {
-        run.x = x0;
-        run.y = y0;
-        run.v = true;
-    }
+    KPt run = kpt_none();
+    if (region == 0) run.s = kSlotP0;  // kappa(P_0) = 0
     for (int w = 0; w < wave; ++w) {
-        TPt o;
-        o.x = S.wx[w];
-        o.y = S.wy[w];
-        o.v = S.wv[w] != 0u;
-        run = tmax(run, o, lx, ly, sgn);
+        KPt o;
+        o.k = S.wk[w];
+        o.s = S.ws[w];
+        if (follows(run, o)) run = o;
     }
-    run = tmax(run, ex, lx, ly, sgn);
+    if (follows(run, ex)) run = ex;
     uint32_t kmask = 0;
-    double2 v[kTI];  // loaded again (cache hits) rather than held across the scan
+#pragma unroll
+    for (int k = 0; k < kTI; ++k) {
+        if (it[k].s != kSlotNone && follows(run, it[k])) {
+            kmask |= 1u << k;
+            run = it[k];
+        }
+    }
+    // the kept points' coordinates and indices (one batch of loads)
+    double2 v[kTI];
     uint32_t id[kTI];
 #pragma unroll
     for (int k = 0; k < kTI; ++k) {
-        const uint32_t w = (uint32_t)(tid * ipt + k);
-        if (k < ipt && w < nwalk) {
-            const uint32_t sl = xx[walk_pos(w)];
-            v[k] = cand_xy[sl];
-            id[k] = cand_idx[sl];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kTI; ++k) {
-        const uint32_t w = (uint32_t)(tid * ipt + k);
-        if (k < ipt && w < nwalk) {
-            TPt q;
-            q.x = v[k].x;
-            q.y = v[k].y;
-            q.v = true;
-            const bool kp = (!run.v) || sgn * orient(lx, ly, run.x, run.y, q.x, q.y) >= 0;
-            kmask |= kp ? (1u << k) : 0u;
-            run = tmax(run, q, lx, ly, sgn);
+        if ((kmask >> k) & 1u) {
+            v[k] = cand_xy[it[k].s];
+            id[k] = cand_idx[it[k].s];
         }
     }
 
