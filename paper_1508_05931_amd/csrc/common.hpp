@@ -35,6 +35,7 @@ struct Params {
 
 constexpr uint32_t kTailDone = 0u;
 constexpr uint32_t kTailOverflow = 1u;
+constexpr uint32_t kTailUnset = 0xFFFFFFFFu;  // host side: not yet written by the tail
 
 constexpr uint32_t kFlagNonfinite = 1u;
 constexpr uint32_t kFlagRange = 2u;
@@ -71,6 +72,7 @@ enum TicketId {
     kTicketCompact = 5,
     kTicketTail = 6,
     kTicketBatch = 7,
+    kTicketTailDone = 8,
 };
 
 constexpr int kBucketBits = 12;                 // coarse angle buckets of the bucketed round 2

@@ -55,8 +55,10 @@ struct hull2d_ctx {
     int parts = 0;
     Counters* ctr = nullptr;  // separate allocation, zeroed once, persists
 
-    // pinned host buffers (h_ds holds the two problem statuses)
+    // pinned host buffers (h_ds holds the two problem statuses; the tail
+    // writes them itself through h_ds_dev)
     DevStatus* h_ds = nullptr;
+    DevStatus* h_ds_dev = nullptr;
     double2* h_xy = nullptr;
     int32_t* h_idx = nullptr;
     double2* h_xy_dev = nullptr;   // the same buffers as the device addresses them
@@ -547,14 +549,19 @@ hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
     c->occ = query_occupancy();
     if (hipMalloc((void**)&c->ctr, sizeof(Counters)) != hipSuccess ||
         hipMemset(c->ctr, 0, sizeof(Counters)) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_ds, 2 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_ds, 2 * sizeof(DevStatus),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->h_ds_dev, c->h_ds, 0) != hipSuccess) {
         (void)hipGetLastError();
         hull2d_destroy(c);
         return HULL2D_ERR_OUT_OF_MEMORY;
     }
+    // Stage events only time the stream (the host waits on ev_sync): without
+    // the system-scope fence a record does not write back and invalidate the
+    // caches, which otherwise idles the device for several microseconds.
     bool ev_ok = true;
     for (int i = 0; i < HULL2D_NUM_STAGES + 2; ++i)
-        ev_ok = ev_ok && hipEventCreate(&c->ev[i]) == hipSuccess;
+        ev_ok = ev_ok && hipEventCreateWithFlags(&c->ev[i], hipEventDisableSystemFence) == hipSuccess;
     c->have_events = ev_ok;
     if (hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
@@ -729,11 +736,19 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
         st = ensure_host(c, 2 * (int64_t)kTailCap);
         if (st != HULL2D_OK) return st;
         const uint32_t e = ++c->epoch;
+        c->h_ds[1].tail_state = kTailUnset;  // the kernel overwrites it
         HX_TRY(launch_tail(c->cand_xy, c->cand_idx, c->cand_key, c->cand_kap, c->bmax, c->prm,
-                           c->ds + 1, c->h_xy_dev, c->h_idx_dev, c->stat, c->ctr, e, s));
+                           c->ds, c->h_xy_dev, c->h_idx_dev, c->h_ds_dev, c->stat, c->ctr, e, s));
         mark(HULL2D_STAGE_TAIL);
-        st = read_status();
-        if (st != HULL2D_OK) return st;
+        // the tail leaves the kept points and both statuses in host memory:
+        // one wait ends the call unless the candidates did not fit
+        if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
+        HX_TRY(spin_sync(c));
+        if (c->h_ds[1].tail_state == kTailUnset) {
+            // not written: read the statuses the usual way
+            st = read_status();
+            if (st != HULL2D_OK) return st;
+        }
         tail_done = c->h_ds[1].tail_state == kTailDone;
     }
     if (!tail_done) {
@@ -769,14 +784,18 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     st = ensure_host(c, m);
     if (st != HULL2D_OK) return st;
     auto t_d2h = std::chrono::steady_clock::now();
-    if (m > 0 && !tail_done) {
-        HX_TRY(hipMemcpyAsync(c->h_xy, c->out_xy, (size_t)m * sizeof(double2), hipMemcpyDeviceToHost, s));
-        HX_TRY(hipMemcpyAsync(c->h_idx, c->out_idx, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (!tail_done) {
+        if (m > 0) {
+            HX_TRY(hipMemcpyAsync(c->h_xy, c->out_xy, (size_t)m * sizeof(double2),
+                                  hipMemcpyDeviceToHost, s));
+            HX_TRY(hipMemcpyAsync(c->h_idx, c->out_idx, (size_t)m * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s));
+        }
+        mark(HULL2D_STAGE_D2H);
+        if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
+        HX_TRY(spin_sync(c));
     }
-    mark(HULL2D_STAGE_D2H);
-    if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
-    HX_TRY(spin_sync(c));
-    const double ms_d2h_wall = ms_since(t_d2h);
+    const double ms_d2h_wall = tail_done ? 0.0 : ms_since(t_d2h);
 
     auto t_scan = std::chrono::steady_clock::now();
     std::vector<int64_t>& stk = c->stk;

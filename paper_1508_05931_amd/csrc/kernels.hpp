@@ -114,11 +114,12 @@ hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, con
 // kTailSlots candidates, at most kTailCap selected per region); otherwise
 // sets tail_state to kTailOverflow in ds2 and writes nothing else that the
 // other path needs.  pub: one look-back status word (the right region's
-// kept count).
+// kept count).  ds: the round-1 status and the candidate status after it;
+// host_ds: host memory (device-visible) that receives both at the end.
 hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
                        const uint32_t* cand_kap, const uint32_t* exact, const Params* prm,
-                       DevStatus* ds2, double2* out_xy, int32_t* out_idx, uint64_t* pub, Counters* ctr,
-                       uint32_t epoch, hipStream_t s);
+                       DevStatus* ds, double2* out_xy, int32_t* out_idx, DevStatus* host_ds,
+                       uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s);
 // The batched form: one persistent launch, each workgroup computing whole
 // hulls of the sets in `order` (device, S entries); per set s, its points are
 // xy[offs[s], offs[s+1]) and its workspace the same range of every array.

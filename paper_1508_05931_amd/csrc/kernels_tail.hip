@@ -132,18 +132,16 @@ __device__ inline uint32_t block_excl_sum(uint32_t v, TailLds& S, uint32_t& tota
 
 constexpr uint32_t kTailPubOverflow = 0xFFFFFFFFu;  // the right region did not fit
 
-__global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_xy,
-                                              const uint32_t* __restrict__ cand_idx,
-                                              const uint32_t* __restrict__ cand_key,
-                                              const uint32_t* __restrict__ cand_kap,
-                                              const uint32_t* __restrict__ exact,
-                                              const Params* __restrict__ prm,
-                                              DevStatus* __restrict__ ds2,
-                                              double2* __restrict__ out_xy,
-                                              int32_t* __restrict__ out_idx,
-                                              uint64_t* __restrict__ pub, Counters* __restrict__ ctr,
-                                              uint32_t epoch) {
-    __shared__ TailLds S;
+// One workgroup's part (every return is uniform over the workgroup).
+__device__ __forceinline__ void tail_body(const double2* __restrict__ cand_xy,
+                                          const uint32_t* __restrict__ cand_idx,
+                                          const uint32_t* __restrict__ cand_key,
+                                          const uint32_t* __restrict__ cand_kap,
+                                          const uint32_t* __restrict__ exact,
+                                          const Params* __restrict__ prm,
+                                          DevStatus* __restrict__ ds2, double2* __restrict__ out_xy,
+                                          int32_t* __restrict__ out_idx, uint64_t* __restrict__ pub,
+                                          Counters* __restrict__ ctr, uint32_t epoch, TailLds& S) {
     const int tid = (int)threadIdx.x;
     const int lane = (int)__lane_id(), wave = tid >> 6;
     if (tid == 0) {
@@ -545,14 +543,45 @@ __global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_x
     }
 }
 
+// The two workgroups, then the second of them to finish copies both problem
+// statuses (round 1 and candidates) to host memory, so that the host needs
+// no copy of its own after the tail.
+__global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_xy,
+                                              const uint32_t* __restrict__ cand_idx,
+                                              const uint32_t* __restrict__ cand_key,
+                                              const uint32_t* __restrict__ cand_kap,
+                                              const uint32_t* __restrict__ exact,
+                                              const Params* __restrict__ prm,
+                                              DevStatus* __restrict__ ds, double2* __restrict__ out_xy,
+                                              int32_t* __restrict__ out_idx,
+                                              DevStatus* __restrict__ host_ds,
+                                              uint64_t* __restrict__ pub, Counters* __restrict__ ctr,
+                                              uint32_t epoch) {
+    __shared__ TailLds S;
+    tail_body(cand_xy, cand_idx, cand_key, cand_kap, exact, prm, ds + 1, out_xy, out_idx, pub, ctr,
+              epoch, S);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // this workgroup's status writes before its ticket
+        uint32_t* done = &ctr->ticket[16 * kTicketTailDone];
+        if (take_ticket(done) == 1u) {
+            reset_ticket(done);
+            __threadfence();  // the other workgroup's writes after its ticket
+            const volatile uint32_t* src = reinterpret_cast<const volatile uint32_t*>(ds);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(host_ds);
+            for (int i = 0; i < (int)(2 * sizeof(DevStatus) / sizeof(uint32_t)); ++i) dst[i] = src[i];
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
                        const uint32_t* cand_kap, const uint32_t* exact, const Params* prm,
-                       DevStatus* ds2, double2* out_xy, int32_t* out_idx, uint64_t* pub, Counters* ctr,
-                       uint32_t epoch, hipStream_t s) {
+                       DevStatus* ds, double2* out_xy, int32_t* out_idx, DevStatus* host_ds,
+                       uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s) {
     hipLaunchKernelGGL(k_tail, dim3(2), dim3(kTB), 0, s, cand_xy, cand_idx, cand_key, cand_kap, exact,
-                       prm, ds2, out_xy, out_idx, pub, ctr, epoch);
+                       prm, ds, out_xy, out_idx, host_ds, pub, ctr, epoch);
     return hipGetLastError();
 }
 
