@@ -181,7 +181,8 @@ hull2d_status hull2d_load_weights(hull2d_ctx* ctx, const char* path);
 hull2d_status hull2d_get_weights(hull2d_ctx* ctx, float* h_params, int64_t count);
 
 /* The network input of a point set: 32 x 32 occupancy histogram of the
- * sample (points i with ((i >> 8) & 15) == 0) over the sample's bounding box,
+ * sample (all points when n <= 4096, else 16 blocks of 256 consecutive points,
+ * block b starting at floor(b n / 16)) over the sample's bounding box,
  * cell (cy * 32 + cx), each count times 1024 / (sample size).  d_xy device
  * float64 [n][2]; d_x device float32 [1024].  Synchronous. */
 hull2d_status hull2d_histogram(hull2d_ctx* ctx, const double* d_xy, int64_t n, float* d_x);

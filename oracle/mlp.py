@@ -95,9 +95,13 @@ def forward_bf16(flat, x):
 
 
 def sample_index(n: int) -> np.ndarray:
-    """The histogram's sample: every 16th block of 256 consecutive points."""
-    i = np.arange(n)
-    return i[((i >> 8) & 15) == 0]
+    """The histogram's sample: all points when n <= 4096, else 16 blocks of
+    256 consecutive points, block b starting at floor(b * n / 16) (4096
+    points whatever n; for n = 65536 every 16th block of 256)."""
+    if n <= 4096:
+        return np.arange(n)
+    starts = [(b * n) // 16 for b in range(16)]
+    return np.concatenate([np.arange(st, st + 256) for st in starts])
 
 
 def histogram(xy) -> np.ndarray:

@@ -3,8 +3,8 @@
 //
 // Proposal (per hull, before the first round):
 //   k_sample_bbox, k_sample_hist  32 x 32 occupancy histogram of a sample
-//                                 (every 16th block of 256 points) over the
-//                                 sample's bounding box
+//                                 (16 evenly spaced blocks of 256 points)
+//                                 over the sample's bounding box
 //   k_mlp_layer ×3, k_mlp_dirs    1024 -> 256 -> 256 -> 32 network, bfloat16
 //                                 weights and layer inputs, float32 sums, one
 //                                 wave per output unit: 16 directions
@@ -38,15 +38,15 @@ __device__ inline uint16_t to_bf16(float f) {
 }
 __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// The sample: point i with ((i >> 8) & 15) == 0; sample position s maps to
-// i = (s >> 8) * 4096 + (s & 255).
-__device__ inline int64_t sample_point(int64_t s) { return (s >> 8) * 4096 + (s & 255); }
+// The sample: every point when n <= 4096, otherwise 16 blocks of 256
+// consecutive points, block b starting at floor(b n / 16): 4096 points for
+// any larger n, so the network reads histograms of one density whatever the
+// set size (a 65,536-point set gives every 16th block of 256).  Sample
+// position s maps to point (s >> 8) n / 16 + (s & 255).
+__host__ __device__ inline int64_t sample_size(int64_t n) { return n < 4096 ? n : 4096; }
 
-__host__ __device__ inline int64_t sample_slots(int64_t n) { return ((n + 4095) / 4096) * 256; }
-
-__host__ __device__ inline int64_t sample_size(int64_t n) {
-    const int64_t full = n / 4096, rem = n - full * 4096;
-    return full * 256 + (rem < 256 ? rem : 256);
+__device__ inline int64_t sample_point(int64_t s, int64_t n) {
+    return n <= 4096 ? s : ((s >> 8) * n) / 16 + (s & 255);
 }
 
 __global__ __launch_bounds__(kHB) void k_sample_bbox(const double2* __restrict__ xy, int64_t n,
@@ -56,10 +56,10 @@ __global__ __launch_bounds__(kHB) void k_sample_bbox(const double2* __restrict__
     if (blockIdx.x == 0)
         for (int i = (int)threadIdx.x; i < kMlpIn; i += kHB) hist[i] = 0;
     double lo_x = INFINITY, lo_y = INFINITY, hi_x = -INFINITY, hi_y = -INFINITY;
-    const int64_t slots = sample_slots(n);
+    const int64_t slots = sample_size(n);
     for (int64_t s = (int64_t)blockIdx.x * kHB + threadIdx.x; s < slots; s += (int64_t)gridDim.x * kHB) {
-        const int64_t i = sample_point(s);
-        if (i < n) {
+        const int64_t i = sample_point(s, n);
+        {
             const double2 p = xy[i];
             lo_x = fmin(lo_x, p.x);
             lo_y = fmin(lo_y, p.y);
@@ -148,10 +148,10 @@ __global__ __launch_bounds__(kHB) void k_sample_hist(const double2* __restrict__
 binned:
     __syncthreads();
     const double lo_x = s_box[0], lo_y = s_box[1], sx = s_box[2], sy = s_box[3];
-    const int64_t slots = sample_slots(n);
+    const int64_t slots = sample_size(n);
     for (int64_t s = (int64_t)blockIdx.x * kHB + threadIdx.x; s < slots; s += (int64_t)gridDim.x * kHB) {
-        const int64_t i = sample_point(s);
-        if (i < n) {
+        const int64_t i = sample_point(s, n);
+        {
             const double2 p = xy[i];
             atomicAdd(&s_h[cell_of(p.y, lo_y, sy) * 32 + cell_of(p.x, lo_x, sx)], 1u);
         }
@@ -421,7 +421,7 @@ __global__ void k_to_bf16(const float* __restrict__ w, int64_t count, uint16_t* 
 // launchers
 // ---------------------------------------------------------------------------
 int learned_grid(int64_t n, int cu_count) {
-    const int64_t g = (sample_slots(n) + kHB - 1) / kHB;
+    const int64_t g = (sample_size(n) + kHB - 1) / kHB;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cu_count));
 }
 

@@ -181,7 +181,8 @@ def main(argv=None):
         "format": "HULL2D_MLP_PARAMS little-endian float32: W1[256][1024] b1[256] W2[256][256] "
                   "b2[256] W3[32][256] b3[32]",
         "shapes": {"in": N_IN, "hidden": [N_H, N_H], "out": N_OUT, "directions": K},
-        "histogram": "32x32 occupancy of points i with ((i>>8)&15)==0 over their bounding box, "
+        "histogram": "32x32 occupancy of the sample (all points when n <= 4096, else 16 blocks "
+                     "of 256 consecutive points starting at floor(b*n/16)) over its bounding box, "
                      "count*1024/sample_size, cell = cy*32+cx",
         "train_sets": f"{args.sets} mixture sets of {args.points} points, streams (1000+i, 2)",
         "eval_sets": f"{args.eval_sets} mixture sets of {args.points} points, streams (2000+i, 2)",

@@ -123,6 +123,16 @@ def test_histogram_definition():
     assert h.shape == (1024,) and abs(float(h.sum()) - 1024.0) < 1e-2
     s = mlp.sample_index(65_536)
     assert s.size == 4096 and s[0] == 0 and s[255] == 255 and s[256] == 4096
+    # every 16th block of 256 at this size
+    i = np.arange(65_536)
+    assert np.array_equal(s, i[((i >> 8) & 15) == 0])
+    # 4096 points at any larger size, blocks at floor(b n / 16), inside [0, n)
+    for n in (4097, 100_003, 20_000_000):
+        t = mlp.sample_index(n)
+        assert t.size == 4096 and np.all(np.diff(t) > 0) and t[-1] < n
+        assert [int(t[256 * b]) for b in (1, 7, 15)] == [n // 16, 7 * n // 16, 15 * n // 16]
+    assert np.array_equal(mlp.sample_index(4096), np.arange(4096))
+    assert np.array_equal(mlp.sample_index(37), np.arange(37))
     # the sample's four extreme coordinates land in the corner cells' rows / columns
     q = pts[s]
     assert h.reshape(32, 32)[:, 0].sum() > 0 and h.reshape(32, 32)[:, 31].sum() > 0
