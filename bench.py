@@ -34,19 +34,19 @@ PAPER_MS_SQUARE_DISK_20M = 446.4 + 418.1
 # kernel and `traffic` is null.
 TRAFFIC = {
     "filter1": {
-        "bytes": 536_100_000,  # 320.4 MB fetched + 215.7 MB written
+        "bytes": 535_700_000,  # 320.4 MB fetched + 215.3 MB written
         "profile": "profiles/hull_square_disk_20M_hbm_counters.md",
         "sources": {
             "paper_1508_05931_amd/csrc/kernels_filter.hip":
-                "6d2bed648f1220833fa5592e48d70ea88506fe658c821c2d513b85088399c42c",
+                "41ff5acd3a3dd0d37cc6b0c6d8b9daf59c57c96ae25d41f943a7df7a0419af2e",
             "paper_1508_05931_amd/csrc/steps.hpp":
-                "061f425d5156acfaf0ca11853ad0fb47c35a5629c30b912c2a3fd083b79f16af",
+                "3769217f35918d9f1ce83dbc71915cc697f0d1bc7e5a2036fe61156b5dbdb72f",
             "paper_1508_05931_amd/csrc/exact.hpp":
-                "7f48b015bed6a41be070153b2472d7c7a215c3cd311bae3684ba9262af659081",
+                "492fba6ee743cba0bb741d699072aaffa58163bfd2ddf06fa43db6642a3a9861",
             "paper_1508_05931_amd/csrc/common.hpp":
-                "4b00ea1c65565b2f7b09d40210d031a8dab3a8f1a246b9c63af7da04fd0e8bba",
+                "81d9a7ea2e755ffb60897bf2177575a11f6a8ef0ab304da10db0e8e5332869c9",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "dd99bf4958ae94e05d64516fa831d1576e1fa45e5c583bc1d0ad7f0f9df2c21a",
+                "75aa972a358de908a32cb32785bd3fea7ccda063b4e092c1a616e40f2f85dc00",
         },
     },
 }
@@ -82,7 +82,9 @@ def kernel_bytes(stage: str, n: int, ms: int, nc: int, m2: int, full: bool) -> f
         "extremes": 16.0 * n,
         "filter1": 16.0 * n + 24.0 * ms,
         "longest": 0.0,
-        "buckets": 12.0 * ms if full else 40.0 * ms + 24.0 * nc,
+        # bucketed: maxima over a 1/8 sample of the survivors (20 B each),
+        # then every survivor classified, candidates written (28 B each)
+        "buckets": 12.0 * ms if full else 22.5 * ms + 28.0 * nc,
         "histogram": 4.0 * nc,
         "sort0": 12.0 * nc,
         "sort1": 16.0 * nc,
@@ -92,7 +94,8 @@ def kernel_bytes(stage: str, n: int, ms: int, nc: int, m2: int, full: bool) -> f
         "ties_long": 0.0,
         "round2": 21.0 * nc,
         "compact": 1.0 * nc + 44.0 * m2,
-        "tail": 24.0 * nc + 20.0 * m2,
+        # candidates' keys read, kept points read and written to the host
+        "tail": 8.0 * nc + 40.0 * m2,
     }[stage]
 
 
