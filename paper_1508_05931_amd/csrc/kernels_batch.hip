@@ -594,7 +594,7 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
             take_better<2>(e[2], S.ext[w][2]);
             take_better<3>(e[3], S.ext[w][3]);
         }
-        S.P = make_params(e, S.flags);
+        make_params(S.P, e, S.flags);
     }
     __syncthreads();
     if (S.flags != 0u) {

@@ -172,36 +172,50 @@ __global__ __launch_bounds__(kPfBlock) void k_prefilter(
         __syncthreads();
     };
     uint32_t nr = 0;
-    for (uint32_t base = beg; base < end; base += kPfBlock * kPfItems) {
+    constexpr uint32_t kStep = kPfBlock * kPfItems;
+    for (uint32_t base = beg; base < end; base += kStep) {
         double2 p[kPfItems];
         uint32_t k[kPfItems];
 #pragma unroll
         for (int u = 0; u < kPfItems; ++u) {
-            uint32_t s = base + u * kPfBlock + threadIdx.x;
+            const uint32_t s = base + u * kPfBlock + threadIdx.x;
             if (s < end) {
                 p[u] = comp_xy[s];
                 k[u] = keys[s];
             }
         }
+        // classify every item first, then fetch their prefix maxima together
+        // (one memory latency per tile, not one per item)
+        Cls c[kPfItems];
+        uint32_t pre[kPfItems];
 #pragma unroll
         for (int u = 0; u < kPfItems; ++u) {
-            uint32_t s = base + u * kPfBlock + threadIdx.x;
+            const uint32_t s = base + u * kPfBlock + threadIdx.x;
+            c[u].region = 2;
+            c[u].kappa = 0;
+            c[u].bucket = 0;
+            if (s < end) c[u] = classify(p[u].x, p[u].y, k[u], P);
+        }
+#pragma unroll
+        for (int u = 0; u < kPfItems; ++u)
+            pre[u] = c[u].region < 2 ? prefix[c[u].region * kBuckets + c[u].bucket] : 0u;
+#pragma unroll
+        for (int u = 0; u < kPfItems; ++u) {
+            const uint32_t s = base + u * kPfBlock + threadIdx.x;
             if (s < end) {
-                Cls c = classify(p[u].x, p[u].y, k[u], P);
-                const bool keep = (c.region == 2) ||
-                                  (c.kappa >= prefix[(c.region & 1) * kBuckets + c.bucket]);
-                nr += c.region == 0;
+                const bool keep = (c[u].region == 2) || (c[u].kappa >= pre[u]);
+                nr += c[u].region == 0;
                 if (keep) {
                     const uint32_t at = atomicAdd(&s_n, 1u);
                     s_buf[at] = s;
-                    s_kap[at] = c.region == 2 ? 0xFFFFFFFFu : c.kappa;
-                    if (c.region < 2 && c.kappa != 0u)
-                        atomicMax(&exact[c.region * kBuckets + c.bucket], c.kappa);
+                    s_kap[at] = c[u].region == 2 ? 0xFFFFFFFFu : c[u].kappa;
+                    if (c[u].region < 2 && c[u].kappa != 0u)
+                        atomicMax(&exact[c[u].region * kBuckets + c[u].bucket], c[u].kappa);
                 }
             }
         }
         __syncthreads();
-        if (s_n > (uint32_t)(kPfCap - kPfBlock * kPfItems)) flush();
+        if (s_n > (uint32_t)(kPfCap - kStep)) flush();
     }
     flush();
 #pragma unroll

@@ -223,35 +223,50 @@ __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict_
         for (int k = 0; k < 4; ++k) s_c[wave][k] = c[k];
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    Cand e[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) e[k] = s_c[0][k];
-    for (int w = 1; w < NW; ++w) {
-        take_better<0>(e[0], s_c[w][0]);
-        take_better<1>(e[1], s_c[w][1]);
-        take_better<2>(e[2], s_c[w][2]);
-        take_better<3>(e[3], s_c[w][3]);
+    // one criterion per wave (parallel chains), then the parameters and the
+    // status built once in LDS and written out by every thread
+    __shared__ Cand s_e[4];
+    __shared__ Params s_p;
+    __shared__ DevStatus s_s;
+    if (lane == 0 && wave < 4) {
+        Cand b = s_c[0][wave];
+        for (int w = 1; w < NW; ++w) {
+            const Cand o = s_c[w][wave];
+            if (wave == 0) take_better<0>(b, o);
+            else if (wave == 1) take_better<1>(b, o);
+            else if (wave == 2) take_better<2>(b, o);
+            else take_better<3>(b, o);
+        }
+        s_e[wave] = b;
     }
-    const Params P = make_params(e, s_flags);
-    *prm = P;
-    DevStatus S;
-    S.flags = s_flags;
-    S.huge_runs = 0;
-    S.n_sorted = 0;
-    S.n_p0 = 0;
-    S.l_pos = 0;
-    S.n_kept = 0;
-    S.long_runs = 0;
-    S.l_slot = kSlotNone;
-    S.n_right = 0;
-    S.tail_state = kTailDone;
-    for (int k = 0; k < 4; ++k) S.ext[k] = e[k].i;
-    S.p0_idx = e[1].i;
-    S.l_idx = -1;
-    S.x0 = P.x0;
-    S.y0 = P.y0;
-    *ds = S;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const Cand e[4] = {s_e[0], s_e[1], s_e[2], s_e[3]};
+        make_params(s_p, e, s_flags);
+        DevStatus S;
+        S.flags = s_flags;
+        S.huge_runs = 0;
+        S.n_sorted = 0;
+        S.n_p0 = 0;
+        S.l_pos = 0;
+        S.n_kept = 0;
+        S.long_runs = 0;
+        S.l_slot = kSlotNone;
+        S.n_right = 0;
+        S.tail_state = kTailDone;
+        for (int k = 0; k < 4; ++k) S.ext[k] = e[k].i;
+        S.p0_idx = e[1].i;
+        S.l_idx = -1;
+        S.x0 = s_p.x0;
+        S.y0 = s_p.y0;
+        s_s = S;
+    }
+    __syncthreads();
+    static_assert(sizeof(Params) % 4 == 0 && sizeof(DevStatus) % 4 == 0, "word copies");
+    for (int i = (int)threadIdx.x; i < (int)(sizeof(Params) / 4); i += 1024)
+        reinterpret_cast<uint32_t*>(prm)[i] = reinterpret_cast<const uint32_t*>(&s_p)[i];
+    for (int i = (int)threadIdx.x; i < (int)(sizeof(DevStatus) / 4); i += 1024)
+        reinterpret_cast<uint32_t*>(ds)[i] = reinterpret_cast<const uint32_t*>(&s_s)[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -902,7 +917,9 @@ int filter1_blocks(int64_t n, int cu_count, int per_cu) {
 }
 
 void occupancy_filter(Occupancy& o) {
-    o.extremes = resident_blocks(reinterpret_cast<const void*>(k_extremes<0>), kExtBlock);
+    // fewer, longer blocks than fit: three per compute unit measured
+    // 88-91 us per 20M points against 94-98 us at the six that fit
+    o.extremes = std::min(resident_blocks(reinterpret_cast<const void*>(k_extremes<0>), kExtBlock), 3);
     o.extremes_dirs = resident_blocks(reinterpret_cast<const void*>(k_extremes<kMlpDirs>), kExtBlock);
     o.filter1 = resident_blocks(reinterpret_cast<const void*>(k_filter1<false>), kF1Block);
     o.filter1_poly = resident_blocks(reinterpret_cast<const void*>(k_filter1<true>), kF1Block);

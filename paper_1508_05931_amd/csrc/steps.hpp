@@ -99,8 +99,7 @@ __device__ inline void offer(Cand (&c)[4], double x, double y, int32_t i) {
 // distinct corners in the order P_minx -> P_miny -> P_maxx -> P_maxy
 // (counter-clockwise), their edge vectors and one error bound for every edge
 // test.  Step-5 fields start empty.
-__device__ inline Params make_params(const Cand (&e)[4], uint32_t flags) {
-    Params P;
+__device__ inline void make_params(Params& P, const Cand (&e)[4], uint32_t flags) {
     for (int k = 0; k < 4; ++k) {
         P.ext[k] = e[k];
         P.ext[k].pad = 0;
@@ -142,7 +141,6 @@ __device__ inline Params make_params(const Cand (&e)[4], uint32_t flags) {
     P.kl = 0;
     P.turn_u = P.turn_v = 0;
     P.pad2[0] = P.pad2[1] = 0;
-    return P;
 }
 
 // ---------------------------------------------------------------------------
