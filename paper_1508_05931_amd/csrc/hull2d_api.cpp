@@ -45,14 +45,13 @@ struct hull2d_ctx {
     uint32_t* cand_idx = nullptr;
     uint32_t* cand_key = nullptr;
     uint32_t* cand_kap = nullptr;
-    uint32_t* part = nullptr;     // per-block bucket maxima
     uint32_t* bmax = nullptr;     // sampled bucket maxima, then those over the candidates
     uint32_t* prefix = nullptr;
     uint32_t* seg_count = nullptr;  // round-1 segments (one per filter block)
     uint32_t* seg_off = nullptr;
     double* blk_d2 = nullptr;
     uint32_t* blk_best = nullptr;
-    int parts = 0;
+    int parts = 0;  // blocks of k_bucket_max
     Counters* ctr = nullptr;  // separate allocation, zeroed once, persists
 
     // pinned host buffers (h_ds holds the two problem statuses; the tail
@@ -125,11 +124,11 @@ constexpr int kMaxSegs = 8192;  // round-1 blocks (resident blocks of the whole 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t off[27];
+    size_t off[26];
     size_t total;
 };
 
-Layout plan(int64_t n, int parts) {
+Layout plan(int64_t n) {
     const size_t N = (size_t)(n > 0 ? n : 1);
     const size_t sort_tiles = (size_t)ceil_div((int64_t)N, kSortTile);
     const size_t f1_tiles = (size_t)ceil_div((int64_t)N, kF1Tile);
@@ -137,7 +136,7 @@ Layout plan(int64_t n, int parts) {
     stat_words = std::max(stat_words, f1_tiles + 2);
     stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kR2Tile) + 4);
     stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kCpTile) + 2);
-    const size_t sizes[27] = {
+    const size_t sizes[26] = {
         (size_t)kExtGridMax * 4 * sizeof(Cand),      // 0 partial
         sizeof(Params),                              // 1
         2 * sizeof(DevStatus),                       // 2 round-1 problem, candidate problem
@@ -159,15 +158,14 @@ Layout plan(int64_t n, int parts) {
         N * sizeof(double2),                         // 18 cand_xy
         N * sizeof(uint32_t),                        // 19 cand_idx
         N * sizeof(uint32_t),                        // 20 cand_key
-        (size_t)parts * 2 * kBuckets * sizeof(uint32_t),  // 21 part
-        2 * kBuckets * sizeof(uint32_t),             // 22 bmax
-        2 * kBuckets * sizeof(uint32_t),             // 23 prefix
-        (size_t)kMaxSegs * sizeof(uint32_t),         // 24 seg_count
-        (size_t)kMaxSegs * sizeof(uint32_t),         // 25 seg_off
-        N * sizeof(uint32_t)};                       // 26 cand_kap
+        2 * kBuckets * sizeof(uint32_t),             // 21 bmax
+        2 * kBuckets * sizeof(uint32_t),             // 22 prefix
+        (size_t)kMaxSegs * sizeof(uint32_t),         // 23 seg_count
+        (size_t)kMaxSegs * sizeof(uint32_t),         // 24 seg_off
+        N * sizeof(uint32_t)};                       // 25 cand_kap
     Layout L{};
     size_t o = 0;
-    for (int i = 0; i < 27; ++i) {
+    for (int i = 0; i < 26; ++i) {
         L.off[i] = o;
         o = align_up(o + sizes[i], 256);
     }
@@ -185,8 +183,11 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
         c->dmem = nullptr;
         c->cap_n = -1;
     }
-    c->parts = std::min(c->occ.bucket_max, 2) * c->cu_count;
-    Layout L = plan(want, c->parts);
+    // blocks of the sampled bucket maxima: each folds up to 2 x 4096 table
+    // entries into the shared table with atomics; one per compute unit
+    // measured best (64, 128 and 256 blocks tried)
+    c->parts = std::max(1, c->cu_count);
+    Layout L = plan(want);
     if (hipMalloc((void**)&c->dmem, L.total) != hipSuccess) {
         (void)hipGetLastError();
         c->dmem = nullptr;
@@ -214,12 +215,11 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
     c->cand_xy = (double2*)(b + L.off[18]);
     c->cand_idx = (uint32_t*)(b + L.off[19]);
     c->cand_key = (uint32_t*)(b + L.off[20]);
-    c->part = (uint32_t*)(b + L.off[21]);
-    c->bmax = (uint32_t*)(b + L.off[22]);
-    c->prefix = (uint32_t*)(b + L.off[23]);
-    c->seg_count = (uint32_t*)(b + L.off[24]);
-    c->seg_off = (uint32_t*)(b + L.off[25]);
-    c->cand_kap = (uint32_t*)(b + L.off[26]);
+    c->bmax = (uint32_t*)(b + L.off[21]);
+    c->prefix = (uint32_t*)(b + L.off[22]);
+    c->seg_count = (uint32_t*)(b + L.off[23]);
+    c->seg_off = (uint32_t*)(b + L.off[24]);
+    c->cand_kap = (uint32_t*)(b + L.off[25]);
     // Look-back words carry the call's epoch; zero means "not ready" for any epoch.
     if (hipMemsetAsync(c->stat, 0, L.off[11] - L.off[10], c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -650,12 +650,12 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
                           c->comp_idx, c->keys_a, c->seg_count, c->blk_d2, c->blk_best, c->ds, s));
     mark(HULL2D_STAGE_FILTER1);
     // Step 5 (needs every survivor's distance; the sort does not)
+    const bool full = c->opt.round2_chunk != 0 || c->opt.full_sort != 0;
     HX_TRY(launch_longest(segs, c->blk_d2, c->blk_best, c->seg_count, c->seg_off, c->comp_xy, c->keys_a,
-                          c->prm, c->ds, s));
+                          c->prm, c->ds, full ? nullptr : c->bmax, s));
     mark(HULL2D_STAGE_LONGEST);
     // The sorting problem: every round-1 survivor (Step 4 as printed, and the
     // paper's subsets), or only the candidates of the bucketed filter.
-    const bool full = c->opt.round2_chunk != 0 || c->opt.full_sort != 0;
     DevStatus* pds = c->ds;
     const double2* pxy = c->comp_xy;
     const uint32_t* pidx = c->comp_idx;
@@ -663,9 +663,9 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     const uint32_t* pvals = c->cand_idx;   // and their slots in the segments
     if (!full) {
         DevStatus* ds2 = c->ds + 1;
-        HX_TRY(launch_bucket_max(n, segs, c->seg_count, c->comp_xy, c->keys_a, c->prm, c->ds, c->part,
+        HX_TRY(launch_bucket_max(n, segs, c->seg_count, c->comp_xy, c->keys_a, c->prm, c->bmax,
                                  c->parts, s));
-        HX_TRY(launch_bucket_scan(c->part, c->parts, c->bmax, c->prefix, ds2, s));
+        HX_TRY(launch_bucket_scan(c->bmax, c->prefix, ds2, s));
         HX_TRY(launch_prefilter(n, segs, c->seg_count, c->comp_xy, c->comp_idx, c->keys_a, c->prm,
                                 c->ds, c->prefix, c->cand_xy, c->cand_idx, c->cand_key, c->cand_kap,
                                 c->bmax, ds2, s));

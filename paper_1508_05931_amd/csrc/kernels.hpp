@@ -58,7 +58,7 @@ int extremes_grid(int64_t n, int cu_count, int per_cu);
 // exactly once: a block that cannot be resident would run in a second,
 // mostly empty wave of blocks.
 struct Occupancy {
-    int extremes = 1, extremes_dirs = 1, filter1 = 1, filter1_poly = 1, bucket_max = 1;
+    int extremes = 1, extremes_dirs = 1, filter1 = 1, filter1_poly = 1;
 };
 // At least 1 when the query fails.
 inline int resident_blocks(const void* kernel, int block) {
@@ -70,11 +70,9 @@ inline int resident_blocks(const void* kernel, int block) {
     return b > 0 ? b : 1;
 }
 void occupancy_filter(Occupancy& o);  // extremes, filter1
-void occupancy_bucket(Occupancy& o);  // bucket_max
 inline Occupancy query_occupancy() {
     Occupancy o;
     occupancy_filter(o);
-    occupancy_bucket(o);
     return o;
 }
 
@@ -90,10 +88,12 @@ hipError_t launch_filter1(const double* xy, int64_t n, int blocks, const Params*
                           uint32_t* seg_count, double* blk_d2, uint32_t* blk_best, DevStatus* ds,
                           hipStream_t s);
 
-// Step 5 and the segment offsets (one block).
+// Step 5 and the segment offsets (one block); also clears bmax (2 x
+// kBuckets, the bucketed filter's sampled maxima) unless it is NULL.
 hipError_t launch_longest(int blocks, const double* blk_d2, const uint32_t* blk_best,
                           const uint32_t* seg_count, uint32_t* seg_off, const double2* comp_xy,
-                          const uint32_t* keys, Params* prm, DevStatus* ds, hipStream_t s);
+                          const uint32_t* keys, Params* prm, DevStatus* ds, uint32_t* bmax,
+                          hipStream_t s);
 
 // Dense (key, slot) pairs of all survivors (for the full sort).
 hipError_t launch_densify(int64_t n, int blocks, const uint32_t* seg_count, const uint32_t* seg_off,
@@ -105,8 +105,8 @@ hipError_t launch_densify(int64_t n, int blocks, const uint32_t* seg_count, cons
 // The candidates form a new (small) sorting problem with status ds2.
 constexpr int kBmBlock = 512;
 hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
-                             const uint32_t* keys, const Params* prm, DevStatus* ds, uint32_t* part,
-                             int parts, hipStream_t s);
+                             const uint32_t* keys, const Params* prm, uint32_t* bmax, int parts,
+                             hipStream_t s);
 // The exact prefix maxima from `exact` (the bucket maxima over the
 // candidates, 2 x kBuckets), the candidates they select (cand_kap: their
 // kappa), then Steps 4 and 6-7 plus the stable removal, for a
@@ -182,8 +182,7 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t cou
                        float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_to_bf16(const float* w, int64_t count, uint16_t* wb, hipStream_t s);
 
-hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, uint32_t* prefix,
-                              DevStatus* ds2, hipStream_t s);
+hipError_t launch_bucket_scan(uint32_t* bmax, uint32_t* prefix, DevStatus* ds2, hipStream_t s);
 hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
                             const uint32_t* comp_idx, const uint32_t* keys, const Params* prm,
                             DevStatus* ds, const uint32_t* prefix, double2* cand_xy,

@@ -34,21 +34,21 @@ constexpr uint32_t kBmSample = 8;  // bucket maxima from 1/8 of each segment
 
 __device__ inline Params load_params(const Params* __restrict__ prm) { return *prm; }
 
-// Per-block maxima of kappa per (region, bucket) into LDS, written out as one
-// table per block, over a sample: the first 1/kBmSample of each segment's
-// survivors.  Prefix maxima of a table built from any subset of the points
-// are lower bounds of the exact ones, so the candidates they select include
-// every point the exact table selects (the one-workgroup tail narrows them
-// to exactly those).  Each block takes a contiguous range of segments; every
-// thread loads kBmItems points before it uses any of them, so enough loads
-// are in flight to cover the memory latency.
+// Maxima of kappa per (region, bucket) over a sample: the first
+// 1/kBmSample of each segment's survivors.  Each block builds its table in
+// LDS, then folds its non-empty entries into bmax (cleared by k_longest)
+// with device atomics.  Prefix maxima of a table built from any subset of
+// the points are lower bounds of the exact ones, so the candidates they
+// select include every point the exact table selects (the one-workgroup
+// tail narrows them to exactly those).  Each block takes a contiguous range
+// of segments; every thread loads kBmItems points before it uses any of
+// them, so enough loads are in flight to cover the memory latency.
 __global__ __launch_bounds__(kBmBlock) void k_bucket_max(int64_t chunk, int segs,
                                                         const uint32_t* __restrict__ seg_count,
                                                         const double2* __restrict__ comp_xy,
                                                         const uint32_t* __restrict__ keys,
                                                         const Params* __restrict__ prm,
-                                                        DevStatus* __restrict__ ds,
-                                                        uint32_t* __restrict__ part) {
+                                                        uint32_t* __restrict__ bmax) {
     __shared__ uint32_t s_tab[2 * kBuckets];
     for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += kBmBlock) s_tab[i] = 0;
     __syncthreads();
@@ -81,23 +81,8 @@ __global__ __launch_bounds__(kBmBlock) void k_bucket_max(int64_t chunk, int segs
     }
     }
     __syncthreads();
-    uint32_t* out = part + (size_t)blockIdx.x * 2 * kBuckets;
-    for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += kBmBlock) out[i] = s_tab[i];
-}
-
-// Column maxima of the per-block tables: a block takes 64 columns, its four
-// waves split the rows, several loads in flight per thread.
-__global__ __launch_bounds__(256) void k_bucket_reduce(const uint32_t* __restrict__ part, int parts,
-                                                       uint32_t* __restrict__ bmax) {
-    __shared__ uint32_t s_m[4][64];
-    const int c = (int)(threadIdx.x & 63), g = (int)(threadIdx.x >> 6);
-    const int col = (int)blockIdx.x * 64 + c;
-    uint32_t m = 0;
-#pragma unroll 8
-    for (int p = g; p < parts; p += 4) m = max(m, part[(size_t)p * 2 * kBuckets + col]);
-    s_m[g][c] = m;
-    __syncthreads();
-    if (g == 0) bmax[col] = max(max(s_m[0][c], s_m[1][c]), max(s_m[2][c], s_m[3][c]));
+    for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += kBmBlock)
+        if (s_tab[i]) atomicMax(&bmax[i], s_tab[i]);
 }
 
 // Exclusive prefix maxima in walking order: ascending buckets for the right
@@ -228,18 +213,14 @@ __global__ __launch_bounds__(kPfBlock) void k_prefilter(
 }  // namespace
 
 hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, const double2* comp_xy,
-                             const uint32_t* keys, const Params* prm, DevStatus* ds, uint32_t* part,
-                             int parts, hipStream_t s) {
+                             const uint32_t* keys, const Params* prm, uint32_t* bmax, int parts,
+                             hipStream_t s) {
     hipLaunchKernelGGL(k_bucket_max, dim3(parts), dim3(kBmBlock), 0, s, filter1_chunk(n, segs), segs,
-                       seg_count, comp_xy, keys, prm, ds, part);
+                       seg_count, comp_xy, keys, prm, bmax);
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_scan(const uint32_t* part, int parts, uint32_t* bmax, uint32_t* prefix,
-                              DevStatus* ds2, hipStream_t s) {
-    hipLaunchKernelGGL(k_bucket_reduce, dim3(2 * kBuckets / 64), dim3(256), 0, s, part, parts, bmax);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_bucket_scan(uint32_t* bmax, uint32_t* prefix, DevStatus* ds2, hipStream_t s) {
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, bmax, prefix, ds2);
     return hipGetLastError();
 }
@@ -253,10 +234,6 @@ hipError_t launch_prefilter(int64_t n, int segs, const uint32_t* seg_count, cons
                        comp_xy, comp_idx, keys, prm, ds, prefix, cand_xy, cand_idx, cand_key, cand_kap,
                        exact, ds2);
     return hipGetLastError();
-}
-
-void occupancy_bucket(Occupancy& o) {
-    o.bucket_max = resident_blocks(reinterpret_cast<const void*>(k_bucket_max), kBmBlock);
 }
 
 }  // namespace hx

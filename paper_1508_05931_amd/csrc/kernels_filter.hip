@@ -454,9 +454,13 @@ __global__ __launch_bounds__(1024) void k_longest(int nblk, const double* __rest
                                                   const double2* __restrict__ comp_xy,
                                                   const uint32_t* __restrict__ keys,
                                                   Params* __restrict__ prm,
-                                                  DevStatus* __restrict__ ds) {
+                                                  DevStatus* __restrict__ ds,
+                                                  uint32_t* __restrict__ bmax) {
     __shared__ double s_d[16];
     __shared__ uint32_t s_i[16], s_s[16], s_c[16];
+    // the bucketed filter's table of sampled bucket maxima starts empty
+    if (bmax)
+        for (int i = (int)threadIdx.x; i < 2 * kBuckets; i += 1024) bmax[i] = 0;
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
     double d = -1.0;
     uint32_t bi = 0xFFFFFFFFu, bs = 0xFFFFFFFFu;
@@ -947,9 +951,10 @@ hipError_t launch_filter1(const double* xy, int64_t n, int blocks, const Params*
 
 hipError_t launch_longest(int blocks, const double* blk_d2, const uint32_t* blk_best,
                           const uint32_t* seg_count, uint32_t* seg_off, const double2* comp_xy,
-                          const uint32_t* keys, Params* prm, DevStatus* ds, hipStream_t s) {
+                          const uint32_t* keys, Params* prm, DevStatus* ds, uint32_t* bmax,
+                          hipStream_t s) {
     hipLaunchKernelGGL(k_longest, dim3(1), dim3(1024), 0, s, blocks, blk_d2, blk_best, seg_count,
-                       seg_off, comp_xy, keys, prm, ds);
+                       seg_off, comp_xy, keys, prm, ds, bmax);
     return hipGetLastError();
 }
 

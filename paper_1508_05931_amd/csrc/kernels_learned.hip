@@ -244,65 +244,68 @@ __global__ __launch_bounds__(64 * kDirs) void k_poly(const DirBest* __restrict__
         s_y[t] = p.y;
     }
     __syncthreads();
-    if (t != 0) return;
-    Poly Q;
-    Q.pad = 0;
-    Q.nv = 0;
-    double cx[kPolyMax], cy[kPolyMax];
-    int nc = 0;
-    const bool ok = prm->flags == 0u;
-    for (int j = 0; j < kPolyMax; ++j) {
-        lo->cand[j] = s_c[j];
-        if (!ok || s_c[j] == INT32_MAX) continue;
-        double2 p;
-        p.x = s_x[j];
-        p.y = s_y[j];
-        // insertion by (x, y), dropping repeats
-        int k = nc;
-        bool dup = false;
-        for (int a = 0; a < nc; ++a) dup |= (cx[a] == p.x && cy[a] == p.y);
-        if (dup) continue;
-        while (k > 0 && (cx[k - 1] > p.x || (cx[k - 1] == p.x && cy[k - 1] > p.y))) {
-            cx[k] = cx[k - 1];
-            cy[k] = cy[k - 1];
-            --k;
+    // one thread builds the hull with its arrays in LDS (no scratch), then
+    // every thread copies the polygon out
+    __shared__ Poly Q;
+    __shared__ double cx[kPolyMax], cy[kPolyMax], hx_[2 * kPolyMax + 1], hy_[2 * kPolyMax + 1];
+    if (t == 0) {
+        Q.pad = 0;
+        Q.nv = 0;
+        int nc = 0;
+        const bool ok = prm->flags == 0u;
+        for (int j = 0; j < kPolyMax; ++j) {
+            lo->cand[j] = s_c[j];
+            if (!ok || s_c[j] == INT32_MAX) continue;
+            const double px = s_x[j], py = s_y[j];
+            // insertion by (x, y), dropping repeats
+            bool dup = false;
+            for (int a = 0; a < nc; ++a) dup |= (cx[a] == px && cy[a] == py);
+            if (dup) continue;
+            int k = nc;
+            while (k > 0 && (cx[k - 1] > px || (cx[k - 1] == px && cy[k - 1] > py))) {
+                cx[k] = cx[k - 1];
+                cy[k] = cy[k - 1];
+                --k;
+            }
+            cx[k] = px;
+            cy[k] = py;
+            ++nc;
         }
-        cx[k] = p.x;
-        cy[k] = p.y;
-        ++nc;
-    }
-    double hx_[2 * kPolyMax + 1], hy_[2 * kPolyMax + 1];
-    int h = 0;
-    if (nc >= 3) {
-        for (int i = 0; i < nc; ++i) {
-            while (h >= 2 && orient(hx_[h - 2], hy_[h - 2], hx_[h - 1], hy_[h - 1], cx[i], cy[i]) <= 0) --h;
-            hx_[h] = cx[i];
-            hy_[h] = cy[i];
-            ++h;
+        int h = 0;
+        if (nc >= 3) {
+            for (int i = 0; i < nc; ++i) {
+                while (h >= 2 && orient(hx_[h - 2], hy_[h - 2], hx_[h - 1], hy_[h - 1], cx[i], cy[i]) <= 0) --h;
+                hx_[h] = cx[i];
+                hy_[h] = cy[i];
+                ++h;
+            }
+            const int base = h;
+            for (int i = nc - 2; i >= 0; --i) {
+                while (h > base && orient(hx_[h - 2], hy_[h - 2], hx_[h - 1], hy_[h - 1], cx[i], cy[i]) <= 0) --h;
+                hx_[h] = cx[i];
+                hy_[h] = cy[i];
+                ++h;
+            }
+            --h;  // the last point repeats the first
         }
-        const int base = h;
-        for (int i = nc - 2; i >= 0; --i) {
-            while (h > base && orient(hx_[h - 2], hy_[h - 2], hx_[h - 1], hy_[h - 1], cx[i], cy[i]) <= 0) --h;
-            hx_[h] = cx[i];
-            hy_[h] = cy[i];
-            ++h;
-        }
-        --h;  // the last point repeats the first
+        Q.nv = h >= 3 ? h : 0;
+        // every corner and point lies in the Step-1 bounding box W x H
+        const double W = prm->ext[2].x - prm->ext[0].x, H = prm->ext[3].y - prm->ext[1].y;
+        Q.qb = 9.0 * kEps * W * H;
     }
-    Q.nv = h >= 3 ? h : 0;
-    for (int j = 0; j < kPolyMax; ++j) {
-        Q.px[j] = j < Q.nv ? hx_[j] : 0.0;
-        Q.py[j] = j < Q.nv ? hy_[j] : 0.0;
+    __syncthreads();
+    if (t < kPolyMax) {
+        const int nv = Q.nv, j = t;
+        const int j1 = j + 1 < nv ? j + 1 : 0;
+        Q.px[j] = j < nv ? hx_[j] : 0.0;
+        Q.py[j] = j < nv ? hy_[j] : 0.0;
+        Q.ex[j] = j < nv ? hx_[j1] - hx_[j] : 0.0;
+        Q.ey[j] = j < nv ? hy_[j1] - hy_[j] : 0.0;
     }
-    for (int j = 0; j < kPolyMax; ++j) {
-        const int j1 = j + 1 < Q.nv ? j + 1 : 0;
-        Q.ex[j] = j < Q.nv ? Q.px[j1] - Q.px[j] : 0.0;
-        Q.ey[j] = j < Q.nv ? Q.py[j1] - Q.py[j] : 0.0;
-    }
-    // every corner and point lies in the Step-1 bounding box W x H
-    const double W = prm->ext[2].x - prm->ext[0].x, H = prm->ext[3].y - prm->ext[1].y;
-    Q.qb = 9.0 * kEps * W * H;
-    lo->poly = Q;
+    __syncthreads();
+    static_assert(sizeof(Poly) % 8 == 0, "double copies");
+    for (int i = t; i < (int)(sizeof(Poly) / 8); i += (int)blockDim.x)
+        reinterpret_cast<double*>(&lo->poly)[i] = reinterpret_cast<const double*>(&Q)[i];
 }
 
 // ---------------------------------------------------------------------------

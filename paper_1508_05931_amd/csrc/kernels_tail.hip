@@ -481,24 +481,39 @@ __device__ __forceinline__ void tail_body(const double2* __restrict__ cand_xy,
             run = it[k];
         }
     }
-    // the kept points' coordinates and indices (one batch of loads)
-    double2 v[kTI];
-    uint32_t id[kTI];
-#pragma unroll
-    for (int k = 0; k < kTI; ++k) {
-        if ((kmask >> k) & 1u) {
-            v[k] = cand_xy[it[k].s];
-            id[k] = cand_idx[it[k].s];
-        }
-    }
-
-    // ---- 4. stable removal in angular order.  Right region: thread order is
-    //         position order.  Left region: P_l first, then the walked items,
-    //         whose positions fall as the walk index rises.
+    // ---- 4. stable removal in angular order, staged in LDS so that the
+    //         writes to host memory are contiguous.  Right region: walk
+    //         order.  Left region: P_l first, then the walked items in
+    //         reverse (their positions fall as the walk index rises).
     uint32_t tot;
     const uint32_t c = (uint32_t)__popc(kmask);
     const uint32_t excl = block_excl_sum(c, S, tot);
-    uint32_t base = 0;
+    if (region == 0 && tid == 0) stat_store(pub, stat_pack(epoch, kStatInclusive, tot));
+    uint16_t* stage = S.ix[cur ^ 1];  // free since the exact order of long runs
+    {
+        uint32_t j = excl;
+#pragma unroll
+        for (int k = 0; k < kTI; ++k) {
+            if ((kmask >> k) & 1u) {
+                stage[region == 0 ? j : tot - 1u - j] = (uint16_t)it[k].s;
+                ++j;
+            }
+        }
+    }
+    __syncthreads();
+    // output position q = tid + r * kTB: gather the point, then write
+    double2 v[kTI];
+    uint32_t id[kTI];
+#pragma unroll
+    for (int r = 0; r < kTI; ++r) {
+        const uint32_t q = (uint32_t)(tid + r * kTB);
+        if (q < tot) {
+            const uint32_t sl = stage[q];
+            v[r] = cand_xy[sl];
+            id[r] = cand_idx[sl];
+        }
+    }
+    uint32_t o0 = 0;
     if (region == 1) {
         if (tid == 0) {
             uint64_t w;
@@ -510,36 +525,22 @@ __device__ __forceinline__ void tail_body(const double2* __restrict__ cand_xy,
             S.total = stat_value(w);
         }
         __syncthreads();
-        base = S.total;
+        const uint32_t base = S.total;
         if (base == kTailPubOverflow) return;  // the host takes the other path
-    }
-    if (region == 0) {
-        uint32_t o = excl;
-#pragma unroll
-        for (int k = 0; k < kTI; ++k) {
-            if ((kmask >> k) & 1u) {
-                out_xy[o] = v[k];
-                out_idx[o] = (int32_t)id[k];
-                ++o;
-            }
-        }
-        if (tid == 0) stat_store(pub, stat_pack(epoch, kStatInclusive, tot));
-    } else {
         if (tid == 0) {
             out_xy[base] = make_double2(rl.x, rl.y);
             out_idx[base] = (int32_t)rl.idx;
+            ds2->n_kept = base + 1u + tot;
         }
-        // kept items of later threads come first
-        uint32_t o = base + 1u + (tot - excl - c);
+        o0 = base + 1u;
+    }
 #pragma unroll
-        for (int k = kTI - 1; k >= 0; --k) {
-            if ((kmask >> k) & 1u) {
-                out_xy[o] = v[k];
-                out_idx[o] = (int32_t)id[k];
-                ++o;
-            }
+    for (int r = 0; r < kTI; ++r) {
+        const uint32_t q = (uint32_t)(tid + r * kTB);
+        if (q < tot) {
+            out_xy[o0 + q] = v[r];
+            out_idx[o0 + q] = (int32_t)id[r];
         }
-        if (tid == 0) ds2->n_kept = base + 1u + tot;
     }
 }
 
