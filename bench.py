@@ -169,12 +169,23 @@ def batched(steps: int):
         ts.append(time.perf_counter() - t0)
     st = ctx.last_stats
     ms = float(np.median(ts)) * 1e3
+    # the same sets through the plain single-hull path, one call per set
+    views = [d[offs[i]:offs[i + 1]] for i in range(len(offs) - 1)]
+    for v in views[:64]:
+        ctx.compute(v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v in views:
+        ctx.compute(v)
+    loop_ms = (time.perf_counter() - t0) * 1e3
     ctx.close()
     return {"workload": "4096 sets, sizes log-uniform 64..200000, 4 distributions",
             "n_points": int(offs[-1]), "n_hull": int(st.n_hull), "reps": reps,
             "ms_median": round(ms, 3), "ms_device": round(float(st.ms_device), 3),
             "Mpoints_per_s": round(offs[-1] / (ms * 1e-3) / 1e6, 1),
-            "sets_on_host_path": int(st.n_candidates)}
+            "sets_on_host_path": int(st.n_candidates),
+            "per_set_loop": {"ms": round(loop_ms, 2),
+                             "Mpoints_per_s": round(offs[-1] / (loop_ms * 1e-3) / 1e6, 1)}}
 
 
 def main():

@@ -70,9 +70,7 @@ enum TicketId {
     kTicketSort0 = 0,  // ..3
     kTicketRound2 = 4,
     kTicketCompact = 5,
-    kTicketTail = 6,
     kTicketBatch = 7,
-    kTicketTailDone = 8,
 };
 
 constexpr int kBucketBits = 12;                 // coarse angle buckets of the bucketed round 2

@@ -45,6 +45,8 @@ struct hull2d_ctx {
     uint32_t* cand_idx = nullptr;
     uint32_t* cand_key = nullptr;
     uint32_t* cand_kap = nullptr;
+    uint16_t* tail_slot = nullptr;  // the tail's kept slots [2][kTailCap], then two counts
+    uint32_t* tail_count = nullptr;
     uint32_t* bmax = nullptr;     // sampled bucket maxima, then those over the candidates
     uint32_t* prefix = nullptr;
     uint32_t* seg_count = nullptr;  // round-1 segments (one per filter block)
@@ -124,7 +126,7 @@ constexpr int kMaxSegs = 8192;  // round-1 blocks (resident blocks of the whole 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t off[26];
+    size_t off[27];
     size_t total;
 };
 
@@ -136,7 +138,7 @@ Layout plan(int64_t n) {
     stat_words = std::max(stat_words, f1_tiles + 2);
     stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kR2Tile) + 4);
     stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kCpTile) + 2);
-    const size_t sizes[26] = {
+    const size_t sizes[27] = {
         (size_t)kExtGridMax * 4 * sizeof(Cand),      // 0 partial
         sizeof(Params),                              // 1
         2 * sizeof(DevStatus),                       // 2 round-1 problem, candidate problem
@@ -162,10 +164,11 @@ Layout plan(int64_t n) {
         2 * kBuckets * sizeof(uint32_t),             // 22 prefix
         (size_t)kMaxSegs * sizeof(uint32_t),         // 23 seg_count
         (size_t)kMaxSegs * sizeof(uint32_t),         // 24 seg_off
-        N * sizeof(uint32_t)};                       // 25 cand_kap
+        N * sizeof(uint32_t),                        // 25 cand_kap
+        2 * (size_t)kTailCap * sizeof(uint16_t) + 2 * sizeof(uint32_t)};  // 26 tail slots, counts
     Layout L{};
     size_t o = 0;
-    for (int i = 0; i < 26; ++i) {
+    for (int i = 0; i < 27; ++i) {
         L.off[i] = o;
         o = align_up(o + sizes[i], 256);
     }
@@ -220,6 +223,8 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
     c->seg_count = (uint32_t*)(b + L.off[23]);
     c->seg_off = (uint32_t*)(b + L.off[24]);
     c->cand_kap = (uint32_t*)(b + L.off[25]);
+    c->tail_slot = (uint16_t*)(b + L.off[26]);
+    c->tail_count = (uint32_t*)(b + L.off[26] + 2 * (size_t)kTailCap * sizeof(uint16_t));
     // Look-back words carry the call's epoch; zero means "not ready" for any epoch.
     if (hipMemsetAsync(c->stat, 0, L.off[11] - L.off[10], c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -730,15 +735,15 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     };
     bool tail_done = false;
     if (!full) {
-        // small candidate sets: one workgroup per region does the rest,
-        // writing the kept points straight to the host buffers (at most
-        // kTailCap per region)
-        st = ensure_host(c, 2 * (int64_t)kTailCap);
+        // small candidate sets: one workgroup per region does the rest, the
+        // kept points then go straight to the host buffers (at most
+        // kTailCap per region and P_l)
+        st = ensure_host(c, 2 * (int64_t)kTailCap + 1);
         if (st != HULL2D_OK) return st;
-        const uint32_t e = ++c->epoch;
         c->h_ds[1].tail_state = kTailUnset;  // the kernel overwrites it
         HX_TRY(launch_tail(c->cand_xy, c->cand_idx, c->cand_key, c->cand_kap, c->bmax, c->prm,
-                           c->ds, c->h_xy_dev, c->h_idx_dev, c->h_ds_dev, c->stat, c->ctr, e, s));
+                           c->ds, c->tail_slot, c->tail_count, c->h_xy_dev, c->h_idx_dev,
+                           c->h_ds_dev, s));
         mark(HULL2D_STAGE_TAIL);
         // the tail leaves the kept points and both statuses in host memory:
         // one wait ends the call unless the candidates did not fit

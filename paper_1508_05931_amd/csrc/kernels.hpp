@@ -109,17 +109,19 @@ hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, con
                              hipStream_t s);
 // The exact prefix maxima from `exact` (the bucket maxima over the
 // candidates, 2 x kBuckets), the candidates they select (cand_kap: their
-// kappa), then Steps 4 and 6-7 plus the stable removal, for a
-// candidate set small enough for one workgroup per region (at most
-// kTailSlots candidates, at most kTailCap selected per region); otherwise
-// sets tail_state to kTailOverflow in ds2 and writes nothing else that the
-// other path needs.  pub: one look-back status word (the right region's
-// kept count).  ds: the round-1 status and the candidate status after it;
-// host_ds: host memory (device-visible) that receives both at the end.
+// kappa), then Steps 4 and 6-7 plus the stable removal, for a candidate set
+// small enough for one workgroup per region (at most kTailSlots candidates,
+// at most kTailCap selected per region); otherwise sets tail_state to
+// kTailOverflow in the candidate status and writes nothing else that the
+// other path needs.  ds: the round-1 status and the candidate status after
+// it.  oslot [2][kTailCap] and ocount [2]: the kept slots per region.
+// out_xy / out_idx: the kept points (right region, P_l, left region), device
+// or mapped host memory; host_ds: host memory (device-visible) that receives
+// both statuses, the candidate status with its kept count.
 hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
                        const uint32_t* cand_kap, const uint32_t* exact, const Params* prm,
-                       DevStatus* ds, double2* out_xy, int32_t* out_idx, DevStatus* host_ds,
-                       uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s);
+                       DevStatus* ds, uint16_t* oslot, uint32_t* ocount, double2* out_xy,
+                       int32_t* out_idx, DevStatus* host_ds, hipStream_t s);
 // The batched form: one persistent launch, each workgroup computing whole
 // hulls of the sets in `order` (device, S entries); per set s, its points are
 // xy[offs[s], offs[s+1]) and its workspace the same range of every array.

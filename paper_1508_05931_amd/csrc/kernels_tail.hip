@@ -4,9 +4,8 @@
 // left (a few ten thousand points at most on uniform inputs of 20M points).
 // For such a set the multi-kernel sort, the look-back scan of Steps 6-7 and
 // the compaction are dominated by launch gaps and look-back latency, so two
-// workgroups of 1024 threads do all of it, one region each, with the
-// region's keys and slots in LDS and every global access issued in batches
-// (the run time is a handful of memory latencies):
+// independent workgroups of 1024 threads do it, one region each, with the
+// region's keys and slots in LDS and every global access issued in batches:
 //
 //   0. the exact prefix maxima of the region's buckets in walking order,
 //      from the bucket maxima over the candidates (the candidates were
@@ -24,10 +23,9 @@
 //      point is kept when it follows, seen from P_l, the maximum of all points
 //      walked before it; the right region is walked forward from P_0, the left
 //      one backward from its last point, P_l itself is always kept);
-//   4. the stable removal: the kept points in angular order, right region,
-//      then P_l and the left region (the left workgroup waits for the right
-//      one's count; the workgroups take the regions in ticket order, so the
-//      one waited for is always running).
+//   4. the stable removal: the kept points' slots in angular order per
+//      region; k_tail_out (many blocks) then gathers the points and writes
+//      the right region, P_l and the left region in order.
 //
 // More than kTailSlots candidates, a region with more than kTailCap selected
 // points, more than kTailLongMax long runs or a run longer than kRunCap sets
@@ -130,8 +128,6 @@ __device__ inline uint32_t block_excl_sum(uint32_t v, TailLds& S, uint32_t& tota
     return pre + inc - v;
 }
 
-constexpr uint32_t kTailPubOverflow = 0xFFFFFFFFu;  // the right region did not fit
-
 // One workgroup's part (every return is uniform over the workgroup).
 __device__ __forceinline__ void tail_body(const double2* __restrict__ cand_xy,
                                           const uint32_t* __restrict__ cand_idx,
@@ -139,36 +135,22 @@ __device__ __forceinline__ void tail_body(const double2* __restrict__ cand_xy,
                                           const uint32_t* __restrict__ cand_kap,
                                           const uint32_t* __restrict__ exact,
                                           const Params* __restrict__ prm,
-                                          DevStatus* __restrict__ ds2, double2* __restrict__ out_xy,
-                                          int32_t* __restrict__ out_idx, uint64_t* __restrict__ pub,
-                                          Counters* __restrict__ ctr, uint32_t epoch, TailLds& S) {
+                                          DevStatus* __restrict__ ds2, uint16_t* __restrict__ oslot,
+                                          uint32_t* __restrict__ ocount, TailLds& S) {
     const int tid = (int)threadIdx.x;
     const int lane = (int)__lane_id(), wave = tid >> 6;
-    if (tid == 0) {
-        uint32_t* counter = &ctr->ticket[16 * kTicketTail];
-        const uint32_t t = take_ticket(counter);
-        if (t == 1u) reset_ticket(counter);  // both workgroups have taken theirs
-        S.count = t;
-    }
-    __syncthreads();
-    const int region = (int)S.count;  // 0: right region, 1: left region
+    const int region = (int)blockIdx.x;  // 0: right region, 1: left region
     const int sgn = region == 0 ? 1 : -1;
-    __syncthreads();
     const uint32_t nc = ds2->n_sorted;
     const double x0 = prm->x0, y0 = prm->y0, lx = prm->lx, ly = prm->ly;
     const uint32_t kl = prm->kl;
     const uint32_t lslot = ds2->l_slot;
-    // Every exit of the right workgroup publishes its count (or the overflow
-    // mark) so that the left one never waits for nothing.
     auto give_up = [&]() {
-        if (tid == 0) {
-            ds2->tail_state = kTailOverflow;
-            if (region == 0) stat_store(pub, stat_pack(epoch, kStatInclusive, kTailPubOverflow));
-        }
+        if (tid == 0) ds2->tail_state = kTailOverflow;
     };
     if (nc == 0) {
-        if (tid == 0 && region == 1) ds2->n_kept = 0;
-        return;  // nobody waits: the left workgroup needs no count
+        if (tid == 0) ocount[region] = 0;
+        return;
     }
     if (nc > kTailSlots || lslot >= nc) {
         give_up();
@@ -481,97 +463,75 @@ __device__ __forceinline__ void tail_body(const double2* __restrict__ cand_xy,
             run = it[k];
         }
     }
-    // ---- 4. stable removal in angular order, staged in LDS so that the
-    //         writes to host memory are contiguous.  Right region: walk
-    //         order.  Left region: P_l first, then the walked items in
-    //         reverse (their positions fall as the walk index rises).
+    // ---- 4. the kept points' slots in angular order: right region in walk
+    //         order, left region in reverse (its positions fall as the walk
+    //         index rises); k_tail_out gathers and writes them.
     uint32_t tot;
     const uint32_t c = (uint32_t)__popc(kmask);
     const uint32_t excl = block_excl_sum(c, S, tot);
-    if (region == 0 && tid == 0) stat_store(pub, stat_pack(epoch, kStatInclusive, tot));
-    uint16_t* stage = S.ix[cur ^ 1];  // free since the exact order of long runs
-    {
-        uint32_t j = excl;
+    uint16_t* out = oslot + (size_t)region * kTailCap;
+    uint32_t j = excl;
 #pragma unroll
-        for (int k = 0; k < kTI; ++k) {
-            if ((kmask >> k) & 1u) {
-                stage[region == 0 ? j : tot - 1u - j] = (uint16_t)it[k].s;
-                ++j;
-            }
+    for (int k = 0; k < kTI; ++k) {
+        if ((kmask >> k) & 1u) {
+            out[region == 0 ? j : tot - 1u - j] = (uint16_t)it[k].s;
+            ++j;
         }
     }
-    __syncthreads();
-    // output position q = tid + r * kTB: gather the point, then write
-    double2 v[kTI];
-    uint32_t id[kTI];
-#pragma unroll
-    for (int r = 0; r < kTI; ++r) {
-        const uint32_t q = (uint32_t)(tid + r * kTB);
-        if (q < tot) {
-            const uint32_t sl = stage[q];
-            v[r] = cand_xy[sl];
-            id[r] = cand_idx[sl];
-        }
-    }
-    uint32_t o0 = 0;
-    if (region == 1) {
-        if (tid == 0) {
-            uint64_t w;
-            for (;;) {
-                w = stat_load(pub);
-                if (stat_flag(w, epoch) == kStatInclusive) break;
-                __builtin_amdgcn_s_sleep(2);
-            }
-            S.total = stat_value(w);
-        }
-        __syncthreads();
-        const uint32_t base = S.total;
-        if (base == kTailPubOverflow) return;  // the host takes the other path
-        if (tid == 0) {
-            out_xy[base] = make_double2(rl.x, rl.y);
-            out_idx[base] = (int32_t)rl.idx;
-            ds2->n_kept = base + 1u + tot;
-        }
-        o0 = base + 1u;
-    }
-#pragma unroll
-    for (int r = 0; r < kTI; ++r) {
-        const uint32_t q = (uint32_t)(tid + r * kTB);
-        if (q < tot) {
-            out_xy[o0 + q] = v[r];
-            out_idx[o0 + q] = (int32_t)id[r];
-        }
-    }
+    if (tid == 0) ocount[region] = tot;
 }
 
-// The two workgroups, then the second of them to finish copies both problem
-// statuses (round 1 and candidates) to host memory, so that the host needs
-// no copy of its own after the tail.
+// One workgroup per region.
 __global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_xy,
                                               const uint32_t* __restrict__ cand_idx,
                                               const uint32_t* __restrict__ cand_key,
                                               const uint32_t* __restrict__ cand_kap,
                                               const uint32_t* __restrict__ exact,
                                               const Params* __restrict__ prm,
-                                              DevStatus* __restrict__ ds, double2* __restrict__ out_xy,
-                                              int32_t* __restrict__ out_idx,
-                                              DevStatus* __restrict__ host_ds,
-                                              uint64_t* __restrict__ pub, Counters* __restrict__ ctr,
-                                              uint32_t epoch) {
+                                              DevStatus* __restrict__ ds2,
+                                              uint16_t* __restrict__ oslot,
+                                              uint32_t* __restrict__ ocount) {
     __shared__ TailLds S;
-    tail_body(cand_xy, cand_idx, cand_key, cand_kap, exact, prm, ds + 1, out_xy, out_idx, pub, ctr,
-              epoch, S);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();  // this workgroup's status writes before its ticket
-        uint32_t* done = &ctr->ticket[16 * kTicketTailDone];
-        if (take_ticket(done) == 1u) {
-            reset_ticket(done);
-            __threadfence();  // the other workgroup's writes after its ticket
-            const volatile uint32_t* src = reinterpret_cast<const volatile uint32_t*>(ds);
-            uint32_t* dst = reinterpret_cast<uint32_t*>(host_ds);
-            for (int i = 0; i < (int)(2 * sizeof(DevStatus) / sizeof(uint32_t)); ++i) dst[i] = src[i];
-        }
+    tail_body(cand_xy, cand_idx, cand_key, cand_kap, exact, prm, ds2, oslot, ocount, S);
+}
+
+// The stable removal's output: the right region's kept points, P_l, the
+// left region's, gathered by slot and written to (host) memory by many
+// blocks; block 0 also sets the kept count and copies both problem statuses
+// (round 1 and candidates) to host memory, so the host needs no copy of its
+// own.  Nothing is written but the statuses when the tail gave up.
+constexpr int kOutBlock = 256;
+constexpr int kOutGrid = 32;
+
+__global__ __launch_bounds__(kOutBlock) void k_tail_out(const double2* __restrict__ cand_xy,
+                                                        const uint32_t* __restrict__ cand_idx,
+                                                        DevStatus* __restrict__ ds,
+                                                        const uint16_t* __restrict__ oslot,
+                                                        const uint32_t* __restrict__ ocount,
+                                                        double2* __restrict__ out_xy,
+                                                        int32_t* __restrict__ out_idx,
+                                                        DevStatus* __restrict__ host_ds) {
+    const DevStatus* ds2 = ds + 1;
+    const bool done = ds2->tail_state == kTailDone;
+    const uint32_t nc = ds2->n_sorted;
+    const uint32_t nr = done && nc > 0 ? ocount[0] : 0u;
+    const uint32_t nl = done && nc > 0 ? ocount[1] : 0u;
+    const uint32_t total = done && nc > 0 ? nr + 1u + nl : 0u;
+    const uint32_t lslot = ds2->l_slot;
+    for (uint32_t q = blockIdx.x * kOutBlock + threadIdx.x; q < total; q += kOutGrid * kOutBlock) {
+        const uint32_t sl = q < nr ? (uint32_t)oslot[q]
+                          : q == nr ? lslot
+                                    : (uint32_t)oslot[kTailCap + (q - nr - 1u)];
+        out_xy[q] = cand_xy[sl];
+        out_idx[q] = (int32_t)cand_idx[sl];
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2 * sizeof(DevStatus) / sizeof(uint32_t)) {
+        const int w = (int)threadIdx.x;
+        uint32_t v = reinterpret_cast<const uint32_t*>(ds)[w];
+        // n_kept of the candidate problem
+        if (w == (int)((sizeof(DevStatus) + offsetof(DevStatus, n_kept)) / sizeof(uint32_t)) && done)
+            v = total;
+        reinterpret_cast<uint32_t*>(host_ds)[w] = v;
     }
 }
 
@@ -579,10 +539,14 @@ __global__ __launch_bounds__(kTB) void k_tail(const double2* __restrict__ cand_x
 
 hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
                        const uint32_t* cand_kap, const uint32_t* exact, const Params* prm,
-                       DevStatus* ds, double2* out_xy, int32_t* out_idx, DevStatus* host_ds,
-                       uint64_t* pub, Counters* ctr, uint32_t epoch, hipStream_t s) {
+                       DevStatus* ds, uint16_t* oslot, uint32_t* ocount, double2* out_xy,
+                       int32_t* out_idx, DevStatus* host_ds, hipStream_t s) {
     hipLaunchKernelGGL(k_tail, dim3(2), dim3(kTB), 0, s, cand_xy, cand_idx, cand_key, cand_kap, exact,
-                       prm, ds, out_xy, out_idx, host_ds, pub, ctr, epoch);
+                       prm, ds + 1, oslot, ocount);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tail_out, dim3(kOutGrid), dim3(kOutBlock), 0, s, cand_xy, cand_idx, ds, oslot,
+                       ocount, out_xy, out_idx, host_ds);
     return hipGetLastError();
 }
 

@@ -83,6 +83,28 @@ def test_device_orient_vs_exact(torch_dev, ctx):
         assert g == orient_q(r[0:2], r[2:4], r[4:6])
 
 
+def test_device_orient_shared_coordinates(torch_dev, ctx):
+    """Triples with repeated points or a shared x or y coordinate (exactly
+    collinear or not), at several scales: the exact-zero shortcut of the
+    predicate and the cases next to it."""
+    rng = random.Random(43)
+    rows = []
+    for _ in range(4000):
+        s = math.ldexp(1.0, rng.choice([-290, -40, 0, 40, 290]))
+        a = (rng.uniform(-1, 1) * s, rng.uniform(-1, 1) * s)
+        b = (rng.uniform(-1, 1) * s, rng.uniform(-1, 1) * s)
+        y1 = rng.uniform(-1, 1) * s
+        rows += [(*a, *a, *b), (*a, *b, *a), (*a, *b, *b), (*a, *a, *a),
+                 (*a, a[0], b[1], *b), (a[0], y1, *a, a[0], b[1]), (y1, a[1], *a, b[0], a[1]),
+                 (*a, a[0], b[1], b[0], a[1]), (*a, b[0], a[1], *b),
+                 (*a, _walk(a[0], 1), a[1], a[0], _walk(a[1], 1))]
+    abc = np.array(rows, dtype=np.float64)
+    say(f"device orient on {len(rows)} degenerate triples")
+    got = ctx.debug_orient(to_dev(torch_dev, abc))
+    for r, g in zip(rows, got):
+        assert g == orient_q(r[0:2], r[2:4], r[4:6]), r
+
+
 def _key_q(x, y, x0, y0):
     from fractions import Fraction
     dx = Fraction(x) - Fraction(x0)
