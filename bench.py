@@ -34,19 +34,19 @@ PAPER_MS_SQUARE_DISK_20M = 446.4 + 418.1
 # kernel and `traffic` is null.
 TRAFFIC = {
     "filter1": {
-        "bytes": 535_700_000,  # 320.4 MB fetched + 215.3 MB written
+        "bytes": 535_600_000,  # 320.3 MB fetched + 215.3 MB written
         "profile": "profiles/hull_square_disk_20M_hbm_counters.md",
         "sources": {
             "paper_1508_05931_amd/csrc/kernels_filter.hip":
-                "41ff5acd3a3dd0d37cc6b0c6d8b9daf59c57c96ae25d41f943a7df7a0419af2e",
+                "64f69a225314502e643a6573f57e65473b4eb4982459fd89b3e9453f811abc51",
             "paper_1508_05931_amd/csrc/steps.hpp":
-                "3769217f35918d9f1ce83dbc71915cc697f0d1bc7e5a2036fe61156b5dbdb72f",
+                "b8a17d37316efece011b1de67cb39106b34fe7134dc7e05fd035c1f6ed96ebb0",
             "paper_1508_05931_amd/csrc/exact.hpp":
                 "492fba6ee743cba0bb741d699072aaffa58163bfd2ddf06fa43db6642a3a9861",
             "paper_1508_05931_amd/csrc/common.hpp":
-                "81d9a7ea2e755ffb60897bf2177575a11f6a8ef0ab304da10db0e8e5332869c9",
+                "39fc60510659876fdf9f0fa85222224c07ee35a18aa185435dca38f50ca8cc5c",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "75aa972a358de908a32cb32785bd3fea7ccda063b4e092c1a616e40f2f85dc00",
+                "93826fdec546bc61fbd804232e8fe5c44834e2c08cfd41991e125dd1744bd8b4",
         },
     },
 }
