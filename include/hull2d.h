@@ -67,7 +67,9 @@ typedef struct {
      * c > 0: subsets of c points.  The hull is identical in every mode; only
      * the number of round-2 survivors and the time change. */
     int32_t round2_chunk;
-    /* 1: record per-kernel device times (HIP events) into hull2d_stats. */
+    /* 1: record per-kernel device times (HIP events) into hull2d_stats.
+     * 2: record only Step 1 and Steps 2-3 (the two streaming passes over the
+     * input), two events per call; the other stage times stay 0. */
     int32_t profile;
     /* Only for round2_chunk = 0.  0 (default): sort only the round-1 survivors
      * that can still be running maxima of the walk (coarse angle buckets and
@@ -118,7 +120,7 @@ typedef struct {
     int64_t n_candidates; /* points sorted for round 2 (= n_sorted with full_sort)  */
     double ms_total;      /* host wall clock of the whole call                     */
     double ms_device;     /* first kernel start to end of the host copy (events)   */
-    double ms_stage[HULL2D_NUM_STAGES]; /* filled when options.profile = 1        */
+    double ms_stage[HULL2D_NUM_STAGES]; /* filled when options.profile = 1 (2: two) */
 } hull2d_stats;
 
 /* Create a context on HIP device `device` using stream `hip_stream`

@@ -136,10 +136,14 @@ def _i32p(a: np.ndarray):
 
 
 class Hull2D:
-    """A library context bound to one device and one HIP stream."""
+    """A library context bound to one device and one HIP stream.
+
+    profile: 0 (or False) no stage times; 1 (or True) every stage's device
+    time in last_stats.ms_stage (one HIP event per stage); 2 only Step 1 and
+    Steps 2-3 (two events per call)."""
 
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
-                 profile: bool = False, full_sort: bool = False, learned: bool = False,
+                 profile: int = 0, full_sort: bool = False, learned: bool = False,
                  weights=None):
         import torch
         lib = load_library()
@@ -149,7 +153,7 @@ class Hull2D:
             stream = torch.cuda.current_stream(device)
         self.device = int(device)
         self.stream = stream
-        opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(bool(profile)),
+        opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
                        int(bool(full_sort)), int(bool(learned)))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),

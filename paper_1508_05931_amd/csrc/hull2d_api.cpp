@@ -620,11 +620,13 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     if (st != HULL2D_OK) return st;
 
     const bool prof = c->opt.profile && c->have_events;
+    const bool prof_all = prof && c->opt.profile == 1;  // 2: Steps 1 and 2-3 only
     hipStream_t s = c->stream;
     int marks[2 * HULL2D_NUM_STAGES];
     int n_marks = 0;
     auto mark = [&](int i) {
-        if (prof && n_marks < 2 * HULL2D_NUM_STAGES) {
+        const bool want = prof_all || (prof && (i == HULL2D_STAGE_EXTREMES || i == HULL2D_STAGE_FILTER1));
+        if (want && n_marks < 2 * HULL2D_NUM_STAGES) {
             (void)hipEventRecord(c->ev[i], s);
             marks[n_marks++] = i;
         }
