@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restric
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int64_t j = i + u * stride;
-            if (j < n) p[u] = xy[j];
+            if (j < n) p[u] = load_stream(&xy[j]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
 #pragma unroll
         for (int k = 0; k < kF1Ipt; ++k) {
             const int64_t pos = beg + k * kF1Block + threadIdx.x;
-            if (pos < end) nx[k] = xy[pos];
+            if (pos < end) nx[k] = load_stream(&xy[pos]);
         }
     }
     for (int64_t base = beg; base < end; base += kF1Tile) {
@@ -339,13 +339,13 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
 #pragma unroll
             for (int k = 0; k < kF1Ipt; ++k) {
                 const int64_t pos = nb + k * kF1Block + threadIdx.x;
-                if (pos < end) nx[k] = xy[pos];
+                if (pos < end) nx[k] = load_stream(&xy[pos]);
             }
         } else {
 #pragma unroll
             for (int k = 0; k < kF1Ipt; ++k) {
                 const int64_t pos = base + k * kF1Block + threadIdx.x;
-                if (pos < end) p[k] = xy[pos];
+                if (pos < end) p[k] = load_stream(&xy[pos]);
             }
         }
         uint64_t mask[kF1Ipt];
@@ -391,6 +391,9 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
             if ((mask[k] >> lane) & 1ull) {
                 int64_t pos = base + k * kF1Block + threadIdx.x;
                 int64_t o = cursor + s_off[k * NW + wave] + (uint32_t)__popcll(mask[k] & lanemask_lt());
+                // plain stores: the survivors are read again soon (the
+                // bucket maxima and the candidates), from the cache when
+                // they are still there
                 comp_xy[o] = p[k];
                 comp_idx[o] = (uint32_t)pos;
                 keys[o] = key[k];
