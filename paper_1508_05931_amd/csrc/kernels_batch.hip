@@ -555,7 +555,7 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
 #pragma unroll
     for (int k = 0; k < kBI; ++k) {
         const uint32_t i = (uint32_t)(k * kBB + tid);
-        if (i < n) nx[k] = xy[i];
+        if (i < n) nx[k] = load_stream(&xy[i]);
     }
     for (uint32_t b0 = 0; b0 < n; b0 += kBT) {
         double2 p[kBI];
@@ -563,7 +563,7 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
         for (int k = 0; k < kBI; ++k) {
             p[k] = nx[k];
             const uint32_t i = b0 + kBT + (uint32_t)(k * kBB + tid);
-            if (i < n) nx[k] = xy[i];
+            if (i < n) nx[k] = load_stream(&xy[i]);
         }
 #pragma unroll
         for (int k = 0; k < kBI; ++k) {
@@ -630,7 +630,7 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
 #pragma unroll
             for (int k = 0; k < kBI; ++k) {
                 const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
-                if (i < n) p[k] = xy[i];
+                if (i < n) p[k] = load_stream(&xy[i]);
             }
 #pragma unroll
             for (int k = 0; k < kBI; ++k) {
