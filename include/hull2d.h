@@ -85,7 +85,20 @@ typedef struct {
      * (hull2d_set_weights / hull2d_load_weights), else hull2d_compute
      * returns HULL2D_ERR_WEIGHTS. */
     int32_t filter;
-    int32_t reserved[3];
+    /* Schedule of the batched form (hull2d_batch); 0 keeps each default.
+     * batch_blocks_per_cu: workgroups per compute unit of the persistent
+     * launch (1 or 2; 0: as many as fit).  batch_order: the order in which
+     * workgroups take the sets: 0 by size class (powers of two), largest
+     * first; 1 by exact size, largest first; 2 input order.
+     * paper_1508_05931_amd/autotune.py picks both by timing. */
+    int32_t batch_blocks_per_cu;
+    int32_t batch_order;
+    /* 1: hull2d_batch captures its device work (the uploads of the offsets
+     * and the schedule, the persistent launch, the download of the per-set
+     * counts) in a HIP graph on the first call and replays it while the
+     * set count, the points' address and the workspace stay the same;
+     * 0: plain stream work every call.  The results are identical. */
+    int32_t batch_graph;
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */

@@ -9,6 +9,7 @@ functions raise.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from dataclasses import dataclass, field
 
@@ -47,7 +48,8 @@ class HullError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("round2_chunk", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("full_sort", ctypes.c_int32),
-                ("filter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("filter", ctypes.c_int32), ("batch_blocks_per_cu", ctypes.c_int32),
+                ("batch_order", ctypes.c_int32), ("batch_graph", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -135,16 +137,35 @@ def _i32p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
 
 
+TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "batch.json")
+
+
+def tuned_batch_schedule() -> dict:
+    """The batched form's schedule chosen by autotune.py (empty: none)."""
+    try:
+        with open(TUNING) as f:
+            t = json.load(f)
+        return {k: int(t[k]) for k in ("batch_blocks_per_cu", "batch_order") if k in t}
+    except (OSError, ValueError, KeyError, TypeError):
+        return {}
+
+
 class Hull2D:
     """A library context bound to one device and one HIP stream.
 
     profile: 0 (or False) no stage times; 1 (or True) every stage's device
     time in last_stats.ms_stage (one HIP event per stage); 2 only Step 1 and
-    Steps 2-3 (two events per call)."""
+    Steps 2-3 (two events per call).
+
+    batch_graph: capture and replay the batched form's device work in a HIP
+    graph.  batch_blocks_per_cu / batch_order: the batched form's schedule;
+    None takes the values autotune.py stored in tuning/batch.json, else the
+    library's defaults."""
 
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
                  profile: int = 0, full_sort: bool = False, learned: bool = False,
-                 weights=None):
+                 weights=None, batch_graph: bool = True, batch_blocks_per_cu: int | None = None,
+                 batch_order: int | None = None):
         import torch
         lib = load_library()
         if device is None:
@@ -153,8 +174,14 @@ class Hull2D:
             stream = torch.cuda.current_stream(device)
         self.device = int(device)
         self.stream = stream
+        tuned = tuned_batch_schedule()
+        if batch_blocks_per_cu is None:
+            batch_blocks_per_cu = tuned.get("batch_blocks_per_cu", 0)
+        if batch_order is None:
+            batch_order = tuned.get("batch_order", 0)
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
-                       int(bool(full_sort)), int(bool(learned)))
+                       int(bool(full_sort)), int(bool(learned)), int(batch_blocks_per_cu),
+                       int(batch_order), int(bool(batch_graph)))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))

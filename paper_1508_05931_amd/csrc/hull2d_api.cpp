@@ -3,6 +3,7 @@
 // and the final Graham stack scan on the host (Step 8 of gScan, Section 3).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -93,6 +94,17 @@ struct hull2d_ctx {
     int64_t hb_cap_h = -1;
     int32_t* hb_hull = nullptr;
     int batch_grid = 0;
+    // the batched form's device work captured in a graph, and what it was
+    // captured for (replayed while all of it is unchanged)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t bgraph = nullptr;
+    bool bgraph_off = false;  // capture failed once: plain stream work
+    int32_t bg_S = -1;
+    int64_t bg_N = -1;
+    const double* bg_xy = nullptr;
+    const void* bg_ws = nullptr;  // device workspace
+    const void* bg_hb = nullptr;  // pinned staging
+    int bg_grid = 0;
 
     // learned filter: weights (float32 master + bfloat16 inference copies),
     // optimiser state, the per-call proposal, training activations
@@ -261,6 +273,12 @@ hull2d_status ensure_host(hull2d_ctx* c, int64_t m) {
 // candidates, radix ping-pong, keep flags, hull indices) and S-sized per-set
 // arrays, plus pinned staging for the offsets, the order and the results.
 hull2d_status ensure_batch(hull2d_ctx* c, int64_t N, int32_t S) {
+    if ((N > c->bcap_n || S > c->bcap_s || S > c->hb_cap_s) && c->bgraph) {
+        // the captured work names the buffers replaced below
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipGraphExecDestroy(c->bgraph);
+        c->bgraph = nullptr;
+    }
     if (N > c->bcap_n || S > c->bcap_s) {
         const int64_t wn = std::max<int64_t>(std::max<int64_t>(N, c->bcap_n), 1);
         const int64_t ws = std::max<int64_t>(std::max<int64_t>(S, c->bcap_s), 1);
@@ -582,6 +600,8 @@ void hull2d_destroy(hull2d_ctx* c) {
     if (c->stream || c->dmem) (void)hipStreamSynchronize(c->stream);
     if (c->dmem) (void)hipFree(c->dmem);
     if (c->ctr) (void)hipFree(c->ctr);
+    if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_ds) (void)hipHostFree(c->h_ds);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
@@ -875,15 +895,27 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
     const int64_t N = h_offsets[S];
     hull2d_status st = ensure_batch(c, N, S);
     if (st != HULL2D_OK) return st;
-    if (c->batch_grid == 0) c->batch_grid = c->cu_count * std::max(1, batch_blocks_per_cu());
+    {
+        const int fit = std::max(1, batch_blocks_per_cu());
+        const int want = c->opt.batch_blocks_per_cu > 0 ? std::min(c->opt.batch_blocks_per_cu, fit) : fit;
+        c->batch_grid = c->cu_count * want;
+    }
     hipStream_t s = c->stream;
 
-    // largest sets first (by size class: the schedule only needs it roughly)
+    // the order in which workgroups take the sets
     std::memcpy(c->hb_offs, h_offsets, (size_t)(S + 1) * sizeof(int64_t));
-    {
+    auto size_of = [&](int32_t i) { return h_offsets[i + 1] - h_offsets[i]; };
+    if (c->opt.batch_order == 2) {
+        for (int32_t i = 0; i < S; ++i) c->hb_order[i] = i;
+    } else if (c->opt.batch_order == 1) {
+        for (int32_t i = 0; i < S; ++i) c->hb_order[i] = i;
+        std::stable_sort(c->hb_order, c->hb_order + S,
+                         [&](int32_t a, int32_t b) { return size_of(a) > size_of(b); });
+    } else {
+        // largest size class (power of two) first: counting sort, stable
         int32_t cnt[64] = {0};
         auto cls = [&](int32_t i) {
-            const int64_t n = h_offsets[i + 1] - h_offsets[i];
+            const int64_t n = size_of(i);
             return 63 - (n > 0 ? __builtin_clzll((unsigned long long)n) : 63);
         };
         for (int32_t i = 0; i < S; ++i) ++cnt[cls(i)];
@@ -895,18 +927,72 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         }
         for (int32_t i = 0; i < S; ++i) c->hb_order[pos[cls(i)]++] = i;
     }
-    if (c->have_events) HX_TRY(hipEventRecord(c->ev[HULL2D_NUM_STAGES], s));
-    HX_TRY(hipMemcpyAsync(c->b_offs, c->hb_offs, (size_t)(S + 1) * 8, hipMemcpyHostToDevice, s));
-    HX_TRY(hipMemcpyAsync(c->b_order, c->hb_order, (size_t)S * 4, hipMemcpyHostToDevice, s));
-    HX_TRY(hipMemsetAsync(c->b_meta, 0, 4, s));
     int32_t* d_count = c->b_meta + 1;
     int32_t* d_start = d_count + S;
     uint32_t* d_flags = (uint32_t*)(d_start + S);
-    HX_TRY(launch_batch(reinterpret_cast<const double2*>(d_xy), c->b_offs, c->b_order, S, c->b_sv_xy,
-                        c->b_sv_idx, c->b_sv_key, c->b_cd_xy, c->b_cd_idx, c->b_cd_key, c->b_ka,
-                        c->b_kb, c->b_va, c->b_vb, c->b_flag, c->b_hull, (uint32_t*)c->b_meta,
-                        d_count, d_start, d_flags, c->ctr, c->batch_grid, s));
-    HX_TRY(hipMemcpyAsync(c->hb_meta, c->b_meta, (size_t)(3 * S + 1) * 4, hipMemcpyDeviceToHost, s));
+    // the device work of one call: uploads of the offsets and the order, the
+    // counter reset, the persistent launch, the download of the per-set
+    // counts, starts and flags
+    auto device_work = [&](hipStream_t q) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(c->b_offs, c->hb_offs, (size_t)(S + 1) * 8, hipMemcpyHostToDevice, q);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->b_order, c->hb_order, (size_t)S * 4, hipMemcpyHostToDevice, q);
+        if (e == hipSuccess) e = launch_batch_clear((uint32_t*)c->b_meta, q);
+        if (e == hipSuccess)
+            e = launch_batch(reinterpret_cast<const double2*>(d_xy), c->b_offs, c->b_order, S, c->b_sv_xy,
+                             c->b_sv_idx, c->b_sv_key, c->b_cd_xy, c->b_cd_idx, c->b_cd_key, c->b_ka,
+                             c->b_kb, c->b_va, c->b_vb, c->b_flag, c->b_hull, (uint32_t*)c->b_meta,
+                             d_count, d_start, d_flags, c->ctr, c->batch_grid, q);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->hb_meta, c->b_meta, (size_t)(3 * S + 1) * 4, hipMemcpyDeviceToHost, q);
+        return e;
+    };
+    if (c->have_events) HX_TRY(hipEventRecord(c->ev[HULL2D_NUM_STAGES], s));
+    bool replayed = false;
+    if (c->opt.batch_graph && !c->bgraph_off) {
+        const bool same = c->bgraph && c->bg_S == S && c->bg_N == N && c->bg_xy == d_xy &&
+                          c->bg_ws == (const void*)c->b_sv_xy && c->bg_hb == (const void*)c->hb_offs &&
+                          c->bg_grid == c->batch_grid;
+        if (!same) {
+            if (c->bgraph) {
+                (void)hipGraphExecDestroy(c->bgraph);
+                c->bgraph = nullptr;
+            }
+            // captured on a stream of its own (the caller's stream may be the
+            // null stream, which cannot be captured), replayed on the caller's
+            if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+                (void)hipGetLastError();
+                c->cap_stream = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            bool ok = c->cap_stream &&
+                      hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                const hipError_t we = device_work(c->cap_stream);
+                ok = hipStreamEndCapture(c->cap_stream, &g) == hipSuccess && we == hipSuccess && g;
+            }
+            if (ok) ok = hipGraphInstantiate(&c->bgraph, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (!ok) {
+                (void)hipGetLastError();
+                if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
+                c->bgraph = nullptr;
+                c->bgraph_off = true;
+            } else {
+                c->bg_S = S;
+                c->bg_N = N;
+                c->bg_xy = d_xy;
+                c->bg_ws = (const void*)c->b_sv_xy;
+                c->bg_hb = (const void*)c->hb_offs;
+                c->bg_grid = c->batch_grid;
+            }
+        }
+        if (c->bgraph) {
+            HX_TRY(hipGraphLaunch(c->bgraph, s));
+            replayed = true;
+        }
+    }
+    if (!replayed) HX_TRY(device_work(s));
     HX_TRY(spin_sync(c));
     const int32_t* cnt = c->hb_meta + 1;
     const int32_t* start = cnt + S;

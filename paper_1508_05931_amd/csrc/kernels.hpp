@@ -135,6 +135,9 @@ hipError_t launch_batch(const double2* xy, const int64_t* offs, const int32_t* o
                         uint32_t* hull_cursor, int32_t* h_count, int32_t* h_start,
                         uint32_t* h_flags, Counters* ctr, int grid, hipStream_t s);
 int batch_blocks_per_cu();
+// Clears the batched form's hull-buffer counter (meta[0]); a kernel rather
+// than a memset so that the work can be captured in a graph.
+hipError_t launch_batch_clear(uint32_t* meta, hipStream_t s);
 constexpr uint32_t kBatchFallback = 4u;
 
 // ---- learned-filter variant of Steps 1-2 and its network ----------------

@@ -1005,6 +1005,15 @@ hipError_t launch_batch(const double2* xy, const int64_t* offs, const int32_t* o
     return hipGetLastError();
 }
 
+namespace {
+__global__ void k_batch_clear(uint32_t* __restrict__ meta) { meta[0] = 0; }
+}  // namespace
+
+hipError_t launch_batch_clear(uint32_t* meta, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(1), 0, s, meta);
+    return hipGetLastError();
+}
+
 int batch_blocks_per_cu() {
     return resident_blocks(reinterpret_cast<const void*>(k_batch), kBB);
 }

@@ -69,3 +69,15 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(hx, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         hx.load_library()
+
+
+def test_shipped_batch_schedule_is_valid():
+    """The autotuner's stored schedule names options the library accepts,
+    and the binding's option struct has the header's size."""
+    import paper_1508_05931_amd as hx
+    if not os.path.exists(hx.TUNING):
+        pytest.skip("no tuned schedule in the tree")
+    t = hx.tuned_batch_schedule()
+    assert t["batch_blocks_per_cu"] in (1, 2) and t["batch_order"] in (0, 1, 2)
+    # uint32 struct_size and seven int32 fields, as hull2d_options
+    assert ctypes.sizeof(hx._Options) == 4 + 7 * 4

@@ -186,3 +186,51 @@ def test_batch_4096_sets_golden(torch_dev, ctx):
     for i in pick:
         s = pts[offs[i]:offs[i + 1]]
         assert hulls[out_offs[i]:out_offs[i + 1]].tolist() == oracle.hull(s).tolist()
+
+
+def _graph_sets(seed):
+    sizes = synth.batch_sizes(200, 64.0, 20_000.0, 950)
+    return [synth.batch_set(int(n), k, seed)[0] for k, n in enumerate(sizes)]
+
+
+def test_batch_graph_replays_match_eager(torch_dev, hx):
+    """The captured batch work, replayed several times with eager work and
+    synchronisations between the replays, gives the eager result every time,
+    also after new points are written into the same buffer."""
+    sets = _graph_sets(951)
+    pts, offs = _concat(sets)
+    d = torch_dev.from_numpy(pts).cuda()
+    cg = hx.Hull2D(batch_graph=True)
+    ce = hx.Hull2D(batch_graph=False)
+    want_h, want_o = ce.batch(d, offs)
+    say("batch graph replays")
+    for r in range(4):
+        h, o = cg.batch(d, offs)
+        assert o.tolist() == want_o.tolist() and h.tolist() == want_h.tolist(), f"replay {r}"
+        one = cg.compute(d[offs[3]:offs[4]])
+        assert one.tolist() == oracle.hull(sets[3]).tolist()
+        torch_dev.cuda.synchronize()
+    sets2 = _graph_sets(952)
+    pts2, offs2 = _concat(sets2)
+    assert offs2.tolist() == offs.tolist()
+    d.copy_(torch_dev.from_numpy(pts2))
+    torch_dev.cuda.synchronize()
+    h2, o2 = cg.batch(d, offs)
+    w2, wo2 = ce.batch(d, offs)
+    assert o2.tolist() == wo2.tolist() and h2.tolist() == w2.tolist()
+    _check_all(h2, o2, sets2)
+    cg.close()
+    ce.close()
+
+
+@pytest.mark.parametrize("blocks,order", [(1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (2, 2)])
+def test_batch_schedules_agree(torch_dev, hx, blocks, order):
+    """Every schedule the autotuner chooses from gives the same hulls."""
+    sets = _graph_sets(953)
+    pts, offs = _concat(sets)
+    d = torch_dev.from_numpy(pts).cuda()
+    say(f"batch schedule blocks={blocks} order={order}")
+    c = hx.Hull2D(batch_blocks_per_cu=blocks, batch_order=order)
+    h, o = c.batch(d, offs)
+    _check_all(h, o, sets)
+    c.close()

@@ -138,3 +138,4 @@ def test_histogram_definition():
     assert h.reshape(32, 32)[:, 0].sum() > 0 and h.reshape(32, 32)[:, 31].sum() > 0
     assert np.allclose(h.reshape(32, 32).sum(), 1024.0)
     assert mlp.histogram(np.zeros((0, 2))).sum() == 0
+
