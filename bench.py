@@ -34,19 +34,19 @@ PAPER_MS_SQUARE_DISK_20M = 446.4 + 418.1
 # kernel and `traffic` is null.
 TRAFFIC = {
     "filter1": {
-        "bytes": 535_600_000,  # 320.3 MB fetched + 215.3 MB written
+        "bytes": 534_000_000,  # 320.3 MB fetched + 213.7 MB written
         "profile": "profiles/hull_square_disk_20M_hbm_counters.md",
         "sources": {
             "paper_1508_05931_amd/csrc/kernels_filter.hip":
-                "64f69a225314502e643a6573f57e65473b4eb4982459fd89b3e9453f811abc51",
+                "6df56172e77c186a34e022d60742acc26e51d70b6062c05a39290b8238e6e83c",
             "paper_1508_05931_amd/csrc/steps.hpp":
                 "b8a17d37316efece011b1de67cb39106b34fe7134dc7e05fd035c1f6ed96ebb0",
             "paper_1508_05931_amd/csrc/exact.hpp":
                 "492fba6ee743cba0bb741d699072aaffa58163bfd2ddf06fa43db6642a3a9861",
             "paper_1508_05931_amd/csrc/common.hpp":
-                "39fc60510659876fdf9f0fa85222224c07ee35a18aa185435dca38f50ca8cc5c",
+                "044be352493ceaba3339859e0a74a6c108f123de1ccffeb5df255bc633cfd97f",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "93826fdec546bc61fbd804232e8fe5c44834e2c08cfd41991e125dd1744bd8b4",
+                "4c0ee9f8894cb62576e8ddcdf86572518bb532c71bcb0d3fd9962412be460641",
         },
     },
 }
