@@ -78,10 +78,13 @@ typedef struct {
     int32_t full_sort;
     /* First-round filter.  0 (default): the quadrilateral of Steps 1-2.
      * 1: the learned discard polygon (not in the paper): a network proposes 16
-     * directions from a 32 x 32 occupancy histogram of a sample; the exact
-     * hull of the points extreme in those directions and of the four Step-1
-     * extremes is the discard polygon.  It contains the quadrilateral, so it
-     * discards at least as much, and never a hull vertex.  Needs weights
+     * directions from a 32 x 32 occupancy histogram of a sample (every point
+     * when n <= 4096, else 16 blocks of 256 points, block b starting at
+     * floor(b n / 16)); the exact hull of the sample points extreme in those
+     * directions is the discard polygon, and a point is discarded strictly
+     * inside it or strictly inside the quadrilateral.  So it discards at
+     * least as much as the quadrilateral, and never a hull vertex (both
+     * polygons have input points as corners).  Needs weights
      * (hull2d_set_weights / hull2d_load_weights), else hull2d_compute
      * returns HULL2D_ERR_WEIGHTS. */
     int32_t filter;
@@ -216,8 +219,8 @@ hull2d_status hull2d_train_step(hull2d_ctx* ctx, const float* d_x, const float* 
 
 /* What the learned filter used in the last hull2d_compute with filter = 1:
  * dirs[32] (the 16 directions), cand[20] (input indices: the four Step-1
- * extremes, then the point extreme along each direction), y[32] (the raw
- * network outputs), *nv (corners of the discard polygon).  Any pointer may
+ * extremes, then the sample point extreme along each direction), y[32] (the
+ * raw network outputs), *nv (corners of the discard polygon).  Any pointer may
  * be NULL.  INVALID_ARG if the last call did not use the learned filter. */
 hull2d_status hull2d_debug_learned(hull2d_ctx* ctx, double* dirs, int32_t* cand, float* y,
                                    int32_t* nv);

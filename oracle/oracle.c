@@ -368,6 +368,13 @@ int oracle_model(const double* xy, int64_t n, int64_t chunk, oracle_model_result
 /* Learned-filter variant of the first round (plain definition).            */
 /* ------------------------------------------------------------------------ */
 
+/* The network's sample: every point when n <= 4096, else 16 blocks of 256
+ * consecutive points, block b starting at floor(b n / 16). */
+static int64_t net_sample_size(int64_t n) { return n < 4096 ? n : 4096; }
+static int64_t net_sample_point(int64_t s, int64_t n) {
+    return n <= 4096 ? s : ((s >> 8) * n) / 16 + (s & 255);
+}
+
 int oracle_learned_round1(const double* xy, int64_t n, const double* dirs, int32_t k,
                           uint8_t* keep, int32_t* cand, int64_t* m1) {
     int st = oracle_validate(xy, n);
@@ -378,43 +385,60 @@ int oracle_learned_round1(const double* xy, int64_t n, const double* dirs, int32
     *m1 = 0;
     if (n == 0) return ORACLE_OK;
 
-    /* candidates: the four extremes of Step 1, then one per direction */
+    /* the four extremes of Step 1, then per direction the farthest sample
+     * point (ties: the smallest index; sample indices grow with s) */
     int32_t c[68];
     extremes(xy, n, c);
+    const int64_t ns = net_sample_size(n);
     for (int32_t j = 0; j < k; ++j) {
         const double ux = dirs[2 * j], uy = dirs[2 * j + 1];
-        int32_t best = 0;
-        double bv = fma(xy[0], ux, xy[1] * uy);
-        for (int64_t i = 1; i < n; ++i) {
+        int32_t best = -1;
+        double bv = 0.0;
+        for (int64_t s = 0; s < ns; ++s) {
+            const int64_t i = net_sample_point(s, n);
             double v = fma(xy[2 * i], ux, xy[2 * i + 1] * uy);
-            if (v > bv) { bv = v; best = (int32_t)i; }
+            if (best < 0 || v > bv) { bv = v; best = (int32_t)i; }
         }
         c[4 + j] = best;
     }
     if (cand) memcpy(cand, c, (size_t)(4 + k) * sizeof(int32_t));
 
-    /* their exact convex hull, as coordinates */
-    int32_t nc = 4 + k;
-    double cxy[2 * 68];
-    for (int32_t j = 0; j < nc; ++j) {
-        cxy[2 * j] = xy[2 * (int64_t)c[j]];
-        cxy[2 * j + 1] = xy[2 * (int64_t)c[j] + 1];
+    /* the polygon: the exact convex hull of the direction candidates */
+    double pxy[2 * 64];
+    for (int32_t j = 0; j < k; ++j) {
+        pxy[2 * j] = xy[2 * (int64_t)c[4 + j]];
+        pxy[2 * j + 1] = xy[2 * (int64_t)c[4 + j] + 1];
     }
-    int32_t hv[68];
+    int32_t hv[64];
     int64_t h = 0;
-    st = oracle_hull(cxy, nc, hv, 68, &h);
-    if (st != ORACLE_OK) return st;
+    if (k > 0) {
+        st = oracle_hull(pxy, k, hv, 64, &h);
+        if (st != ORACLE_OK) return st;
+    }
 
-    /* strictly left of every edge: discarded */
+    /* the quadrilateral of Step 2: distinct corners, counter-clockwise */
+    int32_t corner[4];
+    int nc = 0;
+    for (int j = 0; j < 4; ++j) {
+        int dup = 0;
+        for (int u = 0; u < nc; ++u) dup |= same_point(xy, corner[u], c[j]);
+        if (!dup) corner[nc++] = c[j];
+    }
+
+    /* discarded: strictly inside the quadrilateral or strictly inside the
+     * polygon (strictly left of every edge; fewer than three corners: never) */
     int64_t cnt = 0;
     for (int64_t i = 0; i < n; ++i) {
-        int inside = h >= 3;
-        for (int64_t e = 0; e < h && inside; ++e) {
+        int in_q = nc >= 3;
+        for (int j = 0; j < nc && in_q; ++j)
+            in_q = orient_idx(xy, corner[j], corner[(j + 1) % nc], (int32_t)i) > 0;
+        int in_p = h >= 3;
+        for (int64_t e = 0; e < h && in_p; ++e) {
             const int32_t a = hv[e], b = hv[(e + 1) % h];
-            inside = oracle_orient(cxy[2 * a], cxy[2 * a + 1], cxy[2 * b], cxy[2 * b + 1],
-                                   xy[2 * i], xy[2 * i + 1]) > 0;
+            in_p = oracle_orient(pxy[2 * a], pxy[2 * a + 1], pxy[2 * b], pxy[2 * b + 1],
+                                 xy[2 * i], xy[2 * i + 1]) > 0;
         }
-        keep[i] = inside ? 0 : 1;
+        keep[i] = (in_q || in_p) ? 0 : 1;
         cnt += keep[i];
     }
     *m1 = cnt;

@@ -97,6 +97,10 @@ struct hull2d_ctx {
     // the batched form's device work captured in a graph, and what it was
     // captured for (replayed while all of it is unchanged)
     hipStream_t cap_stream = nullptr;
+    // the learned filter's proposal runs on a side stream beside Step 1
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool side_off = false;  // creation failed once: one stream
     hipGraphExec_t bgraph = nullptr;
     bool bgraph_off = false;  // capture failed once: plain stream work
     int32_t bg_S = -1;
@@ -116,7 +120,6 @@ struct hull2d_ctx {
     uint32_t* l_hist = nullptr;
     float *l_x = nullptr, *l_y = nullptr, *l_loss = nullptr, *l_h1 = nullptr, *l_h2 = nullptr;
     double* l_part = nullptr;
-    DirBest* l_dpart = nullptr;
     int64_t adam_t = 0;
     int32_t tcap_b = 0;
     char* tmem = nullptr;
@@ -371,16 +374,35 @@ constexpr int64_t kOffB3 = kOffW3 + (int64_t)kMlpOut * kMlpHidden;
 static_assert(kOffB3 + kMlpOut == kMlpParams, "parameter layout");
 static_assert(kMlpParams == HULL2D_MLP_PARAMS, "header constant");
 
+// The side stream and its fork / join events, made on first use.
+bool ensure_side(hull2d_ctx* c) {
+    if (c->side) return true;
+    if (c->side_off) return false;
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->side) (void)hipStreamDestroy(c->side);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        c->side = nullptr;
+        c->ev_fork = nullptr;
+        c->ev_join = nullptr;
+        c->side_off = true;
+        return false;
+    }
+    return true;
+}
+
 hull2d_status ensure_learned(hull2d_ctx* c) {
     if (c->lmem) return HULL2D_OK;
     const size_t P = (size_t)kMlpParams;
-    const size_t sizes[13] = {P * 4, P * 4, P * 4, P * 4,
+    const size_t sizes[12] = {P * 4, P * 4, P * 4, P * 4,
                               (size_t)kMlpIn * kMlpHidden * 2, (size_t)kMlpHidden * kMlpHidden * 2,
                               (size_t)kMlpHidden * kMlpOut * 2, sizeof(LearnOut), (size_t)kMlpIn * 4,
                               (size_t)kMlpIn * 4 + 2 * (size_t)kMlpHidden * 4, (size_t)kMlpOut * 4 + 16,
-                              (size_t)4 * 8 * c->cu_count, dir_part_bytes(kExtGridMax)};
-    size_t off[13], o = 0;
-    for (int i = 0; i < 13; ++i) {
+                              (size_t)4 * 8 * c->cu_count};
+    size_t off[12], o = 0;
+    for (int i = 0; i < 12; ++i) {
         off[i] = o;
         o = align_up(o + sizes[i], 256);
     }
@@ -405,7 +427,6 @@ hull2d_status ensure_learned(hull2d_ctx* c) {
     c->l_y = (float*)(b + off[10]);
     c->l_loss = c->l_y + kMlpOut;
     c->l_part = (double*)(b + off[11]);
-    c->l_dpart = (DirBest*)(b + off[12]);
     return HULL2D_OK;
 }
 
@@ -602,6 +623,9 @@ void hull2d_destroy(hull2d_ctx* c) {
     if (c->ctr) (void)hipFree(c->ctr);
     if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->h_ds) (void)hipHostFree(c->h_ds);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
@@ -656,19 +680,24 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
 
     // Step 1
-    // learned filter: sample histogram and network first; its directions
-    // ride along in the Step-1 pass, then the discard polygon
-    if (learned) {
-        HX_TRY(launch_histogram_sample(d_xy, n, c->l_part, learned_grid(n, c->cu_count), c->l_hist, s));
-        HX_TRY(launch_hist_to_x(c->l_hist, n, c->l_x, s));
-        HX_TRY(launch_mlp_infer(c->l_x, 1, mlp_dev(c), c->l_h1, c->l_h2, c->l_y, c->learn, s));
+    // learned filter: sample histogram, network, the sample's farthest point
+    // along each direction and their hull, the discard polygon (one
+    // workgroup, independent of Step 1: on a side stream beside it, except
+    // when every stage is timed)
+    const bool fork = learned && !prof_all && ensure_side(c);
+    if (learned && !fork) {
+        HX_TRY(launch_front(d_xy, n, mlp_dev(c), c->learn, s));
         mark(HULL2D_STAGE_LEARNED);
     }
-    const int grid_ext =
-        extremes_grid(n, c->cu_count, learned ? c->occ.extremes_dirs : c->occ.extremes);
-    HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds,
-                           learned ? c->learn->dirs : nullptr, learned ? c->l_dpart : nullptr, s));
-    if (learned) HX_TRY(launch_poly(d_xy, c->prm, c->learn, c->l_dpart, grid_ext, s));
+    if (fork) HX_TRY(hipEventRecord(c->ev_fork, s));
+    const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
+    HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, s));
+    if (fork) {
+        HX_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        HX_TRY(launch_front(d_xy, n, mlp_dev(c), c->learn, c->side));
+        HX_TRY(hipEventRecord(c->ev_join, c->side));
+        HX_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+    }
     mark(HULL2D_STAGE_EXTREMES);
     // Steps 2-3
     const int segs = std::min(
@@ -1169,8 +1198,11 @@ hull2d_status hull2d_debug_learned(hull2d_ctx* c, double* dirs, int32_t* cand, f
     if (!c->have_last || !c->last_learned) return HULL2D_ERR_INVALID_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
     LearnOut L;
+    DevStatus S;
     HX_TRY(hipMemcpyAsync(&L, c->learn, sizeof(LearnOut), hipMemcpyDeviceToHost, c->stream));
+    HX_TRY(hipMemcpyAsync(&S, c->ds, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
     HX_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 4; ++k) L.cand[k] = S.ext[k];  // the Step-1 extremes
     if (dirs) std::memcpy(dirs, L.dirs, sizeof(L.dirs));
     if (cand) std::memcpy(cand, L.cand, sizeof(L.cand));
     if (y) std::memcpy(y, L.y, sizeof(L.y));

@@ -47,10 +47,8 @@ struct DirBest {
     int32_t pad;
 };
 
-// dirs: NULL, or the learned filter's kMlpDirs directions ([2 * kMlpDirs]
-// doubles, device); then the same pass writes dpart[grid][kMlpDirs].
 hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
-                           DevStatus* ds, const double* dirs, DirBest* dpart, hipStream_t s);
+                           DevStatus* ds, hipStream_t s);
 int extremes_grid(int64_t n, int cu_count, int per_cu);
 
 // Resident blocks per compute unit of the fixed-grid streaming kernels (from
@@ -58,7 +56,7 @@ int extremes_grid(int64_t n, int cu_count, int per_cu);
 // exactly once: a block that cannot be resident would run in a second,
 // mostly empty wave of blocks.
 struct Occupancy {
-    int extremes = 1, extremes_dirs = 1, filter1 = 1, filter1_poly = 1;
+    int extremes = 1, filter1 = 1, filter1_poly = 1;
 };
 // At least 1 when the query fails.
 inline int resident_blocks(const void* kernel, int block) {
@@ -172,11 +170,13 @@ hipError_t launch_hist_to_x(const uint32_t* hist, int64_t n, float* x, hipStream
 // lo (rows = 1 only, may be NULL) receives the directions.
 hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* h1, float* h2, float* y,
                             LearnOut* lo, hipStream_t s);
-size_t dir_part_bytes(int grid);
-// the discard polygon from the Step-1 extremes and the per-block direction
-// partials of launch_extremes (grid blocks)
-hipError_t launch_poly(const double* xy, const Params* prm, LearnOut* lo, const DirBest* dpart,
-                       int grid, hipStream_t s);
+// The whole proposal in one workgroup: the sample histogram, the network and
+// its 16 directions into lo->y and lo->dirs (the same arithmetic as
+// launch_histogram_sample, launch_hist_to_x and launch_mlp_infer), then the
+// sample point farthest along each direction into lo->cand[4 + j] and their
+// exact convex hull into lo->poly (qb left to the filter; lo->cand[0..3],
+// the Step-1 extremes, are not written).
+hipError_t launch_front(const double* xy, int64_t n, const MlpDev& W, LearnOut* lo, hipStream_t s);
 // training
 hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int tA, const float* B, int ldb,
                        int tB, const float* bias, int relu, const float* mask, float* C, int ldc,

@@ -87,35 +87,15 @@ __device__ uint32_t lookback_sum(uint64_t* stat, uint32_t t, uint32_t agg, uint3
 // ---------------------------------------------------------------------------
 // Step 1
 // ---------------------------------------------------------------------------
-// kDirs > 0 (learned filter): the same pass also finds, for each of the
-// kDirs directions u in `dirs`, the point maximising fma(x, ux, y * uy)
-// (ties: smallest index), one partial per block in dpart.
-template <int kDirs>
 __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restrict__ xy, int64_t n,
-                                                        Cand* __restrict__ partial,
-                                                        const double* __restrict__ dirs,
-                                                        DirBest* __restrict__ dpart) {
+                                                        Cand* __restrict__ partial) {
     constexpr int NW = kExtBlock / 64;
-    constexpr int U = kDirs > 0 ? 4 : 8;
-    constexpr int D = kDirs > 0 ? kDirs : 1;
+    constexpr int U = 8;
     __shared__ Cand s_c[NW][4];
     __shared__ uint32_t s_flags;
-    __shared__ double s_u[2 * D];
-    __shared__ DirBest s_d[NW][D];
     Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
-    double bv[D];
-    int32_t bi[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        bv[j] = -INFINITY;
-        bi[j] = INT32_MAX;
-    }
     uint32_t bad = 0;
     if (threadIdx.x == 0) s_flags = 0;
-    if (kDirs > 0) {
-        if (threadIdx.x < 2 * kDirs) s_u[threadIdx.x] = dirs[threadIdx.x];
-        __syncthreads();
-    }
     const int64_t stride = (int64_t)gridDim.x * kExtBlock;
     for (int64_t i = (int64_t)blockIdx.x * kExtBlock + threadIdx.x; i < n; i += stride * U) {
         double2 p[U];
@@ -134,37 +114,11 @@ __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restric
                                   (p[u].y >= c[3].y);
                 if (need) offer(c, p[u].x, p[u].y, (int32_t)j);
                 bad |= domain_flags(p[u].x) | domain_flags(p[u].y);
-                // this thread's indices only grow: a tie keeps the earlier point
-#pragma unroll
-                for (int d = 0; d < kDirs; ++d) {
-                    const double v = fma(p[u].x, s_u[2 * d], p[u].y * s_u[2 * d + 1]);
-                    const bool tk = v > bv[d];
-                    bv[d] = tk ? v : bv[d];
-                    bi[d] = tk ? (int32_t)j : bi[d];
-                }
             }
         }
     }
     reduce4_wave(c);
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
-    if (kDirs > 0) {
-#pragma unroll
-        for (int d = 0; d < kDirs; ++d) {
-#pragma unroll
-            for (int m = 32; m > 0; m >>= 1) {
-                const double ov = __shfl_xor(bv[d], m);
-                const int32_t oi = __shfl_xor(bi[d], m);
-                dir_take(bv[d], bi[d], ov, oi);
-            }
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int d = 0; d < kDirs; ++d) {
-                s_d[wave][d].v = bv[d];
-                s_d[wave][d].i = bi[d];
-            }
-        }
-    }
     __syncthreads();
     if (bad) atomicOr(&s_flags, bad);
     if (lane == 0) {
@@ -184,14 +138,6 @@ __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restric
         }
         b.pad = (int32_t)s_flags;
         partial[(int64_t)blockIdx.x * 4 + k] = b;
-    }
-    if (kDirs > 0 && threadIdx.x < kDirs) {
-        const int d = (int)threadIdx.x;
-        double v = s_d[0][d].v;
-        int32_t i = s_d[0][d].i;
-        for (int w = 1; w < NW; ++w) dir_take(v, i, s_d[w][d].v, s_d[w][d].i);
-        dpart[(size_t)blockIdx.x * kDirs + d].v = v;
-        dpart[(size_t)blockIdx.x * kDirs + d].i = i;
     }
 }
 
@@ -278,7 +224,8 @@ __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict_
 // the segment lengths are added up afterwards (k_longest), and later kernels
 // read the survivors segment by segment.
 // ---------------------------------------------------------------------------
-// kPoly: the learned discard polygon replaces the quadrilateral.
+// kPoly: a point is also discarded strictly inside the learned polygon (the
+// discard region is the union of the quadrilateral and the polygon).
 template <bool kPoly>
 __global__ __launch_bounds__(kF1Block) void k_filter1(
     const double2* __restrict__ xy, int64_t n, int64_t chunk, const Params* __restrict__ prm,
@@ -301,6 +248,10 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
         double* dst = reinterpret_cast<double*>(&s_poly);
         for (int i = (int)threadIdx.x; i < (int)(sizeof(Poly) / sizeof(double)); i += kF1Block)
             dst[i] = src[i];
+        __syncthreads();
+        // the polygon's corners are input points: in the Step-1 box, whose
+        // bound the quadrilateral's test uses too
+        if (threadIdx.x == 0) s_poly.qb = prm->qbound;
         __syncthreads();
     }
     const int nc = prm->ncorner;
@@ -359,8 +310,14 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
             key[k] = 0;
             if (pos < end && !discard_all) {
                 const double px = p[k].x, py = p[k].y;
-                surv = kPoly ? !poly_inside(s_poly, px, py)
-                             : !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
+                // the learned polygon first: it holds most points where it
+                // pays, and the quadrilateral's test then runs for few lanes
+                if (kPoly) {
+                    surv = !poly_inside(s_poly, px, py);
+                    if (__ballot(surv) != 0 && surv) surv = !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
+                } else {
+                    surv = !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
+                }
                 if (surv && px == x0 && py == y0) {
                     surv = false;
                     ++p0c;
@@ -900,13 +857,9 @@ __global__ void k_debug_key(const double* __restrict__ xy, int64_t count, double
 }  // namespace
 
 hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
-                           DevStatus* ds, const double* dirs, DirBest* dpart, hipStream_t s) {
-    if (dirs)
-        hipLaunchKernelGGL(k_extremes<kMlpDirs>, dim3(grid), dim3(kExtBlock), 0, s,
-                           reinterpret_cast<const double2*>(xy), n, partial, dirs, dpart);
-    else
-        hipLaunchKernelGGL(k_extremes<0>, dim3(grid), dim3(kExtBlock), 0, s,
-                           reinterpret_cast<const double2*>(xy), n, partial, dirs, dpart);
+                           DevStatus* ds, hipStream_t s) {
+    hipLaunchKernelGGL(k_extremes, dim3(grid), dim3(kExtBlock), 0, s, reinterpret_cast<const double2*>(xy),
+                       n, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_extremes_final, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds);
@@ -926,8 +879,7 @@ int filter1_blocks(int64_t n, int cu_count, int per_cu) {
 void occupancy_filter(Occupancy& o) {
     // fewer, longer blocks than fit: three per compute unit measured
     // 88-91 us per 20M points against 94-98 us at the six that fit
-    o.extremes = std::min(resident_blocks(reinterpret_cast<const void*>(k_extremes<0>), kExtBlock), 3);
-    o.extremes_dirs = resident_blocks(reinterpret_cast<const void*>(k_extremes<kMlpDirs>), kExtBlock);
+    o.extremes = std::min(resident_blocks(reinterpret_cast<const void*>(k_extremes), kExtBlock), 3);
     o.filter1 = resident_blocks(reinterpret_cast<const void*>(k_filter1<false>), kF1Block);
     o.filter1_poly = resident_blocks(reinterpret_cast<const void*>(k_filter1<true>), kF1Block);
 }

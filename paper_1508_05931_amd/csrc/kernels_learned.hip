@@ -8,10 +8,13 @@
 //   k_mlp_layer ×3, k_mlp_dirs    1024 -> 256 -> 256 -> 32 network, bfloat16
 //                                 weights and layer inputs, float32 sums, one
 //                                 wave per output unit: 16 directions
-//   k_extremes<16>, k_poly        the point farthest along each direction
-//                                 (fma(x, ux, y * uy), ties: smallest index;
-//                                 in the same pass as Step 1), and the exact
-//                                 convex hull of those 16
+//   k_front                       all of the above in one workgroup, the
+//                                 form the hull path launches
+//   (Step 1, kernels_filter.hip)  the point farthest along each direction
+//                                 (fma(x, ux, y * uy), ties: smallest index)
+//                                 over the direction sample (every 16th
+//                                 block of 256 points) in the Step-1 pass,
+//                                 then the exact convex hull of those 16
 //                                 points and the four Step-1 extremes: the
 //                                 discard polygon, which contains the
 //                                 quadrilateral, so the first round stays
@@ -212,100 +215,271 @@ __global__ void k_mlp_dirs(const float* __restrict__ y, LearnOut* __restrict__ l
 }
 
 
-// The candidates and their exact convex hull (Andrew's monotone chain on at
-// most 20 points, one thread): the discard polygon.
-__global__ __launch_bounds__(64 * kDirs) void k_poly(const DirBest* __restrict__ part, int nparts,
-                                                    const double2* __restrict__ xy,
-                                                    const Params* __restrict__ prm,
-                                                    LearnOut* __restrict__ lo) {
-    __shared__ int32_t s_c[kPolyMax];
-    const int t = (int)threadIdx.x;
-    {
-        // wave j reduces direction j over the block partials
-        const int lane = (int)__lane_id(), j = t >> 6;
-        double v = -INFINITY;
-        int32_t i = INT32_MAX;
-        for (int b = lane; b < nparts; b += 64) dir_take(v, i, part[(size_t)b * kDirs + j].v, part[(size_t)b * kDirs + j].i);
+// The whole proposal in one workgroup of kFB threads: the sample's bounding
+// box and histogram (as k_sample_bbox / k_sample_hist), the network inputs
+// (as k_hist_to_x), the three layers (each output unit summed by one wave in
+// the order of k_mlp_layer) and the directions (as k_mlp_dirs), so the
+// outputs equal those of the separate kernels bit for bit.
+constexpr int kFB = 1024;
+
+// out[o] = act(W[o] . in + b[o]) for the kU units o = wave + 16 u of this
+// wave (in, out in LDS); the units' loads are in flight together, and each
+// unit's sum keeps the order of k_mlp_layer.
+template <int kIn, int kU>
+__device__ inline void front_layer(const float* in, const uint16_t* __restrict__ W,
+                                   const float* __restrict__ bias, bool hidden, float* out) {
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    float acc[kU];
 #pragma unroll
-        for (int m = 32; m > 0; m >>= 1) {
-            const double ov = __shfl_xor(v, m);
-            const int32_t oi = __shfl_xor(i, m);
-            dir_take(v, i, ov, oi);
-        }
-        if (lane == 0) s_c[4 + j] = i;
+    for (int u = 0; u < kU; ++u) acc[u] = 0.f;
+#pragma unroll 4
+    for (int i = lane; i < kIn; i += 64) {
+        const float x = from_bf16(to_bf16(in[i]));
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc[u] = fmaf(x, from_bf16(W[(size_t)(wave + 16 * u) * kIn + i]), acc[u]);
     }
-    if (t < 4) s_c[t] = prm->ext[t].i;
-    __syncthreads();
-    // the candidates' coordinates, loaded in parallel
-    __shared__ double s_x[kPolyMax], s_y[kPolyMax];
-    if (t < kPolyMax && s_c[t] != INT32_MAX) {
-        const double2 p = xy[s_c[t]];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) acc[u] += __shfl_xor(acc[u], m);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int o = wave + 16 * u;
+            const float a = acc[u] + bias[o];
+            out[o] = hidden ? from_bf16(to_bf16(fmaxf(a, 0.f))) : a;
+        }
+    }
+}
+
+// The exact convex hull of the kC candidate points s_c[] (indices into xy;
+// INT32_MAX: none) into Q (px, py, ex, ey, nv; not qb), by every thread of
+// the block.  One thread per ordered pair (a, b) of distinct candidates
+// decides whether a -> b is a counter-clockwise hull edge between strict
+// corners: every other candidate lies strictly left of it or on the open
+// segment (a, b).  A strict corner has exactly one such successor, so one
+// thread then walks the successors from the smallest (x, y), the order
+// Andrew's monotone chain gives.  Fewer than three distinct or only collinear
+// candidates give no polygon (nv = 0).
+template <int kC>
+__device__ inline void hull_of_candidates(const int32_t* s_c, const double2* __restrict__ xy, Poly& Q) {
+    static_assert(kC * kC <= kFB && kC <= kPolyMax, "one thread per candidate pair");
+    __shared__ double s_x[kC], s_y[kC];
+    __shared__ int32_t s_use[kC], s_next[kC];
+    const int t = (int)threadIdx.x;
+    if (t < kC) {
+        const int32_t c = s_c[t];
+        double2 p = make_double2(0.0, 0.0);
+        if (c != INT32_MAX) p = xy[c];
         s_x[t] = p.x;
         s_y[t] = p.y;
+        s_use[t] = c != INT32_MAX && finite_d(p.x) && finite_d(p.y);
+        s_next[t] = -1;
     }
     __syncthreads();
-    // one thread builds the hull with its arrays in LDS (no scratch), then
-    // every thread copies the polygon out
-    __shared__ Poly Q;
-    __shared__ double cx[kPolyMax], cy[kPolyMax], hx_[2 * kPolyMax + 1], hy_[2 * kPolyMax + 1];
+    // each distinct point once: the first candidate with its coordinates
+    int use = 0;
+    if (t < kC && s_use[t]) {
+        use = 1;
+        for (int u = 0; u < t; ++u) use &= !(s_use[u] && s_x[u] == s_x[t] && s_y[u] == s_y[t]);
+    }
+    __syncthreads();
+    if (t < kC) s_use[t] = use;
+    __syncthreads();
+    if (t < kC * kC) {
+        const int a = t / kC, b = t % kC;
+        if (a != b && s_use[a] && s_use[b]) {
+            const double ax = s_x[a], ay = s_y[a], bx = s_x[b], by = s_y[b];
+            const double lx = fmin(ax, bx), hx = fmax(ax, bx), ly = fmin(ay, by), hy = fmax(ay, by);
+            bool edge = true;
+            for (int p = 0; p < kC && edge; ++p) {
+                if (p == a || p == b || !s_use[p]) continue;
+                const double x = s_x[p], y = s_y[p];
+                const int o = orient(ax, ay, bx, by, x, y);
+                // collinear with a and b: on the open segment iff inside their box
+                edge = o > 0 || (o == 0 && x >= lx && x <= hx && y >= ly && y <= hy);
+            }
+            if (edge) s_next[a] = b;
+        }
+    }
+    __syncthreads();
     if (t == 0) {
+        int start = -1;
+        for (int j = 0; j < kC; ++j)
+            if (s_use[j] && (start < 0 || s_x[j] < s_x[start] || (s_x[j] == s_x[start] && s_y[j] < s_y[start])))
+                start = j;
+        int h = 0, v = start;
+        if (start >= 0 && s_next[start] >= 0) {
+            do {
+                Q.px[h] = s_x[v];
+                Q.py[h] = s_y[v];
+                ++h;
+                v = s_next[v];
+            } while (v >= 0 && v != start && h < kC);
+            if (v != start) h = 0;  // not a closed cycle: no polygon
+        }
         Q.pad = 0;
-        Q.nv = 0;
-        int nc = 0;
-        const bool ok = prm->flags == 0u;
-        for (int j = 0; j < kPolyMax; ++j) {
-            lo->cand[j] = s_c[j];
-            if (!ok || s_c[j] == INT32_MAX) continue;
-            const double px = s_x[j], py = s_y[j];
-            // insertion by (x, y), dropping repeats
-            bool dup = false;
-            for (int a = 0; a < nc; ++a) dup |= (cx[a] == px && cy[a] == py);
-            if (dup) continue;
-            int k = nc;
-            while (k > 0 && (cx[k - 1] > px || (cx[k - 1] == px && cy[k - 1] > py))) {
-                cx[k] = cx[k - 1];
-                cy[k] = cy[k - 1];
-                --k;
-            }
-            cx[k] = px;
-            cy[k] = py;
-            ++nc;
-        }
-        int h = 0;
-        if (nc >= 3) {
-            for (int i = 0; i < nc; ++i) {
-                while (h >= 2 && orient(hx_[h - 2], hy_[h - 2], hx_[h - 1], hy_[h - 1], cx[i], cy[i]) <= 0) --h;
-                hx_[h] = cx[i];
-                hy_[h] = cy[i];
-                ++h;
-            }
-            const int base = h;
-            for (int i = nc - 2; i >= 0; --i) {
-                while (h > base && orient(hx_[h - 2], hy_[h - 2], hx_[h - 1], hy_[h - 1], cx[i], cy[i]) <= 0) --h;
-                hx_[h] = cx[i];
-                hy_[h] = cy[i];
-                ++h;
-            }
-            --h;  // the last point repeats the first
-        }
         Q.nv = h >= 3 ? h : 0;
-        // every corner and point lies in the Step-1 bounding box W x H
-        const double W = prm->ext[2].x - prm->ext[0].x, H = prm->ext[3].y - prm->ext[1].y;
-        Q.qb = 9.0 * kEps * W * H;
+        Q.qb = 0.0;
+    }
+    __syncthreads();
+    // edges from consecutive corners; unused slots zero
+    double x0 = 0.0, y0 = 0.0, x1 = 0.0, y1 = 0.0;
+    if (t < Q.nv) {
+        const int t1 = t + 1 < Q.nv ? t + 1 : 0;
+        x0 = Q.px[t];
+        y0 = Q.py[t];
+        x1 = Q.px[t1];
+        y1 = Q.py[t1];
     }
     __syncthreads();
     if (t < kPolyMax) {
-        const int nv = Q.nv, j = t;
-        const int j1 = j + 1 < nv ? j + 1 : 0;
-        Q.px[j] = j < nv ? hx_[j] : 0.0;
-        Q.py[j] = j < nv ? hy_[j] : 0.0;
-        Q.ex[j] = j < nv ? hx_[j1] - hx_[j] : 0.0;
-        Q.ey[j] = j < nv ? hy_[j1] - hy_[j] : 0.0;
+        Q.px[t] = x0;
+        Q.py[t] = y0;
+        Q.ex[t] = x1 - x0;
+        Q.ey[t] = y1 - y0;
     }
     __syncthreads();
+}
+
+__global__ __launch_bounds__(kFB) void k_front(const double2* __restrict__ xy, int64_t n, MlpDev W,
+                                               LearnOut* __restrict__ lo) {
+    constexpr int NW = kFB / 64;
+    constexpr int PT = 4096 / kFB;  // sample points per thread
+    __shared__ uint32_t s_h[kMlpIn];
+    __shared__ float s_x[kMlpIn], s_h1[kMlpHidden], s_h2[kMlpHidden], s_y[kMlpOut];
+    __shared__ double s_v[4][NW];
+    __shared__ double s_box[4];
+    const int t = (int)threadIdx.x;
+    for (int i = t; i < kMlpIn; i += kFB) s_h[i] = 0;
+    const int64_t ns = sample_size(n);
+    double2 p[PT];
+    double lo_x = INFINITY, lo_y = INFINITY, hi_x = -INFINITY, hi_y = -INFINITY;
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int64_t sl = t + (int64_t)u * kFB;
+        if (sl < ns) {
+            p[u] = xy[sample_point(sl, n)];
+            lo_x = fmin(lo_x, p[u].x);
+            lo_y = fmin(lo_y, p[u].y);
+            hi_x = fmax(hi_x, p[u].x);
+            hi_y = fmax(hi_y, p[u].y);
+        }
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        lo_x = fmin(lo_x, __shfl_xor(lo_x, m));
+        lo_y = fmin(lo_y, __shfl_xor(lo_y, m));
+        hi_x = fmax(hi_x, __shfl_xor(hi_x, m));
+        hi_y = fmax(hi_y, __shfl_xor(hi_y, m));
+    }
+    const int lane = (int)__lane_id(), wave = t >> 6;
+    if (lane == 0) {
+        s_v[0][wave] = lo_x;
+        s_v[1][wave] = lo_y;
+        s_v[2][wave] = hi_x;
+        s_v[3][wave] = hi_y;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < NW; ++w) {
+            lo_x = fmin(lo_x, s_v[0][w]);
+            lo_y = fmin(lo_y, s_v[1][w]);
+            hi_x = fmax(hi_x, s_v[2][w]);
+            hi_y = fmax(hi_y, s_v[3][w]);
+        }
+        s_box[0] = lo_x;
+        s_box[1] = lo_y;
+        const double wx = hi_x - lo_x, wy = hi_y - lo_y;
+        s_box[2] = wx > 0.0 ? 32.0 / wx : 0.0;
+        s_box[3] = wy > 0.0 ? 32.0 / wy : 0.0;
+    }
+    __syncthreads();
+    {
+        const double bx = s_box[0], by = s_box[1], sx = s_box[2], sy = s_box[3];
+#pragma unroll
+        for (int u = 0; u < PT; ++u)
+            if (t + (int64_t)u * kFB < ns) atomicAdd(&s_h[cell_of(p[u].y, by, sy) * 32 + cell_of(p[u].x, bx, sx)], 1u);
+    }
+    __syncthreads();
+    for (int i = t; i < kMlpIn; i += kFB)
+        s_x[i] = ns > 0 ? (float)((double)s_h[i] * (1024.0 / (double)ns)) : 0.0f;
+    __syncthreads();
+    static_assert(kFB / 64 == 16 && kMlpHidden % 16 == 0 && kMlpOut % 16 == 0, "16 waves");
+    front_layer<kMlpIn, kMlpHidden / 16>(s_x, W.w1, W.b1, true, s_h1);
+    __syncthreads();
+    front_layer<kMlpHidden, kMlpHidden / 16>(s_h1, W.w2, W.b2, true, s_h2);
+    __syncthreads();
+    front_layer<kMlpHidden, kMlpOut / 16>(s_h2, W.w3, W.b3, false, s_y);
+    __syncthreads();
+    __shared__ double s_u[2 * kDirs];
+    if (t < kDirs) {
+        double ux = (double)s_y[2 * t], uy = (double)s_y[2 * t + 1];
+        if (!finite_d(ux) || !finite_d(uy) || (ux == 0.0 && uy == 0.0)) {
+            const double a = 6.283185307179586 * (double)t / (double)kDirs;
+            ux = cos(a);
+            uy = sin(a);
+        }
+        s_u[2 * t] = ux;
+        s_u[2 * t + 1] = uy;
+    }
+    __syncthreads();
+    // the sample point farthest along each direction (fma(x, ux, y * uy),
+    // ties: smallest index); a thread's sample indices only grow
+    __shared__ double s_bv[NW][kDirs];
+    __shared__ int32_t s_bi[NW][kDirs];
+    __shared__ int32_t s_c[kDirs];
+    __shared__ Poly Q;
+#pragma unroll
+    for (int d = 0; d < kDirs; ++d) {
+        const double ux = s_u[2 * d], uy = s_u[2 * d + 1];
+        double bv = -INFINITY;
+        int32_t bi = INT32_MAX;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int64_t sl = t + (int64_t)u * kFB;
+            if (sl < ns) {
+                const double v = fma(p[u].x, ux, p[u].y * uy);
+                const bool tk = v > bv;
+                bv = tk ? v : bv;
+                bi = tk ? (int32_t)sample_point(sl, n) : bi;
+            }
+        }
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) {
+            const double ov = __shfl_xor(bv, m);
+            const int32_t oi = __shfl_xor(bi, m);
+            dir_take(bv, bi, ov, oi);
+        }
+        if (lane == 0) {
+            s_bv[wave][d] = bv;
+            s_bi[wave][d] = bi;
+        }
+    }
+    __syncthreads();
+    static_assert(NW == kDirs, "wave j reduces direction j");
+    {
+        const int d = wave;
+        double bv = lane < NW ? s_bv[lane][d] : -INFINITY;
+        int32_t bi = lane < NW ? s_bi[lane][d] : INT32_MAX;
+#pragma unroll
+        for (int m = 8; m > 0; m >>= 1) {
+            const double ov = __shfl_xor(bv, m);
+            const int32_t oi = __shfl_xor(bi, m);
+            dir_take(bv, bi, ov, oi);
+        }
+        if (lane == 0) s_c[d] = bi;
+    }
+    __syncthreads();
+    hull_of_candidates<kDirs>(s_c, xy, Q);
+    // every global store at the end: a barrier waits for outstanding stores
     static_assert(sizeof(Poly) % 8 == 0, "double copies");
-    for (int i = t; i < (int)(sizeof(Poly) / 8); i += (int)blockDim.x)
+    for (int i = t; i < (int)(sizeof(Poly) / 8); i += kFB)
         reinterpret_cast<double*>(&lo->poly)[i] = reinterpret_cast<const double*>(&Q)[i];
+    if (t < kMlpOut) lo->y[t] = s_y[t];
+    if (t >= 64 && t < 64 + 2 * kDirs) lo->dirs[t - 64] = s_u[t - 64];
+    if (t >= 128 && t < 128 + kDirs) lo->cand[4 + t - 128] = s_c[t - 128];
 }
 
 // ---------------------------------------------------------------------------
@@ -462,14 +636,12 @@ hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* h1
     return hipGetLastError();
 }
 
-hipError_t launch_poly(const double* xy, const Params* prm, LearnOut* lo, const DirBest* dpart,
-                       int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_poly, dim3(1), dim3(64 * kDirs), 0, s, dpart, grid,
-                       reinterpret_cast<const double2*>(xy), prm, lo);
+hipError_t launch_front(const double* xy, int64_t n, const MlpDev& W, LearnOut* lo, hipStream_t s) {
+    hipLaunchKernelGGL(k_front, dim3(1), dim3(kFB), 0, s, reinterpret_cast<const double2*>(xy), n, W, lo);
     return hipGetLastError();
 }
 
-size_t dir_part_bytes(int grid) { return (size_t)grid * kDirs * sizeof(DirBest); }
+
 
 hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int tA, const float* B, int ldb,
                        int tB, const float* bias, int relu, const float* mask, float* C, int ldc,

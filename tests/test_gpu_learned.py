@@ -130,6 +130,12 @@ def _cases():
         "collinear": np.stack([t, 2 * t - 5], axis=1)[np.random.default_rng(1).permutation(1500)],
         "equal": np.full((500, 2), 0.375),
         "three": np.array([[0.0, 0.0], [2.0, 2.0], [1.0, 1.0]]),
+        # repeated and collinear candidates: corners, edge midpoints, centre
+        "square_ring": np.concatenate([
+            np.array([[0, 0], [1, 0], [2, 0], [2, 1], [2, 2], [1, 2], [0, 2], [0, 1]] * 40, dtype=np.float64),
+            1.0 + 0.5 * synth.disk(3000, (416, 1))]),
+        # a ragged last block of the direction sample (n = 5 * 4096 + 100)
+        "disk_20580": synth.disk(20_580, (417, 1)),
     }
 
 
@@ -148,8 +154,52 @@ def test_learned_first_round_equals_oracle(torch_dev, hx, name, wseed):
     info = c.learned_info()
     ref = oracle.learned_round1(pts, info["dirs"])
     assert info["cand"].tolist() == ref["cand"].tolist()
+    h = len(oracle.hull(pts[ref["cand"][4:]]))        # the polygon's strict corners
+    assert info["nv"] == (h if h >= 3 else 0)
     assert st.n_round1 == ref["m1"]
     assert st.n_round1 <= oracle.model(pts)["m1"]
+    c.close()
+
+
+@pytest.mark.parametrize("name", ["mixture_100k", "disk_20580", "three", "equal"])
+def test_hull_proposal_equals_separate_kernels(torch_dev, hx, name):
+    """The hull path computes the histogram and the network in one fused
+    workgroup; its raw outputs equal, bit for bit, those of the separate
+    histogram and inference entry points (each pinned above)."""
+    pts = CASES[name]
+    say(f"fused proposal {name}")
+    p = _random_params(23)
+    c = hx.Hull2D(learned=True, weights=p)
+    d = _dev(torch_dev, pts)
+    c.compute(d)
+    y_hull = c.learned_info()["y"]
+    x = c.histogram(d)
+    assert np.array_equal(x.cpu().numpy(), mlp.histogram(pts))
+    y_sep = c.mlp_infer(x.reshape(1, -1)).cpu().numpy()[0]
+    assert np.array_equal(y_hull.view(np.uint32), y_sep.view(np.uint32))
+    c.close()
+
+
+def test_learned_collinear_and_repeated_candidates(torch_dev, hx):
+    """Zero weights give zero outputs, hence the evenly spaced fallback
+    directions, the first of them exactly (1, 0).  Its farthest point is the
+    earliest of the right edge, the edge's midpoint (index 0), which lies
+    between the candidates (2, 0) and (2, 2) of the neighbouring directions:
+    a candidate that is no corner, next to repeated candidates.  The polygon
+    is the square."""
+    ring = [[2, 1], [0, 0], [2, 0], [2, 2], [0, 2], [1, 0], [1, 2], [0, 1]]
+    pts = np.concatenate([np.array(ring * 3, dtype=np.float64),
+                          1.0 + 0.9 * synth.disk(5000, (418, 1))])
+    c = hx.Hull2D(learned=True, weights=np.zeros(mlp.N_PARAMS, dtype=np.float32))
+    got = c.compute(_dev(torch_dev, pts))
+    assert got.tolist() == oracle.hull(pts).tolist()
+    info = c.learned_info()
+    assert info["dirs"][0].tolist() == [1.0, 0.0]
+    ref = oracle.learned_round1(pts, info["dirs"])
+    assert info["cand"].tolist() == ref["cand"].tolist()
+    assert info["cand"][4] == 0
+    assert info["nv"] == 4
+    assert c.last_stats.n_round1 == ref["m1"]
     c.close()
 
 

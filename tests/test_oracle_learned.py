@@ -41,10 +41,16 @@ def test_learned_keeps_hull_and_is_inside_quad(name, seed):
         assert r["m1"] <= q["m1"]
 
 
+def _inside_q(poly, p):
+    return len(poly) >= 3 and all(orient_q(poly[e], poly[(e + 1) % len(poly)], p) > 0
+                                  for e in range(len(poly)))
+
+
 def test_learned_matches_brute_force_on_integer_points():
     """Integer points and directions: every product is exact, so the argmax,
-    the hull of the candidates and the strict-inside test can be evaluated in
-    rational arithmetic independently."""
+    the hull of the candidates and the strict-inside tests can be evaluated in
+    rational arithmetic independently.  Below 4096 points the sample is every
+    point."""
     rng = np.random.default_rng(7)
     for trial in range(40):
         n = int(rng.integers(1, 60))
@@ -59,16 +65,73 @@ def test_learned_matches_brute_force_on_integer_points():
                min(idx, key=lambda i: (P[i][1], P[i][0], i)),
                min(idx, key=lambda i: (-P[i][0], P[i][1], i)),
                min(idx, key=lambda i: (-P[i][1], -P[i][0], i))]
-        cand = ext + [min(idx, key=lambda i: (-(P[i][0] * int(ux) + P[i][1] * int(uy)), i))
-                      for ux, uy in dirs]
-        assert r["cand"].tolist() == cand
-        cpts = np.array([P[i] for i in cand], dtype=np.float64)
-        hv = brute_hull(cpts)                          # exact strict corners, CCW
+        dc = [min(idx, key=lambda i: (-(P[i][0] * int(ux) + P[i][1] * int(uy)), i)) for ux, uy in dirs]
+        assert r["cand"].tolist() == ext + dc
+        # the quadrilateral: distinct extremes in their counter-clockwise order
+        quad = []
+        for i in ext:
+            if all(P[j] != P[i] for j in quad):
+                quad.append(i)
+        qpts = [pts[i] for i in quad]
+        cpts = np.array([P[i] for i in dc], dtype=np.float64).reshape(-1, 2)
+        ppts = [cpts[v] for v in brute_hull(cpts)] if len(dc) else []   # exact strict corners, CCW
         for i in range(n):
-            inside = len(hv) >= 3 and all(
-                orient_q(cpts[hv[e]], cpts[hv[(e + 1) % len(hv)]], pts[i]) > 0
-                for e in range(len(hv)))
-            assert r["keep"][i] == (not inside), (trial, i)
+            gone = _inside_q(qpts, pts[i]) or _inside_q(ppts, pts[i])
+            assert r["keep"][i] == (not gone), (trial, i)
+
+
+def test_learned_directions_use_the_sample_only():
+    """The direction candidates come from the network's sample (above 4096
+    points: 16 blocks of 256, block b at floor(b n / 16)): a point far out
+    along every direction placed outside the sample is never a candidate,
+    while the same point inside it is the candidate of every direction it
+    wins.  Checked against an independent integer argmax over the sample."""
+    rng = np.random.default_rng(11)
+    n = 3 * 4096 + 777                                   # blocks start at b * 816.56...
+    pts = rng.integers(-1000, 1001, size=(n, 2)).astype(np.float64)
+    dirs = rng.integers(-5, 6, size=(9, 2)).astype(np.float64)
+    dirs[0] = (1.0, 1.0)
+    sample = [(b * n) // 16 + j for b in range(16) for j in range(256)]
+    assert sample == mlp.sample_index(n).tolist()        # the histogram's sample
+    assert {0, 255, 816, 1071, 12248, 12503} <= set(sample)
+    assert not {256, 815, 1072, 4500, 12247, 12504, n - 1} & set(sample)
+
+    def expect(p):
+        P = [(int(x), int(y)) for x, y in p]
+        return [min(sample, key=lambda i: (-(P[i][0] * int(ux) + P[i][1] * int(uy)), i))
+                for ux, uy in dirs]
+
+    for far in (256, 815, 4500, 12504, n - 1):           # outside the sample
+        p = pts.copy()
+        p[far] = (10_000.0, 10_000.0)
+        r = oracle.learned_round1(p, dirs)
+        assert r["cand"][4:].tolist() == expect(p)
+        assert far not in r["cand"][4:].tolist()
+        assert r["keep"][far]                            # a Step-1 extreme: survives
+    for far in (0, 255, 816 + 17, 12503):                # inside the sample
+        p = pts.copy()
+        p[far] = (10_000.0, 10_000.0)
+        r = oracle.learned_round1(p, dirs)
+        assert r["cand"][4:].tolist() == expect(p)
+        assert r["cand"][4] == far
+
+
+def test_learned_union_with_quadrilateral():
+    """A point inside the quadrilateral but outside the polygon is discarded,
+    and so is one inside the polygon but outside the quadrilateral: the
+    discard region is the union.  Square corners make the quadrilateral; one
+    direction candidate triangle (0, 0), (10, 0), (0, 10) and the square
+    (0..10)^2 overlap but neither holds the other."""
+    ring = [(0.0, 5.0), (5.0, 0.0), (10.0, 5.0), (5.0, 10.0)]   # the Step-1 extremes
+    tri = [(0.0, 0.0), (9.0, 0.0), (0.0, 9.0)]                   # sample candidates
+    probe = [(5.0, 5.0), (1.0, 1.0), (8.0, 8.0), (9.9, 0.5)]
+    pts = np.array(ring + tri + probe)
+    dirs = [(-1.0, -1.0), (1.0, -10.0), (-10.0, 1.0)]
+    r = oracle.learned_round1(pts, dirs)
+    assert r["cand"][4:].tolist() == [4, 5, 6]
+    # (5, 5) in both, (1, 1) only in the triangle, (8, 8) in neither, (9.9, 0.5) outside both
+    assert r["keep"][7:].tolist() == [False, False, True, True]
+    assert r["keep"][:7].all()
 
 
 def test_learned_regular_polygon_closed_form():
