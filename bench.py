@@ -38,7 +38,7 @@ TRAFFIC = {
         "profile": "profiles/hull_square_disk_20M_hbm_counters.md",
         "sources": {
             "paper_1508_05931_amd/csrc/kernels_filter.hip":
-                "6df56172e77c186a34e022d60742acc26e51d70b6062c05a39290b8238e6e83c",
+                "aa54d9ca15ee9676c762b727bc8753753c54a0f74e25aa5c1ef4e64d3bbe4a1c",
             "paper_1508_05931_amd/csrc/steps.hpp":
                 "b8a17d37316efece011b1de67cb39106b34fe7134dc7e05fd035c1f6ed96ebb0",
             "paper_1508_05931_amd/csrc/exact.hpp":
@@ -46,7 +46,7 @@ TRAFFIC = {
             "paper_1508_05931_amd/csrc/common.hpp":
                 "044be352493ceaba3339859e0a74a6c108f123de1ccffeb5df255bc633cfd97f",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "4c0ee9f8894cb62576e8ddcdf86572518bb532c71bcb0d3fd9962412be460641",
+                "007390d8142df7fbf660c4ed772c6b8e17de32a6997ba6d5eeb84655e624dda4",
         },
     },
 }

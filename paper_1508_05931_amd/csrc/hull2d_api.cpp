@@ -97,10 +97,6 @@ struct hull2d_ctx {
     // the batched form's device work captured in a graph, and what it was
     // captured for (replayed while all of it is unchanged)
     hipStream_t cap_stream = nullptr;
-    // the learned filter's proposal runs on a side stream beside Step 1
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    bool side_off = false;  // creation failed once: one stream
     hipGraphExec_t bgraph = nullptr;
     bool bgraph_off = false;  // capture failed once: plain stream work
     int32_t bg_S = -1;
@@ -374,25 +370,6 @@ constexpr int64_t kOffB3 = kOffW3 + (int64_t)kMlpOut * kMlpHidden;
 static_assert(kOffB3 + kMlpOut == kMlpParams, "parameter layout");
 static_assert(kMlpParams == HULL2D_MLP_PARAMS, "header constant");
 
-// The side stream and its fork / join events, made on first use.
-bool ensure_side(hull2d_ctx* c) {
-    if (c->side) return true;
-    if (c->side_off) return false;
-    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();
-        if (c->side) (void)hipStreamDestroy(c->side);
-        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-        c->side = nullptr;
-        c->ev_fork = nullptr;
-        c->ev_join = nullptr;
-        c->side_off = true;
-        return false;
-    }
-    return true;
-}
-
 hull2d_status ensure_learned(hull2d_ctx* c) {
     if (c->lmem) return HULL2D_OK;
     const size_t P = (size_t)kMlpParams;
@@ -623,9 +600,6 @@ void hull2d_destroy(hull2d_ctx* c) {
     if (c->ctr) (void)hipFree(c->ctr);
     if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->side) (void)hipStreamDestroy(c->side);
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->h_ds) (void)hipHostFree(c->h_ds);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
@@ -680,24 +654,16 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
 
     // Step 1
-    // learned filter: sample histogram, network, the sample's farthest point
-    // along each direction and their hull, the discard polygon (one
-    // workgroup, independent of Step 1: on a side stream beside it, except
-    // when every stage is timed)
-    const bool fork = learned && !prof_all && ensure_side(c);
-    if (learned && !fork) {
+    // learned filter first: sample histogram, network, the sample's farthest
+    // point along each direction and their hull, the discard polygon (one
+    // workgroup).  It does not depend on Step 1, but running it on a second
+    // stream beside Step 1 measured no faster: the two share the device.
+    if (learned) {
         HX_TRY(launch_front(d_xy, n, mlp_dev(c), c->learn, s));
         mark(HULL2D_STAGE_LEARNED);
     }
-    if (fork) HX_TRY(hipEventRecord(c->ev_fork, s));
     const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
     HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, s));
-    if (fork) {
-        HX_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-        HX_TRY(launch_front(d_xy, n, mlp_dev(c), c->learn, c->side));
-        HX_TRY(hipEventRecord(c->ev_join, c->side));
-        HX_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
-    }
     mark(HULL2D_STAGE_EXTREMES);
     // Steps 2-3
     const int segs = std::min(

@@ -222,13 +222,18 @@ __global__ void k_mlp_dirs(const float* __restrict__ y, LearnOut* __restrict__ l
 // outputs equal those of the separate kernels bit for bit.
 constexpr int kFB = 1024;
 
-// out[o] = act(W[o] . in + b[o]) for the kU units o = wave + 16 u of this
-// wave (in, out in LDS); the units' loads are in flight together, and each
-// unit's sum keeps the order of k_mlp_layer.
+// out[o] = act(W[o] . in + b[o]) for every unit o (in, out in LDS): wave w
+// takes the kU units o = w + 16 u, all their loads in flight together, each
+// lane summing every 64th input as k_mlp_layer does; the 64 lane sums of a
+// unit are then added by a tree in LDS (s[l] += s[l + m], m = 32 .. 1) that
+// associates them as k_mlp_layer's butterfly does for lane 0, so each output
+// equals k_mlp_layer's bit for bit.  s_r: [kMlpHidden][64] floats.
 template <int kIn, int kU>
 __device__ inline void front_layer(const float* in, const uint16_t* __restrict__ W,
-                                   const float* __restrict__ bias, bool hidden, float* out) {
-    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+                                   const float* __restrict__ bias, bool hidden, float* out,
+                                   float (*s_r)[64]) {
+    constexpr int kOut = 16 * kU;
+    const int t = (int)threadIdx.x, lane = (int)__lane_id(), wave = t >> 6;
     float acc[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) acc[u] = 0.f;
@@ -239,23 +244,23 @@ __device__ inline void front_layer(const float* in, const uint16_t* __restrict__
         for (int u = 0; u < kU; ++u) acc[u] = fmaf(x, from_bf16(W[(size_t)(wave + 16 * u) * kIn + i]), acc[u]);
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-#pragma unroll
-        for (int m = 32; m > 0; m >>= 1) acc[u] += __shfl_xor(acc[u], m);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int o = wave + 16 * u;
-            const float a = acc[u] + bias[o];
-            out[o] = hidden ? from_bf16(to_bf16(fmaxf(a, 0.f))) : a;
+    for (int u = 0; u < kU; ++u) s_r[wave + 16 * u][lane] = acc[u];
+    __syncthreads();
+    for (int m = 32; m > 0; m >>= 1) {
+        for (int e = t; e < kOut * m; e += kFB) {
+            const int o = e / m, l = e - o * m;
+            s_r[o][l] = s_r[o][l] + s_r[o][l + m];
         }
+        __syncthreads();
+    }
+    for (int o = t; o < kOut; o += kFB) {
+        const float a = s_r[o][0] + bias[o];
+        out[o] = hidden ? from_bf16(to_bf16(fmaxf(a, 0.f))) : a;
     }
 }
 
-// The exact convex hull of the kC candidate points s_c[] (indices into xy;
-// INT32_MAX: none) into Q (px, py, ex, ey, nv; not qb), by every thread of
-// the block.  One thread per ordered pair (a, b) of distinct candidates
+// The exact convex hull of the kC candidate points pts[s_c[j]] (INT32_MAX:
+// none) into Q (px, py, ex, ey, nv; not qb), by every thread of the block.  One thread per ordered pair (a, b) of distinct candidates
 // decides whether a -> b is a counter-clockwise hull edge between strict
 // corners: every other candidate lies strictly left of it or on the open
 // segment (a, b).  A strict corner has exactly one such successor, so one
@@ -263,7 +268,7 @@ __device__ inline void front_layer(const float* in, const uint16_t* __restrict__
 // Andrew's monotone chain gives.  Fewer than three distinct or only collinear
 // candidates give no polygon (nv = 0).
 template <int kC>
-__device__ inline void hull_of_candidates(const int32_t* s_c, const double2* __restrict__ xy, Poly& Q) {
+__device__ inline void hull_of_candidates(const int32_t* s_c, const double2* pts, Poly& Q) {
     static_assert(kC * kC <= kFB && kC <= kPolyMax, "one thread per candidate pair");
     __shared__ double s_x[kC], s_y[kC];
     __shared__ int32_t s_use[kC], s_next[kC];
@@ -271,7 +276,7 @@ __device__ inline void hull_of_candidates(const int32_t* s_c, const double2* __r
     if (t < kC) {
         const int32_t c = s_c[t];
         double2 p = make_double2(0.0, 0.0);
-        if (c != INT32_MAX) p = xy[c];
+        if (c != INT32_MAX) p = pts[c];
         s_x[t] = p.x;
         s_y[t] = p.y;
         s_use[t] = c != INT32_MAX && finite_d(p.x) && finite_d(p.y);
@@ -349,6 +354,8 @@ __global__ __launch_bounds__(kFB) void k_front(const double2* __restrict__ xy, i
     constexpr int PT = 4096 / kFB;  // sample points per thread
     __shared__ uint32_t s_h[kMlpIn];
     __shared__ float s_x[kMlpIn], s_h1[kMlpHidden], s_h2[kMlpHidden], s_y[kMlpOut];
+    __shared__ float s_r[kMlpHidden][64];  // a layer's lane sums
+    __shared__ double2 s_pt[4096];         // the sample, by sample position
     __shared__ double s_v[4][NW];
     __shared__ double s_box[4];
     const int t = (int)threadIdx.x;
@@ -361,6 +368,7 @@ __global__ __launch_bounds__(kFB) void k_front(const double2* __restrict__ xy, i
         const int64_t sl = t + (int64_t)u * kFB;
         if (sl < ns) {
             p[u] = xy[sample_point(sl, n)];
+            s_pt[sl] = p[u];
             lo_x = fmin(lo_x, p[u].x);
             lo_y = fmin(lo_y, p[u].y);
             hi_x = fmax(hi_x, p[u].x);
@@ -407,11 +415,11 @@ __global__ __launch_bounds__(kFB) void k_front(const double2* __restrict__ xy, i
         s_x[i] = ns > 0 ? (float)((double)s_h[i] * (1024.0 / (double)ns)) : 0.0f;
     __syncthreads();
     static_assert(kFB / 64 == 16 && kMlpHidden % 16 == 0 && kMlpOut % 16 == 0, "16 waves");
-    front_layer<kMlpIn, kMlpHidden / 16>(s_x, W.w1, W.b1, true, s_h1);
+    front_layer<kMlpIn, kMlpHidden / 16>(s_x, W.w1, W.b1, true, s_h1, s_r);
     __syncthreads();
-    front_layer<kMlpHidden, kMlpHidden / 16>(s_h1, W.w2, W.b2, true, s_h2);
+    front_layer<kMlpHidden, kMlpHidden / 16>(s_h1, W.w2, W.b2, true, s_h2, s_r);
     __syncthreads();
-    front_layer<kMlpHidden, kMlpOut / 16>(s_h2, W.w3, W.b3, false, s_y);
+    front_layer<kMlpHidden, kMlpOut / 16>(s_h2, W.w3, W.b3, false, s_y, s_r);
     __syncthreads();
     __shared__ double s_u[2 * kDirs];
     if (t < kDirs) {
@@ -426,60 +434,45 @@ __global__ __launch_bounds__(kFB) void k_front(const double2* __restrict__ xy, i
     }
     __syncthreads();
     // the sample point farthest along each direction (fma(x, ux, y * uy),
-    // ties: smallest index); a thread's sample indices only grow
-    __shared__ double s_bv[NW][kDirs];
-    __shared__ int32_t s_bi[NW][kDirs];
+    // ties: smallest index, that is smallest sample position): wave d takes
+    // direction d, lane l the positions l, l + 64, ... (consecutive lanes,
+    // consecutive LDS words)
     __shared__ int32_t s_c[kDirs];
     __shared__ Poly Q;
-#pragma unroll
-    for (int d = 0; d < kDirs; ++d) {
+    static_assert(NW == kDirs, "wave d: direction d");
+    {
+        const int d = wave;
         const double ux = s_u[2 * d], uy = s_u[2 * d + 1];
         double bv = -INFINITY;
-        int32_t bi = INT32_MAX;
-#pragma unroll
-        for (int u = 0; u < PT; ++u) {
-            const int64_t sl = t + (int64_t)u * kFB;
-            if (sl < ns) {
-                const double v = fma(p[u].x, ux, p[u].y * uy);
-                const bool tk = v > bv;
-                bv = tk ? v : bv;
-                bi = tk ? (int32_t)sample_point(sl, n) : bi;
-            }
+        int32_t bs = INT32_MAX;
+#pragma unroll 8
+        for (int sl = lane; sl < (int)ns; sl += 64) {
+            const double2 q = s_pt[sl];
+            const double v = fma(q.x, ux, q.y * uy);
+            const bool tk = v > bv;
+            bv = tk ? v : bv;
+            bs = tk ? sl : bs;
         }
 #pragma unroll
         for (int m = 32; m > 0; m >>= 1) {
             const double ov = __shfl_xor(bv, m);
-            const int32_t oi = __shfl_xor(bi, m);
-            dir_take(bv, bi, ov, oi);
+            const int32_t os = __shfl_xor(bs, m);
+            dir_take(bv, bs, ov, os);
         }
-        if (lane == 0) {
-            s_bv[wave][d] = bv;
-            s_bi[wave][d] = bi;
-        }
+        if (lane == 0) s_c[d] = bs;
     }
     __syncthreads();
-    static_assert(NW == kDirs, "wave j reduces direction j");
-    {
-        const int d = wave;
-        double bv = lane < NW ? s_bv[lane][d] : -INFINITY;
-        int32_t bi = lane < NW ? s_bi[lane][d] : INT32_MAX;
-#pragma unroll
-        for (int m = 8; m > 0; m >>= 1) {
-            const double ov = __shfl_xor(bv, m);
-            const int32_t oi = __shfl_xor(bi, m);
-            dir_take(bv, bi, ov, oi);
-        }
-        if (lane == 0) s_c[d] = bi;
-    }
-    __syncthreads();
-    hull_of_candidates<kDirs>(s_c, xy, Q);
+    hull_of_candidates<kDirs>(s_c, s_pt, Q);
     // every global store at the end: a barrier waits for outstanding stores
     static_assert(sizeof(Poly) % 8 == 0, "double copies");
     for (int i = t; i < (int)(sizeof(Poly) / 8); i += kFB)
         reinterpret_cast<double*>(&lo->poly)[i] = reinterpret_cast<const double*>(&Q)[i];
     if (t < kMlpOut) lo->y[t] = s_y[t];
     if (t >= 64 && t < 64 + 2 * kDirs) lo->dirs[t - 64] = s_u[t - 64];
-    if (t >= 128 && t < 128 + kDirs) lo->cand[4 + t - 128] = s_c[t - 128];
+    if (t >= 128 && t < 128 + kDirs) {
+        const int32_t sl = s_c[t - 128];
+        lo->cand[4 + t - 128] = sl == INT32_MAX ? INT32_MAX : (int32_t)sample_point(sl, n);
+    }
 }
 
 // ---------------------------------------------------------------------------
