@@ -114,7 +114,7 @@ struct hull2d_ctx {
     uint16_t *m_w1 = nullptr, *m_w2 = nullptr, *m_w3 = nullptr;
     LearnOut* learn = nullptr;
     uint32_t* l_hist = nullptr;
-    float *l_x = nullptr, *l_y = nullptr, *l_loss = nullptr, *l_h1 = nullptr, *l_h2 = nullptr;
+    float* l_loss = nullptr;
     double* l_part = nullptr;
     int64_t adam_t = 0;
     int32_t tcap_b = 0;
@@ -373,13 +373,12 @@ static_assert(kMlpParams == HULL2D_MLP_PARAMS, "header constant");
 hull2d_status ensure_learned(hull2d_ctx* c) {
     if (c->lmem) return HULL2D_OK;
     const size_t P = (size_t)kMlpParams;
-    const size_t sizes[12] = {P * 4, P * 4, P * 4, P * 4,
+    const size_t sizes[11] = {P * 4, P * 4, P * 4, P * 4,
                               (size_t)kMlpIn * kMlpHidden * 2, (size_t)kMlpHidden * kMlpHidden * 2,
                               (size_t)kMlpHidden * kMlpOut * 2, sizeof(LearnOut), (size_t)kMlpIn * 4,
-                              (size_t)kMlpIn * 4 + 2 * (size_t)kMlpHidden * 4, (size_t)kMlpOut * 4 + 16,
-                              (size_t)4 * 8 * c->cu_count};
-    size_t off[12], o = 0;
-    for (int i = 0; i < 12; ++i) {
+                              16, (size_t)4 * 8 * c->cu_count};
+    size_t off[11], o = 0;
+    for (int i = 0; i < 11; ++i) {
         off[i] = o;
         o = align_up(o + sizes[i], 256);
     }
@@ -398,12 +397,8 @@ hull2d_status ensure_learned(hull2d_ctx* c) {
     c->m_w3 = (uint16_t*)(b + off[6]);
     c->learn = (LearnOut*)(b + off[7]);
     c->l_hist = (uint32_t*)(b + off[8]);
-    c->l_x = (float*)(b + off[9]);
-    c->l_h1 = c->l_x + kMlpIn;
-    c->l_h2 = c->l_h1 + kMlpHidden;
-    c->l_y = (float*)(b + off[10]);
-    c->l_loss = c->l_y + kMlpOut;
-    c->l_part = (double*)(b + off[11]);
+    c->l_loss = (float*)(b + off[9]);
+    c->l_part = (double*)(b + off[10]);
     return HULL2D_OK;
 }
 
@@ -1112,7 +1107,7 @@ hull2d_status hull2d_mlp_infer(hull2d_ctx* c, const float* d_x, int32_t rows, fl
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
     hull2d_status st = ensure_train(c, rows);
     if (st != HULL2D_OK) return st;
-    HX_TRY(launch_mlp_infer(d_x, rows, mlp_dev(c), c->t_h1, c->t_h2, d_y, nullptr, c->stream));
+    HX_TRY(launch_mlp_infer(d_x, rows, mlp_dev(c), c->t_h1, c->t_h2, d_y, c->stream));
     HX_TRY(hipStreamSynchronize(c->stream));
     return HULL2D_OK;
 }

@@ -166,10 +166,9 @@ int learned_grid(int64_t n, int cu_count);
 hipError_t launch_histogram_sample(const double* xy, int64_t n, double* part, int grid, uint32_t* hist,
                                    hipStream_t s);
 hipError_t launch_hist_to_x(const uint32_t* hist, int64_t n, float* x, hipStream_t s);
-// rows inputs x [rows][1024] -> y [rows][32]; h1, h2 [rows][256] scratch;
-// lo (rows = 1 only, may be NULL) receives the directions.
+// rows inputs x [rows][1024] -> y [rows][32]; h1, h2 [rows][256] scratch.
 hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* h1, float* h2, float* y,
-                            LearnOut* lo, hipStream_t s);
+                            hipStream_t s);
 // The whole proposal in one workgroup: the sample histogram, the network and
 // its 16 directions into lo->y and lo->dirs (the same arithmetic as
 // launch_histogram_sample, launch_hist_to_x and launch_mlp_infer), then the

@@ -1,24 +1,18 @@
 // kernels_learned.hip - the learned-filter variant of Steps 1-2 (not in the
 // paper) and the training kernels of its network.
 //
-// Proposal (per hull, before the first round):
-//   k_sample_bbox, k_sample_hist  32 x 32 occupancy histogram of a sample
-//                                 (16 evenly spaced blocks of 256 points)
-//                                 over the sample's bounding box
-//   k_mlp_layer ×3, k_mlp_dirs    1024 -> 256 -> 256 -> 32 network, bfloat16
-//                                 weights and layer inputs, float32 sums, one
-//                                 wave per output unit: 16 directions
-//   k_front                       all of the above in one workgroup, the
-//                                 form the hull path launches
-//   (Step 1, kernels_filter.hip)  the point farthest along each direction
-//                                 (fma(x, ux, y * uy), ties: smallest index)
-//                                 over the direction sample (every 16th
-//                                 block of 256 points) in the Step-1 pass,
-//                                 then the exact convex hull of those 16
-//                                 points and the four Step-1 extremes: the
-//                                 discard polygon, which contains the
-//                                 quadrilateral, so the first round stays
-//                                 conservative whatever the network says
+// Proposal (per hull, before the first round), k_front, one workgroup:
+//   32 x 32 occupancy histogram of a sample (every point up to 4096, else 16
+//   evenly spaced blocks of 256 points) over the sample's bounding box; the
+//   1024 -> 256 -> 256 -> 32 network (bfloat16 weights and layer inputs,
+//   float32 sums): 16 directions; the sample point farthest along each
+//   (fma(x, ux, y * uy), ties: smallest index); their exact convex hull, the
+//   discard polygon.  The first round discards strictly inside it or
+//   strictly inside the quadrilateral; both have input points as corners,
+//   so it stays conservative whatever the network says.
+// k_sample_bbox, k_sample_hist, k_hist_to_x and k_mlp_layer compute the
+// histogram and the network as separate kernels for the standalone entry
+// points (k_front's outputs equal theirs bit for bit).
 // Training (float32, off the timed path): tiled GEMM with bias / ReLU
 // epilogues, mean-squared-error gradient, column sums, Adam.
 #include "exact.hpp"
@@ -197,28 +191,10 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_layer(const float* __res
     }
 }
 
-// The 16 directions of one row of outputs (non-finite or zero: the evenly
-// spaced direction of that slot).
-__global__ void k_mlp_dirs(const float* __restrict__ y, LearnOut* __restrict__ lo) {
-    const int t = (int)threadIdx.x;
-    if (t >= kDirs) return;
-    double ux = (double)y[2 * t], uy = (double)y[2 * t + 1];
-    if (!finite_d(ux) || !finite_d(uy) || (ux == 0.0 && uy == 0.0)) {
-        const double a = 6.283185307179586 * (double)t / (double)kDirs;
-        ux = cos(a);
-        uy = sin(a);
-    }
-    lo->y[2 * t] = y[2 * t];
-    lo->y[2 * t + 1] = y[2 * t + 1];
-    lo->dirs[2 * t] = ux;
-    lo->dirs[2 * t + 1] = uy;
-}
-
-
 // The whole proposal in one workgroup of kFB threads: the sample's bounding
 // box and histogram (as k_sample_bbox / k_sample_hist), the network inputs
 // (as k_hist_to_x), the three layers (each output unit summed by one wave in
-// the order of k_mlp_layer) and the directions (as k_mlp_dirs), so the
+// the order of k_mlp_layer) and the directions, so the
 // outputs equal those of the separate kernels bit for bit.
 constexpr int kFB = 1024;
 
@@ -612,7 +588,7 @@ hipError_t launch_hist_to_x(const uint32_t* hist, int64_t n, float* x, hipStream
 }
 
 hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* h1, float* h2, float* y,
-                            LearnOut* lo, hipStream_t s) {
+                            hipStream_t s) {
     hipLaunchKernelGGL(k_mlp_layer, dim3(kMlpHidden / kMlpWaves, rows), dim3(64 * kMlpWaves), 0, s, x,
                        kMlpIn, W.w1, W.b1, kMlpHidden, 1, h1);
     hipError_t e = hipGetLastError();
@@ -623,9 +599,6 @@ hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* h1
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mlp_layer, dim3(kMlpOut / kMlpWaves, rows), dim3(64 * kMlpWaves), 0, s, h2,
                        kMlpHidden, W.w3, W.b3, kMlpOut, 0, y);
-    e = hipGetLastError();
-    if (e != hipSuccess || !lo) return e;
-    hipLaunchKernelGGL(k_mlp_dirs, dim3(1), dim3(64), 0, s, y, lo);
     return hipGetLastError();
 }
 
