@@ -46,7 +46,7 @@ TRAFFIC = {
             "paper_1508_05931_amd/csrc/common.hpp":
                 "044be352493ceaba3339859e0a74a6c108f123de1ccffeb5df255bc633cfd97f",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "007390d8142df7fbf660c4ed772c6b8e17de32a6997ba6d5eeb84655e624dda4",
+                "6357e8f06f579beb94a75ce1e27b8a1fbb4de5e2939fa9fd17ddbe45542dd962",
         },
     },
 }
