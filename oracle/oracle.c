@@ -403,42 +403,30 @@ int oracle_learned_round1(const double* xy, int64_t n, const double* dirs, int32
     }
     if (cand) memcpy(cand, c, (size_t)(4 + k) * sizeof(int32_t));
 
-    /* the polygon: the exact convex hull of the direction candidates */
-    double pxy[2 * 64];
-    for (int32_t j = 0; j < k; ++j) {
-        pxy[2 * j] = xy[2 * (int64_t)c[4 + j]];
-        pxy[2 * j + 1] = xy[2 * (int64_t)c[4 + j] + 1];
+    /* the polygon: the exact convex hull of all the candidates, the four
+     * extremes included, so that it contains the quadrilateral */
+    const int32_t nc = 4 + k;
+    double cxy[2 * 68];
+    for (int32_t j = 0; j < nc; ++j) {
+        cxy[2 * j] = xy[2 * (int64_t)c[j]];
+        cxy[2 * j + 1] = xy[2 * (int64_t)c[j] + 1];
     }
-    int32_t hv[64];
+    int32_t hv[68];
     int64_t h = 0;
-    if (k > 0) {
-        st = oracle_hull(pxy, k, hv, 64, &h);
-        if (st != ORACLE_OK) return st;
-    }
+    st = oracle_hull(cxy, nc, hv, 68, &h);
+    if (st != ORACLE_OK) return st;
 
-    /* the quadrilateral of Step 2: distinct corners, counter-clockwise */
-    int32_t corner[4];
-    int nc = 0;
-    for (int j = 0; j < 4; ++j) {
-        int dup = 0;
-        for (int u = 0; u < nc; ++u) dup |= same_point(xy, corner[u], c[j]);
-        if (!dup) corner[nc++] = c[j];
-    }
-
-    /* discarded: strictly inside the quadrilateral or strictly inside the
-     * polygon (strictly left of every edge; fewer than three corners: never) */
+    /* discarded: strictly inside it (strictly left of every edge; fewer than
+     * three corners: never) */
     int64_t cnt = 0;
     for (int64_t i = 0; i < n; ++i) {
-        int in_q = nc >= 3;
-        for (int j = 0; j < nc && in_q; ++j)
-            in_q = orient_idx(xy, corner[j], corner[(j + 1) % nc], (int32_t)i) > 0;
-        int in_p = h >= 3;
-        for (int64_t e = 0; e < h && in_p; ++e) {
+        int inside = h >= 3;
+        for (int64_t e = 0; e < h && inside; ++e) {
             const int32_t a = hv[e], b = hv[(e + 1) % h];
-            in_p = oracle_orient(pxy[2 * a], pxy[2 * a + 1], pxy[2 * b], pxy[2 * b + 1],
-                                 xy[2 * i], xy[2 * i + 1]) > 0;
+            inside = oracle_orient(cxy[2 * a], cxy[2 * a + 1], cxy[2 * b], cxy[2 * b + 1],
+                                   xy[2 * i], xy[2 * i + 1]) > 0;
         }
-        keep[i] = (in_q || in_p) ? 0 : 1;
+        keep[i] = inside ? 0 : 1;
         cnt += keep[i];
     }
     *m1 = cnt;

@@ -76,17 +76,18 @@ int oracle_round2(const double* q, int64_t N, int64_t l, int64_t chunk, uint8_t*
  *            (Section 3.4); c > 0 = subsets of c points. */
 int oracle_model(const double* xy, int64_t n, int64_t chunk, oracle_model_result* r);
 
-/* First round with a learned discard polygon beside the quadrilateral (the
- * learned-filter variant; not in the paper).  dirs is [k][2]: for each
+/* First round with a learned discard polygon instead of the quadrilateral
+ * (the learned-filter variant; not in the paper).  dirs is [k][2]: for each
  * direction u the candidate is the point of the network's sample (every point
  * when n <= 4096, else 16 blocks of 256 points, block b starting at
  * floor(b n / 16)) maximising fma(x, ux, y * uy) (ties: smallest index).  The
- * polygon is the exact convex hull of these k points (strict corners); a point
- * is discarded when it is strictly inside the polygon or strictly inside the
- * Step-2 quadrilateral (a polygon of fewer than three corners discards
- * nothing).  keep[n] receives 1 for survivors; cand[k+4] (may be NULL) the
- * four Step-1 extremes, then the direction candidates; *m1 the survivor
- * count.  Directions need not be normalised; they must be finite. */
+ * candidates are these k points and the four Step-1 extremes; the polygon is
+ * their exact convex hull (strict corners), which contains the
+ * quadrilateral, and a point is discarded when it is strictly inside it (a
+ * polygon of fewer than three corners discards nothing).  keep[n] receives 1
+ * for survivors; cand[k+4] (may be NULL) the candidate indices (extremes
+ * first); *m1 the survivor count.  Directions need not be normalised; they
+ * must be finite. */
 int oracle_learned_round1(const double* xy, int64_t n, const double* dirs, int32_t k,
                           uint8_t* keep, int32_t* cand, int64_t* m1);
 

@@ -649,16 +649,17 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
 
     // Step 1
-    // learned filter first: sample histogram, network, the sample's farthest
-    // point along each direction and their hull, the discard polygon (one
-    // workgroup).  It does not depend on Step 1, but running it on a second
-    // stream beside Step 1 measured no faster: the two share the device.
+    // learned filter first: sample histogram, network and the sample's
+    // farthest point along each direction (one workgroup); the end of Step 1
+    // then builds the discard polygon.  The proposal does not depend on the
+    // Step-1 pass, but running it on a second stream beside it measured no
+    // faster: the two share the device.
     if (learned) {
         HX_TRY(launch_front(d_xy, n, mlp_dev(c), c->learn, s));
         mark(HULL2D_STAGE_LEARNED);
     }
     const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
-    HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, s));
+    HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, learned ? c->learn : nullptr, s));
     mark(HULL2D_STAGE_EXTREMES);
     // Steps 2-3
     const int segs = std::min(
@@ -1159,11 +1160,8 @@ hull2d_status hull2d_debug_learned(hull2d_ctx* c, double* dirs, int32_t* cand, f
     if (!c->have_last || !c->last_learned) return HULL2D_ERR_INVALID_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
     LearnOut L;
-    DevStatus S;
     HX_TRY(hipMemcpyAsync(&L, c->learn, sizeof(LearnOut), hipMemcpyDeviceToHost, c->stream));
-    HX_TRY(hipMemcpyAsync(&S, c->ds, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
     HX_TRY(hipStreamSynchronize(c->stream));
-    for (int k = 0; k < 4; ++k) L.cand[k] = S.ext[k];  // the Step-1 extremes
     if (dirs) std::memcpy(dirs, L.dirs, sizeof(L.dirs));
     if (cand) std::memcpy(cand, L.cand, sizeof(L.cand));
     if (y) std::memcpy(y, L.y, sizeof(L.y));

@@ -47,8 +47,12 @@ struct DirBest {
     int32_t pad;
 };
 
+// lo: NULL, or (learned filter) the proposal whose candidates lo->cand[4..19]
+// join the four extremes; the final block then writes their exact hull to
+// lo->poly and the extremes to lo->cand[0..3].
+struct LearnOut;
 hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
-                           DevStatus* ds, hipStream_t s);
+                           DevStatus* ds, LearnOut* lo, hipStream_t s);
 int extremes_grid(int64_t n, int cu_count, int per_cu);
 
 // Resident blocks per compute unit of the fixed-grid streaming kernels (from
@@ -172,9 +176,8 @@ hipError_t launch_mlp_infer(const float* x, int rows, const MlpDev& W, float* h1
 // The whole proposal in one workgroup: the sample histogram, the network and
 // its 16 directions into lo->y and lo->dirs (the same arithmetic as
 // launch_histogram_sample, launch_hist_to_x and launch_mlp_infer), then the
-// sample point farthest along each direction into lo->cand[4 + j] and their
-// exact convex hull into lo->poly (qb left to the filter; lo->cand[0..3],
-// the Step-1 extremes, are not written).
+// sample point farthest along each direction into lo->cand[4 + j] (the
+// polygon is built at the end of Step 1, launch_extremes).
 hipError_t launch_front(const double* xy, int64_t n, const MlpDev& W, LearnOut* lo, hipStream_t s);
 // training
 hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int tA, const float* B, int ldb,

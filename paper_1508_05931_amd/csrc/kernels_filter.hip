@@ -144,9 +144,14 @@ __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restric
 // One block: final reduction of the partial candidates, the distinct
 // counter-clockwise corners P_minx -> P_miny -> P_maxx -> P_maxy, the pivot,
 // and the per-call reset of the status fields later kernels accumulate into.
+// kLearned: then the discard polygon, the exact hull of the four extremes and
+// the proposal's 16 candidates (lo->cand[4..19]) into lo->poly.
+template <bool kLearned>
 __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict__ partial, int nblocks,
                                                         Params* __restrict__ prm,
-                                                        DevStatus* __restrict__ ds) {
+                                                        DevStatus* __restrict__ ds,
+                                                        const double2* __restrict__ xy,
+                                                        LearnOut* __restrict__ lo) {
     constexpr int NW = 1024 / 64;
     __shared__ Cand s_c[NW][4];
     __shared__ uint32_t s_flags;
@@ -213,6 +218,20 @@ __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict_
         reinterpret_cast<uint32_t*>(prm)[i] = reinterpret_cast<const uint32_t*>(&s_p)[i];
     for (int i = (int)threadIdx.x; i < (int)(sizeof(DevStatus) / 4); i += 1024)
         reinterpret_cast<uint32_t*>(ds)[i] = reinterpret_cast<const uint32_t*>(&s_s)[i];
+    if (kLearned) {
+        static_assert(kPolyMax * kPolyMax <= 1024, "one thread per candidate pair");
+        __shared__ int32_t s_cand[kPolyMax];
+        __shared__ Poly Q;
+        const int t = (int)threadIdx.x;
+        // outside the domain: no polygon (every point is refused anyway)
+        if (t < kPolyMax) s_cand[t] = s_flags != 0u ? INT32_MAX : (t < 4 ? s_e[t].i : lo->cand[t]);
+        __syncthreads();
+        hull_of_candidates<kPolyMax>(s_cand, xy, Q);
+        static_assert(sizeof(Poly) % 8 == 0, "double copies");
+        for (int i = t; i < (int)(sizeof(Poly) / 8); i += 1024)
+            reinterpret_cast<double*>(&lo->poly)[i] = reinterpret_cast<const double*>(&Q)[i];
+        if (t < 4) lo->cand[t] = s_e[t].i;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -224,8 +243,8 @@ __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict_
 // the segment lengths are added up afterwards (k_longest), and later kernels
 // read the survivors segment by segment.
 // ---------------------------------------------------------------------------
-// kPoly: a point is also discarded strictly inside the learned polygon (the
-// discard region is the union of the quadrilateral and the polygon).
+// kPoly: the learned discard polygon (which contains the quadrilateral)
+// replaces it.
 template <bool kPoly>
 __global__ __launch_bounds__(kF1Block) void k_filter1(
     const double2* __restrict__ xy, int64_t n, int64_t chunk, const Params* __restrict__ prm,
@@ -250,7 +269,7 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
             dst[i] = src[i];
         __syncthreads();
         // the polygon's corners are input points: in the Step-1 box, whose
-        // bound the quadrilateral's test uses too
+        // bound the quadrilateral's test uses
         if (threadIdx.x == 0) s_poly.qb = prm->qbound;
         __syncthreads();
     }
@@ -310,14 +329,8 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
             key[k] = 0;
             if (pos < end && !discard_all) {
                 const double px = p[k].x, py = p[k].y;
-                // the learned polygon first: it holds most points where it
-                // pays, and the quadrilateral's test then runs for few lanes
-                if (kPoly) {
-                    surv = !poly_inside(s_poly, px, py);
-                    if (__ballot(surv) != 0 && surv) surv = !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
-                } else {
-                    surv = !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
-                }
+                surv = kPoly ? !poly_inside(s_poly, px, py)
+                             : !quad_inside(qx, qy, ex, ey, qb, nc, px, py);
                 if (surv && px == x0 && py == y0) {
                     surv = false;
                     ++p0c;
@@ -857,12 +870,17 @@ __global__ void k_debug_key(const double* __restrict__ xy, int64_t count, double
 }  // namespace
 
 hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
-                           DevStatus* ds, hipStream_t s) {
-    hipLaunchKernelGGL(k_extremes, dim3(grid), dim3(kExtBlock), 0, s, reinterpret_cast<const double2*>(xy),
-                       n, partial);
+                           DevStatus* ds, LearnOut* lo, hipStream_t s) {
+    const double2* p = reinterpret_cast<const double2*>(xy);
+    hipLaunchKernelGGL(k_extremes, dim3(grid), dim3(kExtBlock), 0, s, p, n, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_extremes_final, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds);
+    if (lo) {
+        hipLaunchKernelGGL(k_extremes_final<true>, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds, p, lo);
+    } else {
+        hipLaunchKernelGGL(k_extremes_final<false>, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds, nullptr,
+                           nullptr);
+    }
     return hipGetLastError();
 }
 

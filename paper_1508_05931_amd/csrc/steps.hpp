@@ -214,6 +214,96 @@ __device__ inline bool poly_inside(const Poly& Q, double x, double y) {
     return poly_orient(Q.px[lo], Q.py[lo], Q.px[hi], Q.py[hi], qb, x, y) > 0;
 }
 
+// The exact convex hull of the kC candidate points pts[s_c[j]] (INT32_MAX:
+// none) into Q (px, py, ex, ey, nv; not qb), by every thread of a block of
+// at least kC * kC threads.  One thread per ordered pair (a, b) of distinct candidates
+// decides whether a -> b is a counter-clockwise hull edge between strict
+// corners: every other candidate lies strictly left of it or on the open
+// segment (a, b).  A strict corner has exactly one such successor, so one
+// thread then walks the successors from the smallest (x, y), the order
+// Andrew's monotone chain gives.  Fewer than three distinct or only collinear
+// candidates give no polygon (nv = 0).
+template <int kC>
+__device__ inline void hull_of_candidates(const int32_t* s_c, const double2* pts, Poly& Q) {
+    static_assert(kC <= kPolyMax, "corners fit the polygon");
+    __shared__ double s_x[kC], s_y[kC];
+    __shared__ int32_t s_use[kC], s_next[kC];
+    const int t = (int)threadIdx.x;
+    if (t < kC) {
+        const int32_t c = s_c[t];
+        double2 p = make_double2(0.0, 0.0);
+        if (c != INT32_MAX) p = pts[c];
+        s_x[t] = p.x;
+        s_y[t] = p.y;
+        s_use[t] = c != INT32_MAX && fabs(p.x) <= DBL_MAX && fabs(p.y) <= DBL_MAX;
+        s_next[t] = -1;
+    }
+    __syncthreads();
+    // each distinct point once: the first candidate with its coordinates
+    int use = 0;
+    if (t < kC && s_use[t]) {
+        use = 1;
+        for (int u = 0; u < t; ++u) use &= !(s_use[u] && s_x[u] == s_x[t] && s_y[u] == s_y[t]);
+    }
+    __syncthreads();
+    if (t < kC) s_use[t] = use;
+    __syncthreads();
+    if (t < kC * kC) {
+        const int a = t / kC, b = t % kC;
+        if (a != b && s_use[a] && s_use[b]) {
+            const double ax = s_x[a], ay = s_y[a], bx = s_x[b], by = s_y[b];
+            const double lx = fmin(ax, bx), hx = fmax(ax, bx), ly = fmin(ay, by), hy = fmax(ay, by);
+            bool edge = true;
+            for (int p = 0; p < kC && edge; ++p) {
+                if (p == a || p == b || !s_use[p]) continue;
+                const double x = s_x[p], y = s_y[p];
+                const int o = orient(ax, ay, bx, by, x, y);
+                // collinear with a and b: on the open segment iff inside their box
+                edge = o > 0 || (o == 0 && x >= lx && x <= hx && y >= ly && y <= hy);
+            }
+            if (edge) s_next[a] = b;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        int start = -1;
+        for (int j = 0; j < kC; ++j)
+            if (s_use[j] && (start < 0 || s_x[j] < s_x[start] || (s_x[j] == s_x[start] && s_y[j] < s_y[start])))
+                start = j;
+        int h = 0, v = start;
+        if (start >= 0 && s_next[start] >= 0) {
+            do {
+                Q.px[h] = s_x[v];
+                Q.py[h] = s_y[v];
+                ++h;
+                v = s_next[v];
+            } while (v >= 0 && v != start && h < kC);
+            if (v != start) h = 0;  // not a closed cycle: no polygon
+        }
+        Q.pad = 0;
+        Q.nv = h >= 3 ? h : 0;
+        Q.qb = 0.0;
+    }
+    __syncthreads();
+    // edges from consecutive corners; unused slots zero
+    double x0 = 0.0, y0 = 0.0, x1 = 0.0, y1 = 0.0;
+    if (t < Q.nv) {
+        const int t1 = t + 1 < Q.nv ? t + 1 : 0;
+        x0 = Q.px[t];
+        y0 = Q.py[t];
+        x1 = Q.px[t1];
+        y1 = Q.py[t1];
+    }
+    __syncthreads();
+    if (t < kPolyMax) {
+        Q.px[t] = x0;
+        Q.py[t] = y0;
+        Q.ex[t] = x1 - x0;
+        Q.ey[t] = y1 - y0;
+    }
+    __syncthreads();
+}
+
 // Larger value wins, then the smaller index (extreme point along a direction).
 __device__ inline void dir_take(double& bv, int32_t& bi, double v, int32_t i) {
     const bool tk = (v > bv) | ((v == bv) & (i < bi));

@@ -154,7 +154,7 @@ def test_learned_first_round_equals_oracle(torch_dev, hx, name, wseed):
     info = c.learned_info()
     ref = oracle.learned_round1(pts, info["dirs"])
     assert info["cand"].tolist() == ref["cand"].tolist()
-    h = len(oracle.hull(pts[ref["cand"][4:]]))        # the polygon's strict corners
+    h = len(oracle.hull(pts[ref["cand"]]))            # the polygon's strict corners
     assert info["nv"] == (h if h >= 3 else 0)
     assert st.n_round1 == ref["m1"]
     assert st.n_round1 <= oracle.model(pts)["m1"]
@@ -184,9 +184,9 @@ def test_learned_collinear_and_repeated_candidates(torch_dev, hx):
     """Zero weights give zero outputs, hence the evenly spaced fallback
     directions, the first of them exactly (1, 0).  Its farthest point is the
     earliest of the right edge, the edge's midpoint (index 0), which lies
-    between the candidates (2, 0) and (2, 2) of the neighbouring directions:
-    a candidate that is no corner, next to repeated candidates.  The polygon
-    is the square."""
+    between the candidates (2, 0) and (2, 2) (the Step-1 extremes and the
+    neighbouring directions' points): a candidate that is no corner, next to
+    repeated candidates.  The polygon is the square."""
     ring = [[2, 1], [0, 0], [2, 0], [2, 2], [0, 2], [1, 0], [1, 2], [0, 1]]
     pts = np.concatenate([np.array(ring * 3, dtype=np.float64),
                           1.0 + 0.9 * synth.disk(5000, (418, 1))])

@@ -67,17 +67,10 @@ def test_learned_matches_brute_force_on_integer_points():
                min(idx, key=lambda i: (-P[i][1], -P[i][0], i))]
         dc = [min(idx, key=lambda i: (-(P[i][0] * int(ux) + P[i][1] * int(uy)), i)) for ux, uy in dirs]
         assert r["cand"].tolist() == ext + dc
-        # the quadrilateral: distinct extremes in their counter-clockwise order
-        quad = []
-        for i in ext:
-            if all(P[j] != P[i] for j in quad):
-                quad.append(i)
-        qpts = [pts[i] for i in quad]
-        cpts = np.array([P[i] for i in dc], dtype=np.float64).reshape(-1, 2)
-        ppts = [cpts[v] for v in brute_hull(cpts)] if len(dc) else []   # exact strict corners, CCW
+        cpts = np.array([P[i] for i in ext + dc], dtype=np.float64)
+        ppts = [cpts[v] for v in brute_hull(cpts)]       # exact strict corners, CCW
         for i in range(n):
-            gone = _inside_q(qpts, pts[i]) or _inside_q(ppts, pts[i])
-            assert r["keep"][i] == (not gone), (trial, i)
+            assert r["keep"][i] == (not _inside_q(ppts, pts[i])), (trial, i)
 
 
 def test_learned_directions_use_the_sample_only():
@@ -116,21 +109,21 @@ def test_learned_directions_use_the_sample_only():
         assert r["cand"][4] == far
 
 
-def test_learned_union_with_quadrilateral():
-    """A point inside the quadrilateral but outside the polygon is discarded,
-    and so is one inside the polygon but outside the quadrilateral: the
-    discard region is the union.  Square corners make the quadrilateral; one
-    direction candidate triangle (0, 0), (10, 0), (0, 10) and the square
-    (0..10)^2 overlap but neither holds the other."""
+def test_learned_polygon_contains_the_quadrilateral():
+    """The polygon is the hull of the direction candidates and the four
+    Step-1 extremes: a point inside the quadrilateral but outside the
+    candidates' own hull is discarded, and so is one between the two that
+    neither holds alone."""
     ring = [(0.0, 5.0), (5.0, 0.0), (10.0, 5.0), (5.0, 10.0)]   # the Step-1 extremes
     tri = [(0.0, 0.0), (9.0, 0.0), (0.0, 9.0)]                   # sample candidates
-    probe = [(5.0, 5.0), (1.0, 1.0), (8.0, 8.0), (9.9, 0.5)]
+    probe = [(5.0, 5.0), (1.0, 1.0), (7.0, 6.0), (9.0, 3.0), (9.9, 0.5)]
     pts = np.array(ring + tri + probe)
     dirs = [(-1.0, -1.0), (1.0, -10.0), (-10.0, 1.0)]
     r = oracle.learned_round1(pts, dirs)
     assert r["cand"][4:].tolist() == [4, 5, 6]
-    # (5, 5) in both, (1, 1) only in the triangle, (8, 8) in neither, (9.9, 0.5) outside both
-    assert r["keep"][7:].tolist() == [False, False, True, True]
+    # (5, 5) in both, (1, 1) only in the triangle, (7, 6) only in the
+    # quadrilateral, (9, 3) in neither but inside their hull; (9.9, 0.5) outside
+    assert r["keep"][7:].tolist() == [False, False, False, False, True]
     assert r["keep"][:7].all()
 
 
