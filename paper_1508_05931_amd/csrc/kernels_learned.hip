@@ -167,7 +167,8 @@ __global__ void k_hist_to_x(const uint32_t* __restrict__ hist, int64_t n, float*
 }
 
 // One layer for rows of inputs (blockIdx.y = row): out = act(W in + b), one
-// wave per output unit, each lane summing every 64th input (bfloat16 weights
+// wave per output unit, lane l summing inputs 2l + 128k and 2l + 1 + 128k for
+// k = 0, 1, ... in that order (one 4-byte load per pair of bfloat16 weights
 // [out][in], layer input rounded to bfloat16, float32 sums).  act: ReLU then
 // bfloat16 rounding (hidden layers), or none (the output layer).
 constexpr int kMlpWaves = 4;  // output units per workgroup
@@ -182,7 +183,11 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_layer(const float* __res
     const float* x = in + (size_t)blockIdx.y * n_in;
     const uint16_t* w = W + (size_t)o * n_in;
     float acc = 0.f;
-    for (int i = lane; i < n_in; i += 64) acc = fmaf(from_bf16(to_bf16(x[i])), from_bf16(w[i]), acc);
+    for (int i = 2 * lane; i < n_in; i += 128) {
+        const uint32_t w2 = *reinterpret_cast<const uint32_t*>(w + i);  // inputs i, i + 1
+        acc = fmaf(from_bf16(to_bf16(x[i])), from_bf16((uint16_t)(w2 & 0xFFFFu)), acc);
+        acc = fmaf(from_bf16(to_bf16(x[i + 1])), from_bf16((uint16_t)(w2 >> 16)), acc);
+    }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
     if (lane == 0) {
@@ -200,7 +205,7 @@ constexpr int kFB = 1024;
 
 // out[o] = act(W[o] . in + b[o]) for every unit o (in, out in LDS): wave w
 // takes the kU units o = w + 16 u, all their loads in flight together, each
-// lane summing every 64th input as k_mlp_layer does; the 64 lane sums of a
+// lane summing its inputs in the order k_mlp_layer does; the 64 lane sums of a
 // unit are then added by a tree in LDS (s[l] += s[l + m], m = 32 .. 1) that
 // associates them as k_mlp_layer's butterfly does for lane 0, so each output
 // equals k_mlp_layer's bit for bit.  s_r: [kMlpHidden][64] floats.
@@ -213,11 +218,18 @@ __device__ inline void front_layer(const float* in, const uint16_t* __restrict__
     float acc[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) acc[u] = 0.f;
-#pragma unroll 4
-    for (int i = lane; i < kIn; i += 64) {
-        const float x = from_bf16(to_bf16(in[i]));
+#pragma unroll 2
+    for (int i = 2 * lane; i < kIn; i += 128) {
+        const float x0 = from_bf16(to_bf16(in[i])), x1 = from_bf16(to_bf16(in[i + 1]));
+        uint32_t w2[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) acc[u] = fmaf(x, from_bf16(W[(size_t)(wave + 16 * u) * kIn + i]), acc[u]);
+        for (int u = 0; u < kU; ++u)
+            w2[u] = *reinterpret_cast<const uint32_t*>(W + (size_t)(wave + 16 * u) * kIn + i);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            acc[u] = fmaf(x0, from_bf16((uint16_t)(w2[u] & 0xFFFFu)), acc[u]);
+            acc[u] = fmaf(x1, from_bf16((uint16_t)(w2[u] >> 16)), acc[u]);
+        }
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) s_r[wave + 16 * u][lane] = acc[u];
