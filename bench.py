@@ -38,15 +38,15 @@ TRAFFIC = {
         "profile": "profiles/hull_square_disk_20M_hbm_counters.md",
         "sources": {
             "paper_1508_05931_amd/csrc/kernels_filter.hip":
-                "aa54d9ca15ee9676c762b727bc8753753c54a0f74e25aa5c1ef4e64d3bbe4a1c",
+                "eb10d0268da482d2c03267e327c04c2a85933129c8a55362ca0720dbc2ea054e",
             "paper_1508_05931_amd/csrc/steps.hpp":
-                "b8a17d37316efece011b1de67cb39106b34fe7134dc7e05fd035c1f6ed96ebb0",
+                "7b32c3f7365b9f2d34df8ffb0e4d4f2e7e4fab099590c99ecfe683078a7d91c4",
             "paper_1508_05931_amd/csrc/exact.hpp":
                 "492fba6ee743cba0bb741d699072aaffa58163bfd2ddf06fa43db6642a3a9861",
             "paper_1508_05931_amd/csrc/common.hpp":
                 "044be352493ceaba3339859e0a74a6c108f123de1ccffeb5df255bc633cfd97f",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "6357e8f06f579beb94a75ce1e27b8a1fbb4de5e2939fa9fd17ddbe45542dd962",
+                "d7ab157ab54f5a20c27d97668bd7fa788679e03e50e727db0d488fe43a857ba9",
         },
     },
 }
