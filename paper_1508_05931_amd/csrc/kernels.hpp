@@ -163,6 +163,7 @@ struct LearnOut {
     double dirs[2 * kMlpDirs];  // directions used (network output, or the fallback)
     float y[kMlpOut];           // raw network outputs
     int32_t cand[kPolyMax];     // candidates: the four Step-1 extremes, then one per direction
+    double cxy[2 * kMlpDirs];   // coordinates of the direction candidates
 };
 
 int learned_grid(int64_t n, int cu_count);

@@ -145,12 +145,12 @@ __global__ __launch_bounds__(kExtBlock) void k_extremes(const double2* __restric
 // counter-clockwise corners P_minx -> P_miny -> P_maxx -> P_maxy, the pivot,
 // and the per-call reset of the status fields later kernels accumulate into.
 // kLearned: then the discard polygon, the exact hull of the four extremes and
-// the proposal's 16 candidates (lo->cand[4..19]) into lo->poly.
+// the proposal's 16 candidates (lo->cand[4..19], coordinates lo->cxy) into
+// lo->poly.
 template <bool kLearned>
 __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict__ partial, int nblocks,
                                                         Params* __restrict__ prm,
                                                         DevStatus* __restrict__ ds,
-                                                        const double2* __restrict__ xy,
                                                         LearnOut* __restrict__ lo) {
     constexpr int NW = 1024 / 64;
     __shared__ Cand s_c[NW][4];
@@ -220,13 +220,22 @@ __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict_
         reinterpret_cast<uint32_t*>(ds)[i] = reinterpret_cast<const uint32_t*>(&s_s)[i];
     if (kLearned) {
         static_assert(kPolyMax * kPolyMax <= 1024, "one thread per candidate pair");
-        __shared__ int32_t s_cand[kPolyMax];
+        __shared__ double s_x[kPolyMax], s_y[kPolyMax];
+        __shared__ int32_t s_use[kPolyMax];
         __shared__ Poly Q;
         const int t = (int)threadIdx.x;
-        // outside the domain: no polygon (every point is refused anyway)
-        if (t < kPolyMax) s_cand[t] = s_flags != 0u ? INT32_MAX : (t < 4 ? s_e[t].i : lo->cand[t]);
+        // the extremes' coordinates are here, the candidates' in lo; outside
+        // the domain: no polygon (every point is refused anyway)
+        if (t < kPolyMax) {
+            const int32_t c = t < 4 ? s_e[t].i : lo->cand[t];
+            const double x = t < 4 ? s_e[t].x : lo->cxy[2 * (t - 4)];
+            const double y = t < 4 ? s_e[t].y : lo->cxy[2 * (t - 4) + 1];
+            s_x[t] = x;
+            s_y[t] = y;
+            s_use[t] = s_flags == 0u && c != INT32_MAX && fabs(x) <= DBL_MAX && fabs(y) <= DBL_MAX;
+        }
         __syncthreads();
-        hull_of_candidates<kPolyMax>(s_cand, xy, Q);
+        hull_of_points<kPolyMax>(s_x, s_y, s_use, Q);
         static_assert(sizeof(Poly) % 8 == 0, "double copies");
         for (int i = t; i < (int)(sizeof(Poly) / 8); i += 1024)
             reinterpret_cast<double*>(&lo->poly)[i] = reinterpret_cast<const double*>(&Q)[i];
@@ -876,10 +885,9 @@ hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (lo) {
-        hipLaunchKernelGGL(k_extremes_final<true>, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds, p, lo);
+        hipLaunchKernelGGL(k_extremes_final<true>, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds, lo);
     } else {
-        hipLaunchKernelGGL(k_extremes_final<false>, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds, nullptr,
-                           nullptr);
+        hipLaunchKernelGGL(k_extremes_final<false>, dim3(1), dim3(1024), 0, s, partial, grid, prm, ds, nullptr);
     }
     return hipGetLastError();
 }

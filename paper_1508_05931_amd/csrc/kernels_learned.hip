@@ -364,8 +364,12 @@ __global__ __launch_bounds__(kFB) void k_front(const double2* __restrict__ xy, i
     if (t < kMlpOut) lo->y[t] = s_y[t];
     if (t >= 64 && t < 64 + 2 * kDirs) lo->dirs[t - 64] = s_u[t - 64];
     if (t >= 128 && t < 128 + kDirs) {
-        const int32_t sl = s_c[t - 128];
-        lo->cand[4 + t - 128] = sl == INT32_MAX ? INT32_MAX : (int32_t)sample_point(sl, n);
+        const int d = t - 128;
+        const int32_t sl = s_c[d];
+        lo->cand[4 + d] = sl == INT32_MAX ? INT32_MAX : (int32_t)sample_point(sl, n);
+        const double2 q = sl == INT32_MAX ? make_double2(0.0, 0.0) : s_pt[sl];
+        lo->cxy[2 * d] = q.x;
+        lo->cxy[2 * d + 1] = q.y;
     }
 }
 

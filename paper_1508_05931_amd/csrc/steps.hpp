@@ -214,39 +214,38 @@ __device__ inline bool poly_inside(const Poly& Q, double x, double y) {
     return poly_orient(Q.px[lo], Q.py[lo], Q.px[hi], Q.py[hi], qb, x, y) > 0;
 }
 
-// The exact convex hull of the kC candidate points pts[s_c[j]] (INT32_MAX:
-// none) into Q (px, py, ex, ey, nv; not qb), by every thread of a block of
-// at least kC * kC threads.  One thread per ordered pair (a, b) of distinct candidates
-// decides whether a -> b is a counter-clockwise hull edge between strict
-// corners: every other candidate lies strictly left of it or on the open
-// segment (a, b).  A strict corner has exactly one such successor, so one
-// thread then walks the successors from the smallest (x, y), the order
-// Andrew's monotone chain gives.  Fewer than three distinct or only collinear
-// candidates give no polygon (nv = 0).
+// The exact convex hull of kC candidate points (s_x, s_y; s_use[j] = 0: no
+// point) into Q (px, py, ex, ey, nv; not qb), by every thread of a block of
+// at least kC * kC threads; s_use is overwritten.  One thread per ordered
+// pair (a, b) of distinct points decides whether a -> b is a
+// counter-clockwise hull edge between strict corners: every other point lies
+// strictly left of it or on the open segment (a, b).  A strict corner has
+// exactly one such successor.  The corners are then placed in the order of
+// Andrew's monotone chain, counter-clockwise from the smallest (x, y): a
+// corner's position is the number of corners u with orient(start, u, v) > 0
+// (strict convexity makes that the angular order around the start).  Fewer
+// than three corners give no polygon (nv = 0).
 template <int kC>
-__device__ inline void hull_of_candidates(const int32_t* s_c, const double2* pts, Poly& Q) {
+__device__ inline void hull_of_points(const double* s_x, const double* s_y, int32_t* s_use, Poly& Q) {
     static_assert(kC <= kPolyMax, "corners fit the polygon");
-    __shared__ double s_x[kC], s_y[kC];
-    __shared__ int32_t s_use[kC], s_next[kC];
+    __shared__ int32_t s_next[kC];
+    __shared__ int32_t s_start, s_nv;
     const int t = (int)threadIdx.x;
-    if (t < kC) {
-        const int32_t c = s_c[t];
-        double2 p = make_double2(0.0, 0.0);
-        if (c != INT32_MAX) p = pts[c];
-        s_x[t] = p.x;
-        s_y[t] = p.y;
-        s_use[t] = c != INT32_MAX && fabs(p.x) <= DBL_MAX && fabs(p.y) <= DBL_MAX;
-        s_next[t] = -1;
-    }
-    __syncthreads();
     // each distinct point once: the first candidate with its coordinates
     int use = 0;
     if (t < kC && s_use[t]) {
         use = 1;
         for (int u = 0; u < t; ++u) use &= !(s_use[u] && s_x[u] == s_x[t] && s_y[u] == s_y[t]);
     }
+    if (t == 0) {
+        s_start = -1;
+        s_nv = 0;
+    }
     __syncthreads();
-    if (t < kC) s_use[t] = use;
+    if (t < kC) {
+        s_use[t] = use;
+        s_next[t] = -1;
+    }
     __syncthreads();
     if (t < kC * kC) {
         const int a = t / kC, b = t % kC;
@@ -265,41 +264,44 @@ __device__ inline void hull_of_candidates(const int32_t* s_c, const double2* pts
         }
     }
     __syncthreads();
-    if (t == 0) {
-        int start = -1;
-        for (int j = 0; j < kC; ++j)
-            if (s_use[j] && (start < 0 || s_x[j] < s_x[start] || (s_x[j] == s_x[start] && s_y[j] < s_y[start])))
-                start = j;
-        int h = 0, v = start;
-        if (start >= 0 && s_next[start] >= 0) {
-            do {
-                Q.px[h] = s_x[v];
-                Q.py[h] = s_y[v];
-                ++h;
-                v = s_next[v];
-            } while (v >= 0 && v != start && h < kC);
-            if (v != start) h = 0;  // not a closed cycle: no polygon
+    const bool corner = t < kC && s_use[t] && s_next[t] >= 0;
+    if (corner) {
+        bool least = true;  // the smallest (x, y) of the distinct points
+        for (int u = 0; u < kC; ++u)
+            least &= !(s_use[u] && (s_x[u] < s_x[t] || (s_x[u] == s_x[t] && s_y[u] < s_y[t])));
+        if (least) s_start = t;
+        atomicAdd(&s_nv, 1);
+    }
+    __syncthreads();
+    const int start = s_start, nv = s_nv >= 3 && start >= 0 ? s_nv : 0;
+    int pos = -1;
+    if (corner && nv > 0) {
+        pos = 0;
+        if (t != start) {
+            const double sx = s_x[start], sy = s_y[start];
+            pos = 1;
+            for (int u = 0; u < kC; ++u)
+                if (u != start && u != t && s_use[u] && s_next[u] >= 0)
+                    pos += orient(sx, sy, s_x[u], s_y[u], s_x[t], s_y[t]) > 0;
         }
+    }
+    if (t < kPolyMax && t >= nv) {
+        Q.px[t] = 0.0;
+        Q.py[t] = 0.0;
+        Q.ex[t] = 0.0;
+        Q.ey[t] = 0.0;
+    }
+    if (pos >= 0 && pos < kPolyMax) {
+        const int nx = s_next[t];
+        Q.px[pos] = s_x[t];
+        Q.py[pos] = s_y[t];
+        Q.ex[pos] = s_x[nx] - s_x[t];
+        Q.ey[pos] = s_y[nx] - s_y[t];
+    }
+    if (t == 0) {
         Q.pad = 0;
-        Q.nv = h >= 3 ? h : 0;
+        Q.nv = nv;
         Q.qb = 0.0;
-    }
-    __syncthreads();
-    // edges from consecutive corners; unused slots zero
-    double x0 = 0.0, y0 = 0.0, x1 = 0.0, y1 = 0.0;
-    if (t < Q.nv) {
-        const int t1 = t + 1 < Q.nv ? t + 1 : 0;
-        x0 = Q.px[t];
-        y0 = Q.py[t];
-        x1 = Q.px[t1];
-        y1 = Q.py[t1];
-    }
-    __syncthreads();
-    if (t < kPolyMax) {
-        Q.px[t] = x0;
-        Q.py[t] = y0;
-        Q.ex[t] = x1 - x0;
-        Q.ey[t] = y1 - y0;
     }
     __syncthreads();
 }
