@@ -38,15 +38,15 @@ TRAFFIC = {
         "profile": "profiles/hull_square_disk_20M_hbm_counters.md",
         "sources": {
             "paper_1508_05931_amd/csrc/kernels_filter.hip":
-                "eb10d0268da482d2c03267e327c04c2a85933129c8a55362ca0720dbc2ea054e",
+                "82e53e6b266215982c7d85550d3bb091b6bd40116f317974bc1a0b13b194fa52",
             "paper_1508_05931_amd/csrc/steps.hpp":
-                "7b32c3f7365b9f2d34df8ffb0e4d4f2e7e4fab099590c99ecfe683078a7d91c4",
+                "8e60bb756ef40c536e5d9acdb9c5097a2a648fa16538b70ee0406e8c7f734db2",
             "paper_1508_05931_amd/csrc/exact.hpp":
                 "492fba6ee743cba0bb741d699072aaffa58163bfd2ddf06fa43db6642a3a9861",
             "paper_1508_05931_amd/csrc/common.hpp":
                 "044be352493ceaba3339859e0a74a6c108f123de1ccffeb5df255bc633cfd97f",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "d7ab157ab54f5a20c27d97668bd7fa788679e03e50e727db0d488fe43a857ba9",
+                "096c60741311ef7199b3ace33901eda36d453629eed8d01e6c408db8d7dffb59",
         },
     },
 }
