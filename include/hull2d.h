@@ -81,10 +81,10 @@ typedef struct {
      * directions from a 32 x 32 occupancy histogram of a sample (every point
      * when n <= 4096, else 16 blocks of 256 points, block b starting at
      * floor(b n / 16)); the exact hull of the sample points extreme in those
-     * directions is the discard polygon, and a point is discarded strictly
-     * inside it or strictly inside the quadrilateral.  So it discards at
-     * least as much as the quadrilateral, and never a hull vertex (both
-     * polygons have input points as corners).  Needs weights
+     * directions and of the four Step-1 extremes is the discard polygon, and
+     * a point is discarded strictly inside it.  It contains the
+     * quadrilateral, so it discards at least as much, and never a hull
+     * vertex (its corners are input points).  Needs weights
      * (hull2d_set_weights / hull2d_load_weights), else hull2d_compute
      * returns HULL2D_ERR_WEIGHTS. */
     int32_t filter;

@@ -6,10 +6,11 @@
 //   evenly spaced blocks of 256 points) over the sample's bounding box; the
 //   1024 -> 256 -> 256 -> 32 network (bfloat16 weights and layer inputs,
 //   float32 sums): 16 directions; the sample point farthest along each
-//   (fma(x, ux, y * uy), ties: smallest index); their exact convex hull, the
-//   discard polygon.  The first round discards strictly inside it or
-//   strictly inside the quadrilateral; both have input points as corners,
-//   so it stays conservative whatever the network says.
+//   (fma(x, ux, y * uy), ties: smallest index).  The final Step-1 block
+//   (kernels_filter.hip) then takes the exact convex hull of these 16
+//   points and the four Step-1 extremes: the discard polygon, which
+//   contains the quadrilateral, so the first round stays conservative
+//   whatever the network says.
 // k_sample_bbox, k_sample_hist, k_hist_to_x and k_mlp_layer compute the
 // histogram and the network as separate kernels for the standalone entry
 // points (k_front's outputs equal theirs bit for bit).
