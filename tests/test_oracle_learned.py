@@ -1,9 +1,11 @@
 """Pins of the learned-filter oracle and of the network reference.
 
-The learned first round must keep every hull vertex, keep at least what the
-quadrilateral keeps, match a brute-force exact evaluation of its definition
-on small integer inputs, and give the closed-form survivor count on a
-regular polygon.  The network reference's gradient must match central
+The learned first round must keep every hull vertex, keep nothing the
+quadrilateral discards, match a brute-force exact evaluation of its
+definition on small integer inputs, take its direction candidates from the
+network's sample only, discard between the quadrilateral and the
+candidates' own hull, and give the closed-form survivor count on a regular
+polygon.  The network reference's gradient must match central
 finite differences, and its layers must reduce to the bias on zero weights.
 """
 import math
