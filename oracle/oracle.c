@@ -215,7 +215,10 @@ static int64_t chunk_length(int64_t chunk, int64_t m) {
  * backward from P_temp = q[N-1]; a point strictly right of P_temp -> P_l is
  * interior.  With subsets (Section 3.4) every subset restarts P_temp at its
  * first point in walking order and keeps that point untested, except the right
- * region's first subset, which starts from P_0 as the figure does. */
+ * region's first subset, which starts from P_0 as the figure does.  Subsets
+ * are cut in walking order: the right region from q[1] upward, the left
+ * region from q[N-1] downward, so each region's short leftover subset is the
+ * one next to P_longest. */
 int oracle_round2(const double* q, int64_t N, int64_t l, int64_t chunk, uint8_t* keep) {
     if (N < 1 || l < 0 || l >= N || !q || !keep || (l == 0 && N > 1)) return ORACLE_BADARG;
     for (int64_t i = 0; i < N; ++i) keep[i] = 1;

@@ -197,3 +197,132 @@ def test_histogram_definition():
     assert np.allclose(h.reshape(32, 32).sum(), 1024.0)
     assert mlp.histogram(np.zeros((0, 2))).sum() == 0
 
+
+
+def _sparse_params():
+    """A network whose only non-zero parameters are the few below, so every
+    output can be worked out by hand (values are float32 and dyadic)."""
+    p = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
+    # layer 1: unit 0 = x0 + 2^-9 (not a bfloat16 value: rounds down to 1
+    # when x0 = 1); unit 1 = x1 + 2^-8 - 2 (for x1 = 3 a tie between 1 and
+    # 1 + 2^-7 -> even -> 1)
+    p["W1"][0, 0] = 1.0
+    p["b1"][0] = 2.0 ** -9
+    p["W1"][1, 1] = 1.0
+    p["b1"][1] = 2.0 ** -8 - 2.0
+    # layer 2: identity on units 0 and 1
+    p["W2"][0, 0] = 1.0
+    p["W2"][1, 1] = 1.0
+    # layer 3: y0 = 3 h0 + 1/4; y1 = w h1 + b with w = 1 + 2^-9 (rounds to 1
+    # in bfloat16) and b = 1 + 2^-12 (a float32 bias, not rounded)
+    p["W3"][0, 0] = 3.0
+    p["b3"][0] = 0.25
+    p["W3"][1, 1] = 1.0 + 2.0 ** -9
+    p["b3"][1] = 1.0 + 2.0 ** -12
+    return mlp.pack(p)
+
+
+def _sparse_input():
+    x = np.zeros((1, mlp.N_IN))
+    x[0, 0] = 1.0
+    # 3 + 2^-7 is not a bfloat16 value either: the input rounds to 3 first
+    x[0, 1] = 3.0 + 2.0 ** -7
+    return x
+
+
+def test_forward_bf16_hand_worked():
+    """The inference reference on a hand-worked case: weights and layer inputs
+    rounded to bfloat16 (nearest, ties to even), biases kept in float32, the
+    last layer's output not rounded.  Expected values by hand, in exact
+    rationals:
+      x0 = 1 -> z = 1 + 2^-9 -> h1[0] = bf16(z) = 1 (2^-9 < half an ulp 2^-8);
+      x1 = bf16(3 + 2^-7) = 3 (ulp at 2 is 2^-6, 2^-7 is a tie -> even 3)
+        -> z = 3 + 2^-8 - 2 = 1 + 2^-8, a tie -> h1[1] = 1 (even);
+        unrounded, x1 would give 1 + 3*2^-8, a tie -> 1 + 2^-6;
+      h2 = h1 (identity, already bfloat16);
+      y0 = 3 * 1 + 1/4; y1 = bf16(1 + 2^-9) * 1 + (1 + 2^-12) = 2 + 2^-12;
+      every other output is 0."""
+    y = mlp.forward_bf16(_sparse_params(), _sparse_input())
+    want = np.zeros(mlp.N_OUT)
+    want[0] = float(Fraction(3) + Fraction(1, 4))
+    want[1] = float(Fraction(2) + Fraction(1, 4096))
+    assert y.shape == (1, mlp.N_OUT)
+    assert np.array_equal(y[0], want), (y[0][:2], want[:2])
+    # the float64 network differs on both outputs (no rounding anywhere)
+    y64, _ = mlp.forward(_sparse_params(), _sparse_input())
+    assert y64[0, 0] == 3 * (1 + 2.0 ** -9) + 0.25
+    assert y64[0, 0] != y[0, 0] and y64[0, 1] != y[0, 1]
+
+
+def test_forward_bf16_pin_catches_plausible_mistakes(monkeypatch):
+    """Each plausible misreading of the inference precision changes the
+    hand-worked outputs above: hidden activations left unrounded, biases
+    rounded, inputs unrounded, or ties rounded away from zero."""
+    params, x = _sparse_params(), _sparse_input()
+    want = mlp.forward_bf16(params, x)
+    real = mlp.bf16
+
+    def run(fake):
+        monkeypatch.setattr(mlp, "bf16", fake)
+        try:
+            return mlp.forward_bf16(params, x)
+        finally:
+            monkeypatch.setattr(mlp, "bf16", real)
+
+    calls = {"n": 0}
+
+    def skip_hidden(a):            # 1st call rounds x, 2nd W1, 3rd h1 ...
+        calls["n"] += 1
+        return np.asarray(a, dtype=np.float64) if calls["n"] in (3, 5) else real(a)
+
+    def skip_input(a):
+        calls["n"] += 1
+        return np.asarray(a, dtype=np.float64) if calls["n"] == 1 else real(a)
+
+    def ties_away(a):
+        f = np.ascontiguousarray(a, dtype=np.float32)
+        u = f.view(np.uint32).astype(np.uint64)
+        r = ((u + 0x8000) >> 16) << 16
+        return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+    for fake in (skip_hidden, skip_input, ties_away):
+        calls["n"] = 0
+        assert not np.array_equal(run(fake), want), fake.__name__
+    # rounding the biases as well
+    p = mlp.unpack(params)
+    for k in ("b1", "b2", "b3"):
+        p[k] = real(p[k])
+    assert not np.array_equal(mlp.forward_bf16(mlp.pack(p), x), want)
+
+
+def _cell(h, cx, cy):
+    return float(h.reshape(32, 32)[cy, cx])
+
+
+def test_histogram_cell_map_hand_placed():
+    """Hand-placed points on a bounding box of 8 x 2 (x from -4 to 4, y from
+    1 to 3): a cell is 1/4 wide and 1/16 high, every scale factor is exact,
+    and a cell index is cy * 32 + cx with cx = floor((x + 4) * 4) and
+    cy = floor((y - 1) * 16), clipped to 31 (the box maximum lands in cell
+    31).  Eight points, so each count weighs 1024 / 8 = 128."""
+    pts = np.array([
+        (-4.0, 1.0),        # box minimum -> (0, 0)
+        (4.0, 3.0),         # box maximum -> (31, 31) after clipping 32
+        (-2.25, 1.0625),    # (7, 1): x + 4 = 1.75 -> 7; y - 1 = 1/16 -> 1
+        (-2.2500000000000004, 1.0),  # one ulp left of the boundary -> (6, 0)
+        (0.0, 2.5),         # (16, 24)
+        (0.0, 2.5),         # same cell again
+        (3.99, 1.01),       # (31, 0)
+        (-3.9, 2.99),       # (0, 31)
+    ])
+    h = mlp.histogram(pts)
+    want = {(0, 0): 1, (31, 31): 1, (7, 1): 1, (6, 0): 1, (16, 24): 2, (31, 0): 1, (0, 31): 1}
+    for (cx, cy), k in want.items():
+        assert _cell(h, cx, cy) == 128.0 * k, (cx, cy)
+    assert float(h.sum()) == 128.0 * 8
+    # x and y are not interchangeable: the transposed cells are empty
+    assert _cell(h, 24, 16) == 0.0 and _cell(h, 1, 7) == 0.0
+    # a flat box (all y equal) puts everything in row 0
+    flat = np.array([(0.0, 5.0), (1.0, 5.0), (2.0, 5.0), (4.0, 5.0)])
+    hf = mlp.histogram(flat)
+    assert [_cell(hf, cx, 0) for cx in (0, 8, 16, 31)] == [256.0] * 4

@@ -243,3 +243,84 @@ def test_subsets_only_add_survivors(name):
         assert base <= set(oracle.model(pts, chunk)["round2"].tolist())
     m1 = oracle.model(pts, 1)
     assert m1["m2"] == len(m1["sorted"]) + 1   # subsets of one point test nothing
+
+
+# Round 2 on hand-made sequences.  P_0 = (0, 0) and P_l = (0, 1000); every
+# other point has small integer coordinates (|x|, |y| <= 10); two points
+# that are compared either differ in x or are the same point.  Then
+# orient(T, P_l, P) =
+# -T.x (P.y - T.y) - (1000 - T.y)(P.x - T.x), whose second term (at least
+# 990 in magnitude) outweighs the first (at most 200): P is strictly left of
+# T -> P_l exactly when P.x < T.x, strictly right exactly when P.x > T.x.
+# So the right region discards P_i when P_i.x < P_temp.x, the left region
+# when P_i.x > P_temp.x; a copy of P_temp (orientation 0) is kept.
+def _r2_sequence(right_x, left_x):
+    q = [(0.0, 0.0)] + [(float(x), 1.0) for x in right_x] + [(0.0, 1000.0)] + \
+        [(float(x), 2.0) for x in left_x]
+    return np.array(q), 1 + len(right_x)
+
+
+def test_round2_subsets_hand_worked():
+    """Section 3.4's subsets on a hand-worked sequence (positions 1..7 right
+    of P_l at 8, positions 9..15 left).  Subsets restart P_temp at their first
+    point in walking order, which is kept untested; the right region's first
+    subset starts from P_0.  The right region is cut from position 1 upward,
+    the left region from the last position downward (its walking order), so
+    its last subset, next to P_l, is the short one.  Expected masks worked
+    out by hand from the x rule above."""
+    rx = [5, 3, 7, 2, 6, 9, 1]
+    lx = [4, 8, 2, 6, 3, 9, 5]
+    q, l = _r2_sequence(rx, lx)
+    assert l == 8 and len(q) == 16
+    # one walk per region (Figure 2): right keeps running maxima of x from 0
+    # (5, 7, 9); left walks 15 -> 9 from x = 5 keeping running minima (3, 2)
+    one = oracle.round2(q, l, 0)
+    assert one[1:8].tolist() == [1, 0, 1, 0, 0, 1, 0]
+    assert one[9:16].tolist() == [0, 0, 1, 0, 1, 0, 1]
+    # subsets of 3.  Right: [1,2,3] from P_0 -> 5 keep, 3 drop, 7 keep;
+    # [4,5,6] from x=2 (kept) -> 6 keep, 9 keep; [7] alone (kept).
+    # Left, cut from the top: [15,14,13] from x=5 -> 9 drop, 3 keep;
+    # [12,11,10] from x=6 (kept) -> 2 keep, 8 drop; [9] alone (kept).
+    three = oracle.round2(q, l, 3)
+    assert three[1:8].tolist() == [1, 0, 1, 1, 1, 1, 1]
+    assert three[9:16].tolist() == [1, 0, 1, 1, 1, 0, 1]
+    # cut from the bottom instead, the left region would keep 12 (x=6 after
+    # 13's x=3 in subset [14,13,12]) and drop 9: the layout is pinned
+    assert three[12] and three[9]
+    assert three[0] and three[l]
+    # the right region's first subset starts from P_0, so its first point is
+    # tested: x = -1 is strictly left of P_0 -> P_l and dropped
+    q2, l2 = _r2_sequence([-1, 4, 2, 6], [3])
+    # (one walk: 4 keep, 2 drop, 6 keep; subsets of 3: [1,2,3] likewise, [4]
+    # alone is kept)
+    for c in (0, 3):
+        assert oracle.round2(q2, l2, c)[1:l2].tolist() == [0, 1, 0, 1]
+
+
+def test_round2_paper_subsets_hand_worked():
+    """The paper's division: 1024 subsets of ceil(m/1024) points per region.
+    With m = 2053 points the subsets hold 3 points; the x pattern (5, 3, 7)
+    repeated makes every subset, the first one from P_0 and the others from
+    their own first point (x = 5), keep 5, drop 3, keep 7; the last subset
+    holds the leftover 2053 - 684*3 = 1 point, kept.  The left region
+    mirrors it with the pattern (5, 7, 3) read from the top: each subset
+    starts at x = 5 (kept), drops 7, keeps 3 -- and its leftover point, at
+    position l + 1, starts a subset of its own."""
+    m = 2053
+    rx = [(5, 3, 7)[i % 3] for i in range(m)]
+    lx = [None] * m
+    for k in range(m):                  # k counts from the top (walking order)
+        lx[m - 1 - k] = (5, 7, 3)[k % 3]
+    q, l = _r2_sequence(rx, lx)
+    keep = oracle.round2(q, l, -1)
+    right = keep[1:l]
+    assert right[:-1].tolist() == [1, 0, 1] * 684 and right[-1]
+    left_walk = keep[l + 1:][::-1]     # in walking order, from the top
+    assert left_walk[:-1].tolist() == [1, 0, 1] * 684 and left_walk[-1]
+    # one walk instead: the right region keeps the first 5 and every copy
+    # of the running maximum 7 (684 of them); the left region the first 5
+    # and every copy of the running minimum 3 (684)
+    one = oracle.round2(q, l, 0)
+    assert one[1] and int(one[1:l].sum()) == 685
+    assert all(one[1 + i] == (i == 0 or rx[i] == 7) for i in range(m))
+    assert int(one[l + 1:].sum()) == 685
