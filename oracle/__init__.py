@@ -55,6 +55,20 @@ class _ModelResult(ctypes.Structure):
     ]
 
 
+class _ChainResult(ctypes.Structure):
+    _fields_ = [
+        ("extremes", ctypes.c_int32 * 4),
+        ("m1", ctypes.c_int64),
+        ("region", ctypes.POINTER(ctypes.c_int8)),
+        ("n_region", ctypes.c_int64 * 4),
+        ("n_kept", ctypes.c_int64 * 4),
+        ("kept", ctypes.POINTER(ctypes.c_int32)),
+        ("m2", ctypes.c_int64),
+        ("h", ctypes.c_int64),
+        ("hull", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -81,6 +95,8 @@ def _load():
         lib.oracle_round2.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_round2.restype = ctypes.c_int
+        lib.oracle_chain.argtypes = [dp, ctypes.c_int64, ctypes.POINTER(_ChainResult)]
+        lib.oracle_chain.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -182,3 +198,33 @@ def learned_round1(xy, dirs) -> dict:
     if st != OK:
         raise OracleError(st)
     return {"keep": keep[:n].astype(bool), "cand": cand, "m1": int(m1.value)}
+
+
+def chain(xy) -> dict:
+    """The four-region variant (see oracle.h): extremes, the region of every
+    point (-1 discarded by round 1, 4 on the quadrilateral's boundary), the
+    kept points per region in walking order, and the canonical hull."""
+    a = _points(xy)
+    n = a.shape[0]
+    m = max(n, 1)
+    reg = np.zeros(m, dtype=np.int8)
+    kept = np.zeros(m, dtype=np.int32)
+    hl = np.zeros(m, dtype=np.int32)
+    r = _ChainResult()
+    r.region = reg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+    r.kept = kept.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    r.hull = hl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    st = _load().oracle_chain(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, ctypes.byref(r))
+    if st != OK:
+        raise OracleError(st)
+    nk = list(r.n_kept)
+    offs = np.cumsum([0] + nk)
+    return {
+        "extremes": list(r.extremes),
+        "m1": int(r.m1),
+        "region": reg[:n].copy(),
+        "n_region": list(r.n_region),
+        "kept": [kept[offs[k]:offs[k + 1]].copy() for k in range(4)],
+        "m2": int(r.m2),
+        "hull": hl[:r.h].copy(),
+    }

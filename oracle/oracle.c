@@ -435,3 +435,142 @@ int oracle_learned_round1(const double* xy, int64_t n, const double* dirs, int32
     *m1 = cnt;
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The four-region variant of Section 5.1 / Table 8 (CudaChain's design, the */
+/* paper's comparison method): the same first round, then the survivors go   */
+/* to four sub-regions, each sorted by one coordinate, and a second round    */
+/* discards by comparing coordinates.                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Region k holds the survivors strictly outside edge k of the cycle
+ * P_minx -> P_miny -> P_maxx -> P_maxy -> P_minx (the first such edge; a
+ * repeated corner makes its edge empty).  In region k the coordinates
+ * rotated by -90 degrees k times, (u, v) = (x, y), (y, -x), (-x, -y), (-y, x)
+ * (negation is exact), put every region in the lower-left position: its
+ * hull chain runs from corner k to corner k+1 with u rising and v falling. */
+static void rot_uv(int k, double x, double y, double* u, double* v) {
+    switch (k & 3) {
+        case 0: *u = x; *v = y; break;
+        case 1: *u = y; *v = -x; break;
+        case 2: *u = -x; *v = -y; break;
+        default: *u = -y; *v = x; break;
+    }
+}
+
+static int g_region;         /* comparator context: the region being sorted */
+
+/* Sorting of one region: u ascending (R0 by x, R1 by y, R2 by x descending,
+ * R3 by y descending), then v ascending, then index. */
+static int cmp_region(const void* pa, const void* pb) {
+    int32_t a = *(const int32_t*)pa, b = *(const int32_t*)pb;
+    double au, av, bu, bv;
+    rot_uv(g_region, g_xy[2 * (int64_t)a], g_xy[2 * (int64_t)a + 1], &au, &av);
+    rot_uv(g_region, g_xy[2 * (int64_t)b], g_xy[2 * (int64_t)b + 1], &bu, &bv);
+    if (au != bu) return au < bu ? -1 : 1;
+    if (av != bv) return av < bv ? -1 : 1;
+    return (a > b) - (a < b);
+}
+
+int oracle_chain(const double* xy, int64_t n, oracle_chain_result* r) {
+    int st = oracle_validate(xy, n);
+    if (st != ORACLE_OK) return st;
+    if (!r || (n > 0 && (!r->region || !r->kept || !r->hull))) return ORACLE_BADARG;
+    r->m1 = 0; r->m2 = 0; r->h = 0;
+    for (int k = 0; k < 4; ++k) { r->extremes[k] = -1; r->n_region[k] = 0; r->n_kept[k] = 0; }
+    if (n == 0) return ORACLE_OK;
+
+    /* first round: Steps 1-2, the same as gScan's */
+    int32_t c[4];
+    extremes(xy, n, c);
+    memcpy(r->extremes, c, sizeof(c));
+    int32_t corner[4];
+    int nc = 0;
+    for (int k = 0; k < 4; ++k) {
+        int dup = 0;
+        for (int j = 0; j < nc; ++j) dup |= same_point(xy, corner[j], c[k]);
+        if (!dup) corner[nc++] = c[k];
+    }
+
+    /* distribution into the four sub-regions (-1: discarded by round 1,
+     * 4: on the quadrilateral's boundary, not strictly outside any edge) */
+    int32_t* lists = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    int32_t* stack = (int32_t*)malloc((size_t)(n + 8) * sizeof(int32_t));
+    if (!lists || !stack) { free(lists); free(stack); return ORACLE_NOMEM; }
+    int64_t m1 = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int inside = nc >= 3;
+        for (int j = 0; j < nc && inside; ++j)
+            inside = orient_idx(xy, corner[j], corner[(j + 1) % nc], (int32_t)i) > 0;
+        int reg = -1;
+        if (!inside) {
+            ++m1;
+            reg = 4;
+            for (int k = 0; k < 4 && reg == 4; ++k)
+                if (orient_idx(xy, c[k], c[(k + 1) & 3], (int32_t)i) < 0) reg = k;
+        }
+        r->region[i] = (int8_t)reg;
+    }
+    r->m1 = m1;
+
+    /* per region: sort by the region's coordinate, then walk it keeping the
+     * running minimum of v; a point is kept only when its v is strictly
+     * below every v before it (a point before it with v no larger lies
+     * towards the region's corner on both axes, so this one is not a
+     * vertex of the region's chain) */
+    int64_t nk = 0;
+    for (int k = 0; k < 4; ++k) {
+        int64_t m = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (r->region[i] == k) lists[m++] = (int32_t)i;
+        r->n_region[k] = m;
+        g_xy = xy;
+        g_region = k;
+        qsort(lists, (size_t)m, sizeof(int32_t), cmp_region);
+        double vmin = INFINITY;
+        int64_t kept = 0;
+        for (int64_t j = 0; j < m; ++j) {
+            double u, v;
+            rot_uv(k, xy[2 * (int64_t)lists[j]], xy[2 * (int64_t)lists[j] + 1], &u, &v);
+            if (v < vmin) {
+                r->kept[nk++] = lists[j];
+                ++kept;
+                vmin = v;
+            }
+        }
+        r->n_kept[k] = kept;
+    }
+    r->m2 = nk + nc;
+
+    /* the final hull (the paper's second stage, on the host): per region a
+     * stack scan of corner k, the kept points in walking order and corner
+     * k+1 (a non-left turn pops, a repeat of the top is skipped): the hull's
+     * chain from corner k to corner k+1.  The chains, each without its last
+     * point (the next chain's first), form the hull from P_minx on. */
+    int64_t h = 0;
+    int64_t at = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int64_t beg = h;
+        for (int64_t j = -1; j <= r->n_kept[k]; ++j) {
+            const int32_t p = j < 0 ? c[k] : j == r->n_kept[k] ? c[(k + 1) & 3] : r->kept[at + j];
+            if (h > beg && same_point(xy, stack[h - 1], p)) continue;
+            while (h - beg >= 2 && orient_idx(xy, stack[h - 2], stack[h - 1], p) <= 0) --h;
+            stack[h++] = p;
+        }
+        at += r->n_kept[k];
+        --h;  /* corner k+1: the next chain starts with it */
+    }
+    if (h == 0) stack[h++] = c[0];  /* one distinct point */
+    /* canonical start: the lexicographically smallest vertex */
+    int64_t start = 0;
+    for (int64_t i = 1; i < h; ++i) {
+        double x = xy[2 * (int64_t)stack[i]], y = xy[2 * (int64_t)stack[i] + 1];
+        double bx = xy[2 * (int64_t)stack[start]], by = xy[2 * (int64_t)stack[start] + 1];
+        if (x < bx || (x == bx && y < by)) start = i;
+    }
+    for (int64_t i = 0; i < h; ++i) r->hull[i] = stack[(start + i) % h];
+    r->h = h;
+    free(lists);
+    free(stack);
+    return ORACLE_OK;
+}

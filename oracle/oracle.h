@@ -91,6 +91,31 @@ int oracle_model(const double* xy, int64_t n, int64_t chunk, oracle_model_result
 int oracle_learned_round1(const double* xy, int64_t n, const double* dirs, int32_t k,
                           uint8_t* keep, int32_t* cand, int64_t* m1);
 
+/* The four-region variant (Section 5.1, Table 8: the comparison method
+ * CudaChain's design, built on Akl and Toussaint's heuristic): Steps 1-2 as
+ * above; every survivor strictly outside edge k of the cycle P_minx ->
+ * P_miny -> P_maxx -> P_maxy goes to region k (the first such edge), the
+ * others (on the quadrilateral's boundary) to none; each region is sorted by
+ * x or y (region k in the coordinates (u, v) rotated by -90 degrees k times:
+ * u ascending, then v, then index) and walked keeping a point only when its
+ * v is strictly below every v before it; the final hull is one stack scan
+ * per region from corner k to corner k+1 over the kept points. */
+typedef struct {
+    int32_t extremes[4];      /* P_minx, P_miny, P_maxx, P_maxy                 */
+    int64_t m1;               /* first-round survivors                          */
+    int8_t* region;           /* [n]: 0..3, 4 = on the boundary, -1 = discarded */
+    int64_t n_region[4];      /* points per region                              */
+    int64_t n_kept[4];        /* points each region keeps                       */
+    int32_t* kept;            /* [n]: kept points, region 0 first, each in its
+                                 walking order                                 */
+    int64_t m2;               /* points given to the final stage: the kept
+                                 points and the distinct corners              */
+    int64_t h;
+    int32_t* hull;            /* [n]: canonical hull                            */
+} oracle_chain_result;
+
+int oracle_chain(const double* xy, int64_t n, oracle_chain_result* r);
+
 #ifdef __cplusplus
 }
 #endif
