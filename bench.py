@@ -99,21 +99,29 @@ def kernel_bytes(stage: str, n: int, ms: int, nc: int, m2: int, full: bool) -> f
     }[stage]
 
 
-def cpu_baseline(sets, sample_n: int):
-    """The oracle (single-threaded C monotone chain) on the first sample_n
-    points of each set, timed on this host."""
+def cpu_baseline(sets, names, reps: int):
+    """The oracle (single-threaded C monotone chain) on the full sets of the
+    workload, timed on this host: the median of `reps` runs per set."""
+    import numpy as np
     import oracle
-    total_pts, total_s = 0, 0.0
-    for pts in sets:
-        s = pts[:sample_n].copy()
-        t0 = time.perf_counter()
-        oracle.hull(s)
-        total_s += time.perf_counter() - t0
-        total_pts += s.shape[0]
+    total_pts, total_s, per = 0, 0.0, {}
+    for nm, pts in zip(names, sets):
+        ts = []
+        for _ in range(max(1, reps)):
+            t0 = time.perf_counter()
+            oracle.hull(pts)
+            ts.append(time.perf_counter() - t0)
+        med = float(np.median(ts))
+        progress(f"oracle on {nm}: {med:.1f} s")
+        per[nm] = round(med, 2)
+        total_s += med
+        total_pts += pts.shape[0]
     return {"value": round(total_pts / total_s / 1e6, 3), "unit": "Mpoints/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"first {sample_n} points of each 20M set ({total_pts} points), "
-                      f"{total_s:.1f} s on {platform.processor() or platform.machine()}"}
+            "sample": f"the full sets {' + '.join(names)} ({total_pts} points), median of "
+                      f"{max(1, reps)} run(s) per set, seconds {per}, on "
+                      f"{platform.processor() or platform.machine()} "
+                      f"({os.cpu_count()} logical CPUs, one used)"}
 
 
 def learned(steps: int):
@@ -129,9 +137,10 @@ def learned(steps: int):
         return None
     d = torch.from_numpy(synth.workload("mixture_20M")).cuda()
     out = {"workload": "mixture_20M", "weights": "paper_1508_05931_amd/weights/filter16.f32"}
-    for key, ctx in (("quad", hx.Hull2D(profile=True)),
-                     ("learned", hx.Hull2D(profile=True, learned=True, weights=w))):
-        ctx.compute(d)
+    hulls = {}
+    for key, ctx in (("quad", hx.Hull2D(profile=2)),
+                     ("learned", hx.Hull2D(profile=2, learned=True, weights=w))):
+        hulls[key] = ctx.compute(d)
         torch.cuda.synchronize()
         reps = max(3, steps // 2)
         ts = []
@@ -143,8 +152,9 @@ def learned(steps: int):
         ms = float(np.median(ts)) * 1e3
         out[key] = {"ms_median": round(ms, 4), "Mpoints_per_s": round(d.shape[0] / (ms * 1e-3) / 1e6, 1),
                     "survivors_round1": int(st.n_round1), "n_hull": int(st.n_hull),
-                    "ms_learned_stage": round(float(st.ms_stage["learned"]), 4)}
+                    "survivors_round2": int(st.n_round2), "sorted_for_round2": int(st.n_candidates)}
         ctx.close()
+    out["identical_output"] = bool(np.array_equal(hulls["quad"], hulls["learned"]))
     return out
 
 
@@ -188,6 +198,103 @@ def batched(steps: int):
                              "Mpoints_per_s": round(offs[-1] / (loop_ms * 1e-3) / 1e6, 1)}}
 
 
+def profiled_pass(hx, names, host, dev, reps: int, warmup: int, **kw):
+    """Per-kernel device times from a pass with one HIP event per stage
+    (outside any timed region; the events cost the stream a little), and each
+    kernel's algorithmic bytes for the sizes of that call."""
+    import numpy as np
+    pctx = hx.Hull2D(profile=1, **kw)
+    for _ in range(max(1, warmup)):
+        for d in dev:
+            pctx.compute(d)
+    stage_ms = {nm: {k: [] for k in KERNEL_STAGES + ["d2h", "host_scan"]} for nm in names}
+    pstats = {}
+    for _ in range(max(3, reps)):
+        for nm, d in zip(names, dev):
+            pctx.compute(d)
+            pstats[nm] = pctx.last_stats
+            for k in stage_ms[nm]:
+                stage_ms[nm][k].append(pstats[nm].ms_stage[k])
+    pctx.close()
+    full = bool(kw.get("full_sort") or kw.get("round2_chunk", 0) != 0)
+    kern = {}
+    for k in KERNEL_STAGES:
+        ms_sum, bytes_sum = 0.0, 0.0
+        for nm, a in zip(names, host):
+            st = pstats[nm]
+            ms_sum += float(np.mean(stage_ms[nm][k]))
+            bytes_sum += kernel_bytes(k, a.shape[0], st.n_sorted, st.n_candidates,
+                                      st.n_round2 - 1, full)
+        kern[k] = {"ms": ms_sum / len(names), "bytes": bytes_sum / len(names)}
+    # filter + sort segment (Steps 1-7): the kernels that ran, their
+    # algorithmic bytes (what those kernels must move), and the bytes of the
+    # method's own formula for comparison
+    seg_ms, seg_bytes, formula = 0.0, 0.0, 0.0
+    for nm, a in zip(names, host):
+        st = pstats[nm]
+        n = a.shape[0]
+        for k in KERNEL_STAGES:
+            ms = float(np.mean(stage_ms[nm][k]))
+            seg_ms += ms
+            if ms > 0.0:
+                seg_bytes += kernel_bytes(k, n, st.n_sorted, st.n_candidates, st.n_round2 - 1, full)
+        formula += 32.0 * n + 80.0 * st.n_round1 + 20.0 * st.n_round2
+    seg = {"ms_per_hull": round(seg_ms / len(names), 4),
+           "bytes_run_per_hull": round(seg_bytes / len(names)),
+           "GBps_run": round(seg_bytes / (seg_ms * 1e-3) / 1e9, 1),
+           "frac_of_peak": round(seg_bytes / (seg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "bytes_formula_per_hull": round(formula / len(names)),
+           "GBps_formula": round(formula / (seg_ms * 1e-3) / 1e9, 1),
+           "formula": "32n + 80*round1 + 20*round2 (every survivor written, sorted, walked)"}
+    return kern, pstats, stage_ms, seg
+
+
+def dominant(kern, ms_override=None):
+    """The kernel with the longest average duration, and its roofline."""
+    dom = max(KERNEL_STAGES, key=lambda k: kern[k]["ms"])
+    dom_ms = kern[dom]["ms"] if ms_override is None or dom not in ms_override else ms_override[dom]
+    achieved = kern[dom]["bytes"] / (dom_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": measured_traffic(dom), "algorithmic_bytes": round(kern[dom]["bytes"]),
+            "ms_per_launch": round(dom_ms, 4),
+            "ms_from": "timed region" if ms_override and dom in ms_override else "profiled pass"}
+
+
+def timed_sets(hx, names, dev, steps: int, warmup: int, **kw):
+    """Median wall time of hull2d_compute per set and the last call's stats."""
+    import numpy as np
+    import torch
+    ctx = hx.Hull2D(**kw)
+    for _ in range(max(1, warmup)):
+        for d in dev:
+            ctx.compute(d)
+    torch.cuda.synchronize()
+    out = {}
+    for nm, d in zip(names, dev):
+        ts = []
+        for _ in range(max(1, steps)):
+            t0 = time.perf_counter()
+            ctx.compute(d)
+            ts.append(time.perf_counter() - t0)
+        st = ctx.last_stats
+        ms = float(np.median(ts)) * 1e3
+        n = int(d.shape[0])
+        out[nm] = {"n": n, "h": int(st.n_hull), "ms_median": round(ms, 4),
+                   "Mpoints_per_s": round(n / (ms * 1e-3) / 1e6, 1),
+                   "survivors_round1": round(st.n_round1 / n, 5),
+                   "survivors_round2": round(st.n_round2 / n, 7),
+                   "sorted_for_round2": int(st.n_candidates),
+                   "ms_host_scan": round(float(st.ms_stage["host_scan"]), 4)}
+    ctx.close()
+    return out
+
+
+def progress(msg: str):
+    """A line on stderr after each leg (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,12 +305,15 @@ def main():
                     help="sort every round-1 survivor (Step 4 as printed)")
     ap.add_argument("--no-full-sort-line", action="store_true",
                     help="skip the extra timing of the full-sort mode")
-    ap.add_argument("--cpu-sample", type=int, default=5_000_000)
+    ap.add_argument("--cpu-reps", type=int, default=1,
+                    help="oracle runs per 20M set for cpu_baseline (median)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-filter comparison on the 20M mixture")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the timing of the batched form (4096 sets)")
+    ap.add_argument("--no-adversarial", action="store_true",
+                    help="skip the adversarial workloads (annulus + 2^20-gon, integer grid)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 320 MB device buffer three times (reference for HBM "
                          "byte counters) and exit")
@@ -234,25 +344,13 @@ def main():
     dev = [torch.from_numpy(a).cuda() for a in host]
     torch.cuda.synchronize()
     full = bool(args.full_sort or args.round2_chunk != 0)
-    # Stage breakdown from a profiled pass outside the timed region (one HIP
-    # event per stage; the events themselves cost the stream a little).
-    pctx = hx.Hull2D(round2_chunk=args.round2_chunk, profile=1, full_sort=args.full_sort)
-    for _ in range(max(1, args.warmup)):
-        for d in dev:
-            pctx.compute(d)
-    stage_ms = {nm: {k: [] for k in KERNEL_STAGES + ["d2h", "host_scan"]} for nm in names}
-    pstats = {}
-    for _ in range(max(3, args.steps // 4)):
-        for nm, d in zip(names, dev):
-            pctx.compute(d)
-            pstats[nm] = pctx.last_stats
-            for k in stage_ms[nm]:
-                stage_ms[nm][k].append(pstats[nm].ms_stage[k])
-    pctx.close()
+    mode = dict(round2_chunk=args.round2_chunk, full_sort=args.full_sort)
+    kern, pstats, stage_ms, seg = profiled_pass(hx, names, host, dev, args.steps // 4, args.warmup,
+                                                **mode)
 
     # The timed region: events only around Step 1 and Steps 2-3, the two
     # streaming passes over the input (the dominant kernel is one of them).
-    ctx = hx.Hull2D(round2_chunk=args.round2_chunk, profile=2, full_sort=args.full_sort)
+    ctx = hx.Hull2D(profile=2, **mode)
     for _ in range(args.warmup):
         for d in dev:
             ctx.compute(d)
@@ -269,38 +367,20 @@ def main():
             per_set[nm]["filter1"].append(st.ms_stage["filter1"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    ctx.close()
 
     n_total = sum(a.shape[0] for a in host)
     ms_per_step = elapsed * 1e3 / args.steps
     value = n_total / (ms_per_step * 1e-3) / 1e6
-
-    # per-kernel averages (profiled pass), and the dominant kernel's duration
-    # from the timed region when it is one of the two timed there
-    kern = {}
-    for k in KERNEL_STAGES:
-        ms_sum, bytes_sum = 0.0, 0.0
-        for nm, a in zip(names, host):
-            st = pstats[nm]
-            ms_sum += float(np.mean(stage_ms[nm][k]))
-            bytes_sum += kernel_bytes(k, a.shape[0], st.n_sorted, st.n_candidates,
-                                      st.n_round2 - 1, full)
-        kern[k] = {"ms": ms_sum / len(names), "bytes": bytes_sum / len(names)}
-    dom = max(KERNEL_STAGES, key=lambda k: kern[k]["ms"])
-    dom_ms = kern[dom]["ms"]
-    timed_in_region = dom in ("extremes", "filter1")
-    if timed_in_region:
-        dom_ms = float(np.mean([np.mean(per_set[nm][dom]) for nm in names]))
-    achieved = kern[dom]["bytes"] / (dom_ms * 1e-3) / 1e9
+    timed = {k: float(np.mean([np.mean(per_set[nm][k]) for nm in names]))
+             for k in ("extremes", "filter1")}
+    roof = dominant(kern, timed)
+    progress(f"timed region done: {value:.0f} Mpoints/s")
 
     sets_out = {}
-    fs_bytes, fs_ms = 0.0, 0.0
     for nm, a in zip(names, host):
         st = per_set[nm]["stats"]
         n = a.shape[0]
-        t_fs = sum(float(np.mean(stage_ms[nm][k])) for k in KERNEL_STAGES)
-        b_alg = 32.0 * n + 80.0 * st.n_round1 + 20.0 * st.n_round2
-        fs_bytes += b_alg
-        fs_ms += t_fs
         sets_out[nm] = {
             "n": n, "h": st.n_hull,
             "ms_median": round(float(np.median(per_set[nm]["ms"])), 4),
@@ -308,7 +388,7 @@ def main():
             "survivors_round1": round(st.n_round1 / n, 5),
             "survivors_round2": round(st.n_round2 / n, 7),
             "sorted_for_round2": st.n_candidates,
-            "ms_filter_sort": round(t_fs, 4),
+            "ms_filter_sort": round(sum(float(np.mean(stage_ms[nm][k])) for k in KERNEL_STAGES), 4),
             "ms_d2h": round(float(np.mean(stage_ms[nm]["d2h"])), 4),
             "ms_host_scan": round(float(np.mean(stage_ms[nm]["host_scan"])), 4),
         }
@@ -332,22 +412,15 @@ def main():
                    else f"subsets ({args.round2_chunk})",
                    "sort": "every round-1 survivor" if full else
                    "candidates of the bucketed filter"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": measured_traffic(dom),
-                     "algorithmic_bytes": round(kern[dom]["bytes"]),
-                     "ms_per_launch": round(dom_ms, 4),
-                     "ms_from": "timed region" if timed_in_region else "profiled pass"},
-        "filter_sort": {"GBps_alg": round(fs_bytes / (fs_ms * 1e-3) / 1e9, 1),
-                        "frac_of_peak": round(fs_bytes / (fs_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                        "bytes_alg_formula": "32n + 80*round1 + 20*round2"},
+        "roofline": roof,
+        "filter_sort": seg,
         "kernels_ms": {k: round(v["ms"], 4) for k, v in kern.items()},
         "sets": sets_out,
     }
-    ctx.close()
     if not full and not args.no_full_sort_line:
-        # the paper's Step 4 as printed: every round-1 survivor sorted
+        # the paper's Step 4 as printed: every round-1 survivor sorted; its
+        # own per-kernel breakdown, roofline and segment figures
+        fk, _, _, fseg = profiled_pass(hx, names, host, dev, args.steps // 4, 1, full_sort=True)
         fctx = hx.Hull2D(full_sort=True)
         for d in dev:
             fctx.compute(d)
@@ -359,15 +432,35 @@ def main():
                 fctx.compute(d)
         torch.cuda.synchronize()
         fms = (time.perf_counter() - t1) * 1e3 / reps
-        out["full_sort"] = {"ms_per_step": round(fms, 4),
-                            "Mpoints_per_s": round(n_total / (fms * 1e-3) / 1e6, 1)}
         fctx.close()
+        out["full_sort"] = {"ms_per_step": round(fms, 4),
+                            "Mpoints_per_s": round(n_total / (fms * 1e-3) / 1e6, 1),
+                            "roofline": dominant(fk), "filter_sort": fseg,
+                            "kernels_ms": {k: round(v["ms"], 4) for k, v in fk.items()}}
+        progress("full-sort leg done")
+    if not args.no_adversarial:
+        # the all-extreme limitation the paper discusses (Section 5.3) and
+        # exact ties: 10M annulus points + 10M vertices of a 2^20-gon, and a
+        # 500 x 500 integer grid with every cell four times
+        adv_names = ["annulus_ngon_20M", "grid_500x4"]
+        adv_dev = [torch.from_numpy(synth.workload(nm)).cuda() for nm in adv_names]
+        adv = timed_sets(hx, adv_names, adv_dev, max(3, args.steps // 4), 1)
+        # the annulus is where the sort and round 2 see ~10M points
+        ak, _, _, aseg = profiled_pass(hx, adv_names[:1], adv_dev[:1], adv_dev[:1], 1, 1)
+        adv["annulus_ngon_20M"].update({"roofline": dominant(ak), "filter_sort": aseg,
+                                        "kernels_ms": {k: round(v["ms"], 4) for k, v in ak.items()}})
+        out["adversarial"] = adv
+        progress("adversarial leg done")
+        del adv_dev
+        torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = batched(args.steps)
+        progress("batched leg done")
     if not args.no_learned:
         out["learned_filter"] = learned(args.steps)
+        progress("learned leg done")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(host, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(host, names, args.cpu_reps)
     print(json.dumps(out), flush=True)
 
 

@@ -3,8 +3,7 @@
  *
  * The data-parallel first stage of gScan (G. Mei, "gScan: Accelerating
  * Graham Scan on the GPU", Sections 2 and 3) as hand-written HIP kernels,
- * followed by the paper's final stack scan (Step 8; on the host for one hull,
- * on the device in the batched form):
+ * followed by the paper's final stack scan (Step 8, on the device):
  *
  *   Step 1  four extreme points by parallel reduction           (Section 3.1)
  *   Step 2  discard points strictly inside their quadrilateral  (Section 3.1)
@@ -12,7 +11,8 @@
  *   Step 4  sort of the survivors by exact angle                 (Section 3.3)
  *   Step 5-6 farthest point P_l splits the sorted list          (Section 2.1)
  *   Step 7  second-round filter per region (Figure 2)           (Section 3.4)
- *   Step 8  Graham stack scan of the kept points (host)         (Section 3)
+ *   Step 8  stack scan of the kept points, as chains of pieces
+ *           joined at their common tangents                      (Section 3)
  *
  * Input: n points as float64 [n][2] (x, y interleaved) in device memory.
  * Output: the canonical hull as int32 input indices in host memory:
@@ -102,6 +102,20 @@ typedef struct {
      * set count, the points' address and the workspace stay the same;
      * 0: plain stream work every call.  The results are identical. */
     int32_t batch_graph;
+    /* 0 (default): gScan, Steps 1-8 as above.  1: the four-region variant of
+     * Section 5.1 (Table 8's comparison method): Steps 1-2, then every
+     * survivor strictly outside edge k of the cycle P_minx -> P_miny -> P_maxx
+     * -> P_maxy (the first such edge) goes to region k, which is ordered by
+     * one coordinate (x, y, -x, -y for k = 0..3; ties by the other, negated
+     * for k = 1, 2: (u, v) = (x, y), (y, -x), (-x, -y), (-y, x), then index)
+     * and walked keeping a point only when its v is strictly below every v
+     * before it; the hull is one stack scan per region from corner k over the
+     * kept points to corner k+1 (on the host, as the variant's second stage).
+     * Same canonical output.  Only the candidates (v below the minimum of
+     * every earlier one of 4096 buckets of u) are sorted and walked, which
+     * keeps the same points.  round2_chunk, full_sort and filter do not
+     * apply. */
+    int32_t method;
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */
@@ -123,7 +137,8 @@ enum {
     HULL2D_STAGE_TAIL,           /* Steps 4, 6-7 on a small candidate set, one workgroup */
     HULL2D_STAGE_LEARNED,        /* learned filter: histogram, network, polygon     */
     HULL2D_STAGE_D2H,            /* copy of the kept points to the host             */
-    HULL2D_STAGE_HOST_SCAN,      /* Step 8 on the host (wall clock)                 */
+    HULL2D_STAGE_HOST_SCAN,      /* Step 8 on the host (wall clock; 0 when the device finished it) */
+    HULL2D_STAGE_SCAN,           /* Step 8 on the device                            */
     HULL2D_NUM_STAGES
 };
 
@@ -225,6 +240,14 @@ hull2d_status hull2d_train_step(hull2d_ctx* ctx, const float* d_x, const float* 
 hull2d_status hull2d_debug_learned(hull2d_ctx* ctx, double* dirs, int32_t* cand, float* y,
                                    int32_t* nv);
 
+/* The last hull2d_compute with method = 1: counts[14] = {m1, survivors in
+ * regions 0-3, candidates in regions 0-3, kept points in regions 0-3, m2 (kept
+ * points plus distinct corners)}, and kept[cap] the kept points' input
+ * indices, region 0 first, each region in walking order.  Any pointer may be
+ * NULL.  CAPACITY if cap is smaller than the kept points; INVALID_ARG if the
+ * last call did not use the variant. */
+hull2d_status hull2d_debug_chain(hull2d_ctx* ctx, int64_t* counts, int32_t* kept, int64_t cap);
+
 /* ---- Checking entry points (exact predicates on the device) ------------ */
 
 /* out[i] = sign of (b - a) x (c - a) for triple i, computed by the device
@@ -253,6 +276,13 @@ hull2d_status hull2d_debug_angle_key(hull2d_ctx* ctx, const double* d_xy, int64_
  * CAPACITY if cap is smaller than n_sorted or n_round2. */
 hull2d_status hull2d_debug_stages(hull2d_ctx* ctx, int32_t* extremes, int32_t* sorted,
                                   int32_t* round2, int64_t cap, int64_t* counts);
+
+/* The round-1 survivors of the last hull2d_compute on this context (Step 2,
+ * Section 3.1; with filter = 1 the learned polygon's survivors): their input
+ * indices in ascending order, copies of the pivot P_0 excluded.  idx: host,
+ * cap entries; *n_out receives the count.  CAPACITY if cap is smaller (then
+ * idx is untouched); INVALID_ARG if no compute call has run yet. */
+hull2d_status hull2d_debug_round1(hull2d_ctx* ctx, int32_t* idx, int64_t cap, int64_t* n_out);
 
 #ifdef __cplusplus
 }

@@ -8,9 +8,12 @@ functions raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import json
 import os
+import sys
+import weakref
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -28,13 +31,13 @@ OK, INVALID_ARG, NONFINITE, RANGE, CAPACITY, OUT_OF_MEMORY, DEVICE, WEIGHTS, UNI
 
 STAGES = ["extremes", "extremes_final", "filter1", "longest", "histogram", "sort0", "sort1",
           "sort2", "sort3", "ties", "ties_long", "buckets", "round2", "compact", "tail",
-          "learned", "d2h", "host_scan"]
+          "learned", "d2h", "host_scan", "scan"]
 
 EXPORTED = ["hull2d_create", "hull2d_compute", "hull2d_batch", "hull2d_destroy",
             "hull2d_status_string", "hull2d_set_weights", "hull2d_load_weights",
             "hull2d_get_weights", "hull2d_histogram", "hull2d_mlp_infer", "hull2d_train_step",
             "hull2d_debug_learned", "hull2d_debug_orient", "hull2d_debug_angle_key",
-            "hull2d_debug_stages"]
+            "hull2d_debug_stages", "hull2d_debug_round1", "hull2d_debug_chain"]
 
 MLP_PARAMS = 336416  # HULL2D_MLP_PARAMS
 
@@ -49,7 +52,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("round2_chunk", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("full_sort", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("batch_blocks_per_cu", ctypes.c_int32),
-                ("batch_order", ctypes.c_int32), ("batch_graph", ctypes.c_int32)]
+                ("batch_order", ctypes.c_int32), ("batch_graph", ctypes.c_int32),
+                ("method", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -62,6 +66,25 @@ class _Stats(ctypes.Structure):
 
 
 _lib = None
+
+# Every open context, so that the ones still open when the interpreter exits
+# are destroyed while the HIP runtime is still up (see _close_all).
+_live: "weakref.WeakSet[Hull2D]" = weakref.WeakSet()
+_atexit_registered = False
+
+
+def _close_all():
+    """Destroys every context still open.  Registered with atexit when the
+    first context is created, which is after torch (and with it the HIP
+    runtime) has been loaded, so it runs before their teardown: destroying a
+    context synchronises its stream and frees device and pinned memory, which
+    must not happen once the runtime has been finalised."""
+    for ctx in list(_live):
+        try:
+            ctx.close()
+        except Exception:
+            pass
+    _default.clear()
 
 
 def load_library():
@@ -93,6 +116,10 @@ def load_library():
     lib.hull2d_debug_stages.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                         ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
     lib.hull2d_debug_stages.restype = ctypes.c_int
+    lib.hull2d_debug_round1.argtypes = [vp, ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
+    lib.hull2d_debug_round1.restype = ctypes.c_int
+    lib.hull2d_debug_chain.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), i64]
+    lib.hull2d_debug_chain.restype = ctypes.c_int
     fp = ctypes.POINTER(ctypes.c_float)
     lib.hull2d_set_weights.argtypes = [vp, fp, i64]
     lib.hull2d_set_weights.restype = ctypes.c_int
@@ -165,7 +192,7 @@ class Hull2D:
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
                  profile: int = 0, full_sort: bool = False, learned: bool = False,
                  weights=None, batch_graph: bool = True, batch_blocks_per_cu: int | None = None,
-                 batch_order: int | None = None):
+                 batch_order: int | None = None, method: int = 0):
         import torch
         lib = load_library()
         if device is None:
@@ -181,7 +208,7 @@ class Hull2D:
             batch_order = tuned.get("batch_order", 0)
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
                        int(bool(full_sort)), int(bool(learned)), int(batch_blocks_per_cu),
-                       int(batch_order), int(bool(batch_graph)))
+                       int(batch_order), int(bool(batch_graph)), int(method))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))
@@ -189,6 +216,11 @@ class Hull2D:
             raise HullError(st, "hull2d_create")
         self._h = h
         self._lib = lib
+        global _atexit_registered
+        _live.add(self)
+        if not _atexit_registered:
+            atexit.register(_close_all)
+            _atexit_registered = True
         self.last_stats: Stats | None = None
         self._out = np.empty(1024, dtype=np.int32)
         if weights is not None:
@@ -203,6 +235,10 @@ class Hull2D:
             self._h = None
 
     def __del__(self):
+        # During interpreter shutdown the HIP runtime may already be gone:
+        # contexts open at exit are destroyed by the atexit hook, never here.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -347,6 +383,35 @@ class Hull2D:
         return {"extremes": ext.tolist(), "sorted": srt[:ns].copy() if have_sorted else None,
                 "l": l, "round2": r2[:m2].copy(), "longest": longest, "m2": m2,
                 "n_sorted": ns, "n_candidates": ncand}
+
+    def round1_survivors(self) -> np.ndarray:
+        """Input indices (ascending) of the last compute's round-1 survivors,
+        copies of the pivot excluded."""
+        cap = max(int(self.last_stats.n) if self.last_stats else 0, 1)
+        out = np.empty(cap, dtype=np.int32)
+        n = ctypes.c_int64(0)
+        st = self._lib.hull2d_debug_round1(self._h, _i32p(out), cap, ctypes.byref(n))
+        if st != OK:
+            raise HullError(st, "hull2d_debug_round1")
+        return out[:n.value].copy()
+
+    def chain_info(self) -> dict:
+        """Counts and kept lists of the last compute with method=1 (the
+        four-region variant)."""
+        counts = np.zeros(14, dtype=np.int64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        st = self._lib.hull2d_debug_chain(self._h, counts.ctypes.data_as(i64p), None, 0)
+        if st != OK:
+            raise HullError(st, "hull2d_debug_chain")
+        nk = [int(v) for v in counts[9:13]]
+        kept = np.zeros(max(sum(nk), 1), dtype=np.int32)
+        st = self._lib.hull2d_debug_chain(self._h, None, _i32p(kept), kept.shape[0])
+        if st != OK:
+            raise HullError(st, "hull2d_debug_chain")
+        offs = np.cumsum([0] + nk)
+        return {"m1": int(counts[0]), "n_region": [int(v) for v in counts[1:5]],
+                "n_cand": [int(v) for v in counts[5:9]], "n_kept": nk, "m2": int(counts[13]),
+                "kept": [kept[offs[k]:offs[k + 1]].copy() for k in range(4)]}
 
     def debug_orient(self, abc) -> "np.ndarray":
         import torch

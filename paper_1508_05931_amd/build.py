@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libhull2d.so")
 
 SOURCES = ["kernels_filter.hip", "kernels_sort.hip", "kernels_bucket.hip", "kernels_tail.hip",
-           "kernels_batch.hip", "kernels_learned.hip", "hull2d_api.cpp"]
+           "kernels_batch.hip", "kernels_learned.hip", "kernels_scan.hip", "kernels_chain.hip", "hull2d_api.cpp"]
 
 # Contraction off: the exact predicates need every a*b+c rounded twice unless
 # fma() is written out.  Packed fp32 instructions are not generated.

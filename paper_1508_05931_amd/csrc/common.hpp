@@ -37,6 +37,13 @@ constexpr uint32_t kTailDone = 0u;
 constexpr uint32_t kTailOverflow = 1u;
 constexpr uint32_t kTailUnset = 0xFFFFFFFFu;  // host side: not yet written by the tail
 
+// State of the device's Step 8 (k_scan), as the host copy of the candidate
+// status reports it.
+constexpr uint32_t kScanNone = 0u;      // not run (the tail gave up)
+constexpr uint32_t kScanDone = 1u;      // the hull is in host memory
+constexpr uint32_t kScanOverflow = 2u;  // the parts' chains did not fit: the host scans
+constexpr uint32_t kScanUnset = 0xFFFFFFFFu;  // host side: not yet written
+
 constexpr uint32_t kFlagNonfinite = 1u;
 constexpr uint32_t kFlagRange = 2u;
 
@@ -55,6 +62,8 @@ struct DevStatus {
     uint32_t n_right;     // points before P_l in angular order (bucketed filter)
     uint32_t tail_state;  // candidate problem: kTailDone, or kTailOverflow (too large for
                           // the one-workgroup tail; the multi-kernel path runs instead)
+    uint32_t n_hull;      // host copy only: hull vertices found by the device scan (Step 8)
+    uint32_t scan_state;  // host copy only: kScanNone, kScanDone or kScanOverflow
     int32_t ext[4];
     int32_t p0_idx, l_idx;
     double x0, y0;
@@ -71,6 +80,7 @@ enum TicketId {
     kTicketRound2 = 4,
     kTicketCompact = 5,
     kTicketBatch = 7,
+    kTicketScan = 8,
 };
 
 constexpr int kBucketBits = 12;                 // coarse angle buckets of the bucketed round 2

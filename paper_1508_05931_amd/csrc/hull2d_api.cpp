@@ -18,17 +18,15 @@
 
 using namespace hx;
 
-struct hull2d_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    hull2d_options opt{};
-    int cu_count = 256;
-    Occupancy occ;
-    bool broken = false;
+// A point of the four-region variant's final stage on the host.
+struct HostPt {
+    double x, y;
+    int32_t i;
+};
 
-    // device workspace (grows on demand)
-    int64_t cap_n = -1;
-    char* dmem = nullptr;
+// The device buffers of one hull2d_compute call, carved out of one block of
+// device memory (the context's own allocation, grown on demand).
+struct Workspace {
     Cand* partial = nullptr;
     Params* prm = nullptr;
     DevStatus* ds = nullptr;
@@ -37,6 +35,7 @@ struct hull2d_ctx {
     uint32_t* comp_idx = nullptr;
     uint32_t *keys_a = nullptr, *keys_b = nullptr, *vals_a = nullptr, *vals_b = nullptr;
     uint64_t* stat = nullptr;
+    size_t stat_bytes = 0;
     uint32_t* long_list = nullptr;
     uint32_t* huge_list = nullptr;
     uint8_t* keep = nullptr;
@@ -54,7 +53,26 @@ struct hull2d_ctx {
     uint32_t* seg_off = nullptr;
     double* blk_d2 = nullptr;
     uint32_t* blk_best = nullptr;
-    int parts = 0;  // blocks of k_bucket_max
+    uint32_t* part_len = nullptr;  // device Step 8: chain length of each part
+    ChainTables chain{};           // the four-region variant
+    // epoch counter of the look-back words in `stat` (a word is ready only
+    // for the epoch that wrote it)
+    uint32_t* epoch = nullptr;
+};
+
+struct hull2d_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hull2d_options opt{};
+    int cu_count = 256;
+    Occupancy occ;
+    bool broken = false;
+
+    // device workspace (grows on demand)
+    int64_t cap_n = -1;
+    char* dmem = nullptr;
+    Workspace own{};
+    uint32_t own_epoch = 0;
     Counters* ctr = nullptr;  // separate allocation, zeroed once, persists
 
     // pinned host buffers (h_ds holds the two problem statuses; the tail
@@ -63,8 +81,10 @@ struct hull2d_ctx {
     DevStatus* h_ds_dev = nullptr;
     double2* h_xy = nullptr;
     int32_t* h_idx = nullptr;
+    int32_t* h_hull = nullptr;     // the hull written by the device Step 8
     double2* h_xy_dev = nullptr;   // the same buffers as the device addresses them
     int32_t* h_idx_dev = nullptr;
+    int32_t* h_hull_dev = nullptr;
     int64_t h_cap = 0;
 
     uint32_t epoch = 0;
@@ -74,6 +94,16 @@ struct hull2d_ctx {
     hipEvent_t ev_sync = nullptr;  // spin-waited: a sleeping wait can add milliseconds
     std::vector<int64_t> stk;      // host scan buffers, reused across calls
     std::vector<int32_t> hull;
+    std::vector<uint32_t> huge_host;  // the list of over-long equal-key runs
+    // four-region variant: what its last kernel leaves in host memory, the
+    // kept lists that did not fit there, the final stage's stack
+    ChainHost* h_chain = nullptr;
+    ChainHost* h_chain_dev = nullptr;
+    std::vector<double2> chain_xy;
+    std::vector<int32_t> chain_ix;
+    std::vector<HostPt> cstk;
+    bool last_chain = false;
+    ChainHost last_chain_host{};
 
     // batched form: workspace over all points of a batch, per-set results
     int64_t bcap_n = -1;
@@ -125,8 +155,11 @@ struct hull2d_ctx {
 
     // the last compute call, for hull2d_debug_stages
     bool have_last = false;
+    Workspace last_ws{};
     bool last_full = false;
+    bool last_tail = false;  // the one-workgroup tail finished the last call
     int64_t last_n = 0;
+    int last_segs = 0;  // round-1 segments of the last call
     DevStatus last_ds{}, last_ds2{};
 };
 
@@ -134,22 +167,23 @@ namespace {
 
 constexpr int kMaxSegs = 8192;  // round-1 blocks (resident blocks of the whole chip) at most
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t cdiv(size_t a, size_t b) { return (a + b - 1) / b; }
+constexpr size_t smax(size_t a, size_t b) { return a > b ? a : b; }
 
 struct Layout {
-    size_t off[27];
+    size_t off[29];
     size_t total;
 };
 
-Layout plan(int64_t n) {
+// Offsets of the workspace arrays for inputs of up to n points.
+constexpr Layout plan(int64_t n) {
     const size_t N = (size_t)(n > 0 ? n : 1);
-    const size_t sort_tiles = (size_t)ceil_div((int64_t)N, kSortTile);
-    const size_t f1_tiles = (size_t)ceil_div((int64_t)N, kF1Tile);
-    size_t stat_words = sort_tiles * 256;
-    stat_words = std::max(stat_words, f1_tiles + 2);
-    stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kR2Tile) + 4);
-    stat_words = std::max(stat_words, (size_t)ceil_div((int64_t)N, kCpTile) + 2);
-    const size_t sizes[27] = {
+    size_t stat_words = cdiv(N, kSortTile) * 256;
+    stat_words = smax(stat_words, cdiv(N, kF1Tile) + 2);
+    stat_words = smax(stat_words, cdiv(N, kR2Tile) + 4);
+    stat_words = smax(stat_words, cdiv(N, kCpTile) + 2);
+    const size_t sizes[29] = {
         (size_t)kExtGridMax * 4 * sizeof(Cand),      // 0 partial
         sizeof(Params),                              // 1
         2 * sizeof(DevStatus),                       // 2 round-1 problem, candidate problem
@@ -176,15 +210,60 @@ Layout plan(int64_t n) {
         (size_t)kMaxSegs * sizeof(uint32_t),         // 23 seg_count
         (size_t)kMaxSegs * sizeof(uint32_t),         // 24 seg_off
         N * sizeof(uint32_t),                        // 25 cand_kap
-        2 * (size_t)kTailCap * sizeof(uint16_t) + 2 * sizeof(uint32_t)};  // 26 tail slots, counts
+        2 * (size_t)kTailCap * sizeof(uint16_t) + 2 * sizeof(uint32_t),  // 26 tail slots, counts
+        (size_t)kScanMaxParts * sizeof(uint32_t),    // 27 part_len (device Step 8)
+        kChainTableBytes};                           // 28 tables of the four-region variant
     Layout L{};
     size_t o = 0;
-    for (int i = 0; i < 27; ++i) {
+    for (int i = 0; i < 29; ++i) {
         L.off[i] = o;
         o = align_up(o + sizes[i], 256);
     }
     L.total = o;
     return L;
+}
+
+// Points the workspace arrays into `b`, laid out for up to n points.
+void carve(char* b, int64_t n, Workspace& w) {
+    const Layout L = plan(n);
+    w.partial = (Cand*)(b + L.off[0]);
+    w.prm = (Params*)(b + L.off[1]);
+    w.ds = (DevStatus*)(b + L.off[2]);
+    w.hist = (uint32_t*)(b + L.off[3]);
+    w.comp_xy = (double2*)(b + L.off[4]);
+    w.comp_idx = (uint32_t*)(b + L.off[5]);
+    w.keys_a = (uint32_t*)(b + L.off[6]);
+    w.keys_b = (uint32_t*)(b + L.off[7]);
+    w.vals_a = (uint32_t*)(b + L.off[8]);
+    w.vals_b = (uint32_t*)(b + L.off[9]);
+    w.stat = (uint64_t*)(b + L.off[10]);
+    w.stat_bytes = L.off[11] - L.off[10];
+    w.blk_d2 = (double*)(b + L.off[11]);
+    w.blk_best = (uint32_t*)(b + L.off[12]);
+    w.long_list = (uint32_t*)(b + L.off[13]);
+    w.huge_list = (uint32_t*)(b + L.off[14]);
+    w.keep = (uint8_t*)(b + L.off[15]);
+    w.out_xy = (double2*)(b + L.off[16]);
+    w.out_idx = (int32_t*)(b + L.off[17]);
+    w.cand_xy = (double2*)(b + L.off[18]);
+    w.cand_idx = (uint32_t*)(b + L.off[19]);
+    w.cand_key = (uint32_t*)(b + L.off[20]);
+    w.bmax = (uint32_t*)(b + L.off[21]);
+    w.prefix = (uint32_t*)(b + L.off[22]);
+    w.seg_count = (uint32_t*)(b + L.off[23]);
+    w.seg_off = (uint32_t*)(b + L.off[24]);
+    w.cand_kap = (uint32_t*)(b + L.off[25]);
+    w.tail_slot = (uint16_t*)(b + L.off[26]);
+    w.tail_count = (uint32_t*)(b + L.off[26] + 2 * (size_t)kTailCap * sizeof(uint16_t));
+    w.part_len = (uint32_t*)(b + L.off[27]);
+    char* t = b + L.off[28];
+    const size_t B4 = 4 * (size_t)kChainBuckets;
+    w.chain.bmin = (uint64_t*)t;
+    w.chain.prefix = (double*)(t + B4 * 8);
+    w.chain.count = (uint32_t*)(t + B4 * 16);
+    w.chain.cursor = (uint32_t*)(t + B4 * 20);
+    w.chain.offset = (uint32_t*)(t + B4 * 24);
+    w.chain.st = (ChainStatus*)(t + align_up(B4 * 28 + 4, 64));
 }
 
 hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
@@ -197,47 +276,16 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
         c->dmem = nullptr;
         c->cap_n = -1;
     }
-    // blocks of the sampled bucket maxima: each folds up to 2 x 4096 table
-    // entries into the shared table with atomics; one per compute unit
-    // measured best (64, 128 and 256 blocks tried)
-    c->parts = std::max(1, c->cu_count);
-    Layout L = plan(want);
+    const Layout L = plan(want);
     if (hipMalloc((void**)&c->dmem, L.total) != hipSuccess) {
         (void)hipGetLastError();
         c->dmem = nullptr;
         return HULL2D_ERR_OUT_OF_MEMORY;
     }
-    char* b = c->dmem;
-    c->partial = (Cand*)(b + L.off[0]);
-    c->prm = (Params*)(b + L.off[1]);
-    c->ds = (DevStatus*)(b + L.off[2]);
-    c->hist = (uint32_t*)(b + L.off[3]);
-    c->comp_xy = (double2*)(b + L.off[4]);
-    c->comp_idx = (uint32_t*)(b + L.off[5]);
-    c->keys_a = (uint32_t*)(b + L.off[6]);
-    c->keys_b = (uint32_t*)(b + L.off[7]);
-    c->vals_a = (uint32_t*)(b + L.off[8]);
-    c->vals_b = (uint32_t*)(b + L.off[9]);
-    c->stat = (uint64_t*)(b + L.off[10]);
-    c->blk_d2 = (double*)(b + L.off[11]);
-    c->blk_best = (uint32_t*)(b + L.off[12]);
-    c->long_list = (uint32_t*)(b + L.off[13]);
-    c->huge_list = (uint32_t*)(b + L.off[14]);
-    c->keep = (uint8_t*)(b + L.off[15]);
-    c->out_xy = (double2*)(b + L.off[16]);
-    c->out_idx = (int32_t*)(b + L.off[17]);
-    c->cand_xy = (double2*)(b + L.off[18]);
-    c->cand_idx = (uint32_t*)(b + L.off[19]);
-    c->cand_key = (uint32_t*)(b + L.off[20]);
-    c->bmax = (uint32_t*)(b + L.off[21]);
-    c->prefix = (uint32_t*)(b + L.off[22]);
-    c->seg_count = (uint32_t*)(b + L.off[23]);
-    c->seg_off = (uint32_t*)(b + L.off[24]);
-    c->cand_kap = (uint32_t*)(b + L.off[25]);
-    c->tail_slot = (uint16_t*)(b + L.off[26]);
-    c->tail_count = (uint32_t*)(b + L.off[26] + 2 * (size_t)kTailCap * sizeof(uint16_t));
+    carve(c->dmem, want, c->own);
+    c->own.epoch = &c->own_epoch;
     // Look-back words carry the call's epoch; zero means "not ready" for any epoch.
-    if (hipMemsetAsync(c->stat, 0, L.off[11] - L.off[10], c->stream) != hipSuccess ||
+    if (hipMemsetAsync(c->own.stat, 0, c->own.stat_bytes, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         c->broken = true;
         return HULL2D_ERR_DEVICE;
@@ -246,21 +294,41 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
     return HULL2D_OK;
 }
 
+// The next look-back epoch of workspace w.  A look-back word keeps 30 bits
+// of the epoch that wrote it; when the counter comes round to a multiple of
+// 2^30 the words are cleared first (by a kernel), so that a word left by an
+// earlier launch never looks ready.
+uint32_t next_epoch(hull2d_ctx* c, Workspace& w) {
+    uint32_t e = __atomic_add_fetch(w.epoch, 1u, __ATOMIC_RELAXED);
+    if ((e & 0x3FFFFFFFu) == 0u) {
+        if (launch_clear_words(w.stat, w.stat_bytes / sizeof(uint64_t), c->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            c->broken = true;
+        }
+        e = __atomic_add_fetch(w.epoch, 1u, __ATOMIC_RELAXED);
+    }
+    return e;
+}
+
 hull2d_status ensure_host(hull2d_ctx* c, int64_t m) {
     if (m <= c->h_cap) return HULL2D_OK;
     int64_t want = std::max<int64_t>(m, 4096);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
+    if (c->h_hull) (void)hipHostFree(c->h_hull);
     c->h_xy = nullptr;
     c->h_idx = nullptr;
+    c->h_hull = nullptr;
     c->h_cap = 0;
-    // mapped and coherent: the one-workgroup tail writes the kept points
+    // mapped and coherent: the device writes the kept points or the hull
     // here directly, saving a copy and a wait
     const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
     if (hipHostMalloc((void**)&c->h_xy, (size_t)want * sizeof(double2), fl) != hipSuccess ||
         hipHostMalloc((void**)&c->h_idx, (size_t)want * sizeof(int32_t), fl) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_hull, (size_t)(want + 1) * sizeof(int32_t), fl) != hipSuccess ||
         hipHostGetDevicePointer((void**)&c->h_xy_dev, c->h_xy, 0) != hipSuccess ||
-        hipHostGetDevicePointer((void**)&c->h_idx_dev, c->h_idx, 0) != hipSuccess) {
+        hipHostGetDevicePointer((void**)&c->h_idx_dev, c->h_idx, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->h_hull_dev, c->h_hull, 0) != hipSuccess) {
         (void)hipGetLastError();
         return HULL2D_ERR_OUT_OF_MEMORY;
     }
@@ -515,6 +583,439 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Argument checks and the start of a compute call (both entry points).
+// Returns OK with n == 0 handled (nothing more to do), or an error.
+hull2d_status begin_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32_t* h_out,
+                            int64_t cap, int64_t* n_out, hull2d_stats* stats) {
+    if (!c || !n_out || n < 0 || cap < 0 || (n > 0 && !d_xy) || (cap > 0 && !h_out))
+        return HULL2D_ERR_INVALID_ARG;
+    if (n > (int64_t)INT32_MAX) return HULL2D_ERR_INVALID_ARG;
+    if (c->broken) return HULL2D_ERR_DEVICE;
+    *n_out = 0;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->n = n;
+    }
+    c->have_last = false;
+    c->last_learned = false;
+    c->last_chain = false;
+    if (c->opt.method != 0 && c->opt.method != 1) return HULL2D_ERR_INVALID_ARG;
+    if (c->opt.method == 0 && c->opt.filter == 1 && !c->have_weights) return HULL2D_ERR_WEIGHTS;
+    if (n == 0) return HULL2D_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    return HULL2D_OK;
+}
+
+// Steps 1-8 for one hull, on workspace w (large enough for n points).
+hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, const double* d_xy,
+                           int64_t n, int32_t* h_out, int64_t cap, int64_t* n_out,
+                           hull2d_stats* stats, std::chrono::steady_clock::time_point t_start) {
+    const bool learned = c->opt.filter == 1;
+    hull2d_status st = HULL2D_OK;
+
+    const bool prof = c->opt.profile && c->have_events;
+    const bool prof_all = prof && c->opt.profile == 1;  // 2: Steps 1 and 2-3 only
+    hipStream_t s = c->stream;
+    int marks[2 * HULL2D_NUM_STAGES];
+    int n_marks = 0;
+    auto mark = [&](int i) {
+        const bool want = prof_all || (prof && (i == HULL2D_STAGE_EXTREMES || i == HULL2D_STAGE_FILTER1));
+        if (want && n_marks < 2 * HULL2D_NUM_STAGES) {
+            (void)hipEventRecord(c->ev[i], s);
+            marks[n_marks++] = i;
+        }
+    };
+    hipEvent_t ev_begin = c->ev[HULL2D_NUM_STAGES];
+    hipEvent_t ev_end = c->ev[HULL2D_NUM_STAGES + 1];
+    if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
+
+    // Step 1
+    // learned filter first: sample histogram, network and the sample's
+    // farthest point along each direction (one workgroup); the end of Step 1
+    // then builds the discard polygon.  The proposal does not depend on the
+    // Step-1 pass, but running it on a second stream beside it measured no
+    // faster: the two share the device.
+    if (learned) {
+        HX_TRY(launch_front(d_xy, n, mlp_dev(c), c->learn, s));
+        mark(HULL2D_STAGE_LEARNED);
+    }
+    const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
+    HX_TRY(launch_extremes(d_xy, n, w.partial, grid_ext, w.prm, w.ds, learned ? c->learn : nullptr, s));
+    mark(HULL2D_STAGE_EXTREMES);
+    // Steps 2-3
+    const int segs = std::min(
+        filter1_blocks(n, c->cu_count, learned ? c->occ.filter1_poly : c->occ.filter1), kMaxSegs);
+    HX_TRY(launch_filter1(d_xy, n, segs, w.prm, learned ? &c->learn->poly : nullptr, w.comp_xy,
+                          w.comp_idx, w.keys_a, w.seg_count, w.blk_d2, w.blk_best, w.ds, s));
+    mark(HULL2D_STAGE_FILTER1);
+    // Step 5 (needs every survivor's distance; the sort does not)
+    const bool full = c->opt.round2_chunk != 0 || c->opt.full_sort != 0;
+    HX_TRY(launch_longest(segs, w.blk_d2, w.blk_best, w.seg_count, w.seg_off, w.comp_xy, w.keys_a,
+                          w.prm, w.ds, full ? nullptr : w.bmax, s));
+    mark(HULL2D_STAGE_LONGEST);
+    // The sorting problem: every round-1 survivor (Step 4 as printed, and the
+    // paper's subsets), or only the candidates of the bucketed filter.
+    DevStatus* pds = w.ds;
+    const double2* pxy = w.comp_xy;
+    const uint32_t* pidx = w.comp_idx;
+    const uint32_t* pkeys = w.cand_key;   // dense keys of the full problem
+    const uint32_t* pvals = w.cand_idx;   // and their slots in the segments
+    if (!full) {
+        DevStatus* ds2 = w.ds + 1;
+        HX_TRY(launch_bucket_max(n, segs, w.seg_count, w.comp_xy, w.keys_a, w.prm, w.bmax,
+                                 std::max(1, c->cu_count), s));
+        HX_TRY(launch_bucket_scan(w.bmax, w.prefix, ds2, s));
+        HX_TRY(launch_prefilter(n, segs, w.seg_count, w.comp_xy, w.comp_idx, w.keys_a, w.prm,
+                                w.ds, w.prefix, w.cand_xy, w.cand_idx, w.cand_key, w.cand_kap,
+                                w.bmax, ds2, s));
+        pds = ds2;
+        pxy = w.cand_xy;
+        pidx = w.cand_idx;
+        pkeys = w.cand_key;
+        pvals = nullptr;
+    } else {
+        HX_TRY(launch_densify(n, segs, w.seg_count, w.seg_off, w.keys_a, w.cand_key, w.cand_idx, s));
+    }
+    mark(HULL2D_STAGE_BUCKETS);
+
+    // Step 4 and Steps 6-7 with the stable removal, by the multi-kernel path
+    // (any size), followed by the status read-back.
+    auto sort_path = [&]() -> hull2d_status {
+        HX_TRY(launch_histogram(pkeys, pds, w.hist,
+                                (int)std::min<int64_t>(kHistGridMax, std::max<int64_t>(1, ceil_div(n, 4096))), s));
+        mark(HULL2D_STAGE_HISTOGRAM);
+        const uint32_t* kin = pkeys;
+        const uint32_t* vin = pvals;
+        uint32_t* kout = w.keys_b;
+        uint32_t* vout = w.vals_b;
+        for (int pass = 0; pass < 4; ++pass) {
+            const uint32_t e = next_epoch(c, w);
+            HX_TRY(launch_sort_pass(n, pass, kin, vin, kout, vout, w.hist, pds, w.stat, c->ctr, e,
+                                    c->cu_count, s));
+            mark(HULL2D_STAGE_SORT0 + pass);
+            kin = kout;
+            vin = vout;
+            kout = (kout == w.keys_b) ? w.keys_a : w.keys_b;
+            vout = (vout == w.vals_b) ? w.vals_a : w.vals_b;
+        }
+        // after four passes the result is in keys_a / vals_a
+        HX_TRY(launch_ties(n, w.keys_a, w.vals_a, pxy, pidx, w.prm, pds, w.long_list, s));
+        mark(HULL2D_STAGE_TIES);
+        HX_TRY(launch_ties_long(w.keys_a, w.vals_a, pxy, pidx, w.prm, pds, w.long_list,
+                                w.huge_list, c->cu_count, s));
+        mark(HULL2D_STAGE_TIES_LONG);
+        return HULL2D_OK;
+    };
+    uint32_t* slots = w.vals_a;
+    auto round2 = [&]() -> hull2d_status {
+        if (c->opt.round2_chunk == 0) {
+            const uint32_t e = next_epoch(c, w);
+            HX_TRY(launch_round2_scan(n, slots, pxy, w.prm, pds, w.keep, w.stat, c->ctr, e,
+                                      c->cu_count, s));
+        } else {
+            HX_TRY(launch_round2_chunks(n, c->opt.round2_chunk, slots, pxy, w.prm, pds, w.keep, s));
+        }
+        mark(HULL2D_STAGE_ROUND2);
+        const uint32_t e = next_epoch(c, w);
+        HX_TRY(launch_compact(n, w.keep, slots, pxy, pidx, w.out_xy, w.out_idx, pds, w.stat,
+                              c->ctr, e, c->cu_count, s));
+        mark(HULL2D_STAGE_COMPACT);
+        return HULL2D_OK;
+    };
+    auto read_status = [&]() -> hull2d_status {
+        HX_TRY(hipMemcpyAsync(c->h_ds, w.ds, 2 * sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        HX_TRY(spin_sync(c));
+        return HULL2D_OK;
+    };
+    bool tail_done = false;
+    bool scanned = false;  // Step 8 ran on the device: the hull is in c->h_hull
+    uint32_t* scan_ticket = &c->ctr->ticket[kTicketScan * 16];
+    if (!full) {
+        // small candidate sets: one workgroup per region does Steps 4 and
+        // 6-7, then Step 8 runs on the device and the hull and both statuses
+        // go straight to host memory (at most kTailCap kept points per
+        // region and P_l)
+        st = ensure_host(c, 2 * (int64_t)kTailCap + 1);
+        if (st != HULL2D_OK) return st;
+        c->h_ds[1].tail_state = kTailUnset;  // the kernels overwrite these
+        c->h_ds[1].scan_state = kScanUnset;
+        HX_TRY(launch_tail(w.cand_xy, w.cand_idx, w.cand_key, w.cand_kap, w.bmax, w.prm,
+                           w.ds, w.tail_slot, w.tail_count, nullptr, nullptr, nullptr, s));
+        mark(HULL2D_STAGE_TAIL);
+        HX_TRY(launch_scan_tail(w.cand_xy, w.cand_idx, w.tail_slot, w.tail_count, w.ds, w.out_xy,
+                                w.keys_b, w.part_len, scan_ticket, c->h_hull_dev, c->h_ds_dev, s));
+        mark(HULL2D_STAGE_SCAN);
+        // one wait ends the call unless the candidates did not fit
+        if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
+        HX_TRY(spin_sync(c));
+        if (c->h_ds[1].tail_state == kTailUnset) {
+            // not written: read the statuses the usual way
+            st = read_status();
+            if (st != HULL2D_OK) return st;
+        }
+        tail_done = c->h_ds[1].tail_state == kTailDone;
+        scanned = tail_done && c->h_ds[1].scan_state == kScanDone;
+        // the scan did nothing: its event is recorded again if the list
+        // form runs later (one event per stage)
+        if (!tail_done && n_marks > 0 && marks[n_marks - 1] == HULL2D_STAGE_SCAN) --n_marks;
+        if (tail_done && !scanned) {
+            // the parts' chains were too many for one workgroup: the kept
+            // points go to host memory for the host scan
+            HX_TRY(launch_tail_out(w.cand_xy, w.cand_idx, w.ds, w.tail_slot, w.tail_count, c->h_xy_dev,
+                                   c->h_idx_dev, c->h_ds_dev, s));
+            mark(HULL2D_STAGE_D2H);
+            if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
+            HX_TRY(spin_sync(c));
+        }
+    }
+    if (!tail_done) {
+        st = sort_path();
+        if (st != HULL2D_OK) return st;
+        st = round2();
+        if (st != HULL2D_OK) return st;
+        st = read_status();
+        if (st != HULL2D_OK) return st;
+    }
+    DevStatus D = c->h_ds[0];
+    DevStatus DP = full ? c->h_ds[0] : c->h_ds[1];
+    if (D.flags & kFlagNonfinite) return HULL2D_ERR_NONFINITE;
+    if (D.flags & kFlagRange) return HULL2D_ERR_RANGE;
+    if (!tail_done && DP.huge_runs > 0) {
+        // Runs of equal keys longer than one workgroup sorts: merge them, then
+        // run the second round again on the corrected order.
+        std::vector<uint32_t>& hl = c->huge_host;
+        hl.resize(2 * (size_t)DP.huge_runs);
+        HX_TRY(hipMemcpyAsync(hl.data(), w.huge_list, hl.size() * sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, s));
+        HX_TRY(spin_sync(c));
+        for (uint32_t r = 0; r < DP.huge_runs; ++r)
+            HX_TRY(launch_huge_run(slots, w.vals_b, hl[2 * r], hl[2 * r + 1], pxy, pidx, w.prm, pds, s));
+        st = round2();
+        if (st != HULL2D_OK) return st;
+        st = read_status();
+        if (st != HULL2D_OK) return st;
+        D = c->h_ds[0];
+        DP = full ? c->h_ds[0] : c->h_ds[1];
+    }
+    const DevStatus DS = DP;
+    const int64_t m = (int64_t)DS.n_kept;
+    st = ensure_host(c, m + 1);
+    if (st != HULL2D_OK) return st;
+    if (!tail_done && m <= (int64_t)kScanMaxParts * kScanPart) {
+        // Step 8 on the device over the compacted kept points; the parts'
+        // chains go to arrays that are dead by now
+        double2* part_xy = pxy == w.cand_xy ? w.comp_xy : w.cand_xy;
+        c->h_ds[1].scan_state = kScanUnset;
+        HX_TRY(launch_scan_list(w.out_xy, w.out_idx, m, D.x0, D.y0, D.p0_idx, w.ds, part_xy, w.keys_b,
+                                w.part_len, scan_ticket, c->h_hull_dev, c->h_ds_dev, s));
+        mark(HULL2D_STAGE_SCAN);
+        if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
+        HX_TRY(spin_sync(c));
+        scanned = c->h_ds[1].scan_state == kScanDone;
+    }
+    auto t_d2h = std::chrono::steady_clock::now();
+    if (!tail_done && !scanned) {
+        if (m > 0) {
+            HX_TRY(hipMemcpyAsync(c->h_xy, w.out_xy, (size_t)m * sizeof(double2),
+                                  hipMemcpyDeviceToHost, s));
+            HX_TRY(hipMemcpyAsync(c->h_idx, w.out_idx, (size_t)m * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s));
+        }
+        mark(HULL2D_STAGE_D2H);
+        if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
+        HX_TRY(spin_sync(c));
+    }
+    const double ms_d2h_wall = tail_done || scanned ? 0.0 : ms_since(t_d2h);
+
+    // Step 8 on the host when the device scan did not finish the hull
+    auto t_scan = std::chrono::steady_clock::now();
+    int64_t h = 0;
+    const int32_t* hull_out = c->h_hull;
+    if (scanned) {
+        h = (int64_t)c->h_ds[1].n_hull;
+    } else {
+        std::vector<int64_t>& stk = c->stk;
+        std::vector<int32_t>& hull = c->hull;
+        stk.reserve((size_t)m + 1);
+        h = graham_scan(D.x0, D.y0, D.p0_idx, c->h_xy, c->h_idx, m, stk, hull);
+        hull_out = hull.data();
+    }
+    const double ms_scan = scanned ? 0.0 : ms_since(t_scan);
+
+    c->have_last = true;
+    c->last_learned = learned;
+    c->last_full = full;
+    c->last_n = n;
+    c->last_segs = segs;
+    c->last_ws = w;
+    c->last_tail = tail_done;
+    c->last_ds = D;
+    c->last_ds2 = DS;
+
+    *n_out = h;
+    if (stats) {
+        stats->n_round1 = (int64_t)D.n_sorted + (int64_t)D.n_p0;
+        stats->n_sorted = D.n_sorted;
+        stats->n_round2 = m + 1;
+        stats->n_hull = h;
+        stats->n_candidates = DS.n_sorted;
+        if (c->have_events) {
+            float f = 0.f;
+            if (hipEventElapsedTime(&f, ev_begin, ev_end) == hipSuccess)
+                stats->ms_device = f;
+        }
+        if (prof) {
+            // each recorded stage ends at its event and starts at the previous
+            // recorded one; Step 1's two kernels are reported under EXTREMES
+            hipEvent_t prev = ev_begin;
+            for (int k = 0; k < n_marks; ++k) {
+                float f = 0.f;
+                if (hipEventElapsedTime(&f, prev, c->ev[marks[k]]) == hipSuccess && f > 0.f)
+                    stats->ms_stage[marks[k]] += f;
+                prev = c->ev[marks[k]];
+            }
+        }
+        stats->ms_stage[HULL2D_STAGE_HOST_SCAN] = ms_scan;
+        if (!prof) stats->ms_stage[HULL2D_STAGE_D2H] = ms_d2h_wall;
+    }
+    if (h > cap) {
+        if (stats) stats->ms_total = ms_since(t_start);
+        return HULL2D_ERR_CAPACITY;
+    }
+    std::memcpy(h_out, hull_out, (size_t)h * sizeof(int32_t));
+    if (stats) stats->ms_total = ms_since(t_start);
+    return HULL2D_OK;
+}
+
+// The four-region variant (options.method = 1; Section 5.1, Table 8): Steps
+// 1-2 as gScan, then the regions, their candidates, the exact sort and the
+// walk per region on the device (launch_chain), and the variant's second
+// stage on the host: per region one stack scan from corner k over the kept
+// points to corner k+1 (a non-left turn pops, a repeat of the top is
+// skipped), the chains joined without their last points, the result rotated
+// to the lexicographically smallest vertex.
+hull2d_status compute_chain(hull2d_ctx* c, Workspace& w, const double* d_xy, int64_t n,
+                            int32_t* h_out, int64_t cap, int64_t* n_out, hull2d_stats* stats,
+                            std::chrono::steady_clock::time_point t_start) {
+    hipStream_t s = c->stream;
+    hull2d_status st = ensure_host(c, 4 * (int64_t)kChainHostCap);
+    if (st != HULL2D_OK) return st;
+    hipEvent_t ev_begin = c->ev[HULL2D_NUM_STAGES];
+    hipEvent_t ev_end = c->ev[HULL2D_NUM_STAGES + 1];
+    if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
+    const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
+    HX_TRY(launch_extremes(d_xy, n, w.partial, grid_ext, w.prm, w.ds, nullptr, s));
+    HX_TRY(launch_chain(d_xy, n, w.prm, w.ds, w.chain, w.cand_xy, w.cand_idx, w.cand_key, w.comp_xy,
+                        w.comp_idx, w.out_xy, w.out_idx, c->h_chain_dev, c->h_xy_dev, c->h_idx_dev,
+                        c->cu_count * 8, s));
+    if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
+    HX_TRY(spin_sync(c));
+    const ChainHost H = *c->h_chain;
+    if (H.ds0.flags & kFlagNonfinite) return HULL2D_ERR_NONFINITE;
+    if (H.ds0.flags & kFlagRange) return HULL2D_ERR_RANGE;
+    for (int r = 0; r < 4; ++r)
+        if (H.overflow[r]) return HULL2D_ERR_UNIMPLEMENTED;
+
+    // the kept lists: in the host buffers, or copied from the device
+    const double2* kxy[4];
+    const int32_t* kix[4];
+    size_t off_host = 0;
+    for (int r = 0; r < 4; ++r)
+        if (!H.on_host[r]) off_host += H.n_kept[r];
+    if (off_host > 0) {
+        c->chain_xy.resize(off_host);
+        c->chain_ix.resize(off_host);
+    }
+    size_t at = 0;
+    for (int r = 0; r < 4; ++r) {
+        if (H.on_host[r]) {
+            kxy[r] = c->h_xy + (size_t)r * kChainHostCap;
+            kix[r] = c->h_idx + (size_t)r * kChainHostCap;
+            continue;
+        }
+        kxy[r] = c->chain_xy.data() + at;
+        kix[r] = c->chain_ix.data() + at;
+        if (H.n_kept[r] > 0) {
+            HX_TRY(hipMemcpyAsync(c->chain_xy.data() + at, w.out_xy + H.kept_at[r],
+                                  (size_t)H.n_kept[r] * sizeof(double2), hipMemcpyDeviceToHost, s));
+            HX_TRY(hipMemcpyAsync(c->chain_ix.data() + at, w.out_idx + H.kept_at[r],
+                                  (size_t)H.n_kept[r] * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        }
+        at += H.n_kept[r];
+    }
+    if (off_host > 0) HX_TRY(spin_sync(c));
+
+    auto t_scan = std::chrono::steady_clock::now();
+    std::vector<HostPt>& stk = c->cstk;
+    stk.clear();
+    size_t need = 8;
+    for (int r = 0; r < 4; ++r) need += H.n_kept[r];
+    stk.reserve(need);
+    for (int k = 0; k < 4; ++k) {
+        const size_t beg = stk.size();
+        auto push = [&](double x, double y, int32_t i) {
+            if (stk.size() > beg && stk.back().x == x && stk.back().y == y) return;
+            while (stk.size() - beg >= 2) {
+                const HostPt& a = stk[stk.size() - 2];
+                const HostPt& b = stk.back();
+                if (orient(a.x, a.y, b.x, b.y, x, y) > 0) break;
+                stk.pop_back();
+            }
+            stk.push_back(HostPt{x, y, i});
+        };
+        push(H.cx[k], H.cy[k], H.ci[k]);
+        for (uint32_t j = 0; j < H.n_kept[k]; ++j) push(kxy[k][j].x, kxy[k][j].y, kix[k][j]);
+        push(H.cx[(k + 1) & 3], H.cy[(k + 1) & 3], H.ci[(k + 1) & 3]);
+        stk.pop_back();  // corner k+1 starts the next chain
+    }
+    if (stk.empty()) stk.push_back(HostPt{H.cx[0], H.cy[0], H.ci[0]});
+    const int64_t h = (int64_t)stk.size();
+    size_t start = 0;
+    for (size_t k = 1; k < stk.size(); ++k)
+        if (stk[k].x < stk[start].x || (stk[k].x == stk[start].x && stk[k].y < stk[start].y)) start = k;
+    const double ms_scan = ms_since(t_scan);
+
+    int distinct = 0;
+    for (int k = 0; k < 4; ++k) {
+        bool dup = false;
+        for (int j = 0; j < k; ++j) dup |= (H.cx[j] == H.cx[k] && H.cy[j] == H.cy[k]);
+        distinct += dup ? 0 : 1;
+    }
+    c->have_last = true;
+    c->last_learned = false;
+    c->last_chain = true;
+    c->last_chain_host = H;
+    c->last_n = n;
+    c->last_ws = w;
+    c->last_ds = H.ds0;
+    *n_out = h;
+    if (stats) {
+        int64_t kept = 0, cand = 0, inreg = 0;
+        for (int r = 0; r < 4; ++r) {
+            kept += H.n_kept[r];
+            cand += H.n_cand[r];
+            inreg += H.n_region[r];
+        }
+        stats->n_round1 = H.m1;
+        stats->n_sorted = inreg;
+        stats->n_candidates = cand;
+        stats->n_round2 = kept + distinct;
+        stats->n_hull = h;
+        if (c->have_events) {
+            float f = 0.f;
+            if (hipEventElapsedTime(&f, ev_begin, ev_end) == hipSuccess) stats->ms_device = f;
+        }
+        stats->ms_stage[HULL2D_STAGE_HOST_SCAN] = ms_scan;
+    }
+    if (h > cap) {
+        if (stats) stats->ms_total = ms_since(t_start);
+        return HULL2D_ERR_CAPACITY;
+    }
+    for (int64_t k = 0; k < h; ++k) h_out[k] = stk[(start + (size_t)k) % (size_t)h].i;
+    if (stats) stats->ms_total = ms_since(t_start);
+    return HULL2D_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -567,7 +1068,10 @@ hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
         hipMemset(c->ctr, 0, sizeof(Counters)) != hipSuccess ||
         hipHostMalloc((void**)&c->h_ds, 2 * sizeof(DevStatus),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
-        hipHostGetDevicePointer((void**)&c->h_ds_dev, c->h_ds, 0) != hipSuccess) {
+        hipHostGetDevicePointer((void**)&c->h_ds_dev, c->h_ds, 0) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_chain, sizeof(ChainHost),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->h_chain_dev, c->h_chain, 0) != hipSuccess) {
         (void)hipGetLastError();
         hull2d_destroy(c);
         return HULL2D_ERR_OUT_OF_MEMORY;
@@ -596,8 +1100,10 @@ void hull2d_destroy(hull2d_ctx* c) {
     if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_ds) (void)hipHostFree(c->h_ds);
+    if (c->h_chain) (void)hipHostFree(c->h_chain);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
     if (c->h_idx) (void)hipHostFree(c->h_idx);
+    if (c->h_hull) (void)hipHostFree(c->h_hull);
     if (c->bmem) (void)hipFree(c->bmem);
     if (c->lmem) (void)hipFree(c->lmem);
     if (c->tmem) (void)hipFree(c->tmem);
@@ -614,254 +1120,12 @@ void hull2d_destroy(hull2d_ctx* c) {
 hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32_t* h_out,
                              int64_t cap, int64_t* n_out, hull2d_stats* stats) {
     auto t_start = std::chrono::steady_clock::now();
-    if (!c || !n_out || n < 0 || cap < 0 || (n > 0 && !d_xy) || (cap > 0 && !h_out))
-        return HULL2D_ERR_INVALID_ARG;
-    if (n > (int64_t)INT32_MAX) return HULL2D_ERR_INVALID_ARG;
-    if (c->broken) return HULL2D_ERR_DEVICE;
-    *n_out = 0;
-    if (stats) {
-        std::memset(stats, 0, sizeof(*stats));
-        stats->n = n;
-    }
-    c->have_last = false;
-    c->last_learned = false;
-    const bool learned = c->opt.filter == 1;
-    if (learned && !c->have_weights) return HULL2D_ERR_WEIGHTS;
-    if (n == 0) return HULL2D_OK;
-    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
-    hull2d_status st = ensure_workspace(c, n);
+    hull2d_status st = begin_compute(c, d_xy, n, h_out, cap, n_out, stats);
+    if (st != HULL2D_OK || n == 0) return st;
+    st = ensure_workspace(c, n);
     if (st != HULL2D_OK) return st;
-
-    const bool prof = c->opt.profile && c->have_events;
-    const bool prof_all = prof && c->opt.profile == 1;  // 2: Steps 1 and 2-3 only
-    hipStream_t s = c->stream;
-    int marks[2 * HULL2D_NUM_STAGES];
-    int n_marks = 0;
-    auto mark = [&](int i) {
-        const bool want = prof_all || (prof && (i == HULL2D_STAGE_EXTREMES || i == HULL2D_STAGE_FILTER1));
-        if (want && n_marks < 2 * HULL2D_NUM_STAGES) {
-            (void)hipEventRecord(c->ev[i], s);
-            marks[n_marks++] = i;
-        }
-    };
-    hipEvent_t ev_begin = c->ev[HULL2D_NUM_STAGES];
-    hipEvent_t ev_end = c->ev[HULL2D_NUM_STAGES + 1];
-    if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
-
-    // Step 1
-    // learned filter first: sample histogram, network and the sample's
-    // farthest point along each direction (one workgroup); the end of Step 1
-    // then builds the discard polygon.  The proposal does not depend on the
-    // Step-1 pass, but running it on a second stream beside it measured no
-    // faster: the two share the device.
-    if (learned) {
-        HX_TRY(launch_front(d_xy, n, mlp_dev(c), c->learn, s));
-        mark(HULL2D_STAGE_LEARNED);
-    }
-    const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
-    HX_TRY(launch_extremes(d_xy, n, c->partial, grid_ext, c->prm, c->ds, learned ? c->learn : nullptr, s));
-    mark(HULL2D_STAGE_EXTREMES);
-    // Steps 2-3
-    const int segs = std::min(
-        filter1_blocks(n, c->cu_count, learned ? c->occ.filter1_poly : c->occ.filter1), kMaxSegs);
-    HX_TRY(launch_filter1(d_xy, n, segs, c->prm, learned ? &c->learn->poly : nullptr, c->comp_xy,
-                          c->comp_idx, c->keys_a, c->seg_count, c->blk_d2, c->blk_best, c->ds, s));
-    mark(HULL2D_STAGE_FILTER1);
-    // Step 5 (needs every survivor's distance; the sort does not)
-    const bool full = c->opt.round2_chunk != 0 || c->opt.full_sort != 0;
-    HX_TRY(launch_longest(segs, c->blk_d2, c->blk_best, c->seg_count, c->seg_off, c->comp_xy, c->keys_a,
-                          c->prm, c->ds, full ? nullptr : c->bmax, s));
-    mark(HULL2D_STAGE_LONGEST);
-    // The sorting problem: every round-1 survivor (Step 4 as printed, and the
-    // paper's subsets), or only the candidates of the bucketed filter.
-    DevStatus* pds = c->ds;
-    const double2* pxy = c->comp_xy;
-    const uint32_t* pidx = c->comp_idx;
-    const uint32_t* pkeys = c->cand_key;   // dense keys of the full problem
-    const uint32_t* pvals = c->cand_idx;   // and their slots in the segments
-    if (!full) {
-        DevStatus* ds2 = c->ds + 1;
-        HX_TRY(launch_bucket_max(n, segs, c->seg_count, c->comp_xy, c->keys_a, c->prm, c->bmax,
-                                 c->parts, s));
-        HX_TRY(launch_bucket_scan(c->bmax, c->prefix, ds2, s));
-        HX_TRY(launch_prefilter(n, segs, c->seg_count, c->comp_xy, c->comp_idx, c->keys_a, c->prm,
-                                c->ds, c->prefix, c->cand_xy, c->cand_idx, c->cand_key, c->cand_kap,
-                                c->bmax, ds2, s));
-        pds = ds2;
-        pxy = c->cand_xy;
-        pidx = c->cand_idx;
-        pkeys = c->cand_key;
-        pvals = nullptr;
-    } else {
-        HX_TRY(launch_densify(n, segs, c->seg_count, c->seg_off, c->keys_a, c->cand_key, c->cand_idx, s));
-    }
-    mark(HULL2D_STAGE_BUCKETS);
-
-    // Step 4 and Steps 6-7 with the stable removal, by the multi-kernel path
-    // (any size), followed by the status read-back.
-    auto sort_path = [&]() -> hull2d_status {
-        HX_TRY(launch_histogram(pkeys, pds, c->hist,
-                                (int)std::min<int64_t>(kHistGridMax, std::max<int64_t>(1, ceil_div(n, 4096))), s));
-        mark(HULL2D_STAGE_HISTOGRAM);
-        const uint32_t* kin = pkeys;
-        const uint32_t* vin = pvals;
-        uint32_t* kout = c->keys_b;
-        uint32_t* vout = c->vals_b;
-        for (int pass = 0; pass < 4; ++pass) {
-            const uint32_t e = ++c->epoch;
-            HX_TRY(launch_sort_pass(n, pass, kin, vin, kout, vout, c->hist, pds, c->stat, c->ctr, e,
-                                    c->cu_count, s));
-            mark(HULL2D_STAGE_SORT0 + pass);
-            kin = kout;
-            vin = vout;
-            kout = (kout == c->keys_b) ? c->keys_a : c->keys_b;
-            vout = (vout == c->vals_b) ? c->vals_a : c->vals_b;
-        }
-        // after four passes the result is in keys_a / vals_a
-        HX_TRY(launch_ties(n, c->keys_a, c->vals_a, pxy, pidx, c->prm, pds, c->long_list, s));
-        mark(HULL2D_STAGE_TIES);
-        HX_TRY(launch_ties_long(c->keys_a, c->vals_a, pxy, pidx, c->prm, pds, c->long_list,
-                                c->huge_list, c->cu_count, s));
-        mark(HULL2D_STAGE_TIES_LONG);
-        return HULL2D_OK;
-    };
-    uint32_t* slots = c->vals_a;
-    auto round2 = [&]() -> hull2d_status {
-        if (c->opt.round2_chunk == 0) {
-            const uint32_t e = ++c->epoch;
-            HX_TRY(launch_round2_scan(n, slots, pxy, c->prm, pds, c->keep, c->stat, c->ctr, e,
-                                      c->cu_count, s));
-        } else {
-            HX_TRY(launch_round2_chunks(n, c->opt.round2_chunk, slots, pxy, c->prm, pds, c->keep, s));
-        }
-        mark(HULL2D_STAGE_ROUND2);
-        const uint32_t e = ++c->epoch;
-        HX_TRY(launch_compact(n, c->keep, slots, pxy, pidx, c->out_xy, c->out_idx, pds, c->stat,
-                              c->ctr, e, c->cu_count, s));
-        mark(HULL2D_STAGE_COMPACT);
-        return HULL2D_OK;
-    };
-    auto read_status = [&]() -> hull2d_status {
-        HX_TRY(hipMemcpyAsync(c->h_ds, c->ds, 2 * sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-        HX_TRY(spin_sync(c));
-        return HULL2D_OK;
-    };
-    bool tail_done = false;
-    if (!full) {
-        // small candidate sets: one workgroup per region does the rest, the
-        // kept points then go straight to the host buffers (at most
-        // kTailCap per region and P_l)
-        st = ensure_host(c, 2 * (int64_t)kTailCap + 1);
-        if (st != HULL2D_OK) return st;
-        c->h_ds[1].tail_state = kTailUnset;  // the kernel overwrites it
-        HX_TRY(launch_tail(c->cand_xy, c->cand_idx, c->cand_key, c->cand_kap, c->bmax, c->prm,
-                           c->ds, c->tail_slot, c->tail_count, c->h_xy_dev, c->h_idx_dev,
-                           c->h_ds_dev, s));
-        mark(HULL2D_STAGE_TAIL);
-        // the tail leaves the kept points and both statuses in host memory:
-        // one wait ends the call unless the candidates did not fit
-        if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
-        HX_TRY(spin_sync(c));
-        if (c->h_ds[1].tail_state == kTailUnset) {
-            // not written: read the statuses the usual way
-            st = read_status();
-            if (st != HULL2D_OK) return st;
-        }
-        tail_done = c->h_ds[1].tail_state == kTailDone;
-    }
-    if (!tail_done) {
-        st = sort_path();
-        if (st != HULL2D_OK) return st;
-        st = round2();
-        if (st != HULL2D_OK) return st;
-        st = read_status();
-        if (st != HULL2D_OK) return st;
-    }
-    DevStatus D = c->h_ds[0];
-    DevStatus DP = full ? c->h_ds[0] : c->h_ds[1];
-    if (D.flags & kFlagNonfinite) return HULL2D_ERR_NONFINITE;
-    if (D.flags & kFlagRange) return HULL2D_ERR_RANGE;
-    if (!tail_done && DP.huge_runs > 0) {
-        // Runs of equal keys longer than one workgroup sorts: merge them, then
-        // run the second round again on the corrected order.
-        std::vector<uint32_t> hl(2 * (size_t)DP.huge_runs);
-        HX_TRY(hipMemcpyAsync(hl.data(), c->huge_list, hl.size() * sizeof(uint32_t),
-                              hipMemcpyDeviceToHost, s));
-        HX_TRY(spin_sync(c));
-        for (uint32_t r = 0; r < DP.huge_runs; ++r)
-            HX_TRY(launch_huge_run(slots, c->vals_b, hl[2 * r], hl[2 * r + 1], pxy, pidx, c->prm, pds, s));
-        st = round2();
-        if (st != HULL2D_OK) return st;
-        st = read_status();
-        if (st != HULL2D_OK) return st;
-        D = c->h_ds[0];
-        DP = full ? c->h_ds[0] : c->h_ds[1];
-    }
-    const DevStatus DS = DP;
-    const int64_t m = (int64_t)DS.n_kept;
-    st = ensure_host(c, m);
-    if (st != HULL2D_OK) return st;
-    auto t_d2h = std::chrono::steady_clock::now();
-    if (!tail_done) {
-        if (m > 0) {
-            HX_TRY(hipMemcpyAsync(c->h_xy, c->out_xy, (size_t)m * sizeof(double2),
-                                  hipMemcpyDeviceToHost, s));
-            HX_TRY(hipMemcpyAsync(c->h_idx, c->out_idx, (size_t)m * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, s));
-        }
-        mark(HULL2D_STAGE_D2H);
-        if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
-        HX_TRY(spin_sync(c));
-    }
-    const double ms_d2h_wall = tail_done ? 0.0 : ms_since(t_d2h);
-
-    auto t_scan = std::chrono::steady_clock::now();
-    std::vector<int64_t>& stk = c->stk;
-    std::vector<int32_t>& hull = c->hull;
-    stk.reserve((size_t)m + 1);
-    const int64_t h = graham_scan(D.x0, D.y0, D.p0_idx, c->h_xy, c->h_idx, m, stk, hull);
-    const double ms_scan = ms_since(t_scan);
-
-    c->have_last = true;
-    c->last_learned = learned;
-    c->last_full = full;
-    c->last_n = n;
-    c->last_ds = D;
-    c->last_ds2 = DS;
-
-    *n_out = h;
-    if (stats) {
-        stats->n_round1 = (int64_t)D.n_sorted + (int64_t)D.n_p0;
-        stats->n_sorted = D.n_sorted;
-        stats->n_round2 = m + 1;
-        stats->n_hull = h;
-        stats->n_candidates = DS.n_sorted;
-        if (c->have_events) {
-            float f = 0.f;
-            if (hipEventElapsedTime(&f, ev_begin, ev_end) == hipSuccess)
-                stats->ms_device = f;
-        }
-        if (prof) {
-            // each recorded stage ends at its event and starts at the previous
-            // recorded one; Step 1's two kernels are reported under EXTREMES
-            hipEvent_t prev = ev_begin;
-            for (int k = 0; k < n_marks; ++k) {
-                float f = 0.f;
-                if (hipEventElapsedTime(&f, prev, c->ev[marks[k]]) == hipSuccess && f > 0.f)
-                    stats->ms_stage[marks[k]] += f;
-                prev = c->ev[marks[k]];
-            }
-        }
-        stats->ms_stage[HULL2D_STAGE_HOST_SCAN] = ms_scan;
-        if (!prof) stats->ms_stage[HULL2D_STAGE_D2H] = ms_d2h_wall;
-    }
-    if (h > cap) {
-        if (stats) stats->ms_total = ms_since(t_start);
-        return HULL2D_ERR_CAPACITY;
-    }
-    std::memcpy(h_out, hull.data(), (size_t)h * sizeof(int32_t));
-    if (stats) stats->ms_total = ms_since(t_start);
-    return HULL2D_OK;
+    if (c->opt.method == 1) return compute_chain(c, c->own, d_xy, n, h_out, cap, n_out, stats, t_start);
+    return compute_impl(c, c->own, d_xy, n, h_out, cap, n_out, stats, t_start);
 }
 
 hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_offsets, int32_t S,
@@ -1191,7 +1455,7 @@ hull2d_status hull2d_debug_angle_key(hull2d_ctx* c, const double* d_xy, int64_t 
 hull2d_status hull2d_debug_stages(hull2d_ctx* c, int32_t* extremes, int32_t* sorted, int32_t* round2,
                                   int64_t cap, int64_t* counts) {
     if (!c || cap < 0) return HULL2D_ERR_INVALID_ARG;
-    if (!c->have_last) return HULL2D_ERR_INVALID_ARG;
+    if (!c->have_last || c->last_chain) return HULL2D_ERR_INVALID_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
     const DevStatus& D = c->last_ds;
     const DevStatus& DS = c->last_ds2;
@@ -1212,15 +1476,90 @@ hull2d_status hull2d_debug_stages(hull2d_ctx* c, int32_t* extremes, int32_t* sor
     if (sorted && c->last_full && ms > 0) {
         // the sorted slots sit in vals_a after four passes
         std::vector<uint32_t> sl((size_t)ms), ix((size_t)c->last_n);
-        HX_TRY(hipMemcpy(sl.data(), c->vals_a, (size_t)ms * sizeof(uint32_t), hipMemcpyDeviceToHost));
-        HX_TRY(hipMemcpy(ix.data(), c->comp_idx, (size_t)c->last_n * sizeof(uint32_t),
+        HX_TRY(hipMemcpy(sl.data(), c->last_ws.vals_a, (size_t)ms * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HX_TRY(hipMemcpy(ix.data(), c->last_ws.comp_idx, (size_t)c->last_n * sizeof(uint32_t),
                          hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < ms; ++i) sorted[i] = (int32_t)ix[sl[i]];
     }
     if (round2) {
+        // the kept points in angular order, read back from the device: the
+        // tail's kept slots into the candidates (right region, P_l, left
+        // region), or the compacted list of the multi-kernel path
+        const Workspace& w = c->last_ws;
         round2[0] = D.p0_idx;
-        for (int64_t i = 0; i + 1 < m2; ++i) round2[i + 1] = c->h_idx[i];
+        const int64_t m = m2 - 1;
+        if (m > 0 && c->last_tail) {
+            uint32_t cnt[2];
+            std::vector<uint16_t> sl(2 * (size_t)kTailCap);
+            std::vector<uint32_t> ix((size_t)DS.n_sorted);
+            HX_TRY(hipMemcpy(cnt, w.tail_count, sizeof(cnt), hipMemcpyDeviceToHost));
+            HX_TRY(hipMemcpy(sl.data(), w.tail_slot, sl.size() * sizeof(uint16_t), hipMemcpyDeviceToHost));
+            HX_TRY(hipMemcpy(ix.data(), w.cand_idx, ix.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            if ((int64_t)cnt[0] + 1 + (int64_t)cnt[1] != m) return HULL2D_ERR_DEVICE;
+            int64_t o = 1;
+            for (uint32_t k = 0; k < cnt[0]; ++k) round2[o++] = (int32_t)ix[sl[k]];
+            round2[o++] = (int32_t)ix[DS.l_slot];
+            for (uint32_t k = 0; k < cnt[1]; ++k) round2[o++] = (int32_t)ix[sl[kTailCap + k]];
+        } else if (m > 0) {
+            HX_TRY(hipMemcpy(round2 + 1, w.out_idx, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost));
+        }
     }
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_debug_chain(hull2d_ctx* c, int64_t* counts, int32_t* kept, int64_t cap) {
+    if (!c || cap < 0) return HULL2D_ERR_INVALID_ARG;
+    if (!c->have_last || !c->last_chain) return HULL2D_ERR_INVALID_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    const ChainHost& H = c->last_chain_host;
+    int64_t total = 0;
+    for (int r = 0; r < 4; ++r) total += H.n_kept[r];
+    if (counts) {
+        int distinct = 0;
+        for (int k = 0; k < 4; ++k) {
+            bool dup = false;
+            for (int j = 0; j < k; ++j) dup |= (H.cx[j] == H.cx[k] && H.cy[j] == H.cy[k]);
+            distinct += dup ? 0 : 1;
+        }
+        counts[0] = H.m1;
+        for (int r = 0; r < 4; ++r) {
+            counts[1 + r] = H.n_region[r];
+            counts[5 + r] = H.n_cand[r];
+            counts[9 + r] = H.n_kept[r];
+        }
+        counts[13] = total + distinct;
+    }
+    if (kept) {
+        if (cap < total) return HULL2D_ERR_CAPACITY;
+        int64_t o = 0;
+        for (int r = 0; r < 4; ++r) {
+            if (H.n_kept[r] > 0)
+                HX_TRY(hipMemcpy(kept + o, c->last_ws.out_idx + H.kept_at[r], (size_t)H.n_kept[r] * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost));
+            o += H.n_kept[r];
+        }
+    }
+    return HULL2D_OK;
+}
+
+hull2d_status hull2d_debug_round1(hull2d_ctx* c, int32_t* idx, int64_t cap, int64_t* n_out) {
+    if (!c || !n_out || cap < 0 || (cap > 0 && !idx)) return HULL2D_ERR_INVALID_ARG;
+    if (!c->have_last || c->last_chain) return HULL2D_ERR_INVALID_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
+    const int64_t ms = c->last_ds.n_sorted;
+    *n_out = ms;
+    if (cap < ms) return HULL2D_ERR_CAPACITY;
+    if (ms == 0) return HULL2D_OK;
+    // segment b holds its survivors in input order at [b * chunk, + seg_count[b])
+    const int segs = c->last_segs;
+    const int64_t chunk = filter1_chunk(c->last_n, segs);
+    std::vector<uint32_t> cnt((size_t)segs), ix((size_t)c->last_n);
+    HX_TRY(hipMemcpy(cnt.data(), c->last_ws.seg_count, (size_t)segs * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HX_TRY(hipMemcpy(ix.data(), c->last_ws.comp_idx, (size_t)c->last_n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    int64_t o = 0;
+    for (int b = 0; b < segs; ++b)
+        for (uint32_t k = 0; k < cnt[(size_t)b] && o < ms; ++k) idx[o++] = (int32_t)ix[(size_t)(b * chunk + k)];
+    if (o != ms) return HULL2D_ERR_DEVICE;
     return HULL2D_OK;
 }
 

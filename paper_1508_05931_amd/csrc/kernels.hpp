@@ -35,6 +35,8 @@ constexpr int kTailBlock = 1024;                 // the one-workgroup tail
 constexpr int kTailCap = 12288;                  // candidates per region it sorts in LDS
 constexpr uint32_t kTailSlots = 65536;           // candidates it reads (16-bit slots)
 constexpr int kBatchBlock = 512;                 // threads per set in the batched kernel
+constexpr int kScanPart = 6144;                  // kept points per workgroup of the device Step 8
+constexpr int kScanMaxParts = 1024;              // its workgroups at most
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -119,11 +121,85 @@ hipError_t launch_bucket_max(int64_t n, int segs, const uint32_t* seg_count, con
 // it.  oslot [2][kTailCap] and ocount [2]: the kept slots per region.
 // out_xy / out_idx: the kept points (right region, P_l, left region), device
 // or mapped host memory; host_ds: host memory (device-visible) that receives
-// both statuses, the candidate status with its kept count.
+// both statuses, the candidate status with its kept count.  out_xy NULL:
+// only the kept slots (the gather is launch_tail_out, or the device scan
+// reads the slots itself).
 hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint32_t* cand_key,
                        const uint32_t* cand_kap, const uint32_t* exact, const Params* prm,
                        DevStatus* ds, uint16_t* oslot, uint32_t* ocount, double2* out_xy,
                        int32_t* out_idx, DevStatus* host_ds, hipStream_t s);
+// The kept points and statuses gathered for the host (the tail's output
+// when the device scan below did not finish the hull).
+hipError_t launch_tail_out(const double2* cand_xy, const uint32_t* cand_idx, DevStatus* ds,
+                           const uint16_t* oslot, const uint32_t* ocount, double2* out_xy,
+                           int32_t* out_idx, DevStatus* host_ds, hipStream_t s);
+
+// Step 8 on the device (kernels_scan.hip): the hull of the kept points, in
+// angular order about P_0, rotated to its lexicographically smallest vertex,
+// as input indices in `out` (host-visible); host_ds receives the statuses
+// (tail form: both problems, with n_kept, n_hull and scan_state of the
+// candidate problem; list form: n_hull and scan_state of host_ds[1]).  The
+// parts' chains go to part_xy / part_idx (at each part's first position,
+// kScanPart points per part) and part_len [kScanMaxParts]; ticket is a
+// counter that is zero between launches.
+// Tail form: the kept slots of launch_tail (right region, P_l, left region).
+hipError_t launch_scan_tail(const double2* cand_xy, const uint32_t* cand_idx, const uint16_t* oslot,
+                            const uint32_t* ocount, const DevStatus* ds, double2* part_xy,
+                            uint32_t* part_idx, uint32_t* part_len, uint32_t* ticket, int32_t* out,
+                            DevStatus* host_ds, hipStream_t s);
+// List form: m kept points in kept_xy / kept_idx (m <= kScanMaxParts * kScanPart).
+hipError_t launch_scan_list(const double2* kept_xy, const int32_t* kept_idx, int64_t m, double x0,
+                            double y0, int32_t p0_idx, const DevStatus* ds, double2* part_xy,
+                            uint32_t* part_idx, uint32_t* part_len, uint32_t* ticket, int32_t* out,
+                            DevStatus* host_ds, hipStream_t s);
+
+// ---- the four-region variant (Section 5.1, Table 8) -------------------
+constexpr int kChainBuckets = 4096;   // buckets along u per region
+constexpr int kChainCap = 4096;       // candidates one workgroup sorts at a time
+constexpr int kChainHostCap = 16384;  // kept points per region written to host memory directly
+
+// Device counters of one call (cleared by the first kernel).
+struct ChainStatus {
+    uint32_t m1;           // round-1 survivors (regions 0-3 and the boundary)
+    uint32_t n_region[4];  // survivors per region
+    uint32_t n_cand;       // candidates of all regions
+    uint32_t pad[10];
+};
+
+// Device tables of one call.
+struct ChainTables {
+    uint64_t* bmin;     // [4][kChainBuckets] minimum of v per bucket (order-preserving keys)
+    double* prefix;     // [4][kChainBuckets] minimum over the earlier buckets
+    uint32_t* count;    // [4][kChainBuckets] candidates per bucket
+    uint32_t* offset;   // [4 * kChainBuckets + 1] where each bucket's candidates start
+    uint32_t* cursor;   // [4][kChainBuckets] grouping cursors
+    ChainStatus* st;
+};
+constexpr size_t kChainTableBytes = 4 * (size_t)kChainBuckets * (8 + 8 + 4 + 4 + 4) + 4 + 256;
+
+// What the last kernel leaves in host memory.
+struct ChainHost {
+    DevStatus ds0;          // the round-1 status (domain flags, Step-1 extremes)
+    double cx[4], cy[4];    // the corners P_minx, P_miny, P_maxx, P_maxy
+    int32_t ci[4];
+    uint32_t m1;
+    uint32_t n_region[4];
+    uint32_t n_cand[4];     // candidates per region
+    uint32_t n_kept[4];     // kept points per region
+    uint32_t kept_at[4];    // where each region's kept list starts in out_xy / out_idx
+    uint32_t on_host[4];    // 1: the list is also in the host buffers (kChainHostCap per region)
+    uint32_t overflow[4];   // 1: a bucket held more candidates than one chunk (not computed)
+};
+
+// Steps 1-2 are done (prm, ds); the rest of the variant up to its kept
+// lists.  cand_*: candidates (n entries at most); grp_*: the same grouped by
+// bucket; out_*: kept lists (device, at the region's first candidate
+// position); host, host_xy, host_idx: host-visible.
+hipError_t launch_chain(const double* xy, int64_t n, const Params* prm, const DevStatus* ds, ChainTables T,
+                        double2* cand_xy, uint32_t* cand_idx, uint32_t* cand_rb, double2* grp_xy,
+                        uint32_t* grp_idx, double2* out_xy, int32_t* out_idx, ChainHost* host,
+                        double2* host_xy, int32_t* host_idx, int grid, hipStream_t s);
+
 // The batched form: one persistent launch, each workgroup computing whole
 // hulls of the sets in `order` (device, S entries); per set s, its points are
 // xy[offs[s], offs[s+1]) and its workspace the same range of every array.
@@ -231,6 +307,9 @@ hipError_t launch_compact(int64_t n, const uint8_t* keep, const uint32_t* slots,
                           const double2* comp_xy, const uint32_t* comp_idx, double2* out_xy,
                           int32_t* out_idx, DevStatus* ds, uint64_t* stat, Counters* ctr,
                           uint32_t epoch, int cu_count, hipStream_t s);
+
+// Sets `words` 64-bit words at p to zero (a kernel, so that it may be captured).
+hipError_t launch_clear_words(uint64_t* p, size_t words, hipStream_t s);
 
 // Checking kernels.
 hipError_t launch_debug_orient(const double* abc, int64_t count, int32_t* out, hipStream_t s);

@@ -109,6 +109,8 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* __restrict__ bma
         ds2->l_slot = kNoSlot;
         ds2->n_right = 0;
         ds2->tail_state = kTailDone;
+        ds2->n_hull = 0;
+        ds2->scan_state = kScanNone;
     }
 }
 

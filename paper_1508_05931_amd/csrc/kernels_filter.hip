@@ -205,6 +205,8 @@ __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict_
         S.l_slot = kSlotNone;
         S.n_right = 0;
         S.tail_state = kTailDone;
+        S.n_hull = 0;
+        S.scan_state = kScanNone;
         for (int k = 0; k < 4; ++k) S.ext[k] = e[k].i;
         S.p0_idx = e[1].i;
         S.l_idx = -1;
@@ -862,6 +864,12 @@ __global__ __launch_bounds__(kCpBlock) void k_compact(
     }
 }
 
+__global__ void k_clear_words(uint64_t* __restrict__ p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
 __global__ void k_debug_orient(const double* __restrict__ abc, int64_t count, int32_t* __restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
@@ -908,6 +916,13 @@ void occupancy_filter(Occupancy& o) {
     o.extremes = std::min(resident_blocks(reinterpret_cast<const void*>(k_extremes), kExtBlock), 3);
     o.filter1 = resident_blocks(reinterpret_cast<const void*>(k_filter1<false>), kF1Block);
     o.filter1_poly = resident_blocks(reinterpret_cast<const void*>(k_filter1<true>), kF1Block);
+}
+
+hipError_t launch_clear_words(uint64_t* p, size_t words, hipStream_t s) {
+    if (words == 0) return hipSuccess;
+    const int grid = (int)std::min<size_t>(1024, (words + 255) / 256);
+    hipLaunchKernelGGL(k_clear_words, dim3(grid), dim3(256), 0, s, p, words);
+    return hipGetLastError();
 }
 
 int64_t filter1_chunk(int64_t n, int blocks) {

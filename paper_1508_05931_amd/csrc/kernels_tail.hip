@@ -544,7 +544,13 @@ hipError_t launch_tail(const double2* cand_xy, const uint32_t* cand_idx, const u
     hipLaunchKernelGGL(k_tail, dim3(2), dim3(kTB), 0, s, cand_xy, cand_idx, cand_key, cand_kap, exact,
                        prm, ds + 1, oslot, ocount);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !out_xy) return e;
+    return launch_tail_out(cand_xy, cand_idx, ds, oslot, ocount, out_xy, out_idx, host_ds, s);
+}
+
+hipError_t launch_tail_out(const double2* cand_xy, const uint32_t* cand_idx, DevStatus* ds,
+                           const uint16_t* oslot, const uint32_t* ocount, double2* out_xy,
+                           int32_t* out_idx, DevStatus* host_ds, hipStream_t s) {
     hipLaunchKernelGGL(k_tail_out, dim3(kOutGrid), dim3(kOutBlock), 0, s, cand_xy, cand_idx, ds, oslot,
                        ocount, out_xy, out_idx, host_ds);
     return hipGetLastError();

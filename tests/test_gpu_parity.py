@@ -324,3 +324,102 @@ def test_full_size_matches_golden(torch_dev, ctx, name):
     st = ctx.last_stats
     say(f"  n={st.n} round1={st.n_round1} round2={st.n_round2} h={st.n_hull} "
         f"ms={st.ms_total:.3f}")
+
+
+WEIGHTS = os.path.join(ROOT, "paper_1508_05931_amd", "weights", "filter16.f32")
+
+
+@pytest.mark.parametrize("name,mode", [("square_20M", "full_sort"), ("disk_20M", "full_sort"),
+                                       ("mixture_20M", "learned")])
+def test_full_size_modes_match_golden(torch_dev, hx, name, mode):
+    """The paper's Step 4 as printed (every round-1 survivor sorted) on the
+    20M square and disk, and the learned filter with the shipped weights on
+    its own 20M mixture: the same oracle-written hulls as the default path."""
+    if mode == "learned" and not os.path.exists(WEIGHTS):
+        pytest.skip("no trained weights in the tree")
+    g = _golden()[name]
+    say(f"full size {name} ({mode}): generating")
+    pts = synth.workload(name)
+    assert synth.content_hash(pts) == g["input_hash"]
+    c = hx.Hull2D(full_sort=True) if mode == "full_sort" else hx.Hull2D(learned=True, weights=WEIGHTS)
+    say(f"full size {name} ({mode}): hull on GPU")
+    got = c.compute(to_dev(torch_dev, pts))
+    assert len(got) == g["h"]
+    assert got[:16].tolist() == g["head"]
+    assert hashlib.sha256(np.ascontiguousarray(got, dtype="<i4").tobytes()).hexdigest() == g["sha256"]
+    st = c.last_stats
+    if mode == "full_sort":
+        assert st.n_candidates == st.n_sorted
+    say(f"  n={st.n} round1={st.n_round1} round2={st.n_round2} h={st.n_hull}")
+    c.close()
+
+
+def _without_pivot_copies(pts, keep, pivot):
+    px, py = pts[pivot]
+    return np.flatnonzero(keep & ~((pts[:, 0] == px) & (pts[:, 1] == py))).astype(np.int32)
+
+
+@pytest.mark.parametrize("mode", ["bucketed", "full_sort", "learned"])
+def test_round1_survivors_element_by_element(torch_dev, hx, mode):
+    """Step 2's survivors, index by index, on sets of over a million points:
+    the quadrilateral's against the oracle's model (the bucketed and the
+    full-sort modes share Step 2 but not what follows), the learned polygon's
+    against the oracle's learned first round for the directions the device
+    used."""
+    if mode == "learned":
+        if not os.path.exists(WEIGHTS):
+            pytest.skip("no trained weights in the tree")
+        pts = synth.mixture(1_500_007, (81, 1))
+        c = hx.Hull2D(learned=True, weights=WEIGHTS)
+    else:
+        pts = synth.disk(1_000_003, (80, 1)) if mode == "bucketed" else synth.square(1_200_001, (82, 1))
+        c = hx.Hull2D(full_sort=(mode == "full_sort"))
+    say(f"round-1 survivors {mode} n={len(pts)}")
+    c.compute(to_dev(torch_dev, pts))
+    got = c.round1_survivors()
+    m = oracle.model(pts)
+    if mode == "learned":
+        keep = oracle.learned_round1(pts, c.learned_info()["dirs"])["keep"]
+    else:
+        keep = m["round1_keep"]
+    want = _without_pivot_copies(pts, keep, m["pivot"])
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+    assert c.last_stats.n_sorted == len(want)
+    c.close()
+
+
+def _ngon(k, seed):
+    """k vertices of a regular k-gon (every point a hull vertex), shuffled."""
+    return synth.ngon(k, int(math.log2(k)), seed)
+
+
+@pytest.mark.parametrize("name,full,where", [
+    ("square_100k", False, "device"),       # one part
+    ("disk_100k", False, "device"),
+    ("grid_200x3", False, "device"),        # collinear and repeated kept points
+    ("dup_heavy", False, "device"),
+    ("ngon_16384", False, "host"),          # three parts whose chains overflow one workgroup
+    ("disk_100k", True, "device"),          # list form (multi-kernel path)
+    ("collinear_10k", True, "device"),
+    ("ngon_131072", True, "host"),          # list form, chains overflow
+])
+def test_step8_device_and_host_fallback(torch_dev, hx, name, full, where):
+    """Step 8 runs on the device (chunk scans joined at common tangents) and
+    falls back to the host scan when the parts' chains do not fit one
+    workgroup; the hull equals the oracle's either way."""
+    pts = {"ngon_16384": lambda: _ngon(16384, (98, 1)),
+           "ngon_131072": lambda: _ngon(131072, (99, 1))}.get(name, lambda: CASES[name])()
+    say(f"step 8 {name} full={full}")
+    c = hx.Hull2D(profile=True, full_sort=full)
+    got = c.compute(to_dev(torch_dev, pts))
+    assert got.tolist() == oracle.hull(pts).tolist()
+    st = c.last_stats
+    if where == "device":
+        assert st.ms_stage["host_scan"] == 0.0 and st.ms_stage["scan"] > 0.0
+    else:
+        assert st.ms_stage["host_scan"] > 0.0
+    m = oracle.model(pts)
+    s = c.stages(len(pts) + 1)
+    assert s["round2"].tolist() == m["round2"].tolist()
+    c.close()
