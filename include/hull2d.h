@@ -54,8 +54,12 @@ typedef enum {
     HULL2D_ERR_OUT_OF_MEMORY = 5,/* device or pinned host allocation failed        */
     HULL2D_ERR_DEVICE = 6,       /* a HIP call failed; the context is unusable     */
     HULL2D_ERR_WEIGHTS = 7,      /* learned-filter weights missing or corrupt      */
-    HULL2D_ERR_UNIMPLEMENTED = 8
+    HULL2D_ERR_UNIMPLEMENTED = 8,
+    HULL2D_ERR_TOO_LARGE = 9     /* n above HULL2D_NOALLOC_MAX_POINTS (no-allocation entry point) */
 } hull2d_status;
+
+/* Largest input of hull2d_compute_noalloc (2^18 points). */
+#define HULL2D_NOALLOC_MAX_POINTS 262144
 
 /* Options.  Zero-initialise, then set struct_size = sizeof(hull2d_options). */
 typedef struct {
@@ -116,6 +120,10 @@ typedef struct {
      * keeps the same points.  round2_chunk, full_sort and filter do not
      * apply. */
     int32_t method;
+    /* 1: hull2d_create also reserves the host buffers of
+     * hull2d_compute_noalloc for its largest input (about 5 MB of pinned and
+     * 3 MB of pageable host memory); required by that entry point. */
+    int32_t reserve_noalloc;
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */
@@ -168,6 +176,24 @@ hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
 hull2d_status hull2d_compute(hull2d_ctx* ctx, const double* d_xy, int64_t n,
                              int32_t* h_out, int64_t cap, int64_t* n_out,
                              hull2d_stats* stats);
+
+/* hull2d_compute for callers that cannot allocate memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same result, with no hipMalloc, hipFree, pinned or heap
+ * allocation inside the call.  The device workspace is a fixed array of the
+ * library (about 23 MB on each device the library runs on, held until the
+ * process ends) sized for HULL2D_NOALLOC_MAX_POINTS points; the context must
+ * have been created with options.reserve_noalloc = 1 (else INVALID_ARG),
+ * which reserves the host buffers at creation.  Every call on a device
+ * shares that device's array, so calls that overlap on one device (from any
+ * context or thread) race; calls on one context are serialised by its
+ * stream as usual.  The array keeps the last call's contents; the call
+ * itself initialises everything it reads.
+ * TOO_LARGE: n > HULL2D_NOALLOC_MAX_POINTS (nothing is computed).  Other
+ * errors as hull2d_compute. */
+hull2d_status hull2d_compute_noalloc(hull2d_ctx* ctx, const double* d_xy, int64_t n,
+                                     int32_t* h_out, int64_t cap, int64_t* n_out,
+                                     hull2d_stats* stats);
 
 /* Hulls of S independent sets stored back to back at d_xy: set s is points
  * [h_offsets[s], h_offsets[s+1]) (host array of S+1 non-decreasing int64,

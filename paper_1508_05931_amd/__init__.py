@@ -25,15 +25,17 @@ STATUS = {
     0: "ok", 1: "invalid argument", 2: "non-finite coordinate",
     3: "coordinate magnitude outside [2^-300, 2^300]", 4: "output capacity too small",
     5: "out of memory", 6: "device error", 7: "weights missing or corrupt",
-    8: "not implemented",
+    8: "not implemented", 9: "input larger than HULL2D_NOALLOC_MAX_POINTS",
 }
-OK, INVALID_ARG, NONFINITE, RANGE, CAPACITY, OUT_OF_MEMORY, DEVICE, WEIGHTS, UNIMPLEMENTED = range(9)
+(OK, INVALID_ARG, NONFINITE, RANGE, CAPACITY, OUT_OF_MEMORY, DEVICE, WEIGHTS, UNIMPLEMENTED,
+ TOO_LARGE) = range(10)
+NOALLOC_MAX_POINTS = 262144  # HULL2D_NOALLOC_MAX_POINTS
 
 STAGES = ["extremes", "extremes_final", "filter1", "longest", "histogram", "sort0", "sort1",
           "sort2", "sort3", "ties", "ties_long", "buckets", "round2", "compact", "tail",
           "learned", "d2h", "host_scan", "scan"]
 
-EXPORTED = ["hull2d_create", "hull2d_compute", "hull2d_batch", "hull2d_destroy",
+EXPORTED = ["hull2d_create", "hull2d_compute", "hull2d_compute_noalloc", "hull2d_batch", "hull2d_destroy",
             "hull2d_status_string", "hull2d_set_weights", "hull2d_load_weights",
             "hull2d_get_weights", "hull2d_histogram", "hull2d_mlp_infer", "hull2d_train_step",
             "hull2d_debug_learned", "hull2d_debug_orient", "hull2d_debug_angle_key",
@@ -53,7 +55,7 @@ class _Options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("full_sort", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("batch_blocks_per_cu", ctypes.c_int32),
                 ("batch_order", ctypes.c_int32), ("batch_graph", ctypes.c_int32),
-                ("method", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("reserve_noalloc", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -102,6 +104,8 @@ def load_library():
     lib.hull2d_compute.argtypes = [vp, vp, i64, ctypes.POINTER(i32), i64, ctypes.POINTER(i64),
                                    ctypes.POINTER(_Stats)]
     lib.hull2d_compute.restype = ctypes.c_int
+    lib.hull2d_compute_noalloc.argtypes = lib.hull2d_compute.argtypes
+    lib.hull2d_compute_noalloc.restype = ctypes.c_int
     lib.hull2d_batch.argtypes = [vp, vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32), i64,
                                  ctypes.POINTER(i64), ctypes.POINTER(_Stats)]
     lib.hull2d_batch.restype = ctypes.c_int
@@ -192,7 +196,7 @@ class Hull2D:
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
                  profile: int = 0, full_sort: bool = False, learned: bool = False,
                  weights=None, batch_graph: bool = True, batch_blocks_per_cu: int | None = None,
-                 batch_order: int | None = None, method: int = 0):
+                 batch_order: int | None = None, reserve_noalloc: bool = False, method: int = 0):
         import torch
         lib = load_library()
         if device is None:
@@ -208,7 +212,8 @@ class Hull2D:
             batch_order = tuned.get("batch_order", 0)
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
                        int(bool(full_sort)), int(bool(learned)), int(batch_blocks_per_cu),
-                       int(batch_order), int(bool(batch_graph)), int(method))
+                       int(batch_order), int(bool(batch_graph)), int(method),
+                       int(bool(reserve_noalloc)))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))
@@ -266,6 +271,28 @@ class Hull2D:
             raise HullError(st, "hull2d_compute")
         self.last_stats = Stats._from(stats)
         return self._out[:hn.value].copy()
+
+    def compute_noalloc(self, xy, out: np.ndarray) -> np.ndarray:
+        """hull2d_compute_noalloc: the hull written into the caller's int32
+        array `out` (no allocation inside the library call; the context must
+        be created with reserve_noalloc=True).  Returns the filled prefix."""
+        import torch
+        if not (isinstance(xy, torch.Tensor) and xy.is_cuda and xy.dtype == torch.float64):
+            raise TypeError("xy must be a float64 CUDA tensor of shape [n, 2]")
+        if xy.dim() != 2 or xy.shape[1] != 2 or not xy.is_contiguous():
+            raise ValueError("xy must be a contiguous [n, 2] tensor")
+        if out.dtype != np.int32 or not out.flags["C_CONTIGUOUS"]:
+            raise TypeError("out must be a contiguous int32 array")
+        n = xy.shape[0]
+        stats = _Stats()
+        hn = ctypes.c_int64(0)
+        st = self._lib.hull2d_compute_noalloc(self._h, ctypes.c_void_p(xy.data_ptr() if n else 0), n,
+                                              _i32p(out), out.shape[0], ctypes.byref(hn),
+                                              ctypes.byref(stats))
+        if st != OK:
+            raise HullError(st, "hull2d_compute_noalloc")
+        self.last_stats = Stats._from(stats)
+        return out[:hn.value]
 
     def batch(self, xy, offsets) -> "tuple[np.ndarray, np.ndarray]":
         """Hulls of the sets xy[offsets[s]:offsets[s+1]] of a float64 [N, 2]

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -25,7 +26,8 @@ struct HostPt {
 };
 
 // The device buffers of one hull2d_compute call, carved out of one block of
-// device memory (the context's own allocation, grown on demand).
+// device memory: the context's own allocation (grown on demand), or the
+// library's fixed scratch array for the no-allocation entry point.
 struct Workspace {
     Cand* partial = nullptr;
     Params* prm = nullptr;
@@ -104,6 +106,9 @@ struct hull2d_ctx {
     std::vector<HostPt> cstk;
     bool last_chain = false;
     ChainHost last_chain_host{};
+    // created with reserve_noalloc: every host buffer above holds
+    // HULL2D_NOALLOC_MAX_POINTS points, so hull2d_compute_noalloc grows none
+    bool noalloc_ready = false;
 
     // batched form: workspace over all points of a batch, per-set results
     int64_t bcap_n = -1;
@@ -294,6 +299,43 @@ hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
     return HULL2D_OK;
 }
 
+// ---- the no-allocation entry point's fixed device workspace --------------
+// One array per device (each device that loads the library holds its own
+// copy until the process ends), laid out by plan() for the largest input the
+// entry point accepts.  Its host-side name is not a device address: host code
+// uses only the address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kNoAllocMax = HULL2D_NOALLOC_MAX_POINTS;
+constexpr size_t kScratchBytes = plan(kNoAllocMax).total;
+static_assert(kScratchBytes <= (size_t)32 << 20, "scratch stays modest");
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+// look-back epochs of each device's scratch, shared by all contexts on it
+uint32_t g_scratch_epoch[kMaxDevices] = {};
+
+// Looks up the scratch array's address on `device` (which must be current)
+// once, at context creation.  False if the runtime refused.
+bool init_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return false;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return true;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return false;
+    }
+    g_scratch_ptr[device] = p;
+    return true;
+}
+
+void* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 // The next look-back epoch of workspace w.  A look-back word keeps 30 bits
 // of the epoch that wrote it; when the counter comes round to a multiple of
 // 2^30 the words are cleared first (by a kernel), so that a word left by an
@@ -334,6 +376,13 @@ hull2d_status ensure_host(hull2d_ctx* c, int64_t m) {
     }
     c->h_cap = want;
     return HULL2D_OK;
+}
+
+// ensure_host, except that a no-allocation call never grows the buffers
+// (they were reserved for the largest input it accepts).
+hull2d_status host_buffers(hull2d_ctx* c, int64_t m, bool noalloc) {
+    if (noalloc) return m <= c->h_cap ? HULL2D_OK : HULL2D_ERR_TOO_LARGE;
+    return ensure_host(c, m);
 }
 
 // Batched form: device arrays over all N points of a batch (survivors,
@@ -606,8 +655,10 @@ hull2d_status begin_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32_
     return HULL2D_OK;
 }
 
-// Steps 1-8 for one hull, on workspace w (large enough for n points).
-hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, const double* d_xy,
+// Steps 1-8 for one hull, on workspace w (large enough for n points).  With
+// noalloc the host buffers must already be large enough for n points (the
+// context was created with reserve_noalloc) and nothing is allocated.
+hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, bool noalloc, const double* d_xy,
                            int64_t n, int32_t* h_out, int64_t cap, int64_t* n_out,
                            hull2d_stats* stats, std::chrono::steady_clock::time_point t_start) {
     const bool learned = c->opt.filter == 1;
@@ -735,7 +786,7 @@ hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, const double* d_xy,
         // 6-7, then Step 8 runs on the device and the hull and both statuses
         // go straight to host memory (at most kTailCap kept points per
         // region and P_l)
-        st = ensure_host(c, 2 * (int64_t)kTailCap + 1);
+        st = host_buffers(c, 2 * (int64_t)kTailCap + 1, noalloc);
         if (st != HULL2D_OK) return st;
         c->h_ds[1].tail_state = kTailUnset;  // the kernels overwrite these
         c->h_ds[1].scan_state = kScanUnset;
@@ -784,6 +835,7 @@ hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, const double* d_xy,
         // Runs of equal keys longer than one workgroup sorts: merge them, then
         // run the second round again on the corrected order.
         std::vector<uint32_t>& hl = c->huge_host;
+        if (noalloc && 2 * (size_t)DP.huge_runs > hl.capacity()) return HULL2D_ERR_TOO_LARGE;
         hl.resize(2 * (size_t)DP.huge_runs);
         HX_TRY(hipMemcpyAsync(hl.data(), w.huge_list, hl.size() * sizeof(uint32_t),
                               hipMemcpyDeviceToHost, s));
@@ -799,7 +851,7 @@ hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, const double* d_xy,
     }
     const DevStatus DS = DP;
     const int64_t m = (int64_t)DS.n_kept;
-    st = ensure_host(c, m + 1);
+    st = host_buffers(c, m + 1, noalloc);
     if (st != HULL2D_OK) return st;
     if (!tail_done && m <= (int64_t)kScanMaxParts * kScanPart) {
         // Step 8 on the device over the compacted kept points; the parts'
@@ -894,11 +946,11 @@ hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, const double* d_xy,
 // points to corner k+1 (a non-left turn pops, a repeat of the top is
 // skipped), the chains joined without their last points, the result rotated
 // to the lexicographically smallest vertex.
-hull2d_status compute_chain(hull2d_ctx* c, Workspace& w, const double* d_xy, int64_t n,
+hull2d_status compute_chain(hull2d_ctx* c, Workspace& w, bool noalloc, const double* d_xy, int64_t n,
                             int32_t* h_out, int64_t cap, int64_t* n_out, hull2d_stats* stats,
                             std::chrono::steady_clock::time_point t_start) {
     hipStream_t s = c->stream;
-    hull2d_status st = ensure_host(c, 4 * (int64_t)kChainHostCap);
+    hull2d_status st = host_buffers(c, 4 * (int64_t)kChainHostCap, noalloc);
     if (st != HULL2D_OK) return st;
     hipEvent_t ev_begin = c->ev[HULL2D_NUM_STAGES];
     hipEvent_t ev_end = c->ev[HULL2D_NUM_STAGES + 1];
@@ -923,6 +975,7 @@ hull2d_status compute_chain(hull2d_ctx* c, Workspace& w, const double* d_xy, int
     for (int r = 0; r < 4; ++r)
         if (!H.on_host[r]) off_host += H.n_kept[r];
     if (off_host > 0) {
+        if (noalloc && off_host > c->chain_xy.capacity()) return HULL2D_ERR_TOO_LARGE;
         c->chain_xy.resize(off_host);
         c->chain_ix.resize(off_host);
     }
@@ -950,6 +1003,7 @@ hull2d_status compute_chain(hull2d_ctx* c, Workspace& w, const double* d_xy, int
     stk.clear();
     size_t need = 8;
     for (int r = 0; r < 4; ++r) need += H.n_kept[r];
+    if (noalloc && need > stk.capacity()) return HULL2D_ERR_TOO_LARGE;
     stk.reserve(need);
     for (int k = 0; k < 4; ++k) {
         const size_t beg = stk.size();
@@ -1031,6 +1085,7 @@ const char* hull2d_status_string(hull2d_status s) {
         case HULL2D_ERR_DEVICE: return "device error";
         case HULL2D_ERR_WEIGHTS: return "learned-filter weights missing or corrupt";
         case HULL2D_ERR_UNIMPLEMENTED: return "not implemented";
+        case HULL2D_ERR_TOO_LARGE: return "input larger than HULL2D_NOALLOC_MAX_POINTS";
     }
     return "unknown status";
 }
@@ -1075,6 +1130,31 @@ hull2d_status hull2d_create(hull2d_ctx** out, int device, void* hip_stream,
         (void)hipGetLastError();
         hull2d_destroy(c);
         return HULL2D_ERR_OUT_OF_MEMORY;
+    }
+    // the no-allocation entry point: the fixed device workspace of this
+    // device, and (on request) host buffers for its largest input
+    const bool have_scratch = init_scratch(device);
+    if (c->opt.reserve_noalloc) {
+        if (!have_scratch) {
+            hull2d_destroy(c);
+            return HULL2D_ERR_DEVICE;
+        }
+        if (ensure_host(c, kNoAllocMax + 1) != HULL2D_OK) {
+            hull2d_destroy(c);
+            return HULL2D_ERR_OUT_OF_MEMORY;
+        }
+        try {
+            c->stk.reserve((size_t)kNoAllocMax + 1);
+            c->hull.reserve((size_t)kNoAllocMax + 1);
+            c->huge_host.reserve(2 * ((size_t)kNoAllocMax / kRunCap + 2));
+            c->chain_xy.reserve((size_t)kNoAllocMax);
+            c->chain_ix.reserve((size_t)kNoAllocMax);
+            c->cstk.reserve((size_t)kNoAllocMax + 8);
+        } catch (...) {
+            hull2d_destroy(c);
+            return HULL2D_ERR_OUT_OF_MEMORY;
+        }
+        c->noalloc_ready = true;
     }
     // Stage events only time the stream (the host waits on ev_sync): without
     // the system-scope fence a record does not write back and invalidate the
@@ -1124,8 +1204,24 @@ hull2d_status hull2d_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32
     if (st != HULL2D_OK || n == 0) return st;
     st = ensure_workspace(c, n);
     if (st != HULL2D_OK) return st;
-    if (c->opt.method == 1) return compute_chain(c, c->own, d_xy, n, h_out, cap, n_out, stats, t_start);
-    return compute_impl(c, c->own, d_xy, n, h_out, cap, n_out, stats, t_start);
+    if (c->opt.method == 1) return compute_chain(c, c->own, false, d_xy, n, h_out, cap, n_out, stats, t_start);
+    return compute_impl(c, c->own, false, d_xy, n, h_out, cap, n_out, stats, t_start);
+}
+
+hull2d_status hull2d_compute_noalloc(hull2d_ctx* c, const double* d_xy, int64_t n, int32_t* h_out,
+                                     int64_t cap, int64_t* n_out, hull2d_stats* stats) {
+    auto t_start = std::chrono::steady_clock::now();
+    if (c && n > kNoAllocMax) return HULL2D_ERR_TOO_LARGE;
+    if (c && !c->noalloc_ready) return HULL2D_ERR_INVALID_ARG;
+    hull2d_status st = begin_compute(c, d_xy, n, h_out, cap, n_out, stats);
+    if (st != HULL2D_OK || n == 0) return st;
+    void* base = scratch_address(c->device);
+    if (!base) return HULL2D_ERR_DEVICE;
+    Workspace w;
+    carve((char*)base, kNoAllocMax, w);
+    w.epoch = &g_scratch_epoch[c->device];
+    if (c->opt.method == 1) return compute_chain(c, w, true, d_xy, n, h_out, cap, n_out, stats, t_start);
+    return compute_impl(c, w, true, d_xy, n, h_out, cap, n_out, stats, t_start);
 }
 
 hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_offsets, int32_t S,
