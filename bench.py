@@ -70,7 +70,7 @@ def measured_traffic(kernel: str):
 
 
 KERNEL_STAGES = ["extremes", "filter1", "longest", "buckets", "histogram", "sort0", "sort1",
-                 "sort2", "sort3", "ties", "ties_long", "round2", "compact", "tail"]
+                 "sort2", "sort3", "ties", "ties_long", "round2", "compact", "tail", "scan"]
 
 
 def kernel_bytes(stage: str, n: int, ms: int, nc: int, m2: int, full: bool) -> float:
@@ -96,6 +96,8 @@ def kernel_bytes(stage: str, n: int, ms: int, nc: int, m2: int, full: bool) -> f
         "compact": 1.0 * nc + 44.0 * m2,
         # candidates' keys read, kept points read and written to the host
         "tail": 8.0 * nc + 40.0 * m2,
+        # Step 8 on the device: the kept points read (20 B each)
+        "scan": 20.0 * m2,
     }[stage]
 
 

@@ -3,7 +3,8 @@
  *
  * The data-parallel first stage of gScan (G. Mei, "gScan: Accelerating
  * Graham Scan on the GPU", Sections 2 and 3) as hand-written HIP kernels,
- * followed by the paper's final stack scan (Step 8, on the device):
+ * followed by the paper's final stack scan (Step 8, on the host or on the
+ * device, options.scan):
  *
  *   Step 1  four extreme points by parallel reduction           (Section 3.1)
  *   Step 2  discard points strictly inside their quadrilateral  (Section 3.1)
@@ -124,6 +125,13 @@ typedef struct {
      * hull2d_compute_noalloc for its largest input (about 5 MB of pinned and
      * 3 MB of pageable host memory); required by that entry point. */
     int32_t reserve_noalloc;
+    /* Where Step 8 runs.  0 (default): on the device when at least 65,536
+     * points are kept by round 2 and the one-workgroup tail did not take
+     * them, else on the host (faster for fewer kept points); 1: on the
+     * device whenever possible; 2: on the host.  Same output either way;
+     * the device falls back to the host when the chains of its parts exceed
+     * one workgroup's LDS. */
+    int32_t scan;
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */

@@ -55,7 +55,8 @@ class _Options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("full_sort", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("batch_blocks_per_cu", ctypes.c_int32),
                 ("batch_order", ctypes.c_int32), ("batch_graph", ctypes.c_int32),
-                ("method", ctypes.c_int32), ("reserve_noalloc", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("reserve_noalloc", ctypes.c_int32),
+                ("scan", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -196,7 +197,8 @@ class Hull2D:
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
                  profile: int = 0, full_sort: bool = False, learned: bool = False,
                  weights=None, batch_graph: bool = True, batch_blocks_per_cu: int | None = None,
-                 batch_order: int | None = None, reserve_noalloc: bool = False, method: int = 0):
+                 batch_order: int | None = None, reserve_noalloc: bool = False, method: int = 0,
+                 scan: int = 0):
         import torch
         lib = load_library()
         if device is None:
@@ -213,7 +215,7 @@ class Hull2D:
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
                        int(bool(full_sort)), int(bool(learned)), int(batch_blocks_per_cu),
                        int(batch_order), int(bool(batch_graph)), int(method),
-                       int(bool(reserve_noalloc)))
+                       int(bool(reserve_noalloc)), int(scan))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))

@@ -171,6 +171,9 @@ struct hull2d_ctx {
 namespace {
 
 constexpr int kMaxSegs = 8192;  // round-1 blocks (resident blocks of the whole chip) at most
+// Step 8 on the device by default from this many kept points on (the host
+// scan is faster below; measured on the 20M square and disk)
+constexpr int64_t kScanAutoMin = 65536;
 
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 constexpr size_t cdiv(size_t a, size_t b) { return (a + b - 1) / b; }
@@ -649,6 +652,7 @@ hull2d_status begin_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32_
     c->last_learned = false;
     c->last_chain = false;
     if (c->opt.method != 0 && c->opt.method != 1) return HULL2D_ERR_INVALID_ARG;
+    if (c->opt.scan < 0 || c->opt.scan > 2) return HULL2D_ERR_INVALID_ARG;
     if (c->opt.method == 0 && c->opt.filter == 1 && !c->have_weights) return HULL2D_ERR_WEIGHTS;
     if (n == 0) return HULL2D_OK;
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;
@@ -680,25 +684,36 @@ hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, bool noalloc, const doub
     hipEvent_t ev_end = c->ev[HULL2D_NUM_STAGES + 1];
     if (c->have_events) HX_TRY(hipEventRecord(ev_begin, s));
 
-    // Step 1
-    // learned filter first: sample histogram, network and the sample's
-    // farthest point along each direction (one workgroup); the end of Step 1
-    // then builds the discard polygon.  The proposal does not depend on the
-    // Step-1 pass, but running it on a second stream beside it measured no
-    // faster: the two share the device.
+    // Step 1 and Steps 2-3
+    const int segs = std::min(
+        filter1_blocks(n, c->cu_count, learned ? c->occ.filter1_poly : c->occ.filter1),
+        learned ? std::min(kMaxSegs, kExtGridMax) : kMaxSegs);
     if (learned) {
+        // The learned filter: first the proposal (sample histogram, network,
+        // the sample's farthest point along each direction and the hull of
+        // those points; one workgroup), then one pass over the input takes
+        // Step 1's extremes and drops the points strictly inside that hull
+        // (the final polygon contains it), the end of Step 1 builds the final
+        // polygon, and Steps 2-3 read only the points the pass kept.  The
+        // pre-filtered points sit in out_xy / out_idx (not yet in use), their
+        // per-block counts in seg_off (Step 5 writes it later).
         HX_TRY(launch_front(d_xy, n, mlp_dev(c), c->learn, s));
         mark(HULL2D_STAGE_LEARNED);
+        uint32_t* pre_idx = reinterpret_cast<uint32_t*>(w.out_idx);
+        HX_TRY(launch_pre(d_xy, n, segs, c->learn, w.partial, w.out_xy, pre_idx, w.seg_off, s));
+        HX_TRY(launch_extremes_final(w.partial, segs, w.prm, w.ds, c->learn, s));
+        mark(HULL2D_STAGE_EXTREMES);
+        HX_TRY(launch_filter1_pre(w.out_xy, pre_idx, w.seg_off, n, segs, w.prm, &c->learn->poly, w.comp_xy,
+                                  w.comp_idx, w.keys_a, w.seg_count, w.blk_d2, w.blk_best, w.ds, s));
+        mark(HULL2D_STAGE_FILTER1);
+    } else {
+        const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
+        HX_TRY(launch_extremes(d_xy, n, w.partial, grid_ext, w.prm, w.ds, nullptr, s));
+        mark(HULL2D_STAGE_EXTREMES);
+        HX_TRY(launch_filter1(d_xy, n, segs, w.prm, nullptr, w.comp_xy, w.comp_idx, w.keys_a,
+                              w.seg_count, w.blk_d2, w.blk_best, w.ds, s));
+        mark(HULL2D_STAGE_FILTER1);
     }
-    const int grid_ext = extremes_grid(n, c->cu_count, c->occ.extremes);
-    HX_TRY(launch_extremes(d_xy, n, w.partial, grid_ext, w.prm, w.ds, learned ? c->learn : nullptr, s));
-    mark(HULL2D_STAGE_EXTREMES);
-    // Steps 2-3
-    const int segs = std::min(
-        filter1_blocks(n, c->cu_count, learned ? c->occ.filter1_poly : c->occ.filter1), kMaxSegs);
-    HX_TRY(launch_filter1(d_xy, n, segs, w.prm, learned ? &c->learn->poly : nullptr, w.comp_xy,
-                          w.comp_idx, w.keys_a, w.seg_count, w.blk_d2, w.blk_best, w.ds, s));
-    mark(HULL2D_STAGE_FILTER1);
     // Step 5 (needs every survivor's distance; the sort does not)
     const bool full = c->opt.round2_chunk != 0 || c->opt.full_sort != 0;
     HX_TRY(launch_longest(segs, w.blk_d2, w.blk_best, w.seg_count, w.seg_off, w.comp_xy, w.keys_a,
@@ -781,21 +796,32 @@ hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, bool noalloc, const doub
     bool tail_done = false;
     bool scanned = false;  // Step 8 ran on the device: the hull is in c->h_hull
     uint32_t* scan_ticket = &c->ctr->ticket[kTicketScan * 16];
+    // Step 8 on the device for the tail's kept points only when asked: at
+    // the tail's sizes (at most 2 kTailCap + 1 kept points) the host scan
+    // of the kept points is faster
+    const bool scan_tail = c->opt.scan == 1;
     if (!full) {
         // small candidate sets: one workgroup per region does Steps 4 and
-        // 6-7, then Step 8 runs on the device and the hull and both statuses
-        // go straight to host memory (at most kTailCap kept points per
-        // region and P_l)
+        // 6-7; the kept points (or, with the device scan, the hull) and both
+        // statuses go straight to host memory (at most kTailCap kept points
+        // per region and P_l)
         st = host_buffers(c, 2 * (int64_t)kTailCap + 1, noalloc);
         if (st != HULL2D_OK) return st;
         c->h_ds[1].tail_state = kTailUnset;  // the kernels overwrite these
         c->h_ds[1].scan_state = kScanUnset;
-        HX_TRY(launch_tail(w.cand_xy, w.cand_idx, w.cand_key, w.cand_kap, w.bmax, w.prm,
-                           w.ds, w.tail_slot, w.tail_count, nullptr, nullptr, nullptr, s));
-        mark(HULL2D_STAGE_TAIL);
-        HX_TRY(launch_scan_tail(w.cand_xy, w.cand_idx, w.tail_slot, w.tail_count, w.ds, w.out_xy,
-                                w.keys_b, w.part_len, scan_ticket, c->h_hull_dev, c->h_ds_dev, s));
-        mark(HULL2D_STAGE_SCAN);
+        if (scan_tail) {
+            HX_TRY(launch_tail(w.cand_xy, w.cand_idx, w.cand_key, w.cand_kap, w.bmax, w.prm,
+                               w.ds, w.tail_slot, w.tail_count, nullptr, nullptr, nullptr, s));
+            mark(HULL2D_STAGE_TAIL);
+            HX_TRY(launch_scan_tail(w.cand_xy, w.cand_idx, w.tail_slot, w.tail_count, w.ds, w.out_xy,
+                                    w.keys_b, w.part_len, scan_ticket, c->h_hull_dev, c->h_ds_dev, s));
+            mark(HULL2D_STAGE_SCAN);
+        } else {
+            HX_TRY(launch_tail(w.cand_xy, w.cand_idx, w.cand_key, w.cand_kap, w.bmax, w.prm,
+                               w.ds, w.tail_slot, w.tail_count, c->h_xy_dev, c->h_idx_dev,
+                               c->h_ds_dev, s));
+            mark(HULL2D_STAGE_TAIL);
+        }
         // one wait ends the call unless the candidates did not fit
         if (c->have_events) HX_TRY(hipEventRecord(ev_end, s));
         HX_TRY(spin_sync(c));
@@ -805,11 +831,11 @@ hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, bool noalloc, const doub
             if (st != HULL2D_OK) return st;
         }
         tail_done = c->h_ds[1].tail_state == kTailDone;
-        scanned = tail_done && c->h_ds[1].scan_state == kScanDone;
+        scanned = scan_tail && tail_done && c->h_ds[1].scan_state == kScanDone;
         // the scan did nothing: its event is recorded again if the list
         // form runs later (one event per stage)
         if (!tail_done && n_marks > 0 && marks[n_marks - 1] == HULL2D_STAGE_SCAN) --n_marks;
-        if (tail_done && !scanned) {
+        if (scan_tail && tail_done && !scanned) {
             // the parts' chains were too many for one workgroup: the kept
             // points go to host memory for the host scan
             HX_TRY(launch_tail_out(w.cand_xy, w.cand_idx, w.ds, w.tail_slot, w.tail_count, c->h_xy_dev,
@@ -853,7 +879,8 @@ hull2d_status compute_impl(hull2d_ctx* c, Workspace& w, bool noalloc, const doub
     const int64_t m = (int64_t)DS.n_kept;
     st = host_buffers(c, m + 1, noalloc);
     if (st != HULL2D_OK) return st;
-    if (!tail_done && m <= (int64_t)kScanMaxParts * kScanPart) {
+    const bool scan_list = c->opt.scan == 1 || (c->opt.scan == 0 && m >= kScanAutoMin);
+    if (!tail_done && scan_list && m <= (int64_t)kScanMaxParts * kScanPart) {
         // Step 8 on the device over the compacted kept points; the parts'
         // chains go to arrays that are dead by now
         double2* part_xy = pxy == w.cand_xy ? w.comp_xy : w.cand_xy;

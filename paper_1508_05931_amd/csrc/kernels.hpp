@@ -56,6 +56,16 @@ struct LearnOut;
 hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid, Params* prm,
                            DevStatus* ds, LearnOut* lo, hipStream_t s);
 int extremes_grid(int64_t n, int cu_count, int per_cu);
+// The final reduction of Step 1 alone (over nblocks partial results).
+hipError_t launch_extremes_final(const Cand* partial, int nblocks, Params* prm, DevStatus* ds,
+                                 LearnOut* lo, hipStream_t s);
+// Learned filter, one pass over the input (blocks = the Steps 2-3 blocks,
+// at most kExtGridMax): Step 1's partial extremes of block b's input range,
+// and the points of that range not strictly inside lo->spoly (which the
+// final discard polygon contains), compacted in input order to pre_xy /
+// pre_idx at the block's range, their count in pre_count[b].
+hipError_t launch_pre(const double* xy, int64_t n, int blocks, const LearnOut* lo, Cand* partial,
+                      double2* pre_xy, uint32_t* pre_idx, uint32_t* pre_count, hipStream_t s);
 
 // Resident blocks per compute unit of the fixed-grid streaming kernels (from
 // the runtime's occupancy calculator), so that one launch fills the chip
@@ -91,6 +101,13 @@ hipError_t launch_filter1(const double* xy, int64_t n, int blocks, const Params*
                           const Poly* poly, double2* comp_xy, uint32_t* comp_idx, uint32_t* keys,
                           uint32_t* seg_count, double* blk_d2, uint32_t* blk_best, DevStatus* ds,
                           hipStream_t s);
+
+// Steps 2-3 with the learned polygon over launch_pre's output instead of the
+// input (the same blocks and ranges).
+hipError_t launch_filter1_pre(const double2* pre_xy, const uint32_t* pre_idx, const uint32_t* pre_count,
+                              int64_t n, int blocks, const Params* prm, const Poly* poly,
+                              double2* comp_xy, uint32_t* comp_idx, uint32_t* keys, uint32_t* seg_count,
+                              double* blk_d2, uint32_t* blk_best, DevStatus* ds, hipStream_t s);
 
 // Step 5 and the segment offsets (one block); also clears bmax (2 x
 // kBuckets, the bucketed filter's sampled maxima) unless it is NULL.
@@ -236,6 +253,7 @@ struct MlpDev {
 // What the proposal produced for one hull.
 struct LearnOut {
     Poly poly;                  // the discard polygon
+    Poly spoly;                 // the hull of the direction candidates alone (inside poly)
     double dirs[2 * kMlpDirs];  // directions used (network output, or the fallback)
     float y[kMlpOut];           // raw network outputs
     int32_t cand[kPolyMax];     // candidates: the four Step-1 extremes, then one per direction

@@ -256,13 +256,16 @@ __global__ __launch_bounds__(1024) void k_extremes_final(const Cand* __restrict_
 // ---------------------------------------------------------------------------
 // kPoly: the learned discard polygon (which contains the quadrilateral)
 // replaces it.
-template <bool kPoly>
+// kPre: the input is the learned pre-filter's output (launch_pre): block b
+// reads in_count[b] points at its range, their input indices in in_idx.
+template <bool kPoly, bool kPre = false>
 __global__ __launch_bounds__(kF1Block) void k_filter1(
     const double2* __restrict__ xy, int64_t n, int64_t chunk, const Params* __restrict__ prm,
     const Poly* __restrict__ poly,
     double2* __restrict__ comp_xy, uint32_t* __restrict__ comp_idx, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ seg_count, double* __restrict__ blk_d2, uint32_t* __restrict__ blk_best,
-    DevStatus* __restrict__ ds) {
+    DevStatus* __restrict__ ds, const uint32_t* __restrict__ in_idx = nullptr,
+    const uint32_t* __restrict__ in_count = nullptr) {
     constexpr int NW = kF1Block / 64;
     constexpr int G = kF1Ipt * NW;  // (item, wave) groups in position order
     __shared__ uint32_t s_off[G];
@@ -296,7 +299,7 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
         ey[j] = prm->ey[j];
     }
     const int64_t beg = (int64_t)blockIdx.x * chunk;
-    const int64_t end = min(n, beg + chunk);
+    const int64_t end = kPre ? beg + (int64_t)in_count[blockIdx.x] : min(n, beg + chunk);
     int64_t cursor = beg;  // next output position of this segment
     double bd2 = -1.0;     // this thread's farthest survivor so far
     uint32_t bidx = 0xFFFFFFFFu, bslot = 0xFFFFFFFFu;
@@ -331,6 +334,15 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
         }
         uint64_t mask[kF1Ipt];
         uint32_t key[kF1Ipt];
+        // the points' input indices (their positions, unless pre-filtered)
+        uint32_t pid[kPre ? kF1Ipt : 1];
+        if constexpr (kPre) {
+#pragma unroll
+            for (int k = 0; k < kF1Ipt; ++k) {
+                const int64_t pos = base + k * kF1Block + threadIdx.x;
+                pid[k] = pos < end ? in_idx[pos] : 0u;
+            }
+        }
         double td2 = -1.0;
         uint32_t tidx = 0xFFFFFFFFu, tgrp = 0, trank = 0;
 #pragma unroll
@@ -349,14 +361,16 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
                 if (surv) {
                     key[k] = angle_key(px, py, x0, y0);
                     const double d2 = dist2(px, py, x0, y0);
-                    const bool take = (d2 > td2) | ((d2 == td2) & ((uint32_t)pos < tidx));
+                    const uint32_t pi = kPre ? pid[kPre ? k : 0] : (uint32_t)pos;
+                    const bool take = (d2 > td2) | ((d2 == td2) & (pi < tidx));
                     td2 = take ? d2 : td2;
-                    tidx = take ? (uint32_t)pos : tidx;
+                    tidx = take ? pi : tidx;
                     tgrp = take ? (uint32_t)(k * NW + wave) : tgrp;
                 }
             }
             mask[k] = __ballot(surv);
-            if (surv && tidx == (uint32_t)pos) trank = __popcll(mask[k] & lanemask_lt());
+            if (surv && tidx == (kPre ? pid[kPre ? k : 0] : (uint32_t)pos))
+                trank = __popcll(mask[k] & lanemask_lt());
             if (lane == 0) s_off[k * NW + wave] = (uint32_t)__popcll(mask[k]);
         }
         __syncthreads();
@@ -376,7 +390,7 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
                 // bucket maxima and the candidates), from the cache when
                 // they are still there
                 comp_xy[o] = p[k];
-                comp_idx[o] = (uint32_t)pos;
+                comp_idx[o] = kPre ? pid[kPre ? k : 0] : (uint32_t)pos;
                 keys[o] = key[k];
             }
         }
@@ -426,6 +440,119 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
         seg_count[blockIdx.x] = (uint32_t)(cursor - beg);
         if (pc) atomicAdd(&ds->n_p0, pc);
     }
+}
+
+// Learned filter: Step 1's partial extremes and the pre-filter in one pass.
+// Block b owns the input range [b*chunk, (b+1)*chunk) (as k_filter1 does)
+// and compacts, in input order, the points not strictly inside the
+// direction candidates' hull (lo->spoly) into the same range of pre_xy /
+// pre_idx.  That hull lies inside the final discard polygon (the hull of
+// the candidates and the four extremes), so only points the final test
+// would discard are dropped here; the final test then reads the few points
+// left instead of the input.  No common error bound is known yet (the
+// bounding box comes from this pass), so each orientation test uses its own,
+// and a point whose tests float64 cannot settle is kept (the final, exact
+// test settles it).
+// Points per thread and tile of k_pre: more loads in flight than Steps 2-3
+// (the pass writes little).
+constexpr int kPreIpt = 4;
+constexpr int kPreTile = kF1Block * kPreIpt;
+
+__global__ __launch_bounds__(kF1Block) void k_pre(const double2* __restrict__ xy, int64_t n, int64_t chunk,
+                                                  const LearnOut* __restrict__ lo,
+                                                  Cand* __restrict__ partial, double2* __restrict__ pre_xy,
+                                                  uint32_t* __restrict__ pre_idx,
+                                                  uint32_t* __restrict__ pre_count) {
+    constexpr int NW = kF1Block / 64;
+    constexpr int G = kPreIpt * NW;
+    static_assert(G <= 64, "one wave scans the group counts");
+    __shared__ uint32_t s_off[G];
+    __shared__ uint32_t s_total;
+    __shared__ Cand s_c[NW][4];
+    __shared__ uint32_t s_flags;
+    __shared__ PolyF s_poly;
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    if (threadIdx.x == 0) {
+        make_polyf(lo->spoly, s_poly);
+        s_flags = 0;
+    }
+    __syncthreads();
+    Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
+    uint32_t bad = 0;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = min(n, beg + chunk);
+    int64_t cursor = beg;
+    double2 nx[kPreIpt];
+#pragma unroll
+    for (int k = 0; k < kPreIpt; ++k) {
+        const int64_t pos = beg + k * kF1Block + threadIdx.x;
+        if (pos < end) nx[k] = load_stream(&xy[pos]);
+    }
+    for (int64_t base = beg; base < end; base += kPreTile) {
+        double2 p[kPreIpt];
+#pragma unroll
+        for (int k = 0; k < kPreIpt; ++k) p[k] = nx[k];
+#pragma unroll
+        for (int k = 0; k < kPreIpt; ++k) {
+            const int64_t pos = base + kPreTile + k * kF1Block + threadIdx.x;
+            if (pos < end) nx[k] = load_stream(&xy[pos]);
+        }
+        uint64_t mask[kPreIpt];
+#pragma unroll
+        for (int k = 0; k < kPreIpt; ++k) {
+            const int64_t pos = base + k * kF1Block + threadIdx.x;
+            bool keep = false;
+            if (pos < end) {
+                const double px = p[k].x, py = p[k].y;
+                const bool need = (px <= c[0].x) | (py <= c[1].y) | (px >= c[2].x) | (py >= c[3].y);
+                if (need) offer(c, px, py, (int32_t)pos);
+                bad |= domain_flags(px) | domain_flags(py);
+                keep = !poly_surely_inside_f32(s_poly, px, py);
+            }
+            mask[k] = __ballot(keep);
+            if (lane == 0) s_off[k * NW + wave] = (uint32_t)__popcll(mask[k]);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t v = lane < G ? s_off[lane] : 0u;
+            uint32_t inc = wave_incl_scan(v);
+            if (lane < G) s_off[lane] = inc - v;
+            if (lane == 63) s_total = inc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPreIpt; ++k) {
+            if ((mask[k] >> lane) & 1ull) {
+                const int64_t pos = base + k * kF1Block + threadIdx.x;
+                const int64_t o = cursor + s_off[k * NW + wave] + (uint32_t)__popcll(mask[k] & lanemask_lt());
+                pre_xy[o] = p[k];
+                pre_idx[o] = (uint32_t)pos;
+            }
+        }
+        cursor += s_total;
+        __syncthreads();
+    }
+    reduce4_wave(c);
+    if (bad) atomicOr(&s_flags, bad);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_c[wave][k] = c[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = (int)threadIdx.x;
+        Cand b = s_c[0][k];
+        for (int w = 1; w < NW; ++w) {
+            const Cand o = s_c[w][k];
+            if (k == 0) take_better<0>(b, o);
+            else if (k == 1) take_better<1>(b, o);
+            else if (k == 2) take_better<2>(b, o);
+            else take_better<3>(b, o);
+        }
+        b.pad = (int32_t)s_flags;
+        partial[(int64_t)blockIdx.x * 4 + k] = b;
+    }
+    if (threadIdx.x == 0) pre_count[blockIdx.x] = (uint32_t)(cursor - beg);
 }
 
 // Step 5 and the segment totals: one block.  The farthest survivor (largest
@@ -900,6 +1027,31 @@ hipError_t launch_extremes(const double* xy, int64_t n, Cand* partial, int grid,
     return hipGetLastError();
 }
 
+hipError_t launch_extremes_final(const Cand* partial, int nblocks, Params* prm, DevStatus* ds,
+                                 LearnOut* lo, hipStream_t s) {
+    if (lo)
+        hipLaunchKernelGGL(k_extremes_final<true>, dim3(1), dim3(1024), 0, s, partial, nblocks, prm, ds, lo);
+    else
+        hipLaunchKernelGGL(k_extremes_final<false>, dim3(1), dim3(1024), 0, s, partial, nblocks, prm, ds,
+                           nullptr);
+    return hipGetLastError();
+}
+hipError_t launch_pre(const double* xy, int64_t n, int blocks, const LearnOut* lo, Cand* partial,
+                      double2* pre_xy, uint32_t* pre_idx, uint32_t* pre_count, hipStream_t s) {
+    if (blocks > kExtGridMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pre, dim3(blocks), dim3(kF1Block), 0, s, reinterpret_cast<const double2*>(xy), n,
+                       filter1_chunk(n, blocks), lo, partial, pre_xy, pre_idx, pre_count);
+    return hipGetLastError();
+}
+hipError_t launch_filter1_pre(const double2* pre_xy, const uint32_t* pre_idx, const uint32_t* pre_count,
+                              int64_t n, int blocks, const Params* prm, const Poly* poly,
+                              double2* comp_xy, uint32_t* comp_idx, uint32_t* keys, uint32_t* seg_count,
+                              double* blk_d2, uint32_t* blk_best, DevStatus* ds, hipStream_t s) {
+    hipLaunchKernelGGL((k_filter1<true, true>), dim3(blocks), dim3(kF1Block), 0, s, pre_xy, n,
+                       filter1_chunk(n, blocks), prm, poly, comp_xy, comp_idx, keys, seg_count, blk_d2,
+                       blk_best, ds, pre_idx, pre_count);
+    return hipGetLastError();
+}
 int extremes_grid(int64_t n, int cu_count, int per_cu) {
     int64_t g = std::min<int64_t>((int64_t)cu_count * per_cu, ceil_div(n, kExtBlock * 8));
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, kExtGridMax));

@@ -361,7 +361,25 @@ __global__ __launch_bounds__(kFB) void k_front(const double2* __restrict__ xy, i
         if (lane == 0) s_c[d] = bs;
     }
     __syncthreads();
+    // the hull of the direction candidates alone: the final discard polygon
+    // (their hull with the Step-1 extremes) contains it, so the Step-1 pass
+    // can already drop the points strictly inside it
+    __shared__ double s_cx[kDirs], s_cy[kDirs];
+    __shared__ int32_t s_cu[kDirs];
+    __shared__ Poly s_sp;
+    if (t < kDirs) {
+        const int32_t sl = s_c[t];
+        const double2 q = sl == INT32_MAX ? make_double2(0.0, 0.0) : s_pt[sl];
+        s_cx[t] = q.x;
+        s_cy[t] = q.y;
+        s_cu[t] = sl != INT32_MAX && finite_d(q.x) && finite_d(q.y);
+    }
+    __syncthreads();
+    hull_of_points<kDirs>(s_cx, s_cy, s_cu, s_sp);
     // every global store at the end: a barrier waits for outstanding stores
+    static_assert(sizeof(Poly) % 8 == 0, "double copies");
+    for (int i = t; i < (int)(sizeof(Poly) / 8); i += kFB)
+        reinterpret_cast<double*>(&lo->spoly)[i] = reinterpret_cast<const double*>(&s_sp)[i];
     if (t < kMlpOut) lo->y[t] = s_y[t];
     if (t >= 64 && t < 64 + 2 * kDirs) lo->dirs[t - 64] = s_u[t - 64];
     if (t >= 128 && t < 128 + kDirs) {

@@ -198,20 +198,105 @@ __device__ inline int poly_orient(double ax, double ay, double bx, double by, do
 // j and j+1, and strictly left of the edge j -> j+1.  A point on a diagonal
 // strictly before its far end is inside (the diagonal's interior lies in the
 // polygon's), which the last test decides as well.
+// kOwnBound: every test takes the adaptive orient's own error bound (for
+// points outside any known bounding box), not the common bound Q.qb.
+template <bool kOwnBound = false>
 __device__ inline bool poly_inside(const Poly& Q, double x, double y) {
     const int m = Q.nv;
     if (m < 3) return false;
     const double x0 = Q.px[0], y0 = Q.py[0], qb = Q.qb;
-    if (poly_orient(x0, y0, Q.px[1], Q.py[1], qb, x, y) <= 0) return false;
-    if (poly_orient(x0, y0, Q.px[m - 1], Q.py[m - 1], qb, x, y) >= 0) return false;
+    auto side = [&](double ax, double ay, double bx, double by) {
+        return kOwnBound ? orient(ax, ay, bx, by, x, y) : poly_orient(ax, ay, bx, by, qb, x, y);
+    };
+    if (side(x0, y0, Q.px[1], Q.py[1]) <= 0) return false;
+    if (side(x0, y0, Q.px[m - 1], Q.py[m - 1]) >= 0) return false;
     // invariant: p is left of (or on) diagonal lo, strictly right of diagonal hi
     int lo = 1, hi = m - 1;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (poly_orient(x0, y0, Q.px[mid], Q.py[mid], qb, x, y) >= 0) lo = mid;
+        if (side(x0, y0, Q.px[mid], Q.py[mid]) >= 0) lo = mid;
         else hi = mid;
     }
-    return poly_orient(Q.px[lo], Q.py[lo], Q.px[hi], Q.py[hi], qb, x, y) > 0;
+    return side(Q.px[lo], Q.py[lo], Q.px[hi], Q.py[hi]) > 0;
+}
+
+// Conservative polygon test for a pre-filter: true only when float64
+// arithmetic alone proves p strictly inside (every orientation it relies on
+// clears the forward error bound); "cannot tell" counts as not inside, so a
+// point it drops is one the exact test drops too.  A wedge chosen wrongly
+// next to a diagonal is harmless: a convex polygon's inside points lie left
+// of every edge, and points beyond a corner lie right of both its edges.
+__device__ inline int sure_side(double ax, double ay, double bx, double by, double x, double y) {
+    const double acx = ax - x, bcy = by - y, acy = ay - y, bcx = bx - x;
+    const double l = acx * bcy, r = acy * bcx;
+    const double det = l - r, bound = kOrientBound * (fabs(l) + fabs(r));
+    return det > bound ? 1 : (-det > bound ? -1 : 0);
+}
+__device__ inline bool poly_surely_inside(const Poly& Q, double x, double y) {
+    const int m = Q.nv;
+    if (m < 3) return false;
+    const double x0 = Q.px[0], y0 = Q.py[0];
+    if (sure_side(x0, y0, Q.px[1], Q.py[1], x, y) <= 0) return false;
+    if (sure_side(x0, y0, Q.px[m - 1], Q.py[m - 1], x, y) >= 0) return false;
+    int lo = 1, hi = m - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sure_side(x0, y0, Q.px[mid], Q.py[mid], x, y) >= 0) lo = mid;
+        else hi = mid;
+    }
+    return sure_side(Q.px[lo], Q.py[lo], Q.px[hi], Q.py[hi], x, y) > 0;
+}
+
+// The same test in float32 on coordinates relative to corner 0 (faster; for
+// the pre-filter only).  Corners and point enter as float32 differences from
+// corner 0, each within a relative 2^-24 (one float64 subtraction, one
+// conversion); with M the largest magnitude among them, every difference of
+// two of them is off by at most 3.01 u M, every product by 16.04 u M^2, a
+// determinant by 40.1 u M^2 (u = 2^-24), so a determinant beyond
+// 48 u M^2 has the exact sign.  Magnitudes outside [2^-50, 2^50] (or not
+// finite) settle nothing.
+struct PolyF {
+    int32_t nv;
+    float m;                     // largest corner magnitude (relative to corner 0)
+    double x0, y0;               // corner 0
+    float px[kPolyMax], py[kPolyMax];
+};
+
+__device__ inline void make_polyf(const Poly& Q, PolyF& F) {
+    F.nv = Q.nv;
+    F.x0 = Q.px[0];
+    F.y0 = Q.py[0];
+    float m = 0.f;
+    for (int j = 0; j < kPolyMax; ++j) {
+        F.px[j] = j < Q.nv ? (float)(Q.px[j] - Q.px[0]) : 0.f;
+        F.py[j] = j < Q.nv ? (float)(Q.py[j] - Q.py[0]) : 0.f;
+        m = fmaxf(m, fmaxf(fabsf(F.px[j]), fabsf(F.py[j])));
+    }
+    F.m = m;
+}
+
+__device__ inline int sure_side_f(float ax, float ay, float bx, float by, float x, float y, float bound) {
+    const float acx = ax - x, bcy = by - y, acy = ay - y, bcx = bx - x;
+    const float det = acx * bcy - acy * bcx;
+    return det > bound ? 1 : (-det > bound ? -1 : 0);
+}
+
+__device__ inline bool poly_surely_inside_f32(const PolyF& F, double x, double y) {
+    const int m = F.nv;
+    if (m < 3) return false;
+    const float px = (float)(x - F.x0), py = (float)(y - F.y0);
+    const float M = fmaxf(F.m, fmaxf(fabsf(px), fabsf(py)));
+    if (!(M >= 0x1p-50f && M <= 0x1p50f)) return false;
+    const float bound = 48.0f * 0x1p-24f * M * M * 1.0001f;
+    if (sure_side_f(0.f, 0.f, F.px[1], F.py[1], px, py, bound) <= 0) return false;
+    if (sure_side_f(0.f, 0.f, F.px[m - 1], F.py[m - 1], px, py, bound) >= 0) return false;
+    int lo = 1, hi = m - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sure_side_f(0.f, 0.f, F.px[mid], F.py[mid], px, py, bound) >= 0) lo = mid;
+        else hi = mid;
+    }
+    return sure_side_f(F.px[lo], F.py[lo], F.px[hi], F.py[hi], px, py, bound) > 0;
 }
 
 // The exact convex hull of kC candidate points (s_x, s_y; s_use[j] = 0: no

@@ -405,13 +405,13 @@ def _ngon(k, seed):
     ("ngon_131072", True, "host"),          # list form, chains overflow
 ])
 def test_step8_device_and_host_fallback(torch_dev, hx, name, full, where):
-    """Step 8 runs on the device (chunk scans joined at common tangents) and
-    falls back to the host scan when the parts' chains do not fit one
-    workgroup; the hull equals the oracle's either way."""
+    """Step 8 on the device (options.scan = 1: chunk scans joined at common
+    tangents) falls back to the host scan when the parts' chains do not fit
+    one workgroup; the hull equals the oracle's either way."""
     pts = {"ngon_16384": lambda: _ngon(16384, (98, 1)),
            "ngon_131072": lambda: _ngon(131072, (99, 1))}.get(name, lambda: CASES[name])()
     say(f"step 8 {name} full={full}")
-    c = hx.Hull2D(profile=True, full_sort=full)
+    c = hx.Hull2D(profile=True, full_sort=full, scan=1)
     got = c.compute(to_dev(torch_dev, pts))
     assert got.tolist() == oracle.hull(pts).tolist()
     st = c.last_stats
@@ -423,3 +423,21 @@ def test_step8_device_and_host_fallback(torch_dev, hx, name, full, where):
     s = c.stages(len(pts) + 1)
     assert s["round2"].tolist() == m["round2"].tolist()
     c.close()
+
+
+@pytest.mark.parametrize("name,full,where", [
+    ("disk_100k", False, "host"),           # the tail's kept points: host by default
+    ("annulus_400k", False, "device"),      # over 65,536 kept points by the multi-kernel path
+])
+def test_step8_default_placement(torch_dev, hx, name, full, where):
+    pts = synth.annulus(400_000, 0.9999, (66, 1)) if name == "annulus_400k" else CASES[name]
+    c = hx.Hull2D(profile=True, full_sort=full)
+    got = c.compute(to_dev(torch_dev, pts))
+    assert got.tolist() == oracle.hull(pts).tolist()
+    st = c.last_stats
+    say(f"step 8 default {name}: kept {st.n_round2} host {st.ms_stage['host_scan']:.3f} "
+        f"device {st.ms_stage['scan']:.3f}")
+    if where == "host":
+        assert st.ms_stage["scan"] == 0.0 and st.ms_stage["host_scan"] > 0.0
+    elif st.n_round2 > 65536:
+        assert st.ms_stage["scan"] > 0.0
