@@ -314,6 +314,8 @@ def main():
                     help="skip the learned-filter comparison on the 20M mixture")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the timing of the batched form (4096 sets)")
+    ap.add_argument("--no-four-region", action="store_true",
+                    help="skip the four-region variant (Section 5.1) on the 20M sets")
     ap.add_argument("--no-adversarial", action="store_true",
                     help="skip the adversarial workloads (annulus + 2^20-gon, integer grid)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -440,6 +442,14 @@ def main():
                             "roofline": dominant(fk), "filter_sort": fseg,
                             "kernels_ms": {k: round(v["ms"], 4) for k, v in fk.items()}}
         progress("full-sort leg done")
+    if not args.no_four_region:
+        # the paper's comparison method (Section 5.1, Table 8) on the same sets
+        fr = timed_sets(hx, names, dev, max(3, args.steps // 2), 1, method=1)
+        fr_ms = sum(v["ms_median"] for v in fr.values())
+        out["four_region"] = {"ms_per_step": round(fr_ms, 4),
+                              "Mpoints_per_s": round(n_total / (fr_ms * 1e-3) / 1e6, 1),
+                              "sets": fr}
+        progress("four-region leg done")
     if not args.no_adversarial:
         # the all-extreme limitation the paper discusses (Section 5.3) and
         # exact ties: 10M annulus points + 10M vertices of a 2^20-gon, and a

@@ -117,7 +117,7 @@ typedef struct {
      * before it; the hull is one stack scan per region from corner k over the
      * kept points to corner k+1 (on the host, as the variant's second stage).
      * Same canonical output.  Only the candidates (v below the minimum of
-     * every earlier one of 4096 buckets of u) are sorted and walked, which
+     * every earlier one of 65,536 buckets of u) are sorted and walked, which
      * keeps the same points.  round2_chunk, full_sort and filter do not
      * apply. */
     int32_t method;
@@ -132,6 +132,10 @@ typedef struct {
      * the device falls back to the host when the chains of its parts exceed
      * one workgroup's LDS. */
     int32_t scan;
+    /* Largest device workspace the context may allocate for one hull, in
+     * MiB (0: no limit).  A call that needs more returns
+     * HULL2D_ERR_OUT_OF_MEMORY and leaves the context usable. */
+    int32_t workspace_limit_mib;
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */

@@ -56,7 +56,7 @@ class _Options(ctypes.Structure):
                 ("filter", ctypes.c_int32), ("batch_blocks_per_cu", ctypes.c_int32),
                 ("batch_order", ctypes.c_int32), ("batch_graph", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("reserve_noalloc", ctypes.c_int32),
-                ("scan", ctypes.c_int32)]
+                ("scan", ctypes.c_int32), ("workspace_limit_mib", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -198,7 +198,7 @@ class Hull2D:
                  profile: int = 0, full_sort: bool = False, learned: bool = False,
                  weights=None, batch_graph: bool = True, batch_blocks_per_cu: int | None = None,
                  batch_order: int | None = None, reserve_noalloc: bool = False, method: int = 0,
-                 scan: int = 0):
+                 scan: int = 0, workspace_limit_mib: int = 0):
         import torch
         lib = load_library()
         if device is None:
@@ -215,7 +215,7 @@ class Hull2D:
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
                        int(bool(full_sort)), int(bool(learned)), int(batch_blocks_per_cu),
                        int(batch_order), int(bool(batch_graph)), int(method),
-                       int(bool(reserve_noalloc)), int(scan))
+                       int(bool(reserve_noalloc)), int(scan), int(workspace_limit_mib))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))

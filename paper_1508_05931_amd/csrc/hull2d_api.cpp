@@ -271,20 +271,29 @@ void carve(char* b, int64_t n, Workspace& w) {
     w.chain.count = (uint32_t*)(t + B4 * 16);
     w.chain.cursor = (uint32_t*)(t + B4 * 20);
     w.chain.offset = (uint32_t*)(t + B4 * 24);
-    w.chain.st = (ChainStatus*)(t + align_up(B4 * 28 + 4, 64));
+    const size_t tiles = B4 / 1024;
+    w.chain.tile_min = (double*)(t + align_up(B4 * 28 + 4, 64));
+    w.chain.tile_sum = (uint32_t*)(t + align_up(B4 * 28 + 4, 64) + tiles * 8);
+    w.chain.st = (ChainStatus*)(t + align_up(B4 * 28 + 4 + tiles * 12, 64) + 64);
 }
 
 hull2d_status ensure_workspace(hull2d_ctx* c, int64_t n) {
     if (n <= c->cap_n) return HULL2D_OK;
     int64_t want = n;
     if (c->cap_n > 0 && want < c->cap_n + c->cap_n / 4) want = c->cap_n + c->cap_n / 4;
+    Layout L = plan(want);
+    const size_t limit = c->opt.workspace_limit_mib > 0 ? (size_t)c->opt.workspace_limit_mib << 20 : 0;
+    if (limit && L.total > limit && want > n) {
+        want = n;  // no headroom within the limit
+        L = plan(want);
+    }
+    if (limit && L.total > limit) return HULL2D_ERR_OUT_OF_MEMORY;  // the old workspace stays
     if (c->dmem) {
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(c->dmem);
         c->dmem = nullptr;
         c->cap_n = -1;
     }
-    const Layout L = plan(want);
     if (hipMalloc((void**)&c->dmem, L.total) != hipSuccess) {
         (void)hipGetLastError();
         c->dmem = nullptr;
@@ -652,7 +661,7 @@ hull2d_status begin_compute(hull2d_ctx* c, const double* d_xy, int64_t n, int32_
     c->last_learned = false;
     c->last_chain = false;
     if (c->opt.method != 0 && c->opt.method != 1) return HULL2D_ERR_INVALID_ARG;
-    if (c->opt.scan < 0 || c->opt.scan > 2) return HULL2D_ERR_INVALID_ARG;
+    if (c->opt.scan < 0 || c->opt.scan > 2 || c->opt.workspace_limit_mib < 0) return HULL2D_ERR_INVALID_ARG;
     if (c->opt.method == 0 && c->opt.filter == 1 && !c->have_weights) return HULL2D_ERR_WEIGHTS;
     if (n == 0) return HULL2D_OK;
     if (hipSetDevice(c->device) != hipSuccess) return HULL2D_ERR_DEVICE;

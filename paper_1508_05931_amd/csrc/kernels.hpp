@@ -171,7 +171,7 @@ hipError_t launch_scan_list(const double2* kept_xy, const int32_t* kept_idx, int
                             DevStatus* host_ds, hipStream_t s);
 
 // ---- the four-region variant (Section 5.1, Table 8) -------------------
-constexpr int kChainBuckets = 4096;   // buckets along u per region
+constexpr int kChainBuckets = 65536;  // buckets along u per region
 constexpr int kChainCap = 4096;       // candidates one workgroup sorts at a time
 constexpr int kChainHostCap = 16384;  // kept points per region written to host memory directly
 
@@ -190,9 +190,12 @@ struct ChainTables {
     uint32_t* count;    // [4][kChainBuckets] candidates per bucket
     uint32_t* offset;   // [4 * kChainBuckets + 1] where each bucket's candidates start
     uint32_t* cursor;   // [4][kChainBuckets] grouping cursors
+    double* tile_min;   // [4 kChainBuckets / 1024] per-tile results of the table scans
+    uint32_t* tile_sum;
     ChainStatus* st;
 };
-constexpr size_t kChainTableBytes = 4 * (size_t)kChainBuckets * (8 + 8 + 4 + 4 + 4) + 4 + 256;
+constexpr size_t kChainTableBytes = 4 * (size_t)kChainBuckets * (8 + 8 + 4 + 4 + 4) + 4 + 256 +
+                                    4 * (size_t)kChainBuckets / 1024 * 12 + 256;
 
 // What the last kernel leaves in host memory.
 struct ChainHost {

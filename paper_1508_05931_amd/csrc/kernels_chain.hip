@@ -38,6 +38,9 @@ namespace {
 
 constexpr int kCB = kChainBuckets;
 constexpr int kPassBlock = 256;
+constexpr int kPassU = 4;
+constexpr int kSample = 8;  // pass 0 reads one block of points in kSample
+constexpr int kCandBuf = 2048;  // pass 1: candidates buffered per block
 constexpr int kTailT = 1024;
 constexpr uint64_t kKeyEmpty = ~0ull;
 
@@ -130,9 +133,15 @@ __global__ void k_chain_clear(ChainTables T) {
         reinterpret_cast<uint32_t*>(T.st)[threadIdx.x] = 0u;
 }
 
-// Pass 0: survivors per region and each bucket's minimum of v.  Pass 1: the
-// candidates (v below the minimum over the earlier buckets), appended with
-// their region and bucket, and counted per bucket.
+// Pass 0, over a sample (every kSample-th block of kPassBlock points): each
+// bucket's minimum of v over the sample.  Those are upper bounds of the
+// true minima, so the candidate test of pass 1 (v below the minimum over
+// the earlier buckets) keeps a superset of the exact candidates; walking
+// that superset keeps the same points (the smallest v before any point is
+// first reached at a point kept by the full walk, which passes the test
+// whatever the table).  Pass 1, over every point: survivors per region, and
+// the candidates, appended with their region and bucket and counted per
+// bucket.
 template <int kPass>
 __global__ __launch_bounds__(kPassBlock) void k_chain_pass(const double2* __restrict__ xy, int64_t n,
                                                            const Params* __restrict__ prm, ChainTables T,
@@ -142,58 +151,96 @@ __global__ __launch_bounds__(kPassBlock) void k_chain_pass(const double2* __rest
     __shared__ Regions R;
     load_regions(prm, R);
     __shared__ uint32_t s_cnt[kPassBlock / 64][5];
+    // pass 1: this block's candidates (input index, region and bucket),
+    // appended to the global list with one atomic per flush
+    __shared__ uint32_t s_bi[kCandBuf], s_brb[kCandBuf];
+    __shared__ uint32_t s_bn, s_at;
+    if (threadIdx.x == 0) s_bn = 0;
     __syncthreads();
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
     uint32_t cnt[5] = {0u, 0u, 0u, 0u, 0u};
-    const int64_t stride = (int64_t)gridDim.x * kPassBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kPassBlock; base < n; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        int r = -1;
-        double u = 0.0, v = 0.0;
-        double2 p = make_double2(0.0, 0.0);
-        if (i < n && !R.none) {
-            p = load_stream(&xy[i]);
-            r = region_of(R, p.x, p.y);
+    auto flush = [&]() {
+        __syncthreads();
+        const uint32_t nb = s_bn;
+        if (threadIdx.x == 0 && nb) s_at = atomicAdd(&T.st->n_cand, nb);
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < nb; j += kPassBlock) {
+            const uint32_t i = s_bi[j];
+            cand_xy[s_at + j] = xy[i];
+            cand_idx[s_at + j] = i;
+            cand_rb[s_at + j] = s_brb[j];
         }
-        if (kPass == 0) {
-            cnt[0] += r == 0;
-            cnt[1] += r == 1;
-            cnt[2] += r == 2;
-            cnt[3] += r == 3;
-            cnt[4] += r == 4;
-            if (r >= 0 && r < 4) {
-                rot_uv(r, p.x, p.y, u, v);
-                const int b = bucket_of(R, r, u);
-                const uint64_t key = key_of(v);
-                uint64_t* cell = &T.bmin[r * kCB + b];
-                if (key < __hip_atomic_load(cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                    __hip_atomic_fetch_min(cell, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        } else {
-            bool cand = false;
-            int b = 0;
-            if (r >= 0 && r < 4) {
-                rot_uv(r, p.x, p.y, u, v);
-                b = bucket_of(R, r, u);
-                cand = v < T.prefix[r * kCB + b];
-            }
-            const uint64_t mask = __ballot(cand);
-            if (mask) {
-                uint32_t at = 0;
-                const int leader = __ffsll((unsigned long long)mask) - 1;
-                if (lane == leader) at = atomicAdd(&T.st->n_cand, (uint32_t)__popcll(mask));
-                at = __shfl(at, leader);
-                if (cand) {
-                    const uint32_t o = at + (uint32_t)__popcll(mask & lanemask_lt());
-                    cand_xy[o] = p;
-                    cand_idx[o] = (uint32_t)i;
-                    cand_rb[o] = ((uint32_t)r << 16) | (uint32_t)b;
-                    atomicAdd(&T.count[r * kCB + b], 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) s_bn = 0;
+        __syncthreads();
+    };
+    // pass 0 takes blocks 0, kSample, 2 kSample, ... of kPassBlock points
+    const int64_t step = kPass == 0 ? (int64_t)kSample * kPassBlock : kPassBlock;
+    const int64_t stride = (int64_t)gridDim.x * step;
+    // kPassU points per thread and turn, their loads issued together
+    for (int64_t base = (int64_t)blockIdx.x * step; base < n; base += stride * kPassU) {
+        if (kPass == 1) {
+            // every thread reads the same fill level (nobody appends between
+            // the two barriers), so all of them flush or none
+            __syncthreads();
+            const bool full = s_bn + kPassBlock * kPassU > (uint32_t)kCandBuf;
+            __syncthreads();
+            if (full) flush();
+        }
+        double2 pu[kPassU];
+#pragma unroll
+        for (int q = 0; q < kPassU; ++q) {
+            const int64_t i = base + q * stride + threadIdx.x;
+            pu[q] = i < n && !R.none ? load_stream(&xy[i]) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < kPassU; ++q) {
+            const int64_t i = base + q * stride + threadIdx.x;
+            const double2 p = pu[q];
+            int r = -1;
+            double u = 0.0, v = 0.0;
+            if (i < n && !R.none) r = region_of(R, p.x, p.y);
+            if (kPass == 0) {
+                if (r >= 0 && r < 4) {
+                    rot_uv(r, p.x, p.y, u, v);
+                    const int b = bucket_of(R, r, u);
+                    const uint64_t key = key_of(v);
+                    uint64_t* cell = &T.bmin[r * kCB + b];
+                    // a plain read: the value only falls, so a stale one
+                    // costs at most an atomic that changes nothing
+                    if (key < *cell)
+                        __hip_atomic_fetch_min(cell, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            } else {
+                cnt[0] += r == 0;
+                cnt[1] += r == 1;
+                cnt[2] += r == 2;
+                cnt[3] += r == 3;
+                cnt[4] += r == 4;
+                bool cand = false;
+                int b = 0;
+                if (r >= 0 && r < 4) {
+                    rot_uv(r, p.x, p.y, u, v);
+                    b = bucket_of(R, r, u);
+                    cand = v < T.prefix[r * kCB + b];
+                }
+                const uint64_t mask = __ballot(cand);
+                if (mask) {
+                    uint32_t at = 0;
+                    const int leader = __ffsll((unsigned long long)mask) - 1;
+                    if (lane == leader) at = atomicAdd(&s_bn, (uint32_t)__popcll(mask));
+                    at = __shfl(at, leader);
+                    if (cand) {
+                        const uint32_t o = at + (uint32_t)__popcll(mask & lanemask_lt());
+                        s_bi[o] = (uint32_t)i;
+                        s_brb[o] = ((uint32_t)r << 16) | (uint32_t)b;
+                    }
                 }
             }
         }
     }
-    if (kPass == 0) {
+    if (kPass == 1) {
+        flush();
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             const uint32_t t = wave_total(cnt[k]);
@@ -211,26 +258,81 @@ __global__ __launch_bounds__(kPassBlock) void k_chain_pass(const double2* __rest
     }
 }
 
-// Exclusive prefix minima of the bucket minima (one region per loop turn),
-// then the candidates' grouping offsets: exclusive sums of the per-bucket
-// counts over (region, bucket).  One block; `phase` 0 or 1.
+// The two table scans, by tiles of kScanTile entries (kTiles in all, a
+// region's tiles consecutive).  kPhase 0: exclusive prefix minima of the
+// bucket minima within each region (T.prefix); kPhase 1: the candidates'
+// grouping offsets, exclusive sums of the per-bucket counts over (region,
+// bucket) (T.offset, T.cursor, and the total at T.offset[4 kChainBuckets]).
+// k_chain_tiles: each tile's minimum or sum; k_chain_scan: one block per
+// tile, its carry from the earlier tiles' results, then the tile's scan.
+constexpr int kScanTile = 1024;
+constexpr int kTiles = 4 * kCB / kScanTile;
+constexpr int kTilesPerRegion = kCB / kScanTile;
+static_assert(kTiles <= 1024, "one thread per tile in the carry");
+
+__device__ inline double bucket_min(const ChainTables& T, int e) {
+    const uint64_t k = T.bmin[e];
+    return k == kKeyEmpty ? __builtin_inf() : value_of(k);
+}
+
 template <int kPhase>
-__global__ __launch_bounds__(1024) void k_chain_scan(ChainTables T) {
-    constexpr int E = 4 * kCB / 1024;  // consecutive entries per thread (all regions)
-    __shared__ double s_m[16];
-    __shared__ uint32_t s_s[16];
+__global__ __launch_bounds__(kScanTile) void k_chain_tiles(ChainTables T) {
+    __shared__ double s_m[kScanTile / 64];
+    __shared__ uint32_t s_s[kScanTile / 64];
     const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
-    const int beg = tid * E;  // never crosses a region (kCB is a multiple of E)
+    const int e = (int)blockIdx.x * kScanTile + tid;
     if (kPhase == 0) {
-        double loc[E];
-        double m = __builtin_inf();
-        for (int e = 0; e < E; ++e) {
-            const uint64_t k = T.bmin[beg + e];
-            loc[e] = k == kKeyEmpty ? __builtin_inf() : value_of(k);
+        double m = bucket_min(T, e);
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) m = fmin(m, __shfl_xor(m, d));
+        if (lane == 0) s_m[wave] = m;
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < kScanTile / 64; ++w) m = fmin(m, s_m[w]);
+            T.tile_min[blockIdx.x] = m;
         }
-        for (int e = 0; e < E; ++e) m = fmin(m, loc[e]);
-        // inclusive min-scan over the threads of one region
-        double inc = m;
+    } else {
+        uint32_t c = wave_total(T.count[e]);
+        if (lane == 0) s_s[wave] = c;
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < kScanTile / 64; ++w) c += s_s[w];
+            T.tile_sum[blockIdx.x] = c;
+        }
+    }
+}
+
+template <int kPhase>
+__global__ __launch_bounds__(kScanTile) void k_chain_scan(ChainTables T) {
+    __shared__ double s_m[kScanTile / 64];
+    __shared__ uint32_t s_s[kScanTile / 64];
+    __shared__ double s_carry_m;
+    __shared__ uint32_t s_carry_s;
+    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    const int tile = (int)blockIdx.x;
+    const int e = tile * kScanTile + tid;
+    // the carry: wave 0 folds the earlier tiles (of the region, for minima)
+    if (wave == 0) {
+        const int first = kPhase == 0 ? (tile / kTilesPerRegion) * kTilesPerRegion : 0;
+        double m = __builtin_inf();
+        uint32_t c = 0;
+        for (int t = first + lane; t < tile; t += 64) {
+            if (kPhase == 0) m = fmin(m, T.tile_min[t]);
+            else c += T.tile_sum[t];
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            m = fmin(m, __shfl_xor(m, d));
+            c += __shfl_xor(c, d);
+        }
+        if (lane == 0) {
+            s_carry_m = m;
+            s_carry_s = c;
+        }
+    }
+    if (kPhase == 0) {
+        const double v = bucket_min(T, e);
+        double inc = v;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const double o = __shfl_up(inc, d);
@@ -238,24 +340,13 @@ __global__ __launch_bounds__(1024) void k_chain_scan(ChainTables T) {
         }
         if (lane == 63) s_m[wave] = inc;
         __syncthreads();
-        // waves per region: kCB / E / 64
-        constexpr int WPR = kCB / E / 64;
-        const int w0 = (wave / WPR) * WPR;
         double ex = __shfl_up(inc, 1);
         if (lane == 0) ex = __builtin_inf();
-        for (int w = w0; w < wave; ++w) ex = fmin(ex, s_m[w]);
-        for (int e = 0; e < E; ++e) {
-            T.prefix[beg + e] = ex;
-            ex = fmin(ex, loc[e]);
-        }
+        for (int w = 0; w < wave; ++w) ex = fmin(ex, s_m[w]);
+        T.prefix[e] = fmin(ex, s_carry_m);
     } else {
-        uint32_t loc[E];
-        uint32_t s = 0;
-        for (int e = 0; e < E; ++e) {
-            loc[e] = T.count[beg + e];
-            s += loc[e];
-        }
-        uint32_t inc = s;
+        const uint32_t v = T.count[e];
+        uint32_t inc = v;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const uint32_t o = __shfl_up(inc, d);
@@ -263,14 +354,47 @@ __global__ __launch_bounds__(1024) void k_chain_scan(ChainTables T) {
         }
         if (lane == 63) s_s[wave] = inc;
         __syncthreads();
-        uint32_t ex = inc - s;
+        uint32_t ex = inc - v;
         for (int w = 0; w < wave; ++w) ex += s_s[w];
-        for (int e = 0; e < E; ++e) {
-            T.offset[beg + e] = ex;
-            T.cursor[beg + e] = ex;
-            ex += loc[e];
+        ex += s_carry_s;
+        T.offset[e] = ex;
+        T.cursor[e] = ex;
+        if (e == 4 * kCB - 1) T.offset[4 * kCB] = ex + v;
+    }
+}
+
+// The bucket minima folded over the candidates too (into the sampled
+// table): the smallest v of the earlier buckets is attained at a candidate,
+// so the prefix of this table is the exact one.
+__global__ __launch_bounds__(256) void k_chain_cand_min(ChainTables T, const double2* __restrict__ cand_xy,
+                                                        const uint32_t* __restrict__ cand_rb) {
+    const uint32_t nc = T.st->n_cand;
+    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < nc; j += gridDim.x * 256) {
+        const uint32_t rb = cand_rb[j];
+        const int r = (int)(rb >> 16);
+        double u, v;
+        rot_uv(r, cand_xy[j].x, cand_xy[j].y, u, v);
+        const uint64_t key = key_of(v);
+        uint64_t* cell = &T.bmin[r * kCB + (int)(rb & 0xFFFFu)];
+        if (key < *cell) __hip_atomic_fetch_min(cell, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The exact candidates (v below the exact minimum over the earlier buckets):
+// marked (bit 31 of cand_rb) and counted per bucket.
+__global__ __launch_bounds__(256) void k_chain_count(ChainTables T, const double2* __restrict__ cand_xy,
+                                                     uint32_t* __restrict__ cand_rb) {
+    const uint32_t nc = T.st->n_cand;
+    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < nc; j += gridDim.x * 256) {
+        const uint32_t rb = cand_rb[j];
+        const int r = (int)(rb >> 16);
+        const int cell = r * kCB + (int)(rb & 0xFFFFu);
+        double u, v;
+        rot_uv(r, cand_xy[j].x, cand_xy[j].y, u, v);
+        if (v < T.prefix[cell]) {
+            cand_rb[j] = rb | 0x80000000u;
+            atomicAdd(&T.count[cell], 1u);
         }
-        if (tid == 1023) T.offset[4 * kCB] = ex;
     }
 }
 
@@ -284,7 +408,8 @@ __global__ __launch_bounds__(256) void k_chain_group(ChainTables T, const double
     const uint32_t nc = T.st->n_cand;
     for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < nc; j += gridDim.x * 256) {
         const uint32_t rb = cand_rb[j];
-        const uint32_t cell = (rb >> 16) * kCB + (rb & 0xFFFFu);
+        if (!(rb & 0x80000000u)) continue;  // not an exact candidate
+        const uint32_t cell = ((rb >> 16) & 0x7FFFu) * kCB + (rb & 0xFFFFu);
         const uint32_t o = atomicAdd(&T.cursor[cell], 1u);
         grp_xy[o] = cand_xy[j];
         grp_idx[o] = cand_idx[j];
@@ -588,18 +713,30 @@ hipError_t launch_chain(const double* xy, int64_t n, const Params* prm, const De
                         uint32_t* grp_idx, double2* out_xy, int32_t* out_idx, ChainHost* host,
                         double2* host_xy, int32_t* host_idx, int grid, hipStream_t s) {
     const double2* p = reinterpret_cast<const double2*>(xy);
-    hipLaunchKernelGGL(k_chain_clear, dim3(16), dim3(1024), 0, s, T);
+    hipLaunchKernelGGL(k_chain_clear, dim3(256), dim3(1024), 0, s, T);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_chain_pass<0>, dim3(grid), dim3(kPassBlock), 0, s, p, n, prm, T, cand_xy,
                        cand_idx, cand_rb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_chain_scan<0>, dim3(1), dim3(1024), 0, s, T);
+    hipLaunchKernelGGL(k_chain_tiles<0>, dim3(kTiles), dim3(kScanTile), 0, s, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chain_scan<0>, dim3(kTiles), dim3(kScanTile), 0, s, T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_chain_pass<1>, dim3(grid), dim3(kPassBlock), 0, s, p, n, prm, T, cand_xy,
                        cand_idx, cand_rb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_chain_scan<1>, dim3(1), dim3(1024), 0, s, T);
+    hipLaunchKernelGGL(k_chain_cand_min, dim3(256), dim3(256), 0, s, T, cand_xy, cand_rb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chain_tiles<0>, dim3(kTiles), dim3(kScanTile), 0, s, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chain_scan<0>, dim3(kTiles), dim3(kScanTile), 0, s, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chain_count, dim3(256), dim3(256), 0, s, T, cand_xy, cand_rb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chain_tiles<1>, dim3(kTiles), dim3(kScanTile), 0, s, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chain_scan<1>, dim3(kTiles), dim3(kScanTile), 0, s, T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_chain_group, dim3(256), dim3(256), 0, s, T, cand_xy, cand_idx, cand_rb, grp_xy,
                        grp_idx);

@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kF1Block) void k_filter1(
 // test settles it).
 // Points per thread and tile of k_pre: more loads in flight than Steps 2-3
 // (the pass writes little).
-constexpr int kPreIpt = 4;
+constexpr int kPreIpt = 8;
 constexpr int kPreTile = kF1Block * kPreIpt;
 
 __global__ __launch_bounds__(kF1Block) void k_pre(const double2* __restrict__ xy, int64_t n, int64_t chunk,

@@ -441,3 +441,19 @@ def test_step8_default_placement(torch_dev, hx, name, full, where):
         assert st.ms_stage["scan"] == 0.0 and st.ms_stage["host_scan"] > 0.0
     elif st.n_round2 > 65536:
         assert st.ms_stage["scan"] > 0.0
+
+
+def test_out_of_memory_path(torch_dev, hx):
+    """A workspace limit makes the allocation fail: OUT_OF_MEMORY, nothing
+    written, and the context still computes inputs that fit."""
+    c = hx.Hull2D(workspace_limit_mib=16)
+    big = synth.square(1_000_000, (83, 1))
+    with pytest.raises(hx.HullError) as e:
+        c.compute(to_dev(torch_dev, big))
+    assert e.value.status == hx.OUT_OF_MEMORY
+    small = synth.disk(50_000, (84, 1))
+    assert c.compute(to_dev(torch_dev, small)).tolist() == oracle.hull(small).tolist()
+    with pytest.raises(hx.HullError) as e:
+        c.compute(to_dev(torch_dev, big))
+    assert e.value.status == hx.OUT_OF_MEMORY
+    c.close()
