@@ -136,6 +136,15 @@ typedef struct {
      * MiB (0: no limit).  A call that needs more returns
      * HULL2D_ERR_OUT_OF_MEMORY and leaves the context usable. */
     int32_t workspace_limit_mib;
+    /* How hull2d_batch spreads the sets over the device.  0 (default): tiled
+     * -- every pass over points runs over tiles of 4,096 points of all sets
+     * at once (so a large set is shared by many workgroups), the passes over
+     * a whole set (reductions, bucket prefixes, the sort and walk of each
+     * region, Step 8) take one workgroup per set or region; the candidates
+     * are grouped by angle bucket and sorted bucket by bucket in LDS.  1: one
+     * persistent launch, each workgroup computing whole sets start to end
+     * (batch_blocks_per_cu and batch_order apply to it only).  Same output. */
+    int32_t batch_engine;
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */

@@ -56,7 +56,8 @@ class _Options(ctypes.Structure):
                 ("filter", ctypes.c_int32), ("batch_blocks_per_cu", ctypes.c_int32),
                 ("batch_order", ctypes.c_int32), ("batch_graph", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("reserve_noalloc", ctypes.c_int32),
-                ("scan", ctypes.c_int32), ("workspace_limit_mib", ctypes.c_int32)]
+                ("scan", ctypes.c_int32), ("workspace_limit_mib", ctypes.c_int32),
+                ("batch_engine", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -190,15 +191,16 @@ class Hull2D:
     Steps 2-3 (two events per call).
 
     batch_graph: capture and replay the batched form's device work in a HIP
-    graph.  batch_blocks_per_cu / batch_order: the batched form's schedule;
-    None takes the values autotune.py stored in tuning/batch.json, else the
-    library's defaults."""
+    graph.  batch_engine: 0 tiled (passes over points share a large set among
+    many workgroups), 1 one persistent workgroup per set.  batch_blocks_per_cu
+    / batch_order: the persistent engine's schedule; None takes the values
+    autotune.py stored in tuning/batch.json, else the library's defaults."""
 
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
                  profile: int = 0, full_sort: bool = False, learned: bool = False,
                  weights=None, batch_graph: bool = True, batch_blocks_per_cu: int | None = None,
                  batch_order: int | None = None, reserve_noalloc: bool = False, method: int = 0,
-                 scan: int = 0, workspace_limit_mib: int = 0):
+                 scan: int = 0, workspace_limit_mib: int = 0, batch_engine: int = 0):
         import torch
         lib = load_library()
         if device is None:
@@ -215,7 +217,8 @@ class Hull2D:
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
                        int(bool(full_sort)), int(bool(learned)), int(batch_blocks_per_cu),
                        int(batch_order), int(bool(batch_graph)), int(method),
-                       int(bool(reserve_noalloc)), int(scan), int(workspace_limit_mib))
+                       int(bool(reserve_noalloc)), int(scan), int(workspace_limit_mib),
+                       int(batch_engine))
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))
@@ -241,10 +244,12 @@ class Hull2D:
             self._lib.hull2d_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # During interpreter shutdown the HIP runtime may already be gone:
         # contexts open at exit are destroyed by the atexit hook, never here.
-        if sys.is_finalizing():
+        # The check is bound as a default argument because module globals
+        # (sys among them) can already be None when a late __del__ runs.
+        if _finalizing():
             return
         try:
             self.close()

@@ -117,6 +117,7 @@ struct hull2d_ctx {
     double2 *b_sv_xy = nullptr, *b_cd_xy = nullptr;
     uint32_t *b_sv_idx = nullptr, *b_sv_key = nullptr, *b_cd_idx = nullptr, *b_cd_key = nullptr;
     uint32_t *b_ka = nullptr, *b_kb = nullptr, *b_va = nullptr, *b_vb = nullptr;
+    uint2* b_gk = nullptr;         // tiled engine: candidates by bucket (key, position)
     uint8_t* b_flag = nullptr;
     int32_t* b_hull = nullptr;
     int64_t* b_offs = nullptr;
@@ -128,7 +129,19 @@ struct hull2d_ctx {
     int32_t* hb_meta = nullptr;
     int64_t hb_cap_h = -1;
     int32_t* hb_hull = nullptr;
+    WSetIn* hb_win = nullptr;      // tiled engine: per-set layout (hb_cap_s entries)
     int batch_grid = 0;
+    // tiled engine: per-set records, tile arrays, bucket tables
+    int64_t wcap_s = -1, wcap_nt = -1, wcap_te = -1;
+    char* wmem = nullptr;
+    WSetIn* w_in = nullptr;
+    WSet* w_set = nullptr;
+    int32_t* w_tile_set = nullptr;
+    Cand* w_tile_ext = nullptr;
+    uint32_t* w_tile_flags = nullptr;
+    WFar* w_tile_far = nullptr;
+    uint32_t *w_tile_cnt = nullptr, *w_tile_ccnt = nullptr;
+    uint32_t *w_tab = nullptr, *w_bcnt = nullptr;
     // the batched form's device work captured in a graph, and what it was
     // captured for (replayed while all of it is unchanged)
     hipStream_t cap_stream = nullptr;
@@ -140,6 +153,9 @@ struct hull2d_ctx {
     const void* bg_ws = nullptr;  // device workspace
     const void* bg_hb = nullptr;  // pinned staging
     int bg_grid = 0;
+    int bg_engine = -1;
+    int64_t bg_nt = -1;
+    const void* bg_wm = nullptr;  // tiled engine's workspace
 
     // learned filter: weights (float32 master + bfloat16 inference copies),
     // optimiser state, the per-call proposal, training activations
@@ -417,16 +433,17 @@ hull2d_status ensure_batch(hull2d_ctx* c, int64_t N, int32_t S) {
             c->bcap_n = -1;
             c->bcap_s = -1;
         }
-        const size_t sizes[15] = {
+        const size_t sizes[16] = {
             (size_t)wn * sizeof(double2), (size_t)wn * 4, (size_t)wn * 4,   // survivors
             (size_t)wn * sizeof(double2), (size_t)wn * 4, (size_t)wn * 4,   // candidates
             (size_t)wn * 4, (size_t)wn * 4, (size_t)wn * 4, (size_t)wn * 4,  // ka kb va vb
             (size_t)wn,                                                      // flags
             (size_t)wn * 4,                                                  // hull
             (size_t)(ws + 1) * 8, (size_t)ws * 4,                            // offsets, order
-            (size_t)(3 * ws + 1) * 4};                                       // meta
-        size_t off[15], o = 0;
-        for (int i = 0; i < 15; ++i) {
+            (size_t)(3 * ws + 1) * 4,                                        // meta
+            (size_t)wn * sizeof(uint2)};                                     // grouped candidates
+        size_t off[16], o = 0;
+        for (int i = 0; i < 16; ++i) {
             off[i] = o;
             o = align_up(o + sizes[i], 256);
         }
@@ -446,6 +463,7 @@ hull2d_status ensure_batch(hull2d_ctx* c, int64_t N, int32_t S) {
         c->b_kb = (uint32_t*)(b + off[7]);
         c->b_va = (uint32_t*)(b + off[8]);
         c->b_vb = (uint32_t*)(b + off[9]);
+        c->b_gk = (uint2*)(b + off[15]);
         c->b_flag = (uint8_t*)(b + off[10]);
         c->b_hull = (int32_t*)(b + off[11]);
         c->b_offs = (int64_t*)(b + off[12]);
@@ -458,19 +476,71 @@ hull2d_status ensure_batch(hull2d_ctx* c, int64_t N, int32_t S) {
         if (c->hb_offs) (void)hipHostFree(c->hb_offs);
         if (c->hb_order) (void)hipHostFree(c->hb_order);
         if (c->hb_meta) (void)hipHostFree(c->hb_meta);
+        if (c->hb_win) (void)hipHostFree(c->hb_win);
         c->hb_offs = nullptr;
         c->hb_order = nullptr;
         c->hb_meta = nullptr;
+        c->hb_win = nullptr;
         c->hb_cap_s = -1;
         const int64_t ws = std::max<int64_t>(S, 1);
         if (hipHostMalloc((void**)&c->hb_offs, (size_t)(ws + 1) * 8, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void**)&c->hb_order, (size_t)ws * 4, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&c->hb_meta, (size_t)(3 * ws + 1) * 4, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc((void**)&c->hb_meta, (size_t)(3 * ws + 1) * 4, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&c->hb_win, (size_t)ws * sizeof(WSetIn), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return HULL2D_ERR_OUT_OF_MEMORY;
         }
         c->hb_cap_s = ws;
     }
+    return HULL2D_OK;
+}
+
+// The tiled engine's device workspace for S sets, NT tiles and TE entries of
+// each bucket table.
+hull2d_status ensure_wide(hull2d_ctx* c, int64_t S, int64_t NT, int64_t TE) {
+    if (S <= c->wcap_s && NT <= c->wcap_nt && TE <= c->wcap_te) return HULL2D_OK;
+    if (c->bgraph) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipGraphExecDestroy(c->bgraph);
+        c->bgraph = nullptr;
+    }
+    const int64_t ws = std::max<int64_t>(std::max<int64_t>(S, c->wcap_s), 1);
+    const int64_t wt = std::max<int64_t>(std::max<int64_t>(NT, c->wcap_nt), 1);
+    const int64_t we = std::max<int64_t>(std::max<int64_t>(TE, c->wcap_te), 1);
+    if (c->wmem) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->wmem);
+        c->wmem = nullptr;
+        c->wcap_s = c->wcap_nt = c->wcap_te = -1;
+    }
+    const size_t sizes[10] = {(size_t)ws * sizeof(WSetIn), (size_t)ws * sizeof(WSet),
+                              (size_t)wt * 4, (size_t)wt * 4 * sizeof(Cand), (size_t)wt * 4,
+                              (size_t)wt * sizeof(WFar), (size_t)wt * 4, (size_t)wt * 4,
+                              (size_t)we * 4, (size_t)we * 4};
+    size_t off[10], o = 0;
+    for (int i = 0; i < 10; ++i) {
+        off[i] = o;
+        o = align_up(o + sizes[i], 256);
+    }
+    if (hipMalloc((void**)&c->wmem, o) != hipSuccess) {
+        (void)hipGetLastError();
+        c->wmem = nullptr;
+        return HULL2D_ERR_OUT_OF_MEMORY;
+    }
+    char* b = c->wmem;
+    c->w_in = (WSetIn*)(b + off[0]);
+    c->w_set = (WSet*)(b + off[1]);
+    c->w_tile_set = (int32_t*)(b + off[2]);
+    c->w_tile_ext = (Cand*)(b + off[3]);
+    c->w_tile_flags = (uint32_t*)(b + off[4]);
+    c->w_tile_far = (WFar*)(b + off[5]);
+    c->w_tile_cnt = (uint32_t*)(b + off[6]);
+    c->w_tile_ccnt = (uint32_t*)(b + off[7]);
+    c->w_tab = (uint32_t*)(b + off[8]);
+    c->w_bcnt = (uint32_t*)(b + off[9]);
+    c->wcap_s = ws;
+    c->wcap_nt = wt;
+    c->wcap_te = we;
     return HULL2D_OK;
 }
 
@@ -1227,6 +1297,8 @@ void hull2d_destroy(hull2d_ctx* c) {
     if (c->hb_order) (void)hipHostFree(c->hb_order);
     if (c->hb_meta) (void)hipHostFree(c->hb_meta);
     if (c->hb_hull) (void)hipHostFree(c->hb_hull);
+    if (c->hb_win) (void)hipHostFree(c->hb_win);
+    if (c->wmem) (void)hipFree(c->wmem);
     for (int i = 0; i < HULL2D_NUM_STAGES + 2; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     if (c->ev_sync) (void)hipEventDestroy(c->ev_sync);
@@ -1271,6 +1343,7 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         if (h_offsets[s + 1] < h_offsets[s] || h_offsets[s + 1] - h_offsets[s] > (int64_t)INT32_MAX)
             return HULL2D_ERR_INVALID_ARG;
     if (h_offsets[S] > 0 && !d_xy) return HULL2D_ERR_INVALID_ARG;
+    if (c->opt.batch_engine < 0 || c->opt.batch_engine > 1) return HULL2D_ERR_INVALID_ARG;
     if (c->broken) return HULL2D_ERR_DEVICE;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
@@ -1314,6 +1387,33 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         }
         for (int32_t i = 0; i < S; ++i) c->hb_order[pos[cls(i)]++] = i;
     }
+    // the tiled engine's layout: each set's tiles and bucket tables (2^bb
+    // buckets per region: about a quarter of the set's size, 16 to 4096)
+    const int engine = c->opt.batch_engine;
+    int64_t NT = 0, TE = 0;
+    if (engine == 0) {
+        for (int32_t i = 0; i < S; ++i) {
+            const int64_t n = size_of(i);
+            WSetIn& w = c->hb_win[i];
+            uint32_t bb = 0;
+            if (n > 0) {
+                bb = 4;
+                while (bb < 12 && ((int64_t)1 << bb) < (n + 3) / 4) ++bb;
+            }
+            w.o = h_offsets[i];
+            w.n = (uint32_t)n;
+            w.t0 = (uint32_t)NT;
+            w.nt = (uint32_t)((n + kWideTile - 1) / kWideTile);
+            w.bb = bb;
+            w.toff = (uint32_t)TE;
+            w.pad = 0;
+            NT += w.nt;
+            TE += n > 0 ? ((int64_t)2 << bb) : 0;
+            if (NT > (int64_t)UINT32_MAX || TE > (int64_t)UINT32_MAX) return HULL2D_ERR_OUT_OF_MEMORY;
+        }
+        st = ensure_wide(c, S, NT, TE);
+        if (st != HULL2D_OK) return st;
+    }
     int32_t* d_count = c->b_meta + 1;
     int32_t* d_start = d_count + S;
     uint32_t* d_flags = (uint32_t*)(d_start + S);
@@ -1321,6 +1421,50 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
     // counter reset, the persistent launch, the download of the per-set
     // counts, starts and flags
     auto device_work = [&](hipStream_t q) -> hipError_t {
+        if (engine == 0) {
+            hipError_t e = hipMemcpyAsync(c->w_in, c->hb_win, (size_t)S * sizeof(WSetIn), hipMemcpyHostToDevice, q);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->b_order, c->hb_order, (size_t)S * 4, hipMemcpyHostToDevice, q);
+            if (e == hipSuccess) e = launch_batch_clear((uint32_t*)c->b_meta, q);
+            if (e == hipSuccess) {
+                WideArgs a;
+                a.xy = reinterpret_cast<const double2*>(d_xy);
+                a.in = c->w_in;
+                a.ws = c->w_set;
+                a.order = c->b_order;
+                a.S = S;
+                a.NT = (uint32_t)NT;
+                a.tile_set = c->w_tile_set;
+                a.tile_ext = c->w_tile_ext;
+                a.tile_flags = c->w_tile_flags;
+                a.tile_far = c->w_tile_far;
+                a.tile_cnt = c->w_tile_cnt;
+                a.tile_ccnt = c->w_tile_ccnt;
+                a.tab = c->w_tab;
+                a.bcnt = c->w_bcnt;
+                a.sv_xy = c->b_sv_xy;
+                a.sv_idx = c->b_sv_idx;
+                a.sv_key = c->b_sv_key;
+                a.cd_xy = c->b_cd_xy;
+                a.cd_idx = c->b_cd_idx;
+                a.cd_key = c->b_cd_key;
+                a.ka = c->b_ka;
+                a.kb = c->b_kb;
+                a.va = c->b_va;
+                a.vb = c->b_vb;
+                a.gk = c->b_gk;
+                a.flag = c->b_flag;
+                a.hull = c->b_hull;
+                a.hull_cursor = (uint32_t*)c->b_meta;
+                a.h_count = d_count;
+                a.h_start = d_start;
+                a.h_flags = d_flags;
+                e = launch_wide(a, q);
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->hb_meta, c->b_meta, (size_t)(3 * S + 1) * 4, hipMemcpyDeviceToHost, q);
+            return e;
+        }
         hipError_t e = hipMemcpyAsync(c->b_offs, c->hb_offs, (size_t)(S + 1) * 8, hipMemcpyHostToDevice, q);
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->b_order, c->hb_order, (size_t)S * 4, hipMemcpyHostToDevice, q);
@@ -1339,7 +1483,8 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
     if (c->opt.batch_graph && !c->bgraph_off) {
         const bool same = c->bgraph && c->bg_S == S && c->bg_N == N && c->bg_xy == d_xy &&
                           c->bg_ws == (const void*)c->b_sv_xy && c->bg_hb == (const void*)c->hb_offs &&
-                          c->bg_grid == c->batch_grid;
+                          c->bg_grid == c->batch_grid && c->bg_engine == engine && c->bg_nt == NT &&
+                          c->bg_wm == (const void*)c->wmem;
         if (!same) {
             if (c->bgraph) {
                 (void)hipGraphExecDestroy(c->bgraph);
@@ -1372,6 +1517,9 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 c->bg_ws = (const void*)c->b_sv_xy;
                 c->bg_hb = (const void*)c->hb_offs;
                 c->bg_grid = c->batch_grid;
+                c->bg_engine = engine;
+                c->bg_nt = NT;
+                c->bg_wm = (const void*)c->wmem;
             }
         }
         if (c->bgraph) {

@@ -238,6 +238,72 @@ int batch_blocks_per_cu();
 hipError_t launch_batch_clear(uint32_t* meta, hipStream_t s);
 constexpr uint32_t kBatchFallback = 4u;
 
+// The tiled engine of the batched form: the passes over a set's points are
+// split into tiles of kWideTile points and the tiles of all sets make one
+// grid per pass; what spans a whole set (reductions, bucket prefixes, the
+// sort and walk of each region, Step 8) takes one workgroup per set.
+constexpr uint32_t kWideTile = 4096;
+
+// Per set, written by the host: the set's first point, its size, its tiles
+// (t0 .. t0 + nt) and its bucket tables (toff .. toff + 2^(bb+1) entries of
+// each table; 2^bb buckets per region).
+struct WSetIn {
+    int64_t o;
+    uint32_t n, t0, nt, bb, toff, pad;
+};
+
+// Per set, written by the device.
+struct WSet {
+    Params P;           // Step 1, then Step 5's fields
+    uint32_t flags;     // domain flags, or kBatchFallback
+    uint32_t m1;        // round-1 survivors
+    uint32_t lslot;     // P_l's position among them
+    uint32_t c[2];      // candidates of each region (sort regions: before P_l, P_l and after)
+    uint32_t big[2];    // the largest bucket of each region
+    uint32_t k[2];      // points each region keeps after the walk
+    uint32_t klo[2];    // where each region's kept points start
+    uint32_t pad;
+};
+
+// Step 5 within one tile: the farthest survivor, its index and position.
+struct WFar {
+    double d2;
+    uint32_t idx, slot;
+};
+
+struct WideArgs {
+    const double2* xy;
+    const WSetIn* in;      // [S]
+    WSet* ws;              // [S]
+    const int32_t* order;  // [S] sets largest first
+    int32_t S;
+    uint32_t NT;           // tiles
+    int32_t* tile_set;     // [NT]
+    Cand* tile_ext;        // [NT][4]
+    uint32_t* tile_flags;  // [NT]
+    WFar* tile_far;        // [NT]
+    uint32_t* tile_cnt;    // [NT] survivors of the tile (at its own first position)
+    uint32_t* tile_ccnt;   // [NT] candidates of the tile (likewise)
+    uint32_t* tab;         // bucket maxima, then their exclusive prefix maxima
+    uint32_t* bcnt;        // candidates per sort bucket, then bucket starts, then ends
+    double2* sv_xy;        // [N] survivors; after the walk, the kept points
+    uint32_t* sv_idx;
+    uint32_t* sv_key;
+    double2* cd_xy;        // [N] candidates, packed tile by tile
+    uint32_t* cd_idx;
+    uint32_t* cd_key;
+    uint32_t *ka, *kb, *va, *vb;  // [N] sort and Step-8 scratch
+    uint2* gk;             // [N] candidates by sort bucket: (angle key, position in cd_*)
+    uint8_t* flag;         // [N]
+    int32_t* hull;         // output as for launch_batch
+    uint32_t* hull_cursor;
+    int32_t* h_count;
+    int32_t* h_start;
+    uint32_t* h_flags;
+};
+// The whole tiled engine on stream s (hull_cursor must be 0 at launch).
+hipError_t launch_wide(const WideArgs& a, hipStream_t s);
+
 // ---- learned-filter variant of Steps 1-2 and its network ----------------
 constexpr int64_t kMlpParams = (int64_t)kMlpIn * kMlpHidden + kMlpHidden +
                                (int64_t)kMlpHidden * kMlpHidden + kMlpHidden +

@@ -177,7 +177,7 @@ __device__ inline BPt shfl_up_bpt(const BPt& p, int d) {
 // walking the tiles in order.  Returns 0 when the result is in (k0, v0), 1
 // when it is in (k1, v1).
 // ---------------------------------------------------------------------------
-__device__ int wg_radix(BatchLds& S, uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+__device__ __forceinline__ int wg_radix(BatchLds& S, uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                         uint32_t cnt) {
     const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
     for (int j = tid; j < 4 * 256; j += kBB) (&S.u.rs.hist[0][0])[j] = 0;
@@ -273,7 +273,7 @@ __device__ int wg_radix(BatchLds& S, uint32_t* k0, uint32_t* v0, uint32_t* k1, u
 // Exact order inside runs of equal keys (sorted keys K, slots V into the
 // candidate arrays).  Returns false when a run is too long for the
 // workgroup (the set goes to the host).
-__device__ bool wg_ties(BatchLds& S, const uint32_t* K, uint32_t* V, uint32_t cnt, const double2* cxy,
+__device__ __forceinline__ bool wg_ties(BatchLds& S, const uint32_t* K, uint32_t* V, uint32_t cnt, const double2* cxy,
                         const uint32_t* cidx, double x0, double y0) {
     const int tid = (int)threadIdx.x;
     if (tid == 0) S.nlong = 0;
@@ -351,7 +351,7 @@ __device__ bool wg_ties(BatchLds& S, const uint32_t* K, uint32_t* V, uint32_t cn
 // from tile to tile; keep flags by position.  Right region: positions
 // 0..cnt-1 after P_0.  Left region: positions cnt-1 down to 1, P_l (position
 // 0) always kept.
-__device__ void wg_walk(BatchLds& S, const uint32_t* V, uint32_t cnt, int region,
+__device__ __forceinline__ void wg_walk(BatchLds& S, const uint32_t* V, uint32_t cnt, int region,
                         const double2* cxy, uint8_t* flag, double x0, double y0, double lx,
                         double ly) {
     const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
@@ -422,7 +422,7 @@ __device__ void wg_walk(BatchLds& S, const uint32_t* V, uint32_t cnt, int region
 
 // Stable removal: kept candidates of one region in position order appended to
 // (oxy, oidx) from `at`; returns the new end.
-__device__ uint32_t wg_compact(BatchLds& S, const uint32_t* V, const uint8_t* flag, uint32_t cnt,
+__device__ __forceinline__ uint32_t wg_compact(BatchLds& S, const uint32_t* V, const uint8_t* flag, uint32_t cnt,
                                const double2* cxy, const uint32_t* cidx, double2* oxy,
                                uint32_t* oidx, uint32_t at) {
     const int tid = (int)threadIdx.x;
@@ -455,7 +455,7 @@ __device__ uint32_t wg_compact(BatchLds& S, const uint32_t* V, const uint8_t* fl
 // equal to the top).  The stack, without P_0, goes to st[0..); returns its
 // size.  The result is the hull of P_0 and the chunk, so a point it drops is
 // no vertex of the whole hull either.
-__device__ uint32_t graham_run(const double2* K, const uint32_t* A, uint32_t beg, uint32_t end,
+__device__ __forceinline__ uint32_t graham_run(const double2* K, const uint32_t* A, uint32_t beg, uint32_t end,
                                uint32_t* st, double x0, double y0) {
     uint32_t top = 0;              // stack entries above P_0
     double tx = x0, ty = y0;       // top of the stack (P_0 when top == 0)
@@ -488,7 +488,7 @@ __device__ uint32_t graham_run(const double2* K, const uint32_t* A, uint32_t beg
 }
 
 // graham_run on points staged in LDS (positions are u16 indices into x, y).
-__device__ uint32_t graham_lds(const double* __restrict__ gx, const double* __restrict__ gy,
+__device__ __forceinline__ uint32_t graham_lds(const double* __restrict__ gx, const double* __restrict__ gy,
                                const uint16_t* A, uint32_t beg, uint32_t end, uint16_t* st, double x0,
                                double y0) {
     uint32_t top = 0;
@@ -519,10 +519,158 @@ __device__ uint32_t graham_lds(const double* __restrict__ gx, const double* __re
     return top;
 }
 
+// Where a set's hull goes: hull[start[s] ..+ count[s]], flags[s] = 0.
+struct HullSink {
+    int32_t* hull;
+    uint32_t* cursor;
+    int32_t* count;
+    int32_t* start;
+    uint32_t* flags;
+};
+
+// Step 8 of one set and its output.  The kept list (angular order, P_0 not
+// in it) is positions 0..m-1 of (kxy, kidx), or first[0..m) of them when
+// `first` is not null (then first == b0); b0, b1, b2 hold m positions each.
+__device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int32_t s, const double2* kxy,
+                            const uint32_t* kidx, uint32_t* first, uint32_t m, uint32_t* b0,
+                            uint32_t* b1, uint32_t* b2, double x0, double y0, int32_t p0_idx) {
+    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    // reduce chunks in parallel (in HBM while many points are left, then in
+    // LDS), then one thread
+    uint32_t* cur_a = first;  // positions into the kept list (null: all of them)
+    uint32_t len = m;
+    uint32_t* bufs[3] = {b0, b1, b2};
+    int nb = 0;
+    bool stuck = false;
+    while (len > kGLds && !stuck) {
+        const uint32_t ch = max(16u, (len + kBB - 1) / kBB);
+        uint32_t* st = bufs[nb % 3] == cur_a ? bufs[(nb + 1) % 3] : bufs[nb % 3];
+        uint32_t* dst = nullptr;
+        for (int q = 0; q < 3; ++q)
+            if (bufs[q] != cur_a && bufs[q] != st) dst = bufs[q];
+        const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
+        const uint32_t h = graham_run(kxy, cur_a, beg, end, st + beg, x0, y0);
+        uint32_t tot;
+        const uint32_t at = bexcl(h, S, tot);
+        for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
+        __syncthreads();
+        stuck = (uint64_t)tot * 10u > (uint64_t)len * 9u;
+        cur_a = dst;
+        len = tot;
+        ++nb;
+    }
+    const bool in_lds = len <= kGLds;
+    uint32_t* fin = b0;       // final stack (HBM path)
+    uint16_t* fin16 = nullptr;  // final stack (LDS path)
+    if (in_lds) {
+        for (uint32_t i = (uint32_t)tid; i < len; i += kBB) {
+            const uint32_t pos = cur_a ? cur_a[i] : i;
+            const double2 q = kxy[pos];
+            S.u.gs.x[i] = q.x;
+            S.u.gs.y[i] = q.y;
+            S.u.gs.pos[i] = pos;
+        }
+        __syncthreads();
+        uint16_t* cur = nullptr;
+        uint16_t* b16[3] = {S.u.gs.a, S.u.gs.b, S.u.gs.c};
+        int k = 0;
+        bool stk = false;
+        while (len > kGOne && !stk) {
+            const uint32_t ch = max(8u, (len + kBB - 1) / kBB);
+            uint16_t* st = b16[k % 3] == cur ? b16[(k + 1) % 3] : b16[k % 3];
+            uint16_t* dst = nullptr;
+            for (int q = 0; q < 3; ++q)
+                if (b16[q] != cur && b16[q] != st) dst = b16[q];
+            const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
+            const uint32_t h = graham_lds(S.u.gs.x, S.u.gs.y, cur, beg, end, st + beg, x0, y0);
+            uint32_t tot;
+            const uint32_t at = bexcl(h, S, tot);
+            for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
+            __syncthreads();
+            stk = (uint64_t)tot * 10u > (uint64_t)len * 9u;
+            cur = dst;
+            len = tot;
+            ++k;
+        }
+        fin16 = S.u.gs.a;
+        for (int q = 0; q < 3; ++q)
+            if (b16[q] != cur) fin16 = b16[q];
+        if (tid == 0) S.h = graham_lds(S.u.gs.x, S.u.gs.y, cur, 0, len, fin16, x0, y0) + 1u;
+    } else {
+        for (int q = 0; q < 3; ++q)
+            if (bufs[q] != cur_a) fin = bufs[q];
+        if (tid == 0) S.h = graham_run(kxy, cur_a, 0, len, fin, x0, y0) + 1u;
+    }
+    __syncthreads();
+    const uint32_t h = S.h;
+    // stack entry k >= 1: its point and its kept-list position
+    auto vpos = [&](uint32_t k) -> uint32_t { return in_lds ? S.u.gs.pos[fin16[k - 1]] : fin[k - 1]; };
+    // canonical start: the lexicographically smallest vertex (P_0 is entry 0)
+    {
+        double bx = INFINITY, by = INFINITY;
+        uint32_t bk = kNone;
+        for (uint32_t k = (uint32_t)tid; k < h; k += kBB) {
+            double x, y;
+            if (k == 0) {
+                x = x0;
+                y = y0;
+            } else if (in_lds) {
+                x = S.u.gs.x[fin16[k - 1]];
+                y = S.u.gs.y[fin16[k - 1]];
+            } else {
+                const double2 q = kxy[fin[k - 1]];
+                x = q.x;
+                y = q.y;
+            }
+            const bool tk = (x < bx) | ((x == bx) & (y < by));
+            bx = tk ? x : bx;
+            by = tk ? y : by;
+            bk = tk ? k : bk;
+        }
+#pragma unroll
+        for (int msk = 32; msk > 0; msk >>= 1) {
+            const double ox = __shfl_xor(bx, msk), oy = __shfl_xor(by, msk);
+            const uint32_t ok = __shfl_xor(bk, msk);
+            const bool tk = (ox < bx) | ((ox == bx) & (oy < by));
+            bx = tk ? ox : bx;
+            by = tk ? oy : by;
+            bk = tk ? ok : bk;
+        }
+        if (lane == 0) {
+            S.bd2[wave] = bx;
+            S.wx[wave] = by;
+            S.bidx[wave] = bk;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < kBW; ++w) {
+                const bool tk = (S.bd2[w] < bx) | ((S.bd2[w] == bx) & (S.wx[w] < by));
+                bx = tk ? S.bd2[w] : bx;
+                by = tk ? S.wx[w] : by;
+                bk = tk ? S.bidx[w] : bk;
+            }
+            S.start = bk;
+            S.hpos = atomicAdd(H.cursor, h);
+        }
+        __syncthreads();
+    }
+    const uint32_t start = S.start, at = S.hpos;
+    for (uint32_t k = (uint32_t)tid; k < h; k += kBB) {
+        const uint32_t e = (start + k) % h;
+        H.hull[at + k] = e == 0 ? p0_idx : (int32_t)kidx[vpos(e)];
+    }
+    if (tid == 0) {
+        H.count[s] = (int32_t)h;
+        H.start[s] = (int32_t)at;
+        H.flags[s] = 0;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // One set, start to end.
 // ---------------------------------------------------------------------------
-__device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
+__device__ __forceinline__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
     const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
     const int64_t o = A.offs[s];
     const uint32_t n = (uint32_t)(A.offs[s + 1] - o);
@@ -821,136 +969,13 @@ __device__ void batch_set(const BatchArgs& A, BatchLds& S, int32_t s) {
         }
     }
 
-    // ---- Step 8: reduce chunks in parallel (in HBM while many points are
-    //      left, then in LDS), then one thread
-    uint32_t* cur_a = nullptr;  // positions into the kept list (null: all of them)
-    uint32_t len = m;
-    uint32_t* bufs[3] = {ka, kb, va};
-    int nb = 0;
-    bool stuck = false;
-    while (len > kGLds && !stuck) {
-        const uint32_t ch = max(16u, (len + kBB - 1) / kBB);
-        uint32_t* st = bufs[nb % 3] == cur_a ? bufs[(nb + 1) % 3] : bufs[nb % 3];
-        uint32_t* dst = nullptr;
-        for (int q = 0; q < 3; ++q)
-            if (bufs[q] != cur_a && bufs[q] != st) dst = bufs[q];
-        const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
-        const uint32_t h = graham_run(sv_xy, cur_a, beg, end, st + beg, x0, y0);
-        uint32_t tot;
-        const uint32_t at = bexcl(h, S, tot);
-        for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
-        __syncthreads();
-        stuck = (uint64_t)tot * 10u > (uint64_t)len * 9u;
-        cur_a = dst;
-        len = tot;
-        ++nb;
-    }
-    const bool in_lds = len <= kGLds;
-    uint32_t* fin = ka;       // final stack (HBM path)
-    uint16_t* fin16 = nullptr;  // final stack (LDS path)
-    if (in_lds) {
-        for (uint32_t i = (uint32_t)tid; i < len; i += kBB) {
-            const uint32_t pos = cur_a ? cur_a[i] : i;
-            const double2 q = sv_xy[pos];
-            S.u.gs.x[i] = q.x;
-            S.u.gs.y[i] = q.y;
-            S.u.gs.pos[i] = pos;
-        }
-        __syncthreads();
-        uint16_t* cur = nullptr;
-        uint16_t* b16[3] = {S.u.gs.a, S.u.gs.b, S.u.gs.c};
-        int k = 0;
-        bool stk = false;
-        while (len > kGOne && !stk) {
-            const uint32_t ch = max(8u, (len + kBB - 1) / kBB);
-            uint16_t* st = b16[k % 3] == cur ? b16[(k + 1) % 3] : b16[k % 3];
-            uint16_t* dst = nullptr;
-            for (int q = 0; q < 3; ++q)
-                if (b16[q] != cur && b16[q] != st) dst = b16[q];
-            const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
-            const uint32_t h = graham_lds(S.u.gs.x, S.u.gs.y, cur, beg, end, st + beg, x0, y0);
-            uint32_t tot;
-            const uint32_t at = bexcl(h, S, tot);
-            for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
-            __syncthreads();
-            stk = (uint64_t)tot * 10u > (uint64_t)len * 9u;
-            cur = dst;
-            len = tot;
-            ++k;
-        }
-        fin16 = S.u.gs.a;
-        for (int q = 0; q < 3; ++q)
-            if (b16[q] != cur) fin16 = b16[q];
-        if (tid == 0) S.h = graham_lds(S.u.gs.x, S.u.gs.y, cur, 0, len, fin16, x0, y0) + 1u;
-    } else {
-        for (int q = 0; q < 3; ++q)
-            if (bufs[q] != cur_a) fin = bufs[q];
-        if (tid == 0) S.h = graham_run(sv_xy, cur_a, 0, len, fin, x0, y0) + 1u;
-    }
-    __syncthreads();
-    const uint32_t h = S.h;
-    // stack entry k >= 1: its point and its kept-list position
-    auto vpos = [&](uint32_t k) -> uint32_t { return in_lds ? S.u.gs.pos[fin16[k - 1]] : fin[k - 1]; };
-    // canonical start: the lexicographically smallest vertex (P_0 is entry 0)
-    {
-        double bx = INFINITY, by = INFINITY;
-        uint32_t bk = kNone;
-        for (uint32_t k = (uint32_t)tid; k < h; k += kBB) {
-            double x, y;
-            if (k == 0) {
-                x = x0;
-                y = y0;
-            } else if (in_lds) {
-                x = S.u.gs.x[fin16[k - 1]];
-                y = S.u.gs.y[fin16[k - 1]];
-            } else {
-                const double2 q = sv_xy[fin[k - 1]];
-                x = q.x;
-                y = q.y;
-            }
-            const bool tk = (x < bx) | ((x == bx) & (y < by));
-            bx = tk ? x : bx;
-            by = tk ? y : by;
-            bk = tk ? k : bk;
-        }
-#pragma unroll
-        for (int msk = 32; msk > 0; msk >>= 1) {
-            const double ox = __shfl_xor(bx, msk), oy = __shfl_xor(by, msk);
-            const uint32_t ok = __shfl_xor(bk, msk);
-            const bool tk = (ox < bx) | ((ox == bx) & (oy < by));
-            bx = tk ? ox : bx;
-            by = tk ? oy : by;
-            bk = tk ? ok : bk;
-        }
-        if (lane == 0) {
-            S.bd2[wave] = bx;
-            S.wx[wave] = by;
-            S.bidx[wave] = bk;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int w = 1; w < kBW; ++w) {
-                const bool tk = (S.bd2[w] < bx) | ((S.bd2[w] == bx) & (S.wx[w] < by));
-                bx = tk ? S.bd2[w] : bx;
-                by = tk ? S.wx[w] : by;
-                bk = tk ? S.bidx[w] : bk;
-            }
-            S.start = bk;
-            S.hpos = atomicAdd(A.hull_cursor, h);
-        }
-        __syncthreads();
-    }
-    const uint32_t start = S.start, at = S.hpos;
-    for (uint32_t k = (uint32_t)tid; k < h; k += kBB) {
-        const uint32_t e = (start + k) % h;
-        A.hull[at + k] = e == 0 ? p0_idx : (int32_t)sv_idx[vpos(e)];
-    }
-    if (tid == 0) {
-        A.h_count[s] = (int32_t)h;
-        A.h_start[s] = (int32_t)at;
-        A.h_flags[s] = 0;
-    }
-    __syncthreads();
+    HullSink H;
+    H.hull = A.hull;
+    H.cursor = A.hull_cursor;
+    H.count = A.h_count;
+    H.start = A.h_start;
+    H.flags = A.h_flags;
+    batch_step8(S, H, s, sv_xy, sv_idx, nullptr, m, ka, kb, va, x0, y0, p0_idx);
 }
 
 __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchArgs A) {
@@ -1016,6 +1041,1199 @@ hipError_t launch_batch_clear(uint32_t* meta, hipStream_t s) {
 
 int batch_blocks_per_cu() {
     return resident_blocks(reinterpret_cast<const void*>(k_batch), kBB);
+}
+
+// ===========================================================================
+// The tiled engine.  Passes over points (Step 1, Steps 2-3, the bucket
+// maxima, the candidates, their grouping by bucket) run one workgroup per
+// tile of kWideTile points over the tiles of all sets; the reductions and
+// bucket prefixes of a set take one workgroup per set; each region of a set
+// is sorted and walked by one workgroup (candidates already grouped by their
+// angle bucket, so a tile of whole buckets is sorted in LDS bucket by
+// bucket); Step 8 takes one workgroup per set.
+// ===========================================================================
+namespace {
+
+constexpr int kWB = 256;              // threads of the tile passes
+constexpr int kWW = kWB / 64;
+constexpr int kWI = 4;                // points per thread per round
+constexpr uint32_t kWT = kWideTile;
+constexpr uint32_t kCT = 2048;        // candidates per walk tile
+constexpr int kCI = (int)kCT / kBB;   // walk positions per thread
+constexpr uint32_t kSortOne = 32;     // buckets up to this size: one thread sorts them
+constexpr uint16_t kInf16 = 0xFFFFu;  // bitonic padding (after every real entry)
+static_assert(kCI * kBB == (int)kCT, "walk tile");
+static_assert(kCT < kInf16, "16-bit tile positions");
+
+struct WalkTile {
+    uint32_t key[kCT], key2[kCT];  // radix ping-pong (the sort overwrites both)
+    uint16_t perm[kCT];  // tile positions in sorted order
+    uint16_t tmp[kCT];   // radix ping-pong, bitonic buffer
+    uint32_t base[256];
+    uint16_t wc[kBW][256];
+    uint32_t cpos[kCT];       // each entry's position in the candidate arrays
+    uint32_t bend[kBuckets];  // the region's bucket ends
+    const double2* xy;        // the set's candidates (global memory)
+    const uint32_t* idx;
+};
+
+struct alignas(16) WalkLds {
+    union {
+        WalkTile t;
+    } u;
+    double wx[kBW], wy[kBW];
+    uint32_t wv[kBW], wsum[kBW];
+    uint32_t tlo, thi, nbig;
+    uint32_t big[kCT / (kSortOne + 1) + 1];
+};
+
+__device__ inline uint32_t wide_tile_set(const WideArgs& A, uint32_t t, WSetIn& in, uint32_t& lo, uint32_t& hi) {
+    const int32_t s = A.tile_set[t];
+    in = A.in[s];
+    lo = (t - in.t0) * kWT;
+    hi = min(lo + kWT, in.n);
+    return (uint32_t)s;
+}
+
+// ---- prep: tile owners, cleared tables and counters (one workgroup per set)
+__global__ __launch_bounds__(kWB) void k_wprep(WideArgs A) {
+    const int32_t s = (int32_t)blockIdx.x;
+    const WSetIn in = A.in[s];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t j = tid; j < in.nt; j += kWB) A.tile_set[in.t0 + j] = s;
+    const uint32_t ent = in.n > 0 ? (2u << in.bb) : 0u;
+    for (uint32_t j = tid; j < ent; j += kWB) A.tab[in.toff + j] = 0u;
+    if (tid == 0) {
+        WSet& W = A.ws[s];
+        W.flags = 0u;
+        W.m1 = 0u;
+        W.lslot = 0u;
+        for (int r = 0; r < 2; ++r) {
+            W.c[r] = 0u;
+            W.big[r] = 0u;
+            W.k[r] = 0u;
+            W.klo[r] = 0u;
+        }
+    }
+}
+
+// ---- Step 1 on a tile: its four extreme points and domain flags
+__global__ __launch_bounds__(kWB) void k_wext(WideArgs A) {
+    __shared__ Cand s_ext[kWW][4];
+    __shared__ uint32_t s_bad;
+    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    const uint32_t t = blockIdx.x;
+    WSetIn in;
+    uint32_t lo, hi;
+    wide_tile_set(A, t, in, lo, hi);
+    const double2* xy = A.xy + in.o;
+    if (tid == 0) s_bad = 0u;
+    Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
+    uint32_t bad = 0;
+    for (uint32_t b0 = lo; b0 < hi; b0 += kWB * kWI) {
+        double2 p[kWI];
+#pragma unroll
+        for (int k = 0; k < kWI; ++k) {
+            const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
+            p[k] = make_double2(0.0, 0.0);
+            if (i < hi) p[k] = load_stream(&xy[i]);
+        }
+#pragma unroll
+        for (int k = 0; k < kWI; ++k) {
+            const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
+            if (i < hi) {
+                const bool need = (p[k].x <= c[0].x) | (p[k].y <= c[1].y) | (p[k].x >= c[2].x) |
+                                  (p[k].y >= c[3].y);
+                if (need) offer(c, p[k].x, p[k].y, (int32_t)i);
+                bad |= domain_flags(p[k].x) | domain_flags(p[k].y);
+            }
+        }
+    }
+    reduce4_wave(c);
+    __syncthreads();
+    if (bad) atomicOr(&s_bad, bad);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_ext[wave][k] = c[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        Cand e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = s_ext[0][k];
+        for (int w = 1; w < kWW; ++w) {
+            take_better<0>(e[0], s_ext[w][0]);
+            take_better<1>(e[1], s_ext[w][1]);
+            take_better<2>(e[2], s_ext[w][2]);
+            take_better<3>(e[3], s_ext[w][3]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) A.tile_ext[4 * t + k] = e[k];
+        A.tile_flags[t] = s_bad;
+    }
+}
+
+// ---- Step 1 of a set: its tiles' extremes, the quadrilateral, P_0
+__global__ __launch_bounds__(64) void k_wparams(WideArgs A) {
+    const int32_t s = (int32_t)blockIdx.x;
+    const WSetIn in = A.in[s];
+    const uint32_t lane = threadIdx.x;
+    if (in.n == 0) return;
+    Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
+    uint32_t bad = 0;
+    for (uint32_t j = lane; j < in.nt; j += 64) {
+        const uint32_t t = in.t0 + j;
+        take_better<0>(c[0], A.tile_ext[4 * t + 0]);
+        take_better<1>(c[1], A.tile_ext[4 * t + 1]);
+        take_better<2>(c[2], A.tile_ext[4 * t + 2]);
+        take_better<3>(c[3], A.tile_ext[4 * t + 3]);
+        bad |= A.tile_flags[t];
+    }
+    reduce4_wave(c);
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) bad |= __shfl_xor(bad, m);
+    if (lane == 0) {
+        make_params(A.ws[s].P, c, bad);
+        A.ws[s].flags = bad;
+    }
+}
+
+// ---- Steps 2-3 on a tile: survivors (packed at the tile's first position)
+//      with their angle keys, and the tile's farthest survivor (Step 5)
+__global__ __launch_bounds__(kWB) void k_wfilter(WideArgs A) {
+    __shared__ uint32_t s_cnt;
+    __shared__ double s_d2[kWW];
+    __shared__ uint32_t s_i[kWW], s_sl[kWW];
+    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    const uint32_t t = blockIdx.x;
+    WSetIn in;
+    uint32_t lo, hi;
+    const uint32_t s = wide_tile_set(A, t, in, lo, hi);
+    const WSet& W = A.ws[s];
+    if (W.flags != 0u) return;
+    double qx[4], qy[4], ex[4], ey[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        qx[j] = W.P.qx[j];
+        qy[j] = W.P.qy[j];
+        ex[j] = W.P.ex[j];
+        ey[j] = W.P.ey[j];
+    }
+    const double qb = W.P.qbound, x0 = W.P.x0, y0 = W.P.y0;
+    const int nc = W.P.ncorner;
+    const double2* xy = A.xy + in.o;
+    double2* sv_xy = A.sv_xy + in.o;
+    uint32_t* sv_idx = A.sv_idx + in.o;
+    uint32_t* sv_key = A.sv_key + in.o;
+    if (tid == 0) s_cnt = 0u;
+    __syncthreads();
+    double bd2 = -1.0;
+    uint32_t bidx = kNone, bslot = kNone;
+    for (uint32_t b0 = lo; b0 < hi; b0 += kWB * kWI) {
+        double2 p[kWI];
+#pragma unroll
+        for (int k = 0; k < kWI; ++k) {
+            const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
+            p[k] = make_double2(0.0, 0.0);
+            if (i < hi) p[k] = load_stream(&xy[i]);
+        }
+#pragma unroll
+        for (int k = 0; k < kWI; ++k) {
+            const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
+            bool surv = false;
+            if (i < hi) {
+                surv = !quad_inside(qx, qy, ex, ey, qb, nc, p[k].x, p[k].y) &&
+                       !(p[k].x == x0 && p[k].y == y0);
+            }
+            const uint32_t at = wave_append(surv, &s_cnt);
+            if (surv) {
+                const uint32_t pos = lo + at;
+                sv_xy[pos] = p[k];
+                sv_idx[pos] = i;
+                sv_key[pos] = angle_key(p[k].x, p[k].y, x0, y0);
+                const double d2 = dist2(p[k].x, p[k].y, x0, y0);
+                const bool tk = (d2 > bd2) | ((d2 == bd2) & (i < bidx));
+                bd2 = tk ? d2 : bd2;
+                bidx = tk ? i : bidx;
+                bslot = tk ? pos : bslot;
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        const double od = __shfl_xor(bd2, m);
+        const uint32_t oi = __shfl_xor(bidx, m);
+        const uint32_t os = __shfl_xor(bslot, m);
+        const bool tk = (od > bd2) | ((od == bd2) & (oi < bidx));
+        bd2 = tk ? od : bd2;
+        bidx = tk ? oi : bidx;
+        bslot = tk ? os : bslot;
+    }
+    if (lane == 0) {
+        s_d2[wave] = bd2;
+        s_i[wave] = bidx;
+        s_sl[wave] = bslot;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kWW; ++w) {
+            const bool tk = (s_d2[w] > bd2) | ((s_d2[w] == bd2) & (s_i[w] < bidx));
+            bd2 = tk ? s_d2[w] : bd2;
+            bidx = tk ? s_i[w] : bidx;
+            bslot = tk ? s_sl[w] : bslot;
+        }
+        WFar f;
+        f.d2 = bd2;
+        f.idx = bidx;
+        f.slot = bslot;
+        A.tile_far[t] = f;
+        A.tile_cnt[t] = s_cnt;
+    }
+}
+
+// ---- Step 5 of a set: P_l, the farthest survivor (smallest index on ties)
+__global__ __launch_bounds__(64) void k_wfar(WideArgs A) {
+    const int32_t s = (int32_t)blockIdx.x;
+    const WSetIn in = A.in[s];
+    const uint32_t lane = threadIdx.x;
+    if (in.n == 0) return;
+    WSet& W = A.ws[s];
+    if (W.flags != 0u) return;
+    double bd2 = -1.0;
+    uint32_t bidx = kNone, bslot = kNone, m1 = 0;
+    for (uint32_t j = lane; j < in.nt; j += 64) {
+        const uint32_t t = in.t0 + j;
+        const WFar f = A.tile_far[t];
+        m1 += A.tile_cnt[t];
+        const bool tk = (f.d2 > bd2) | ((f.d2 == bd2) & (f.idx < bidx));
+        bd2 = tk ? f.d2 : bd2;
+        bidx = tk ? f.idx : bidx;
+        bslot = tk ? f.slot : bslot;
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        const double od = __shfl_xor(bd2, m);
+        const uint32_t oi = __shfl_xor(bidx, m);
+        const uint32_t os = __shfl_xor(bslot, m);
+        m1 += __shfl_xor(m1, m);
+        const bool tk = (od > bd2) | ((od == bd2) & (oi < bidx));
+        bd2 = tk ? od : bd2;
+        bidx = tk ? oi : bidx;
+        bslot = tk ? os : bslot;
+    }
+    if (lane == 0) {
+        W.m1 = m1;
+        if (m1 > 0) {
+            const double2 q = A.sv_xy[in.o + bslot];
+            W.P.lx = q.x;
+            W.P.ly = q.y;
+            W.P.l_idx = (int32_t)bidx;
+            W.P.kl = A.sv_key[in.o + bslot];
+            const uint32_t tu = turn_key(W.P.x0, W.P.y0, q.x, q.y);
+            W.P.turn_u = tu;
+            W.P.turn_v = tu + 0x80000000u;
+            W.lslot = bslot;
+        }
+    }
+}
+
+// The fields of Step 6-7's classification, read once per workgroup.
+struct WCls {
+    double x0, y0, lx, ly;
+    uint32_t kl, tu, tv;
+    int32_t l_idx;
+    __device__ explicit WCls(const Params& P)
+        : x0(P.x0), y0(P.y0), lx(P.lx), ly(P.ly), kl(P.kl), tu(P.turn_u), tv(P.turn_v), l_idx(P.l_idx) {}
+    __device__ Cls operator()(double x, double y, uint32_t key) const {
+        return classify_at(x, y, key, x0, y0, lx, ly, kl, tu, tv);
+    }
+};
+
+// ---- Steps 6-7, bucket maxima: the survivors of a group of kBGroup tiles
+//      of one set reduced in an LDS table, whose non-empty entries go to the
+//      set's table; every survivor's direction key and region are kept for
+//      the candidate pass (ka and the bytes of vb)
+constexpr uint32_t kBGroup = 8;
+
+__global__ __launch_bounds__(kWB) void k_wbmax(WideArgs A) {
+    __shared__ uint32_t s_tab[2 * kBuckets];
+    const int tid = (int)threadIdx.x;
+    const uint32_t t = blockIdx.x;
+    WSetIn in;
+    uint32_t lo, hi;
+    const uint32_t s = wide_tile_set(A, t, in, lo, hi);
+    if ((t - in.t0) % kBGroup != 0u) return;
+    const WSet& W = A.ws[s];
+    if (W.flags != 0u || W.m1 == 0u) return;
+    const WCls C(W.P);
+    const uint32_t sh = 32u - in.bb;
+    const uint32_t ent = 2u << in.bb;
+    const size_t o = (size_t)in.o;
+    const double2* sv_xy = A.sv_xy + o;
+    const uint32_t* sv_key = A.sv_key + o;
+    uint32_t* kap = A.ka + o;
+    uint8_t* reg = reinterpret_cast<uint8_t*>(A.vb) + o;
+    for (uint32_t j = (uint32_t)tid; j < ent; j += kWB) s_tab[j] = 0u;
+    __syncthreads();
+    const uint32_t tend = min(t + kBGroup, in.t0 + in.nt);
+    for (uint32_t u = t; u < tend; ++u) {
+        const uint32_t ulo = (u - in.t0) * kWT, uend = ulo + A.tile_cnt[u];
+        for (uint32_t b0 = ulo; b0 < uend; b0 += kWB * kWI) {
+            double2 p[kWI];
+            uint32_t key[kWI];
+#pragma unroll
+            for (int k = 0; k < kWI; ++k) {
+                const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
+                p[k] = make_double2(0.0, 0.0);
+                key[k] = 0;
+                if (i < uend) {
+                    p[k] = sv_xy[i];
+                    key[k] = sv_key[i];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kWI; ++k) {
+                const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
+                if (i < uend) {
+                    const Cls cl = C(p[k].x, p[k].y, key[k]);
+                    if (cl.region < 2) atomicMax(&s_tab[((uint32_t)cl.region << in.bb) + (key[k] >> sh)], cl.kappa);
+                    kap[i] = cl.kappa;
+                    reg[i] = (uint8_t)cl.region;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t* tab = A.tab + in.toff;
+    for (uint32_t j = (uint32_t)tid; j < ent; j += kWB) {
+        const uint32_t v = s_tab[j];
+        if (v != 0u) atomicMax(&tab[j], v);
+    }
+}
+
+// Exclusive block scan over kWB threads (sum or max); all threads call it.
+template <bool kMax>
+__device__ inline uint32_t wblock_scan(uint32_t v, uint32_t* s_w, uint32_t& total) {
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d);
+        if (lane >= d) inc = kMax ? max(inc, o) : inc + o;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWW; ++w) {
+        const uint32_t x = s_w[w];
+        if (w < wave) pre = kMax ? max(pre, x) : pre + x;
+        tot = kMax ? max(tot, x) : tot + x;
+    }
+    __syncthreads();
+    total = tot;
+    const uint32_t ex = __shfl_up(inc, 1);
+    const uint32_t lane_ex = lane == 0 ? 0u : ex;
+    return kMax ? max(pre, lane_ex) : pre + lane_ex;
+}
+
+// ---- Steps 6-7, prefix maxima of each region's bucket maxima in walking
+//      order (right region ascending from kappa(P_0) = 0, left region
+//      descending), in place; one workgroup per set
+__global__ __launch_bounds__(kWB) void k_wprefix(WideArgs A) {
+    __shared__ uint32_t s_w[kWW];
+    const int32_t s = (int32_t)blockIdx.x;
+    const WSetIn in = A.in[s];
+    const uint32_t tid = threadIdx.x;
+    if (in.n == 0) return;
+    const WSet& W = A.ws[s];
+    if (W.flags != 0u || W.m1 == 0u) return;
+    const uint32_t B = 1u << in.bb;
+    const uint32_t per = B > (uint32_t)kWB ? B / kWB : 1u;
+    constexpr int kPer = kBuckets / kWB;
+    for (int region = 0; region < 2; ++region) {
+        uint32_t* T = A.tab + in.toff + ((uint32_t)region << in.bb);
+        uint32_t v[kPer];
+        uint32_t tmax = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t w = tid * per + (uint32_t)k;
+            v[k] = 0;
+            if ((uint32_t)k < per && w < B) {
+                v[k] = T[region == 0 ? w : B - 1 - w];
+                tmax = max(tmax, v[k]);
+            }
+        }
+        uint32_t tot;
+        uint32_t run = wblock_scan<true>(tmax, s_w, tot);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t w = tid * per + (uint32_t)k;
+            if ((uint32_t)k < per && w < B) {
+                T[region == 0 ? w : B - 1 - w] = run;
+                run = max(run, v[k]);
+            }
+        }
+    }
+}
+
+// ---- Steps 6-7, candidates of a tile: kept by the prefix maxima, given
+//      their sort region (before P_l in the exact angular order: 0; P_l and
+//      after: 1), packed at the tile's first position
+__global__ __launch_bounds__(kWB) void k_wcand(WideArgs A) {
+    __shared__ uint32_t s_cnt;
+    const int tid = (int)threadIdx.x;
+    const uint32_t t = blockIdx.x;
+    WSetIn in;
+    uint32_t lo, hi;
+    const uint32_t s = wide_tile_set(A, t, in, lo, hi);
+    const WSet& W = A.ws[s];
+    if (W.flags != 0u || W.m1 == 0u) return;
+    const uint32_t cnt = A.tile_cnt[t];
+    const WCls C(W.P);
+    const uint32_t lslot = W.lslot;
+    const uint32_t sh = 32u - in.bb;
+    const uint32_t* tab = A.tab + in.toff;
+    const size_t o = (size_t)in.o;
+    const uint32_t* kap = A.ka + o;
+    const uint8_t* reg = reinterpret_cast<const uint8_t*>(A.vb) + o;
+    if (tid == 0) s_cnt = 0u;
+    __syncthreads();
+    for (uint32_t b0 = lo; b0 < lo + cnt; b0 += kWB) {
+        const uint32_t i = b0 + (uint32_t)tid;
+        bool keep = false;
+        double2 p = make_double2(0.0, 0.0);
+        uint32_t key = 0, idx = 0, sreg = 0;
+        if (i < lo + cnt) {
+            key = A.sv_key[o + i];
+            const uint32_t region = reg[i];
+            const uint32_t bucket = key >> sh;
+            keep = region == 2u || kap[i] >= tab[(region << in.bb) + bucket];
+            if (keep) {
+                p = A.sv_xy[o + i];
+                idx = A.sv_idx[o + i];
+                if (key != C.kl) sreg = key < C.kl ? 0u : 1u;
+                else if (i == lslot) sreg = 1u;
+                else sreg = angle_less(p.x, p.y, idx, C.lx, C.ly, (uint32_t)C.l_idx, C.x0, C.y0) ? 0u : 1u;
+            }
+        }
+        const uint32_t at = wave_append(keep, &s_cnt);
+        if (keep) {
+            const size_t q = o + lo + at;
+            A.cd_xy[q] = p;
+            A.cd_idx[q] = idx;
+            A.cd_key[q] = key;
+            A.flag[q] = (uint8_t)sreg;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) A.tile_ccnt[t] = s_cnt;
+}
+
+// ---- one workgroup per set: its candidates (packed tile by tile) counted
+//      per sort bucket in LDS, the bucket starts (region 0 from 0, region 1
+//      after it), then every candidate's angle key and position placed in
+//      its bucket of gk (one 8-byte store each; order within a bucket
+//      arbitrary: the walk sorts each tile); the bucket ends, the region
+//      sizes and their largest bucket go to global memory for the walk
+__global__ __launch_bounds__(kBB) void k_wgroup(WideArgs A) {
+    __shared__ uint32_t s_cnt[2 * kBuckets];
+    __shared__ uint32_t s_w[kBW];
+    const int32_t s = A.order[blockIdx.x];
+    const WSetIn in = A.in[s];
+    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    if (in.n == 0) return;
+    WSet& W = A.ws[s];
+    if (W.flags != 0u || W.m1 == 0u) return;
+    const uint32_t B = 1u << in.bb, sh = 32u - in.bb;
+    const size_t o = (size_t)in.o;
+    for (uint32_t j = (uint32_t)tid; j < 2u * B; j += kBB) s_cnt[j] = 0u;
+    __syncthreads();
+    constexpr int kU = 4;  // loads in flight per thread
+    for (uint32_t u = in.t0; u < in.t0 + in.nt; ++u) {
+        const uint32_t ulo = (u - in.t0) * kWT, uend = ulo + A.tile_ccnt[u];
+        for (uint32_t b0 = ulo; b0 < uend; b0 += kBB * kU) {
+            uint32_t key[kU], sr[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
+                key[k] = 0;
+                sr[k] = 0;
+                if (i < uend) {
+                    key[k] = A.cd_key[o + i];
+                    sr[k] = A.flag[o + i];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
+                if (i < uend) atomicAdd(&s_cnt[(sr[k] << in.bb) + (key[k] >> sh)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    // exclusive prefix sums, region by region; thread tid takes buckets
+    // [tid * per, tid * per + per) of the region
+    const uint32_t per = B > (uint32_t)kBB ? B / kBB : 1u;
+    constexpr int kPer = kBuckets / kBB;
+    uint32_t base = 0;
+    for (int region = 0; region < 2; ++region) {
+        uint32_t* T = s_cnt + ((uint32_t)region << in.bb);
+        uint32_t v[kPer];
+        uint32_t tsum = 0, tmax = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t w = (uint32_t)tid * per + (uint32_t)k;
+            v[k] = 0;
+            if ((uint32_t)k < per && w < B) v[k] = T[w];
+            tsum += v[k];
+            tmax = max(tmax, v[k]);
+        }
+        uint32_t inc = tsum, mx = tmax;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t q = __shfl_up(inc, d);
+            if (lane >= d) inc += q;
+            mx = max(mx, __shfl_xor(mx, d));
+        }
+        if (lane == 63) s_w[wave] = inc;
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+        for (int w = 0; w < kBW; ++w) {
+            const uint32_t x = s_w[w];
+            if (w < wave) pre += x;
+            tot += x;
+        }
+        __syncthreads();
+        if (lane == 0) s_w[wave] = mx;
+        __syncthreads();
+        uint32_t big = 0;
+        for (int w = 0; w < kBW; ++w) big = max(big, s_w[w]);
+        uint32_t run = base + pre + inc - tsum;
+        uint32_t* ends = A.bcnt + in.toff + ((uint32_t)region << in.bb);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t w = (uint32_t)tid * per + (uint32_t)k;
+            if ((uint32_t)k < per && w < B) {
+                T[w] = run;
+                run += v[k];
+                ends[w] = run;
+            }
+        }
+        if (tid == 0) {
+            W.c[region] = tot;
+            W.big[region] = big;
+        }
+        base += tot;
+        __syncthreads();
+    }
+    for (uint32_t u = in.t0; u < in.t0 + in.nt; ++u) {
+        const uint32_t ulo = (u - in.t0) * kWT, uend = ulo + A.tile_ccnt[u];
+        for (uint32_t b0 = ulo; b0 < uend; b0 += kBB * kU) {
+            uint32_t key[kU], sr[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
+                key[k] = sr[k] = 0;
+                if (i < uend) {
+                    key[k] = A.cd_key[o + i];
+                    sr[k] = A.flag[o + i];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
+                if (i < uend) {
+                    const uint32_t pos = atomicAdd(&s_cnt[(sr[k] << in.bb) + (key[k] >> sh)], 1u);
+                    A.gk[o + pos] = make_uint2(key[k], i);
+                }
+            }
+        }
+    }
+}
+
+// The exact order of Step 4 between two tile entries of equal angle key.
+__device__ inline bool tile_less(const WalkTile& T, uint32_t a, uint32_t b, double x0, double y0) {
+    const double2 p = T.xy[T.cpos[a]], q = T.xy[T.cpos[b]];
+    return angle_less(p.x, p.y, T.idx[T.cpos[a]], q.x, q.y, T.idx[T.cpos[b]], x0, y0);
+}
+__device__ inline bool tile_less_pad(const WalkTile& T, uint16_t a, uint16_t b, double x0, double y0) {
+    if (a == kInf16) return false;
+    if (b == kInf16) return true;
+    return tile_less(T, a, b, x0, y0);
+}
+
+// Stable LSD radix sort (8-bit digits) of the tile's angle keys with their
+// positions, in LDS: T.perm[0..nt) ends as the positions in key order (equal
+// keys in position order); returns the sorted keys (T.key or T.key2).  A
+// pass is skipped when the smallest and largest key agree on that digit and
+// every digit above it (then every key does).
+__device__ __forceinline__ const uint32_t* tile_radix(WalkTile& T, uint32_t* s_wsum, uint32_t nt) {
+    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+    for (uint32_t j = (uint32_t)tid; j < nt; j += kBB) {
+        kmin = min(kmin, T.key[j]);
+        kmax = max(kmax, T.key[j]);
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        kmin = min(kmin, __shfl_xor(kmin, d));
+        kmax = max(kmax, __shfl_xor(kmax, d));
+    }
+    if (lane == 0) {
+        s_wsum[wave] = kmin;
+        T.base[wave] = kmax;
+    }
+    __syncthreads();
+    for (int w = 0; w < kBW; ++w) {
+        kmin = min(kmin, s_wsum[w]);
+        kmax = max(kmax, T.base[w]);
+    }
+    const uint32_t diff = kmin ^ kmax;  // every key lies in [kmin, kmax]
+    __syncthreads();
+    uint32_t* ks = T.key;
+    uint16_t* vs = T.perm;
+    uint32_t* kd = T.key2;
+    uint16_t* vd = T.tmp;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        // the smallest and largest key agree on this digit and above: so
+        // does every key, and the pass would not move anything
+        if ((diff >> shift) == 0u) continue;
+        for (int j = tid; j < kBW * 256; j += kBB) (&T.wc[0][0])[j] = 0;
+        __syncthreads();
+        uint32_t key[kCI], rank[kCI];
+        uint16_t val[kCI];
+#pragma unroll
+        for (int k = 0; k < kCI; ++k) {
+            const uint32_t p = (uint32_t)(wave * 64 * kCI + k * 64 + lane);
+            key[k] = 0;
+            val[k] = 0;
+            if (p < nt) {
+                key[k] = ks[p];
+                val[k] = vs[p];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kCI; ++k) {
+            const uint32_t p = (uint32_t)(wave * 64 * kCI + k * 64 + lane);
+            const bool valid = p < nt;
+            const uint32_t dig = (key[k] >> shift) & 0xFFu;
+            const uint64_t m = match_digit8(dig, valid);
+            uint32_t prior = 0;
+            if (valid) prior = T.wc[wave][dig];
+            const uint32_t below = (uint32_t)__popcll(m & lanemask_lt());
+            __builtin_amdgcn_wave_barrier();
+            if (valid && below == 0u) T.wc[wave][dig] = (uint16_t)(prior + (uint32_t)__popcll(m));
+            __builtin_amdgcn_wave_barrier();
+            rank[k] = prior + below;
+        }
+        __syncthreads();
+        if (tid < 256) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kBW; ++w) {
+                const uint32_t c = T.wc[w][tid];
+                T.wc[w][tid] = (uint16_t)tot;
+                tot += c;
+            }
+            const uint32_t inc = bw_incl(tot);
+            if (lane == 63) s_wsum[wave] = inc;
+            T.base[tid] = inc - tot;
+        }
+        __syncthreads();
+        if (tid < 256) {
+            uint32_t pre = 0;
+            for (int w = 0; w < wave; ++w) pre += s_wsum[w];
+            T.base[tid] += pre;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kCI; ++k) {
+            const uint32_t p = (uint32_t)(wave * 64 * kCI + k * 64 + lane);
+            if (p < nt) {
+                const uint32_t dig = (key[k] >> shift) & 0xFFu;
+                const uint32_t q = T.base[dig] + T.wc[wave][dig] + rank[k];
+                kd[q] = key[k];
+                vd[q] = val[k];
+            }
+        }
+        __syncthreads();
+        uint32_t* tk = ks;
+        ks = kd;
+        kd = tk;
+        uint16_t* tv = vs;
+        vs = vd;
+        vd = tv;
+    }
+    if (vs != T.perm) {
+        for (uint32_t j = (uint32_t)tid; j < nt; j += kBB) T.perm[j] = vs[j];
+        __syncthreads();
+    }
+    return ks;
+}
+
+// Bitonic sort of perm[bs, bs + len) in LDS by the whole workgroup.
+__device__ __forceinline__ void tile_bitonic(WalkTile& T, uint32_t bs, uint32_t len, double x0, double y0) {
+    const uint32_t tid = threadIdx.x;
+    uint32_t P2 = 1;
+    while (P2 < len) P2 <<= 1;
+    for (uint32_t a = tid; a < P2; a += kBB) T.tmp[a] = a < len ? T.perm[bs + a] : kInf16;
+    __syncthreads();
+    for (uint32_t kb = 2; kb <= P2; kb <<= 1) {
+        for (uint32_t jj = kb >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t a = tid; a < P2; a += kBB) {
+                const uint32_t b = a ^ jj;
+                if (b > a) {
+                    const uint16_t ia = T.tmp[a], ib = T.tmp[b];
+                    const bool asc = (a & kb) == 0;
+                    const bool swap = asc ? tile_less_pad(T, ib, ia, x0, y0) : tile_less_pad(T, ia, ib, x0, y0);
+                    if (swap) {
+                        T.tmp[a] = ib;
+                        T.tmp[b] = ia;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t a = tid; a < len; a += kBB) T.perm[bs + a] = T.tmp[a];
+    __syncthreads();
+}
+
+// The region a walk workgroup takes: sets largest first, two regions each.
+struct WRegion {
+    int32_t s;
+    int r;
+    uint32_t cnt, rs, re;
+};
+__device__ inline bool wide_region(const WideArgs& A, WRegion& R) {
+    R.s = A.order[blockIdx.x >> 1];
+    R.r = (int)(blockIdx.x & 1u);
+    const WSet& W = A.ws[R.s];
+    if (A.in[R.s].n == 0 || W.flags != 0u || W.m1 == 0u) return false;
+    R.cnt = W.c[R.r];
+    R.rs = R.r == 0 ? 0u : W.c[0];
+    R.re = R.rs + R.cnt;
+    return true;
+}
+
+// ---- Step 4 and the walk of Figure 2 on one region of one set whose
+//      buckets all fit a tile: tiles of whole buckets in walking order, each
+//      sorted bucket by bucket in LDS, then walked as a max-scan with the
+//      running maximum carried from tile to tile; kept points to (sv_xy,
+//      sv_idx): the right region ascending from its first position, the left
+//      region descending from its last (P_l, always kept, last of all)
+__global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k_wwalk(WideArgs A) {
+    __shared__ WalkLds L;
+    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
+    WRegion R;
+    if (!wide_region(A, R)) return;
+    WSet& W = A.ws[R.s];
+    if (W.big[R.r] > kCT || R.cnt <= 64u) return;
+    const WSetIn in = A.in[R.s];
+    const size_t o = (size_t)in.o;
+    const int r = R.r;
+    const uint32_t rs = R.rs, re = R.re;
+    const double x0 = W.P.x0, y0 = W.P.y0, lx = W.P.lx, ly = W.P.ly;
+    const int sgn = r == 0 ? 1 : -1;
+
+    WalkTile& T = L.u.t;
+    const uint32_t B = 1u << in.bb;
+    const uint32_t* ends = A.bcnt + in.toff + ((uint32_t)r << in.bb);
+    for (uint32_t b = (uint32_t)tid; b < B; b += kBB) T.bend[b] = ends[b];
+    __syncthreads();
+    auto bstart = [&](uint32_t b) -> uint32_t { return b == 0 ? rs : T.bend[b - 1]; };
+    BPt carry = bpt_none();
+    if (r == 0) {
+        carry.x = x0;
+        carry.y = y0;
+        carry.v = true;
+    }
+    uint32_t kept = 0;
+    uint32_t lo_p = rs, hi_p = re;  // positions not walked yet
+    while (lo_p < hi_p) {
+        if (tid == 0) {
+            uint32_t plo, phi;
+            if (r == 0) {
+                // [lo_p, e): e the last bucket end within lo_p + kCT
+                const uint32_t lim = lo_p + min(kCT, hi_p - lo_p);
+                uint32_t a = 0, z = B - 1;  // largest b with bend[b] <= lim (bend[B-1] = re <= lim or not)
+                while (a < z) {
+                    const uint32_t mid = (a + z + 1) >> 1;
+                    if (T.bend[mid] <= lim) a = mid;
+                    else z = mid - 1;
+                }
+                plo = lo_p;
+                phi = T.bend[a];
+            } else {
+                // [e, hi_p): e the first bucket start at or after hi_p - kCT
+                const uint32_t lim = hi_p - min(kCT, hi_p - lo_p);
+                uint32_t a = 0, z = B - 1;  // smallest b with bstart(b) >= lim
+                while (a < z) {
+                    const uint32_t mid = (a + z) >> 1;
+                    if (bstart(mid) >= lim) z = mid;
+                    else a = mid + 1;
+                }
+                plo = bstart(a);
+                phi = hi_p;
+            }
+            L.tlo = plo;
+            L.thi = phi;
+            L.nbig = 0;
+            T.idx = A.cd_idx + o;
+            T.xy = A.cd_xy + o;
+        }
+        __syncthreads();
+        const uint32_t plo = L.tlo, phi = L.thi, nt = phi - plo;
+        for (uint32_t j = (uint32_t)tid; j < nt; j += kBB) {
+            const uint2 g = A.gk[o + plo + j];
+            T.key[j] = g.x;
+            T.cpos[j] = g.y;
+            T.perm[j] = (uint16_t)j;
+        }
+        __syncthreads();
+        // sorted by angle key, then the exact order within runs of equal keys:
+        // short runs by one thread each, longer ones by the workgroup
+        const uint32_t* K = tile_radix(T, L.wsum, nt);
+        for (uint32_t j = (uint32_t)tid; j < nt; j += kBB) {
+            if (j > 0 && K[j - 1] == K[j]) continue;
+            if (!(j + 1 < nt && K[j + 1] == K[j])) continue;
+            uint32_t e = j + 2;
+            while (e < nt && e - j <= kSortOne && K[e] == K[j]) ++e;
+            if (e - j > kSortOne) {
+                const uint32_t at = atomicAdd(&L.nbig, 1u);
+                L.big[at] = j;
+                continue;
+            }
+            for (uint32_t a = j + 1; a < e; ++a) {
+                const uint16_t v = T.perm[a];
+                uint32_t q = a;
+                while (q > j && tile_less(T, v, T.perm[q - 1], x0, y0)) {
+                    T.perm[q] = T.perm[q - 1];
+                    --q;
+                }
+                T.perm[q] = v;
+            }
+        }
+        __syncthreads();
+        const uint32_t nbig = L.nbig;
+        for (uint32_t jb = 0; jb < nbig; ++jb) {
+            const uint32_t j = L.big[jb];
+            uint32_t e = j + 1;
+            while (e < nt && K[e] == K[j]) ++e;
+            tile_bitonic(T, j, e - j, x0, y0);
+        }
+        // the walk: position w of the tile in walking order is sorted rank w
+        // (right region) or nt - 1 - w (left region); P_l, rank 0 of the left
+        // region, is not walked
+        const uint32_t nw = (r == 1 && plo == rs) ? nt - 1u : nt;
+        BPt it[kCI];
+        bool kp[kCI];
+        BPt agg = bpt_none();
+#pragma unroll
+        for (int k = 0; k < kCI; ++k) {
+            const uint32_t w = (uint32_t)(tid * kCI + k);
+            it[k] = bpt_none();
+            if (w < nw) {
+                const double2 v = A.cd_xy[o + T.cpos[T.perm[r == 0 ? w : nt - 1u - w]]];
+                it[k].x = v.x;
+                it[k].y = v.y;
+                it[k].v = true;
+            }
+            agg = bmax(agg, it[k], lx, ly, sgn);
+        }
+        BPt inc = agg;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const BPt q = shfl_up_bpt(inc, d);
+            if (lane >= d) inc = bmax(q, inc, lx, ly, sgn);
+        }
+        BPt ex = shfl_up_bpt(inc, 1);
+        if (lane == 0) ex = bpt_none();
+        if (lane == 63) {
+            L.wx[wave] = inc.x;
+            L.wy[wave] = inc.y;
+            L.wv[wave] = inc.v ? 1u : 0u;
+        }
+        __syncthreads();
+        BPt run = carry, all = carry;
+        for (int w = 0; w < kBW; ++w) {
+            BPt q;
+            q.x = L.wx[w];
+            q.y = L.wy[w];
+            q.v = L.wv[w] != 0u;
+            if (w < wave) run = bmax(run, q, lx, ly, sgn);
+            all = bmax(all, q, lx, ly, sgn);
+        }
+        run = bmax(run, ex, lx, ly, sgn);
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kCI; ++k) {
+            const uint32_t w = (uint32_t)(tid * kCI + k);
+            kp[k] = false;
+            if (w < nw) {
+                kp[k] = (!run.v) || sgn * orient(lx, ly, run.x, run.y, it[k].x, it[k].y) >= 0;
+                run = bmax(run, it[k], lx, ly, sgn);
+                c += kp[k] ? 1u : 0u;
+            }
+        }
+        // kept points in walking order
+        const int lane_ = lane;
+        (void)lane_;
+        uint32_t tot;
+        uint32_t off;
+        {
+            uint32_t incs = c;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t q = __shfl_up(incs, d);
+                if (lane >= d) incs += q;
+            }
+            if (lane == 63) L.wsum[wave] = incs;
+            __syncthreads();
+            uint32_t pre = 0, t2 = 0;
+            for (int w = 0; w < kBW; ++w) {
+                const uint32_t x = L.wsum[w];
+                if (w < wave) pre += x;
+                t2 += x;
+            }
+            tot = t2;
+            off = kept + pre + incs - c;
+        }
+#pragma unroll
+        for (int k = 0; k < kCI; ++k) {
+            const uint32_t w = (uint32_t)(tid * kCI + k);
+            if (w < nw && kp[k]) {
+                const uint32_t e = T.perm[r == 0 ? w : nt - 1u - w];
+                const uint32_t pos = r == 0 ? rs + off : re - 1u - off;
+                A.sv_xy[o + pos] = make_double2(it[k].x, it[k].y);
+                A.sv_idx[o + pos] = T.idx[T.cpos[e]];
+                ++off;
+            }
+        }
+        kept += tot;
+        carry = all;
+        if (r == 0) lo_p = phi;
+        else hi_p = plo;
+        __syncthreads();
+    }
+    if (r == 1 && tid == 0) {
+        const uint32_t pos = re - 1u - kept;
+        A.sv_xy[o + pos] = make_double2(lx, ly);
+        A.sv_idx[o + pos] = (uint32_t)W.P.l_idx;
+    }
+    if (r == 1) ++kept;
+    if (tid == 0) {
+        W.k[r] = kept;
+        W.klo[r] = r == 0 ? rs : re - kept;
+    }
+}
+
+// ---- the same for a region of at most 64 candidates, one wave per region
+//      (eight per workgroup): a bitonic sort across the lanes, the walk as a
+//      wave max-scan, the kept points by ballot
+struct WItem {
+    double x, y;
+    uint32_t idx, key;
+    bool inf;  // padding after every real entry
+};
+
+__device__ inline WItem shfl_item(const WItem& a, int src) {
+    WItem r;
+    r.x = __shfl(a.x, src);
+    r.y = __shfl(a.y, src);
+    r.idx = __shfl(a.idx, src);
+    r.key = __shfl(a.key, src);
+    r.inf = __shfl((int)a.inf, src) != 0;
+    return r;
+}
+
+__device__ inline bool item_less(const WItem& a, const WItem& b, double x0, double y0) {
+    if (a.inf) return false;
+    if (b.inf) return true;
+    if (a.key != b.key) return a.key < b.key;
+    return angle_less(a.x, a.y, a.idx, b.x, b.y, b.idx, x0, y0);
+}
+
+__global__ __launch_bounds__(kBB) void k_wwalk_small(WideArgs A) {
+    const int lane = (int)__lane_id();
+    const uint32_t g = blockIdx.x * (uint32_t)kBW + (threadIdx.x >> 6);
+    if (g >= 2u * (uint32_t)A.S) return;
+    const int32_t s = A.order[g >> 1];
+    const int r = (int)(g & 1u);
+    const WSetIn in = A.in[s];
+    if (in.n == 0) return;
+    WSet& W = A.ws[s];
+    if (W.flags != 0u || W.m1 == 0u) return;
+    const uint32_t cnt = W.c[r];
+    if (cnt > 64u) return;
+    const uint32_t rs = r == 0 ? 0u : W.c[0], re = rs + cnt;
+    const size_t o = (size_t)in.o;
+    const double x0 = W.P.x0, y0 = W.P.y0, lx = W.P.lx, ly = W.P.ly;
+    const int sgn = r == 0 ? 1 : -1;
+    WItem me;
+    me.x = me.y = 0.0;
+    me.idx = me.key = 0;
+    me.inf = (uint32_t)lane >= cnt;
+    if (!me.inf) {
+        const uint2 g = A.gk[o + rs + lane];
+        const double2 v = A.cd_xy[o + g.y];
+        me.x = v.x;
+        me.y = v.y;
+        me.idx = A.cd_idx[o + g.y];
+        me.key = g.x;
+    }
+    for (int k = 2; k <= 64; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const WItem ot = shfl_item(me, lane ^ j);
+            const bool low = (lane & j) == 0, asc = (lane & k) == 0;
+            const bool take = low == asc ? item_less(ot, me, x0, y0) : item_less(me, ot, x0, y0);
+            if (take) me = ot;
+        }
+    }
+    // walking order: rank w (right region) or cnt - 1 - w (left region, whose
+    // rank 0 is P_l: kept, not walked)
+    const uint32_t nw = r == 0 ? cnt : (cnt > 0 ? cnt - 1u : 0u);
+    const int src = r == 0 ? lane : (int)cnt - 1 - lane;
+    const WItem w = shfl_item(me, src < 0 ? 0 : src);
+    BPt it = bpt_none();
+    if ((uint32_t)lane < nw) {
+        it.x = w.x;
+        it.y = w.y;
+        it.v = true;
+    }
+    BPt inc = it;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const BPt q = shfl_up_bpt(inc, d);
+        if (lane >= d) inc = bmax(q, inc, lx, ly, sgn);
+    }
+    BPt ex = shfl_up_bpt(inc, 1);
+    if (lane == 0) ex = bpt_none();
+    BPt run = bpt_none();
+    if (r == 0) {
+        run.x = x0;
+        run.y = y0;
+        run.v = true;
+    }
+    run = bmax(run, ex, lx, ly, sgn);
+    const bool kp = (uint32_t)lane < nw &&
+                    ((!run.v) || sgn * orient(lx, ly, run.x, run.y, it.x, it.y) >= 0);
+    const uint64_t mask = __ballot(kp);
+    const uint32_t off = (uint32_t)__popcll(mask & lanemask_lt());
+    if (kp) {
+        const uint32_t pos = r == 0 ? rs + off : re - 1u - off;
+        A.sv_xy[o + pos] = make_double2(w.x, w.y);
+        A.sv_idx[o + pos] = w.idx;
+    }
+    uint32_t kept = (uint32_t)__popcll(mask);
+    if (r == 1) {
+        if (lane == 0) {
+            const uint32_t pos = re - 1u - kept;
+            A.sv_xy[o + pos] = make_double2(lx, ly);
+            A.sv_idx[o + pos] = (uint32_t)W.P.l_idx;
+        }
+        ++kept;
+    }
+    if (lane == 0) {
+        W.k[r] = kept;
+        W.klo[r] = r == 0 ? rs : re - kept;
+    }
+}
+
+// ---- the same for a region with a bucket larger than a walk tile: the
+//      per-set engine's stable radix sort in HBM, the exact order of equal
+//      keys, its walk and removal (kept points ascending from the region's
+//      first position); an equal-key run too long for the workgroup sends the
+//      set to the host
+__global__ __launch_bounds__(kBB) void k_wwalk_radix(WideArgs A) {
+    __shared__ BatchLds S;
+    const int tid = (int)threadIdx.x;
+    WRegion R;
+    if (!wide_region(A, R)) return;
+    WSet& W = A.ws[R.s];
+    if (W.big[R.r] <= kCT) return;
+    const WSetIn in = A.in[R.s];
+    const size_t o = (size_t)in.o;
+    const uint32_t cnt = R.cnt, rs = R.rs;
+    const double x0 = W.P.x0, y0 = W.P.y0;
+    uint32_t* K0 = A.ka + o + rs;
+    uint32_t* V0 = A.va + o + rs;
+    uint32_t* K1 = A.kb + o + rs;
+    uint32_t* V1 = A.vb + o + rs;
+    for (uint32_t i = (uint32_t)tid; i < cnt; i += kBB) {
+        const uint2 g = A.gk[o + rs + i];
+        K0[i] = g.x;
+        V0[i] = g.y;
+    }
+    __syncthreads();
+    const int cur = wg_radix(S, K0, V0, K1, V1, cnt);
+    const uint32_t* K = cur ? K1 : K0;
+    uint32_t* V = cur ? V1 : V0;
+    if (!wg_ties(S, K, V, cnt, A.cd_xy + o, A.cd_idx + o, x0, y0)) {
+        if (tid == 0) atomicOr(&W.flags, kSetFallback);
+        return;
+    }
+    wg_walk(S, V, cnt, R.r, A.cd_xy + o, A.flag + o + rs, x0, y0, W.P.lx, W.P.ly);
+    const uint32_t end =
+        wg_compact(S, V, A.flag + o + rs, cnt, A.cd_xy + o, A.cd_idx + o, A.sv_xy + o, A.sv_idx + o, rs);
+    if (tid == 0) {
+        W.k[R.r] = end - rs;
+        W.klo[R.r] = rs;
+    }
+}
+
+// ---- Step 8 of a set over its kept points (right region, then the left)
+__global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k_wstep8(WideArgs A) {
+    __shared__ BatchLds S;
+    const int32_t s = A.order[blockIdx.x];
+    const WSetIn in = A.in[s];
+    const uint32_t tid = threadIdx.x;
+    const WSet& W = A.ws[s];
+    if (in.n == 0 || W.flags != 0u) {
+        if (tid == 0) {
+            A.h_count[s] = 0;
+            A.h_start[s] = 0;
+            A.h_flags[s] = in.n == 0 ? 0u : W.flags;
+        }
+        return;
+    }
+    const size_t o = (size_t)in.o;
+    const uint32_t k0 = W.m1 > 0 ? W.k[0] : 0u, k1 = W.m1 > 0 ? W.k[1] : 0u;
+    const uint32_t lo0 = W.klo[0], lo1 = W.klo[1];
+    const uint32_t m = k0 + k1;
+    uint32_t* first = A.ka + o;
+    for (uint32_t q = tid; q < m; q += kBB) first[q] = q < k0 ? lo0 + q : lo1 + (q - k0);
+    __syncthreads();
+    HullSink H;
+    H.hull = A.hull;
+    H.cursor = A.hull_cursor;
+    H.count = A.h_count;
+    H.start = A.h_start;
+    H.flags = A.h_flags;
+    batch_step8(S, H, s, A.sv_xy + o, A.sv_idx + o, first, m, A.ka + o, A.kb + o, A.va + o, W.P.x0, W.P.y0,
+                W.P.p0_idx);
+}
+
+}  // namespace
+
+hipError_t launch_wide(const WideArgs& a, hipStream_t s) {
+    if (a.S <= 0) return hipSuccess;
+    const dim3 S1((unsigned)a.S), NT((unsigned)a.NT), S2((unsigned)(2 * a.S));
+    hipLaunchKernelGGL(k_wprep, S1, dim3(kWB), 0, s, a);
+    if (a.NT > 0) hipLaunchKernelGGL(k_wext, NT, dim3(kWB), 0, s, a);
+    hipLaunchKernelGGL(k_wparams, S1, dim3(64), 0, s, a);
+    if (a.NT > 0) hipLaunchKernelGGL(k_wfilter, NT, dim3(kWB), 0, s, a);
+    hipLaunchKernelGGL(k_wfar, S1, dim3(64), 0, s, a);
+    if (a.NT > 0) hipLaunchKernelGGL(k_wbmax, NT, dim3(kWB), 0, s, a);
+    hipLaunchKernelGGL(k_wprefix, S1, dim3(kWB), 0, s, a);
+    if (a.NT > 0) hipLaunchKernelGGL(k_wcand, NT, dim3(kWB), 0, s, a);
+    hipLaunchKernelGGL(k_wgroup, S1, dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(k_wwalk_small, dim3((unsigned)((2 * a.S + kBW - 1) / kBW)), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(k_wwalk, S2, dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(k_wwalk_radix, S2, dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(k_wstep8, S1, dim3(kBB), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace hx

@@ -417,31 +417,38 @@ struct Cls {
 };
 
 // Region by the exact angular order (angle key first, orientation on equal
-// keys, distance along the ray on the same ray), then the direction key.
-__device__ inline Cls classify(double x, double y, uint32_t key, const Params& P) {
+// keys, distance along the ray on the same ray), then the direction key;
+// from the fields it reads (P_0, P_l, its key and both turn keys).
+__device__ inline Cls classify_at(double x, double y, uint32_t key, double x0, double y0, double lx,
+                                  double ly, uint32_t kl, uint32_t turn_u, uint32_t turn_v) {
     Cls c;
     c.bucket = key >> (32 - kBucketBits);
     c.kappa = 0;
-    if (x == P.lx && y == P.ly) {
+    if (x == lx && y == ly) {
         c.region = 2;
         return c;
     }
     int region;
-    if (key < P.kl) {
+    if (key < kl) {
         region = 0;
-    } else if (key > P.kl) {
+    } else if (key > kl) {
         region = 1;
     } else {
-        int o = orient(P.x0, P.y0, P.lx, P.ly, x, y);
+        int o = orient(x0, y0, lx, ly, x, y);
         if (o != 0) region = o < 0 ? 0 : 1;
-        else region = (y < P.ly || (y == P.ly && x < P.lx)) ? 0 : 1;
+        else region = (y < ly || (y == ly && x < lx)) ? 0 : 1;
     }
-    uint32_t F = turn_key(x, y, P.lx, P.ly);
+    uint32_t F = turn_key(x, y, lx, ly);
     // right region: counter-clockwise from P_0 - P_l; left region: clockwise
     // from P_l - P_0 (the key is reversed so that larger always follows)
-    c.kappa = region == 0 ? F - P.turn_u : 0xFFFFFFFFu - (F - P.turn_v);
+    c.kappa = region == 0 ? F - turn_u : 0xFFFFFFFFu - (F - turn_v);
     c.region = region;
     return c;
+}
+
+// The same with the fields taken from the call's parameters.
+__device__ inline Cls classify(double x, double y, uint32_t key, const Params& P) {
+    return classify_at(x, y, key, P.x0, P.y0, P.lx, P.ly, P.kl, P.turn_u, P.turn_v);
 }
 
 // Exclusive prefix maxima of one region's bucket maxima in walking order:

@@ -79,5 +79,5 @@ def test_shipped_batch_schedule_is_valid():
         pytest.skip("no tuned schedule in the tree")
     t = hx.tuned_batch_schedule()
     assert t["batch_blocks_per_cu"] in (1, 2) and t["batch_order"] in (0, 1, 2)
-    # uint32 struct_size and eleven int32 fields, as hull2d_options
-    assert ctypes.sizeof(hx._Options) == 4 + 11 * 4
+    # uint32 struct_size and twelve int32 fields, as hull2d_options
+    assert ctypes.sizeof(hx._Options) == 4 + 12 * 4

@@ -42,9 +42,12 @@ def hx(torch_dev):
     return hx
 
 
-@pytest.fixture(scope="module")
-def ctx(hx):
-    return hx.Hull2D()
+@pytest.fixture(scope="module", params=[0, 1], ids=["tiled", "persistent"])
+def ctx(hx, request):
+    """A context of each batch engine: tiled (the default) and persistent."""
+    c = hx.Hull2D(batch_engine=request.param)
+    yield c
+    c.close()
 
 
 def _mixed_sets():
@@ -100,6 +103,45 @@ def test_batch_mixed_sets(torch_dev, ctx):
     hulls, out_offs = ctx.batch(d, offs)
     _check_all(hulls, out_offs, sets)
     assert ctx.last_stats.n_candidates >= 1  # the long collinear run went to the host
+
+
+def test_batch_tile_boundaries(torch_dev, ctx):
+    """Sets one point either side of the 4096-point tile and of two tiles,
+    several distributions: the oracle's hulls."""
+    sets = []
+    for i, n in enumerate([1, 2, 3, 4095, 4096, 4097, 8191, 8192, 8193, 12_289]):
+        sets.append(synth.square(n, (160 + i, 1)))
+        sets.append(synth.annulus(n, 0.999, (170 + i, 1)))
+        sets.append(synth.gaussian(n, 1.0, (180 + i, 1)))
+    pts, offs = _concat(sets)
+    say(f"batch tile boundaries S={len(sets)}")
+    hulls, out_offs = ctx.batch(torch_dev.from_numpy(pts).cuda(), offs)
+    _check_all(hulls, out_offs, sets)
+    assert ctx.last_stats.n_candidates == 0
+
+
+def _sliver(n, seed, angle):
+    """n points in a thin triangle (height 1e-4 of its length) rotated by
+    `angle`: seen from its lowest point nearly every point falls in one or
+    two angle buckets."""
+    rng = np.random.default_rng(seed)
+    u, v = rng.random(n), rng.random(n)
+    x, y = u, 1e-4 * u * v
+    c, s = np.cos(angle), np.sin(angle)
+    return np.stack([c * x - s * y, s * x + c * y], axis=1)
+
+
+def test_batch_crowded_buckets(torch_dev, ctx):
+    """Buckets holding more candidates than one walk tile (the tiled engine
+    sorts such a region with the radix sort in HBM); no set needs the host."""
+    sets = [_sliver(n, 190 + i, a) for i, (n, a) in
+            enumerate([(20_000, 0.3), (9_000, 1.2), (30_000, 2.5), (5_000, -0.7), (60_000, 0.01)])]
+    sets.append(synth.square(3000, (199, 1)))
+    pts, offs = _concat(sets)
+    say(f"batch crowded buckets S={len(sets)}")
+    hulls, out_offs = ctx.batch(torch_dev.from_numpy(pts).cuda(), offs)
+    _check_all(hulls, out_offs, sets)
+    assert ctx.last_stats.n_candidates == 0
 
 
 def test_batch_equals_compute(torch_dev, ctx):
@@ -230,7 +272,7 @@ def test_batch_schedules_agree(torch_dev, hx, blocks, order):
     pts, offs = _concat(sets)
     d = torch_dev.from_numpy(pts).cuda()
     say(f"batch schedule blocks={blocks} order={order}")
-    c = hx.Hull2D(batch_blocks_per_cu=blocks, batch_order=order)
+    c = hx.Hull2D(batch_blocks_per_cu=blocks, batch_order=order, batch_engine=1)
     h, o = c.batch(d, offs)
     _check_all(h, o, sets)
     c.close()
