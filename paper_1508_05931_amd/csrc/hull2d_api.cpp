@@ -132,7 +132,7 @@ struct hull2d_ctx {
     WSetIn* hb_win = nullptr;      // tiled engine: per-set layout (hb_cap_s entries)
     int batch_grid = 0;
     // tiled engine: per-set records, tile arrays, bucket tables
-    int64_t wcap_s = -1, wcap_nt = -1, wcap_te = -1;
+    int64_t wcap_s = -1, wcap_nt = -1, wcap_se = -1;
     char* wmem = nullptr;
     WSetIn* w_in = nullptr;
     WSet* w_set = nullptr;
@@ -140,8 +140,8 @@ struct hull2d_ctx {
     Cand* w_tile_ext = nullptr;
     uint32_t* w_tile_flags = nullptr;
     WFar* w_tile_far = nullptr;
-    uint32_t *w_tile_cnt = nullptr, *w_tile_ccnt = nullptr;
-    uint32_t *w_tab = nullptr, *w_bcnt = nullptr;
+    uint32_t* w_tile_cnt = nullptr;
+    uint32_t* w_bcnt = nullptr;
     // the batched form's device work captured in a graph, and what it was
     // captured for (replayed while all of it is unchanged)
     hipStream_t cap_stream = nullptr;
@@ -495,10 +495,10 @@ hull2d_status ensure_batch(hull2d_ctx* c, int64_t N, int32_t S) {
     return HULL2D_OK;
 }
 
-// The tiled engine's device workspace for S sets, NT tiles and TE entries of
-// each bucket table.
-hull2d_status ensure_wide(hull2d_ctx* c, int64_t S, int64_t NT, int64_t TE) {
-    if (S <= c->wcap_s && NT <= c->wcap_nt && TE <= c->wcap_te) return HULL2D_OK;
+// The tiled engine's device workspace for S sets, NT tiles and SE entries
+// of the sort-bucket table.
+hull2d_status ensure_wide(hull2d_ctx* c, int64_t S, int64_t NT, int64_t SE) {
+    if (S <= c->wcap_s && NT <= c->wcap_nt && SE <= c->wcap_se) return HULL2D_OK;
     if (c->bgraph) {
         (void)hipStreamSynchronize(c->stream);
         (void)hipGraphExecDestroy(c->bgraph);
@@ -506,19 +506,18 @@ hull2d_status ensure_wide(hull2d_ctx* c, int64_t S, int64_t NT, int64_t TE) {
     }
     const int64_t ws = std::max<int64_t>(std::max<int64_t>(S, c->wcap_s), 1);
     const int64_t wt = std::max<int64_t>(std::max<int64_t>(NT, c->wcap_nt), 1);
-    const int64_t we = std::max<int64_t>(std::max<int64_t>(TE, c->wcap_te), 1);
+    const int64_t wse = std::max<int64_t>(std::max<int64_t>(SE, c->wcap_se), 1);
     if (c->wmem) {
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(c->wmem);
         c->wmem = nullptr;
-        c->wcap_s = c->wcap_nt = c->wcap_te = -1;
+        c->wcap_s = c->wcap_nt = c->wcap_se = -1;
     }
-    const size_t sizes[10] = {(size_t)ws * sizeof(WSetIn), (size_t)ws * sizeof(WSet),
-                              (size_t)wt * 4, (size_t)wt * 4 * sizeof(Cand), (size_t)wt * 4,
-                              (size_t)wt * sizeof(WFar), (size_t)wt * 4, (size_t)wt * 4,
-                              (size_t)we * 4, (size_t)we * 4};
-    size_t off[10], o = 0;
-    for (int i = 0; i < 10; ++i) {
+    const size_t sizes[8] = {(size_t)ws * sizeof(WSetIn), (size_t)ws * sizeof(WSet),
+                             (size_t)wt * 4, (size_t)wt * 4 * sizeof(Cand), (size_t)wt * 4,
+                             (size_t)wt * sizeof(WFar), (size_t)wt * 4, (size_t)wse * 4};
+    size_t off[8], o = 0;
+    for (int i = 0; i < 8; ++i) {
         off[i] = o;
         o = align_up(o + sizes[i], 256);
     }
@@ -535,12 +534,10 @@ hull2d_status ensure_wide(hull2d_ctx* c, int64_t S, int64_t NT, int64_t TE) {
     c->w_tile_flags = (uint32_t*)(b + off[4]);
     c->w_tile_far = (WFar*)(b + off[5]);
     c->w_tile_cnt = (uint32_t*)(b + off[6]);
-    c->w_tile_ccnt = (uint32_t*)(b + off[7]);
-    c->w_tab = (uint32_t*)(b + off[8]);
-    c->w_bcnt = (uint32_t*)(b + off[9]);
+    c->w_bcnt = (uint32_t*)(b + off[7]);
     c->wcap_s = ws;
     c->wcap_nt = wt;
-    c->wcap_te = we;
+    c->wcap_se = wse;
     return HULL2D_OK;
 }
 
@@ -1387,31 +1384,33 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         }
         for (int32_t i = 0; i < S; ++i) c->hb_order[pos[cls(i)]++] = i;
     }
-    // the tiled engine's layout: each set's tiles and bucket tables (2^bb
-    // buckets per region: about a quarter of the set's size, 16 to 4096)
+    // the tiled engine's layout: each set's tiles and bucket counts (2^bf
+    // buckets per region for the bucket maxima, about a quarter of the set's
+    // size, 16 to 16,384; 2^bs sort buckets, at most 4,096)
     const int engine = c->opt.batch_engine;
-    int64_t NT = 0, TE = 0;
+    int64_t NT = 0, SE = 0;
     if (engine == 0) {
         for (int32_t i = 0; i < S; ++i) {
             const int64_t n = size_of(i);
             WSetIn& w = c->hb_win[i];
-            uint32_t bb = 0;
+            uint32_t bf = 0;
             if (n > 0) {
-                bb = 4;
-                while (bb < 12 && ((int64_t)1 << bb) < (n + 3) / 4) ++bb;
+                bf = 4;
+                while (bf < (uint32_t)kWideFilterBits && ((int64_t)1 << bf) < (n + 3) / 4) ++bf;
             }
             w.o = h_offsets[i];
             w.n = (uint32_t)n;
             w.t0 = (uint32_t)NT;
             w.nt = (uint32_t)((n + kWideTile - 1) / kWideTile);
-            w.bb = bb;
-            w.toff = (uint32_t)TE;
+            w.bf = bf;
+            w.bs = std::min<uint32_t>(bf, (uint32_t)kWideSortBits);
+            w.soff = (uint32_t)SE;
             w.pad = 0;
             NT += w.nt;
-            TE += n > 0 ? ((int64_t)2 << bb) : 0;
-            if (NT > (int64_t)UINT32_MAX || TE > (int64_t)UINT32_MAX) return HULL2D_ERR_OUT_OF_MEMORY;
+            SE += n > 0 ? ((int64_t)2 << w.bs) : 0;
+            if (NT > (int64_t)UINT32_MAX || SE > (int64_t)UINT32_MAX) return HULL2D_ERR_OUT_OF_MEMORY;
         }
-        st = ensure_wide(c, S, NT, TE);
+        st = ensure_wide(c, S, NT, SE);
         if (st != HULL2D_OK) return st;
     }
     int32_t* d_count = c->b_meta + 1;
@@ -1439,8 +1438,6 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 a.tile_flags = c->w_tile_flags;
                 a.tile_far = c->w_tile_far;
                 a.tile_cnt = c->w_tile_cnt;
-                a.tile_ccnt = c->w_tile_ccnt;
-                a.tab = c->w_tab;
                 a.bcnt = c->w_bcnt;
                 a.sv_xy = c->b_sv_xy;
                 a.sv_idx = c->b_sv_idx;

@@ -245,11 +245,14 @@ constexpr uint32_t kBatchFallback = 4u;
 constexpr uint32_t kWideTile = 4096;
 
 // Per set, written by the host: the set's first point, its size, its tiles
-// (t0 .. t0 + nt) and its bucket tables (toff .. toff + 2^(bb+1) entries of
-// each table; 2^bb buckets per region).
+// (t0 .. t0 + nt), its bucket counts (2^bf buckets per region for the
+// bucket maxima, held in LDS; 2^bs per region for the sort buckets, whose
+// ends take entries soff .. soff + 2^(bs+1) of bcnt).
+constexpr int kWideFilterBits = 14;  // at most 16,384 filter buckets per region
+constexpr int kWideSortBits = 12;    // at most 4,096 sort buckets per region
 struct WSetIn {
     int64_t o;
-    uint32_t n, t0, nt, bb, toff, pad;
+    uint32_t n, t0, nt, bf, bs, soff, pad;
 };
 
 // Per set, written by the device.
@@ -283,13 +286,11 @@ struct WideArgs {
     uint32_t* tile_flags;  // [NT]
     WFar* tile_far;        // [NT]
     uint32_t* tile_cnt;    // [NT] survivors of the tile (at its own first position)
-    uint32_t* tile_ccnt;   // [NT] candidates of the tile (likewise)
-    uint32_t* tab;         // bucket maxima, then their exclusive prefix maxima
-    uint32_t* bcnt;        // candidates per sort bucket, then bucket starts, then ends
+    uint32_t* bcnt;        // the sort buckets' ends
     double2* sv_xy;        // [N] survivors; after the walk, the kept points
     uint32_t* sv_idx;
     uint32_t* sv_key;
-    double2* cd_xy;        // [N] candidates, packed tile by tile
+    double2* cd_xy;        // [N] candidates, packed per set
     uint32_t* cd_idx;
     uint32_t* cd_key;
     uint32_t *ka, *kb, *va, *vb;  // [N] sort and Step-8 scratch

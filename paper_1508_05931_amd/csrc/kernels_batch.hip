@@ -38,7 +38,6 @@ constexpr int kBI = 4;                  // items per thread per tile
 constexpr int kBT = kBB * kBI;          // items per tile
 constexpr int kBLongMax = 64;           // equal-key runs longer than kRunSmall per region
 constexpr uint32_t kGLds = 2048;        // Step 8: below this size the points move to LDS
-constexpr uint32_t kGOne = 64;          // Step 8: one thread finishes below this size
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 struct alignas(16) BatchLds {
@@ -519,6 +518,102 @@ __device__ __forceinline__ uint32_t graham_lds(const double* __restrict__ gx, co
     return top;
 }
 
+// Joins T neighbouring chains pairwise until one is left.  Chain t (each
+// the stack scan of P_0 followed by chunk t of ch points of the list, a
+// convex chain after P_0) starts at position t * ch of P[0]; its length is
+// len0[t].  Two neighbouring chains A (earlier) and B combine into the chain
+// of their union by keeping a prefix a_1..a_i of A and a suffix b_j..b_q of
+// B: for a point b of B, the prefix of A the scan keeps when b arrives is the
+// longest whose every step turns left before b (orient(a_{k-1}, a_k, b) > 0,
+// a_0 = P_0), a test monotone in k, so a binary search finds it; the bridge
+// is the one b_j whose a = a_i has a -> b_{j-1} -> b_j not a left turn and
+// a -> b_j -> b_{j+1} a left turn.  np positions in use; entries are LDS
+// indices into (X, Y).  Returns the buffer (0: P0, 1: P1) holding the result
+// as its chain 0, whose length is then len0[0] or len1[0].
+__device__ __forceinline__ int lds_combine(const double* X, const double* Y, uint16_t* P0, uint16_t* P1,
+                                           uint16_t* len0, uint16_t* len1, uint16_t* bi, uint16_t* bj, int T,
+                                           int np, int ch, double x0, double y0) {
+    const int tid = (int)threadIdx.x;
+    int cur = 0;
+    for (int L = 0; (1 << L) < T; ++L) {
+        const int TL = (T + (1 << L) - 1) >> L;
+        const uint16_t* P = cur ? P1 : P0;
+        uint16_t* Q = cur ? P0 : P1;
+        const uint16_t* len = cur ? len1 : len0;
+        uint16_t* nlen = cur ? len0 : len1;
+        // no bridge found (B empty): all of A, none of B
+        for (int t = tid; t < TL / 2; t += kBB) {
+            bi[t] = len[2 * t];
+            bj[t] = len[2 * t + 1];
+        }
+        __syncthreads();
+        for (int s = tid; s < np; s += kBB) {
+            const int c = (s / ch) >> L;
+            if ((c & 1) == 0) continue;
+            const int j = s - ((c * ch) << L);
+            const int q = len[c];
+            if (j >= q) continue;
+            const int sa = ((c - 1) * ch) << L;
+            const int p = len[c - 1];
+            const int pb = P[s];
+            const double bx = X[pb], by = Y[pb];
+            int lo = 0, hi = p;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int pk = P[sa + mid];
+                double px = x0, py = y0;
+                if (mid > 0) {
+                    const int pp = P[sa + mid - 1];
+                    px = X[pp];
+                    py = Y[pp];
+                }
+                if (orient(px, py, X[pk], Y[pk], bx, by) > 0) lo = mid + 1;
+                else hi = mid;
+            }
+            const int i = lo;
+            double ax = x0, ay = y0;
+            if (i > 0) {
+                const int pa = P[sa + i - 1];
+                ax = X[pa];
+                ay = Y[pa];
+            }
+            bool bridge = true;
+            if (j > 0) {
+                const int pp = P[s - 1];
+                bridge = orient(ax, ay, X[pp], Y[pp], bx, by) <= 0;
+            }
+            if (bridge && j + 1 < q) {
+                const int pn = P[s + 1];
+                bridge = orient(ax, ay, bx, by, X[pn], Y[pn]) > 0;
+            }
+            if (bridge) {
+                bi[c >> 1] = (uint16_t)i;
+                bj[c >> 1] = (uint16_t)j;
+            }
+        }
+        __syncthreads();
+        for (int s = tid; s < np; s += kBB) {
+            const int c = (s / ch) >> L;
+            const int k = s - ((c * ch) << L);
+            if (k >= len[c]) continue;
+            int dst = -1;
+            if ((c & 1) == 0) {
+                if (c + 1 >= TL || k < bi[c >> 1]) dst = s;
+            } else if (k >= bj[c >> 1]) {
+                dst = (((c - 1) * ch) << L) + bi[c >> 1] + (k - bj[c >> 1]);
+            }
+            if (dst >= 0) Q[dst] = P[s];
+        }
+        for (int t = tid; t < (TL + 1) / 2; t += kBB) {
+            const int b = 2 * t + 1;
+            nlen[t] = b < TL ? (uint16_t)(bi[t] + (len[b] - bj[t])) : len[2 * t];
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    return cur;
+}
+
 // Where a set's hull goes: hull[start[s] ..+ count[s]], flags[s] = 0.
 struct HullSink {
     int32_t* hull;
@@ -571,31 +666,33 @@ __device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int3
             S.u.gs.pos[i] = pos;
         }
         __syncthreads();
-        uint16_t* cur = nullptr;
-        uint16_t* b16[3] = {S.u.gs.a, S.u.gs.b, S.u.gs.c};
-        int k = 0;
-        bool stk = false;
-        while (len > kGOne && !stk) {
-            const uint32_t ch = max(8u, (len + kBB - 1) / kBB);
-            uint16_t* st = b16[k % 3] == cur ? b16[(k + 1) % 3] : b16[k % 3];
-            uint16_t* dst = nullptr;
-            for (int q = 0; q < 3; ++q)
-                if (b16[q] != cur && b16[q] != st) dst = b16[q];
-            const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
-            const uint32_t h = graham_lds(S.u.gs.x, S.u.gs.y, cur, beg, end, st + beg, x0, y0);
-            uint32_t tot;
-            const uint32_t at = bexcl(h, S, tot);
-            for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
-            __syncthreads();
-            stk = (uint64_t)tot * 10u > (uint64_t)len * 9u;
-            cur = dst;
-            len = tot;
-            ++k;
+        // repeats dropped (copies of a point are adjacent): a[] lists the
+        // LDS entries of the first copy of each point, in order
+        uint32_t keep = 0;
+        const uint32_t per = (len + kBB - 1) / kBB;  // at most kGLds / kBB
+        const uint32_t i0 = min(len, (uint32_t)tid * per), i1 = min(len, i0 + per);
+        for (uint32_t i = i0; i < i1; ++i)
+            keep += (i == 0 || S.u.gs.x[i] != S.u.gs.x[i - 1] || S.u.gs.y[i] != S.u.gs.y[i - 1]) ? 1u : 0u;
+        uint32_t np;
+        uint32_t at = bexcl(keep, S, np);
+        for (uint32_t i = i0; i < i1; ++i)
+            if (i == 0 || S.u.gs.x[i] != S.u.gs.x[i - 1] || S.u.gs.y[i] != S.u.gs.y[i - 1])
+                S.u.gs.a[at++] = (uint16_t)i;
+        __syncthreads();
+        // chunk scans, then neighbouring chains joined at their common
+        // tangent, level by level
+        uint16_t* lens = S.u.gs.c;  // [2][kBB] chain lengths, then the bridges
+        const uint32_t ch = max(4u, (np + kBB - 1) / kBB);
+        const int T = np == 0 ? 0 : (int)((np + ch - 1) / ch);
+        if (tid < T) {
+            const uint32_t beg = (uint32_t)tid * ch, end = min(np, beg + ch);
+            lens[tid] = (uint16_t)graham_lds(S.u.gs.x, S.u.gs.y, S.u.gs.a, beg, end, S.u.gs.b + beg, x0, y0);
         }
-        fin16 = S.u.gs.a;
-        for (int q = 0; q < 3; ++q)
-            if (b16[q] != cur) fin16 = b16[q];
-        if (tid == 0) S.h = graham_lds(S.u.gs.x, S.u.gs.y, cur, 0, len, fin16, x0, y0) + 1u;
+        __syncthreads();
+        const int cur = lds_combine(S.u.gs.x, S.u.gs.y, S.u.gs.b, S.u.gs.a, lens, lens + kBB,
+                                    lens + 2 * kBB, lens + 2 * kBB + kBB / 2, T, (int)np, (int)ch, x0, y0);
+        fin16 = cur == 0 ? S.u.gs.b : S.u.gs.a;
+        if (tid == 0) S.h = (T == 0 ? 0u : (uint32_t)lens[cur * kBB]) + 1u;
     } else {
         for (int q = 0; q < 3; ++q)
             if (bufs[q] != cur_a) fin = bufs[q];
@@ -1063,6 +1160,7 @@ constexpr int kCI = (int)kCT / kBB;   // walk positions per thread
 constexpr uint32_t kSortOne = 32;     // buckets up to this size: one thread sorts them
 constexpr uint16_t kInf16 = 0xFFFFu;  // bitonic padding (after every real entry)
 static_assert(kCI * kBB == (int)kCT, "walk tile");
+static_assert(kBuckets == 1 << kWideSortBits, "sort buckets per region");
 static_assert(kCT < kInf16, "16-bit tile positions");
 
 struct WalkTile {
@@ -1095,14 +1193,12 @@ __device__ inline uint32_t wide_tile_set(const WideArgs& A, uint32_t t, WSetIn& 
     return (uint32_t)s;
 }
 
-// ---- prep: tile owners, cleared tables and counters (one workgroup per set)
+// ---- prep: tile owners and cleared counters (one workgroup per set)
 __global__ __launch_bounds__(kWB) void k_wprep(WideArgs A) {
     const int32_t s = (int32_t)blockIdx.x;
     const WSetIn in = A.in[s];
     const uint32_t tid = threadIdx.x;
     for (uint32_t j = tid; j < in.nt; j += kWB) A.tile_set[in.t0 + j] = s;
-    const uint32_t ent = in.n > 0 ? (2u << in.bb) : 0u;
-    for (uint32_t j = tid; j < ent; j += kWB) A.tab[in.toff + j] = 0u;
     if (tid == 0) {
         WSet& W = A.ws[s];
         W.flags = 0u;
@@ -1347,72 +1443,13 @@ struct WCls {
     __device__ Cls operator()(double x, double y, uint32_t key) const {
         return classify_at(x, y, key, x0, y0, lx, ly, kl, tu, tv);
     }
+    __device__ Cls near(double x, double y, uint32_t key) const {
+        return classify_near(x, y, key, x0, y0, lx, ly, kl, tu, tv);
+    }
 };
 
-// ---- Steps 6-7, bucket maxima: the survivors of a group of kBGroup tiles
-//      of one set reduced in an LDS table, whose non-empty entries go to the
-//      set's table; every survivor's direction key and region are kept for
-//      the candidate pass (ka and the bytes of vb)
-constexpr uint32_t kBGroup = 8;
-
-__global__ __launch_bounds__(kWB) void k_wbmax(WideArgs A) {
-    __shared__ uint32_t s_tab[2 * kBuckets];
-    const int tid = (int)threadIdx.x;
-    const uint32_t t = blockIdx.x;
-    WSetIn in;
-    uint32_t lo, hi;
-    const uint32_t s = wide_tile_set(A, t, in, lo, hi);
-    if ((t - in.t0) % kBGroup != 0u) return;
-    const WSet& W = A.ws[s];
-    if (W.flags != 0u || W.m1 == 0u) return;
-    const WCls C(W.P);
-    const uint32_t sh = 32u - in.bb;
-    const uint32_t ent = 2u << in.bb;
-    const size_t o = (size_t)in.o;
-    const double2* sv_xy = A.sv_xy + o;
-    const uint32_t* sv_key = A.sv_key + o;
-    uint32_t* kap = A.ka + o;
-    uint8_t* reg = reinterpret_cast<uint8_t*>(A.vb) + o;
-    for (uint32_t j = (uint32_t)tid; j < ent; j += kWB) s_tab[j] = 0u;
-    __syncthreads();
-    const uint32_t tend = min(t + kBGroup, in.t0 + in.nt);
-    for (uint32_t u = t; u < tend; ++u) {
-        const uint32_t ulo = (u - in.t0) * kWT, uend = ulo + A.tile_cnt[u];
-        for (uint32_t b0 = ulo; b0 < uend; b0 += kWB * kWI) {
-            double2 p[kWI];
-            uint32_t key[kWI];
-#pragma unroll
-            for (int k = 0; k < kWI; ++k) {
-                const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
-                p[k] = make_double2(0.0, 0.0);
-                key[k] = 0;
-                if (i < uend) {
-                    p[k] = sv_xy[i];
-                    key[k] = sv_key[i];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kWI; ++k) {
-                const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
-                if (i < uend) {
-                    const Cls cl = C(p[k].x, p[k].y, key[k]);
-                    if (cl.region < 2) atomicMax(&s_tab[((uint32_t)cl.region << in.bb) + (key[k] >> sh)], cl.kappa);
-                    kap[i] = cl.kappa;
-                    reg[i] = (uint8_t)cl.region;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    uint32_t* tab = A.tab + in.toff;
-    for (uint32_t j = (uint32_t)tid; j < ent; j += kWB) {
-        const uint32_t v = s_tab[j];
-        if (v != 0u) atomicMax(&tab[j], v);
-    }
-}
-
-// Exclusive block scan over kWB threads (sum or max); all threads call it.
-template <bool kMax>
+// Exclusive block scan over kT threads (sum or max); all threads call it.
+template <bool kMax, int kT>
 __device__ inline uint32_t wblock_scan(uint32_t v, uint32_t* s_w, uint32_t& total) {
     const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
     uint32_t inc = v;
@@ -1425,7 +1462,7 @@ __device__ inline uint32_t wblock_scan(uint32_t v, uint32_t* s_w, uint32_t& tota
     __syncthreads();
     uint32_t pre = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWW; ++w) {
+    for (int w = 0; w < kT / 64; ++w) {
         const uint32_t x = s_w[w];
         if (w < wave) pre = kMax ? max(pre, x) : pre + x;
         tot = kMax ? max(tot, x) : tot + x;
@@ -1437,216 +1474,280 @@ __device__ inline uint32_t wblock_scan(uint32_t v, uint32_t* s_w, uint32_t& tota
     return kMax ? max(pre, lane_ex) : pre + lane_ex;
 }
 
-// ---- Steps 6-7, prefix maxima of each region's bucket maxima in walking
-//      order (right region ascending from kappa(P_0) = 0, left region
-//      descending), in place; one workgroup per set
-__global__ __launch_bounds__(kWB) void k_wprefix(WideArgs A) {
-    __shared__ uint32_t s_w[kWW];
-    const int32_t s = (int32_t)blockIdx.x;
-    const WSetIn in = A.in[s];
-    const uint32_t tid = threadIdx.x;
-    if (in.n == 0) return;
-    const WSet& W = A.ws[s];
-    if (W.flags != 0u || W.m1 == 0u) return;
-    const uint32_t B = 1u << in.bb;
-    const uint32_t per = B > (uint32_t)kWB ? B / kWB : 1u;
-    constexpr int kPer = kBuckets / kWB;
-    for (int region = 0; region < 2; ++region) {
-        uint32_t* T = A.tab + in.toff + ((uint32_t)region << in.bb);
-        uint32_t v[kPer];
-        uint32_t tmax = 0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t w = tid * per + (uint32_t)k;
-            v[k] = 0;
-            if ((uint32_t)k < per && w < B) {
-                v[k] = T[region == 0 ? w : B - 1 - w];
-                tmax = max(tmax, v[k]);
-            }
-        }
-        uint32_t tot;
-        uint32_t run = wblock_scan<true>(tmax, s_w, tot);
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t w = tid * per + (uint32_t)k;
-            if ((uint32_t)k < per && w < B) {
-                T[region == 0 ? w : B - 1 - w] = run;
-                run = max(run, v[k]);
-            }
-        }
-    }
-}
+// ---- Steps 6-7 of one set in one workgroup (sets largest first): the
+//      bucket maxima of its survivors' direction keys (an LDS table of 2^bf
+//      buckets per region; the keys from turn_key_near, each within
+//      kTurnSlack / 8 of the exact one, and each survivor's key and region
+//      kept in ka and the bytes of vb), their exclusive prefix maxima in
+//      walking order (right region ascending from kappa(P_0) = 0, left
+//      region descending), the candidates (every survivor whose key plus
+//      kTurnSlack reaches the prefix maximum: a point dropped has an exact
+//      key below that of a point in an earlier bucket, so the exact walk
+//      drops it too; packed at the set's first
+//      positions of cd_*, with their sort region in flag: before P_l in the
+//      exact angular order 0, P_l and after 1), then the candidates grouped
+//      by sort bucket: counted in LDS, the bucket starts (region 0 from 0,
+//      region 1 after it), every candidate's angle key and position placed
+//      in its bucket of gk (order within a bucket arbitrary: the walk sorts
+//      each tile); the bucket ends, region sizes and largest buckets go to
+//      global memory for the walk.
+//      Two instances: sets of more than 2^kSmallBits buckets per region get
+//      1024 threads and the 128 KB table (one workgroup per compute unit),
+//      the others 256 threads and a 16 KB table.
+constexpr int kSmallBits = 11;
+constexpr uint32_t kPreTiles = 2048;  // sets of up to this many tiles spread their survivors evenly
 
-// ---- Steps 6-7, candidates of a tile: kept by the prefix maxima, given
-//      their sort region (before P_l in the exact angular order: 0; P_l and
-//      after: 1), packed at the tile's first position
-__global__ __launch_bounds__(kWB) void k_wcand(WideArgs A) {
-    __shared__ uint32_t s_cnt;
+template <int kBits, int kMB>
+__global__ __launch_bounds__(kMB) void k_wset(WideArgs A) {
+    constexpr int kMW = kMB / 64;
+    constexpr uint32_t kFiltMax = 1u << kBits;
+    constexpr uint32_t kSortMax = 1u << (kBits < kWideSortBits ? kBits : kWideSortBits);
+    static_assert(kFiltMax % kMB == 0 && kSortMax % kMB == 0, "whole buckets per thread");
+    __shared__ uint32_t s_tab[2 * kFiltMax];
+    __shared__ uint32_t s_pre[kPreTiles + 1];  // survivors before each tile
+    __shared__ uint32_t s_w[kMW];
+    __shared__ uint32_t s_nc;
     const int tid = (int)threadIdx.x;
-    const uint32_t t = blockIdx.x;
-    WSetIn in;
-    uint32_t lo, hi;
-    const uint32_t s = wide_tile_set(A, t, in, lo, hi);
-    const WSet& W = A.ws[s];
-    if (W.flags != 0u || W.m1 == 0u) return;
-    const uint32_t cnt = A.tile_cnt[t];
-    const WCls C(W.P);
-    const uint32_t lslot = W.lslot;
-    const uint32_t sh = 32u - in.bb;
-    const uint32_t* tab = A.tab + in.toff;
-    const size_t o = (size_t)in.o;
-    const uint32_t* kap = A.ka + o;
-    const uint8_t* reg = reinterpret_cast<const uint8_t*>(A.vb) + o;
-    if (tid == 0) s_cnt = 0u;
-    __syncthreads();
-    for (uint32_t b0 = lo; b0 < lo + cnt; b0 += kWB) {
-        const uint32_t i = b0 + (uint32_t)tid;
-        bool keep = false;
-        double2 p = make_double2(0.0, 0.0);
-        uint32_t key = 0, idx = 0, sreg = 0;
-        if (i < lo + cnt) {
-            key = A.sv_key[o + i];
-            const uint32_t region = reg[i];
-            const uint32_t bucket = key >> sh;
-            keep = region == 2u || kap[i] >= tab[(region << in.bb) + bucket];
-            if (keep) {
-                p = A.sv_xy[o + i];
-                idx = A.sv_idx[o + i];
-                if (key != C.kl) sreg = key < C.kl ? 0u : 1u;
-                else if (i == lslot) sreg = 1u;
-                else sreg = angle_less(p.x, p.y, idx, C.lx, C.ly, (uint32_t)C.l_idx, C.x0, C.y0) ? 0u : 1u;
-            }
-        }
-        const uint32_t at = wave_append(keep, &s_cnt);
-        if (keep) {
-            const size_t q = o + lo + at;
-            A.cd_xy[q] = p;
-            A.cd_idx[q] = idx;
-            A.cd_key[q] = key;
-            A.flag[q] = (uint8_t)sreg;
-        }
-    }
-    __syncthreads();
-    if (tid == 0) A.tile_ccnt[t] = s_cnt;
-}
-
-// ---- one workgroup per set: its candidates (packed tile by tile) counted
-//      per sort bucket in LDS, the bucket starts (region 0 from 0, region 1
-//      after it), then every candidate's angle key and position placed in
-//      its bucket of gk (one 8-byte store each; order within a bucket
-//      arbitrary: the walk sorts each tile); the bucket ends, the region
-//      sizes and their largest bucket go to global memory for the walk
-__global__ __launch_bounds__(kBB) void k_wgroup(WideArgs A) {
-    __shared__ uint32_t s_cnt[2 * kBuckets];
-    __shared__ uint32_t s_w[kBW];
     const int32_t s = A.order[blockIdx.x];
     const WSetIn in = A.in[s];
-    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
     if (in.n == 0) return;
+    if (kBits > kSmallBits ? in.bf <= (uint32_t)kSmallBits : in.bf > (uint32_t)kSmallBits) return;
     WSet& W = A.ws[s];
     if (W.flags != 0u || W.m1 == 0u) return;
-    const uint32_t B = 1u << in.bb, sh = 32u - in.bb;
+    const WCls C(W.P);
+    const uint32_t lslot = W.lslot;
     const size_t o = (size_t)in.o;
-    for (uint32_t j = (uint32_t)tid; j < 2u * B; j += kBB) s_cnt[j] = 0u;
+    const double2* sv_xy = A.sv_xy + o;
+    const uint32_t* sv_key = A.sv_key + o;
+    const uint32_t* sv_idx = A.sv_idx + o;
+    uint32_t* kap = A.ka + o;
+    uint8_t* reg = reinterpret_cast<uint8_t*>(A.vb) + o;
+    const uint32_t bf = in.bf, shf = 32u - bf, B = 1u << bf;
+    for (uint32_t j = (uint32_t)tid; j < 2u * B; j += kMB) s_tab[j] = 0u;
+    if (tid == 0) s_nc = 0u;
     __syncthreads();
-    constexpr int kU = 4;  // loads in flight per thread
-    for (uint32_t u = in.t0; u < in.t0 + in.nt; ++u) {
-        const uint32_t ulo = (u - in.t0) * kWT, uend = ulo + A.tile_ccnt[u];
-        for (uint32_t b0 = ulo; b0 < uend; b0 += kBB * kU) {
-            uint32_t key[kU], sr[kU];
+
+    // the survivors of all tiles numbered 0..m1-1 in tile order (sets of
+    // more than kPreTiles tiles go tile by tile instead)
+    const bool flat = in.nt <= kPreTiles;
+    if (flat) {
+        constexpr int kPT = (int)(kPreTiles + kMB - 1) / kMB;
+        uint32_t c[kPT], tsum = 0;
 #pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
+        for (int k = 0; k < kPT; ++k) {
+            const uint32_t j = (uint32_t)tid * kPT + (uint32_t)k;
+            c[k] = j < in.nt ? A.tile_cnt[in.t0 + j] : 0u;
+            tsum += c[k];
+        }
+        uint32_t tot;
+        uint32_t run = wblock_scan<false, kMB>(tsum, s_w, tot);
+#pragma unroll
+        for (int k = 0; k < kPT; ++k) {
+            const uint32_t j = (uint32_t)tid * kPT + (uint32_t)k;
+            if (j < in.nt) s_pre[j] = run;
+            run += c[k];
+        }
+        if (tid == 0) s_pre[in.nt] = tot;
+        __syncthreads();
+    }
+    const uint32_t nt = in.nt;
+    // survivor f of the flat numbering -> its position
+    auto spos = [&](uint32_t f) -> uint32_t {
+        uint32_t a = 0, z = nt - 1;  // last tile whose first survivor is at or before f
+        while (a < z) {
+            const uint32_t mid = (a + z + 1) >> 1;
+            if (s_pre[mid] <= f) a = mid;
+            else z = mid - 1;
+        }
+        return a * kWT + (f - s_pre[a]);
+    };
+    const uint32_t ntile_loops = flat ? 1u : nt;
+
+    // bucket maxima, every thread taking kSI survivors at a time
+    constexpr int kSI = 4;
+    for (uint32_t tl = 0; tl < ntile_loops; ++tl) {
+        const uint32_t fend = flat ? s_pre[nt] : A.tile_cnt[in.t0 + tl];
+        for (uint32_t b0 = 0; b0 < fend; b0 += (uint32_t)kMB * kSI) {
+            double2 p[kSI];
+            uint32_t key[kSI], at[kSI];
+#pragma unroll
+            for (int k = 0; k < kSI; ++k) {
+                const uint32_t f = b0 + (uint32_t)(k * kMB + tid);
+                p[k] = make_double2(0.0, 0.0);
                 key[k] = 0;
-                sr[k] = 0;
-                if (i < uend) {
-                    key[k] = A.cd_key[o + i];
-                    sr[k] = A.flag[o + i];
+                at[k] = 0;
+                if (f < fend) {
+                    at[k] = flat ? spos(f) : tl * kWT + f;
+                    p[k] = sv_xy[at[k]];
+                    key[k] = sv_key[at[k]];
                 }
             }
 #pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
-                if (i < uend) atomicAdd(&s_cnt[(sr[k] << in.bb) + (key[k] >> sh)], 1u);
+            for (int k = 0; k < kSI; ++k) {
+                const uint32_t f = b0 + (uint32_t)(k * kMB + tid);
+                if (f < fend) {
+                    const Cls cl = C.near(p[k].x, p[k].y, key[k]);
+                    if (cl.region < 2) atomicMax(&s_tab[((uint32_t)cl.region << bf) + (key[k] >> shf)], cl.kappa);
+                    kap[at[k]] = cl.kappa;
+                    reg[at[k]] = (uint8_t)cl.region;
+                }
             }
         }
     }
     __syncthreads();
-    // exclusive prefix sums, region by region; thread tid takes buckets
-    // [tid * per, tid * per + per) of the region
-    const uint32_t per = B > (uint32_t)kBB ? B / kBB : 1u;
-    constexpr int kPer = kBuckets / kBB;
-    uint32_t base = 0;
-    for (int region = 0; region < 2; ++region) {
-        uint32_t* T = s_cnt + ((uint32_t)region << in.bb);
-        uint32_t v[kPer];
-        uint32_t tsum = 0, tmax = 0;
+
+    // prefix maxima in walking order, in place
+    {
+        const uint32_t per = B > (uint32_t)kMB ? B / kMB : 1u;
+        constexpr int kPer = (int)kFiltMax / kMB;
+        for (int region = 0; region < 2; ++region) {
+            uint32_t* T = s_tab + ((uint32_t)region << bf);
+            uint32_t v[kPer];
+            uint32_t tmax = 0;
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t w = (uint32_t)tid * per + (uint32_t)k;
-            v[k] = 0;
-            if ((uint32_t)k < per && w < B) v[k] = T[w];
-            tsum += v[k];
-            tmax = max(tmax, v[k]);
-        }
-        uint32_t inc = tsum, mx = tmax;
+            for (int k = 0; k < kPer; ++k) {
+                const uint32_t w = (uint32_t)tid * per + (uint32_t)k;
+                v[k] = 0;
+                if ((uint32_t)k < per && w < B) {
+                    v[k] = T[region == 0 ? w : B - 1 - w];
+                    tmax = max(tmax, v[k]);
+                }
+            }
+            uint32_t tot;
+            uint32_t run = wblock_scan<true, kMB>(tmax, s_w, tot);
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t q = __shfl_up(inc, d);
-            if (lane >= d) inc += q;
-            mx = max(mx, __shfl_xor(mx, d));
-        }
-        if (lane == 63) s_w[wave] = inc;
-        __syncthreads();
-        uint32_t pre = 0, tot = 0;
-        for (int w = 0; w < kBW; ++w) {
-            const uint32_t x = s_w[w];
-            if (w < wave) pre += x;
-            tot += x;
-        }
-        __syncthreads();
-        if (lane == 0) s_w[wave] = mx;
-        __syncthreads();
-        uint32_t big = 0;
-        for (int w = 0; w < kBW; ++w) big = max(big, s_w[w]);
-        uint32_t run = base + pre + inc - tsum;
-        uint32_t* ends = A.bcnt + in.toff + ((uint32_t)region << in.bb);
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t w = (uint32_t)tid * per + (uint32_t)k;
-            if ((uint32_t)k < per && w < B) {
-                T[w] = run;
-                run += v[k];
-                ends[w] = run;
+            for (int k = 0; k < kPer; ++k) {
+                const uint32_t w = (uint32_t)tid * per + (uint32_t)k;
+                if ((uint32_t)k < per && w < B) {
+                    T[region == 0 ? w : B - 1 - w] = run;
+                    run = max(run, v[k]);
+                }
             }
         }
-        if (tid == 0) {
-            W.c[region] = tot;
-            W.big[region] = big;
-        }
-        base += tot;
-        __syncthreads();
     }
-    for (uint32_t u = in.t0; u < in.t0 + in.nt; ++u) {
-        const uint32_t ulo = (u - in.t0) * kWT, uend = ulo + A.tile_ccnt[u];
-        for (uint32_t b0 = ulo; b0 < uend; b0 += kBB * kU) {
-            uint32_t key[kU], sr[kU];
+    __syncthreads();
+
+    // candidates, likewise
+    for (uint32_t tl = 0; tl < ntile_loops; ++tl) {
+        const uint32_t fend = flat ? s_pre[nt] : A.tile_cnt[in.t0 + tl];
+        for (uint32_t b0 = 0; b0 < fend; b0 += (uint32_t)kMB * kSI) {
+            uint32_t key[kSI], kp[kSI], rg[kSI], at[kSI];
 #pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
-                key[k] = sr[k] = 0;
-                if (i < uend) {
-                    key[k] = A.cd_key[o + i];
-                    sr[k] = A.flag[o + i];
+            for (int k = 0; k < kSI; ++k) {
+                const uint32_t f = b0 + (uint32_t)(k * kMB + tid);
+                key[k] = kp[k] = at[k] = 0;
+                rg[k] = 3u;
+                if (f < fend) {
+                    at[k] = flat ? spos(f) : tl * kWT + f;
+                    key[k] = sv_key[at[k]];
+                    kp[k] = kap[at[k]];
+                    rg[k] = reg[at[k]];
                 }
             }
 #pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const uint32_t i = b0 + (uint32_t)(k * kBB + tid);
-                if (i < uend) {
-                    const uint32_t pos = atomicAdd(&s_cnt[(sr[k] << in.bb) + (key[k] >> sh)], 1u);
-                    A.gk[o + pos] = make_uint2(key[k], i);
+            for (int k = 0; k < kSI; ++k) {
+                const uint32_t i = at[k];
+                const bool keep =
+                    rg[k] == 2u ||
+                    (rg[k] < 2u && (uint64_t)kp[k] + kTurnSlack >= s_tab[(rg[k] << bf) + (key[k] >> shf)]);
+                double2 p = make_double2(0.0, 0.0);
+                uint32_t idx = 0, sreg = 0;
+                if (keep) {
+                    p = sv_xy[i];
+                    idx = sv_idx[i];
+                    if (key[k] != C.kl) sreg = key[k] < C.kl ? 0u : 1u;
+                    else if (i == lslot) sreg = 1u;
+                    else sreg = angle_less(p.x, p.y, idx, C.lx, C.ly, (uint32_t)C.l_idx, C.x0, C.y0) ? 0u : 1u;
                 }
+                const uint32_t pos = wave_append(keep, &s_nc);
+                if (keep) {
+                    A.cd_xy[o + pos] = p;
+                    A.cd_idx[o + pos] = idx;
+                    A.cd_key[o + pos] = key[k];
+                    A.flag[o + pos] = (uint8_t)sreg;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t nc = s_nc;
+
+    // grouping by sort bucket (the table now counts, then places)
+    const uint32_t bs = in.bs, shs = 32u - bs, BS = 1u << bs;
+    for (uint32_t j = (uint32_t)tid; j < 2u * BS; j += kMB) s_tab[j] = 0u;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nc; b0 += kMB * kWI) {
+        uint32_t key[kWI], sr[kWI];
+#pragma unroll
+        for (int k = 0; k < kWI; ++k) {
+            const uint32_t i = b0 + (uint32_t)(k * kMB + tid);
+            key[k] = sr[k] = 0;
+            if (i < nc) {
+                key[k] = A.cd_key[o + i];
+                sr[k] = A.flag[o + i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kWI; ++k) {
+            const uint32_t i = b0 + (uint32_t)(k * kMB + tid);
+            if (i < nc) atomicAdd(&s_tab[(sr[k] << bs) + (key[k] >> shs)], 1u);
+        }
+    }
+    __syncthreads();
+    {
+        const uint32_t per = BS > (uint32_t)kMB ? BS / kMB : 1u;
+        constexpr int kPer = (int)kSortMax / kMB;
+        uint32_t base = 0;
+        for (int region = 0; region < 2; ++region) {
+            uint32_t* T = s_tab + ((uint32_t)region << bs);
+            uint32_t v[kPer];
+            uint32_t tsum = 0, tmax = 0;
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const uint32_t w = (uint32_t)tid * per + (uint32_t)k;
+                v[k] = 0;
+                if ((uint32_t)k < per && w < BS) v[k] = T[w];
+                tsum += v[k];
+                tmax = max(tmax, v[k]);
+            }
+            uint32_t tot, big;
+            uint32_t run = base + wblock_scan<false, kMB>(tsum, s_w, tot);
+            (void)wblock_scan<true, kMB>(tmax, s_w, big);
+            uint32_t* ends = A.bcnt + in.soff + ((uint32_t)region << bs);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const uint32_t w = (uint32_t)tid * per + (uint32_t)k;
+                if ((uint32_t)k < per && w < BS) {
+                    T[w] = run;
+                    run += v[k];
+                    ends[w] = run;
+                }
+            }
+            if (tid == 0) {
+                W.c[region] = tot;
+                W.big[region] = big;
+            }
+            base += tot;
+        }
+    }
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nc; b0 += kMB * kWI) {
+        uint32_t key[kWI], sr[kWI];
+#pragma unroll
+        for (int k = 0; k < kWI; ++k) {
+            const uint32_t i = b0 + (uint32_t)(k * kMB + tid);
+            key[k] = sr[k] = 0;
+            if (i < nc) {
+                key[k] = A.cd_key[o + i];
+                sr[k] = A.flag[o + i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kWI; ++k) {
+            const uint32_t i = b0 + (uint32_t)(k * kMB + tid);
+            if (i < nc) {
+                const uint32_t pos = atomicAdd(&s_tab[(sr[k] << bs) + (key[k] >> shs)], 1u);
+                A.gk[o + pos] = make_uint2(key[k], i);
             }
         }
     }
@@ -1838,8 +1939,8 @@ __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int sgn = r == 0 ? 1 : -1;
 
     WalkTile& T = L.u.t;
-    const uint32_t B = 1u << in.bb;
-    const uint32_t* ends = A.bcnt + in.toff + ((uint32_t)r << in.bb);
+    const uint32_t B = 1u << in.bs;
+    const uint32_t* ends = A.bcnt + in.soff + ((uint32_t)r << in.bs);
     for (uint32_t b = (uint32_t)tid; b < B; b += kBB) T.bend[b] = ends[b];
     __syncthreads();
     auto bstart = [&](uint32_t b) -> uint32_t { return b == 0 ? rs : T.bend[b - 1]; };
@@ -2225,10 +2326,8 @@ hipError_t launch_wide(const WideArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_wparams, S1, dim3(64), 0, s, a);
     if (a.NT > 0) hipLaunchKernelGGL(k_wfilter, NT, dim3(kWB), 0, s, a);
     hipLaunchKernelGGL(k_wfar, S1, dim3(64), 0, s, a);
-    if (a.NT > 0) hipLaunchKernelGGL(k_wbmax, NT, dim3(kWB), 0, s, a);
-    hipLaunchKernelGGL(k_wprefix, S1, dim3(kWB), 0, s, a);
-    if (a.NT > 0) hipLaunchKernelGGL(k_wcand, NT, dim3(kWB), 0, s, a);
-    hipLaunchKernelGGL(k_wgroup, S1, dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL((k_wset<kWideFilterBits, 1024>), S1, dim3(1024), 0, s, a);
+    hipLaunchKernelGGL((k_wset<kSmallBits, 256>), S1, dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_wwalk_small, dim3((unsigned)((2 * a.S + kBW - 1) / kBW)), dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(k_wwalk, S2, dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(k_wwalk_radix, S2, dim3(kBB), 0, s, a);
