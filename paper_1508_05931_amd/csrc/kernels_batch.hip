@@ -2285,22 +2285,21 @@ __global__ __launch_bounds__(kBB) void k_wwalk_radix(WideArgs A) {
 }
 
 // ---- Step 8 of a set over its kept points (right region, then the left)
+constexpr uint32_t kStep8Wave = 63;  // kept lists up to this size: one wave per set (P_0 makes 64 entries)
+
+// Kept points of a set after the walk (0 when nothing survived round 1).
+__device__ inline uint32_t wide_kept(const WSet& W) { return W.m1 > 0 ? W.k[0] + W.k[1] : 0u; }
+
 __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k_wstep8(WideArgs A) {
     __shared__ BatchLds S;
     const int32_t s = A.order[blockIdx.x];
     const WSetIn in = A.in[s];
     const uint32_t tid = threadIdx.x;
     const WSet& W = A.ws[s];
-    if (in.n == 0 || W.flags != 0u) {
-        if (tid == 0) {
-            A.h_count[s] = 0;
-            A.h_start[s] = 0;
-            A.h_flags[s] = in.n == 0 ? 0u : W.flags;
-        }
-        return;
-    }
+    // empty and flagged sets, and short kept lists: k_wstep8_small
+    if (in.n == 0 || W.flags != 0u || wide_kept(W) <= kStep8Wave) return;
     const size_t o = (size_t)in.o;
-    const uint32_t k0 = W.m1 > 0 ? W.k[0] : 0u, k1 = W.m1 > 0 ? W.k[1] : 0u;
+    const uint32_t k0 = W.k[0], k1 = W.k[1];
     const uint32_t lo0 = W.klo[0], lo1 = W.klo[1];
     const uint32_t m = k0 + k1;
     uint32_t* first = A.ka + o;
@@ -2314,6 +2313,101 @@ __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k
     H.flags = A.h_flags;
     batch_step8(S, H, s, A.sv_xy + o, A.sv_idx + o, first, m, A.ka + o, A.kb + o, A.va + o, W.P.x0, W.P.y0,
                 W.P.p0_idx);
+}
+
+// ---- Step 8 of a set whose kept list has at most kStep8Wave points, one
+//      wave per set (eight per workgroup): the stack scan of P_0 and the kept
+//      points run by the whole wave in step (every lane takes the same
+//      decisions, points fetched from the lane that holds them), then the
+//      rotation to the smallest vertex and the output.  Also writes the
+//      result of empty and flagged sets.
+__global__ __launch_bounds__(kBB) void k_wstep8_small(WideArgs A) {
+    __shared__ uint8_t s_st[kBW][kStep8Wave];
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    const uint32_t g = blockIdx.x * (uint32_t)kBW + (uint32_t)wave;
+    if (g >= (uint32_t)A.S) return;
+    const int32_t s = A.order[g];
+    const WSetIn in = A.in[s];
+    const WSet& W = A.ws[s];
+    if (in.n == 0 || W.flags != 0u) {
+        if (lane == 0) {
+            A.h_count[s] = 0;
+            A.h_start[s] = 0;
+            A.h_flags[s] = in.n == 0 ? 0u : W.flags;
+        }
+        return;
+    }
+    const uint32_t m = wide_kept(W);
+    if (m > kStep8Wave) return;
+    const size_t o = (size_t)in.o;
+    const double x0 = W.P.x0, y0 = W.P.y0;
+    double px = 0.0, py = 0.0;
+    uint32_t pid = 0;
+    if ((uint32_t)lane < m) {
+        const uint32_t q = (uint32_t)lane < W.k[0] ? W.klo[0] + (uint32_t)lane : W.klo[1] + ((uint32_t)lane - W.k[0]);
+        const double2 v = A.sv_xy[o + q];
+        px = v.x;
+        py = v.y;
+        pid = A.sv_idx[o + q];
+    }
+    uint8_t* st = s_st[wave];
+    uint32_t top = 0;                // stack entries above P_0
+    double tx = x0, ty = y0, sx = x0, sy = y0;
+    for (uint32_t i = 0; i < m; ++i) {
+        const double qx = __shfl(px, (int)i), qy = __shfl(py, (int)i);
+        if (qx == tx && qy == ty) continue;
+        while (top >= 1) {
+            if (orient(sx, sy, tx, ty, qx, qy) > 0) break;
+            --top;
+            tx = sx;
+            ty = sy;
+            if (top >= 2) {
+                const int e = st[top - 2];
+                sx = __shfl(px, e);
+                sy = __shfl(py, e);
+            } else {
+                sx = x0;
+                sy = y0;
+            }
+        }
+        if (lane == 0) st[top] = (uint8_t)i;
+        __builtin_amdgcn_wave_barrier();
+        ++top;
+        sx = tx;
+        sy = ty;
+        tx = qx;
+        ty = qy;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t h = top + 1;  // with P_0 as entry 0
+    // entry k's point: P_0 for k = 0, else stack entry k - 1
+    const int ek = lane >= 1 && (uint32_t)lane < h ? (int)st[lane - 1] : 0;
+    const double ex = __shfl(px, ek), ey = __shfl(py, ek);
+    const uint32_t eid = __shfl(pid, ek);
+    double bx = lane == 0 ? x0 : ex, by = lane == 0 ? y0 : ey;
+    uint32_t bk = (uint32_t)lane < h ? (uint32_t)lane : 0xFFFFFFFFu;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const double ox = __shfl_xor(bx, d), oy = __shfl_xor(by, d);
+        const uint32_t ok = __shfl_xor(bk, d);
+        const bool take = ok != 0xFFFFFFFFu && (bk == 0xFFFFFFFFu || ox < bx || (ox == bx && (oy < by || (oy == by && ok < bk))));
+        bx = take ? ox : bx;
+        by = take ? oy : by;
+        bk = take ? ok : bk;
+    }
+    uint32_t at = 0;
+    if (lane == 0) at = atomicAdd(A.hull_cursor, h);
+    at = __shfl(at, 0);
+    const int32_t id_k = lane == 0 ? W.P.p0_idx : (int32_t)eid;
+    if ((uint32_t)lane < h) {
+        const uint32_t r = ((uint32_t)lane + h - bk) % h;  // output position of entry `lane`
+        A.hull[at + r] = id_k;
+    }
+    if (lane == 0) {
+        A.h_count[s] = (int32_t)h;
+        A.h_start[s] = (int32_t)at;
+        A.h_flags[s] = 0;
+    }
 }
 
 }  // namespace
@@ -2331,6 +2425,7 @@ hipError_t launch_wide(const WideArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_wwalk_small, dim3((unsigned)((2 * a.S + kBW - 1) / kBW)), dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(k_wwalk, S2, dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(k_wwalk_radix, S2, dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(k_wstep8_small, dim3((unsigned)((a.S + kBW - 1) / kBW)), dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(k_wstep8, S1, dim3(kBB), 0, s, a);
     return hipGetLastError();
 }
