@@ -145,6 +145,10 @@ struct hull2d_ctx {
     // the batched form's device work captured in a graph, and what it was
     // captured for (replayed while all of it is unchanged)
     hipStream_t cap_stream = nullptr;
+    // tiled batch engine: the largest sets run on a second stream beside the
+    // others (default priority), joined by events
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t bgraph = nullptr;
     bool bgraph_off = false;  // capture failed once: plain stream work
     int32_t bg_S = -1;
@@ -154,7 +158,8 @@ struct hull2d_ctx {
     const void* bg_hb = nullptr;  // pinned staging
     int bg_grid = 0;
     int bg_engine = -1;
-    int64_t bg_nt = -1;
+    int64_t bg_nt = -1, bg_nt_big = -1;
+    int32_t bg_big = -1;
     const void* bg_wm = nullptr;  // tiled engine's workspace
 
     // learned filter: weights (float32 master + bfloat16 inference copies),
@@ -1282,6 +1287,9 @@ void hull2d_destroy(hull2d_ctx* c) {
     if (c->ctr) (void)hipFree(c->ctr);
     if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->h_ds) (void)hipHostFree(c->h_ds);
     if (c->h_chain) (void)hipHostFree(c->h_chain);
     if (c->h_xy) (void)hipHostFree(c->h_xy);
@@ -1388,9 +1396,20 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
     // buckets per region for the bucket maxima, about a quarter of the set's
     // size, 16 to 16,384; 2^bs sort buckets, at most 4,096)
     const int engine = c->opt.batch_engine;
-    int64_t NT = 0, SE = 0;
+    int64_t NT = 0, SE = 0, NT_big = 0;
+    int32_t S_big = 0;  // the largest sets, run beside the others on a second stream
     if (engine == 0) {
-        for (int32_t i = 0; i < S; ++i) {
+        if (c->opt.batch_order == 2) {
+            // the tiled engine takes its sets largest first whatever the
+            // persistent engine's order option says
+            for (int32_t i = 0; i < S; ++i) c->hb_order[i] = i;
+            std::stable_sort(c->hb_order, c->hb_order + S,
+                             [&](int32_t a, int32_t b) { return size_of(a) > size_of(b); });
+        }
+        while (S_big < std::min<int32_t>(S - 1, kWideBigSets) && size_of(c->hb_order[S_big]) >= kWideBigMin) ++S_big;
+        for (int32_t r = 0; r < S; ++r) {
+            // tiles numbered in this order: the big sets' tiles come first
+            const int32_t i = c->hb_order[r];
             const int64_t n = size_of(i);
             WSetIn& w = c->hb_win[i];
             uint32_t bf = 0;
@@ -1407,8 +1426,17 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
             w.soff = (uint32_t)SE;
             w.pad = 0;
             NT += w.nt;
+            if (r < S_big) NT_big = NT;
             SE += n > 0 ? ((int64_t)2 << w.bs) : 0;
             if (NT > (int64_t)UINT32_MAX || SE > (int64_t)UINT32_MAX) return HULL2D_ERR_OUT_OF_MEMORY;
+        }
+        if (S_big > 0 && !c->side_stream) {
+            if (hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                return HULL2D_ERR_DEVICE;
+            }
         }
         st = ensure_wide(c, S, NT, SE);
         if (st != HULL2D_OK) return st;
@@ -1432,6 +1460,7 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 a.ws = c->w_set;
                 a.order = c->b_order;
                 a.S = S;
+                a.t_base = 0;
                 a.NT = (uint32_t)NT;
                 a.tile_set = c->w_tile_set;
                 a.tile_ext = c->w_tile_ext;
@@ -1456,7 +1485,24 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 a.h_count = d_count;
                 a.h_start = d_start;
                 a.h_flags = d_flags;
-                e = launch_wide(a, q);
+                if (S_big == 0) {
+                    e = launch_wide(a, q);
+                } else {
+                    // the big sets on the side stream, the others on q
+                    WideArgs big = a, rest = a;
+                    big.S = S_big;
+                    big.NT = (uint32_t)NT_big;
+                    rest.order = c->b_order + S_big;
+                    rest.S = S - S_big;
+                    rest.t_base = (uint32_t)NT_big;
+                    rest.NT = (uint32_t)(NT - NT_big);
+                    e = hipEventRecord(c->ev_fork, q);
+                    if (e == hipSuccess) e = hipStreamWaitEvent(c->side_stream, c->ev_fork, 0);
+                    if (e == hipSuccess) e = launch_wide(big, c->side_stream);
+                    if (e == hipSuccess) e = launch_wide(rest, q);
+                    if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side_stream);
+                    if (e == hipSuccess) e = hipStreamWaitEvent(q, c->ev_join, 0);
+                }
             }
             if (e == hipSuccess)
                 e = hipMemcpyAsync(c->hb_meta, c->b_meta, (size_t)(3 * S + 1) * 4, hipMemcpyDeviceToHost, q);
@@ -1481,7 +1527,7 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         const bool same = c->bgraph && c->bg_S == S && c->bg_N == N && c->bg_xy == d_xy &&
                           c->bg_ws == (const void*)c->b_sv_xy && c->bg_hb == (const void*)c->hb_offs &&
                           c->bg_grid == c->batch_grid && c->bg_engine == engine && c->bg_nt == NT &&
-                          c->bg_wm == (const void*)c->wmem;
+                          c->bg_wm == (const void*)c->wmem && c->bg_big == S_big && c->bg_nt_big == NT_big;
         if (!same) {
             if (c->bgraph) {
                 (void)hipGraphExecDestroy(c->bgraph);
@@ -1516,6 +1562,8 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 c->bg_grid = c->batch_grid;
                 c->bg_engine = engine;
                 c->bg_nt = NT;
+                c->bg_big = S_big;
+                c->bg_nt_big = NT_big;
                 c->bg_wm = (const void*)c->wmem;
             }
         }

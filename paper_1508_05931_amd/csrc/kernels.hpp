@@ -243,6 +243,12 @@ constexpr uint32_t kBatchFallback = 4u;
 // grid per pass; what spans a whole set (reductions, bucket prefixes, the
 // sort and walk of each region, Step 8) takes one workgroup per set.
 constexpr uint32_t kWideTile = 4096;
+// The largest sets (at most kWideBigSets of at least kWideBigMin points)
+// run the tiled engine's kernels on a second stream beside the others: their
+// per-set kernels take the longest and would otherwise leave most compute
+// units idle at the end of each per-set launch.
+constexpr int32_t kWideBigSets = 128;
+constexpr int64_t kWideBigMin = 65536;
 
 // Per set, written by the host: the set's first point, its size, its tiles
 // (t0 .. t0 + nt), its bucket counts (2^bf buckets per region for the
@@ -278,9 +284,9 @@ struct WideArgs {
     const double2* xy;
     const WSetIn* in;      // [S]
     WSet* ws;              // [S]
-    const int32_t* order;  // [S] sets largest first
-    int32_t S;
-    uint32_t NT;           // tiles
+    const int32_t* order;  // [S] the sets of this launch, largest first
+    int32_t S;             // sets in this launch
+    uint32_t t_base, NT;   // this launch's tiles: t_base .. t_base + NT (global numbering)
     int32_t* tile_set;     // [NT]
     Cand* tile_ext;        // [NT][4]
     uint32_t* tile_flags;  // [NT]

@@ -1185,6 +1185,8 @@ struct alignas(16) WalkLds {
     uint32_t big[kCT / (kSortOne + 1) + 1];
 };
 
+// Tile t (global numbering) -> its set, the set's layout and the tile's
+// point range within the set.
 __device__ inline uint32_t wide_tile_set(const WideArgs& A, uint32_t t, WSetIn& in, uint32_t& lo, uint32_t& hi) {
     const int32_t s = A.tile_set[t];
     in = A.in[s];
@@ -1195,7 +1197,7 @@ __device__ inline uint32_t wide_tile_set(const WideArgs& A, uint32_t t, WSetIn& 
 
 // ---- prep: tile owners and cleared counters (one workgroup per set)
 __global__ __launch_bounds__(kWB) void k_wprep(WideArgs A) {
-    const int32_t s = (int32_t)blockIdx.x;
+    const int32_t s = A.order[blockIdx.x];
     const WSetIn in = A.in[s];
     const uint32_t tid = threadIdx.x;
     for (uint32_t j = tid; j < in.nt; j += kWB) A.tile_set[in.t0 + j] = s;
@@ -1218,7 +1220,7 @@ __global__ __launch_bounds__(kWB) void k_wext(WideArgs A) {
     __shared__ Cand s_ext[kWW][4];
     __shared__ uint32_t s_bad;
     const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = A.t_base + blockIdx.x;
     WSetIn in;
     uint32_t lo, hi;
     wide_tile_set(A, t, in, lo, hi);
@@ -1271,7 +1273,7 @@ __global__ __launch_bounds__(kWB) void k_wext(WideArgs A) {
 
 // ---- Step 1 of a set: its tiles' extremes, the quadrilateral, P_0
 __global__ __launch_bounds__(64) void k_wparams(WideArgs A) {
-    const int32_t s = (int32_t)blockIdx.x;
+    const int32_t s = A.order[blockIdx.x];
     const WSetIn in = A.in[s];
     const uint32_t lane = threadIdx.x;
     if (in.n == 0) return;
@@ -1301,7 +1303,7 @@ __global__ __launch_bounds__(kWB) void k_wfilter(WideArgs A) {
     __shared__ double s_d2[kWW];
     __shared__ uint32_t s_i[kWW], s_sl[kWW];
     const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = A.t_base + blockIdx.x;
     WSetIn in;
     uint32_t lo, hi;
     const uint32_t s = wide_tile_set(A, t, in, lo, hi);
@@ -1389,7 +1391,7 @@ __global__ __launch_bounds__(kWB) void k_wfilter(WideArgs A) {
 
 // ---- Step 5 of a set: P_l, the farthest survivor (smallest index on ties)
 __global__ __launch_bounds__(64) void k_wfar(WideArgs A) {
-    const int32_t s = (int32_t)blockIdx.x;
+    const int32_t s = A.order[blockIdx.x];
     const WSetIn in = A.in[s];
     const uint32_t lane = threadIdx.x;
     if (in.n == 0) return;
@@ -1644,28 +1646,38 @@ __global__ __launch_bounds__(kMB) void k_wset(WideArgs A) {
                     rg[k] = reg[at[k]];
                 }
             }
+            // keep flags first, then one LDS reservation per wave for all
+            // kSI rounds, then the loads and stores of the candidates
+            bool keep[kSI];
+            uint64_t mk[kSI];
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int k = 0; k < kSI; ++k) {
+                keep[k] = rg[k] == 2u ||
+                          (rg[k] < 2u && (uint64_t)kp[k] + kTurnSlack >= s_tab[(rg[k] << bf) + (key[k] >> shf)]);
+                mk[k] = __ballot(keep[k]);
+                cnt += (uint32_t)__popcll(mk[k]);
+            }
+            uint32_t base = 0;
+            if (__lane_id() == 0 && cnt > 0) base = atomicAdd(&s_nc, cnt);
+            base = __shfl(base, 0);
 #pragma unroll
             for (int k = 0; k < kSI; ++k) {
                 const uint32_t i = at[k];
-                const bool keep =
-                    rg[k] == 2u ||
-                    (rg[k] < 2u && (uint64_t)kp[k] + kTurnSlack >= s_tab[(rg[k] << bf) + (key[k] >> shf)]);
-                double2 p = make_double2(0.0, 0.0);
-                uint32_t idx = 0, sreg = 0;
-                if (keep) {
-                    p = sv_xy[i];
-                    idx = sv_idx[i];
+                if (keep[k]) {
+                    const double2 p = sv_xy[i];
+                    const uint32_t idx = sv_idx[i];
+                    uint32_t sreg;
                     if (key[k] != C.kl) sreg = key[k] < C.kl ? 0u : 1u;
                     else if (i == lslot) sreg = 1u;
                     else sreg = angle_less(p.x, p.y, idx, C.lx, C.ly, (uint32_t)C.l_idx, C.x0, C.y0) ? 0u : 1u;
-                }
-                const uint32_t pos = wave_append(keep, &s_nc);
-                if (keep) {
+                    const uint32_t pos = base + (uint32_t)__popcll(mk[k] & lanemask_lt());
                     A.cd_xy[o + pos] = p;
                     A.cd_idx[o + pos] = idx;
                     A.cd_key[o + pos] = key[k];
                     A.flag[o + pos] = (uint8_t)sreg;
                 }
+                base += (uint32_t)__popcll(mk[k]);
             }
         }
     }
