@@ -265,6 +265,27 @@ def test_batch_graph_replays_match_eager(torch_dev, hx):
     ce.close()
 
 
+def test_batch_graph_with_large_sets(torch_dev, hx):
+    """Sets of 65,536 points and more run on a second stream beside the
+    others; the captured graph (fork and join) replayed several times, with
+    eager work between the replays, gives the eager result every time."""
+    sizes = [70_000, 130_000, 66_000, 90_000] + [int(n) for n in synth.batch_sizes(60, 64.0, 20_000.0, 960)]
+    sets = [synth.batch_set(n, k, 961)[0] for k, n in enumerate(sizes)]
+    pts, offs = _concat(sets)
+    d = torch_dev.from_numpy(pts).cuda()
+    ce = hx.Hull2D(batch_graph=False)
+    want_h, want_o = ce.batch(d, offs)
+    _check_all(want_h, want_o, sets)
+    cg = hx.Hull2D(batch_graph=True)
+    say("batch graph with large sets")
+    for r in range(3):
+        h, o = cg.batch(d, offs)
+        assert o.tolist() == want_o.tolist() and h.tolist() == want_h.tolist(), f"replay {r}"
+        torch_dev.cuda.synchronize()
+    cg.close()
+    ce.close()
+
+
 @pytest.mark.parametrize("blocks,order", [(1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (2, 2)])
 def test_batch_schedules_agree(torch_dev, hx, blocks, order):
     """Every schedule the autotuner chooses from gives the same hulls."""
