@@ -171,8 +171,13 @@ __global__ __launch_bounds__(kPfBlock) void k_prefilter(
                 k[u] = keys[s];
             }
         }
-        // classify every item first, then fetch their prefix maxima together
-        // (one memory latency per tile, not one per item)
+        // classify every item first (with the float32 direction key, within
+        // kTurnSlack / 8 of the exact one), then fetch their prefix maxima
+        // together (one memory latency per tile, not one per item).  A point
+        // is kept unless its key plus kTurnSlack stays below the sampled
+        // prefix maximum: then its exact key is below it, and below the
+        // exact prefix maximum, so every exact candidate is kept.  Kept
+        // points get their exact key.
         Cls c[kPfItems];
         uint32_t pre[kPfItems];
 #pragma unroll
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(kPfBlock) void k_prefilter(
             c[u].region = 2;
             c[u].kappa = 0;
             c[u].bucket = 0;
-            if (s < end) c[u] = classify(p[u].x, p[u].y, k[u], P);
+            if (s < end) c[u] = classify_near(p[u].x, p[u].y, k[u], P.x0, P.y0, P.lx, P.ly, P.kl, P.turn_u, P.turn_v);
         }
 #pragma unroll
         for (int u = 0; u < kPfItems; ++u)
@@ -190,9 +195,10 @@ __global__ __launch_bounds__(kPfBlock) void k_prefilter(
         for (int u = 0; u < kPfItems; ++u) {
             const uint32_t s = base + u * kPfBlock + threadIdx.x;
             if (s < end) {
-                const bool keep = (c[u].region == 2) || (c[u].kappa >= pre[u]);
+                const bool keep = (c[u].region == 2) || ((uint64_t)c[u].kappa + kTurnSlack >= pre[u]);
                 nr += c[u].region == 0;
                 if (keep) {
+                    if (c[u].region < 2) c[u] = classify(p[u].x, p[u].y, k[u], P);
                     const uint32_t at = atomicAdd(&s_n, 1u);
                     s_buf[at] = s;
                     s_kap[at] = c[u].region == 2 ? 0xFFFFFFFFu : c[u].kappa;
