@@ -145,6 +145,21 @@ typedef struct {
      * persistent launch, each workgroup computing whole sets start to end
      * (batch_blocks_per_cu and batch_order apply to it only).  Same output. */
     int32_t batch_engine;
+    /* Schedule of the tiled engine; 0 keeps each default, other values give
+     * the same output.  batch_tile: points per tile of the passes over
+     * points (a power of two, 1,024 to 65,536; default 4,096).
+     * batch_filter_bits: at most 2^batch_filter_bits buckets per region for
+     * the bucket maxima of Steps 6-7 (4 to 14; default 14; a set gets about
+     * one bucket per four points up to that).  batch_sort_bits: at most
+     * 2^batch_sort_bits angle buckets per region for the grouping before the
+     * sort (4 to 12; default 12).  batch_side_sets: how many of the largest
+     * sets (those of at least 65,536 points) run on a second stream beside
+     * the others (1 to 4,096; -1 none, one stream; default 128).
+     * paper_1508_05931_amd/autotune.py picks them by timing. */
+    int32_t batch_tile;
+    int32_t batch_filter_bits;
+    int32_t batch_sort_bits;
+    int32_t batch_side_sets;
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */

@@ -57,7 +57,9 @@ class _Options(ctypes.Structure):
                 ("batch_order", ctypes.c_int32), ("batch_graph", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("reserve_noalloc", ctypes.c_int32),
                 ("scan", ctypes.c_int32), ("workspace_limit_mib", ctypes.c_int32),
-                ("batch_engine", ctypes.c_int32)]
+                ("batch_engine", ctypes.c_int32), ("batch_tile", ctypes.c_int32),
+                ("batch_filter_bits", ctypes.c_int32), ("batch_sort_bits", ctypes.c_int32),
+                ("batch_side_sets", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -173,12 +175,17 @@ def _i32p(a: np.ndarray):
 TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "batch.json")
 
 
+# The schedule knobs autotune.py may store (each 0 = the library default).
+TUNED_KEYS = ("batch_blocks_per_cu", "batch_order", "batch_tile", "batch_filter_bits",
+              "batch_sort_bits", "batch_side_sets")
+
+
 def tuned_batch_schedule() -> dict:
     """The batched form's schedule chosen by autotune.py (empty: none)."""
     try:
         with open(TUNING) as f:
             t = json.load(f)
-        return {k: int(t[k]) for k in ("batch_blocks_per_cu", "batch_order") if k in t}
+        return {k: int(t[k]) for k in TUNED_KEYS if k in t}
     except (OSError, ValueError, KeyError, TypeError):
         return {}
 
@@ -193,14 +200,18 @@ class Hull2D:
     batch_graph: capture and replay the batched form's device work in a HIP
     graph.  batch_engine: 0 tiled (passes over points share a large set among
     many workgroups), 1 one persistent workgroup per set.  batch_blocks_per_cu
-    / batch_order: the persistent engine's schedule; None takes the values
-    autotune.py stored in tuning/batch.json, else the library's defaults."""
+    / batch_order: the persistent engine's schedule; batch_tile /
+    batch_filter_bits / batch_sort_bits / batch_side_sets: the tiled engine's
+    (hull2d_options documents each).  None takes the values autotune.py stored
+    in tuning/batch.json, else the library's defaults."""
 
     def __init__(self, device: int | None = None, stream=None, round2_chunk: int = 0,
                  profile: int = 0, full_sort: bool = False, learned: bool = False,
                  weights=None, batch_graph: bool = True, batch_blocks_per_cu: int | None = None,
                  batch_order: int | None = None, reserve_noalloc: bool = False, method: int = 0,
-                 scan: int = 0, workspace_limit_mib: int = 0, batch_engine: int = 0):
+                 scan: int = 0, workspace_limit_mib: int = 0, batch_engine: int = 0,
+                 batch_tile: int | None = None, batch_filter_bits: int | None = None,
+                 batch_sort_bits: int | None = None, batch_side_sets: int | None = None):
         import torch
         lib = load_library()
         if device is None:
@@ -210,15 +221,16 @@ class Hull2D:
         self.device = int(device)
         self.stream = stream
         tuned = tuned_batch_schedule()
-        if batch_blocks_per_cu is None:
-            batch_blocks_per_cu = tuned.get("batch_blocks_per_cu", 0)
-        if batch_order is None:
-            batch_order = tuned.get("batch_order", 0)
+        given = {"batch_blocks_per_cu": batch_blocks_per_cu, "batch_order": batch_order,
+                 "batch_tile": batch_tile, "batch_filter_bits": batch_filter_bits,
+                 "batch_sort_bits": batch_sort_bits, "batch_side_sets": batch_side_sets}
+        sched = {k: int(v) if v is not None else tuned.get(k, 0) for k, v in given.items()}
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
-                       int(bool(full_sort)), int(bool(learned)), int(batch_blocks_per_cu),
-                       int(batch_order), int(bool(batch_graph)), int(method),
+                       int(bool(full_sort)), int(bool(learned)), sched["batch_blocks_per_cu"],
+                       sched["batch_order"], int(bool(batch_graph)), int(method),
                        int(bool(reserve_noalloc)), int(scan), int(workspace_limit_mib),
-                       int(batch_engine))
+                       int(batch_engine), sched["batch_tile"], sched["batch_filter_bits"],
+                       sched["batch_sort_bits"], sched["batch_side_sets"])
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))

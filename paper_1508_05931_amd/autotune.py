@@ -4,17 +4,26 @@
 
 Times hull2d_batch on the batch workload (the 4096 sets of synth.batch:
 sizes log-uniform in [64, 200000], square, disk, Gaussian and thin-annulus
-sets) for every schedule the library offers: workgroups per compute unit
-of the persistent launch (1 or 2) times the order in which workgroups take
-the sets (0 by size class, largest first; 1 by exact size, largest first;
-2 input order), each as a captured graph.  Every schedule must give the
-same hulls as the first; the fastest (median of `reps` timed calls after
-two warm-up calls) goes to tuning/batch.json, which Hull2D reads as its
-default schedule.
+sets), each schedule as a captured graph, for both engines:
+
+* the persistent engine (batch_engine=1): workgroups per compute unit of the
+  persistent launch (1 or 2) times the order in which workgroups take the
+  sets (0 by size class, largest first; 1 by exact size, largest first; 2
+  input order);
+* the tiled engine (batch_engine=0, the default): points per tile of the
+  passes over points, the largest number of filter buckets per region
+  (2^bits) of Steps 6-7, the largest number of angle buckets per region of
+  the grouping before the sort, and how many of the largest sets run on the
+  second stream (-1: one stream).
+
+Every schedule must give the same hulls as the first; the fastest of each
+engine (median of `reps` timed calls after two warm-up calls) goes to
+tuning/batch.json, which Hull2D reads as its default schedule.
 """
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import os
 import sys
@@ -27,7 +36,17 @@ ROOT = os.path.dirname(HERE)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-CANDIDATES = [(b, o) for b in (1, 2) for o in (0, 1, 2)]
+PERSISTENT = [dict(batch_engine=1, batch_blocks_per_cu=b, batch_order=o) for b in (1, 2) for o in (0, 1, 2)]
+TILE_SIZES = (4096, 8192, 16384, 32768)
+FILTER_BITS = (13, 14)
+SORT_BITS = (11, 12)
+SIDE_SETS = (-1, 256, 384, 512)
+TILED = [dict(batch_engine=0, batch_tile=t, batch_filter_bits=f, batch_sort_bits=s, batch_side_sets=g)
+         for t, f, s, g in itertools.product(TILE_SIZES, FILTER_BITS, SORT_BITS, SIDE_SETS)]
+
+
+def _name(kw: dict) -> str:
+    return "_".join(f"{k.replace('batch_', '')}{v}" for k, v in kw.items() if k != "batch_engine")
 
 
 def main(argv=None):
@@ -43,32 +62,40 @@ def main(argv=None):
     pts, offs, _ = synth.batch(args.sets)
     d = torch.from_numpy(pts).cuda()
     ref = None
-    timings = {}
-    for b, o in CANDIDATES:
-        c = hx.Hull2D(batch_blocks_per_cu=b, batch_order=o, batch_graph=True)
-        for _ in range(2):
-            h, oo = c.batch(d, offs)
-        if ref is None:
-            ref = (h.copy(), oo.copy())
-        elif not (np.array_equal(h, ref[0]) and np.array_equal(oo, ref[1])):
-            raise SystemExit(f"schedule blocks={b} order={o} changed the hulls")
-        ts = []
-        for _ in range(args.reps):
-            t0 = time.perf_counter()
-            c.batch(d, offs)
-            ts.append(time.perf_counter() - t0)
-        c.close()
-        timings[f"blocks{b}_order{o}"] = round(float(np.median(ts)) * 1e3, 3)
-        print(f"blocks per CU {b}, order {o}: {timings[f'blocks{b}_order{o}']:.3f} ms", flush=True)
-    best = min(CANDIDATES, key=lambda bo: timings[f"blocks{bo[0]}_order{bo[1]}"])
-    out = {"batch_blocks_per_cu": best[0], "batch_order": best[1],
-           "workload": f"synth.batch({args.sets}): {int(offs[-1])} points",
-           "ms_median_per_call": timings, "reps": args.reps,
-           "device": torch.cuda.get_device_name(0)}
+    timings = {"persistent": {}, "tiled": {}}
+    best = {}
+    for engine, grid in (("persistent", PERSISTENT), ("tiled", TILED)):
+        for kw in grid:
+            # every knob given, so the stored tuning does not leak into the run
+            full = {k: 0 for k in hx.TUNED_KEYS}
+            full.update(kw)
+            c = hx.Hull2D(batch_graph=True, **full)
+            for _ in range(2):
+                h, oo = c.batch(d, offs)
+            if ref is None:
+                ref = (h.copy(), oo.copy())
+            elif not (np.array_equal(h, ref[0]) and np.array_equal(oo, ref[1])):
+                raise SystemExit(f"schedule {kw} changed the hulls")
+            ts = []
+            for _ in range(args.reps):
+                t0 = time.perf_counter()
+                c.batch(d, offs)
+                ts.append(time.perf_counter() - t0)
+            c.close()
+            ms = round(float(np.median(ts)) * 1e3, 3)
+            timings[engine][_name(kw)] = ms
+            print(f"{engine} {_name(kw)}: {ms:.3f} ms", flush=True)
+            if engine not in best or ms < best[engine][0]:
+                best[engine] = (ms, kw)
+    out = {k: v for k, v in best["persistent"][1].items() if k != "batch_engine"}
+    out.update({k: v for k, v in best["tiled"][1].items() if k != "batch_engine"})
+    out.update({"workload": f"synth.batch({args.sets}): {int(offs[-1])} points",
+                "ms_median_per_call": timings, "reps": args.reps,
+                "device": torch.cuda.get_device_name(0)})
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
-    print(json.dumps(out), flush=True)
+    print(json.dumps({k: v for k, v in out.items() if k != "ms_median_per_call"}), flush=True)
 
 
 if __name__ == "__main__":

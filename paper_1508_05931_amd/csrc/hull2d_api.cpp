@@ -1349,6 +1349,16 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
             return HULL2D_ERR_INVALID_ARG;
     if (h_offsets[S] > 0 && !d_xy) return HULL2D_ERR_INVALID_ARG;
     if (c->opt.batch_engine < 0 || c->opt.batch_engine > 1) return HULL2D_ERR_INVALID_ARG;
+    {
+        // the tiled engine's schedule (0: default)
+        const int32_t t = c->opt.batch_tile;
+        if (t != 0 && (t < (int32_t)kWideTileMin || t > (int32_t)kWideTileMax || (t & (t - 1)) != 0))
+            return HULL2D_ERR_INVALID_ARG;
+        const int32_t fb = c->opt.batch_filter_bits, sb = c->opt.batch_sort_bits, ss = c->opt.batch_side_sets;
+        if (fb != 0 && (fb < 4 || fb > kWideFilterBits)) return HULL2D_ERR_INVALID_ARG;
+        if (sb != 0 && (sb < 4 || sb > kWideSortBits)) return HULL2D_ERR_INVALID_ARG;
+        if (ss < -1 || ss > 4096) return HULL2D_ERR_INVALID_ARG;
+    }
     if (c->broken) return HULL2D_ERR_DEVICE;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
@@ -1406,7 +1416,11 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
             std::stable_sort(c->hb_order, c->hb_order + S,
                              [&](int32_t a, int32_t b) { return size_of(a) > size_of(b); });
         }
-        while (S_big < std::min<int32_t>(S - 1, kWideBigSets) && size_of(c->hb_order[S_big]) >= kWideBigMin) ++S_big;
+        const uint32_t tile = c->opt.batch_tile > 0 ? (uint32_t)c->opt.batch_tile : kWideTile;
+        const uint32_t fbits = c->opt.batch_filter_bits > 0 ? (uint32_t)c->opt.batch_filter_bits : (uint32_t)kWideFilterBits;
+        const uint32_t sbits = c->opt.batch_sort_bits > 0 ? (uint32_t)c->opt.batch_sort_bits : (uint32_t)kWideSortBits;
+        const int32_t side = c->opt.batch_side_sets == 0 ? kWideBigSets : std::max(0, c->opt.batch_side_sets);
+        while (S_big < std::min<int32_t>(S - 1, side) && size_of(c->hb_order[S_big]) >= kWideBigMin) ++S_big;
         for (int32_t r = 0; r < S; ++r) {
             // tiles numbered in this order: the big sets' tiles come first
             const int32_t i = c->hb_order[r];
@@ -1415,16 +1429,17 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
             uint32_t bf = 0;
             if (n > 0) {
                 bf = 4;
-                while (bf < (uint32_t)kWideFilterBits && ((int64_t)1 << bf) < (n + 3) / 4) ++bf;
+                while (bf < fbits && ((int64_t)1 << bf) < (n + 3) / 4) ++bf;
+                bf = std::min(bf, fbits);
             }
             w.o = h_offsets[i];
             w.n = (uint32_t)n;
             w.t0 = (uint32_t)NT;
-            w.nt = (uint32_t)((n + kWideTile - 1) / kWideTile);
+            w.nt = (uint32_t)((n + tile - 1) / tile);
             w.bf = bf;
-            w.bs = std::min<uint32_t>(bf, (uint32_t)kWideSortBits);
+            w.bs = std::min(bf, sbits);
             w.soff = (uint32_t)SE;
-            w.pad = 0;
+            w.tile = tile;
             NT += w.nt;
             if (r < S_big) NT_big = NT;
             SE += n > 0 ? ((int64_t)2 << w.bs) : 0;

@@ -239,26 +239,29 @@ hipError_t launch_batch_clear(uint32_t* meta, hipStream_t s);
 constexpr uint32_t kBatchFallback = 4u;
 
 // The tiled engine of the batched form: the passes over a set's points are
-// split into tiles of kWideTile points and the tiles of all sets make one
-// grid per pass; what spans a whole set (reductions, bucket prefixes, the
-// sort and walk of each region, Step 8) takes one workgroup per set.
+// split into tiles (kWideTile points unless the options say otherwise) and
+// the tiles of all sets make one grid per pass; what spans a whole set
+// (reductions, bucket prefixes, the sort and walk of each region, Step 8)
+// takes one workgroup per set.
 constexpr uint32_t kWideTile = 4096;
-// The largest sets (at most kWideBigSets of at least kWideBigMin points)
-// run the tiled engine's kernels on a second stream beside the others: their
-// per-set kernels take the longest and would otherwise leave most compute
-// units idle at the end of each per-set launch.
+constexpr uint32_t kWideTileMin = 1024, kWideTileMax = 65536;
+// The largest sets (by default at most kWideBigSets of at least kWideBigMin
+// points) run the tiled engine's kernels on a second stream beside the
+// others: their per-set kernels take the longest and would otherwise leave
+// most compute units idle at the end of each per-set launch.
 constexpr int32_t kWideBigSets = 128;
 constexpr int64_t kWideBigMin = 65536;
 
 // Per set, written by the host: the set's first point, its size, its tiles
-// (t0 .. t0 + nt), its bucket counts (2^bf buckets per region for the
-// bucket maxima, held in LDS; 2^bs per region for the sort buckets, whose
-// ends take entries soff .. soff + 2^(bs+1) of bcnt).
+// (t0 .. t0 + nt, `tile` points each, the last one shorter), its bucket
+// counts (2^bf buckets per region for the bucket maxima, held in LDS; 2^bs
+// per region for the sort buckets, whose ends take entries soff ..
+// soff + 2^(bs+1) of bcnt).
 constexpr int kWideFilterBits = 14;  // at most 16,384 filter buckets per region
 constexpr int kWideSortBits = 12;    // at most 4,096 sort buckets per region
 struct WSetIn {
     int64_t o;
-    uint32_t n, t0, nt, bf, bs, soff, pad;
+    uint32_t n, t0, nt, bf, bs, soff, tile;
 };
 
 // Per set, written by the device.

@@ -4,6 +4,7 @@ call is made here."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -79,5 +80,27 @@ def test_shipped_batch_schedule_is_valid():
         pytest.skip("no tuned schedule in the tree")
     t = hx.tuned_batch_schedule()
     assert t["batch_blocks_per_cu"] in (1, 2) and t["batch_order"] in (0, 1, 2)
-    # uint32 struct_size and twelve int32 fields, as hull2d_options
-    assert ctypes.sizeof(hx._Options) == 4 + 12 * 4
+    tile = t.get("batch_tile", 0)
+    assert tile == 0 or (1024 <= tile <= 65536 and tile & (tile - 1) == 0)
+    assert t.get("batch_filter_bits", 0) == 0 or 4 <= t["batch_filter_bits"] <= 14
+    assert t.get("batch_sort_bits", 0) == 0 or 4 <= t["batch_sort_bits"] <= 12
+    assert -1 <= t.get("batch_side_sets", 0) <= 4096
+
+
+def test_option_struct_matches_header(tmp_path):
+    """The binding's option struct has the size and field offsets the C
+    compiler gives hull2d_options."""
+    import paper_1508_05931_amd as hx
+    names = [f[0] for f in hx._Options._fields_]
+    src = tmp_path / "opt.c"
+    body = "".join(f'    printf("%s %zu\\n", "{n}", offsetof(hull2d_options, {n}));\n' for n in names)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "hull2d.h"\nint main(void) {\n'
+                   '    printf("size %zu\\n", sizeof(hull2d_options));\n' + body + '    return 0;\n}\n')
+    exe = tmp_path / "opt"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    assert int(got["size"]) == ctypes.sizeof(hx._Options)
+    for n in names:
+        assert int(got[n]) == getattr(hx._Options, n).offset, n
