@@ -46,7 +46,7 @@ TRAFFIC = {
             "paper_1508_05931_amd/csrc/common.hpp":
                 "b945234c8a977df749c303e9fadbe0b97853518d9b1324d8323dd32fc2e11fd8",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "1c70b7d3d9d7a859bbac6f47b087cc233204a61ddb052c58fe1f843853f9bda1",
+                "36918ef48797467f45cf6d64add6d6b7735422564fa7e37cecb582f536155b96",
         },
     },
 }
