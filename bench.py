@@ -52,12 +52,25 @@ TRAFFIC = {
 }
 
 
+TRAFFIC["batch_tiled"] = {
+    # all kernels of one hull2d_batch call of the tiled engine on the 4096-set
+    # workload, with the tuned schedule
+    "bytes": None,
+    "profile": "profiles/hull_batch_4096_sets_kernel_trace.md",
+    "sources": {rel: None for rel in (
+        "paper_1508_05931_amd/csrc/kernels_batch.hip", "paper_1508_05931_amd/csrc/kernels.hpp",
+        "paper_1508_05931_amd/csrc/steps.hpp", "paper_1508_05931_amd/csrc/exact.hpp",
+        "paper_1508_05931_amd/csrc/common.hpp", "paper_1508_05931_amd/csrc/hull2d_api.cpp",
+        "paper_1508_05931_amd/tuning/batch.json")},
+}
+
+
 def measured_traffic(kernel: str):
     """Profiled HBM bytes per launch of `kernel`, or None when there is no
     profile or the kernel's sources changed since it was taken."""
     import hashlib
     t = TRAFFIC.get(kernel)
-    if t is None:
+    if t is None or t["bytes"] is None:
         return None
     for rel, digest in t["sources"].items():
         path = os.path.join(ROOT, rel)
@@ -203,6 +216,9 @@ def batched(steps: int):
     # every point is read twice (Step 1, then Steps 2-3): 32 bytes a point
     alg = 32.0 * float(offs[-1])
     achieved = alg / (dev_ms * 1e-3) / 1e9
+    # the HBM bytes all kernels of one call move, from the counters
+    traffic = measured_traffic("batch_tiled")
+    traffic_frac = None if traffic is None else round(traffic / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
     return {"workload": "4096 sets, sizes log-uniform 64..200000, 4 distributions",
             "engine": "tiled (batch_engine=0)",
             "n_points": int(offs[-1]), "n_hull": int(st.n_hull), "reps": reps,
@@ -210,8 +226,10 @@ def batched(steps: int):
             "Mpoints_per_s": round(offs[-1] / (ms * 1e-3) / 1e6, 1),
             "sets_on_host_path": int(st.n_candidates),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                         "basis": "32 B per point (two reads of the input) over the device time of a call"},
+                         "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                         "traffic_frac": traffic_frac,
+                         "basis": "32 B per point (two reads of the input) over the device time of a call; "
+                                  "traffic_frac: the counted bytes of all kernels of a call over the same time"},
             "persistent_engine": {"ms_median": round(ms_p, 3), "ms_device": round(dev_p, 3),
                                   "Mpoints_per_s": round(offs[-1] / (ms_p * 1e-3) / 1e6, 1)},
             "per_set_loop": {"ms": round(loop_ms, 2),

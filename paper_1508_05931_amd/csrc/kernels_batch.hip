@@ -1143,7 +1143,7 @@ int batch_blocks_per_cu() {
 // ===========================================================================
 // The tiled engine.  Passes over points (Step 1, Steps 2-3, the bucket
 // maxima, the candidates, their grouping by bucket) run one workgroup per
-// tile of kWideTile points over the tiles of all sets; the reductions and
+// tile of points (kWideTile by default) over the tiles of all sets; the reductions and
 // bucket prefixes of a set take one workgroup per set; each region of a set
 // is sorted and walked by one workgroup (candidates already grouped by their
 // angle bucket, so a tile of whole buckets is sorted in LDS bucket by
@@ -1154,7 +1154,6 @@ namespace {
 constexpr int kWB = 256;              // threads of the tile passes
 constexpr int kWW = kWB / 64;
 constexpr int kWI = 4;                // points per thread per round
-constexpr uint32_t kWT = kWideTile;
 constexpr uint32_t kCT = 2048;        // candidates per walk tile
 constexpr int kCI = (int)kCT / kBB;   // walk positions per thread
 constexpr uint32_t kSortOne = 32;     // buckets up to this size: one thread sorts them
@@ -1190,8 +1189,8 @@ struct alignas(16) WalkLds {
 __device__ inline uint32_t wide_tile_set(const WideArgs& A, uint32_t t, WSetIn& in, uint32_t& lo, uint32_t& hi) {
     const int32_t s = A.tile_set[t];
     in = A.in[s];
-    lo = (t - in.t0) * kWT;
-    hi = min(lo + kWT, in.n);
+    lo = (t - in.t0) * in.tile;
+    hi = min(lo + in.tile, in.n);
     return (uint32_t)s;
 }
 
@@ -1561,7 +1560,7 @@ __global__ __launch_bounds__(kMB) void k_wset(WideArgs A) {
             if (s_pre[mid] <= f) a = mid;
             else z = mid - 1;
         }
-        return a * kWT + (f - s_pre[a]);
+        return a * in.tile + (f - s_pre[a]);
     };
     const uint32_t ntile_loops = flat ? 1u : nt;
 
@@ -1579,7 +1578,7 @@ __global__ __launch_bounds__(kMB) void k_wset(WideArgs A) {
                 key[k] = 0;
                 at[k] = 0;
                 if (f < fend) {
-                    at[k] = flat ? spos(f) : tl * kWT + f;
+                    at[k] = flat ? spos(f) : tl * in.tile + f;
                     p[k] = sv_xy[at[k]];
                     key[k] = sv_key[at[k]];
                 }
@@ -1640,7 +1639,7 @@ __global__ __launch_bounds__(kMB) void k_wset(WideArgs A) {
                 key[k] = kp[k] = at[k] = 0;
                 rg[k] = 3u;
                 if (f < fend) {
-                    at[k] = flat ? spos(f) : tl * kWT + f;
+                    at[k] = flat ? spos(f) : tl * in.tile + f;
                     key[k] = sv_key[at[k]];
                     kp[k] = kap[at[k]];
                     rg[k] = reg[at[k]];
