@@ -336,3 +336,31 @@ def test_batch_tiled_schedule_errors(hx):
         with pytest.raises(hx.HullError):
             c.batch(d, offs)
         c.close()
+
+
+@pytest.mark.parametrize("tile,side", [(0, 0), (1024, -1), (65536, 1)])
+def test_batch_large_sets(torch_dev, hx, tile, side):
+    """Sets of 65,536 to 400,000 points (thin annuli, where every point
+    survives Step 2, a disk, a square, a Gaussian) beside small ones, with
+    several tile sizes and second-stream splits: the oracle's hulls, eager
+    and from a graph."""
+    sets = [synth.annulus(200_000, 0.999, (300, 1)), synth.annulus(70_000, 0.999, (301, 1)),
+            synth.annulus(300_000, 0.999, (302, 1)), synth.disk(400_000, (303, 1)),
+            synth.square(300_000, (304, 1)), synth.annulus(65_536, 0.999, (305, 1)),
+            synth.annulus(40_000, 0.999, (306, 1)), synth.gaussian(100_000, 1.0, (307, 1))]
+    sets += [synth.batch_set(int(n), k, 308)[0] for k, n in enumerate(synth.batch_sizes(30, 64.0, 30_000.0, 309))]
+    pts, offs = _concat(sets)
+    d = torch_dev.from_numpy(pts).cuda()
+    say(f"batch large sets tile={tile} side={side}")
+    kw = dict(batch_tile=tile, batch_side_sets=side)
+    ce = hx.Hull2D(batch_graph=False, **kw)
+    h, o = ce.batch(d, offs)
+    _check_all(h, o, sets)
+    assert ce.last_stats.n_candidates == 0
+    cg = hx.Hull2D(batch_graph=True, **kw)
+    for r in range(2):
+        hg, og = cg.batch(d, offs)
+        assert og.tolist() == o.tolist() and hg.tolist() == h.tolist(), f"replay {r}"
+        torch_dev.cuda.synchronize()
+    cg.close()
+    ce.close()
