@@ -160,6 +160,7 @@ struct hull2d_ctx {
     int bg_engine = -1;
     int64_t bg_nt = -1, bg_nt_big = -1;
     int32_t bg_big = -1;
+    int32_t bg_large[2] = {-1, -1};
     const void* bg_wm = nullptr;  // tiled engine's workspace
 
     // learned filter: weights (float32 master + bfloat16 inference copies),
@@ -1408,14 +1409,14 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
     const int engine = c->opt.batch_engine;
     int64_t NT = 0, SE = 0, NT_big = 0;
     int32_t S_big = 0;  // the largest sets, run beside the others on a second stream
+    int32_t L_big = 0, L_rest = 0;  // sets with the large Steps 6-7 table leading each launch
     if (engine == 0) {
-        if (c->opt.batch_order == 2) {
-            // the tiled engine takes its sets largest first whatever the
-            // persistent engine's order option says
-            for (int32_t i = 0; i < S; ++i) c->hb_order[i] = i;
-            std::stable_sort(c->hb_order, c->hb_order + S,
-                             [&](int32_t a, int32_t b) { return size_of(a) > size_of(b); });
-        }
+        // the tiled engine takes its sets by exact size, largest first,
+        // whatever the persistent engine's order option says: the sets that
+        // need the large Steps 6-7 table are then a prefix of each launch
+        for (int32_t i = 0; i < S; ++i) c->hb_order[i] = i;
+        std::stable_sort(c->hb_order, c->hb_order + S,
+                         [&](int32_t a, int32_t b) { return size_of(a) > size_of(b); });
         const uint32_t tile = c->opt.batch_tile > 0 ? (uint32_t)c->opt.batch_tile : kWideTile;
         const uint32_t fbits = c->opt.batch_filter_bits > 0 ? (uint32_t)c->opt.batch_filter_bits : (uint32_t)kWideFilterBits;
         const uint32_t sbits = c->opt.batch_sort_bits > 0 ? (uint32_t)c->opt.batch_sort_bits : (uint32_t)kWideSortBits;
@@ -1455,6 +1456,15 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         }
         st = ensure_wide(c, S, NT, SE);
         if (st != HULL2D_OK) return st;
+        // the leading sets of each launch (the side stream's, or the only
+        // one, then the others) that need the large Steps 6-7 table
+        auto n_large = [&](int32_t first, int32_t count) {
+            int32_t k = 0;
+            while (k < count && c->hb_win[c->hb_order[first + k]].bf > (uint32_t)kWideSmallBits) ++k;
+            return k;
+        };
+        L_big = S_big > 0 ? n_large(0, S_big) : n_large(0, S);
+        L_rest = S_big > 0 ? n_large(S_big, S - S_big) : 0;
     }
     int32_t* d_count = c->b_meta + 1;
     int32_t* d_start = d_count + S;
@@ -1475,6 +1485,7 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 a.ws = c->w_set;
                 a.order = c->b_order;
                 a.S = S;
+                a.S_large = 0;
                 a.t_base = 0;
                 a.NT = (uint32_t)NT;
                 a.tile_set = c->w_tile_set;
@@ -1501,14 +1512,17 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 a.h_start = d_start;
                 a.h_flags = d_flags;
                 if (S_big == 0) {
+                    a.S_large = L_big;
                     e = launch_wide(a, q);
                 } else {
                     // the big sets on the side stream, the others on q
                     WideArgs big = a, rest = a;
                     big.S = S_big;
+                    big.S_large = L_big;
                     big.NT = (uint32_t)NT_big;
                     rest.order = c->b_order + S_big;
                     rest.S = S - S_big;
+                    rest.S_large = L_rest;
                     rest.t_base = (uint32_t)NT_big;
                     rest.NT = (uint32_t)(NT - NT_big);
                     e = hipEventRecord(c->ev_fork, q);
@@ -1542,7 +1556,8 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         const bool same = c->bgraph && c->bg_S == S && c->bg_N == N && c->bg_xy == d_xy &&
                           c->bg_ws == (const void*)c->b_sv_xy && c->bg_hb == (const void*)c->hb_offs &&
                           c->bg_grid == c->batch_grid && c->bg_engine == engine && c->bg_nt == NT &&
-                          c->bg_wm == (const void*)c->wmem && c->bg_big == S_big && c->bg_nt_big == NT_big;
+                          c->bg_wm == (const void*)c->wmem && c->bg_big == S_big && c->bg_nt_big == NT_big &&
+                          c->bg_large[0] == L_big && c->bg_large[1] == L_rest;
         if (!same) {
             if (c->bgraph) {
                 (void)hipGraphExecDestroy(c->bgraph);
@@ -1579,6 +1594,8 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 c->bg_nt = NT;
                 c->bg_big = S_big;
                 c->bg_nt_big = NT_big;
+                c->bg_large[0] = L_big;
+                c->bg_large[1] = L_rest;
                 c->bg_wm = (const void*)c->wmem;
             }
         }

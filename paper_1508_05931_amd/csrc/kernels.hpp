@@ -258,6 +258,7 @@ constexpr int64_t kWideBigMin = 65536;
 // per region for the sort buckets, whose ends take entries soff ..
 // soff + 2^(bs+1) of bcnt).
 constexpr int kWideFilterBits = 14;  // at most 16,384 filter buckets per region
+constexpr int kWideSmallBits = 11;   // sets of at most 2^11 per region take the small Steps 6-7 workgroup
 constexpr int kWideSortBits = 12;    // at most 4,096 sort buckets per region
 struct WSetIn {
     int64_t o;
@@ -289,6 +290,7 @@ struct WideArgs {
     WSet* ws;              // [S]
     const int32_t* order;  // [S] the sets of this launch, largest first
     int32_t S;             // sets in this launch
+    int32_t S_large;       // its first S_large sets have more than 2^kWideSmallBits filter buckets per region
     uint32_t t_base, NT;   // this launch's tiles: t_base .. t_base + NT (global numbering)
     int32_t* tile_set;     // [NT]
     Cand* tile_ext;        // [NT][4]

@@ -1494,8 +1494,11 @@ __device__ inline uint32_t wblock_scan(uint32_t v, uint32_t* s_w, uint32_t& tota
 //      global memory for the walk.
 //      Two instances: sets of more than 2^kSmallBits buckets per region get
 //      1024 threads and the 128 KB table (one workgroup per compute unit),
-//      the others 256 threads and a 16 KB table.
-constexpr int kSmallBits = 11;
+//      the others 256 threads and a 16 KB table.  Each instance's grid covers
+//      its own sets only (the first S_large sets of the launch, sizes
+//      descending, and the rest), so that no workgroup reserves a table only
+//      to return.
+constexpr int kSmallBits = kWideSmallBits;
 constexpr uint32_t kPreTiles = 2048;  // sets of up to this many tiles spread their survivors evenly
 
 template <int kBits, int kMB>
@@ -1509,7 +1512,7 @@ __global__ __launch_bounds__(kMB) void k_wset(WideArgs A) {
     __shared__ uint32_t s_w[kMW];
     __shared__ uint32_t s_nc;
     const int tid = (int)threadIdx.x;
-    const int32_t s = A.order[blockIdx.x];
+    const int32_t s = A.order[blockIdx.x + (kBits > kSmallBits ? 0u : (uint32_t)A.S_large)];
     const WSetIn in = A.in[s];
     if (in.n == 0) return;
     if (kBits > kSmallBits ? in.bf <= (uint32_t)kSmallBits : in.bf > (uint32_t)kSmallBits) return;
@@ -1918,9 +1921,9 @@ struct WRegion {
     int r;
     uint32_t cnt, rs, re;
 };
-__device__ inline bool wide_region(const WideArgs& A, WRegion& R) {
-    R.s = A.order[blockIdx.x >> 1];
-    R.r = (int)(blockIdx.x & 1u);
+__device__ inline bool wide_region(const WideArgs& A, WRegion& R, uint32_t g = blockIdx.x) {
+    R.s = A.order[g >> 1];
+    R.r = (int)(g & 1u);
     const WSet& W = A.ws[R.s];
     if (A.in[R.s].n == 0 || W.flags != 0u || W.m1 == 0u) return false;
     R.cnt = W.c[R.r];
@@ -2258,13 +2261,11 @@ __global__ __launch_bounds__(kBB) void k_wwalk_small(WideArgs A) {
 //      keys, its walk and removal (kept points ascending from the region's
 //      first position); an equal-key run too long for the workgroup sends the
 //      set to the host
-__global__ __launch_bounds__(kBB) void k_wwalk_radix(WideArgs A) {
-    __shared__ BatchLds S;
+__device__ __forceinline__ void walk_radix_region(const WideArgs& A, BatchLds& S, uint32_t g) {
     const int tid = (int)threadIdx.x;
     WRegion R;
-    if (!wide_region(A, R)) return;
+    if (!wide_region(A, R, g)) return;
     WSet& W = A.ws[R.s];
-    if (W.big[R.r] <= kCT) return;
     const WSetIn in = A.in[R.s];
     const size_t o = (size_t)in.o;
     const uint32_t cnt = R.cnt, rs = R.rs;
@@ -2274,9 +2275,9 @@ __global__ __launch_bounds__(kBB) void k_wwalk_radix(WideArgs A) {
     uint32_t* K1 = A.kb + o + rs;
     uint32_t* V1 = A.vb + o + rs;
     for (uint32_t i = (uint32_t)tid; i < cnt; i += kBB) {
-        const uint2 g = A.gk[o + rs + i];
-        K0[i] = g.x;
-        V0[i] = g.y;
+        const uint2 gg = A.gk[o + rs + i];
+        K0[i] = gg.x;
+        V0[i] = gg.y;
     }
     __syncthreads();
     const int cur = wg_radix(S, K0, V0, K1, V1, cnt);
@@ -2292,6 +2293,35 @@ __global__ __launch_bounds__(kBB) void k_wwalk_radix(WideArgs A) {
     if (tid == 0) {
         W.k[R.r] = end - rs;
         W.klo[R.r] = rs;
+    }
+}
+
+// ---- The regions with a sort bucket larger than a walk tile: Step 4 by the
+//      persistent engine's radix sort in HBM, then the walk.  Such regions
+//      are rare, so a small grid scans all regions (one per thread, kBB at a
+//      time) and walks the ones found, one after another; a grid of one
+//      workgroup per region would reserve this kernel's LDS for every region
+//      only to return.
+constexpr uint32_t kRadixGrid = 32;
+
+__global__ __launch_bounds__(kBB) void k_wwalk_radix(WideArgs A) {
+    __shared__ BatchLds S;
+    __shared__ uint32_t s_list[kBB];
+    __shared__ uint32_t s_n;
+    const int tid = (int)threadIdx.x;
+    const uint32_t nreg = 2u * (uint32_t)A.S;
+    for (uint32_t base = blockIdx.x * (uint32_t)kBB; base < nreg; base += gridDim.x * (uint32_t)kBB) {
+        if (tid == 0) s_n = 0u;
+        __syncthreads();
+        const uint32_t g = base + (uint32_t)tid;
+        WRegion R;
+        if (g < nreg && wide_region(A, R, g) && A.ws[R.s].big[R.r] > kCT) s_list[atomicAdd(&s_n, 1u)] = g;
+        __syncthreads();
+        const uint32_t nl = s_n;
+        for (uint32_t q = 0; q < nl; ++q) {
+            walk_radix_region(A, S, s_list[q]);
+            __syncthreads();
+        }
     }
 }
 
@@ -2431,11 +2461,12 @@ hipError_t launch_wide(const WideArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_wparams, S1, dim3(64), 0, s, a);
     if (a.NT > 0) hipLaunchKernelGGL(k_wfilter, NT, dim3(kWB), 0, s, a);
     hipLaunchKernelGGL(k_wfar, S1, dim3(64), 0, s, a);
-    hipLaunchKernelGGL((k_wset<kWideFilterBits, 1024>), S1, dim3(1024), 0, s, a);
-    hipLaunchKernelGGL((k_wset<kSmallBits, 256>), S1, dim3(256), 0, s, a);
+    if (a.S_large > 0) hipLaunchKernelGGL((k_wset<kWideFilterBits, 1024>), dim3((unsigned)a.S_large), dim3(1024), 0, s, a);
+    if (a.S > a.S_large)
+        hipLaunchKernelGGL((k_wset<kSmallBits, 256>), dim3((unsigned)(a.S - a.S_large)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_wwalk_small, dim3((unsigned)((2 * a.S + kBW - 1) / kBW)), dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(k_wwalk, S2, dim3(kBB), 0, s, a);
-    hipLaunchKernelGGL(k_wwalk_radix, S2, dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(k_wwalk_radix, dim3(kRadixGrid), dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(k_wstep8_small, dim3((unsigned)((a.S + kBW - 1) / kBW)), dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(k_wstep8, S1, dim3(kBB), 0, s, a);
     return hipGetLastError();
