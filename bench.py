@@ -46,7 +46,7 @@ TRAFFIC = {
             "paper_1508_05931_amd/csrc/common.hpp":
                 "b945234c8a977df749c303e9fadbe0b97853518d9b1324d8323dd32fc2e11fd8",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "36918ef48797467f45cf6d64add6d6b7735422564fa7e37cecb582f536155b96",
+                "e89bf2385d949258fa428ed3ba2cf25dea5b8f80f8fe09555e3b935c76dd67b4",
         },
     },
 }
@@ -55,13 +55,13 @@ TRAFFIC = {
 TRAFFIC["batch_tiled"] = {
     # all kernels of one hull2d_batch call of the tiled engine on the 4096-set
     # workload with the tuned schedule (both streams), same scale factors
-    "bytes": 9_655_000_000,  # 7,411.5 MB fetched + 2,243.6 MB written
+    "bytes": 9_649_500_000,  # 7,400.3 MB fetched + 2,249.2 MB written
     "profile": "profiles/hull_batch_4096_sets_kernel_trace.md",
     "sources": {
         "paper_1508_05931_amd/csrc/kernels_batch.hip":
-            "5d3cd5652f77b3810a2c8590b79f6e25bde9240d6f9d26ea4bdffa9495d0b17b",
+            "f3afcbabb530f0352aad7230a73032d3a3ad8c5698fd83fe0645080f91c56c4a",
         "paper_1508_05931_amd/csrc/kernels.hpp":
-            "36918ef48797467f45cf6d64add6d6b7735422564fa7e37cecb582f536155b96",
+            "e89bf2385d949258fa428ed3ba2cf25dea5b8f80f8fe09555e3b935c76dd67b4",
         "paper_1508_05931_amd/csrc/steps.hpp":
             "33fa676280d55236357f5fab49d6890917f601f226406e1aaa653063fafa9744",
         "paper_1508_05931_amd/csrc/exact.hpp":
@@ -69,7 +69,7 @@ TRAFFIC["batch_tiled"] = {
         "paper_1508_05931_amd/csrc/common.hpp":
             "b945234c8a977df749c303e9fadbe0b97853518d9b1324d8323dd32fc2e11fd8",
         "paper_1508_05931_amd/csrc/hull2d_api.cpp":
-            "a647651ec841c190967729d20e708714be9cc1a3c06fefa497ed4026c8f5a513",
+            "a6ba25d7d944b1b83424669a166a0e6d53bfcda42ac0b927bf08f9d485bfeb9a",
         "paper_1508_05931_amd/tuning/batch.json":
             "50f9048d755749c1ffa2c9666c66fd6f243b9a09bcb2377e84b1081052cac345",
     },
