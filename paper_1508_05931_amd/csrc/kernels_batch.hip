@@ -449,18 +449,26 @@ __device__ __forceinline__ uint32_t wg_compact(BatchLds& S, const uint32_t* V, c
     return at;
 }
 
-// Step 8 on a chunk: Graham scan of P_0 followed by K[A[beg..end)) (pop while
-// the last two stack points and the new one do not turn left, skip a point
-// equal to the top).  The stack, without P_0, goes to st[0..); returns its
-// size.  The result is the hull of P_0 and the chunk, so a point it drops is
-// no vertex of the whole hull either.
-__device__ __forceinline__ uint32_t graham_run(const double2* K, const uint32_t* A, uint32_t beg, uint32_t end,
-                               uint32_t* st, double x0, double y0) {
+// Where entry i of a set's kept list lies in its kept-point arrays: the
+// right region's k0 points from lo0, then the left region's from lo1.
+struct KeptMap {
+    uint32_t lo0, k0, lo1;
+    __device__ uint32_t operator()(uint32_t i) const { return i < k0 ? lo0 + i : lo1 + (i - k0); }
+};
+
+// Step 8 on a chunk: Graham scan of P_0 followed by K[A[beg..end)) (or the
+// kept list's own entries beg..end when A is null; pop while the last two
+// stack points and the new one do not turn left, skip a point equal to the
+// top).  The stack, without P_0, goes to st[0..); returns its size.  The
+// result is the hull of P_0 and the chunk, so a point it drops is no vertex
+// of the whole hull either.
+__device__ __forceinline__ uint32_t graham_run(const double2* K, const uint32_t* A, const KeptMap& M, uint32_t beg,
+                               uint32_t end, uint32_t* st, double x0, double y0) {
     uint32_t top = 0;              // stack entries above P_0
     double tx = x0, ty = y0;       // top of the stack (P_0 when top == 0)
     double sx = x0, sy = y0;       // the entry below it (valid when top >= 1)
     for (uint32_t i = beg; i < end; ++i) {
-        const uint32_t pos = A ? A[i] : i;
+        const uint32_t pos = A ? A[i] : M(i);
         const double2 p = K[pos];
         if (p.x == tx && p.y == ty) continue;
         while (top >= 1) {
@@ -624,15 +632,15 @@ struct HullSink {
 };
 
 // Step 8 of one set and its output.  The kept list (angular order, P_0 not
-// in it) is positions 0..m-1 of (kxy, kidx), or first[0..m) of them when
-// `first` is not null (then first == b0); b0, b1, b2 hold m positions each.
+// in it) is entries 0..m-1 of (kxy, kidx) as M places them; b0, b1, b2 hold
+// m positions each.
 __device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int32_t s, const double2* kxy,
-                            const uint32_t* kidx, uint32_t* first, uint32_t m, uint32_t* b0,
+                            const uint32_t* kidx, const KeptMap& M, uint32_t m, uint32_t* b0,
                             uint32_t* b1, uint32_t* b2, double x0, double y0, int32_t p0_idx) {
     const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid >> 6;
     // reduce chunks in parallel (in HBM while many points are left, then in
     // LDS), then one thread
-    uint32_t* cur_a = first;  // positions into the kept list (null: all of them)
+    uint32_t* cur_a = nullptr;  // positions into the kept arrays (null: the kept list through M)
     uint32_t len = m;
     uint32_t* bufs[3] = {b0, b1, b2};
     int nb = 0;
@@ -644,7 +652,7 @@ __device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int3
         for (int q = 0; q < 3; ++q)
             if (bufs[q] != cur_a && bufs[q] != st) dst = bufs[q];
         const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
-        const uint32_t h = graham_run(kxy, cur_a, beg, end, st + beg, x0, y0);
+        const uint32_t h = graham_run(kxy, cur_a, M, beg, end, st + beg, x0, y0);
         uint32_t tot;
         const uint32_t at = bexcl(h, S, tot);
         for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
@@ -659,7 +667,7 @@ __device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int3
     uint16_t* fin16 = nullptr;  // final stack (LDS path)
     if (in_lds) {
         for (uint32_t i = (uint32_t)tid; i < len; i += kBB) {
-            const uint32_t pos = cur_a ? cur_a[i] : i;
+            const uint32_t pos = cur_a ? cur_a[i] : M(i);
             const double2 q = kxy[pos];
             S.u.gs.x[i] = q.x;
             S.u.gs.y[i] = q.y;
@@ -696,7 +704,7 @@ __device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int3
     } else {
         for (int q = 0; q < 3; ++q)
             if (bufs[q] != cur_a) fin = bufs[q];
-        if (tid == 0) S.h = graham_run(kxy, cur_a, 0, len, fin, x0, y0) + 1u;
+        if (tid == 0) S.h = graham_run(kxy, cur_a, M, 0, len, fin, x0, y0) + 1u;
     }
     __syncthreads();
     const uint32_t h = S.h;
@@ -1072,7 +1080,7 @@ __device__ __forceinline__ void batch_set(const BatchArgs& A, BatchLds& S, int32
     H.count = A.h_count;
     H.start = A.h_start;
     H.flags = A.h_flags;
-    batch_step8(S, H, s, sv_xy, sv_idx, nullptr, m, ka, kb, va, x0, y0, p0_idx);
+    batch_step8(S, H, s, sv_xy, sv_idx, KeptMap{0u, m, 0u}, m, ka, kb, va, x0, y0, p0_idx);
 }
 
 __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchArgs A) {
@@ -2335,7 +2343,6 @@ __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ BatchLds S;
     const int32_t s = A.order[blockIdx.x];
     const WSetIn in = A.in[s];
-    const uint32_t tid = threadIdx.x;
     const WSet& W = A.ws[s];
     // empty and flagged sets, and short kept lists: k_wstep8_small
     if (in.n == 0 || W.flags != 0u || wide_kept(W) <= kStep8Wave) return;
@@ -2343,17 +2350,14 @@ __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k
     const uint32_t k0 = W.k[0], k1 = W.k[1];
     const uint32_t lo0 = W.klo[0], lo1 = W.klo[1];
     const uint32_t m = k0 + k1;
-    uint32_t* first = A.ka + o;
-    for (uint32_t q = tid; q < m; q += kBB) first[q] = q < k0 ? lo0 + q : lo1 + (q - k0);
-    __syncthreads();
     HullSink H;
     H.hull = A.hull;
     H.cursor = A.hull_cursor;
     H.count = A.h_count;
     H.start = A.h_start;
     H.flags = A.h_flags;
-    batch_step8(S, H, s, A.sv_xy + o, A.sv_idx + o, first, m, A.ka + o, A.kb + o, A.va + o, W.P.x0, W.P.y0,
-                W.P.p0_idx);
+    batch_step8(S, H, s, A.sv_xy + o, A.sv_idx + o, KeptMap{lo0, k0, lo1}, m, A.ka + o, A.kb + o, A.va + o, W.P.x0,
+                W.P.y0, W.P.p0_idx);
 }
 
 // ---- Step 8 of a set whose kept list has at most kStep8Wave points, one
