@@ -494,6 +494,41 @@ __device__ __forceinline__ uint32_t graham_run(const double2* K, const uint32_t*
     return top;
 }
 
+// graham_run with its stack in LDS, as 16-bit offsets from beg (ls, room for
+// kLdsStack entries: chunks of at most that many points): a pop then reads
+// LDS for the entry below instead of global memory written moments before.
+constexpr uint32_t kLdsStack = 51;
+__device__ __forceinline__ uint32_t graham_run_ls(const double2* K, const uint32_t* A, const KeptMap& M,
+                                                  uint32_t beg, uint32_t end, uint16_t* ls, double x0, double y0) {
+    uint32_t top = 0;
+    double tx = x0, ty = y0, sx = x0, sy = y0;
+    for (uint32_t i = beg; i < end; ++i) {
+        const double2 p = K[A ? A[i] : M(i)];
+        if (p.x == tx && p.y == ty) continue;
+        while (top >= 1) {
+            if (orient(sx, sy, tx, ty, p.x, p.y) > 0) break;
+            --top;
+            tx = sx;
+            ty = sy;
+            if (top >= 2) {
+                const uint32_t j = beg + ls[top - 2];
+                const double2 q = K[A ? A[j] : M(j)];
+                sx = q.x;
+                sy = q.y;
+            } else {
+                sx = x0;
+                sy = y0;
+            }
+        }
+        ls[top++] = (uint16_t)(i - beg);
+        sx = tx;
+        sy = ty;
+        tx = p.x;
+        ty = p.y;
+    }
+    return top;
+}
+
 // graham_run on points staged in LDS (positions are u16 indices into x, y).
 __device__ __forceinline__ uint32_t graham_lds(const double* __restrict__ gx, const double* __restrict__ gy,
                                const uint16_t* A, uint32_t beg, uint32_t end, uint16_t* st, double x0,
@@ -647,16 +682,33 @@ __device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int3
     bool stuck = false;
     while (len > kGLds && !stuck) {
         const uint32_t ch = max(16u, (len + kBB - 1) / kBB);
+        uint32_t len_next;
         uint32_t* st = bufs[nb % 3] == cur_a ? bufs[(nb + 1) % 3] : bufs[nb % 3];
         uint32_t* dst = nullptr;
         for (int q = 0; q < 3; ++q)
             if (bufs[q] != cur_a && bufs[q] != st) dst = bufs[q];
         const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
-        const uint32_t h = graham_run(kxy, cur_a, M, beg, end, st + beg, x0, y0);
-        uint32_t tot;
-        const uint32_t at = bexcl(h, S, tot);
-        for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
+        if (ch <= kLdsStack) {
+            // the stacks in the LDS the final stage has not taken yet
+            static_assert(sizeof(S.u) >= (size_t)kBB * kLdsStack * sizeof(uint16_t), "LDS stacks");
+            uint16_t* ls = reinterpret_cast<uint16_t*>(&S.u) + (size_t)tid * kLdsStack;
+            const uint32_t h = graham_run_ls(kxy, cur_a, M, beg, end, ls, x0, y0);
+            uint32_t tot;
+            const uint32_t at = bexcl(h, S, tot);
+            for (uint32_t j = 0; j < h; ++j) {
+                const uint32_t i = beg + ls[j];
+                dst[at + j] = cur_a ? cur_a[i] : M(i);
+            }
+            len_next = tot;
+        } else {
+            const uint32_t h = graham_run(kxy, cur_a, M, beg, end, st + beg, x0, y0);
+            uint32_t tot;
+            const uint32_t at = bexcl(h, S, tot);
+            for (uint32_t j = 0; j < h; ++j) dst[at + j] = st[beg + j];
+            len_next = tot;
+        }
         __syncthreads();
+        const uint32_t tot = len_next;
         stuck = (uint64_t)tot * 10u > (uint64_t)len * 9u;
         cur_a = dst;
         len = tot;
