@@ -668,7 +668,10 @@ struct HullSink {
 
 // Step 8 of one set and its output.  The kept list (angular order, P_0 not
 // in it) is entries 0..m-1 of (kxy, kidx) as M places them; b0, b1, b2 hold
-// m positions each.
+// m positions each.  kLdsStacks: chunk stacks in LDS where they fit (the
+// persistent engine keeps them in global memory: its kernel is already at
+// its register limit).
+template <bool kLdsStacks>
 __device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int32_t s, const double2* kxy,
                             const uint32_t* kidx, const KeptMap& M, uint32_t m, uint32_t* b0,
                             uint32_t* b1, uint32_t* b2, double x0, double y0, int32_t p0_idx) {
@@ -688,7 +691,7 @@ __device__ __forceinline__ void batch_step8(BatchLds& S, const HullSink& H, int3
         for (int q = 0; q < 3; ++q)
             if (bufs[q] != cur_a && bufs[q] != st) dst = bufs[q];
         const uint32_t beg = min(len, (uint32_t)tid * ch), end = min(len, beg + ch);
-        if (ch <= kLdsStack) {
+        if (kLdsStacks && ch <= kLdsStack) {
             // the stacks in the LDS the final stage has not taken yet
             static_assert(sizeof(S.u) >= (size_t)kBB * kLdsStack * sizeof(uint16_t), "LDS stacks");
             uint16_t* ls = reinterpret_cast<uint16_t*>(&S.u) + (size_t)tid * kLdsStack;
@@ -1132,7 +1135,7 @@ __device__ __forceinline__ void batch_set(const BatchArgs& A, BatchLds& S, int32
     H.count = A.h_count;
     H.start = A.h_start;
     H.flags = A.h_flags;
-    batch_step8(S, H, s, sv_xy, sv_idx, KeptMap{0u, m, 0u}, m, ka, kb, va, x0, y0, p0_idx);
+    batch_step8<false>(S, H, s, sv_xy, sv_idx, KeptMap{0u, m, 0u}, m, ka, kb, va, x0, y0, p0_idx);
 }
 
 __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(BatchArgs A) {
@@ -2408,7 +2411,7 @@ __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k
     H.count = A.h_count;
     H.start = A.h_start;
     H.flags = A.h_flags;
-    batch_step8(S, H, s, A.sv_xy + o, A.sv_idx + o, KeptMap{lo0, k0, lo1}, m, A.ka + o, A.kb + o, A.va + o, W.P.x0,
+    batch_step8<true>(S, H, s, A.sv_xy + o, A.sv_idx + o, KeptMap{lo0, k0, lo1}, m, A.ka + o, A.kb + o, A.va + o, W.P.x0,
                 W.P.y0, W.P.p0_idx);
 }
 
