@@ -55,11 +55,11 @@ TRAFFIC = {
 TRAFFIC["batch_tiled"] = {
     # all kernels of one hull2d_batch call of the tiled engine on the 4096-set
     # workload with the tuned schedule (both streams), same scale factors
-    "bytes": 9_649_500_000,  # 7,400.3 MB fetched + 2,249.2 MB written
+    "bytes": 8_928_500_000,  # 6,840.6 MB fetched + 2,087.9 MB written
     "profile": "profiles/hull_batch_4096_sets_kernel_trace.md",
     "sources": {
         "paper_1508_05931_amd/csrc/kernels_batch.hip":
-            "f3afcbabb530f0352aad7230a73032d3a3ad8c5698fd83fe0645080f91c56c4a",
+            "dc5a63607fcd6c46d789555eabc90cd077ec4ec465ed4c981508615772cd899b",
         "paper_1508_05931_amd/csrc/kernels.hpp":
             "e89bf2385d949258fa428ed3ba2cf25dea5b8f80f8fe09555e3b935c76dd67b4",
         "paper_1508_05931_amd/csrc/steps.hpp":
