@@ -46,7 +46,7 @@ TRAFFIC = {
             "paper_1508_05931_amd/csrc/common.hpp":
                 "b945234c8a977df749c303e9fadbe0b97853518d9b1324d8323dd32fc2e11fd8",
             "paper_1508_05931_amd/csrc/kernels.hpp":
-                "e89bf2385d949258fa428ed3ba2cf25dea5b8f80f8fe09555e3b935c76dd67b4",
+                "bec1a4687ab4f3693c831227513bcb66ff7d49d6249bcd3441975fde7968e309",
         },
     },
 }

@@ -155,11 +155,14 @@ typedef struct {
      * sort (4 to 12; default 12).  batch_side_sets: how many of the largest
      * sets (those of at least 65,536 points) run on a second stream beside
      * the others (1 to 4,096; -1 none, one stream; default 128).
+     * batch_items: points each thread takes per round in the passes over
+     * points (2, 4 or 8; default 4).
      * paper_1508_05931_amd/autotune.py picks them by timing. */
     int32_t batch_tile;
     int32_t batch_filter_bits;
     int32_t batch_sort_bits;
     int32_t batch_side_sets;
+    int32_t batch_items;
 } hull2d_options;
 
 /* Per-kernel stage indices of hull2d_stats.ms_stage. */

@@ -59,7 +59,7 @@ class _Options(ctypes.Structure):
                 ("scan", ctypes.c_int32), ("workspace_limit_mib", ctypes.c_int32),
                 ("batch_engine", ctypes.c_int32), ("batch_tile", ctypes.c_int32),
                 ("batch_filter_bits", ctypes.c_int32), ("batch_sort_bits", ctypes.c_int32),
-                ("batch_side_sets", ctypes.c_int32)]
+                ("batch_side_sets", ctypes.c_int32), ("batch_items", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -177,7 +177,7 @@ TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "bat
 
 # The schedule knobs autotune.py may store (each 0 = the library default).
 TUNED_KEYS = ("batch_blocks_per_cu", "batch_order", "batch_tile", "batch_filter_bits",
-              "batch_sort_bits", "batch_side_sets")
+              "batch_sort_bits", "batch_side_sets", "batch_items")
 
 
 def tuned_batch_schedule() -> dict:
@@ -201,7 +201,8 @@ class Hull2D:
     graph.  batch_engine: 0 tiled (passes over points share a large set among
     many workgroups), 1 one persistent workgroup per set.  batch_blocks_per_cu
     / batch_order: the persistent engine's schedule; batch_tile /
-    batch_filter_bits / batch_sort_bits / batch_side_sets: the tiled engine's
+    batch_filter_bits / batch_sort_bits / batch_side_sets / batch_items: the
+    tiled engine's
     (hull2d_options documents each).  None takes the values autotune.py stored
     in tuning/batch.json, else the library's defaults."""
 
@@ -211,7 +212,8 @@ class Hull2D:
                  batch_order: int | None = None, reserve_noalloc: bool = False, method: int = 0,
                  scan: int = 0, workspace_limit_mib: int = 0, batch_engine: int = 0,
                  batch_tile: int | None = None, batch_filter_bits: int | None = None,
-                 batch_sort_bits: int | None = None, batch_side_sets: int | None = None):
+                 batch_sort_bits: int | None = None, batch_side_sets: int | None = None,
+                 batch_items: int | None = None):
         import torch
         lib = load_library()
         if device is None:
@@ -223,14 +225,15 @@ class Hull2D:
         tuned = tuned_batch_schedule()
         given = {"batch_blocks_per_cu": batch_blocks_per_cu, "batch_order": batch_order,
                  "batch_tile": batch_tile, "batch_filter_bits": batch_filter_bits,
-                 "batch_sort_bits": batch_sort_bits, "batch_side_sets": batch_side_sets}
+                 "batch_sort_bits": batch_sort_bits, "batch_side_sets": batch_side_sets,
+                 "batch_items": batch_items}
         sched = {k: int(v) if v is not None else tuned.get(k, 0) for k, v in given.items()}
         opt = _Options(ctypes.sizeof(_Options), int(round2_chunk), int(profile),
                        int(bool(full_sort)), int(bool(learned)), sched["batch_blocks_per_cu"],
                        sched["batch_order"], int(bool(batch_graph)), int(method),
                        int(bool(reserve_noalloc)), int(scan), int(workspace_limit_mib),
                        int(batch_engine), sched["batch_tile"], sched["batch_filter_bits"],
-                       sched["batch_sort_bits"], sched["batch_side_sets"])
+                       sched["batch_sort_bits"], sched["batch_side_sets"], sched["batch_items"])
         h = ctypes.c_void_p()
         st = lib.hull2d_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream.cuda_stream),
                                ctypes.byref(opt))

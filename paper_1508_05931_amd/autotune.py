@@ -14,11 +14,14 @@ sets), each schedule as a captured graph, for both engines:
   passes over points, the largest number of filter buckets per region
   (2^bits) of Steps 6-7, the largest number of angle buckets per region of
   the grouping before the sort, and how many of the largest sets run on the
-  second stream (-1: one stream).
+  second stream (-1: one stream); then, at the fastest of those, the points
+  each thread takes per round in the passes over points (2, 4 or 8).
 
 Every schedule must give the same hulls as the first; the fastest of each
-engine (median of `reps` timed calls after two warm-up calls) goes to
-tuning/batch.json, which Hull2D reads as its default schedule.
+engine (median device time of `reps` calls after two warm-up calls, from
+the library's events around the call's device work: steadier than the
+wall clock) goes to tuning/batch.json, which Hull2D reads as its default
+schedule.
 """
 from __future__ import annotations
 
@@ -27,7 +30,6 @@ import itertools
 import json
 import os
 import sys
-import time
 
 import numpy as np
 
@@ -41,6 +43,7 @@ TILE_SIZES = (4096, 8192, 16384, 32768)
 FILTER_BITS = (13, 14)
 SORT_BITS = (11, 12)
 SIDE_SETS = (-1, 256, 384, 512)
+ITEMS = (2, 4, 8)
 TILED = [dict(batch_engine=0, batch_tile=t, batch_filter_bits=f, batch_sort_bits=s, batch_side_sets=g)
          for t, f, s, g in itertools.product(TILE_SIZES, FILTER_BITS, SORT_BITS, SIDE_SETS)]
 
@@ -52,7 +55,7 @@ def _name(kw: dict) -> str:
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--sets", type=int, default=4096)
-    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--out", default=os.path.join(HERE, "tuning", "batch.json"))
     args = ap.parse_args(argv)
     import torch
@@ -64,7 +67,13 @@ def main(argv=None):
     ref = None
     timings = {"persistent": {}, "tiled": {}}
     best = {}
-    for engine, grid in (("persistent", PERSISTENT), ("tiled", TILED)):
+    def stages():
+        yield "persistent", PERSISTENT
+        yield "tiled", TILED
+        # points per thread, at the fastest tiled schedule so far
+        yield "tiled", [dict(best["tiled"][1], batch_items=i) for i in ITEMS]
+
+    for engine, grid in stages():
         for kw in grid:
             # every knob given, so the stored tuning does not leak into the run
             full = {k: 0 for k in hx.TUNED_KEYS}
@@ -78,11 +87,10 @@ def main(argv=None):
                 raise SystemExit(f"schedule {kw} changed the hulls")
             ts = []
             for _ in range(args.reps):
-                t0 = time.perf_counter()
                 c.batch(d, offs)
-                ts.append(time.perf_counter() - t0)
+                ts.append(float(c.last_stats.ms_device))
             c.close()
-            ms = round(float(np.median(ts)) * 1e3, 3)
+            ms = round(float(np.median(ts)), 3)
             timings[engine][_name(kw)] = ms
             print(f"{engine} {_name(kw)}: {ms:.3f} ms", flush=True)
             if engine not in best or ms < best[engine][0]:

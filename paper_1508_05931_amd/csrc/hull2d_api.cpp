@@ -1359,6 +1359,8 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         if (fb != 0 && (fb < 4 || fb > kWideFilterBits)) return HULL2D_ERR_INVALID_ARG;
         if (sb != 0 && (sb < 4 || sb > kWideSortBits)) return HULL2D_ERR_INVALID_ARG;
         if (ss < -1 || ss > 4096) return HULL2D_ERR_INVALID_ARG;
+        const int32_t it = c->opt.batch_items;
+        if (it != 0 && it != 2 && it != 4 && it != 8) return HULL2D_ERR_INVALID_ARG;
     }
     if (c->broken) return HULL2D_ERR_DEVICE;
     if (stats) {
@@ -1486,6 +1488,7 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
                 a.order = c->b_order;
                 a.S = S;
                 a.S_large = 0;
+                a.items = c->opt.batch_items > 0 ? c->opt.batch_items : 4;
                 a.t_base = 0;
                 a.NT = (uint32_t)NT;
                 a.tile_set = c->w_tile_set;

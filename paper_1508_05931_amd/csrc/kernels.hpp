@@ -291,6 +291,7 @@ struct WideArgs {
     const int32_t* order;  // [S] the sets of this launch, largest first
     int32_t S;             // sets in this launch
     int32_t S_large;       // its first S_large sets have more than 2^kWideSmallBits filter buckets per region
+    int32_t items;         // points per thread per round in the passes over points: 2, 4 or 8
     uint32_t t_base, NT;   // this launch's tiles: t_base .. t_base + NT (global numbering)
     int32_t* tile_set;     // [NT]
     Cand* tile_ext;        // [NT][4]

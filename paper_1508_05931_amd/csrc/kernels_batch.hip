@@ -1216,7 +1216,7 @@ namespace {
 
 constexpr int kWB = 256;              // threads of the tile passes
 constexpr int kWW = kWB / 64;
-constexpr int kWI = 4;                // points per thread per round
+constexpr int kWI = 4;                // entries per thread per round (grouping); the passes over points take kI of 2, 4 or 8
 constexpr uint32_t kCT = 2048;        // candidates per walk tile
 constexpr int kCI = (int)kCT / kBB;   // walk positions per thread
 constexpr uint32_t kSortOne = 32;     // buckets up to this size: one thread sorts them
@@ -1278,6 +1278,7 @@ __global__ __launch_bounds__(kWB) void k_wprep(WideArgs A) {
 }
 
 // ---- Step 1 on a tile: its four extreme points and domain flags
+template <int kI>
 __global__ __launch_bounds__(kWB) void k_wext(WideArgs A) {
     __shared__ Cand s_ext[kWW][4];
     __shared__ uint32_t s_bad;
@@ -1290,16 +1291,16 @@ __global__ __launch_bounds__(kWB) void k_wext(WideArgs A) {
     if (tid == 0) s_bad = 0u;
     Cand c[4] = {sentinel(0), sentinel(1), sentinel(2), sentinel(3)};
     uint32_t bad = 0;
-    for (uint32_t b0 = lo; b0 < hi; b0 += kWB * kWI) {
-        double2 p[kWI];
+    for (uint32_t b0 = lo; b0 < hi; b0 += kWB * kI) {
+        double2 p[kI];
 #pragma unroll
-        for (int k = 0; k < kWI; ++k) {
+        for (int k = 0; k < kI; ++k) {
             const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
             p[k] = make_double2(0.0, 0.0);
             if (i < hi) p[k] = load_stream(&xy[i]);
         }
 #pragma unroll
-        for (int k = 0; k < kWI; ++k) {
+        for (int k = 0; k < kI; ++k) {
             const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
             if (i < hi) {
                 const bool need = (p[k].x <= c[0].x) | (p[k].y <= c[1].y) | (p[k].x >= c[2].x) |
@@ -1360,6 +1361,7 @@ __global__ __launch_bounds__(64) void k_wparams(WideArgs A) {
 
 // ---- Steps 2-3 on a tile: survivors (packed at the tile's first position)
 //      with their angle keys, and the tile's farthest survivor (Step 5)
+template <int kI>
 __global__ __launch_bounds__(kWB) void k_wfilter(WideArgs A) {
     __shared__ uint32_t s_cnt;
     __shared__ double s_d2[kWW];
@@ -1389,16 +1391,16 @@ __global__ __launch_bounds__(kWB) void k_wfilter(WideArgs A) {
     __syncthreads();
     double bd2 = -1.0;
     uint32_t bidx = kNone, bslot = kNone;
-    for (uint32_t b0 = lo; b0 < hi; b0 += kWB * kWI) {
-        double2 p[kWI];
+    for (uint32_t b0 = lo; b0 < hi; b0 += kWB * kI) {
+        double2 p[kI];
 #pragma unroll
-        for (int k = 0; k < kWI; ++k) {
+        for (int k = 0; k < kI; ++k) {
             const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
             p[k] = make_double2(0.0, 0.0);
             if (i < hi) p[k] = load_stream(&xy[i]);
         }
 #pragma unroll
-        for (int k = 0; k < kWI; ++k) {
+        for (int k = 0; k < kI; ++k) {
             const uint32_t i = b0 + (uint32_t)(k * kWB + tid);
             bool surv = false;
             if (i < hi) {
@@ -2516,9 +2518,17 @@ hipError_t launch_wide(const WideArgs& a, hipStream_t s) {
     if (a.S <= 0) return hipSuccess;
     const dim3 S1((unsigned)a.S), NT((unsigned)a.NT), S2((unsigned)(2 * a.S));
     hipLaunchKernelGGL(k_wprep, S1, dim3(kWB), 0, s, a);
-    if (a.NT > 0) hipLaunchKernelGGL(k_wext, NT, dim3(kWB), 0, s, a);
+    if (a.NT > 0) {
+        if (a.items == 2) hipLaunchKernelGGL(k_wext<2>, NT, dim3(kWB), 0, s, a);
+        else if (a.items == 8) hipLaunchKernelGGL(k_wext<8>, NT, dim3(kWB), 0, s, a);
+        else hipLaunchKernelGGL(k_wext<4>, NT, dim3(kWB), 0, s, a);
+    }
     hipLaunchKernelGGL(k_wparams, S1, dim3(64), 0, s, a);
-    if (a.NT > 0) hipLaunchKernelGGL(k_wfilter, NT, dim3(kWB), 0, s, a);
+    if (a.NT > 0) {
+        if (a.items == 2) hipLaunchKernelGGL(k_wfilter<2>, NT, dim3(kWB), 0, s, a);
+        else if (a.items == 8) hipLaunchKernelGGL(k_wfilter<8>, NT, dim3(kWB), 0, s, a);
+        else hipLaunchKernelGGL(k_wfilter<4>, NT, dim3(kWB), 0, s, a);
+    }
     hipLaunchKernelGGL(k_wfar, S1, dim3(64), 0, s, a);
     if (a.S_large > 0) hipLaunchKernelGGL((k_wset<kWideFilterBits, 1024>), dim3((unsigned)a.S_large), dim3(1024), 0, s, a);
     if (a.S > a.S_large)

@@ -85,6 +85,7 @@ def test_shipped_batch_schedule_is_valid():
     assert t.get("batch_filter_bits", 0) == 0 or 4 <= t["batch_filter_bits"] <= 14
     assert t.get("batch_sort_bits", 0) == 0 or 4 <= t["batch_sort_bits"] <= 12
     assert -1 <= t.get("batch_side_sets", 0) <= 4096
+    assert t.get("batch_items", 0) in (0, 2, 4, 8)
 
 
 def test_option_struct_matches_header(tmp_path):

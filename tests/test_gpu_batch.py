@@ -299,19 +299,21 @@ def test_batch_schedules_agree(torch_dev, hx, blocks, order):
     c.close()
 
 
-@pytest.mark.parametrize("tile,fbits,sbits,side", [
-    (1024, 0, 0, 0), (65536, 0, 0, 0), (0, 4, 4, 0), (0, 9, 6, -1), (2048, 13, 11, 1), (8192, 14, 12, 4096)])
-def test_batch_tiled_schedules_agree(torch_dev, hx, tile, fbits, sbits, side):
+@pytest.mark.parametrize("tile,fbits,sbits,side,items", [
+    (1024, 0, 0, 0, 2), (65536, 0, 0, 0, 8), (0, 4, 4, 0, 0), (0, 9, 6, -1, 8), (2048, 13, 11, 1, 2),
+    (8192, 14, 12, 4096, 4)])
+def test_batch_tiled_schedules_agree(torch_dev, hx, tile, fbits, sbits, side, items):
     """Every schedule of the tiled engine (tile size, bucket bits of the
-    filter and of the grouping, sets on the second stream) gives the
-    oracle's hulls, eager and replayed from a graph."""
+    filter and of the grouping, sets on the second stream, points per thread
+    per round) gives the oracle's hulls, eager and replayed from a graph."""
     sizes = [70_000, 130_000, 66_000] + [int(n) for n in synth.batch_sizes(40, 64.0, 20_000.0, 962)]
     sets = [synth.batch_set(n, k, 963)[0] for k, n in enumerate(sizes)]
     sets += [_sliver(9_000, 964, 1.2), np.array([[0.5, 0.5]]), synth.annulus(4097, 0.999, (965, 1))]
     pts, offs = _concat(sets)
     d = torch_dev.from_numpy(pts).cuda()
-    say(f"batch tiled schedule tile={tile} fbits={fbits} sbits={sbits} side={side}")
-    kw = dict(batch_tile=tile, batch_filter_bits=fbits, batch_sort_bits=sbits, batch_side_sets=side)
+    say(f"batch tiled schedule tile={tile} fbits={fbits} sbits={sbits} side={side} items={items}")
+    kw = dict(batch_tile=tile, batch_filter_bits=fbits, batch_sort_bits=sbits, batch_side_sets=side,
+              batch_items=items)
     ce = hx.Hull2D(batch_graph=False, **kw)
     h, o = ce.batch(d, offs)
     _check_all(h, o, sets)
@@ -331,7 +333,8 @@ def test_batch_tiled_schedule_errors(hx):
     offs = np.array([0, 4], dtype=np.int64)
     for kw in (dict(batch_tile=1000), dict(batch_tile=512), dict(batch_tile=131072),
                dict(batch_filter_bits=3), dict(batch_filter_bits=15), dict(batch_sort_bits=13),
-               dict(batch_side_sets=-2), dict(batch_side_sets=4097)):
+               dict(batch_side_sets=-2), dict(batch_side_sets=4097), dict(batch_items=3),
+               dict(batch_items=16)):
         c = hx.Hull2D(**kw)
         with pytest.raises(hx.HullError):
             c.batch(d, offs)
