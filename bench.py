@@ -55,13 +55,13 @@ TRAFFIC = {
 TRAFFIC["batch_tiled"] = {
     # all kernels of one hull2d_batch call of the tiled engine on the 4096-set
     # workload with the tuned schedule (both streams), same scale factors
-    "bytes": 8_928_500_000,  # 6,840.6 MB fetched + 2,087.9 MB written
+    "bytes": 8_918_800_000,  # 6,830.8 MB fetched + 2,088.0 MB written
     "profile": "profiles/hull_batch_4096_sets_kernel_trace.md",
     "sources": {
         "paper_1508_05931_amd/csrc/kernels_batch.hip":
-            "dc5a63607fcd6c46d789555eabc90cd077ec4ec465ed4c981508615772cd899b",
+            "967e5e310e8a824d32419066f8594a2cdae5ee0d813ea070ee268f07d6a5c414",
         "paper_1508_05931_amd/csrc/kernels.hpp":
-            "e89bf2385d949258fa428ed3ba2cf25dea5b8f80f8fe09555e3b935c76dd67b4",
+            "bec1a4687ab4f3693c831227513bcb66ff7d49d6249bcd3441975fde7968e309",
         "paper_1508_05931_amd/csrc/steps.hpp":
             "33fa676280d55236357f5fab49d6890917f601f226406e1aaa653063fafa9744",
         "paper_1508_05931_amd/csrc/exact.hpp":
@@ -69,9 +69,9 @@ TRAFFIC["batch_tiled"] = {
         "paper_1508_05931_amd/csrc/common.hpp":
             "b945234c8a977df749c303e9fadbe0b97853518d9b1324d8323dd32fc2e11fd8",
         "paper_1508_05931_amd/csrc/hull2d_api.cpp":
-            "a6ba25d7d944b1b83424669a166a0e6d53bfcda42ac0b927bf08f9d485bfeb9a",
+            "c29655123fd588795a2850fe03980068185eb1ec002dcf0c9eb8637761ee4683",
         "paper_1508_05931_amd/tuning/batch.json":
-            "50f9048d755749c1ffa2c9666c66fd6f243b9a09bcb2377e84b1081052cac345",
+            "d53dc0fcea061e10bd57df56b5b7370304b9f75d4147c3b108c3426c8ef753de",
     },
 }
 
