@@ -59,7 +59,7 @@ TRAFFIC["batch_tiled"] = {
     "profile": "profiles/hull_batch_4096_sets_kernel_trace.md",
     "sources": {
         "paper_1508_05931_amd/csrc/kernels_batch.hip":
-            "967e5e310e8a824d32419066f8594a2cdae5ee0d813ea070ee268f07d6a5c414",
+            "683f6205368a9b5ef8020fa5d5e6642693f3e9b15d15280ce9f1634b00b30dae",
         "paper_1508_05931_amd/csrc/kernels.hpp":
             "bec1a4687ab4f3693c831227513bcb66ff7d49d6249bcd3441975fde7968e309",
         "paper_1508_05931_amd/csrc/steps.hpp":
@@ -69,7 +69,7 @@ TRAFFIC["batch_tiled"] = {
         "paper_1508_05931_amd/csrc/common.hpp":
             "b945234c8a977df749c303e9fadbe0b97853518d9b1324d8323dd32fc2e11fd8",
         "paper_1508_05931_amd/csrc/hull2d_api.cpp":
-            "c29655123fd588795a2850fe03980068185eb1ec002dcf0c9eb8637761ee4683",
+            "3f83169190397b1c42e80633cd7d8c280a665c6a93955c82e538221767ac8be6",
         "paper_1508_05931_amd/tuning/batch.json":
             "d53dc0fcea061e10bd57df56b5b7370304b9f75d4147c3b108c3426c8ef753de",
     },

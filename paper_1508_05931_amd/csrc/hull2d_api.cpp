@@ -1420,7 +1420,8 @@ hull2d_status hull2d_batch(hull2d_ctx* c, const double* d_xy, const int64_t* h_o
         std::stable_sort(c->hb_order, c->hb_order + S,
                          [&](int32_t a, int32_t b) { return size_of(a) > size_of(b); });
         const uint32_t tile = c->opt.batch_tile > 0 ? (uint32_t)c->opt.batch_tile : kWideTile;
-        const uint32_t fbits = c->opt.batch_filter_bits > 0 ? (uint32_t)c->opt.batch_filter_bits : (uint32_t)kWideFilterBits;
+        const uint32_t fbits =
+            c->opt.batch_filter_bits > 0 ? (uint32_t)c->opt.batch_filter_bits : (uint32_t)kWideFilterBits;
         const uint32_t sbits = c->opt.batch_sort_bits > 0 ? (uint32_t)c->opt.batch_sort_bits : (uint32_t)kWideSortBits;
         const int32_t side = c->opt.batch_side_sets == 0 ? kWideBigSets : std::max(0, c->opt.batch_side_sets);
         while (S_big < std::min<int32_t>(S - 1, side) && size_of(c->hb_order[S_big]) >= kWideBigMin) ++S_big;

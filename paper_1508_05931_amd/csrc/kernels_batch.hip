@@ -1216,7 +1216,9 @@ namespace {
 
 constexpr int kWB = 256;              // threads of the tile passes
 constexpr int kWW = kWB / 64;
-constexpr int kWI = 4;                // entries per thread per round (grouping); the passes over points take kI of 2, 4 or 8
+// entries per thread per round of the candidates' grouping (the passes over
+// points take kI of 2, 4 or 8, a schedule option)
+constexpr int kWI = 4;
 constexpr uint32_t kCT = 2048;        // candidates per walk tile
 constexpr int kCI = (int)kCT / kBB;   // walk positions per thread
 constexpr uint32_t kSortOne = 32;     // buckets up to this size: one thread sorts them
@@ -2413,8 +2415,8 @@ __global__ __launch_bounds__(kBB) __attribute__((amdgpu_waves_per_eu(4))) void k
     H.count = A.h_count;
     H.start = A.h_start;
     H.flags = A.h_flags;
-    batch_step8<true>(S, H, s, A.sv_xy + o, A.sv_idx + o, KeptMap{lo0, k0, lo1}, m, A.ka + o, A.kb + o, A.va + o, W.P.x0,
-                W.P.y0, W.P.p0_idx);
+    batch_step8<true>(S, H, s, A.sv_xy + o, A.sv_idx + o, KeptMap{lo0, k0, lo1}, m, A.ka + o, A.kb + o,
+                      A.va + o, W.P.x0, W.P.y0, W.P.p0_idx);
 }
 
 // ---- Step 8 of a set whose kept list has at most kStep8Wave points, one
@@ -2492,7 +2494,8 @@ __global__ __launch_bounds__(kBB) void k_wstep8_small(WideArgs A) {
     for (int d = 32; d > 0; d >>= 1) {
         const double ox = __shfl_xor(bx, d), oy = __shfl_xor(by, d);
         const uint32_t ok = __shfl_xor(bk, d);
-        const bool take = ok != 0xFFFFFFFFu && (bk == 0xFFFFFFFFu || ox < bx || (ox == bx && (oy < by || (oy == by && ok < bk))));
+        const bool take = ok != 0xFFFFFFFFu &&
+                          (bk == 0xFFFFFFFFu || ox < bx || (ox == bx && (oy < by || (oy == by && ok < bk))));
         bx = take ? ox : bx;
         by = take ? oy : by;
         bk = take ? ok : bk;
@@ -2530,7 +2533,8 @@ hipError_t launch_wide(const WideArgs& a, hipStream_t s) {
         else hipLaunchKernelGGL(k_wfilter<4>, NT, dim3(kWB), 0, s, a);
     }
     hipLaunchKernelGGL(k_wfar, S1, dim3(64), 0, s, a);
-    if (a.S_large > 0) hipLaunchKernelGGL((k_wset<kWideFilterBits, 1024>), dim3((unsigned)a.S_large), dim3(1024), 0, s, a);
+    if (a.S_large > 0)
+        hipLaunchKernelGGL((k_wset<kWideFilterBits, 1024>), dim3((unsigned)a.S_large), dim3(1024), 0, s, a);
     if (a.S > a.S_large)
         hipLaunchKernelGGL((k_wset<kSmallBits, 256>), dim3((unsigned)(a.S - a.S_large)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_wwalk_small, dim3((unsigned)((2 * a.S + kBW - 1) / kBW)), dim3(kBB), 0, s, a);
