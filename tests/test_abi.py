@@ -105,3 +105,23 @@ def test_option_struct_matches_header(tmp_path):
     assert int(got["size"]) == ctypes.sizeof(hx._Options)
     for n in names:
         assert int(got[n]) == getattr(hx._Options, n).offset, n
+
+
+def test_autotune_grid_is_valid():
+    """Every schedule the autotuner times is one the library accepts (the
+    ranges hull2d_batch checks), and each differs from the others."""
+    from paper_1508_05931_amd import autotune as at
+    seen = set()
+    for kw in at.PERSISTENT:
+        assert kw["batch_engine"] == 1
+        assert kw["batch_blocks_per_cu"] in (1, 2) and kw["batch_order"] in (0, 1, 2)
+        seen.add(tuple(sorted(kw.items())))
+    for kw in at.TILED:
+        assert kw["batch_engine"] == 0
+        t = kw["batch_tile"]
+        assert 1024 <= t <= 65536 and t & (t - 1) == 0
+        assert 4 <= kw["batch_filter_bits"] <= 14 and 4 <= kw["batch_sort_bits"] <= 12
+        assert kw["batch_side_sets"] == -1 or 1 <= kw["batch_side_sets"] <= 4096
+        seen.add(tuple(sorted(kw.items())))
+    assert len(seen) == len(at.PERSISTENT) + len(at.TILED)
+    assert set(at.ITEMS) <= {2, 4, 8}
