@@ -4,10 +4,15 @@ One step = one hull2d_compute of each set of the workload (20,000,000 points
 uniform in [0,1)^2 and 20,000,000 points uniform in the unit disk, the shapes
 and sizes of the paper's Section 4 groups 1 and 2), inputs resident in HBM.
 The step covers every stage: extremes, round-1 discard with exact keys, the
-angular radix sort with exact tie order, the round-2 filter, compaction, the
-copy of the kept points to the host and the host stack scan.
+round-2 filter over the candidates of the angle buckets (sorted in the exact
+angular order), the copy of the kept points to the host and the host stack
+scan.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the headline rate over both sets, the roofline of the
+dominant kernel (algorithmic bytes over its measured time, and its counted
+HBM traffic), per-kernel times, the other legs (full sort, four-region
+variant, adversarial inputs, the batched form with both engines, the learned
+filter) and the CPU oracle's rate.
 """
 from __future__ import annotations
 
