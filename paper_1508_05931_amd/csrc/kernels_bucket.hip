@@ -26,7 +26,7 @@ namespace hx {
 namespace {
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
-constexpr int kPfBlock = 256;
+constexpr int kPfBlock = 512;
 constexpr int kPfItems = 4;    // points loaded per thread before any is used
 constexpr int kPfCap = 4096;   // LDS slots buffered per block before a flush
 constexpr int kBmItems = 4;
